@@ -1,0 +1,173 @@
+/* qdd.h -- C ABI of the MI355X (gfx950) clover-Wilson Dirac operator and its
+ * locally deflated, Schwarz-preconditioned flexible GCR solver.
+ *
+ * What it computes (arXiv:1011.0911, "Comparison of the mass preconditioned HMC
+ * and the DD-HMC algorithm for two-flavour QCD"):
+ *   - D = D_W + c_sw sum_{mu,nu} (i/4) sigma_{mu nu} F_{mu nu} + m     (Eq. 1),
+ *     with m = 1/(2 kappa) - 4, D_W the nearest-neighbour Wilson operator
+ *     -1/2 sum_mu [(1-g_mu) U_mu(x) d_{x+mu,y} + (1+g_mu) U_mu(x-mu)^dag d_{x-mu,y}] + 4;
+ *   - its even-odd Schur complement Dhat = D_ee - D_eo D_oo^{-1} D_oe (Eq. 2;
+ *     the paper's Q_S = D_ee^{-1} Dhat);
+ *   - solves D psi = eta with the locally deflated Schwarz-preconditioned GCR
+ *     the paper uses for its F2 inversions (Sect. 3 and 4, Table 1).
+ *
+ * Conventions: lattice L[0] x L[1] x L[2] x L[3], direction 0 = time; canonical
+ * site index lex = ((x0*L1 + x1)*L2 + x2)*L3 + x3; parity (x0+x1+x2+x3) mod 2;
+ * chiral Euclidean gamma basis g0 = [[0,-1],[-1,0]], gk = [[0,-i sk],[i sk,0]],
+ * g5 = diag(1,1,-1,-1); the fermion boundary sign bc_time multiplies the hops
+ * across the time boundary.
+ *
+ * Canonical arrays at the boundary are device pointers to complex128
+ * (interleaved re, im doubles):
+ *   links      U[lex][mu][a][b]                      (V*4*9 complex)
+ *   spinors    psi[rhs][lex][spin][colour]           (nrhs*V*12 complex)
+ *   even field psi_e[rhs][lex>>1][spin][colour]      (even sites only, nrhs*V/2*12)
+ * Internal ("packed") fields, used by the hot-path calls qdd_dw_hat / qdd_dw,
+ * are opaque device buffers of qdd_field_bytes() bytes made by qdd_pack_field.
+ *
+ * Ownership: the caller allocates every device buffer, including the workspace
+ * of qdd_workspace_bytes() bytes handed to qdd_create; the library keeps
+ * non-owning pointers into it and never allocates device memory itself.
+ * Streams: every call is asynchronous on the stream given to qdd_create, except
+ * where a host result is returned (set_params reads one flag, the solvers read
+ * residual norms each iteration).  One context per host thread.
+ * Errors: every call returns a qdd_status; qdd_last_error() describes the last
+ * failure.  No call aborts or exits.  Arguments are validated before any HIP
+ * call, so invalid geometry or sizes fail without touching the GPU.
+ */
+#ifndef QDD_H
+#define QDD_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QDD_OK = 0,
+  QDD_EINVAL = -1,    /* invalid argument or geometry */
+  QDD_ESTATE = -2,    /* call out of order (e.g. apply before set_params) */
+  QDD_ESINGULAR = -3, /* a 6x6 clover block is not positive definite */
+  QDD_ENOCONV = -4,   /* solver hit nmx iterations or a non-finite residual */
+  QDD_EHIP = -5,      /* HIP runtime error */
+  QDD_ENOWS = -6      /* workspace too small */
+} qdd_status;
+
+typedef enum { QDD_F64 = 0, QDD_F32 = 1, QDD_F16 = 2 } qdd_prec; /* F16 = FP16 storage, FP32 arithmetic */
+
+typedef enum {
+  QDD_PRECOND_NONE = 0, /* plain flexible GCR */
+  QDD_PRECOND_SAP = 1,  /* Schwarz alternating procedure */
+  QDD_PRECOND_DFL = 2   /* deflation + SAP (two-level) */
+} qdd_precond;
+
+typedef struct {
+  int L[4];    /* L[0] = time extent; all even */
+  int bc_time; /* -1 antiperiodic (default), +1 periodic */
+} qdd_geom;
+
+typedef struct {
+  int max_nrhs;        /* largest right-hand-side batch of any call */
+  /* Schwarz preconditioner */
+  int sap_bs[4];       /* block extents; an even number of blocks per direction */
+  int ncy;             /* SAP cycles per preconditioner call */
+  int nmr;             /* minimal-residual steps per block solve */
+  qdd_prec sap_prec;   /* arithmetic of the SAP sweeps (F64, F32, F16 storage) */
+  /* local deflation */
+  int dfl_Ns;          /* deflation vectors (0 = off) */
+  int dfl_bs[4];       /* deflation block extents */
+  int dfl_nit;         /* SAP inverse-iteration rounds in the subspace build */
+  double dfl_coarse_tol; /* relative tolerance of the little-operator solve */
+  int dfl_coarse_nmx;  /* iteration cap of the little-operator solve */
+  /* outer flexible GCR (FP64) */
+  int nkv;             /* Krylov vectors before a restart (<= 32) */
+  int nmx;             /* iteration cap */
+  double tol;          /* relative residual |eta - D psi| / |eta| */
+  qdd_precond precond;
+  int use_net;         /* 1: gauge-covariant network stage inside the preconditioner */
+  int net_nl;          /* network layers */
+  int net_ch[8];       /* channels ch[0] .. ch[nl] (ch[0] = ch[nl] = 1) */
+} qdd_config;
+
+typedef struct {
+  int iters;        /* outer FGCR iterations */
+  int restarts;
+  int converged;    /* 1 if true relative residual <= tol */
+  int fallbacks;    /* network stage rejected (plain SAP used instead) */
+  double true_res;  /* |eta - D psi| / |eta| with FP64 D, at exit */
+  double t_ms[8];   /* stage times: 0 total, 1 preconditioner, 2 operator, 3 Gram-Schmidt,
+                       4 coarse correction, 5 network, 6 SAP, 7 residual restarts */
+} qdd_solve_info;
+
+typedef struct qdd_ctx qdd_ctx;
+
+/* Fills *cfg with the defaults: max_nrhs 1, SAP 4^4 blocks, ncy 5, nmr 4, F32;
+ * no deflation (Ns 0, blocks 4^4, nit 5, coarse tol 1e-6, nmx 2000);
+ * nkv 16, nmx 2048, tol 1e-10, precond NONE; no network (3 layers 1-12-12-1). */
+void qdd_config_default(qdd_config* cfg);
+
+/* Workspace bytes needed for geometry + configuration; 0 if they are invalid. */
+size_t qdd_workspace_bytes(const qdd_geom* geom, const qdd_config* cfg);
+
+/* Creates a context on the current HIP device.  dev_ws: caller-owned device
+ * buffer of ws_bytes (>= qdd_workspace_bytes), 256-byte aligned.  stream: a
+ * hipStream_t (NULL = default stream). */
+qdd_status qdd_create(const qdd_geom* geom, const qdd_config* cfg, void* dev_ws, size_t ws_bytes, void* stream,
+                      qdd_ctx** out);
+void qdd_destroy(qdd_ctx* ctx);
+const char* qdd_last_error(const qdd_ctx* ctx);
+
+/* Gauge ingest (canonical complex128 links, device pointer): builds the
+ * parity-split hopping copies in FP64, FP32 and FP16 with the boundary sign
+ * folded in.  Invalidates clover and deflation data. */
+qdd_status qdd_set_gauge(qdd_ctx* ctx, const double* dev_links);
+
+/* Clover setup (Eq. 1): F_{mu nu} from the clover leaves, A = (4+m) + c_sw
+ * sum (i/4) sigma F as two Hermitian 6x6 blocks per site, their FP64 Cholesky
+ * inverses, and FP32 / FP16 copies.  Synchronises to read the singularity flag:
+ * QDD_ESINGULAR if any block is not positive definite. */
+qdd_status qdd_set_params(qdd_ctx* ctx, double kappa, double csw);
+
+/* Bytes of a packed field of `nrhs` right-hand sides (even_only: even sites). */
+size_t qdd_field_bytes(const qdd_ctx* ctx, qdd_prec prec, int nrhs, int even_only);
+/* canonical complex128 (device) -> packed field of precision prec (FP16 with a
+ * per-site scale), and back. */
+qdd_status qdd_pack_field(qdd_ctx* ctx, qdd_prec prec, int nrhs, int even_only, const double* canon, void* field);
+qdd_status qdd_unpack_field(qdd_ctx* ctx, qdd_prec prec, int nrhs, int even_only, const void* field, double* canon);
+
+/* out_e = Dhat in_e on packed even fields (Eq. 2), nrhs right-hand sides in one
+ * pair of launches; the links and clover blocks are read once per site for all
+ * of them. */
+qdd_status qdd_dw_hat(qdd_ctx* ctx, qdd_prec prec, int nrhs, const void* in_e, void* out_e);
+/* out = D in on packed full fields (Eq. 1). */
+qdd_status qdd_dw(qdd_ctx* ctx, qdd_prec prec, int nrhs, const void* in, void* out);
+
+/* psi = M_sap eta: ncy cycles of the two-colour Schwarz procedure with nmr
+ * minimal-residual steps on the even-odd block operator of every block, in the
+ * configured SAP precision.  Canonical complex128 full fields. */
+qdd_status qdd_sap(qdd_ctx* ctx, int nrhs, const double* eta, double* psi);
+
+/* Local deflation subspace: init holds dfl_Ns canonical full fields (the random
+ * start vectors, supplied by the caller); dfl_nit rounds of SAP inverse
+ * iteration, block orthonormalisation (FP64) and the little Dirac operator
+ * (self + 8 face couplings per block, FP64). */
+qdd_status qdd_dfl_build(qdd_ctx* ctx, const double* init);
+
+/* Solves D psi = eta (canonical full fields, nrhs right-hand sides, psi
+ * overwritten) with FP64 flexible GCR and the configured preconditioner.
+ * info: nrhs entries (host memory) or NULL.  QDD_ENOCONV if any rhs fails. */
+qdd_status qdd_solve(qdd_ctx* ctx, int nrhs, const double* eta, double* psi, qdd_solve_info* info);
+/* Solves Dhat psi_e = eta_e (canonical even fields) with unpreconditioned FP64 FGCR. */
+qdd_status qdd_solve_dhat(qdd_ctx* ctx, int nrhs, const double* eta_e, double* psi_e, qdd_solve_info* info);
+
+/* Launch shape of a kernel family (kernel: 0 = Dhat, 1 = D; prec: qdd_prec):
+ * block threads (64..256, multiple of 64), rhs per thread nr (1, 2, 4) and the
+ * XCD-aware block remap (0/1). */
+qdd_status qdd_set_launch(qdd_ctx* ctx, int kernel, qdd_prec prec, int block, int nr, int xcd);
+qdd_status qdd_get_launch(const qdd_ctx* ctx, int kernel, qdd_prec prec, int* block, int* nr, int* xcd);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

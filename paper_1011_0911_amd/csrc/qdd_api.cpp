@@ -1,0 +1,422 @@
+// Host side of the qdd C ABI: context, workspace layout, set-up calls, the
+// operator entry points and the FP64 flexible GCR driver.
+#include "../../include/qdd.h"
+#include "qdd_api_internal.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+using namespace qdd;
+
+// ------------------------------------------------------------------ helpers
+void qdd_ctx::fail(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  char buf[512];
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  err = buf;
+}
+
+static bool valid_geom(const qdd_geom* g, std::string* why) {
+  if (!g) { *why = "null geometry"; return false; }
+  for (int i = 0; i < 4; ++i)
+    if (g->L[i] < 2 || (g->L[i] & 1)) { *why = "every lattice extent must be even and >= 2"; return false; }
+  if (g->bc_time != 1 && g->bc_time != -1) { *why = "bc_time must be +1 or -1"; return false; }
+  int64_t V = (int64_t)g->L[0] * g->L[1] * g->L[2] * g->L[3];
+  if (V > (int64_t)1 << 30) { *why = "lattice volume above 2^30 sites"; return false; }
+  return true;
+}
+
+static bool valid_blocks(const qdd_geom* g, const int* bs, bool need_even_count, std::string* why,
+                         const char* what) {
+  for (int i = 0; i < 4; ++i) {
+    if (bs[i] < 1 || g->L[i] % bs[i]) { *why = std::string(what) + " block extents must divide the lattice"; return false; }
+    if (need_even_count && ((g->L[i] / bs[i]) & 1)) {
+      *why = std::string(what) + ": the number of blocks in every direction must be even";
+      return false;
+    }
+  }
+  return true;
+}
+
+bool valid_sap_blocks(const qdd_geom* g, const qdd_config* c, std::string* why) {
+  if (!valid_blocks(g, c->sap_bs, true, why, "SAP")) return false;
+  int nsite = c->sap_bs[0] * c->sap_bs[1] * c->sap_bs[2] * c->sap_bs[3];
+  if (nsite > kSapMaxSites || (nsite & 1)) {
+    *why = "SAP blocks must hold an even number of sites, at most 256";
+    return false;
+  }
+  return true;
+}
+
+static bool valid_cfg(const qdd_geom* g, const qdd_config* c, std::string* why) {
+  if (!c) { *why = "null configuration"; return false; }
+  if (c->max_nrhs < 1 || c->max_nrhs > 64) { *why = "max_nrhs must be in 1..64"; return false; }
+  if (c->nkv < 1 || c->nkv > kMaxKv) { *why = "nkv must be in 1..32"; return false; }
+  if (c->nmx < 1) { *why = "nmx must be >= 1"; return false; }
+  if (!(c->tol > 0)) { *why = "tol must be > 0"; return false; }
+  if (c->sap_prec < QDD_F64 || c->sap_prec > QDD_F16) { *why = "invalid sap_prec"; return false; }
+  if (c->precond < QDD_PRECOND_NONE || c->precond > QDD_PRECOND_DFL) { *why = "invalid precond"; return false; }
+  if (c->ncy < 1 || c->nmr < 1) { *why = "ncy and nmr must be >= 1"; return false; }
+  // the Schwarz blocks matter only where SAP runs (preconditioner, subspace build)
+  if (c->precond != QDD_PRECOND_NONE || c->dfl_Ns > 0)
+    if (!valid_sap_blocks(g, c, why)) return false;
+  if (c->dfl_Ns < 0 || c->dfl_Ns > kMaxNs) { *why = "dfl_Ns must be in 0..64"; return false; }
+  if (c->dfl_Ns > 0) {
+    if (!valid_blocks(g, c->dfl_bs, false, why, "deflation")) return false;
+    if (c->dfl_nit < 0 || !(c->dfl_coarse_tol > 0) || c->dfl_coarse_nmx < 1) {
+      *why = "invalid deflation parameters";
+      return false;
+    }
+  }
+  if (c->precond == QDD_PRECOND_DFL && c->dfl_Ns == 0) { *why = "precond DFL needs dfl_Ns > 0"; return false; }
+  if (c->use_net) {
+    if (c->net_nl < 1 || c->net_nl > 7 || c->net_ch[0] != 1 || c->net_ch[c->net_nl] != 1) {
+      *why = "network: 1..7 layers, one input and one output channel";
+      return false;
+    }
+    for (int l = 1; l < c->net_nl; ++l)
+      if (c->net_ch[l] < 1 || c->net_ch[l] > kMaxNetCh) { *why = "network: channels must be in 1..16"; return false; }
+    if (c->dfl_Ns == 0) { *why = "network stage needs deflation (dfl_Ns > 0)"; return false; }
+  }
+  return true;
+}
+
+// ------------------------------------------------------------------ layout
+static size_t elem_bytes(qdd_prec p) { return p == QDD_F64 ? 16 : (p == QDD_F32 ? 8 : 4); }
+
+void compute_layout(const qdd_geom* g, const qdd_config* c, Layout& Lo) {
+  struct Bump {
+    size_t off = 0;
+    size_t take(size_t b) {
+      off = (off + 255) & ~size_t(255);
+      size_t o = off;
+      off += b;
+      return o;
+    }
+  } B;
+  int64_t V = (int64_t)g->L[0] * g->L[1] * g->L[2] * g->L[3], Vh = V / 2;
+  int nr = c->max_nrhs, nkv = c->nkv;
+  int64_t links = 2 * 4 * 9 * Vh, clov = 2 * 36 * Vh;
+  Lo.U[0] = B.take(links * 16);
+  Lo.U[1] = B.take(links * 8);
+  Lo.U[2] = B.take(links * 4);
+  for (int p = 0; p < 3; ++p) {
+    Lo.A[p] = B.take(clov * elem_bytes((qdd_prec)p));
+    Lo.Ai[p] = B.take(clov * elem_bytes((qdd_prec)p));
+  }
+  Lo.tmp_o = B.take((size_t)nr * 12 * Vh * 16);
+  Lo.tmp_o_scale = B.take((size_t)nr * Vh * 4);
+  Lo.flag = B.take(256);
+  // FP64 solver fields (full lattice, nr rhs)
+  size_t f64 = (size_t)nr * 24 * Vh * 16;
+  Lo.eta = B.take(f64);
+  Lo.psi = B.take(f64);
+  Lo.res = B.take(f64);
+  Lo.t64 = B.take(f64);
+  Lo.chi = B.take(f64 * nkv);
+  bool phi32 = c->precond != QDD_PRECOND_NONE && c->sap_prec != QDD_F64;
+  Lo.phi32 = phi32;
+  Lo.phi = B.take((size_t)nr * 24 * Vh * (phi32 ? 8 : 16) * nkv);
+  // SAP fields in the SAP precision: rho, psi, v (+ FP16 scales) and an FP64 staging copy
+  size_t se = elem_bytes(c->sap_prec);
+  Lo.s_rho = B.take((size_t)nr * 24 * Vh * se);
+  Lo.s_psi = B.take((size_t)nr * 24 * Vh * se);
+  Lo.s_v = B.take((size_t)nr * 24 * Vh * se);
+  Lo.s_eta = B.take((size_t)nr * 24 * Vh * se);
+  Lo.s_scale = B.take((size_t)4 * nr * 2 * Vh * 4);
+  Lo.s_tmp = B.take(f64);
+  // deflation
+  Lo.nblk_dfl = 0;
+  if (c->dfl_Ns > 0) {
+    int64_t nb = 1;
+    for (int i = 0; i < 4; ++i) nb *= g->L[i] / c->dfl_bs[i];
+    Lo.nblk_dfl = nb;
+    int Ns = c->dfl_Ns;
+    Lo.dfl_W = B.take((size_t)Ns * 24 * Vh * 16);
+    Lo.dfl_W32 = B.take((size_t)Ns * 24 * Vh * 8);
+    Lo.dfl_A = B.take((size_t)nb * 9 * Ns * Ns * 16);
+    Lo.dfl_Ainv = B.take((size_t)nb * Ns * Ns * 16);
+    size_t cv = (size_t)nr * nb * Ns * 16;
+    Lo.dfl_cvec = B.take(cv * (2 * kCoarseKv + 8));
+    Lo.dfl_init = B.take((size_t)Ns * 24 * Vh * 16);
+  }
+  // network weights and activations
+  if (c->use_net) {
+    size_t nw = 0, maxch = 1;
+    for (int l = 0; l < c->net_nl; ++l) {
+      nw += (size_t)9 * c->net_ch[l] * c->net_ch[l + 1] * 16;
+      maxch = std::max<size_t>(maxch, c->net_ch[l + 1]);
+    }
+    Lo.net_nw = nw;
+    Lo.net_w = B.take(nw * 8);       // complex FP32 (master copy)
+    Lo.net_wb = B.take(nw * 4);      // complex BF16 (compute copy)
+    Lo.net_act = B.take((size_t)(c->net_nl + 1) * maxch * 24 * Vh * 8);
+    Lo.net_grad = B.take(nw * 8);
+    Lo.net_adam = B.take(nw * 16);
+    Lo.net_gpart = B.take((size_t)kNetGradBlocks * nw * 8);
+  }
+  // reductions and small solver arrays
+  Lo.part = B.take((size_t)kDotBlocks * kMaxKv * nr * 16 + 4096);
+  Lo.coef = B.take((size_t)nr * kMaxKv * 16);
+  Lo.ahist = B.take((size_t)kMaxKv * nr * kMaxKv * 16);
+  Lo.bhist = B.take((size_t)kMaxKv * nr * 8);
+  Lo.binv = B.take((size_t)nr * 8);
+  Lo.chist = B.take((size_t)kMaxKv * nr * 16);
+  Lo.rn2 = B.take((size_t)nr * 16 * 4);
+  Lo.alpha = B.take((size_t)nr * kMaxKv * 16);
+  Lo.active = B.take((size_t)nr * 4);
+  Lo.scal = B.take((size_t)nr * 64 * 8);
+  Lo.total = (B.off + 255) & ~size_t(255);
+}
+
+// ------------------------------------------------------------------ API
+extern "C" {
+
+void qdd_config_default(qdd_config* c) {
+  std::memset(c, 0, sizeof(*c));
+  c->max_nrhs = 1;
+  for (int i = 0; i < 4; ++i) c->sap_bs[i] = c->dfl_bs[i] = 4;
+  c->ncy = 5;
+  c->nmr = 4;
+  c->sap_prec = QDD_F32;
+  c->dfl_Ns = 0;
+  c->dfl_nit = 5;
+  c->dfl_coarse_tol = 1e-6;
+  c->dfl_coarse_nmx = 2000;
+  c->nkv = 16;
+  c->nmx = 2048;
+  c->tol = 1e-10;
+  c->precond = QDD_PRECOND_NONE;
+  c->use_net = 0;
+  c->net_nl = 3;
+  c->net_ch[0] = 1;
+  c->net_ch[1] = 12;
+  c->net_ch[2] = 12;
+  c->net_ch[3] = 1;
+}
+
+size_t qdd_workspace_bytes(const qdd_geom* g, const qdd_config* c) {
+  std::string why;
+  if (!valid_geom(g, &why) || !valid_cfg(g, c, &why)) return 0;
+  Layout Lo;
+  compute_layout(g, c, Lo);
+  return Lo.total;
+}
+
+qdd_status qdd_create(const qdd_geom* g, const qdd_config* c, void* ws, size_t ws_bytes, void* stream,
+                      qdd_ctx** out) {
+  if (!out) return QDD_EINVAL;
+  *out = nullptr;
+  std::string why;
+  if (!valid_geom(g, &why) || !valid_cfg(g, c, &why)) {
+    qdd_ctx::last_global() = why;
+    return QDD_EINVAL;
+  }
+  Layout Lo;
+  compute_layout(g, c, Lo);
+  if (!ws || ws_bytes < Lo.total) {
+    qdd_ctx::last_global() = "workspace missing or smaller than qdd_workspace_bytes()";
+    return QDD_ENOWS;
+  }
+  if (((uintptr_t)ws & 255) != 0) {
+    qdd_ctx::last_global() = "workspace must be 256-byte aligned";
+    return QDD_EINVAL;
+  }
+  qdd_ctx* x = new qdd_ctx();
+  x->geom = *g;
+  x->cfg = *c;
+  x->lo = Lo;
+  x->ws = (char*)ws;
+  x->st = (hipStream_t)stream;
+  Geo& G = x->G;
+  for (int i = 0; i < 4; ++i) G.L[i] = g->L[i];
+  G.V = g->L[0] * g->L[1] * g->L[2] * g->L[3];
+  G.Vh = G.V / 2;
+  G.Lh3 = g->L[3] / 2;
+  G.bc = g->bc_time;
+  for (int k = 0; k < 2; ++k)
+    for (int p = 0; p < 3; ++p) x->launch[k][p] = LaunchCfg();
+  *out = x;
+  return QDD_OK;
+}
+
+void qdd_destroy(qdd_ctx* x) { delete x; }
+
+const char* qdd_last_error(const qdd_ctx* x) {
+  return x ? x->err.c_str() : qdd_ctx::last_global().c_str();
+}
+
+qdd_status qdd_set_gauge(qdd_ctx* x, const double* links) {
+  if (!x || !links) return QDD_EINVAL;
+  const Geo& G = x->G;
+  int64_t n = (int64_t)2 * 4 * 9 * G.Vh;
+  HCK(x, launch_pack_links(G, links, x->ptr<double2>(x->lo.U[0]), x->st));
+  HCK(x, launch_convert(x->ptr<double2>(x->lo.U[0]), x->ptr<float2>(x->lo.U[1]), n, x->st));
+  HCK(x, launch_convert(x->ptr<double2>(x->lo.U[0]), x->ptr<__half2>(x->lo.U[2]), n, x->st));
+  x->have_gauge = true;
+  x->have_clover = false;
+  x->have_dfl = false;
+  return QDD_OK;
+}
+
+qdd_status qdd_set_params(qdd_ctx* x, double kappa, double csw) {
+  if (!x) return QDD_EINVAL;
+  if (!x->have_gauge) { x->fail("qdd_set_params before qdd_set_gauge"); return QDD_ESTATE; }
+  if (!(kappa > 0) || !std::isfinite(csw)) { x->fail("kappa must be > 0 and c_sw finite"); return QDD_EINVAL; }
+  const Geo& G = x->G;
+  int* flag = x->ptr<int>(x->lo.flag);
+  HCK(x, hipMemsetAsync(flag, 0, sizeof(int), x->st));
+  HCK(x, launch_clover(G, x->ptr<double2>(x->lo.U[0]), 1.0 / (2.0 * kappa), csw, x->ptr<double2>(x->lo.A[0]),
+                       x->ptr<double2>(x->lo.Ai[0]), flag, x->st));
+  int64_t n = (int64_t)2 * 36 * G.Vh;
+  HCK(x, launch_convert(x->ptr<double2>(x->lo.A[0]), x->ptr<float2>(x->lo.A[1]), n, x->st));
+  HCK(x, launch_convert(x->ptr<double2>(x->lo.Ai[0]), x->ptr<float2>(x->lo.Ai[1]), n, x->st));
+  HCK(x, launch_convert(x->ptr<double2>(x->lo.A[0]), x->ptr<__half2>(x->lo.A[2]), n, x->st));
+  HCK(x, launch_convert(x->ptr<double2>(x->lo.Ai[0]), x->ptr<__half2>(x->lo.Ai[2]), n, x->st));
+  int bad = 0;
+  HCK(x, hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, x->st));
+  HCK(x, hipStreamSynchronize(x->st));
+  x->kappa = kappa;
+  x->csw = csw;
+  x->have_dfl = false;
+  if (bad) {
+    x->have_clover = false;
+    x->fail("%d clover blocks are not positive definite", bad);
+    return QDD_ESINGULAR;
+  }
+  x->have_clover = true;
+  return QDD_OK;
+}
+
+size_t qdd_field_bytes(const qdd_ctx* x, qdd_prec prec, int nrhs, int even_only) {
+  if (!x || nrhs < 1 || prec < QDD_F64 || prec > QDD_F16) return 0;
+  size_t sites = (size_t)x->G.Vh * (even_only ? 1 : 2);
+  size_t b = sites * 12 * elem_bytes(prec) * nrhs;
+  if (prec == QDD_F16) b += sites * 4 * nrhs;  // per-site FP32 scales after the values
+  return b;
+}
+
+qdd_status qdd_pack_field(qdd_ctx* x, qdd_prec prec, int nrhs, int even_only, const double* canon, void* field) {
+  if (!x || !canon || !field || nrhs < 1 || nrhs > x->cfg.max_nrhs || prec < QDD_F64 || prec > QDD_F16) {
+    if (x) x->fail("qdd_pack_field: invalid arguments");
+    return QDD_EINVAL;
+  }
+  PackedView pv = x->packed(prec, nrhs, even_only, field);
+  switch (prec) {
+    case QDD_F64: HCK(x, launch_pack_spinor<double>(x->G, canon, pv.f64, nrhs, even_only, pv.poff, pv.spoff, x->st)); break;
+    case QDD_F32: HCK(x, launch_pack_spinor<float>(x->G, canon, pv.f32, nrhs, even_only, pv.poff, pv.spoff, x->st)); break;
+    default: HCK(x, launch_pack_spinor<__half>(x->G, canon, pv.f16, nrhs, even_only, pv.poff, pv.spoff, x->st)); break;
+  }
+  return QDD_OK;
+}
+
+qdd_status qdd_unpack_field(qdd_ctx* x, qdd_prec prec, int nrhs, int even_only, const void* field, double* canon) {
+  if (!x || !canon || !field || nrhs < 1 || nrhs > x->cfg.max_nrhs || prec < QDD_F64 || prec > QDD_F16) {
+    if (x) x->fail("qdd_unpack_field: invalid arguments");
+    return QDD_EINVAL;
+  }
+  PackedView pv = x->packed(prec, nrhs, even_only, (void*)field);
+  switch (prec) {
+    case QDD_F64: HCK(x, launch_unpack_spinor<double>(x->G, pv.f64, canon, nrhs, even_only, pv.poff, pv.spoff, x->st)); break;
+    case QDD_F32: HCK(x, launch_unpack_spinor<float>(x->G, pv.f32, canon, nrhs, even_only, pv.poff, pv.spoff, x->st)); break;
+    default: HCK(x, launch_unpack_spinor<__half>(x->G, pv.f16, canon, nrhs, even_only, pv.poff, pv.spoff, x->st)); break;
+  }
+  return QDD_OK;
+}
+
+qdd_status qdd_dw_hat(qdd_ctx* x, qdd_prec prec, int nrhs, const void* in, void* out) {
+  if (!x || !in || !out || nrhs < 1 || nrhs > x->cfg.max_nrhs || prec < QDD_F64 || prec > QDD_F16) {
+    if (x) x->fail("qdd_dw_hat: invalid arguments");
+    return QDD_EINVAL;
+  }
+  if (!x->have_clover) { x->fail("qdd_dw_hat before qdd_set_params"); return QDD_ESTATE; }
+  HCK(x, x->dhat(prec, nrhs, (void*)in, out));
+  return QDD_OK;
+}
+
+qdd_status qdd_dw(qdd_ctx* x, qdd_prec prec, int nrhs, const void* in, void* out) {
+  if (!x || !in || !out || nrhs < 1 || nrhs > x->cfg.max_nrhs || prec < QDD_F64 || prec > QDD_F16) {
+    if (x) x->fail("qdd_dw: invalid arguments");
+    return QDD_EINVAL;
+  }
+  if (!x->have_clover) { x->fail("qdd_dw before qdd_set_params"); return QDD_ESTATE; }
+  HCK(x, x->dw(prec, nrhs, (void*)in, out));
+  return QDD_OK;
+}
+
+qdd_status qdd_set_launch(qdd_ctx* x, int kernel, qdd_prec prec, int block, int nr, int xcd) {
+  if (!x || kernel < 0 || kernel > 1 || prec < QDD_F64 || prec > QDD_F16 || block < 64 || block > 256 ||
+      (block & 63) || (nr != 1 && nr != 2 && nr != 4) || (xcd != 0 && xcd != 1)) {
+    if (x) x->fail("qdd_set_launch: invalid arguments");
+    return QDD_EINVAL;
+  }
+  x->launch[kernel][prec] = LaunchCfg{block, nr, xcd};
+  return QDD_OK;
+}
+
+qdd_status qdd_get_launch(const qdd_ctx* x, int kernel, qdd_prec prec, int* block, int* nr, int* xcd) {
+  if (!x || kernel < 0 || kernel > 1 || prec < QDD_F64 || prec > QDD_F16) return QDD_EINVAL;
+  const LaunchCfg& c = x->launch[kernel][prec];
+  if (block) *block = c.block;
+  if (nr) *nr = c.nr;
+  if (xcd) *xcd = c.xcd;
+  return QDD_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ ctx methods
+std::string& qdd_ctx::last_global() {
+  static thread_local std::string s;
+  return s;
+}
+
+PackedView qdd_ctx::packed(qdd_prec prec, int nrhs, int even_only, void* field) const {
+  PackedView v;
+  int64_t n = G.Vh;
+  int64_t sites = n * (even_only ? 1 : 2);
+  int64_t rs = sites * 12;
+  v.poff = 12 * n;  // parity offset within one rhs (elements)
+  v.spoff = n;      // parity offset of the scales
+  char* b = (char*)field;
+  v.f64 = FieldV<double>{(double2*)b, nullptr, rs, sites, (int)n};
+  v.f32 = FieldV<float>{(float2*)b, nullptr, rs, sites, (int)n};
+  float* sc = (float*)(b + (size_t)rs * nrhs * 4);
+  v.f16 = FieldV<__half>{(__half2*)b, sc, rs, sites, (int)n};
+  return v;
+}
+
+hipError_t qdd_ctx::dhat(qdd_prec prec, int nrhs, void* in, void* out) {
+  PackedView a = packed(prec, nrhs, 1, in), b = packed(prec, nrhs, 1, out);
+  int64_t n = G.Vh;
+  const LaunchCfg& c = launch[0][prec];
+  switch (prec) {
+    case QDD_F64: {
+      FieldV<double> t{ptr<double2>(lo.tmp_o), nullptr, 12 * n, n, (int)n};
+      return launch_dhat<double>(G, op<double>(), a.f64, t, b.f64, nrhs, c, st);
+    }
+    case QDD_F32: {
+      FieldV<float> t{ptr<float2>(lo.tmp_o), nullptr, 12 * n, n, (int)n};
+      return launch_dhat<float>(G, op<float>(), a.f32, t, b.f32, nrhs, c, st);
+    }
+    default: {
+      FieldV<__half> t{ptr<__half2>(lo.tmp_o), ptr<float>(lo.tmp_o_scale), 12 * n, n, (int)n};
+      return launch_dhat<__half>(G, op<__half>(), a.f16, t, b.f16, nrhs, c, st);
+    }
+  }
+}
+
+hipError_t qdd_ctx::dw(qdd_prec prec, int nrhs, void* in, void* out) {
+  PackedView a = packed(prec, nrhs, 0, in), b = packed(prec, nrhs, 0, out);
+  const LaunchCfg& c = launch[1][prec];
+  switch (prec) {
+    case QDD_F64: return launch_dw<double>(G, op<double>(), a.f64, b.f64, a.poff, a.spoff, nrhs, c, st);
+    case QDD_F32: return launch_dw<float>(G, op<float>(), a.f32, b.f32, a.poff, a.spoff, nrhs, c, st);
+    default: return launch_dw<__half>(G, op<__half>(), a.f16, b.f16, a.poff, a.spoff, nrhs, c, st);
+  }
+}

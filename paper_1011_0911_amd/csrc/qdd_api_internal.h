@@ -1,0 +1,79 @@
+// Host-side context of the qdd library (not part of the public ABI).
+#pragma once
+#include "../../include/qdd.h"
+#include "qdd_kernels.h"
+#include "qdd_blas.h"
+
+#include <algorithm>
+#include <string>
+
+namespace qdd {
+constexpr int kMaxKv = 32;         // outer Krylov vectors
+constexpr int kSapMaxSites = 256;  // sites per Schwarz block (one workgroup)
+constexpr int kMaxNs = 64;         // deflation vectors
+constexpr int kMaxNetCh = 16;      // network channels
+constexpr int kCoarseKv = 16;      // Krylov vectors of the little-operator GCR
+constexpr int kNetGradBlocks = 256;
+
+// byte offsets of every buffer inside the caller's workspace
+struct Layout {
+  size_t U[3], A[3], Ai[3];
+  size_t tmp_o, tmp_o_scale, flag;
+  size_t eta, psi, res, t64, chi, phi;
+  bool phi32;
+  size_t s_rho, s_psi, s_v, s_eta, s_scale, s_tmp;
+  int64_t nblk_dfl;
+  size_t dfl_W, dfl_W32, dfl_A, dfl_Ainv, dfl_cvec, dfl_init;
+  size_t net_nw, net_w, net_wb, net_act, net_grad, net_adam, net_gpart;
+  size_t part, coef, ahist, bhist, binv, chist, rn2, alpha, active, scal;
+  size_t total;
+};
+
+struct PackedView {
+  FieldV<double> f64;
+  FieldV<float> f32;
+  FieldV<__half> f16;
+  int64_t poff, spoff;
+};
+}  // namespace qdd
+
+void compute_layout(const qdd_geom* g, const qdd_config* c, qdd::Layout& Lo);
+bool valid_sap_blocks(const qdd_geom* g, const qdd_config* c, std::string* why);
+
+struct qdd_ctx {
+  qdd_geom geom;
+  qdd_config cfg;
+  qdd::Geo G;
+  qdd::Layout lo;
+  char* ws = nullptr;
+  hipStream_t st = nullptr;
+  bool have_gauge = false, have_clover = false, have_dfl = false, have_net = false;
+  double kappa = 0, csw = 0;
+  qdd::LaunchCfg launch[2][3];
+  std::string err;
+
+  template <class T>
+  T* ptr(size_t off) const { return (T*)(ws + off); }
+  void fail(const char* fmt, ...);
+  static std::string& last_global();
+
+  template <class S>
+  qdd::DevOp<S> op() const {
+    int p = sizeof(S) == 8 ? 0 : (sizeof(S) == 4 ? 1 : 2);
+    typedef typename qdd::St<S>::E E;
+    return qdd::DevOp<S>{qdd::LinkV<S>{ptr<E>(lo.U[p]), G.Vh}, qdd::CloverV<S>{ptr<E>(lo.A[p]), G.Vh},
+                         qdd::CloverV<S>{ptr<E>(lo.Ai[p]), G.Vh}};
+  }
+  qdd::PackedView packed(qdd_prec prec, int nrhs, int even_only, void* field) const;
+  hipError_t dhat(qdd_prec prec, int nrhs, void* in, void* out);
+  hipError_t dw(qdd_prec prec, int nrhs, void* in, void* out);
+};
+
+#define HCK(x, ...)                                                                   \
+  do {                                                                                \
+    hipError_t e_ = (__VA_ARGS__);                                                         \
+    if (e_ != hipSuccess) {                                                           \
+      (x)->fail("HIP error %s at %s:%d", hipGetErrorString(e_), __FILE__, __LINE__); \
+      return QDD_EHIP;                                                                \
+    }                                                                                 \
+  } while (0)

@@ -1,0 +1,214 @@
+// Vector kernels of the outer flexible GCR (FP64 accumulation).  A "vector" is a
+// contiguous array of n complex numbers (one right-hand side of an internal
+// field); several right-hand sides sit at a fixed stride.  Reductions are
+// two-pass and deterministic: per-block partial sums in a fixed order, then one
+// thread per result sums the partials in block order (no floating-point atomics),
+// so repeated runs give bitwise identical results.
+#include "qdd_kernels.h"
+#include "qdd_blas.h"
+
+namespace qdd {
+
+template <class E>
+__device__ inline cx<double> ldz(const E* p);
+template <>
+__device__ inline cx<double> ldz<double2>(const double2* p) {
+  double2 v = *p;
+  return {v.x, v.y};
+}
+template <>
+__device__ inline cx<double> ldz<float2>(const float2* p) {
+  float2 v = *p;
+  return {(double)v.x, (double)v.y};
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// partial sums: part[(r*m + l) * nb + b] = sum over block b of conj(x_l[r]) y[r]
+template <class E, int MM>
+__global__ void __launch_bounds__(256) k_dots(const E* x, int64_t lstride, int64_t xrs, int m, const double2* y,
+                                              int64_t yrs, int64_t n, double2* part) {
+  __shared__ double sh[MM][4][2];
+  int r = blockIdx.y, nb = gridDim.x;
+  const E* xr = x + r * xrs;
+  const double2* yr = y + r * yrs;
+  cx<double> acc[MM];
+#pragma unroll
+  for (int l = 0; l < MM; ++l) acc[l] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)nb * blockDim.x) {
+    double2 yv = yr[i];
+    cx<double> yy{yv.x, yv.y};
+#pragma unroll
+    for (int l = 0; l < MM; ++l)
+      if (l < m) acc[l] = fmac_c(ldz(xr + l * lstride + i), yy, acc[l]);
+  }
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int l = 0; l < MM; ++l) {
+    if (l < m) {
+      double re = wave_sum(acc[l].re), im = wave_sum(acc[l].im);
+      if (lane == 0) {
+        sh[l][w][0] = re;
+        sh[l][w][1] = im;
+      }
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < m) {
+    int l = threadIdx.x;
+    double re = 0, im = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+      re += sh[l][k][0];
+      im += sh[l][k][1];
+    }
+    part[((int64_t)r * m + l) * nb + blockIdx.x] = make_double2(re, im);
+  }
+}
+
+__global__ void k_dots_final(const double2* part, int nb, int total, double2* out) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  double re = 0, im = 0;
+  for (int b = 0; b < nb; ++b) {
+    double2 v = part[(int64_t)t * nb + b];
+    re += v.x;
+    im += v.y;
+  }
+  out[t] = make_double2(re, im);
+}
+
+template <class E>
+hipError_t launch_dots(const E* x, int64_t lstride, int64_t xrs, int m, const double2* y, int64_t yrs, int64_t n,
+                       int nrhs, double2* part, double2* out, hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  int nb = (int)std::min<int64_t>(kDotBlocks, (n + 255) / 256);
+  dim3 grid(nb, nrhs);
+  if (m <= 1) hipLaunchKernelGGL((k_dots<E, 1>), grid, dim3(256), 0, st, x, lstride, xrs, m, y, yrs, n, part);
+  else if (m <= 4) hipLaunchKernelGGL((k_dots<E, 4>), grid, dim3(256), 0, st, x, lstride, xrs, m, y, yrs, n, part);
+  else if (m <= 8) hipLaunchKernelGGL((k_dots<E, 8>), grid, dim3(256), 0, st, x, lstride, xrs, m, y, yrs, n, part);
+  else if (m <= 16) hipLaunchKernelGGL((k_dots<E, 16>), grid, dim3(256), 0, st, x, lstride, xrs, m, y, yrs, n, part);
+  else if (m <= 32) hipLaunchKernelGGL((k_dots<E, 32>), grid, dim3(256), 0, st, x, lstride, xrs, m, y, yrs, n, part);
+  else return hipErrorInvalidValue;
+  int total = nrhs * m;
+  hipLaunchKernelGGL(k_dots_final, dim3((total + 63) / 64), dim3(64), 0, st, part, nb, total, out);
+  return hipGetLastError();
+}
+
+// y[r] += sgn * sum_l coef[r*ldc + l] * x_l[r]    (active[r] == 0 skips rhs r)
+template <class E, int MM>
+__global__ void __launch_bounds__(256) k_axpy_multi(double2* y, int64_t yrs, const E* x, int64_t lstride,
+                                                    int64_t xrs, int m, const double2* coef, int ldc, double sgn,
+                                                    int64_t n, const int* active) {
+  int r = blockIdx.y;
+  if (active && !active[r]) return;
+  __shared__ cx<double> c[MM];
+  if ((int)threadIdx.x < m) {
+    double2 v = coef[r * ldc + threadIdx.x];
+    c[threadIdx.x] = {sgn * v.x, sgn * v.y};
+  }
+  __syncthreads();
+  double2* yr = y + r * yrs;
+  const E* xr = x + r * xrs;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double2 yv = yr[i];
+    cx<double> acc{yv.x, yv.y};
+#pragma unroll
+    for (int l = 0; l < MM; ++l)
+      if (l < m) acc = fma_c(c[l], ldz(xr + l * lstride + i), acc);
+    yr[i] = make_double2(acc.re, acc.im);
+  }
+}
+
+template <class E>
+hipError_t launch_axpy_multi(double2* y, int64_t yrs, const E* x, int64_t lstride, int64_t xrs, int m,
+                             const double2* coef, int ldc, double sgn, int64_t n, int nrhs, const int* active,
+                             hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  int nb = (int)std::min<int64_t>(2048, (n + 255) / 256);
+  dim3 grid(nb, nrhs);
+  if (m <= 1) hipLaunchKernelGGL((k_axpy_multi<E, 1>), grid, dim3(256), 0, st, y, yrs, x, lstride, xrs, m, coef, ldc, sgn, n, active);
+  else if (m <= 4) hipLaunchKernelGGL((k_axpy_multi<E, 4>), grid, dim3(256), 0, st, y, yrs, x, lstride, xrs, m, coef, ldc, sgn, n, active);
+  else if (m <= 8) hipLaunchKernelGGL((k_axpy_multi<E, 8>), grid, dim3(256), 0, st, y, yrs, x, lstride, xrs, m, coef, ldc, sgn, n, active);
+  else if (m <= 16) hipLaunchKernelGGL((k_axpy_multi<E, 16>), grid, dim3(256), 0, st, y, yrs, x, lstride, xrs, m, coef, ldc, sgn, n, active);
+  else if (m <= 32) hipLaunchKernelGGL((k_axpy_multi<E, 32>), grid, dim3(256), 0, st, y, yrs, x, lstride, xrs, m, coef, ldc, sgn, n, active);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// y[r] = a * x[r] + b * y[r] with per-rhs real scalars (device arrays, may be null = 1/0)
+__global__ void k_axpby(double2* y, int64_t yrs, const double2* x, int64_t xrs, const double* a, const double* b,
+                        int64_t n, const int* active) {
+  int r = blockIdx.y;
+  if (active && !active[r]) return;
+  double av = a ? a[r] : 1.0, bv = b ? b[r] : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double2 xv = x[r * xrs + i], yv = y[r * yrs + i];
+    y[r * yrs + i] = make_double2(av * xv.x + bv * yv.x, av * xv.y + bv * yv.y);
+  }
+}
+
+hipError_t launch_axpby(double2* y, int64_t yrs, const double2* x, int64_t xrs, const double* a, const double* b,
+                        int64_t n, int nrhs, const int* active, hipStream_t st) {
+  int nb = (int)std::min<int64_t>(2048, (n + 255) / 256);
+  hipLaunchKernelGGL(k_axpby, dim3(nb, nrhs), dim3(256), 0, st, y, yrs, x, xrs, a, b, n, active);
+  return hipGetLastError();
+}
+
+// z[r] = x[r] - y[r]
+__global__ void k_sub(double2* z, const double2* x, const double2* y, int64_t rs, int64_t n) {
+  int r = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double2 a = x[r * rs + i], b = y[r * rs + i];
+    z[r * rs + i] = make_double2(a.x - b.x, a.y - b.y);
+  }
+}
+hipError_t launch_sub(double2* z, const double2* x, const double2* y, int64_t rs, int64_t n, int nrhs,
+                      hipStream_t st) {
+  int nb = (int)std::min<int64_t>(2048, (n + 255) / 256);
+  hipLaunchKernelGGL(k_sub, dim3(nb, nrhs), dim3(256), 0, st, z, x, y, rs, n);
+  return hipGetLastError();
+}
+
+// Gram-Schmidt bookkeeping on device (one thread per rhs):
+//  norm step: b = sqrt(|chi|^2), inv = 1/b (written as double2 for scaling)
+__global__ void k_norm_finish(const double2* nrm2, double* b, double* binv, int nrhs) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double v = sqrt(fmax(nrm2[r].x, 0.0));
+  b[r] = v;
+  binv[r] = v > 0 ? 1.0 / v : 0.0;
+}
+hipError_t launch_norm_finish(const double2* nrm2, double* b, double* binv, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm_finish, dim3((nrhs + 63) / 64), dim3(64), 0, st, nrm2, b, binv, nrhs);
+  return hipGetLastError();
+}
+
+// acc[r*lda + l] += src[r*m + l]   (accumulate Gram-Schmidt coefficients)
+__global__ void k_acc_coef(double2* acc, int lda, const double2* src, int m, int nrhs) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m * nrhs) return;
+  int r = t / m, l = t % m;
+  double2 a = acc[r * lda + l], s = src[t];
+  acc[r * lda + l] = make_double2(a.x + s.x, a.y + s.y);
+}
+hipError_t launch_acc_coef(double2* acc, int lda, const double2* src, int m, int nrhs, hipStream_t st) {
+  int t = m * nrhs;
+  if (t == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_acc_coef, dim3((t + 63) / 64), dim3(64), 0, st, acc, lda, src, m, nrhs);
+  return hipGetLastError();
+}
+
+template hipError_t launch_dots<double2>(const double2*, int64_t, int64_t, int, const double2*, int64_t, int64_t, int,
+                                         double2*, double2*, hipStream_t);
+template hipError_t launch_dots<float2>(const float2*, int64_t, int64_t, int, const double2*, int64_t, int64_t, int,
+                                        double2*, double2*, hipStream_t);
+template hipError_t launch_axpy_multi<double2>(double2*, int64_t, const double2*, int64_t, int64_t, int,
+                                               const double2*, int, double, int64_t, int, const int*, hipStream_t);
+template hipError_t launch_axpy_multi<float2>(double2*, int64_t, const float2*, int64_t, int64_t, int,
+                                              const double2*, int, double, int64_t, int, const int*, hipStream_t);
+
+}  // namespace qdd

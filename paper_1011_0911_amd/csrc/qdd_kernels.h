@@ -1,0 +1,55 @@
+// Launcher declarations shared by the kernel translation units and the host
+// library (qdd_api.cpp).
+#pragma once
+#include "qdd_internal.h"
+
+namespace qdd {
+
+// operator data of one storage precision
+template <class S>
+struct DevOp {
+  LinkV<S> U;       // hopping links (boundary sign folded in)
+  CloverV<S> A;     // A(x) on both parities
+  CloverV<S> Ainv;  // A(x)^{-1} on both parities
+};
+
+// launch shape (picked by the autotuner)
+struct LaunchCfg {
+  int block = 256;  // threads per block (one site per thread)
+  int nr = 1;       // right-hand sides per thread
+  int xcd = 1;      // XCD-aware block remap
+};
+
+template <class S>
+hipError_t launch_dhat(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> tmp, FieldV<S> out, int nrhs,
+                       const LaunchCfg& c, hipStream_t st);
+template <class S>
+hipError_t launch_dw(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> out, int64_t poff, int64_t spoff,
+                     int nrhs, const LaunchCfg& c, hipStream_t st);
+
+// ---- packing / conversion (qdd_pack.hip)
+// canonical complex128 links [V][4][3][3] -> FP64 internal hopping links (sign folded in)
+hipError_t launch_pack_links(const Geo& g, const double* canon, double2* U, hipStream_t st);
+// element-wise precision conversion of an array of n complex elements
+hipError_t launch_convert(const double2* in, float2* out, int64_t n, hipStream_t st);
+hipError_t launch_convert(const double2* in, __half2* out, int64_t n, hipStream_t st);
+// canonical spinors [nrhs][V or Vh][4][3] complex128 <-> internal fields
+// (even_only: canonical even-restricted input, internal [rhs][12][Vh]; otherwise
+// internal full field [rhs][parity][12][Vh])
+template <class S>
+hipError_t launch_pack_spinor(const Geo& g, const double* canon, FieldV<S> f, int nrhs, int even_only, int64_t poff,
+                              int64_t spoff, hipStream_t st);
+template <class S>
+hipError_t launch_unpack_spinor(const Geo& g, FieldV<S> f, double* canon, int nrhs, int even_only, int64_t poff,
+                                int64_t spoff, hipStream_t st);
+// convert between internal precisions (same layout): n sites per component, rhs count * parities
+template <class SI, class SO>
+hipError_t launch_field_convert(FieldV<SI> in, FieldV<SO> out, int nvec, hipStream_t st);
+
+// ---- clover (qdd_clover.hip)
+// builds A and A^{-1} (FP64, both parities) from the FP64 internal links; counts
+// blocks whose Cholesky factorisation fails into *bad (device int)
+hipError_t launch_clover(const Geo& g, const double2* U, double diag, double csw, double2* A, double2* Ai, int* bad,
+                         hipStream_t st);
+
+}  // namespace qdd

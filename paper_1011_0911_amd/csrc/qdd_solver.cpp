@@ -1,0 +1,260 @@
+// Outer flexible GCR in FP64 (the outer solver of the paper's locally deflated
+// Schwarz-preconditioned GCR, Sect. 3): phi_k = M(r_k), chi_k = D phi_k,
+// classical Gram-Schmidt with one re-orthogonalisation pass, r -= c_k chi_k; at
+// the end of a cycle the small triangular system is back-substituted on the host,
+// psi += sum alpha_k phi_k, and the residual is recomputed with the FP64
+// operator.  All right-hand sides of a batch advance together through batched
+// kernels; each keeps its own coefficients and convergence flag.
+#include "qdd_api_internal.h"
+#include "qdd_solver.h"
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+using namespace qdd;
+
+qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qdd_solve_info* info) {
+  const Layout& lo = x->lo;
+  hipStream_t st = x->st;
+  int nr = F.nrhs, nkv = x->cfg.nkv, nmx = x->cfg.nmx;
+  int64_t n = F.n;
+  double tol = x->cfg.tol;
+  double2 *r = x->ptr<double2>(lo.res), *t = x->ptr<double2>(lo.t64), *chi = x->ptr<double2>(lo.chi);
+  void* phi = x->ptr<void>(lo.phi);
+  double2 *part = x->ptr<double2>(lo.part), *coef = x->ptr<double2>(lo.coef);
+  double2 *ahist = x->ptr<double2>(lo.ahist), *chist = x->ptr<double2>(lo.chist), *rn2 = x->ptr<double2>(lo.rn2);
+  double *bhist = x->ptr<double>(lo.bhist), *binv = x->ptr<double>(lo.binv);
+  double2* alpha = x->ptr<double2>(lo.alpha);
+  int* active = x->ptr<int>(lo.active);
+  int64_t lstride = (int64_t)nr * n;
+  size_t phi_e = F.phi32 ? 8 : 16;
+  auto phi_k = [&](int k) { return (void*)((char*)phi + (size_t)k * lstride * phi_e); };
+  auto chi_k = [&](int k) { return chi + (size_t)k * lstride; };
+
+  auto t0 = std::chrono::steady_clock::now();
+  std::vector<double> tstage(8, 0.0);
+  auto tic = [&]() { return std::chrono::steady_clock::now(); };
+  auto since = [&](std::chrono::steady_clock::time_point a) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
+  };
+
+  // |eta|
+  std::vector<double2> h2(nr);
+  std::vector<double> etan(nr), rn(nr);
+  HCK(x, launch_dots<double2>(eta, 0, n, 1, eta, n, n, nr, part, rn2, st));
+  HCK(x, hipMemcpyAsync(h2.data(), rn2, nr * sizeof(double2), hipMemcpyDeviceToHost, st));
+  HCK(x, hipStreamSynchronize(st));
+  for (int i = 0; i < nr; ++i) etan[i] = std::sqrt(h2[i].x);
+  // psi = 0, r = eta
+  HCK(x, hipMemsetAsync(psi, 0, (size_t)nr * n * sizeof(double2), st));
+  HCK(x, hipMemcpyAsync(r, eta, (size_t)nr * n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  std::vector<int> act(nr), conv(nr, 0), iters(nr, 0), restarts(nr, 0);
+  for (int i = 0; i < nr; ++i) {
+    rn[i] = etan[i];
+    conv[i] = !(etan[i] > 0);
+    act[i] = !conv[i];
+  }
+  std::vector<double2> ah((size_t)kMaxKv * nr * kMaxKv), chh((size_t)kMaxKv * nr), al((size_t)nr * kMaxKv);
+  std::vector<double> bh((size_t)kMaxKv * nr);
+  bool nonfinite = false;
+  int total_it = 0;
+  qdd_status status = QDD_OK;
+  while (true) {
+    bool any = false;
+    for (int i = 0; i < nr; ++i) any |= act[i];
+    if (!any || total_it >= nmx) break;
+    HCK(x, hipMemcpyAsync(active, act.data(), nr * sizeof(int), hipMemcpyHostToDevice, st));
+    std::vector<int> ks(nr, 0);
+    int k = 0;
+    for (; k < nkv && total_it < nmx; ++k) {
+      auto ta = tic();
+      // phi_k = M(r)
+      qdd_status s = F.prec(r, phi_k(k));
+      if (s != QDD_OK) return s;
+      if (F.sync_stages) HCK(x, hipStreamSynchronize(st));
+      tstage[1] += since(ta);
+      ta = tic();
+      // chi_k = D phi_k
+      if (F.phi32) {
+        FieldV<float> src{(float2*)phi_k(k), nullptr, n, n, (int)n};
+        FieldV<double> dst{t, nullptr, n, n, (int)n};
+        // viewed as nr vectors of n/12 "sites" of 12 components each
+        src.n = dst.n = (int)(n / 12);
+        HCK(x, launch_field_convert<float, double>(src, dst, nr, st));
+        s = F.op(t, chi_k(k));
+      } else {
+        s = F.op((const double2*)phi_k(k), chi_k(k));
+      }
+      if (s != QDD_OK) return s;
+      if (F.sync_stages) HCK(x, hipStreamSynchronize(st));
+      tstage[2] += since(ta);
+      ta = tic();
+      // Gram-Schmidt against chi_0 .. chi_{k-1}, two passes
+      double2* ak = ahist + (size_t)k * nr * kMaxKv;
+      HCK(x, hipMemsetAsync(ak, 0, (size_t)nr * kMaxKv * sizeof(double2), st));
+      if (k > 0)
+        for (int pass = 0; pass < 2; ++pass) {
+          HCK(x, launch_dots<double2>(chi, lstride, n, k, chi_k(k), n, n, nr, part, coef, st));
+          HCK(x, launch_axpy_multi<double2>(chi_k(k), n, chi, lstride, n, k, coef, k, -1.0, n, nr, nullptr, st));
+          HCK(x, launch_acc_coef(ak, kMaxKv, coef, k, nr, st));
+        }
+      HCK(x, launch_dots<double2>(chi_k(k), 0, n, 1, chi_k(k), n, n, nr, part, rn2, st));
+      HCK(x, launch_norm_finish(rn2, bhist + (size_t)k * nr, binv, nr, st));
+      HCK(x, launch_axpby(chi_k(k), n, chi_k(k), n, binv, nullptr, n, nr, nullptr, st));
+      // c_k = <chi_k, r>, r -= c_k chi_k
+      HCK(x, launch_dots<double2>(chi_k(k), 0, n, 1, r, n, n, nr, part, chist + (size_t)k * nr, st));
+      HCK(x, launch_axpy_multi<double2>(r, n, chi_k(k), 0, n, 1, chist + (size_t)k * nr, 1, -1.0, n, nr, active,
+                                        st));
+      HCK(x, launch_dots<double2>(r, 0, n, 1, r, n, n, nr, part, rn2, st));
+      HCK(x, hipMemcpyAsync(h2.data(), rn2, nr * sizeof(double2), hipMemcpyDeviceToHost, st));
+      HCK(x, hipStreamSynchronize(st));
+      tstage[3] += since(ta);
+      ++total_it;
+      bool changed = false, any2 = false;
+      for (int i = 0; i < nr; ++i) {
+        if (!act[i]) continue;
+        ks[i] = k + 1;
+        iters[i]++;
+        rn[i] = std::sqrt(std::fabs(h2[i].x));
+        if (!std::isfinite(h2[i].x)) {
+          nonfinite = true;
+          act[i] = 0;
+          changed = true;
+        } else if (rn[i] <= tol * etan[i]) {
+          act[i] = 0;  // recursive residual converged: stop this rhs for the cycle
+          changed = true;
+        }
+        any2 |= act[i];
+      }
+      if (!any2) { ++k; break; }
+      if (changed) HCK(x, hipMemcpyAsync(active, act.data(), nr * sizeof(int), hipMemcpyHostToDevice, st));
+    }
+    int kk = k;
+    // back substitution per rhs
+    auto ta = tic();
+    HCK(x, hipMemcpyAsync(ah.data(), ahist, (size_t)kk * nr * kMaxKv * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HCK(x, hipMemcpyAsync(bh.data(), bhist, (size_t)kk * nr * sizeof(double), hipMemcpyDeviceToHost, st));
+    HCK(x, hipMemcpyAsync(chh.data(), chist, (size_t)kk * nr * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HCK(x, hipStreamSynchronize(st));
+    std::fill(al.begin(), al.end(), double2{0.0, 0.0});
+    for (int i = 0; i < nr; ++i) {
+      int m = ks[i];
+      for (int j = m - 1; j >= 0; --j) {
+        double sr = chh[(size_t)j * nr + i].x, si = chh[(size_t)j * nr + i].y;
+        for (int l = j + 1; l < m; ++l) {
+          double2 a = ah[((size_t)l * nr + i) * kMaxKv + j], b = al[(size_t)i * kMaxKv + l];
+          sr -= a.x * b.x - a.y * b.y;
+          si -= a.x * b.y + a.y * b.x;
+        }
+        double bj = bh[(size_t)j * nr + i];
+        al[(size_t)i * kMaxKv + j] = bj > 0 ? double2{sr / bj, si / bj} : double2{0.0, 0.0};
+      }
+    }
+    HCK(x, hipMemcpyAsync(alpha, al.data(), (size_t)nr * kMaxKv * sizeof(double2), hipMemcpyHostToDevice, st));
+    if (F.phi32)
+      HCK(x, launch_axpy_multi<float2>(psi, n, (const float2*)phi, lstride, n, kk, alpha, kMaxKv, 1.0, n, nr, nullptr,
+                                       st));
+    else
+      HCK(x, launch_axpy_multi<double2>(psi, n, (const double2*)phi, lstride, n, kk, alpha, kMaxKv, 1.0, n, nr,
+                                        nullptr, st));
+    // true residual r = eta - D psi
+    qdd_status s = F.op(psi, t);
+    if (s != QDD_OK) return s;
+    HCK(x, launch_sub(r, eta, t, n, n, nr, st));
+    HCK(x, launch_dots<double2>(r, 0, n, 1, r, n, n, nr, part, rn2, st));
+    HCK(x, hipMemcpyAsync(h2.data(), rn2, nr * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HCK(x, hipStreamSynchronize(st));
+    tstage[7] += since(ta);
+    for (int i = 0; i < nr; ++i) {
+      if (conv[i]) continue;
+      rn[i] = std::sqrt(std::fabs(h2[i].x));
+      if (!std::isfinite(h2[i].x)) {
+        nonfinite = true;
+        act[i] = 0;
+      } else if (rn[i] <= tol * etan[i]) {
+        conv[i] = 1;
+        act[i] = 0;
+      } else {
+        act[i] = 1;
+        restarts[i]++;
+      }
+    }
+    if (nonfinite) break;
+  }
+  double tot = since(t0);
+  for (int i = 0; i < nr; ++i) {
+    if (!conv[i]) status = QDD_ENOCONV;
+    if (info) {
+      info[i].iters = iters[i];
+      info[i].restarts = conv[i] ? restarts[i] : std::max(0, restarts[i] - 1);
+      info[i].converged = conv[i];
+      info[i].fallbacks = F.fallbacks ? F.fallbacks[i] : 0;
+      info[i].true_res = etan[i] > 0 ? rn[i] / etan[i] : 0.0;
+      for (int s2 = 0; s2 < 8; ++s2) info[i].t_ms[s2] = tstage[s2];
+      info[i].t_ms[0] = tot;
+      for (int s2 = 4; s2 < 7; ++s2) info[i].t_ms[s2] = F.tstage ? F.tstage[s2] : 0.0;
+    }
+  }
+  if (status != QDD_OK) x->fail(nonfinite ? "non-finite residual" : "no convergence within nmx iterations");
+  return status;
+}
+
+// ------------------------------------------------------------------ entry points
+extern "C" qdd_status qdd_solve_dhat(qdd_ctx* x, int nrhs, const double* eta_e, double* psi_e,
+                                     qdd_solve_info* info) {
+  if (!x || !eta_e || !psi_e || nrhs < 1 || nrhs > x->cfg.max_nrhs) {
+    if (x) x->fail("qdd_solve_dhat: invalid arguments");
+    return QDD_EINVAL;
+  }
+  if (!x->have_clover) { x->fail("qdd_solve_dhat before qdd_set_params"); return QDD_ESTATE; }
+  const Layout& lo = x->lo;
+  int64_t n = (int64_t)12 * x->G.Vh;
+  double2 *eta = x->ptr<double2>(lo.eta), *psi = x->ptr<double2>(lo.psi);
+  PackedView pe = x->packed(QDD_F64, nrhs, 1, eta);
+  HCK(x, launch_pack_spinor<double>(x->G, eta_e, pe.f64, nrhs, 1, pe.poff, pe.spoff, x->st));
+  FgcrOps F;
+  F.n = n;
+  F.nrhs = nrhs;
+  F.phi32 = false;
+  F.op = [&](const double2* in, double2* out) -> qdd_status {
+    HCK(x, x->dhat(QDD_F64, nrhs, (void*)in, out));
+    return QDD_OK;
+  };
+  F.prec = [&](const double2* r, void* phi) -> qdd_status {
+    HCK(x, hipMemcpyAsync(phi, r, (size_t)nrhs * n * sizeof(double2), hipMemcpyDeviceToDevice, x->st));
+    return QDD_OK;
+  };
+  // the FGCR buffers hold full fields; with even fields only their first half is used
+  qdd_status s = run_fgcr(x, F, eta, psi, info);
+  PackedView pp = x->packed(QDD_F64, nrhs, 1, psi);
+  HCK(x, launch_unpack_spinor<double>(x->G, pp.f64, psi_e, nrhs, 1, pp.poff, pp.spoff, x->st));
+  HCK(x, hipStreamSynchronize(x->st));
+  return s;
+}
+
+extern "C" qdd_status qdd_solve(qdd_ctx* x, int nrhs, const double* eta_c, double* psi_c, qdd_solve_info* info) {
+  if (!x || !eta_c || !psi_c || nrhs < 1 || nrhs > x->cfg.max_nrhs) {
+    if (x) x->fail("qdd_solve: invalid arguments");
+    return QDD_EINVAL;
+  }
+  if (!x->have_clover) { x->fail("qdd_solve before qdd_set_params"); return QDD_ESTATE; }
+  if (x->cfg.precond == QDD_PRECOND_DFL && !x->have_dfl) {
+    x->fail("deflated solve before qdd_dfl_build");
+    return QDD_ESTATE;
+  }
+  const Layout& lo = x->lo;
+  int64_t n = (int64_t)24 * x->G.Vh;
+  double2 *eta = x->ptr<double2>(lo.eta), *psi = x->ptr<double2>(lo.psi);
+  PackedView pe = x->packed(QDD_F64, nrhs, 0, eta);
+  HCK(x, launch_pack_spinor<double>(x->G, eta_c, pe.f64, nrhs, 0, pe.poff, pe.spoff, x->st));
+  FgcrOps F;
+  qdd_status s0 = make_solver_ops(x, nrhs, F);
+  if (s0 != QDD_OK) return s0;
+  qdd_status s = run_fgcr(x, F, eta, psi, info);
+  PackedView pp = x->packed(QDD_F64, nrhs, 0, psi);
+  HCK(x, launch_unpack_spinor<double>(x->G, pp.f64, psi_c, nrhs, 0, pp.poff, pp.spoff, x->st));
+  HCK(x, hipStreamSynchronize(x->st));
+  return s;
+}

@@ -1,0 +1,259 @@
+"""Python binding of the qdd C ABI (include/qdd.h): argument marshalling only.
+
+PyTorch provides device memory (the workspace and the fields) and the stream;
+every step of the computation runs in the HIP library libqdd.so.  If the
+library has not been built this module raises on load -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqdd.so")
+
+F64, F32, F16 = 0, 1, 2
+PRECOND_NONE, PRECOND_SAP, PRECOND_DFL = 0, 1, 2
+KERNEL_DHAT, KERNEL_DW = 0, 1
+
+QDD_OK, QDD_EINVAL, QDD_ESTATE, QDD_ESINGULAR, QDD_ENOCONV, QDD_EHIP, QDD_ENOWS = 0, -1, -2, -3, -4, -5, -6
+_NAMES = {0: "QDD_OK", -1: "QDD_EINVAL", -2: "QDD_ESTATE", -3: "QDD_ESINGULAR", -4: "QDD_ENOCONV",
+          -5: "QDD_EHIP", -6: "QDD_ENOWS"}
+
+
+class QddError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int * 4), ("bc_time", ctypes.c_int)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("max_nrhs", ctypes.c_int),
+        ("sap_bs", ctypes.c_int * 4), ("ncy", ctypes.c_int), ("nmr", ctypes.c_int), ("sap_prec", ctypes.c_int),
+        ("dfl_Ns", ctypes.c_int), ("dfl_bs", ctypes.c_int * 4), ("dfl_nit", ctypes.c_int),
+        ("dfl_coarse_tol", ctypes.c_double), ("dfl_coarse_nmx", ctypes.c_int),
+        ("nkv", ctypes.c_int), ("nmx", ctypes.c_int), ("tol", ctypes.c_double), ("precond", ctypes.c_int),
+        ("use_net", ctypes.c_int), ("net_nl", ctypes.c_int), ("net_ch", ctypes.c_int * 8),
+    ]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
+                ("fallbacks", ctypes.c_int), ("true_res", ctypes.c_double), ("t_ms", ctypes.c_double * 8)]
+
+    def as_dict(self):
+        return {"iters": self.iters, "restarts": self.restarts, "converged": bool(self.converged),
+                "fallbacks": self.fallbacks, "true_res": self.true_res, "t_ms": list(self.t_ms)}
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+
+# exported symbol -> (restype, argtypes); the test-suite checks this list against include/qdd.h
+SIGNATURES = {
+    "qdd_config_default": (None, [ctypes.POINTER(Config)]),
+    "qdd_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Geom), ctypes.POINTER(Config)]),
+    "qdd_create": (_i, [ctypes.POINTER(Geom), ctypes.POINTER(Config), _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    "qdd_destroy": (None, [_vp]),
+    "qdd_last_error": (ctypes.c_char_p, [_vp]),
+    "qdd_set_gauge": (_i, [_vp, _vp]),
+    "qdd_set_params": (_i, [_vp, _d, _d]),
+    "qdd_field_bytes": (ctypes.c_size_t, [_vp, _i, _i, _i]),
+    "qdd_pack_field": (_i, [_vp, _i, _i, _i, _vp, _vp]),
+    "qdd_unpack_field": (_i, [_vp, _i, _i, _i, _vp, _vp]),
+    "qdd_dw_hat": (_i, [_vp, _i, _i, _vp, _vp]),
+    "qdd_dw": (_i, [_vp, _i, _i, _vp, _vp]),
+    "qdd_sap": (_i, [_vp, _i, _vp, _vp]),
+    "qdd_dfl_build": (_i, [_vp, _vp]),
+    "qdd_solve": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "qdd_solve_dhat": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "qdd_set_launch": (_i, [_vp, _i, _i, _i, _i, _i]),
+    "qdd_get_launch": (_i, [_vp, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+}
+
+
+def lib():
+    """Loads libqdd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1011_0911_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def default_config(**kw) -> Config:
+    c = Config()
+    lib().qdd_config_default(ctypes.byref(c))
+    for k, v in kw.items():
+        if k in ("sap_bs", "dfl_bs", "net_ch"):
+            arr = getattr(c, k)
+            for j, x in enumerate(v):
+                arr[j] = int(x)
+        else:
+            setattr(c, k, v)
+    return c
+
+
+def make_geom(L, bc=-1) -> Geom:
+    g = Geom()
+    for j in range(4):
+        g.L[j] = int(L[j])
+    g.bc_time = int(bc)
+    return g
+
+
+def workspace_bytes(L, cfg: Config, bc=-1) -> int:
+    g = make_geom(L, bc)
+    return int(lib().qdd_workspace_bytes(ctypes.byref(g), ctypes.byref(cfg)))
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One qdd context: workspace, gauge field, clover field, deflation subspace."""
+
+    def __init__(self, L, cfg: Config | None = None, bc: int = -1, device="cuda:0", stream=None):
+        self.L = tuple(int(x) for x in L)
+        self.V = self.L[0] * self.L[1] * self.L[2] * self.L[3]
+        self.Vh = self.V // 2
+        self.cfg = cfg if cfg is not None else default_config()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        g = make_geom(self.L, bc)
+        nbytes = lib().qdd_workspace_bytes(ctypes.byref(g), ctypes.byref(self.cfg))
+        if nbytes == 0:
+            raise QddError(QDD_EINVAL, lib().qdd_last_error(None).decode())
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        st = lib().qdd_create(ctypes.byref(g), ctypes.byref(self.cfg), _ptr(self.ws), nbytes,
+                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != QDD_OK:
+            raise QddError(st, lib().qdd_last_error(None).decode())
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.qdd_destroy(self.h)
+            self.h = None
+
+    # -- helpers
+    def _check(self, st):
+        if st != QDD_OK:
+            raise QddError(st, lib().qdd_last_error(self.h).decode())
+
+    def _c128(self, a) -> torch.Tensor:
+        t = torch.as_tensor(a)
+        t = t.to(device=self.device, dtype=torch.complex128).contiguous()
+        return t
+
+    # -- set-up
+    def set_gauge(self, U):
+        self._U = self._c128(U)
+        assert self._U.numel() == self.V * 36
+        self._check(lib().qdd_set_gauge(self.h, _ptr(self._U)))
+
+    def set_params(self, kappa: float, csw: float):
+        self._check(lib().qdd_set_params(self.h, float(kappa), float(csw)))
+
+    # -- packed fields
+    def field_bytes(self, prec, nrhs, even_only):
+        return int(lib().qdd_field_bytes(self.h, prec, nrhs, int(even_only)))
+
+    def pack(self, prec, canon, even_only):
+        c = self._c128(canon)
+        per = (self.Vh if even_only else self.V) * 12
+        nrhs = c.numel() // per
+        out = torch.empty(self.field_bytes(prec, nrhs, even_only), dtype=torch.uint8, device=self.device)
+        self._check(lib().qdd_pack_field(self.h, prec, nrhs, int(even_only), _ptr(c), _ptr(out)))
+        return out
+
+    def unpack(self, prec, field, nrhs, even_only):
+        n = (self.Vh if even_only else self.V)
+        out = torch.empty((nrhs, n, 4, 3), dtype=torch.complex128, device=self.device)
+        self._check(lib().qdd_unpack_field(self.h, prec, nrhs, int(even_only), _ptr(field), _ptr(out)))
+        return out
+
+    def empty_field(self, prec, nrhs, even_only):
+        return torch.empty(self.field_bytes(prec, nrhs, even_only), dtype=torch.uint8, device=self.device)
+
+    # -- operators on packed fields
+    def dw_hat(self, prec, nrhs, fin, fout):
+        self._check(lib().qdd_dw_hat(self.h, prec, nrhs, _ptr(fin), _ptr(fout)))
+
+    def dw(self, prec, nrhs, fin, fout):
+        self._check(lib().qdd_dw(self.h, prec, nrhs, _ptr(fin), _ptr(fout)))
+
+    # -- canonical convenience wrappers (pack -> apply -> unpack)
+    def apply_dhat(self, psi_e, prec=F64):
+        c = self._c128(psi_e)
+        nrhs = c.numel() // (self.Vh * 12)
+        fi = self.pack(prec, c, True)
+        fo = self.empty_field(prec, nrhs, True)
+        self.dw_hat(prec, nrhs, fi, fo)
+        return self.unpack(prec, fo, nrhs, True)
+
+    def apply_dw(self, psi, prec=F64):
+        c = self._c128(psi)
+        nrhs = c.numel() // (self.V * 12)
+        fi = self.pack(prec, c, False)
+        fo = self.empty_field(prec, nrhs, False)
+        self.dw(prec, nrhs, fi, fo)
+        return self.unpack(prec, fo, nrhs, False)
+
+    # -- solver
+    def sap(self, eta):
+        c = self._c128(eta)
+        nrhs = c.numel() // (self.V * 12)
+        out = torch.empty((nrhs, self.V, 4, 3), dtype=torch.complex128, device=self.device)
+        self._check(lib().qdd_sap(self.h, nrhs, _ptr(c), _ptr(out)))
+        return out
+
+    def dfl_build(self, init):
+        c = self._c128(init)
+        assert c.numel() == self.cfg.dfl_Ns * self.V * 12
+        self._check(lib().qdd_dfl_build(self.h, _ptr(c)))
+
+    def solve(self, eta, check=True):
+        c = self._c128(eta)
+        nrhs = c.numel() // (self.V * 12)
+        out = torch.empty((nrhs, self.V, 4, 3), dtype=torch.complex128, device=self.device)
+        info = (SolveInfo * nrhs)()
+        st = lib().qdd_solve(self.h, nrhs, _ptr(c), _ptr(out), info)
+        if check:
+            self._check(st)
+        return out, [i.as_dict() for i in info], st
+
+    def solve_dhat(self, eta_e, check=True):
+        c = self._c128(eta_e)
+        nrhs = c.numel() // (self.Vh * 12)
+        out = torch.empty((nrhs, self.Vh, 4, 3), dtype=torch.complex128, device=self.device)
+        info = (SolveInfo * nrhs)()
+        st = lib().qdd_solve_dhat(self.h, nrhs, _ptr(c), _ptr(out), info)
+        if check:
+            self._check(st)
+        return out, [i.as_dict() for i in info], st
+
+    def set_launch(self, kernel, prec, block, nr, xcd):
+        self._check(lib().qdd_set_launch(self.h, kernel, prec, block, nr, xcd))
+
+    def get_launch(self, kernel, prec):
+        b, n, x = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        self._check(lib().qdd_get_launch(self.h, kernel, prec, ctypes.byref(b), ctypes.byref(n), ctypes.byref(x)))
+        return b.value, n.value, x.value

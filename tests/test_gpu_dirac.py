@@ -1,0 +1,112 @@
+"""GPU parity of the clover-Wilson operator D (Eq. 1) and its Schur complement
+Dhat (Eq. 2) against the FP64 CPU oracle, through the C ABI.
+
+Tolerances (max-abs error / max-abs reference): FP64 1e-12; FP32 1e-5; FP16
+storage 5e-3 (each stored operand -- spinor, link, clover, the odd-site
+intermediate and the output -- is rounded to FP16 with unit roundoff 2^-11 ~
+4.9e-4 relative to its site maximum; seven such roundings along the Dhat path
+bound the error by ~7 u_h ~ 3.4e-3, rounded up)."""
+import numpy as np
+import pytest
+
+from paper_1011_0911_amd import synth as S
+from tests.gpu_util import make_ctx, relerr, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-5, 2: 5e-3}
+LATTICES = [(4, 4, 4, 4), (6, 4, 4, 4), (8, 6, 4, 4), (4, 4, 6, 8)]
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import torch
+    from paper_1011_0911_amd import qdd
+
+    assert torch.cuda.is_available()
+    qdd.lib()
+    return qdd
+
+
+@pytest.mark.parametrize("L", LATTICES)
+@pytest.mark.parametrize("bc", [-1, 1])
+def test_dw_parity_all_precisions(Q, orc, L, bc):
+    V = int(np.prod(L))
+    ctx, U = make_ctx(Q, L, 0.5, 0.1355, 1.9, 100 + V, bc=bc)
+    A, _ = orc.clover(L, U, 0.1355, 1.9)
+    psi = S.gaussian_field(V, 7)
+    ref = orc.apply_D(L, U, A, psi, bc=bc)
+    for prec in (0, 1, 2):
+        out = to_np(ctx.apply_dw(psi[None], prec))[0]
+        e = relerr(out, ref)
+        print(f"D L={L} bc={bc} prec={prec} err={e:.2e}")
+        assert e < TOL[prec], (prec, e)
+
+
+@pytest.mark.parametrize("L", LATTICES)
+def test_dhat_parity_all_precisions(Q, orc, L):
+    V = int(np.prod(L))
+    ctx, U = make_ctx(Q, L, 0.6, 0.1357, 1.9, 200 + V)
+    A, Ai = orc.clover(L, U, 0.1357, 1.9)
+    pe = S.gaussian_field(V // 2, 8)
+    ref = orc.apply_Dhat(L, U, A, Ai, pe)
+    for prec in (0, 1, 2):
+        out = to_np(ctx.apply_dhat(pe[None], prec))[0]
+        e = relerr(out, ref)
+        print(f"Dhat L={L} prec={prec} err={e:.2e}")
+        assert e < TOL[prec], (prec, e)
+
+
+def test_config1_field_dhat_and_csw0(Q, orc):
+    L = (4, 4, 4, 4)
+    ctx, U = make_ctx(Q, L, 0.3, 0.13, 1.9, S.gauge_seed(1))
+    A, Ai = orc.clover(L, U, 0.13, 1.9)
+    pe = S.gaussian_field(256, S.source_seed(1))[S.even_sites(L)]
+    assert relerr(to_np(ctx.apply_dhat(pe[None], 0))[0], orc.apply_Dhat(L, U, A, Ai, pe)) < 1e-12
+    ctx.set_params(0.13, 0.0)
+    A0, Ai0 = orc.clover(L, U, 0.13, 0.0)
+    assert relerr(to_np(ctx.apply_dhat(pe[None], 0))[0], orc.apply_Dhat(L, U, A0, Ai0, pe)) < 1e-12
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_batched_equals_single_rhs(Q, kernel):
+    L = (8, 6, 4, 4)
+    V = int(np.prod(L))
+    ctx, U = make_ctx(Q, L, 0.5, 0.1355, 1.9, 301, max_nrhs=5)
+    n = V // 2 if kernel == 0 else V
+    psi = S.gaussian_field(n, 9, nrhs=5)
+    app = ctx.apply_dhat if kernel == 0 else ctx.apply_dw
+    for prec in (0, 1):
+        ref = np.stack([to_np(app(psi[r:r + 1], prec))[0] for r in range(5)])
+        for block, nr, xcd in [(64, 1, 0), (128, 2, 1), (256, 4, 1), (192, 4, 0)]:
+            ctx.set_launch(kernel, prec, block, nr, xcd)
+            out = to_np(app(psi, prec))
+            assert np.array_equal(out, ref), (prec, block, nr, xcd)
+        ctx.set_launch(kernel, prec, 256, 1, 1)
+
+
+def test_pack_unpack_roundtrip(Q):
+    L = (4, 4, 4, 8)
+    ctx, U = make_ctx(Q, L, 0.5, 0.1355, 1.9, 302, max_nrhs=2)
+    psi = S.gaussian_field(512, 10, nrhs=2)
+    for even in (0, 1):
+        src = psi[:, :256] if even else psi
+        for prec, tol in ((0, 0.0), (1, 1e-7), (2, 1e-3)):
+            f = ctx.pack(prec, src, even)
+            back = to_np(ctx.unpack(prec, f, 2, even))
+            assert relerr(back, src) <= tol, (even, prec)
+
+
+def test_state_and_singular_errors(Q):
+    import torch
+
+    L = (4, 4, 4, 4)
+    c = Q.Context(L)
+    with pytest.raises(Q.QddError) as e:
+        c.apply_dhat(np.zeros((1, 128, 4, 3), complex))
+    assert e.value.status == Q.QDD_ESTATE
+    c.set_gauge(torch.from_numpy(S.random_su3_links(L, 0.6, 5)))
+    with pytest.raises(Q.QddError) as e:
+        c.set_params(0.1357, 200.0)
+    assert e.value.status == Q.QDD_ESINGULAR
+    c.set_params(0.1357, 1.9)
