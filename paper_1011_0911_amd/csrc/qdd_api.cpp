@@ -46,8 +46,13 @@ static bool valid_blocks(const qdd_geom* g, const int* bs, bool need_even_count,
 bool valid_sap_blocks(const qdd_geom* g, const qdd_config* c, std::string* why) {
   if (!valid_blocks(g, c->sap_bs, true, why, "SAP")) return false;
   int nsite = c->sap_bs[0] * c->sap_bs[1] * c->sap_bs[2] * c->sap_bs[3];
-  if (nsite > kSapMaxSites || (nsite & 1)) {
-    *why = "SAP blocks must hold an even number of sites, at most 256";
+  for (int i = 0; i < 4; ++i)
+    if (c->sap_bs[i] & 1) {
+      *why = "SAP block extents must be even";
+      return false;
+    }
+  if (nsite > kSapMaxSites) {
+    *why = "SAP blocks may hold at most 256 sites";
     return false;
   }
   return true;

@@ -1,0 +1,359 @@
+// Schwarz alternating procedure (the "Schwarz-preconditioned" part of the
+// paper's solver, Sect. 3): multiplicative two-colour SAP with minimal-residual
+// block solves on the even-odd block operator.
+//
+// One workgroup per block, one lane per site (even sites in the low lanes, odd
+// sites in the high lanes).  A half-sweep over the blocks of one colour does,
+// for every block Lambda and every right-hand side:
+//   rho_L += 1/2 H_face V        (corrections V of the neighbouring blocks of the
+//                                 other colour, made in the previous half-sweep)
+//   b      = rho_e + 1/2 H_L A_o^{-1} rho_o
+//   x = 0, r = b; nmr times: p = Dhat_L r, alpha = <p,r>/<p,p>, x += alpha r, r -= alpha p
+//   v_e = x, v_o = A_o^{-1} (rho_o + 1/2 H_L v_e)
+//   psi_L += v, V_L = v, rho_L = (r on even sites, 0 on odd sites)
+// (D = A - H/2; H_L the hops inside the block, H_face those across its faces.)
+// The new block residual needs no extra operator application: on odd sites it is
+// zero by construction and on even sites it is the MR residual r.
+//
+// Within a block the hopping terms are exchanged as projected half-spinors in
+// LDS: every source site writes, per direction, the projection needed by its
+// forward neighbour and the U^dag-transported projection needed by its backward
+// neighbour, so each lane only ever multiplies with its own forward links.  For
+// FP32 and FP16 storage the own links and the clover block stay in registers for
+// the whole half-sweep and are reused across all MR steps and right-hand sides.
+#include "qdd_kernels.h"
+#include "qdd_sap.h"
+
+namespace qdd {
+
+template <class S>
+__device__ inline cx<typename St<S>::T> cvt(typename St<S>::E e);
+template <>
+__device__ inline cx<double> cvt<double>(double2 e) { return {e.x, e.y}; }
+template <>
+__device__ inline cx<float> cvt<float>(float2 e) { return {e.x, e.y}; }
+template <>
+__device__ inline cx<float> cvt<__half>(__half2 e) {
+  float2 f = __half22float2(e);
+  return {f.x, f.y};
+}
+
+template <class T>
+__device__ inline T wsum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// half-spinor exchange buffer: [slot][component][source site]
+template <class T, int NSLOT>
+struct Exch {
+  cx<T> v[NSLOT][6][kSapMaxHalf];
+};
+
+template <class S, class P, int DR>
+__global__ void __launch_bounds__(256) k_sap_half(SapArgs<S, P> a) {
+  typedef typename St<S>::T T;
+  typedef typename St<S>::E E;
+  constexpr bool REG = sizeof(S) <= 4;  // FP32 / FP16: own links + clover in registers
+  __shared__ Exch<T, 2 * DR> ex;
+  __shared__ T red[8][4];
+  const Geo& g = a.g;
+  const int nsb = a.bs[0] * a.bs[1] * a.bs[2] * a.bs[3], nsh = nsb >> 1;
+  const int t = threadIdx.x;
+  const int q = t >= nsh;  // parity of this lane's site
+  const int j = t - q * nsh;
+  // this block: the blockIdx.x-th block of colour a.col
+  int bc[4];
+  {
+    int bl = 2 * blockIdx.x;
+    int nbh3 = a.nb[3];
+    bc[3] = bl % nbh3;
+    int rr = bl / nbh3;
+    bc[2] = rr % a.nb[2];
+    rr /= a.nb[2];
+    bc[1] = rr % a.nb[1];
+    bc[0] = rr / a.nb[1];
+    bc[3] += (a.col + bc[0] + bc[1] + bc[2] + bc[3]) & 1;
+  }
+  // local coordinates of the site
+  int y[4];
+  {
+    int l = 2 * j;
+    y[3] = l % a.bs[3];
+    int rr = l / a.bs[3];
+    y[2] = rr % a.bs[2];
+    rr /= a.bs[2];
+    y[1] = rr % a.bs[1];
+    y[0] = rr / a.bs[1];
+    y[3] += (q + y[0] + y[1] + y[2] + y[3]) & 1;
+  }
+  int x[4];
+  for (int m = 0; m < 4; ++m) x[m] = bc[m] * a.bs[m] + y[m];
+  const int i = lex_of(g, x) >> 1;
+  // neighbour slots inside the block (-1 if the hop crosses a face)
+  int nin[4][2];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      int z[4] = {y[0], y[1], y[2], y[3]};
+      z[m] += d == 0 ? 1 : -1;
+      bool in = z[m] >= 0 && z[m] < a.bs[m];
+      nin[m][d] = in ? ((((z[0] * a.bs[1] + z[1]) * a.bs[2] + z[2]) * a.bs[3] + z[3]) >> 1) : -1;
+    }
+  }
+  // own forward links and clover block (A on even sites, A^{-1} on odd sites)
+  E ureg[REG ? 4 : 1][9];
+  E creg[REG ? 36 : 1];
+  const E* ubase = a.U.p + (int64_t)(q * 4) * 9 * a.U.n + i;
+  const CloverV<S> cl = q == 0 ? a.A : a.Ai;
+  const E* cbase = cl.p + (int64_t)q * 36 * cl.n + i;
+  if constexpr (REG) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) ureg[m][k] = ubase[(int64_t)(m * 9 + k) * a.U.n];
+#pragma unroll
+    for (int k = 0; k < 36; ++k) creg[k] = cbase[(int64_t)k * cl.n];
+  }
+  auto link = [&](int m, cx<T> u[9]) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      if constexpr (REG) u[k] = cvt<S>(ureg[m][k]);
+      else u[k] = cvt<S>(ubase[(int64_t)(m * 9 + k) * a.U.n]);
+    }
+  };
+  auto clover = [&](const cx<T> in[12], cx<T> out[12]) {
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+      cx<T> c[18];
+#pragma unroll
+      for (int k = 0; k < 18; ++k) {
+        if constexpr (REG) c[k] = cvt<S>(creg[blk * 18 + k]);
+        else c[k] = cvt<S>(cbase[(int64_t)(blk * 18 + k) * cl.n]);
+      }
+      herm6_mul<T>(c, in + 6 * blk, out + 6 * blk);
+    }
+  };
+
+  // acc (on target lanes of parity 1-sp) = H_L src (sources: lanes of parity sp)
+  auto hop_block = [&](int sp, const cx<T> src[12], cx<T> acc[12]) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+#pragma unroll
+    for (int r0 = 0; r0 < 4; r0 += DR) {
+      if (q == sp) {
+#pragma unroll
+        for (int m = r0; m < r0 + DR; ++m) {
+          cx<T> h[6], gg[6], u[9];
+          // for the backward neighbour's forward hop: (1 - g_m) projection
+          if (m == 0) project<T, 0, +1>(src, h);
+          else if (m == 1) project<T, 1, +1>(src, h);
+          else if (m == 2) project<T, 2, +1>(src, h);
+          else project<T, 3, +1>(src, h);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) ex.v[2 * (m - r0)][k][j] = h[k];
+          // for the forward neighbour's backward hop: U^dag (1 + g_m) projection
+          if (m == 0) project<T, 0, -1>(src, h);
+          else if (m == 1) project<T, 1, -1>(src, h);
+          else if (m == 2) project<T, 2, -1>(src, h);
+          else project<T, 3, -1>(src, h);
+          link(m, u);
+          su3_mul_half<T, true>(u, h, gg);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) ex.v[2 * (m - r0) + 1][k][j] = gg[k];
+        }
+      }
+      __syncthreads();
+      if (q != sp) {
+#pragma unroll
+        for (int m = r0; m < r0 + DR; ++m) {
+          int jf = nin[m][0], jb = nin[m][1];
+          cx<T> h[6], gg[6], u[9];
+          if (jf >= 0) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) h[k] = ex.v[2 * (m - r0)][k][jf];
+            link(m, u);
+            su3_mul_half<T, false>(u, h, gg);
+            if (m == 0) reconstruct_add<T, 0, +1>(gg, acc);
+            else if (m == 1) reconstruct_add<T, 1, +1>(gg, acc);
+            else if (m == 2) reconstruct_add<T, 2, +1>(gg, acc);
+            else reconstruct_add<T, 3, +1>(gg, acc);
+          }
+          if (jb >= 0) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) gg[k] = ex.v[2 * (m - r0) + 1][k][jb];
+            if (m == 0) reconstruct_add<T, 0, -1>(gg, acc);
+            else if (m == 1) reconstruct_add<T, 1, -1>(gg, acc);
+            else if (m == 2) reconstruct_add<T, 2, -1>(gg, acc);
+            else reconstruct_add<T, 3, -1>(gg, acc);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  };
+
+  auto block_sum2 = [&](T v0, T v1, T v2, T& s0, T& s1, T& s2) {
+    v0 = wsum(v0);
+    v1 = wsum(v1);
+    v2 = wsum(v2);
+    int w = t >> 6, nw = (blockDim.x + 63) >> 6;
+    if ((t & 63) == 0) {
+      red[w][0] = v0;
+      red[w][1] = v1;
+      red[w][2] = v2;
+    }
+    __syncthreads();
+    s0 = s1 = s2 = T(0);
+    for (int k = 0; k < nw; ++k) {
+      s0 += red[k][0];
+      s1 += red[k][1];
+      s2 += red[k][2];
+    }
+    __syncthreads();
+  };
+
+  // field views shifted to this lane's parity
+  FieldV<S> rho = a.rho, vf = a.V, vn = a.V;
+  FieldV<P> psi = a.psi;
+  rho.p += q * a.poff;
+  vf.p += q * a.poff;
+  vn.p += (1 - q) * a.poff;
+  psi.p += q * a.poff;
+  if (rho.scale) {
+    rho.scale += q * a.spoff;
+    vf.scale += q * a.spoff;
+    vn.scale += (1 - q) * a.spoff;
+  }
+  if (psi.scale) psi.scale += q * a.spoff;
+
+  for (int r = 0; r < a.nrhs; ++r) {
+    cx<T> rh[12];
+    ld_spinor(rho, r, i, rh);
+    // boundary: rho += 1/2 H_face V (the neighbours across the faces are of the other parity)
+    if (a.do_bnd) {
+      cx<T> acc[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+      cx<T> s[12], h[6], gg[6], u[9];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        if (nin[m][0] < 0) {
+          int jn = nbr_idx(g, x, m, +1);
+          ld_spinor(vn, r, jn, s);
+          link(m, u);
+          if (m == 0) { project<T, 0, +1>(s, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 0, +1>(gg, acc); }
+          else if (m == 1) { project<T, 1, +1>(s, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 1, +1>(gg, acc); }
+          else if (m == 2) { project<T, 2, +1>(s, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 2, +1>(gg, acc); }
+          else { project<T, 3, +1>(s, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 3, +1>(gg, acc); }
+        }
+        if (nin[m][1] < 0) {
+          int jn = nbr_idx(g, x, m, -1);
+          ld_spinor(vn, r, jn, s);
+          ld_link(a.U, 1 - q, m, jn, u);
+          if (m == 0) { project<T, 0, -1>(s, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 0, -1>(gg, acc); }
+          else if (m == 1) { project<T, 1, -1>(s, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 1, -1>(gg, acc); }
+          else if (m == 2) { project<T, 2, -1>(s, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 2, -1>(gg, acc); }
+          else { project<T, 3, -1>(s, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 3, -1>(gg, acc); }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 12; ++k) rh[k] = rh[k] + T(0.5) * acc[k];
+    }
+    // source reduction: w = A_o^{-1} rho_o (odd lanes); b = rho_e + 1/2 H_L w (even lanes)
+    cx<T> w[12], acc[12], xs[12], rr[12];
+    if (q == 1) clover(rh, w);
+    hop_block(1, w, acc);
+    if (q == 0) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        rr[k] = rh[k] + T(0.5) * acc[k];
+        xs[k] = {T(0), T(0)};
+      }
+    }
+    // minimal-residual steps on Dhat_L
+    for (int it = 0; it < a.nmr; ++it) {
+      hop_block(0, rr, acc);  // odd lanes: acc = H_L r
+      if (q == 1) {
+        cx<T> hh[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) hh[k] = T(-0.5) * acc[k];
+        clover(hh, w);  // w = A_o^{-1} (-1/2 H r)
+      }
+      hop_block(1, w, acc);  // even lanes: acc = H_L w
+      T pr_re = 0, pr_im = 0, pp = 0;
+      cx<T> p[12];
+      if (q == 0) {
+        clover(rr, p);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          p[k] = p[k] + T(0.5) * acc[k];
+          cx<T> z = cmulc(p[k], rr[k]);
+          pr_re += z.re;
+          pr_im += z.im;
+          pp += p[k].re * p[k].re + p[k].im * p[k].im;
+        }
+      }
+      T s0, s1, s2;
+      block_sum2(pr_re, pr_im, pp, s0, s1, s2);
+      cx<T> al = s2 > T(0) ? cx<T>{s0 / s2, s1 / s2} : cx<T>{T(0), T(0)};
+      if (q == 0) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          xs[k] = fma_c(al, rr[k], xs[k]);
+          rr[k] = rr[k] - al * p[k];
+        }
+      }
+    }
+    // odd reconstruction: v_o = A_o^{-1} (rho_o + 1/2 H_L v_e)
+    hop_block(0, xs, acc);
+    cx<T> v[12], rnew[12];
+    if (q == 1) {
+      cx<T> hh[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) hh[k] = rh[k] + T(0.5) * acc[k];
+      clover(hh, v);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) rnew[k] = {T(0), T(0)};
+    } else {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        v[k] = xs[k];
+        rnew[k] = rr[k];
+      }
+    }
+    // write back: psi += v, V = v, rho = new block residual
+    typedef typename St<P>::T TP;
+    cx<TP> pv[12];
+    if (a.first) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) pv[k] = {(TP)v[k].re, (TP)v[k].im};
+    } else {
+      ld_spinor(psi, r, i, pv);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) pv[k] = pv[k] + cx<TP>{(TP)v[k].re, (TP)v[k].im};
+    }
+    st_spinor(psi, r, i, pv);
+    if (a.write_v) st_spinor(vf, r, i, v);
+    st_spinor(rho, r, i, rnew);
+  }
+}
+
+template <class S, class P>
+hipError_t launch_sap_half(const SapArgs<S, P>& a, int nblk_colour, hipStream_t st) {
+  int nsb = a.bs[0] * a.bs[1] * a.bs[2] * a.bs[3];
+  if (nsb > 2 * kSapMaxHalf || nblk_colour <= 0) return hipErrorInvalidValue;
+  if constexpr (sizeof(S) == 8)
+    hipLaunchKernelGGL((k_sap_half<S, P, 2>), dim3(nblk_colour), dim3(nsb), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_sap_half<S, P, 4>), dim3(nblk_colour), dim3(nsb), 0, st, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_sap_half<double, double>(const SapArgs<double, double>&, int, hipStream_t);
+template hipError_t launch_sap_half<float, float>(const SapArgs<float, float>&, int, hipStream_t);
+template hipError_t launch_sap_half<__half, float>(const SapArgs<__half, float>&, int, hipStream_t);
+
+}  // namespace qdd
