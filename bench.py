@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path on one MI355X: the even-odd clover-Wilson operator
+Dhat = D_ee - D_eo D_oo^{-1} D_oe (Eq. 2) applied to a batch of right-hand sides,
+on the 32^3 x 64 workload (random SU(3) links exp(i 0.6 H), kappa 0.1357,
+c_sw 1.9, 8 Gaussian right-hand sides, FP16 storage with FP32 arithmetic).
+
+A step is one Dhat apply of the whole batch (two kernel launches).  Prints one
+JSON line (metric, value in TB/s of algorithmic bytes, roofline of the dominant
+kernel measured with HIP events on the library's stream, CPU-oracle baseline).
+
+Byte model per even site and right-hand side batch of n (reals; each field
+element read or written once per pass, Hermitian 6x6 clover blocks as 36 reals):
+  pass A: psi_e 24n + links 144 + A_o^{-1} 72 + t_o 24n
+  pass B: t_o 24n + links 144 + psi_e 24n + A_e 72 + out 24n
+times the bytes per real (8 FP64, 4 FP32, 2 FP16) plus, for FP16, one FP32
+scale per site and spinor access (8 per rhs in pass A, 12 in pass B).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_TBS = 8.0  # MI355X HBM3E peak
+LATTICE = (64, 32, 32, 32)
+EPS, KAPPA, CSW = 0.6, 0.1357, 1.9
+GAUGE_SEED = 1003
+METRIC = "Dirac-apply TB/s (% HBM peak); solve s to rel-res 1e-10, learned vs plain"
+
+
+def bytes_per_site(prec: int, nrhs: int):
+    """(pass A, pass B) algorithmic bytes per even site for a batch of nrhs."""
+    b = {0: 8, 1: 4, 2: 2}[prec]
+    a = (24 * nrhs + 144 + 72 + 24 * nrhs) * b
+    bb = (24 * nrhs + 144 + 24 * nrhs + 72 + 24 * nrhs) * b
+    if prec == 2:
+        a += 8 * nrhs
+        bb += 12 * nrhs
+    return a, bb
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("qdd_dirac.hip", "qdd_internal.h"):
+        with open(os.path.join(ROOT, "paper_1011_0911_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(prec, nrhs, launch):
+    """HBM bytes per launch of pass B from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source with the same launch shape."""
+    path = os.path.join(ROOT, "profiles", "dhat_32c64_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    key = f"prec{prec}_nrhs{nrhs}"
+    e = d.get("entries", {}).get(key)
+    if not e or e.get("kernel_hash") != kernel_source_hash() or e.get("launch") != list(launch):
+        return None
+    return e.get("pass_b_bytes")
+
+
+def cpu_baseline(U, nrhs_gpu, prec_gpu, budget_s=12.0):
+    """FP64 oracle Dhat on the same lattice, one rhs per apply, as many applies as
+    fit in the time budget; converted to the GPU's unit with its byte model."""
+    import numpy as np
+
+    import oracle
+    from paper_1011_0911_amd import synth as S
+
+    L = LATTICE
+    V = int(np.prod(L))
+    t0 = time.time()
+    A, Ai = oracle.clover(L, U, KAPPA, CSW)
+    t_setup = time.time() - t0
+    pe = S.gaussian_field(V // 2, 77)
+    oracle.apply_Dhat(L, U, A, Ai, pe)  # warm
+    n, t0 = 0, time.time()
+    while True:
+        oracle.apply_Dhat(L, U, A, Ai, pe)
+        n += 1
+        if time.time() - t0 > budget_s or n >= 50:
+            break
+    dt = (time.time() - t0) / n
+    a, b = bytes_per_site(prec_gpu, nrhs_gpu)
+    per_rhs = (a + b) / nrhs_gpu
+    tbs = per_rhs * (V // 2) / dt / 1e12
+    return {"value": round(tbs, 6), "unit": "TB/s", "cores": oracle.get_threads(), "kind": "oracle",
+            "sample": (f"FP64 CPU oracle Dhat on the same 32^3x64 field, 1 rhs per apply, {n} applies of "
+                       f"{dt * 1e3:.0f} ms (clover set-up {t_setup:.1f} s untimed); rate converted with the "
+                       f"GPU's per-rhs byte model ({per_rhs:.0f} B/site)")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--nrhs", type=int, default=8)
+    ap.add_argument("--prec", type=int, default=2, help="0 FP64, 1 FP32, 2 FP16 storage")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only (no multi-GPU path); use --gpus 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1011_0911_amd import qdd
+    from paper_1011_0911_amd import synth as S
+
+    dev = torch.device("cuda:0")
+    L = LATTICE
+    V = int(np.prod(L))
+    Vh = V // 2
+    nrhs, prec = args.nrhs, args.prec
+    t0 = time.time()
+    U = S.random_su3_links(L, EPS, GAUGE_SEED)
+    print(f"[bench] links generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    ctx = qdd.Context(L, qdd.default_config(max_nrhs=max(nrhs, 1)), device=dev)
+    ctx.set_gauge(torch.from_numpy(U))
+    ctx.set_params(KAPPA, CSW)
+    src = S.gaussian_field(Vh, 2000 + 300, nrhs=nrhs)
+    fin = ctx.pack(prec, torch.from_numpy(src), True)
+    fout = ctx.empty_field(prec, nrhs, True)
+    tuned_ms = None
+    if not args.no_tune:
+        cache_path = os.path.join(ROOT, "paper_1011_0911_amd", "tune_cache.json")
+        cache = qdd.load_tune_cache(cache_path)
+        tuned_ms = ctx.autotune(qdd.KERNEL_DHAT, prec, nrhs, fin, fout, reps=5, cache=cache)
+        qdd.save_tune_cache(cache_path, cache)
+    launch = ctx.get_launch(qdd.KERNEL_DHAT, prec)
+    print(f"[bench] launch {launch} (tuned {tuned_ms})", file=sys.stderr, flush=True)
+
+    st = ctx.stream
+    for _ in range(args.warmup):
+        ctx.dw_hat(prec, nrhs, fin, fout)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.time()
+    e0.record(st)
+    for _ in range(args.steps):
+        ctx.dw_hat(prec, nrhs, fin, fout)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.time() - w0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    a_b, b_b = bytes_per_site(prec, nrhs)
+    value = (a_b + b_b) * Vh / (ms_step * 1e-3) / 1e12
+    # dominant kernel (pass B): per-launch durations from HIP events on the library stream
+    ms_a, ms_b = ctx.dw_hat_timed(prec, nrhs, fin, fout, args.steps)
+    ach_b = b_b * Vh / (ms_b * 1e-3) / 1e12
+    ach_a = a_b * Vh / (ms_a * 1e-3) / 1e12
+    traffic = measured_traffic(prec, nrhs, launch)
+    # plain copy of the same size as pass B's algorithmic bytes: the achievable bandwidth
+    nb = (b_b * Vh) // 2 // 16 * 16
+    ca = torch.empty(nb, dtype=torch.uint8, device=dev)
+    cb = torch.empty_like(ca)
+    for _ in range(3):
+        qdd.copy(cb, ca)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(10):
+        qdd.copy(cb, ca)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_tbs = 2 * nb / (c0.elapsed_time(c1) / 10 * 1e-3) / 1e12
+    del ca, cb
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "TB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {0: "f64", 1: "f32", 2: "f32"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "Dhat apply, 32^3x64 lattice, random SU(3) links exp(i*0.6*H), kappa 0.1357, "
+                               "c_sw 1.9, antiperiodic time",
+                   "nrhs": nrhs, "storage": {0: "f64", 1: "f32", 2: "f16 + per-site f32 scale"}[prec],
+                   "even_sites": Vh, "launch": {"block": launch[0], "nr": launch[1], "xcd": launch[2],
+                                                "sb": launch[3]},
+                   "frac_of_peak_whole_apply": round(value / PEAK_HBM_TBS, 4),
+                   "pass_a": {"ms": round(ms_a, 5), "TBs": round(ach_a, 4)},
+                   "copy_reference_TBs": round(copy_tbs, 4), "wall_s_timed": round(wall, 3)},
+        "roofline": {"bound": "hbm", "kernel": "k_dhat_b (pass B)", "achieved": round(ach_b, 4),
+                     "peak": PEAK_HBM_TBS, "unit": "TB/s", "frac": round(ach_b / PEAK_HBM_TBS, 4),
+                     "traffic": traffic, "bytes_per_launch": b_b * Vh, "ms_per_launch": round(ms_b, 5)},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        try:
+            out["cpu_baseline"] = cpu_baseline(U, nrhs, prec)
+        except Exception as e:  # the baseline is reported, never required
+            out["cpu_baseline"] = {"error": str(e)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -154,6 +154,21 @@ qdd_status qdd_sap(qdd_ctx* ctx, int nrhs, const double* eta, double* psi);
  * (self + 8 face couplings per block, FP64). */
 qdd_status qdd_dfl_build(qdd_ctx* ctx, const double* init);
 
+/* Inspection of the deflation data (device pointers, either may be NULL): the
+ * block-orthonormal basis as dfl_Ns canonical full fields, and the little Dirac
+ * operator A[b][f][k][l] = <w_bk, D w_b'l> (complex128, nblk x 9 x Ns x Ns;
+ * f = 0 the block with itself, f = 1 + 2 mu + dir the coupling through the
+ * block's upper (dir 0) or lower (dir 1) face in direction mu; blocks numbered
+ * lexicographically like sites).  Synchronises. */
+qdd_status qdd_dfl_export(qdd_ctx* ctx, double* basis, double* little);
+/* Solves the little system A c = f (device [rhs][nblk][Ns] complex128) with the
+ * FP64 GCR of the preconditioner to relative residual tol; *iters (host) gets
+ * the iteration count. */
+qdd_status qdd_dfl_coarse_solve(qdd_ctx* ctx, int nrhs, const double* f, double* c, double tol, int* iters);
+/* One application of the two-level preconditioner, out = C r + M_sap(r - D C r)
+ * with C = W A^{-1} W^dag (canonical full fields). */
+qdd_status qdd_dfl_precond(qdd_ctx* ctx, int nrhs, const double* r, double* out);
+
 /* Solves D psi = eta (canonical full fields, nrhs right-hand sides, psi
  * overwritten) with FP64 flexible GCR and the configured preconditioner.
  * info: nrhs entries (host memory) or NULL.  QDD_ENOCONV if any rhs fails. */
@@ -162,10 +177,32 @@ qdd_status qdd_solve(qdd_ctx* ctx, int nrhs, const double* eta, double* psi, qdd
 qdd_status qdd_solve_dhat(qdd_ctx* ctx, int nrhs, const double* eta_e, double* psi_e, qdd_solve_info* info);
 
 /* Launch shape of a kernel family (kernel: 0 = Dhat, 1 = D; prec: qdd_prec):
- * block threads (64..256, multiple of 64), rhs per thread nr (1, 2, 4) and the
- * XCD-aware block remap (0/1). */
-qdd_status qdd_set_launch(qdd_ctx* ctx, int kernel, qdd_prec prec, int block, int nr, int xcd);
-qdd_status qdd_get_launch(const qdd_ctx* ctx, int kernel, qdd_prec prec, int* block, int* nr, int* xcd);
+ * block threads (64..256, multiple of 64); nr right-hand sides per lane (1, 2,
+ * 4; the links are loaded once for all of them); xcd: block walk (0 linear;
+ * 1 every XCD takes a contiguous slab of the lattice; 2 slabs whose tiles are
+ * walked time slice first, so time and x1 neighbours stay in the XCD's L2); sb sites per block (0 = block): the block/sb lane groups of a block
+ * take further right-hand sides of the same sites, so a wavefront of 64 lanes
+ * covers 64/sb right-hand sides and fetches each link once for all of them. */
+qdd_status qdd_set_launch(qdd_ctx* ctx, int kernel, qdd_prec prec, int block, int nr, int xcd, int sb);
+qdd_status qdd_get_launch(const qdd_ctx* ctx, int kernel, qdd_prec prec, int* block, int* nr, int* xcd, int* sb);
+
+/* Autotuner: times every candidate launch shape of `kernel` (0 = Dhat on packed
+ * even fields, 1 = D on packed full fields) for this precision and batch size
+ * on the given packed fields (`reps` timed repetitions each, HIP events on the
+ * context stream), installs the fastest in the context and returns its mean
+ * duration in *best_ms.  `out` is overwritten; synchronises. */
+qdd_status qdd_autotune(qdd_ctx* ctx, int kernel, qdd_prec prec, int nrhs, const void* in, void* out, int reps,
+                        float* best_ms);
+
+/* qdd_dw_hat, repeated `reps` times with HIP events recorded on the context's
+ * stream before pass A, between the passes and after pass B; returns the mean
+ * duration of each pass in milliseconds (synchronises). */
+qdd_status qdd_dw_hat_timed(qdd_ctx* ctx, qdd_prec prec, int nrhs, const void* in_e, void* out_e, int reps,
+                            float* ms_pass_a, float* ms_pass_b);
+
+/* Plain device-to-device copy of `bytes` (multiple of 16) with 16-byte vector
+ * loads and stores on `stream`: the HBM bandwidth reference of the benchmarks. */
+qdd_status qdd_copy(void* dst, const void* src, size_t bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -149,6 +149,14 @@ void compute_layout(const qdd_geom* g, const qdd_config* c, Layout& Lo) {
     size_t cv = (size_t)nr * nb * Ns * 16;
     Lo.dfl_cvec = B.take(cv * (2 * kCoarseKv + 8));
     Lo.dfl_init = B.take((size_t)Ns * 24 * Vh * 16);
+    Lo.dfl_cr = B.take((size_t)nr * 24 * Vh * 16);
+    Lo.dfl_t = B.take((size_t)nr * 24 * Vh * 16);
+    Lo.cpart = B.take((size_t)kDotBlocks * kCoarseKv * nr * 16 + 4096);
+    Lo.ccoef = B.take((size_t)nr * kCoarseKv * 16);
+    Lo.crn2 = B.take((size_t)nr * 16);
+    Lo.calpha = B.take((size_t)nr * 16);
+    Lo.cbinv = B.take((size_t)nr * 16);
+    Lo.cactive = B.take((size_t)nr * 4);
   }
   // network weights and activations
   if (c->use_net) {
@@ -354,22 +362,64 @@ qdd_status qdd_dw(qdd_ctx* x, qdd_prec prec, int nrhs, const void* in, void* out
   return QDD_OK;
 }
 
-qdd_status qdd_set_launch(qdd_ctx* x, int kernel, qdd_prec prec, int block, int nr, int xcd) {
-  if (!x || kernel < 0 || kernel > 1 || prec < QDD_F64 || prec > QDD_F16 || block < 64 || block > 256 ||
-      (block & 63) || (nr != 1 && nr != 2 && nr != 4) || (xcd != 0 && xcd != 1)) {
+qdd_status qdd_set_launch(qdd_ctx* x, int kernel, qdd_prec prec, int block, int nr, int xcd, int sb) {
+  bool ok = x && kernel >= 0 && kernel <= 1 && prec >= QDD_F64 && prec <= QDD_F16 && block >= 64 && block <= 256 &&
+            (block & 63) == 0 && (nr == 1 || nr == 2 || nr == 4) && (xcd >= 0 && xcd <= 2) &&
+            (sb == 0 || (sb >= 1 && sb <= block && block % sb == 0));
+  if (!ok) {
     if (x) x->fail("qdd_set_launch: invalid arguments");
     return QDD_EINVAL;
   }
-  x->launch[kernel][prec] = LaunchCfg{block, nr, xcd};
+  x->launch[kernel][prec] = LaunchCfg{block, nr, xcd, sb == block ? 0 : sb};
   return QDD_OK;
 }
 
-qdd_status qdd_get_launch(const qdd_ctx* x, int kernel, qdd_prec prec, int* block, int* nr, int* xcd) {
+qdd_status qdd_get_launch(const qdd_ctx* x, int kernel, qdd_prec prec, int* block, int* nr, int* xcd, int* sb) {
   if (!x || kernel < 0 || kernel > 1 || prec < QDD_F64 || prec > QDD_F16) return QDD_EINVAL;
   const LaunchCfg& c = x->launch[kernel][prec];
   if (block) *block = c.block;
   if (nr) *nr = c.nr;
   if (xcd) *xcd = c.xcd;
+  if (sb) *sb = c.sb > 0 ? c.sb : c.block;
+  return QDD_OK;
+}
+
+qdd_status qdd_dw_hat_timed(qdd_ctx* x, qdd_prec prec, int nrhs, const void* in, void* out, int reps, float* ms_a,
+                            float* ms_b) {
+  if (!x || !in || !out || nrhs < 1 || nrhs > x->cfg.max_nrhs || prec < QDD_F64 || prec > QDD_F16 || reps < 1) {
+    if (x) x->fail("qdd_dw_hat_timed: invalid arguments");
+    return QDD_EINVAL;
+  }
+  if (!x->have_clover) { x->fail("qdd_dw_hat_timed before qdd_set_params"); return QDD_ESTATE; }
+  hipEvent_t e0, e1, e2;
+  HCK(x, hipEventCreate(&e0));
+  HCK(x, hipEventCreate(&e1));
+  HCK(x, hipEventCreate(&e2));
+  float ta = 0, tb = 0;
+  hipError_t err = hipSuccess;
+  for (int r = 0; r < reps && err == hipSuccess; ++r) {
+    err = hipEventRecord(e0, x->st);
+    if (err == hipSuccess) err = x->dhat(prec, nrhs, (void*)in, out, e1);
+    if (err == hipSuccess) err = hipEventRecord(e2, x->st);
+    if (err == hipSuccess) err = hipEventSynchronize(e2);
+    float a = 0, b = 0;
+    if (err == hipSuccess) err = hipEventElapsedTime(&a, e0, e1);
+    if (err == hipSuccess) err = hipEventElapsedTime(&b, e1, e2);
+    ta += a;
+    tb += b;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipEventDestroy(e2);
+  HCK(x, err);
+  if (ms_a) *ms_a = ta / reps;
+  if (ms_b) *ms_b = tb / reps;
+  return QDD_OK;
+}
+
+qdd_status qdd_copy(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!dst || !src || (bytes & 15)) return QDD_EINVAL;
+  if (launch_copy(dst, src, bytes, (hipStream_t)stream) != hipSuccess) return QDD_EHIP;
   return QDD_OK;
 }
 
@@ -396,22 +446,22 @@ PackedView qdd_ctx::packed(qdd_prec prec, int nrhs, int even_only, void* field) 
   return v;
 }
 
-hipError_t qdd_ctx::dhat(qdd_prec prec, int nrhs, void* in, void* out) {
+hipError_t qdd_ctx::dhat(qdd_prec prec, int nrhs, void* in, void* out, hipEvent_t mid) {
   PackedView a = packed(prec, nrhs, 1, in), b = packed(prec, nrhs, 1, out);
   int64_t n = G.Vh;
   const LaunchCfg& c = launch[0][prec];
   switch (prec) {
     case QDD_F64: {
       FieldV<double> t{ptr<double2>(lo.tmp_o), nullptr, 12 * n, n, (int)n};
-      return launch_dhat<double>(G, op<double>(), a.f64, t, b.f64, nrhs, c, st);
+      return launch_dhat<double>(G, op<double>(), a.f64, t, b.f64, nrhs, c, st, 3, mid);
     }
     case QDD_F32: {
       FieldV<float> t{ptr<float2>(lo.tmp_o), nullptr, 12 * n, n, (int)n};
-      return launch_dhat<float>(G, op<float>(), a.f32, t, b.f32, nrhs, c, st);
+      return launch_dhat<float>(G, op<float>(), a.f32, t, b.f32, nrhs, c, st, 3, mid);
     }
     default: {
       FieldV<__half> t{ptr<__half2>(lo.tmp_o), ptr<float>(lo.tmp_o_scale), 12 * n, n, (int)n};
-      return launch_dhat<__half>(G, op<__half>(), a.f16, t, b.f16, nrhs, c, st);
+      return launch_dhat<__half>(G, op<__half>(), a.f16, t, b.f16, nrhs, c, st, 3, mid);
     }
   }
 }

@@ -23,7 +23,8 @@ struct Layout {
   bool phi32;
   size_t s_rho, s_psi, s_v, s_eta, s_scale, s_tmp;
   int64_t nblk_dfl;
-  size_t dfl_W, dfl_W32, dfl_A, dfl_Ainv, dfl_cvec, dfl_init;
+  size_t dfl_W, dfl_W32, dfl_A, dfl_Ainv, dfl_cvec, dfl_init, dfl_cr, dfl_t;
+  size_t cpart, ccoef, crn2, calpha, cbinv, cactive;
   size_t net_nw, net_w, net_wb, net_act, net_grad, net_adam, net_gpart;
   size_t part, coef, ahist, bhist, binv, chist, rn2, alpha, active, scal;
   size_t total;
@@ -49,6 +50,7 @@ struct qdd_ctx {
   hipStream_t st = nullptr;
   bool have_gauge = false, have_clover = false, have_dfl = false, have_net = false;
   double kappa = 0, csw = 0;
+  long coarse_iters = 0;  // little-operator GCR iterations since the last solve began
   qdd::LaunchCfg launch[2][3];
   std::string err;
 
@@ -65,7 +67,7 @@ struct qdd_ctx {
                          qdd::CloverV<S>{ptr<E>(lo.Ai[p]), G.Vh}};
   }
   qdd::PackedView packed(qdd_prec prec, int nrhs, int even_only, void* field) const;
-  hipError_t dhat(qdd_prec prec, int nrhs, void* in, void* out);
+  hipError_t dhat(qdd_prec prec, int nrhs, void* in, void* out, hipEvent_t mid = nullptr);
   hipError_t dw(qdd_prec prec, int nrhs, void* in, void* out);
 };
 

@@ -1,14 +1,281 @@
-// Local deflation (host side).
+// Local deflation, host side: subspace build (SAP inverse iteration, block
+// orthonormalisation, little Dirac operator), the little-operator GCR and the
+// two-level preconditioner M(r) = C r + M_sap(r - D C r), C = W A^{-1} W^dag
+// (W the block-orthonormal basis, A = W^dag D W the little Dirac operator).
 #include "qdd_dfl.h"
+#include "qdd_dfl_kernels.h"
+
+#include <cmath>
+#include <cstring>
+#include <vector>
 
 using namespace qdd;
 
-qdd_status dfl_make_precond(qdd_ctx* x, int, FgcrOps&) {
-  x->fail("deflation not available");
-  return QDD_EINVAL;
+static DflGeo dfl_geo(const qdd_ctx* x) {
+  DflGeo d;
+  d.nblk = 1;
+  for (int m = 0; m < 4; ++m) {
+    d.bs[m] = x->cfg.dfl_bs[m];
+    d.nb[m] = x->G.L[m] / d.bs[m];
+    d.nblk *= d.nb[m];
+  }
+  return d;
 }
 
-extern "C" qdd_status qdd_dfl_build(qdd_ctx* x, const double*) {
-  if (x) x->fail("qdd_dfl_build: not available");
-  return QDD_EINVAL;
+// precision of the deflation correction inside the preconditioner
+static bool dfl_fp64(const qdd_ctx* x) { return x->cfg.sap_prec == QDD_F64; }
+
+// ------------------------------------------------------------------ coarse GCR
+// Solves A c = f (little operator, FP64) for nrhs right-hand sides with restarted
+// GCR to relative residual tol; f, c: [rhs][nblk*Ns].  Returns the iterations.
+static qdd_status coarse_gcr(qdd_ctx* x, int nrhs, const double2* f, double2* c, double tol, int nmx, int* its) {
+  const Layout& lo = x->lo;
+  hipStream_t st = x->st;
+  DflGeo d = dfl_geo(x);
+  int Ns = x->cfg.dfl_Ns;
+  int64_t nc = (int64_t)d.nblk * Ns, slot = (int64_t)x->cfg.max_nrhs * nc;
+  double2* base = x->ptr<double2>(lo.dfl_cvec);
+  double2 *r = base + 2 * slot, *t = base + 3 * slot, *P = base + 4 * slot, *Q = base + (4 + kCoarseKv) * slot;
+  double2* Am = x->ptr<double2>(lo.dfl_A);
+  double2 *part = x->ptr<double2>(lo.cpart), *coef = x->ptr<double2>(lo.ccoef), *rn2 = x->ptr<double2>(lo.crn2);
+  double2* alpha = x->ptr<double2>(lo.calpha);
+  double* binv = x->ptr<double>(lo.cbinv);
+  double* bnrm = binv + x->cfg.max_nrhs;
+  int* active = x->ptr<int>(lo.cactive);
+  int64_t ls = (int64_t)nrhs * nc;  // stride between Krylov vectors of the batch
+  std::vector<double2> h(nrhs);
+  std::vector<double> fn(nrhs);
+  std::vector<int> act(nrhs);
+  HCK(x, launch_dots<double2>(f, 0, nc, 1, f, nc, nc, nrhs, part, rn2, st));
+  HCK(x, hipMemcpyAsync(h.data(), rn2, nrhs * sizeof(double2), hipMemcpyDeviceToHost, st));
+  HCK(x, hipStreamSynchronize(st));
+  for (int i = 0; i < nrhs; ++i) {
+    fn[i] = std::sqrt(h[i].x);
+    act[i] = fn[i] > 0;
+  }
+  HCK(x, hipMemsetAsync(c, 0, (size_t)nrhs * nc * sizeof(double2), st));
+  HCK(x, hipMemcpyAsync(r, f, (size_t)nrhs * nc * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  int it = 0;
+  while (true) {
+    bool any = false;
+    for (int i = 0; i < nrhs; ++i) any |= act[i];
+    if (!any || it >= nmx) break;
+    HCK(x, hipMemcpyAsync(active, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+    int j = 0;
+    for (; j < kCoarseKv && it < nmx; ++j, ++it) {
+      double2 *pj = P + j * ls, *qj = Q + j * ls;
+      HCK(x, hipMemcpyAsync(pj, r, (size_t)nrhs * nc * sizeof(double2), hipMemcpyDeviceToDevice, st));
+      HCK(x, launch_coarse_apply(d, Am, Ns, pj, qj, nc, nrhs, st));
+      if (j > 0)
+        for (int pass = 0; pass < 2; ++pass) {
+          HCK(x, launch_dots<double2>(Q, ls, nc, j, qj, nc, nc, nrhs, part, coef, st));
+          HCK(x, launch_axpy_multi<double2>(qj, nc, Q, ls, nc, j, coef, j, -1.0, nc, nrhs, nullptr, st));
+          HCK(x, launch_axpy_multi<double2>(pj, nc, P, ls, nc, j, coef, j, -1.0, nc, nrhs, nullptr, st));
+        }
+      HCK(x, launch_dots<double2>(qj, 0, nc, 1, qj, nc, nc, nrhs, part, rn2, st));
+      HCK(x, launch_norm_finish(rn2, bnrm, binv, nrhs, st));
+      HCK(x, launch_axpby(qj, nc, qj, nc, binv, nullptr, nc, nrhs, nullptr, st));
+      HCK(x, launch_axpby(pj, nc, pj, nc, binv, nullptr, nc, nrhs, nullptr, st));
+      HCK(x, launch_dots<double2>(qj, 0, nc, 1, r, nc, nc, nrhs, part, alpha, st));
+      HCK(x, launch_axpy_multi<double2>(r, nc, qj, 0, nc, 1, alpha, 1, -1.0, nc, nrhs, active, st));
+      HCK(x, launch_axpy_multi<double2>(c, nc, pj, 0, nc, 1, alpha, 1, 1.0, nc, nrhs, active, st));
+      HCK(x, launch_dots<double2>(r, 0, nc, 1, r, nc, nc, nrhs, part, rn2, st));
+      HCK(x, hipMemcpyAsync(h.data(), rn2, nrhs * sizeof(double2), hipMemcpyDeviceToHost, st));
+      HCK(x, hipStreamSynchronize(st));
+      bool changed = false, any2 = false;
+      for (int i = 0; i < nrhs; ++i) {
+        if (!act[i]) continue;
+        if (!(std::sqrt(std::fabs(h[i].x)) > tol * fn[i]) || !std::isfinite(h[i].x)) {
+          act[i] = 0;
+          changed = true;
+        }
+        any2 |= act[i];
+      }
+      if (!any2) {
+        ++it;
+        ++j;
+        break;
+      }
+      if (changed) HCK(x, hipMemcpyAsync(active, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+    }
+    bool any3 = false;
+    for (int i = 0; i < nrhs; ++i) any3 |= act[i];
+    if (!any3) break;
+    // restart from the true residual r = f - A c
+    HCK(x, launch_coarse_apply(d, Am, Ns, c, t, nc, nrhs, st));
+    HCK(x, launch_sub(r, f, t, nc, nc, nrhs, st));
+  }
+  if (its) *its = it;
+  return QDD_OK;
+}
+
+// ------------------------------------------------------------------ build
+extern "C" qdd_status qdd_dfl_build(qdd_ctx* x, const double* init) {
+  if (!x || !init) {
+    if (x) x->fail("qdd_dfl_build: invalid arguments");
+    return QDD_EINVAL;
+  }
+  if (x->cfg.dfl_Ns <= 0) { x->fail("qdd_dfl_build: dfl_Ns is 0"); return QDD_EINVAL; }
+  if (!x->have_clover) { x->fail("qdd_dfl_build before qdd_set_params"); return QDD_ESTATE; }
+  const Layout& lo = x->lo;
+  const Geo& G = x->G;
+  hipStream_t st = x->st;
+  DflGeo d = dfl_geo(x);
+  int Ns = x->cfg.dfl_Ns, nr = x->cfg.max_nrhs;
+  int64_t vs = (int64_t)24 * G.Vh;
+  double2* W = x->ptr<double2>(lo.dfl_W);
+  PackedView pw = x->packed(QDD_F64, Ns, 0, W);
+  HCK(x, launch_pack_spinor<double>(G, init, pw.f64, Ns, 0, pw.poff, pw.spoff, st));
+  // SAP inverse iteration, nr fields at a time, each normalised after every round
+  double2 *part = x->ptr<double2>(lo.part), *rn2 = x->ptr<double2>(lo.rn2);
+  double *bn = x->ptr<double>(lo.bhist), *binv = x->ptr<double>(lo.binv);
+  void* tmp = x->ptr<void>(lo.phi);
+  for (int it = 0; it < x->cfg.dfl_nit; ++it)
+    for (int l0 = 0; l0 < Ns; l0 += nr) {
+      int nb = std::min(nr, Ns - l0);
+      double2* w = W + l0 * vs;
+      qdd_status s = sap_apply(x, nb, w, tmp);
+      if (s != QDD_OK) return s;
+      if (x->cfg.sap_prec == QDD_F64) {
+        HCK(x, hipMemcpyAsync(w, tmp, (size_t)nb * vs * sizeof(double2), hipMemcpyDeviceToDevice, st));
+      } else {
+        FieldV<float> a{(float2*)tmp, nullptr, vs, vs, (int)(vs / 12)};
+        FieldV<double> b{w, nullptr, vs, vs, (int)(vs / 12)};
+        HCK(x, launch_field_convert<float, double>(a, b, nb, st));
+      }
+      HCK(x, launch_dots<double2>(w, 0, vs, 1, w, vs, vs, nb, part, rn2, st));
+      HCK(x, launch_norm_finish(rn2, bn, binv, nb, st));
+      HCK(x, launch_axpby(w, vs, w, vs, binv, nullptr, vs, nb, nullptr, st));
+    }
+  HCK(x, launch_block_orth(G, d, W, vs, Ns, st));
+  // little operator: self (hops inside blocks) and the 8 face couplings
+  double2* F = x->ptr<double2>(lo.dfl_init);
+  double2* Am = x->ptr<double2>(lo.dfl_A);
+  for (int mode = 0; mode < 9; ++mode) {
+    HCK(x, launch_dfl_hops(G, d, x->op<double>(), W, vs, F, Ns, mode, st));
+    HCK(x, launch_block_dots<double2, double2>(G, d, W, vs, Ns, F, vs, Ns, Am + (int64_t)mode * Ns * Ns,
+                                               (int64_t)9 * Ns * Ns, Ns, 1, st));
+  }
+  if (!dfl_fp64(x)) HCK(x, launch_convert(W, x->ptr<float2>(lo.dfl_W32), (int64_t)Ns * vs, st));
+  HCK(x, hipStreamSynchronize(st));
+  x->have_dfl = true;
+  (void)nr;
+  return QDD_OK;
+}
+
+// ------------------------------------------------------------------ preconditioner
+// c = W^dag r (per block), coarse solve, Cr = W c (precision P), t = D Cr,
+// r1 = r - t (FP64), phi = Cr + M_sap(r1)
+template <class EP>
+static qdd_status dfl_apply(qdd_ctx* x, int nrhs, const double2* r, EP* phi, double* tcoarse) {
+  const Layout& lo = x->lo;
+  const Geo& G = x->G;
+  hipStream_t st = x->st;
+  DflGeo d = dfl_geo(x);
+  int Ns = x->cfg.dfl_Ns;
+  int64_t vs = (int64_t)24 * G.Vh, nc = (int64_t)d.nblk * Ns, slot = (int64_t)x->cfg.max_nrhs * nc;
+  double2* cbase = x->ptr<double2>(lo.dfl_cvec);
+  double2 *cf = cbase, *cc = cbase + slot;
+  constexpr bool F64 = sizeof(EP) == 16;
+  // restriction
+  if constexpr (F64)
+    HCK(x, launch_block_dots<double2, double2>(G, d, x->ptr<double2>(lo.dfl_W), vs, Ns, r, vs, nrhs, cf, Ns, 1, nc,
+                                               st));
+  else
+    HCK(x, launch_block_dots<float2, double2>(G, d, x->ptr<float2>(lo.dfl_W32), vs, Ns, r, vs, nrhs, cf, Ns, 1, nc,
+                                              st));
+  int its = 0;
+  qdd_status s = coarse_gcr(x, nrhs, cf, cc, x->cfg.dfl_coarse_tol, x->cfg.dfl_coarse_nmx, &its);
+  if (s != QDD_OK) return s;
+  x->coarse_iters += its;
+  // prolongation and the deflation-corrected residual
+  EP* Cr = x->ptr<EP>(lo.dfl_cr);
+  EP* t = x->ptr<EP>(lo.dfl_t);
+  if constexpr (F64)
+    HCK(x, launch_prolong<double2, double2>(G, d, x->ptr<double2>(lo.dfl_W), vs, Ns, cc, nc, Cr, vs, nrhs, st));
+  else
+    HCK(x, launch_prolong<float2, float2>(G, d, x->ptr<float2>(lo.dfl_W32), vs, Ns, cc, nc, Cr, vs, nrhs, st));
+  HCK(x, x->dw(F64 ? QDD_F64 : QDD_F32, nrhs, Cr, t));
+  double2* r1 = x->ptr<double2>(lo.s_tmp);
+  if constexpr (F64) {
+    HCK(x, launch_sub(r1, r, (const double2*)t, vs, vs, nrhs, st));
+  } else {
+    FieldV<float> a{(float2*)t, nullptr, vs, vs, (int)(vs / 12)};
+    FieldV<double> b{r1, nullptr, vs, vs, (int)(vs / 12)};
+    HCK(x, launch_field_convert<float, double>(a, b, nrhs, st));
+    HCK(x, launch_sub(r1, r, r1, vs, vs, nrhs, st));
+  }
+  (void)tcoarse;
+  s = sap_apply(x, nrhs, r1, phi);
+  if (s != QDD_OK) return s;
+  HCK(x, launch_add<EP>(phi, Cr, 1.0, (int64_t)nrhs * vs, st));
+  return QDD_OK;
+}
+
+qdd_status dfl_precond_apply(qdd_ctx* x, int nrhs, const double2* r, void* phi) {
+  if (dfl_fp64(x)) return dfl_apply<double2>(x, nrhs, r, (double2*)phi, nullptr);
+  return dfl_apply<float2>(x, nrhs, r, (float2*)phi, nullptr);
+}
+
+qdd_status dfl_make_precond(qdd_ctx* x, int nrhs, FgcrOps& F) {
+  F.prec = [x, nrhs](const double2* r, void* phi) -> qdd_status { return dfl_precond_apply(x, nrhs, r, phi); };
+  return QDD_OK;
+}
+
+// ------------------------------------------------------------------ test / inspection entry points
+extern "C" qdd_status qdd_dfl_export(qdd_ctx* x, double* basis, double* little) {
+  if (!x) return QDD_EINVAL;
+  if (!x->have_dfl) { x->fail("qdd_dfl_export before qdd_dfl_build"); return QDD_ESTATE; }
+  const Layout& lo = x->lo;
+  int Ns = x->cfg.dfl_Ns;
+  if (basis) {
+    PackedView pw = x->packed(QDD_F64, Ns, 0, x->ptr<double2>(lo.dfl_W));
+    HCK(x, launch_unpack_spinor<double>(x->G, pw.f64, basis, Ns, 0, pw.poff, pw.spoff, x->st));
+  }
+  if (little)
+    HCK(x, hipMemcpyAsync(little, x->ptr<double2>(lo.dfl_A), (size_t)lo.nblk_dfl * 9 * Ns * Ns * sizeof(double2),
+                          hipMemcpyDeviceToDevice, x->st));
+  HCK(x, hipStreamSynchronize(x->st));
+  return QDD_OK;
+}
+
+extern "C" qdd_status qdd_dfl_coarse_solve(qdd_ctx* x, int nrhs, const double* f, double* c, double tol, int* iters) {
+  if (!x || !f || !c || nrhs < 1 || nrhs > x->cfg.max_nrhs || !(tol > 0)) {
+    if (x) x->fail("qdd_dfl_coarse_solve: invalid arguments");
+    return QDD_EINVAL;
+  }
+  if (!x->have_dfl) { x->fail("qdd_dfl_coarse_solve before qdd_dfl_build"); return QDD_ESTATE; }
+  DflGeo d = dfl_geo(x);
+  int64_t nc = (int64_t)d.nblk * x->cfg.dfl_Ns, slot = (int64_t)x->cfg.max_nrhs * nc;
+  double2* cbase = x->ptr<double2>(x->lo.dfl_cvec);
+  HCK(x, hipMemcpyAsync(cbase, f, (size_t)nrhs * nc * sizeof(double2), hipMemcpyDeviceToDevice, x->st));
+  qdd_status s = coarse_gcr(x, nrhs, cbase, cbase + slot, tol, 100000, iters);
+  if (s != QDD_OK) return s;
+  HCK(x, hipMemcpyAsync(c, cbase + slot, (size_t)nrhs * nc * sizeof(double2), hipMemcpyDeviceToDevice, x->st));
+  HCK(x, hipStreamSynchronize(x->st));
+  return QDD_OK;
+}
+
+extern "C" qdd_status qdd_dfl_precond(qdd_ctx* x, int nrhs, const double* r_c, double* out_c) {
+  if (!x || !r_c || !out_c || nrhs < 1 || nrhs > x->cfg.max_nrhs) {
+    if (x) x->fail("qdd_dfl_precond: invalid arguments");
+    return QDD_EINVAL;
+  }
+  if (!x->have_dfl) { x->fail("qdd_dfl_precond before qdd_dfl_build"); return QDD_ESTATE; }
+  const Layout& lo = x->lo;
+  double2* r = x->ptr<double2>(lo.res);
+  PackedView pr = x->packed(QDD_F64, nrhs, 0, r);
+  HCK(x, launch_pack_spinor<double>(x->G, r_c, pr.f64, nrhs, 0, pr.poff, pr.spoff, x->st));
+  void* phi = x->ptr<void>(lo.phi);
+  qdd_status s = dfl_precond_apply(x, nrhs, r, phi);
+  if (s != QDD_OK) return s;
+  if (dfl_fp64(x)) {
+    PackedView po = x->packed(QDD_F64, nrhs, 0, phi);
+    HCK(x, launch_unpack_spinor<double>(x->G, po.f64, out_c, nrhs, 0, po.poff, po.spoff, x->st));
+  } else {
+    PackedView po = x->packed(QDD_F32, nrhs, 0, phi);
+    HCK(x, launch_unpack_spinor<float>(x->G, po.f32, out_c, nrhs, 0, po.poff, po.spoff, x->st));
+  }
+  HCK(x, hipStreamSynchronize(x->st));
+  return QDD_OK;
 }

@@ -5,3 +5,4 @@
 
 qdd_status sap_apply(qdd_ctx* x, int nrhs, const double2* eta, void* psi);
 qdd_status dfl_make_precond(qdd_ctx* x, int nrhs, FgcrOps& F);
+qdd_status dfl_precond_apply(qdd_ctx* x, int nrhs, const double2* r, void* phi);

@@ -1,0 +1,38 @@
+// Launchers of the local-deflation kernels (qdd_dfl.hip).
+#pragma once
+#include "qdd_kernels.h"
+#include <type_traits>
+
+namespace qdd {
+
+struct DflGeo {
+  int bs[4], nb[4];  // deflation block extents, blocks per direction
+  int nblk;
+};
+
+__device__ __host__ inline cx<double> cvt_any(double2 v) { return {v.x, v.y}; }
+__device__ __host__ inline cx<double> cvt_any(float2 v) { return {(double)v.x, (double)v.y}; }
+template <class E>
+__device__ inline E to_elem(cx<double> v);
+template <>
+__device__ inline double2 to_elem<double2>(cx<double> v) { return make_double2(v.re, v.im); }
+template <>
+__device__ inline float2 to_elem<float2>(cx<double> v) { return make_float2((float)v.re, (float)v.im); }
+
+hipError_t launch_block_orth(const Geo& g, const DflGeo& d, double2* W, int64_t vs, int Ns, hipStream_t st);
+hipError_t launch_dfl_hops(const Geo& g, const DflGeo& d, const DevOp<double>& op, const double2* W, int64_t vs,
+                           double2* F, int Ns, int mode, hipStream_t st);
+// out[b*bso + kx*ldo + ky*kys] = sum over block b of conj(X_kx) Y_ky
+template <class EX, class EY>
+hipError_t launch_block_dots(const Geo& g, const DflGeo& d, const EX* X, int64_t xvs, int nx, const EY* Y,
+                             int64_t yvs, int ny, double2* out, int64_t bso, int64_t ldo, int64_t kys,
+                             hipStream_t st);
+template <class EW, class EO>
+hipError_t launch_prolong(const Geo& g, const DflGeo& d, const EW* W, int64_t wvs, int Ns, const double2* c,
+                          int64_t nc, EO* out, int64_t ovs, int nrhs, hipStream_t st);
+hipError_t launch_coarse_apply(const DflGeo& d, const double2* A, int Ns, const double2* in, double2* out,
+                               int64_t nc, int nrhs, hipStream_t st);
+// y[i] += a * x[i] over n complex elements (a real)
+template <class E>
+hipError_t launch_add(E* y, const E* x, double a, int64_t n, hipStream_t st);
+}  // namespace qdd

@@ -6,9 +6,10 @@
 //   pass A (odd sites):  t_o = A_o^{-1} H_oe psi_e
 //   pass B (even sites): out_e = A_e psi_e - (1/4) H_eo t_o      = Dhat psi_e
 //   full D (both):       out_p = A_p psi_p - (1/2) H_{p,1-p} psi_{1-p}
-// One lane per site and NR right-hand sides per lane: a link is loaded once and
-// applied to all NR spinors.  Blocks are remapped so that each of the 8 XCDs
-// works on one contiguous slab of the lattice (neighbours share its L2).
+// A lane handles one site and NR right-hand sides (a link is loaded once and
+// applied to all NR spinors); a block holds sb sites times block/sb lane groups
+// that take further right-hand sides, so one wavefront can cover several
+// right-hand sides of the same sites and fetch each link once for all of them.
 #include "qdd_kernels.h"
 
 namespace qdd {
@@ -51,24 +52,43 @@ __device__ inline void hop_all(const Geo& g, const LinkV<S>& U, const FieldV<S>&
   hop_dir<S, 3, NR>(g, U, in, r0, nr, p, i, x, acc);
 }
 
-// block -> (site tile, rhs group), XCD-aware: consecutive hardware block ids go
-// round-robin over the 8 XCDs, so give each XCD a contiguous range of tiles.
-__device__ inline void map_block(int nblk, int nrg, int xcd_remap, int& tile, int& rg) {
-  int b = blockIdx.x;
-  if (xcd_remap && (nblk % 8) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
+// block b of nblk (of one parity) -> (site tile, rhs group).
+// order 0: linear.  order >= 1: hardware block ids go round-robin over the 8
+// XCDs, so every XCD is given a contiguous range of tiles (a slab of the
+// lattice whose neighbours share its L2).  order 2 additionally walks the tiles
+// of an XCD's slab of L0/8 time slices with the time slice fastest, then x1,
+// then the tile within the (x2, x3) row: the time and x1 neighbours of a site
+// are then touched within a few tiles, while the lexicographic walk reaches the
+// time neighbours only one whole time slice later, after they have left the L2.
+__device__ inline void map_block(const Geo& g, int b, int nblk, int nrg, int sb, int order, int& tile, int& rg) {
+  if (order >= 1 && (nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
   rg = b % nrg;
   tile = b / nrg;
+  int row = g.L[2] * g.Lh3;  // sites of one (x0, x1) row of a parity
+  if (order == 2 && (g.L[0] & 7) == 0 && row % sb == 0 && (nblk / nrg) * sb == g.Vh) {
+    int S = g.L[0] >> 3, tpr = row / sb, per_xcd = S * g.L[1] * tpr;
+    int k = tile / per_xcd, t = tile - k * per_xcd;
+    int s = t % S, rest = t / S;
+    int x1 = rest % g.L[1], qd = rest / g.L[1];
+    tile = ((k * S + s) * g.L[1] + x1) * tpr + qd;
+  }
+}
+
+// lane -> (site i, first rhs r0): sb sites x (blockDim / sb) rhs groups of NR
+template <int NR>
+__device__ inline bool lane_site(const Geo& g, int tile, int rg, int sb, int nrhs, int& i, int& r0) {
+  i = tile * sb + (int)(threadIdx.x % sb);
+  r0 = (rg * (int)(blockDim.x / sb) + (int)(threadIdx.x / sb)) * NR;
+  return i < g.Vh && r0 < nrhs;
 }
 
 template <class S, int NR>
 __global__ void __launch_bounds__(256) k_dhat_a(Geo g, LinkV<S> U, CloverV<S> Ai, FieldV<S> in_e, FieldV<S> t_o,
-                                                int nrhs, int nrg, int xcd) {
+                                                int nrhs, int nrg, int order, int sb) {
   typedef typename St<S>::T T;
-  int tile, rg;
-  map_block(gridDim.x, nrg, xcd, tile, rg);
-  int i = tile * blockDim.x + threadIdx.x;
-  if (i >= g.Vh) return;
-  int r0 = rg * NR;
+  int tile, rg, i, r0;
+  map_block(g, blockIdx.x, gridDim.x, nrg, sb, order, tile, rg);
+  if (!lane_site<NR>(g, tile, rg, sb, nrhs, i, r0)) return;
   int nr = min(NR, nrhs - r0);
   int x[4];
   site_coords(g, 1, i, x);
@@ -90,13 +110,11 @@ __global__ void __launch_bounds__(256) k_dhat_a(Geo g, LinkV<S> U, CloverV<S> Ai
 
 template <class S, int NR>
 __global__ void __launch_bounds__(256) k_dhat_b(Geo g, LinkV<S> U, CloverV<S> A, FieldV<S> in_e, FieldV<S> t_o,
-                                                FieldV<S> out_e, int nrhs, int nrg, int xcd) {
+                                                FieldV<S> out_e, int nrhs, int nrg, int order, int sb) {
   typedef typename St<S>::T T;
-  int tile, rg;
-  map_block(gridDim.x, nrg, xcd, tile, rg);
-  int i = tile * blockDim.x + threadIdx.x;
-  if (i >= g.Vh) return;
-  int r0 = rg * NR;
+  int tile, rg, i, r0;
+  map_block(g, blockIdx.x, gridDim.x, nrg, sb, order, tile, rg);
+  if (!lane_site<NR>(g, tile, rg, sb, nrhs, i, r0)) return;
   int nr = min(NR, nrhs - r0);
   int x[4];
   site_coords(g, 0, i, x);
@@ -119,18 +137,17 @@ __global__ void __launch_bounds__(256) k_dhat_b(Geo g, LinkV<S> U, CloverV<S> A,
   }
 }
 
-// full D on both parities; in/out: full fields (parity p at offset p*poff elements)
+// full D on both parities; in/out: full fields (parity p at offset p*poff
+// elements); the two halves of the grid are walked like two Dhat passes
 template <class S, int NR>
 __global__ void __launch_bounds__(256) k_dw(Geo g, LinkV<S> U, CloverV<S> A, FieldV<S> in, FieldV<S> out,
-                                            int64_t poff, int64_t spoff, int nrhs, int nrg, int xcd) {
+                                            int64_t poff, int64_t spoff, int nrhs, int nrg, int order, int sb) {
   typedef typename St<S>::T T;
-  int tile, rg;
-  map_block(gridDim.x, nrg, xcd, tile, rg);
-  int tiles_per_parity = (g.Vh + blockDim.x - 1) / blockDim.x;
-  int p = tile >= tiles_per_parity;
-  int i = (tile - p * tiles_per_parity) * blockDim.x + threadIdx.x;
-  if (i >= g.Vh) return;
-  int r0 = rg * NR;
+  int nh = gridDim.x >> 1;
+  int p = (int)blockIdx.x >= nh;
+  int tile, rg, i, r0;
+  map_block(g, blockIdx.x - p * nh, nh, nrg, sb, order, tile, rg);
+  if (!lane_site<NR>(g, tile, rg, sb, nrhs, i, r0)) return;
   int nr = min(NR, nrhs - r0);
   int x[4];
   site_coords(g, p, i, x);
@@ -167,22 +184,26 @@ static inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 template <class S, int NR>
 static hipError_t launch_dhat_nr(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> tmp, FieldV<S> out,
-                                 int nrhs, const LaunchCfg& c, hipStream_t st) {
-  int nrg = ceil_div(nrhs, NR);
-  int tiles = ceil_div(g.Vh, c.block);
+                                 int nrhs, const LaunchCfg& c, hipStream_t st, int pass, hipEvent_t ev) {
+  int sb = c.sb > 0 ? c.sb : c.block;
+  int nrg = ceil_div(nrhs, NR * (c.block / sb));
+  int tiles = ceil_div(g.Vh, sb);
   dim3 grid(tiles * nrg), blk(c.block);
-  hipLaunchKernelGGL((k_dhat_a<S, NR>), grid, blk, 0, st, g, op.U, op.Ainv, in, tmp, nrhs, nrg, c.xcd);
-  hipLaunchKernelGGL((k_dhat_b<S, NR>), grid, blk, 0, st, g, op.U, op.A, in, tmp, out, nrhs, nrg, c.xcd);
+  if (pass & 1)
+    hipLaunchKernelGGL((k_dhat_a<S, NR>), grid, blk, 0, st, g, op.U, op.Ainv, in, tmp, nrhs, nrg, c.xcd, sb);
+  if (ev) hipEventRecord(ev, st);
+  if (pass & 2)
+    hipLaunchKernelGGL((k_dhat_b<S, NR>), grid, blk, 0, st, g, op.U, op.A, in, tmp, out, nrhs, nrg, c.xcd, sb);
   return hipGetLastError();
 }
 
 template <class S>
 hipError_t launch_dhat(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> tmp, FieldV<S> out, int nrhs,
-                       const LaunchCfg& c, hipStream_t st) {
+                       const LaunchCfg& c, hipStream_t st, int pass, hipEvent_t ev) {
   switch (c.nr) {
-    case 1: return launch_dhat_nr<S, 1>(g, op, in, tmp, out, nrhs, c, st);
-    case 2: return launch_dhat_nr<S, 2>(g, op, in, tmp, out, nrhs, c, st);
-    case 4: return launch_dhat_nr<S, 4>(g, op, in, tmp, out, nrhs, c, st);
+    case 1: return launch_dhat_nr<S, 1>(g, op, in, tmp, out, nrhs, c, st, pass, ev);
+    case 2: return launch_dhat_nr<S, 2>(g, op, in, tmp, out, nrhs, c, st, pass, ev);
+    case 4: return launch_dhat_nr<S, 4>(g, op, in, tmp, out, nrhs, c, st, pass, ev);
     default: return hipErrorInvalidValue;
   }
 }
@@ -190,10 +211,11 @@ hipError_t launch_dhat(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S>
 template <class S, int NR>
 static hipError_t launch_dw_nr(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> out, int64_t poff,
                                int64_t spoff, int nrhs, const LaunchCfg& c, hipStream_t st) {
-  int nrg = ceil_div(nrhs, NR);
-  int tiles = 2 * ceil_div(g.Vh, c.block);
+  int sb = c.sb > 0 ? c.sb : c.block;
+  int nrg = ceil_div(nrhs, NR * (c.block / sb));
+  int tiles = 2 * ceil_div(g.Vh, sb);
   hipLaunchKernelGGL((k_dw<S, NR>), dim3(tiles * nrg), dim3(c.block), 0, st, g, op.U, op.A, in, out, poff, spoff,
-                     nrhs, nrg, c.xcd);
+                     nrhs, nrg, c.xcd, sb);
   return hipGetLastError();
 }
 
@@ -208,17 +230,14 @@ hipError_t launch_dw(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> o
   }
 }
 
-template hipError_t launch_dhat<double>(const Geo&, const DevOp<double>&, FieldV<double>, FieldV<double>,
-                                        FieldV<double>, int, const LaunchCfg&, hipStream_t);
-template hipError_t launch_dhat<float>(const Geo&, const DevOp<float>&, FieldV<float>, FieldV<float>, FieldV<float>,
-                                       int, const LaunchCfg&, hipStream_t);
-template hipError_t launch_dhat<__half>(const Geo&, const DevOp<__half>&, FieldV<__half>, FieldV<__half>,
-                                        FieldV<__half>, int, const LaunchCfg&, hipStream_t);
-template hipError_t launch_dw<double>(const Geo&, const DevOp<double>&, FieldV<double>, FieldV<double>, int64_t,
-                                      int64_t, int, const LaunchCfg&, hipStream_t);
-template hipError_t launch_dw<float>(const Geo&, const DevOp<float>&, FieldV<float>, FieldV<float>, int64_t, int64_t,
-                                     int, const LaunchCfg&, hipStream_t);
-template hipError_t launch_dw<__half>(const Geo&, const DevOp<__half>&, FieldV<__half>, FieldV<__half>, int64_t,
-                                      int64_t, int, const LaunchCfg&, hipStream_t);
+#define INST(S)                                                                                                     \
+  template hipError_t launch_dhat<S>(const Geo&, const DevOp<S>&, FieldV<S>, FieldV<S>, FieldV<S>, int,             \
+                                     const LaunchCfg&, hipStream_t, int, hipEvent_t);                               \
+  template hipError_t launch_dw<S>(const Geo&, const DevOp<S>&, FieldV<S>, FieldV<S>, int64_t, int64_t, int,        \
+                                   const LaunchCfg&, hipStream_t);
+INST(double)
+INST(float)
+INST(__half)
+#undef INST
 
 }  // namespace qdd

@@ -15,14 +15,18 @@ struct DevOp {
 
 // launch shape (picked by the autotuner)
 struct LaunchCfg {
-  int block = 256;  // threads per block (one site per thread)
-  int nr = 1;       // right-hand sides per thread
-  int xcd = 1;      // XCD-aware block remap
+  int block = 256;  // threads per block
+  int nr = 1;       // right-hand sides per thread (register reuse of the links)
+  int xcd = 2;      // block walk: 0 linear, 1 XCD slabs, 2 XCD slabs walked time-slice first
+  int sb = 0;       // sites per block (0 = block); block/sb lane groups take further rhs
 };
 
+// pass: bit 0 = pass A, bit 1 = pass B; ev (optional) is recorded between them
 template <class S>
 hipError_t launch_dhat(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> tmp, FieldV<S> out, int nrhs,
-                       const LaunchCfg& c, hipStream_t st);
+                       const LaunchCfg& c, hipStream_t st, int pass = 3, hipEvent_t ev = nullptr);
+// plain HBM copy (16-byte vectors), the bandwidth reference
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 template <class S>
 hipError_t launch_dw(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> out, int64_t poff, int64_t spoff,
                      int nrhs, const LaunchCfg& c, hipStream_t st);

@@ -22,6 +22,18 @@ __global__ void k_pack_links(Geo g, const double* canon, double2* U) {
   for (int k = 0; k < 9; ++k) dst[(int64_t)k * g.Vh] = make_double2(s * src[2 * k], s * src[2 * k + 1]);
 }
 
+// plain 16-byte-vector copy: the HBM bandwidth reference of the benchmarks
+__global__ void k_copy(uint4* dst, const uint4* src, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    dst[t] = src[t];
+}
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  int64_t n = (int64_t)(bytes / 16);
+  int nb = (int)std::min<int64_t>((n + 255) / 256, 256 * 64);
+  if (n > 0) hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, st, (uint4*)dst, (const uint4*)src, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_pack_links(const Geo& g, const double* canon, double2* U, hipStream_t st) {
   int64_t n = (int64_t)g.V * 4;
   hipLaunchKernelGGL(k_pack_links, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, canon, U);

@@ -74,10 +74,18 @@ SIGNATURES = {
     "qdd_dw": (_i, [_vp, _i, _i, _vp, _vp]),
     "qdd_sap": (_i, [_vp, _i, _vp, _vp]),
     "qdd_dfl_build": (_i, [_vp, _vp]),
+    "qdd_dfl_export": (_i, [_vp, _vp, _vp]),
+    "qdd_dfl_coarse_solve": (_i, [_vp, _i, _vp, _vp, _d, ctypes.POINTER(_i)]),
+    "qdd_dfl_precond": (_i, [_vp, _i, _vp, _vp]),
     "qdd_solve": (_i, [_vp, _i, _vp, _vp, _vp]),
     "qdd_solve_dhat": (_i, [_vp, _i, _vp, _vp, _vp]),
-    "qdd_set_launch": (_i, [_vp, _i, _i, _i, _i, _i]),
-    "qdd_get_launch": (_i, [_vp, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+    "qdd_set_launch": (_i, [_vp, _i, _i, _i, _i, _i, _i]),
+    "qdd_get_launch": (_i, [_vp, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i),
+                            ctypes.POINTER(_i)]),
+    "qdd_dw_hat_timed": (_i, [_vp, _i, _i, _vp, _vp, _i, ctypes.POINTER(ctypes.c_float),
+                              ctypes.POINTER(ctypes.c_float)]),
+    "qdd_copy": (_i, [_vp, _vp, ctypes.c_size_t, _vp]),
+    "qdd_autotune": (_i, [_vp, _i, _i, _i, _vp, _vp, _i, ctypes.POINTER(ctypes.c_float)]),
 }
 
 
@@ -230,6 +238,35 @@ class Context:
         assert c.numel() == self.cfg.dfl_Ns * self.V * 12
         self._check(lib().qdd_dfl_build(self.h, _ptr(c)))
 
+    def dfl_nblocks(self):
+        n = 1
+        for j in range(4):
+            n *= self.L[j] // self.cfg.dfl_bs[j]
+        return n
+
+    def dfl_export(self):
+        """(basis (Ns,V,4,3), little operator (nblk,9,Ns,Ns)) as device complex128 tensors."""
+        Ns = self.cfg.dfl_Ns
+        basis = torch.empty((Ns, self.V, 4, 3), dtype=torch.complex128, device=self.device)
+        little = torch.empty((self.dfl_nblocks(), 9, Ns, Ns), dtype=torch.complex128, device=self.device)
+        self._check(lib().qdd_dfl_export(self.h, _ptr(basis), _ptr(little)))
+        return basis, little
+
+    def dfl_coarse_solve(self, f, tol):
+        c_in = self._c128(f)
+        nrhs = c_in.numel() // (self.dfl_nblocks() * self.cfg.dfl_Ns)
+        out = torch.empty_like(c_in)
+        it = ctypes.c_int()
+        self._check(lib().qdd_dfl_coarse_solve(self.h, nrhs, _ptr(c_in), _ptr(out), float(tol), ctypes.byref(it)))
+        return out, it.value
+
+    def dfl_precond(self, r):
+        c = self._c128(r)
+        nrhs = c.numel() // (self.V * 12)
+        out = torch.empty((nrhs, self.V, 4, 3), dtype=torch.complex128, device=self.device)
+        self._check(lib().qdd_dfl_precond(self.h, nrhs, _ptr(c), _ptr(out)))
+        return out
+
     def solve(self, eta, check=True):
         c = self._c128(eta)
         nrhs = c.numel() // (self.V * 12)
@@ -250,10 +287,60 @@ class Context:
             self._check(st)
         return out, [i.as_dict() for i in info], st
 
-    def set_launch(self, kernel, prec, block, nr, xcd):
-        self._check(lib().qdd_set_launch(self.h, kernel, prec, block, nr, xcd))
+    def set_launch(self, kernel, prec, block, nr, xcd, sb=0):
+        self._check(lib().qdd_set_launch(self.h, kernel, prec, block, nr, xcd, sb))
 
     def get_launch(self, kernel, prec):
-        b, n, x = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        self._check(lib().qdd_get_launch(self.h, kernel, prec, ctypes.byref(b), ctypes.byref(n), ctypes.byref(x)))
-        return b.value, n.value, x.value
+        b, n, x, s = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        self._check(lib().qdd_get_launch(self.h, kernel, prec, ctypes.byref(b), ctypes.byref(n), ctypes.byref(x),
+                                         ctypes.byref(s)))
+        return b.value, n.value, x.value, s.value
+
+    def autotune(self, kernel, prec, nrhs, fin, fout, reps=5, cache=None):
+        """Picks the fastest launch shape (C++ timing loop in the library).  With a
+        cache dict, a previously measured choice for the same key is reused."""
+        key = f"{kernel}/{prec}/{nrhs}/{'x'.join(map(str, self.L))}/{torch.cuda.get_device_properties(self.device).gcnArchName}"
+        if cache is not None and key in cache:
+            b, n, x, s = cache[key]["launch"]
+            self.set_launch(kernel, prec, b, n, x, s)
+            return cache[key]["ms"]
+        ms = ctypes.c_float()
+        self._check(lib().qdd_autotune(self.h, kernel, prec, nrhs, _ptr(fin), _ptr(fout), int(reps), ctypes.byref(ms)))
+        if cache is not None:
+            cache[key] = {"launch": list(self.get_launch(kernel, prec)), "ms": ms.value}
+        return ms.value
+
+    def dw_hat_timed(self, prec, nrhs, fin, fout, reps):
+        """Mean per-pass durations (ms) of `reps` Dhat applies, HIP events on the context stream."""
+        a, b = ctypes.c_float(), ctypes.c_float()
+        self._check(lib().qdd_dw_hat_timed(self.h, prec, nrhs, _ptr(fin), _ptr(fout), int(reps), ctypes.byref(a),
+                                           ctypes.byref(b)))
+        return a.value, b.value
+
+
+def load_tune_cache(path):
+    import json
+
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_tune_cache(path, cache):
+    import json
+
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def copy(dst: torch.Tensor, src: torch.Tensor, stream=None):
+    """HBM copy reference kernel (16-byte vectors) on `stream` (default: current)."""
+    st = stream if stream is not None else torch.cuda.current_stream(dst.device)
+    nbytes = min(dst.numel() * dst.element_size(), src.numel() * src.element_size())
+    r = lib().qdd_copy(_ptr(dst), _ptr(src), nbytes - nbytes % 16, ctypes.c_void_p(st.cuda_stream))
+    if r != QDD_OK:
+        raise QddError(r, "qdd_copy failed")

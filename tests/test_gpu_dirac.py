@@ -78,11 +78,12 @@ def test_batched_equals_single_rhs(Q, kernel):
     app = ctx.apply_dhat if kernel == 0 else ctx.apply_dw
     for prec in (0, 1):
         ref = np.stack([to_np(app(psi[r:r + 1], prec))[0] for r in range(5)])
-        for block, nr, xcd in [(64, 1, 0), (128, 2, 1), (256, 4, 1), (192, 4, 0)]:
-            ctx.set_launch(kernel, prec, block, nr, xcd)
+        for block, nr, xcd, sb in [(64, 1, 0, 0), (128, 2, 1, 0), (256, 4, 1, 0), (192, 4, 0, 0), (128, 1, 1, 16),
+                                   (256, 2, 2, 32), (64, 1, 2, 16), (192, 1, 1, 64), (128, 1, 2, 0), (256, 4, 2, 0)]:
+            ctx.set_launch(kernel, prec, block, nr, xcd, sb)
             out = to_np(app(psi, prec))
-            assert np.array_equal(out, ref), (prec, block, nr, xcd)
-        ctx.set_launch(kernel, prec, 256, 1, 1)
+            assert np.array_equal(out, ref), (prec, block, nr, xcd, sb)
+        ctx.set_launch(kernel, prec, 256, 1, 1, 0)
 
 
 def test_pack_unpack_roundtrip(Q):
