@@ -176,6 +176,39 @@ qdd_status qdd_solve(qdd_ctx* ctx, int nrhs, const double* eta, double* psi, qdd
 /* Solves Dhat psi_e = eta_e (canonical even fields) with unpreconditioned FP64 FGCR. */
 qdd_status qdd_solve_dhat(qdd_ctx* ctx, int nrhs, const double* eta_e, double* psi_e, qdd_solve_info* info);
 
+/* ---- learned preconditioner stage (configuration use_net = 1) ----
+ * A gauge-covariant parallel-transport convolution network N with net_nl
+ * layers and channels net_ch[0..nl]; layer: out_c(x) = sum_{c',d} W[d][c][c']
+ * (T_d in_{c'})(x), d = 0 identity, d = 1+2mu forward transport U_mu(x)
+ * psi(x+mu), d = 2+2mu backward transport U_mu(x-mu)^dag psi(x-mu), W a complex
+ * 4x4 spin matrix.  Weights: complex FP32 (device, interleaved), layer after
+ * layer, each W[d][c][c'][s][s'] row-major; they are used in BF16, activations
+ * in FP32.  Inside the deflated preconditioner:
+ * v = C r + N(r1) + M_sap(r2), r1 = r - D C r, r2 = r1 - D N(r1); for every
+ * right-hand side whose |r2| > |r1| (or not finite) N is dropped (counted in
+ * qdd_solve_info.fallbacks), so the plain method is always the floor. */
+qdd_status qdd_net_num_weights(const qdd_ctx* ctx, int64_t* n);
+qdd_status qdd_net_set_weights(qdd_ctx* ctx, const float* w);
+qdd_status qdd_net_get_weights(qdd_ctx* ctx, float* w);
+/* out = N(in), canonical complex128 full fields (one field). */
+qdd_status qdd_net_forward(qdd_ctx* ctx, const double* in, double* out);
+/* Loss l = sum_i |N(r_i/|r_i|) - e_i/|r_i||^2 / sum_i |e_i/|r_i||^2 over nb pairs
+ * (canonical complex128, device, at most 8) and, if grad != NULL, its complex
+ * gradient dl/dRe W + i dl/dIm W (device, FP32 complex, qdd_net_num_weights). */
+qdd_status qdd_net_loss_grad(qdd_ctx* ctx, int nb, const double* r, const double* e, double* loss, float* grad);
+/* One Adam step (lr; beta 0.9, 0.999) on a mini-batch of nb pairs given as
+ * packed FP32 full fields (as written by qdd_solve_harvest). */
+qdd_status qdd_net_train_step(qdd_ctx* ctx, int nb, const void* r, const void* e, float lr, double* loss);
+/* Solves one right-hand side like qdd_solve and records, at every outer
+ * iteration, r_k and e_k = psi* - psi_k as packed FP32 full fields
+ * (qdd_field_bytes(ctx, QDD_F32, 1, 0) bytes each, consecutive) into the
+ * caller's buffers, up to max_pairs; *npairs gets the count.  e_pairs must hold
+ * max_pairs FP64 fields (qdd_field_bytes(ctx, QDD_F64, 1, 0) each): the
+ * iterates stay in FP64 until psi* is known; the FP32 errors are returned
+ * packed at its front. */
+qdd_status qdd_solve_harvest(qdd_ctx* ctx, const double* eta, double* psi, qdd_solve_info* info, void* r_pairs,
+                             void* e_pairs, int max_pairs, int* npairs);
+
 /* Launch shape of a kernel family (kernel: 0 = Dhat, 1 = D; prec: qdd_prec):
  * block threads (64..256, multiple of 64); nr right-hand sides per lane (1, 2,
  * 4; the links are loaded once for all of them); xcd: block walk (0 linear;

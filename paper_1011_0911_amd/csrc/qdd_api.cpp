@@ -87,6 +87,7 @@ static bool valid_cfg(const qdd_geom* g, const qdd_config* c, std::string* why) 
     for (int l = 1; l < c->net_nl; ++l)
       if (c->net_ch[l] < 1 || c->net_ch[l] > kMaxNetCh) { *why = "network: channels must be in 1..16"; return false; }
     if (c->dfl_Ns == 0) { *why = "network stage needs deflation (dfl_Ns > 0)"; return false; }
+    if (c->sap_prec == QDD_F64) { *why = "network stage needs FP32 or FP16 SAP"; return false; }
   }
   return true;
 }
@@ -158,20 +159,29 @@ void compute_layout(const qdd_geom* g, const qdd_config* c, Layout& Lo) {
     Lo.cbinv = B.take((size_t)nr * 16);
     Lo.cactive = B.take((size_t)nr * 4);
   }
-  // network weights and activations
+  // network weights, activations (levels 0..nl and two gradient buffers) and
+  // the staging area for training pairs
+  Lo.net_nw = 0;
   if (c->use_net) {
-    size_t nw = 0, maxch = 1;
+    size_t nw = 0, maxch = 1, maxl = 0;
     for (int l = 0; l < c->net_nl; ++l) {
-      nw += (size_t)9 * c->net_ch[l] * c->net_ch[l + 1] * 16;
+      size_t k = (size_t)9 * c->net_ch[l] * c->net_ch[l + 1] * 16;
+      nw += k;
+      maxl = std::max(maxl, k);
       maxch = std::max<size_t>(maxch, c->net_ch[l + 1]);
     }
     Lo.net_nw = nw;
-    Lo.net_w = B.take(nw * 8);       // complex FP32 (master copy)
-    Lo.net_wb = B.take(nw * 4);      // complex BF16 (compute copy)
-    Lo.net_act = B.take((size_t)(c->net_nl + 1) * maxch * 24 * Vh * 8);
+    Lo.net_w = B.take(nw * 8);       // complex FP32 master weights
+    Lo.net_wb = B.take(nw * 4);      // complex BF16 compute copy
+    Lo.net_wadj = B.take(nw * 4);    // BF16 adjoint weights (backward pass)
+    Lo.net_act = B.take((size_t)(c->net_nl + 3) * maxch * 24 * Vh * 8);
     Lo.net_grad = B.take(nw * 8);
     Lo.net_adam = B.take(nw * 16);
-    Lo.net_gpart = B.take((size_t)kNetGradBlocks * nw * 8);
+    Lo.net_gpart = B.take((size_t)kNetGradBlocks * maxl * 8);
+    Lo.net_loss = B.take(4096 * 8);
+    Lo.net_tmp = B.take((size_t)nr * 24 * Vh * 8);
+    Lo.net_pairs_bytes = (size_t)2 * 8 * 24 * Vh * 8;
+    Lo.net_pairs = B.take(Lo.net_pairs_bytes);
   }
   // reductions and small solver arrays
   Lo.part = B.take((size_t)kDotBlocks * kMaxKv * nr * 16 + 4096);

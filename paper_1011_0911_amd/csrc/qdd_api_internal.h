@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <string>
+#include <vector>
 
 namespace qdd {
 constexpr int kMaxKv = 32;         // outer Krylov vectors
@@ -25,7 +26,8 @@ struct Layout {
   int64_t nblk_dfl;
   size_t dfl_W, dfl_W32, dfl_A, dfl_Ainv, dfl_cvec, dfl_init, dfl_cr, dfl_t;
   size_t cpart, ccoef, crn2, calpha, cbinv, cactive;
-  size_t net_nw, net_w, net_wb, net_act, net_grad, net_adam, net_gpart;
+  size_t net_nw, net_w, net_wb, net_wadj, net_act, net_grad, net_adam, net_gpart, net_loss, net_tmp;
+  size_t net_pairs, net_pairs_bytes;
   size_t part, coef, ahist, bhist, binv, chist, rn2, alpha, active, scal;
   size_t total;
 };
@@ -41,6 +43,7 @@ struct PackedView {
 void compute_layout(const qdd_geom* g, const qdd_config* c, qdd::Layout& Lo);
 bool valid_sap_blocks(const qdd_geom* g, const qdd_config* c, std::string* why);
 
+struct Harvest;
 struct qdd_ctx {
   qdd_geom geom;
   qdd_config cfg;
@@ -51,6 +54,9 @@ struct qdd_ctx {
   bool have_gauge = false, have_clover = false, have_dfl = false, have_net = false;
   double kappa = 0, csw = 0;
   long coarse_iters = 0;  // little-operator GCR iterations since the last solve began
+  int net_step = 0;       // Adam steps taken
+  std::vector<int> fallbacks;  // network stage rejected, per rhs of the current solve
+  struct Harvest* harvest = nullptr;  // pair capture of the next solve (qdd_solve_harvest)
   qdd::LaunchCfg launch[2][3];
   std::string err;
 

@@ -206,6 +206,22 @@ static qdd_status dfl_apply(qdd_ctx* x, int nrhs, const double2* r, EP* phi, dou
     HCK(x, launch_sub(r1, r, r1, vs, vs, nrhs, st));
   }
   (void)tcoarse;
+  if constexpr (!F64) {
+    if (x->cfg.use_net && x->have_net) {
+      float2* vn = x->ptr<float2>(lo.net_tmp);
+      double2* r2 = x->ptr<double2>(lo.t64);
+      std::vector<int> fb;
+      s = net_stage(x, nrhs, r1, vn, r2, (float2*)t, fb);
+      if (s != QDD_OK) return s;
+      if ((int)x->fallbacks.size() < nrhs) x->fallbacks.resize(nrhs, 0);
+      for (int j = 0; j < nrhs; ++j) x->fallbacks[j] += fb[j];
+      s = sap_apply(x, nrhs, r2, phi);
+      if (s != QDD_OK) return s;
+      HCK(x, launch_add<EP>(phi, Cr, 1.0, (int64_t)nrhs * vs, st));
+      HCK(x, launch_add<EP>(phi, (const EP*)vn, 1.0, (int64_t)nrhs * vs, st));
+      return QDD_OK;
+    }
+  }
   s = sap_apply(x, nrhs, r1, phi);
   if (s != QDD_OK) return s;
   HCK(x, launch_add<EP>(phi, Cr, 1.0, (int64_t)nrhs * vs, st));

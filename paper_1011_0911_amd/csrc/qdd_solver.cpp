@@ -7,6 +7,7 @@
 // kernels; each keeps its own coefficients and convergence flag.
 #include "qdd_api_internal.h"
 #include "qdd_solver.h"
+#include "qdd_net.h"
 
 #include <chrono>
 #include <cmath>
@@ -111,6 +112,38 @@ qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qd
       HCK(x, hipMemcpyAsync(h2.data(), rn2, nr * sizeof(double2), hipMemcpyDeviceToHost, st));
       HCK(x, hipStreamSynchronize(st));
       tstage[3] += since(ta);
+      // (the iteration that converges is not captured: its iterate is the solution, e = 0)
+      if (F.hv && nr == 1 && F.hv->n < F.hv->max && act[0] && std::sqrt(std::fabs(h2[0].x)) > tol * etan[0]) {
+        // capture r_k and psi_k = psi + sum_{j<=k} alpha_j phi_j (back-substitution over the steps so far)
+        Harvest& hv = *F.hv;
+        HCK(x, launch_scale_to_f<double2>(hv.r + (int64_t)hv.n * n, r, 1.0, n, st));
+        int m = k + 1;
+        HCK(x, hipMemcpyAsync(ah.data(), ahist, (size_t)m * kMaxKv * sizeof(double2), hipMemcpyDeviceToHost, st));
+        HCK(x, hipMemcpyAsync(bh.data(), bhist, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, st));
+        HCK(x, hipMemcpyAsync(chh.data(), chist, (size_t)m * sizeof(double2), hipMemcpyDeviceToHost, st));
+        HCK(x, hipStreamSynchronize(st));
+        std::fill(al.begin(), al.end(), double2{0.0, 0.0});
+        for (int j = m - 1; j >= 0; --j) {
+          double sr = chh[j].x, si = chh[j].y;
+          for (int l = j + 1; l < m; ++l) {
+            double2 a = ah[(size_t)l * kMaxKv + j], b = al[l];
+            sr -= a.x * b.x - a.y * b.y;
+            si -= a.x * b.y + a.y * b.x;
+          }
+          al[j] = bh[j] > 0 ? double2{sr / bh[j], si / bh[j]} : double2{0.0, 0.0};
+        }
+        HCK(x, hipMemcpyAsync(alpha, al.data(), kMaxKv * sizeof(double2), hipMemcpyHostToDevice, st));
+        HCK(x, hipMemcpyAsync(t, psi, n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        if (F.phi32)
+          HCK(x, launch_axpy_multi<float2>(t, n, (const float2*)phi, lstride, n, m, alpha, kMaxKv, 1.0, n, 1,
+                                           nullptr, st));
+        else
+          HCK(x, launch_axpy_multi<double2>(t, n, (const double2*)phi, lstride, n, m, alpha, kMaxKv, 1.0, n, 1,
+                                            nullptr, st));
+        HCK(x, hipMemcpyAsync((double2*)hv.e + (int64_t)hv.n * n, t, n * sizeof(double2), hipMemcpyDeviceToDevice,
+                              st));
+        hv.n++;
+      }
       ++total_it;
       bool changed = false, any2 = false;
       for (int i = 0; i < nr; ++i) {
@@ -183,6 +216,13 @@ qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qd
     }
     if (nonfinite) break;
   }
+  if (F.hv)
+    // e_j = psi* - psi_j in FP64, then packed as FP32 at the front of the buffer
+    // (slot j of the FP32 output only overlaps FP64 slots that are already consumed)
+    for (int j = 0; j < F.hv->n; ++j) {
+      HCK(x, launch_sub(t, psi, (const double2*)F.hv->e + (int64_t)j * n, n, n, 1, st));
+      HCK(x, launch_scale_to_f<double2>((float2*)F.hv->e + (int64_t)j * n, t, 1.0, n, st));
+    }
   double tot = since(t0);
   for (int i = 0; i < nr; ++i) {
     if (!conv[i]) status = QDD_ENOCONV;
@@ -250,11 +290,37 @@ extern "C" qdd_status qdd_solve(qdd_ctx* x, int nrhs, const double* eta_c, doubl
   PackedView pe = x->packed(QDD_F64, nrhs, 0, eta);
   HCK(x, launch_pack_spinor<double>(x->G, eta_c, pe.f64, nrhs, 0, pe.poff, pe.spoff, x->st));
   FgcrOps F;
+  x->fallbacks.assign(nrhs, 0);
+  x->coarse_iters = 0;
   qdd_status s0 = make_solver_ops(x, nrhs, F);
   if (s0 != QDD_OK) return s0;
+  F.fallbacks = x->fallbacks.data();
+  F.hv = x->harvest;
   qdd_status s = run_fgcr(x, F, eta, psi, info);
   PackedView pp = x->packed(QDD_F64, nrhs, 0, psi);
   HCK(x, launch_unpack_spinor<double>(x->G, pp.f64, psi_c, nrhs, 0, pp.poff, pp.spoff, x->st));
   HCK(x, hipStreamSynchronize(x->st));
+  return s;
+}
+
+// Plain solve of one right-hand side that records a (residual, error) pair at
+// every outer iteration: r_k = eta - D psi_k (the recursive residual) and
+// e_k = psi* - psi_k, both returned as packed FP32 full fields (training data of
+// the network stage).  The e buffer needs FP64-sized slots: the iterates are kept
+// in FP64 until psi* is known, so that the small errors keep their precision.
+extern "C" qdd_status qdd_solve_harvest(qdd_ctx* x, const double* eta_c, double* psi_c, qdd_solve_info* info,
+                                        void* r_pairs, void* e_pairs, int max_pairs, int* npairs) {
+  if (!x || !r_pairs || !e_pairs || max_pairs < 1 || !npairs) {
+    if (x) x->fail("qdd_solve_harvest: invalid arguments");
+    return QDD_EINVAL;
+  }
+  Harvest hv;
+  hv.r = (float2*)r_pairs;
+  hv.e = e_pairs;
+  hv.max = max_pairs;
+  x->harvest = &hv;
+  qdd_status s = qdd_solve(x, 1, eta_c, psi_c, info);
+  x->harvest = nullptr;
+  *npairs = hv.n;
   return s;
 }

@@ -3,6 +3,14 @@
 #include "qdd_api_internal.h"
 #include <functional>
 
+// optional capture of (residual, iterate) pairs at every iteration (one rhs);
+// after the solve the iterates are turned into errors e_k = psi* - psi_k
+struct Harvest {
+  float2* r = nullptr;  // packed FP32 full fields, one per pair
+  void* e = nullptr;    // FP64-sized slots during the solve; FP32 errors packed at the front afterwards
+  int max = 0, n = 0;
+};
+
 struct FgcrOps {
   int64_t n = 0;      // complex numbers per right-hand side
   int nrhs = 1;
@@ -12,6 +20,7 @@ struct FgcrOps {
   std::function<qdd_status(const double2* r, void* phi)> prec;    // phi = M(r), whole batch
   int* fallbacks = nullptr;  // per rhs (network stage)
   double* tstage = nullptr;  // preconditioner sub-stage times (ms), indices 4..6
+  Harvest* hv = nullptr;
 };
 
 qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qdd_solve_info* info);

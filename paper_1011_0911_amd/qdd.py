@@ -78,6 +78,13 @@ SIGNATURES = {
     "qdd_dfl_coarse_solve": (_i, [_vp, _i, _vp, _vp, _d, ctypes.POINTER(_i)]),
     "qdd_dfl_precond": (_i, [_vp, _i, _vp, _vp]),
     "qdd_solve": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "qdd_net_num_weights": (_i, [_vp, ctypes.POINTER(ctypes.c_int64)]),
+    "qdd_net_set_weights": (_i, [_vp, _vp]),
+    "qdd_net_get_weights": (_i, [_vp, _vp]),
+    "qdd_net_forward": (_i, [_vp, _vp, _vp]),
+    "qdd_net_loss_grad": (_i, [_vp, _i, _vp, _vp, ctypes.POINTER(_d), _vp]),
+    "qdd_net_train_step": (_i, [_vp, _i, _vp, _vp, ctypes.c_float, ctypes.POINTER(_d)]),
+    "qdd_solve_harvest": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _i, ctypes.POINTER(_i)]),
     "qdd_solve_dhat": (_i, [_vp, _i, _vp, _vp, _vp]),
     "qdd_set_launch": (_i, [_vp, _i, _i, _i, _i, _i, _i]),
     "qdd_get_launch": (_i, [_vp, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i),
@@ -286,6 +293,60 @@ class Context:
         if check:
             self._check(st)
         return out, [i.as_dict() for i in info], st
+
+    # -- learned stage
+    def net_num_weights(self):
+        n = ctypes.c_int64()
+        self._check(lib().qdd_net_num_weights(self.h, ctypes.byref(n)))
+        return n.value
+
+    def net_set_weights(self, w):
+        """w: complex weights (numpy or torch), stored as FP32 complex."""
+        t = torch.as_tensor(w).to(device=self.device, dtype=torch.complex64).contiguous()
+        assert t.numel() == self.net_num_weights()
+        self._check(lib().qdd_net_set_weights(self.h, _ptr(t)))
+
+    def net_get_weights(self):
+        t = torch.empty(self.net_num_weights(), dtype=torch.complex64, device=self.device)
+        self._check(lib().qdd_net_get_weights(self.h, _ptr(t)))
+        return t
+
+    def net_forward(self, x):
+        c = self._c128(x)
+        out = torch.empty((self.V, 4, 3), dtype=torch.complex128, device=self.device)
+        self._check(lib().qdd_net_forward(self.h, _ptr(c), _ptr(out)))
+        return out
+
+    def net_loss_grad(self, r, e, with_grad=True):
+        rc, ec = self._c128(r), self._c128(e)
+        nb = rc.numel() // (self.V * 12)
+        loss = ctypes.c_double()
+        g = torch.empty(self.net_num_weights(), dtype=torch.complex64, device=self.device) if with_grad else None
+        self._check(lib().qdd_net_loss_grad(self.h, nb, _ptr(rc), _ptr(ec), ctypes.byref(loss),
+                                            _ptr(g) if g is not None else None))
+        return loss.value, g
+
+    def net_train_step(self, r_pairs, e_pairs, nb, lr):
+        loss = ctypes.c_double()
+        self._check(lib().qdd_net_train_step(self.h, nb, _ptr(r_pairs), _ptr(e_pairs), float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def pair_buffers(self, n):
+        """Device buffers for n (residual, error) pairs: packed FP32 full fields (the
+        error buffer has FP64-sized slots for the harvest; its FP32 pairs sit at the front)."""
+        return (torch.empty(n * self.field_bytes(F32, 1, False), dtype=torch.uint8, device=self.device),
+                torch.empty(n * self.field_bytes(F64, 1, False), dtype=torch.uint8, device=self.device))
+
+    def solve_harvest(self, eta, rbuf, ebuf, max_pairs, check=True):
+        c = self._c128(eta)
+        out = torch.empty((1, self.V, 4, 3), dtype=torch.complex128, device=self.device)
+        info = (SolveInfo * 1)()
+        npairs = ctypes.c_int()
+        st = lib().qdd_solve_harvest(self.h, _ptr(c), _ptr(out), info, _ptr(rbuf), _ptr(ebuf), int(max_pairs),
+                                     ctypes.byref(npairs))
+        if check:
+            self._check(st)
+        return out, info[0].as_dict(), npairs.value
 
     def set_launch(self, kernel, prec, block, nr, xcd, sb=0):
         self._check(lib().qdd_set_launch(self.h, kernel, prec, block, nr, xcd, sb))

@@ -1,0 +1,130 @@
+"""GPU parity of the learned preconditioner stage (gauge-covariant
+parallel-transport network) against the oracle: forward pass and loss gradient
+at the same BF16-rounded weights (GPU: FP32 activations and accumulation,
+tolerance 1e-5 relative), the Wilson-operator special case, training, pair
+harvesting (r_k = D e_k) and the fallback to plain SAP."""
+import numpy as np
+import pytest
+
+from paper_1011_0911_amd import synth as S
+from tests.gpu_util import make_ctx, relerr, to_np
+
+pytestmark = pytest.mark.gpu
+CH = [1, 3, 2, 1]
+
+
+def bf16(w):
+    """Round complex weights to BF16 (round to nearest even) per real part."""
+    f = np.ascontiguousarray(np.stack([w.real, w.imag], -1).astype(np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    g = u.astype(np.uint32).view(np.float32).astype(np.float64)
+    return g[..., 0] + 1j * g[..., 1]
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_1011_0911_amd import qdd
+
+    qdd.lib()
+    return qdd
+
+
+def net_ctx(Q, L, ch, seed, **kw):
+    cfg = dict(sap_bs=(2, 2, 2, 2), dfl_Ns=4, dfl_bs=(2, 2, 2, 2), precond=Q.PRECOND_DFL, use_net=1,
+               net_nl=len(ch) - 1, net_ch=ch, sap_prec=1)
+    cfg.update(kw)
+    return make_ctx(Q, L, 0.5, 0.1355, 1.9, seed, **cfg)
+
+
+def test_net_forward_parity(Q, orc):
+    L = (4, 4, 4, 8)
+    ctx, U = net_ctx(Q, L, CH, 601)
+    W = bf16(S.random_weights(ctx.net_num_weights(), 602, 0.3))
+    ctx.net_set_weights(W)
+    x = S.gaussian_field(512, 603)
+    out = to_np(ctx.net_forward(x))
+    ref = orc.net_forward(L, U, CH, W, x[None])[0]
+    e = relerr(out, ref)
+    print("forward err", e)
+    assert e < 1e-5
+
+
+def test_net_reproduces_wilson_operator(Q, orc):
+    # one 1->1 layer with W_0 = 4, W_{+mu} = -(1-g_mu)/2, W_{-mu} = -(1+g_mu)/2 (all exact
+    # in BF16) is the Wilson operator at kappa = 1/8 and c_sw = 0
+    L = (4, 4, 4, 4)
+    ctx, U = net_ctx(Q, L, [1, 1], 604)
+    g = orc.gamma()
+    W = np.zeros((9, 1, 1, 4, 4), complex)
+    W[0, 0, 0] = 4 * np.eye(4)
+    for mu in range(4):
+        W[1 + 2 * mu, 0, 0] = -0.5 * (np.eye(4) - g[mu])
+        W[2 + 2 * mu, 0, 0] = -0.5 * (np.eye(4) + g[mu])
+    ctx.net_set_weights(W.reshape(-1))
+    psi = S.gaussian_field(256, 605)
+    A0, _ = orc.clover(L, U, 0.125, 0.0)
+    assert relerr(to_np(ctx.net_forward(psi)), orc.apply_D(L, U, A0, psi)) < 1e-6
+
+
+def test_net_loss_gradient_parity(Q, orc):
+    L = (4, 4, 4, 8)
+    ctx, U = net_ctx(Q, L, CH, 606)
+    W = bf16(S.random_weights(ctx.net_num_weights(), 607, 0.3))
+    ctx.net_set_weights(W)
+    r = S.gaussian_field(512, 608, nrhs=3)
+    e = S.gaussian_field(512, 609, nrhs=3)
+    loss, grad = ctx.net_loss_grad(r, e)
+    loss_o, grad_o = orc.net_loss_grad(L, U, CH, W, r, e)
+    eg = relerr(to_np(grad), grad_o)
+    print("loss", loss, loss_o, "grad err", eg)
+    assert abs(loss - loss_o) / loss_o < 1e-5 and eg < 1e-5
+
+
+def test_training_reduces_loss_and_harvest_pairs(Q, orc):
+    import torch
+
+    L = (4, 4, 4, 8)
+    ctx, U = net_ctx(Q, L, CH, 610, dfl_nit=2)
+    A, _ = orc.clover(L, U, 0.1355, 1.9)
+    ctx.dfl_build(S.gaussian_field(512, 611, nrhs=4))
+    ctx.net_set_weights(np.zeros(ctx.net_num_weights(), complex))
+    rb, eb = ctx.pair_buffers(32)
+    eta = S.gaussian_field(512, 612)
+    psi, info, n = ctx.solve_harvest(eta, rb, eb, 32)
+    assert info["converged"] and n == info["iters"] - 1 >= 2
+    # every harvested pair satisfies D e_k = r_k - r* exactly (e_k = psi* - psi_k and
+    # r* = eta - D psi* the final residual); both fields are stored in FP32
+    r_star = eta - orc.apply_D(L, U, A, to_np(psi)[0])
+    fb = ctx.field_bytes(Q.F32, 1, False)
+    for k in range(n):
+        rk = to_np(ctx.unpack(Q.F32, rb[k * fb:(k + 1) * fb], 1, False))[0]
+        ek = to_np(ctx.unpack(Q.F32, eb[k * fb:(k + 1) * fb], 1, False))[0]
+        assert relerr(orc.apply_D(L, U, A, ek), rk - r_star) < 1e-5, k
+    ctx.net_set_weights(bf16(S.random_weights(ctx.net_num_weights(), 613, 0.05)))
+    losses = [ctx.net_train_step(rb, eb, n, 1e-2) for _ in range(30)]
+    print("losses", losses[0], losses[-1])
+    assert losses[-1] < 0.9 * losses[0]
+
+
+@pytest.mark.parametrize("scale,expect_fallback", [(0.0, False), (3.0, True)])
+def test_network_stage_never_worse_than_plain(Q, scale, expect_fallback):
+    # zero weights leave r2 = r1 (accepted, adds nothing); large random weights
+    # increase the residual and are rejected at every iteration.  Either way the
+    # iterates are those of the plain deflated solver.
+    L = (4, 4, 4, 8)
+    ctx, U = net_ctx(Q, L, CH, 614, max_nrhs=2)
+    init = S.gaussian_field(512, 615, nrhs=4)
+    ctx.dfl_build(init)
+    W = S.random_weights(ctx.net_num_weights(), 617, scale) if scale else np.zeros(ctx.net_num_weights(), complex)
+    ctx.net_set_weights(W)
+    eta = S.gaussian_field(512, 616, nrhs=2)
+    psi, info, st = ctx.solve(eta)
+    plain, _ = make_ctx(Q, L, 0.5, 0.1355, 1.9, 614, sap_bs=(2, 2, 2, 2), dfl_Ns=4, dfl_bs=(2, 2, 2, 2),
+                        precond=Q.PRECOND_DFL, sap_prec=1, max_nrhs=2)
+    plain.dfl_build(init)
+    psi2, info2, _ = plain.solve(eta)
+    for r in range(2):
+        assert info[r]["converged"] and info[r]["iters"] == info2[r]["iters"]
+        assert info[r]["fallbacks"] == (info[r]["iters"] if expect_fallback else 0)
+    assert np.array_equal(to_np(psi), to_np(psi2))
