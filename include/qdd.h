@@ -165,6 +165,12 @@ qdd_status qdd_dfl_export(qdd_ctx* ctx, double* basis, double* little);
  * FP64 GCR of the preconditioner to relative residual tol; *iters (host) gets
  * the iteration count. */
 qdd_status qdd_dfl_coarse_solve(qdd_ctx* ctx, int nrhs, const double* f, double* c, double tol, int* iters);
+/* Reuses the deflation subspace of `src` (same gauge field, lattice, blocks, Ns)
+ * at the mass of `dst`: the basis is copied and the little operator shifted,
+ * A_dst = A_src + (1/(2 kappa_dst) - 1/(2 kappa_src)) 1 on every block's self
+ * coupling (exact for a block-orthonormal basis).  Synchronises. */
+qdd_status qdd_dfl_share(qdd_ctx* dst, const qdd_ctx* src);
+
 /* One application of the two-level preconditioner, out = C r + M_sap(r - D C r)
  * with C = W A^{-1} W^dag (canonical full fields). */
 qdd_status qdd_dfl_precond(qdd_ctx* ctx, int nrhs, const double* r, double* out);
@@ -173,6 +179,13 @@ qdd_status qdd_dfl_precond(qdd_ctx* ctx, int nrhs, const double* r, double* out)
  * overwritten) with FP64 flexible GCR and the configured preconditioner.
  * info: nrhs entries (host memory) or NULL.  QDD_ENOCONV if any rhs fails. */
 qdd_status qdd_solve(qdd_ctx* ctx, int nrhs, const double* eta, double* psi, qdd_solve_info* info);
+/* Solves nsys independent systems (lattices, masses and batch sizes may all
+ * differ) concurrently: each context (with its own stream) runs its solve on a
+ * host thread of its own, so the work of all systems is in flight at once and
+ * each stops at its own convergence.  eta[s], psi[s]: canonical fields of
+ * system s; info[s]: nrhs[s] entries or NULL.  Returns the first failure. */
+qdd_status qdd_solve_multi(qdd_ctx* const* ctxs, int nsys, const int* nrhs, const double* const* eta,
+                           double* const* psi, qdd_solve_info* const* info);
 /* Solves Dhat psi_e = eta_e (canonical even fields) with unpreconditioned FP64 FGCR. */
 qdd_status qdd_solve_dhat(qdd_ctx* ctx, int nrhs, const double* eta_e, double* psi_e, qdd_solve_info* info);
 

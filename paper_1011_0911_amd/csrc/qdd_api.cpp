@@ -149,7 +149,10 @@ void compute_layout(const qdd_geom* g, const qdd_config* c, Layout& Lo) {
     Lo.dfl_Ainv = B.take((size_t)nb * Ns * Ns * 16);
     size_t cv = (size_t)nr * nb * Ns * 16;
     Lo.dfl_cvec = B.take(cv * (2 * kCoarseKv + 8));
-    Lo.dfl_init = B.take((size_t)Ns * 24 * Vh * 16);
+    // start fields / block-hop scratch of the build: shares the Krylov space when
+    // that is large enough (the build and the solves never overlap)
+    if ((int64_t)nkv * nr >= Ns) Lo.dfl_init = Lo.chi;
+    else Lo.dfl_init = B.take((size_t)Ns * 24 * Vh * 16);
     Lo.dfl_cr = B.take((size_t)nr * 24 * Vh * 16);
     Lo.dfl_t = B.take((size_t)nr * 24 * Vh * 16);
     Lo.cpart = B.take((size_t)kDotBlocks * kCoarseKv * nr * 16 + 4096);

@@ -295,3 +295,49 @@ extern "C" qdd_status qdd_dfl_precond(qdd_ctx* x, int nrhs, const double* r_c, d
   HCK(x, hipStreamSynchronize(x->st));
   return QDD_OK;
 }
+
+// ------------------------------------------------------------------ subspace sharing across masses
+// shift the diagonal of every block's self-coupling by delta (little operator of
+// D + delta: A = W^dag (D + delta) W = W^dag D W + delta 1 for a block-orthonormal W)
+__global__ void k_little_shift(double2* Am, int Ns, int nblk, double delta) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nblk * Ns) return;
+  int b = t / Ns, k = t % Ns;
+  double2& v = Am[(((int64_t)b * 9) * Ns + k) * Ns + k];
+  v.x += delta;
+}
+
+extern "C" qdd_status qdd_dfl_share(qdd_ctx* dst, const qdd_ctx* src) {
+  if (!dst || !src) return QDD_EINVAL;
+  if (!src->have_dfl) { dst->fail("qdd_dfl_share: source has no deflation subspace"); return QDD_ESTATE; }
+  if (!dst->have_clover) { dst->fail("qdd_dfl_share before qdd_set_params"); return QDD_ESTATE; }
+  for (int m = 0; m < 4; ++m)
+    if (dst->geom.L[m] != src->geom.L[m] || dst->cfg.dfl_bs[m] != src->cfg.dfl_bs[m]) {
+      dst->fail("qdd_dfl_share: lattice or deflation blocks differ");
+      return QDD_EINVAL;
+    }
+  if (dst->cfg.dfl_Ns != src->cfg.dfl_Ns || dst->geom.bc_time != src->geom.bc_time ||
+      (dst->cfg.sap_prec == QDD_F64) != (src->cfg.sap_prec == QDD_F64)) {
+    dst->fail("qdd_dfl_share: Ns, boundary condition or deflation precision differ");
+    return QDD_EINVAL;
+  }
+  const Layout &ld = dst->lo, &ls = src->lo;
+  int Ns = dst->cfg.dfl_Ns;
+  int64_t vs = (int64_t)24 * dst->G.Vh;
+  DflGeo d = dfl_geo(dst);
+  // the same gauge field is assumed; the caller guarantees it (the links are not compared)
+  HCK(dst, hipMemcpyAsync(dst->ptr<double2>(ld.dfl_W), src->ptr<double2>(ls.dfl_W), (size_t)Ns * vs * 16,
+                          hipMemcpyDeviceToDevice, dst->st));
+  if (!dfl_fp64(dst))
+    HCK(dst, hipMemcpyAsync(dst->ptr<float2>(ld.dfl_W32), src->ptr<float2>(ls.dfl_W32), (size_t)Ns * vs * 8,
+                            hipMemcpyDeviceToDevice, dst->st));
+  HCK(dst, hipMemcpyAsync(dst->ptr<double2>(ld.dfl_A), src->ptr<double2>(ls.dfl_A),
+                          (size_t)d.nblk * 9 * Ns * Ns * 16, hipMemcpyDeviceToDevice, dst->st));
+  double delta = 1.0 / (2.0 * dst->kappa) - 1.0 / (2.0 * src->kappa);
+  hipLaunchKernelGGL(k_little_shift, dim3((d.nblk * Ns + 255) / 256), dim3(256), 0, dst->st,
+                     dst->ptr<double2>(ld.dfl_A), Ns, d.nblk, delta);
+  HCK(dst, hipGetLastError());
+  HCK(dst, hipStreamSynchronize(dst->st));
+  dst->have_dfl = true;
+  return QDD_OK;
+}

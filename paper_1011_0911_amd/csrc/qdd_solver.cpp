@@ -324,3 +324,28 @@ extern "C" qdd_status qdd_solve_harvest(qdd_ctx* x, const double* eta_c, double*
   *npairs = hv.n;
   return s;
 }
+
+// ------------------------------------------------------------------ several systems at once
+// Solves nsys independent systems (different lattices, masses, batch sizes):
+// every context runs its flexible GCR on its own host thread and its own
+// stream, so the kernels of all systems are in flight together and each system
+// stops at its own convergence.  info[s] points at nrhs[s] entries (or NULL).
+#include <thread>
+extern "C" qdd_status qdd_solve_multi(qdd_ctx* const* ctxs, int nsys, const int* nrhs, const double* const* eta,
+                                      double* const* psi, qdd_solve_info* const* info) {
+  if (!ctxs || nsys < 1 || !nrhs || !eta || !psi) return QDD_EINVAL;
+  for (int s = 0; s < nsys; ++s)
+    for (int q = s + 1; q < nsys; ++q)
+      if (ctxs[s] == ctxs[q] || (ctxs[s]->st == ctxs[q]->st && ctxs[s]->st != nullptr)) {
+        ctxs[s]->fail("qdd_solve_multi: every system needs its own context and stream");
+        return QDD_EINVAL;
+      }
+  std::vector<qdd_status> st(nsys, QDD_OK);
+  std::vector<std::thread> th;
+  for (int s = 0; s < nsys; ++s)
+    th.emplace_back([&, s]() { st[s] = qdd_solve(ctxs[s], nrhs[s], eta[s], psi[s], info ? info[s] : nullptr); });
+  for (auto& t : th) t.join();
+  for (int s = 0; s < nsys; ++s)
+    if (st[s] != QDD_OK) return st[s];
+  return QDD_OK;
+}

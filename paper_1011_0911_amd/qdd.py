@@ -77,6 +77,9 @@ SIGNATURES = {
     "qdd_dfl_export": (_i, [_vp, _vp, _vp]),
     "qdd_dfl_coarse_solve": (_i, [_vp, _i, _vp, _vp, _d, ctypes.POINTER(_i)]),
     "qdd_dfl_precond": (_i, [_vp, _i, _vp, _vp]),
+    "qdd_dfl_share": (_i, [_vp, _vp]),
+    "qdd_solve_multi": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(_i), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                             ctypes.POINTER(_vp)]),
     "qdd_solve": (_i, [_vp, _i, _vp, _vp, _vp]),
     "qdd_net_num_weights": (_i, [_vp, ctypes.POINTER(ctypes.c_int64)]),
     "qdd_net_set_weights": (_i, [_vp, _vp]),
@@ -259,6 +262,9 @@ class Context:
         self._check(lib().qdd_dfl_export(self.h, _ptr(basis), _ptr(little)))
         return basis, little
 
+    def dfl_share(self, src: "Context"):
+        self._check(lib().qdd_dfl_share(self.h, src.h))
+
     def dfl_coarse_solve(self, f, tol):
         c_in = self._c128(f)
         nrhs = c_in.numel() // (self.dfl_nblocks() * self.cfg.dfl_Ns)
@@ -377,6 +383,34 @@ class Context:
         self._check(lib().qdd_dw_hat_timed(self.h, prec, nrhs, _ptr(fin), _ptr(fout), int(reps), ctypes.byref(a),
                                            ctypes.byref(b)))
         return a.value, b.value
+
+
+def solve_multi(ctxs, etas):
+    """Solves several systems concurrently (each context needs its own stream).
+    Returns (psis, infos, status)."""
+    n = len(ctxs)
+    H = (ctypes.c_void_p * n)(*[c.h for c in ctxs])
+    nr = (ctypes.c_int * n)()
+    E = (ctypes.c_void_p * n)()
+    P = (ctypes.c_void_p * n)()
+    I = (ctypes.c_void_p * n)()
+    keep, psis, infos = [], [], []
+    for k, (c, eta) in enumerate(zip(ctxs, etas)):
+        t = c._c128(eta)
+        m = t.numel() // (c.V * 12)
+        out = torch.empty((m, c.V, 4, 3), dtype=torch.complex128, device=c.device)
+        inf = (SolveInfo * m)()
+        keep.append(t)
+        psis.append(out)
+        infos.append(inf)
+        nr[k] = m
+        E[k] = t.data_ptr()
+        P[k] = out.data_ptr()
+        I[k] = ctypes.cast(inf, ctypes.c_void_p)
+    for c in ctxs:
+        torch.cuda.current_stream(c.device).synchronize()
+    st = lib().qdd_solve_multi(H, n, nr, E, P, I)
+    return psis, [[i.as_dict() for i in inf] for inf in infos], st
 
 
 def load_tune_cache(path):

@@ -1,0 +1,251 @@
+"""The benchmark workloads and their end-to-end drivers (set-up, deflation
+build, solves, network training), all through the C ABI.
+
+Synthetic inputs stand in for the paper's beta = 5.3 dynamical ensembles on
+48 x 24^3 (not available): random SU(3) links exp(i eps H) at the lattice sizes
+and hopping parameters below, Gaussian sources.  Seeds: gauge field of workload
+i: 1000 + i; sources 2000 + 100 i + r; network training sources 3000+; test
+sources 4000+; deflation start fields 5000 + i.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import qdd
+from . import synth as S
+
+WORKLOADS = {
+    1: dict(L=(4, 4, 4, 4), eps=0.3, kappa=0.13, csw=1.9, nrhs=1, op="Dhat", precond=qdd.PRECOND_NONE),
+    2: dict(L=(32, 16, 16, 16), eps=0.5, kappa=0.1355, csw=1.9, nrhs=12, sap_bs=(4, 4, 4, 4), nmr=4, ncy=5,
+            sap_prec=qdd.F32, dfl_Ns=20, precond=qdd.PRECOND_DFL),
+    3: dict(L=(64, 32, 32, 32), eps=0.6, kappa=0.1357, csw=1.9, nrhs=8, sap_bs=(4, 4, 4, 4), nmr=4, ncy=5,
+            sap_prec=qdd.F16, dfl_Ns=24, precond=qdd.PRECOND_DFL),
+    4: dict(lattices=[(8, 8, 8, 8), (16, 16, 16, 16), (48, 24, 24, 24), (64, 32, 32, 32)],
+            kappas=[0.1350, 0.1355, 0.1357], eps=0.6, csw=1.9, nrhs=4, sap_bs=(4, 4, 4, 4), nmr=4, ncy=5,
+            sap_prec=qdd.F32, dfl_Ns=20, precond=qdd.PRECOND_DFL),
+    5: dict(L=(48, 24, 24, 24), eps=0.6, kappa=0.1357, csw=1.9, nrhs=12, sap_bs=(4, 4, 4, 4), nmr=4, ncy=5,
+            sap_prec=qdd.F32, dfl_Ns=20, precond=qdd.PRECOND_DFL, net_ch=(1, 12, 12, 1), train_pairs=4096),
+}
+
+
+def make_context(L, eps, kappa, csw, gauge_seed, U=None, **cfg):
+    """Context with the gauge field and clover set up; returns (ctx, links)."""
+    import torch
+
+    if U is None:
+        U = S.random_su3_links(L, eps, gauge_seed)
+    c = qdd.Context(L, qdd.default_config(**cfg))
+    c.set_gauge(torch.from_numpy(U))
+    c.set_params(kappa, csw)
+    return c, U
+
+
+def solver_config(w: dict, nrhs: int, plain: bool = False, use_net: bool = False, **extra):
+    """qdd_config keywords for a workload; plain = FP64 SAP, FP64 deflation."""
+    cfg = dict(max_nrhs=nrhs, sap_bs=w.get("sap_bs", (4, 4, 4, 4)), nmr=w.get("nmr", 4), ncy=w.get("ncy", 5),
+               sap_prec=qdd.F64 if plain else w.get("sap_prec", qdd.F32), dfl_Ns=w.get("dfl_Ns", 0),
+               dfl_bs=w.get("dfl_bs", (4, 4, 4, 4)), precond=w.get("precond", qdd.PRECOND_NONE))
+    if use_net:
+        ch = w.get("net_ch", (1, 12, 12, 1))
+        cfg.update(use_net=1, net_nl=len(ch) - 1, net_ch=ch)
+    cfg.update(extra)
+    return cfg
+
+
+def timed_solve(ctx, eta):
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.time()
+    psi, info, st = ctx.solve(eta, check=False)
+    torch.cuda.synchronize()
+    return psi, info, st, time.time() - t0
+
+
+def run_solve_workload(wid: int, plain_rhs: int = 1, log=print):
+    """Mixed-precision batched deflated solve of workload wid next to the plain
+    FP64 solver (one right-hand side, FP64 SAP and deflation).  Returns a dict."""
+    import torch
+
+    w = WORKLOADS[wid]
+    L = w["L"]
+    V = int(np.prod(L))
+    nrhs = w["nrhs"]
+    out = {"workload": wid, "lattice": "x".join(map(str, L)), "nrhs": nrhs}
+    t0 = time.time()
+    U = S.random_su3_links(L, w["eps"], S.gauge_seed(wid))
+    log(f"[w{wid}] links {time.time() - t0:.1f} s")
+    eta = np.stack([S.gaussian_field(V, S.source_seed(wid, r)) for r in range(nrhs)])
+    init = S.gaussian_field(V, S.dfl_seed(wid), nrhs=w.get("dfl_Ns", 1))
+    # mixed precision, batched
+    ctx, _ = make_context(L, w["eps"], w["kappa"], w["csw"], 0, U=U, **solver_config(w, nrhs))
+    if w.get("dfl_Ns"):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        ctx.dfl_build(init)
+        torch.cuda.synchronize()
+        out["dfl_build_s"] = time.time() - t0
+    psi, info, st, dt = timed_solve(ctx, eta)
+    out["mixed"] = {"solve_s": dt, "iters": [i["iters"] for i in info],
+                    "true_res_max": max(i["true_res"] for i in info), "converged": all(i["converged"] for i in info),
+                    "sap_prec": {0: "f64", 1: "f32", 2: "f16"}[ctx.cfg.sap_prec]}
+    log(f"[w{wid}] mixed: {out['mixed']}")
+    del ctx
+    torch.cuda.empty_cache()
+    # plain FP64 reference solver on plain_rhs right-hand sides, one at a time
+    pctx, _ = make_context(L, w["eps"], w["kappa"], w["csw"], 0, U=U, **solver_config(w, 1, plain=True))
+    if w.get("dfl_Ns"):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        pctx.dfl_build(init)
+        torch.cuda.synchronize()
+        out["plain_dfl_build_s"] = time.time() - t0
+    ts, its = [], []
+    for r in range(plain_rhs):
+        _, pinfo, pst, pdt = timed_solve(pctx, eta[r:r + 1])
+        ts.append(pdt)
+        its.append(pinfo[0]["iters"])
+    out["plain_fp64"] = {"solve_s_per_rhs": float(np.mean(ts)), "iters": its, "rhs_timed": plain_rhs}
+    out["plain_fp64"]["solve_s_batch_equiv"] = out["plain_fp64"]["solve_s_per_rhs"] * nrhs
+    out["speedup_vs_plain"] = out["plain_fp64"]["solve_s_batch_equiv"] / out["mixed"]["solve_s"]
+    log(f"[w{wid}] plain: {out['plain_fp64']}")
+    del pctx
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_learned(wid: int = 5, train_pairs: int | None = None, chunk_pairs: int = 64, batch: int = 4,
+                lr: float = 1e-3, epochs: int = 1, test_rhs: int | None = None, log=print):
+    """Learned preconditioner workload: harvest (r_k, e_k) pairs from plain
+    deflated SAP-GCR solves on training sources, train the network on them in
+    streamed chunks, then solve fresh test sources with and without the network
+    stage (same deflation subspace).  Returns a dict."""
+    import torch
+
+    w = WORKLOADS[wid]
+    L = w["L"]
+    V = int(np.prod(L))
+    ntest = test_rhs or w["nrhs"]
+    npairs = train_pairs or w["train_pairs"]
+    out = {"workload": wid, "lattice": "x".join(map(str, L)), "train_pairs_target": npairs}
+    U = S.random_su3_links(L, w["eps"], S.gauge_seed(wid))
+    init = S.gaussian_field(V, S.dfl_seed(wid), nrhs=w["dfl_Ns"])
+    ctx, _ = make_context(L, w["eps"], w["kappa"], w["csw"], 0, U=U,
+                          **solver_config(w, ntest, use_net=True))
+    t0 = time.time()
+    ctx.dfl_build(init)
+    torch.cuda.synchronize()
+    out["dfl_build_s"] = time.time() - t0
+    nw = ctx.net_num_weights()
+    ctx.net_set_weights(S.random_weights(nw, 3000, 0.02))
+    # harvest and train in streamed chunks
+    rb, eb = ctx.pair_buffers(chunk_pairs)
+    fb32 = ctx.field_bytes(qdd.F32, 1, False)
+    got, src, steps, losses = 0, 0, 0, []
+    t_h = t_t = 0.0
+    while got < npairs:
+        n_chunk = 0
+        t0 = time.time()
+        while n_chunk < chunk_pairs and got + n_chunk < npairs:
+            eta = S.gaussian_field(V, 3000 + src)
+            src += 1
+            room = chunk_pairs - n_chunk
+            rview = rb[n_chunk * fb32:]
+            # harvest into a staging slot, then move the FP32 pairs next to the previous ones
+            _, info, n = ctx.solve_harvest(eta, rview, eb[n_chunk * fb32:], min(room, npairs - got - n_chunk),
+                                           check=False)
+            n_chunk += n
+        torch.cuda.synchronize()
+        t_h += time.time() - t0
+        t0 = time.time()
+        for _ in range(epochs):
+            for b0 in range(0, n_chunk - batch + 1, batch):
+                losses.append(ctx.net_train_step(rb[b0 * fb32:], eb[b0 * fb32:], batch, lr))
+                steps += 1
+        torch.cuda.synchronize()
+        t_t += time.time() - t0
+        got += n_chunk
+        log(f"[w{wid}] pairs {got}/{npairs} solves {src} steps {steps} loss {losses[-1] if losses else None}")
+    out.update(train_pairs=got, train_solves=src, train_steps=steps, harvest_s=t_h, train_s=t_t,
+               loss_first=losses[0] if losses else None, loss_last=losses[-1] if losses else None)
+    # evaluate on fresh sources: learned vs plain (same deflation subspace, network off)
+    eta = np.stack([S.gaussian_field(V, 4000 + r) for r in range(ntest)])
+    psi, info, st, dt = timed_solve(ctx, eta)
+    out["learned"] = {"solve_s": dt, "iters": [i["iters"] for i in info], "fallbacks": [i["fallbacks"] for i in info],
+                      "true_res_max": max(i["true_res"] for i in info), "converged": all(i["converged"] for i in info)}
+    ctx.net_set_weights(np.zeros(nw, complex))  # zero network: the stage adds nothing, plain iterates
+    psi0, info0, st0, dt0 = timed_solve(ctx, eta)
+    out["plain_same_subspace"] = {"solve_s": dt0, "iters": [i["iters"] for i in info0],
+                                  "true_res_max": max(i["true_res"] for i in info0)}
+    del ctx
+    torch.cuda.empty_cache()
+    # plain method proper: no network stage at all
+    pctx, _ = make_context(L, w["eps"], w["kappa"], w["csw"], 0, U=U, **solver_config(w, ntest))
+    pctx.dfl_build(init)
+    psi1, info1, st1, dt1 = timed_solve(pctx, eta)
+    out["plain"] = {"solve_s": dt1, "iters": [i["iters"] for i in info1],
+                    "true_res_max": max(i["true_res"] for i in info1)}
+    out["learned_vs_plain_time"] = dt1 / dt
+    log(f"[w{wid}] learned {out['learned']} plain {out['plain']}")
+    return out
+
+
+def run_multi(wid: int = 4, nkv: int = 8, log=print):
+    """Batched uneven solves: every lattice of the workload at every mass, nrhs
+    right-hand sides each, all systems solved concurrently (own context and
+    stream each).  The deflation subspace is built once per lattice at the middle
+    mass and shared with the other masses.  The same systems are then solved one
+    after the other for comparison.  Returns a dict."""
+    import torch
+
+    w = WORKLOADS[wid]
+    nrhs = w["nrhs"]
+    ctxs, etas, names = [], [], []
+    t_setup = time.time()
+    t_build = 0.0
+    for li, L in enumerate(w["lattices"]):
+        V = int(np.prod(L))
+        U = S.random_su3_links(L, w["eps"], S.gauge_seed(wid) + 10 * li)
+        init = S.gaussian_field(V, S.dfl_seed(wid) + 10 * li, nrhs=w["dfl_Ns"])
+        group = []
+        for ki, kappa in enumerate(w["kappas"]):
+            c = qdd.Context(L, qdd.default_config(**solver_config(w, nrhs, nkv=nkv)), stream=torch.cuda.Stream())
+            c.set_gauge(torch.from_numpy(U))
+            c.set_params(kappa, w["csw"])
+            group.append(c)
+            etas.append(np.stack([S.gaussian_field(V, S.source_seed(wid, 10 * li + r) + ki) for r in range(nrhs)]))
+            names.append(f"{'x'.join(map(str, L))}/k{kappa}")
+        mid = len(group) // 2
+        torch.cuda.synchronize()
+        t0 = time.time()
+        group[mid].dfl_build(init)
+        for k, c in enumerate(group):
+            if k != mid:
+                c.dfl_share(group[mid])
+        torch.cuda.synchronize()
+        t_build += time.time() - t0
+        ctxs += group
+        del U
+        log(f"[w{wid}] lattice {L} ready")
+    out = {"workload": wid, "systems": len(ctxs), "nrhs_each": nrhs, "setup_s": time.time() - t_setup,
+           "dfl_build_s": t_build}
+    torch.cuda.synchronize()
+    t0 = time.time()
+    psis, infos, st = qdd.solve_multi(ctxs, etas)
+    torch.cuda.synchronize()
+    out["concurrent_s"] = time.time() - t0
+    out["status"] = st
+    out["systems_detail"] = [{"system": n, "iters": [i["iters"] for i in inf], "converged": all(i["converged"] for i in inf),
+                              "true_res_max": max(i["true_res"] for i in inf)} for n, inf in zip(names, infos)]
+    out["all_converged"] = all(d["converged"] for d in out["systems_detail"])
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for c, eta in zip(ctxs, etas):
+        c.solve(eta, check=False)
+        torch.cuda.synchronize()
+    out["sequential_s"] = time.time() - t0
+    out["concurrency_speedup"] = out["sequential_s"] / out["concurrent_s"]
+    log(f"[w{wid}] concurrent {out['concurrent_s']:.3f} s sequential {out['sequential_s']:.3f} s")
+    return out
