@@ -7,6 +7,12 @@ c_sw 1.9, 8 Gaussian right-hand sides, FP16 storage with FP32 arithmetic).
 A step is one Dhat apply of the whole batch (two kernel launches).  Prints one
 JSON line (metric, value in TB/s of algorithmic bytes, roofline of the dominant
 kernel measured with HIP events on the library's stream, CPU-oracle baseline).
+The second half of the metric, seconds to relative residual 1e-10, is measured
+after the timed Dhat steps on the same lattice: the mixed-precision batched
+deflated SAP-GCR solve of the 8 right-hand sides next to the plain FP64 solver,
+and, on 24^3 x 48, the solver with the learned preconditioner stage (network
+trained on the GPU from pairs the plain solver harvests) next to the solver
+without it.
 
 Byte model per even site and right-hand side batch of n (reals; each field
 element read or written once per pass, Hermitian 6x6 clover blocks as 36 reals):
@@ -18,7 +24,6 @@ scale per site and spinor access (8 per rhs in pass A, 12 in pass B).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -45,14 +50,6 @@ def bytes_per_site(prec: int, nrhs: int):
     return a, bb
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("qdd_dirac.hip", "qdd_internal.h"):
-        with open(os.path.join(ROOT, "paper_1011_0911_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(prec, nrhs, launch):
     """HBM bytes per launch of pass B from the committed rocprofv3 counter summary,
     if it was taken on the current kernel source with the same launch shape."""
@@ -64,6 +61,8 @@ def measured_traffic(prec, nrhs, launch):
         return None
     key = f"prec{prec}_nrhs{nrhs}"
     e = d.get("entries", {}).get(key)
+    from paper_1011_0911_amd.profsum import kernel_source_hash
+
     if not e or e.get("kernel_hash") != kernel_source_hash() or e.get("launch") != list(launch):
         return None
     return e.get("pass_b_bytes")
@@ -100,6 +99,40 @@ def cpu_baseline(U, nrhs_gpu, prec_gpu, budget_s=12.0):
                        f"GPU's per-rhs byte model ({per_rhs:.0f} B/site)")}
 
 
+def solve_section(learned_pairs, U=None):
+    """Seconds to relative residual 1e-10 (true FP64 residual): the mixed
+    precision batched solver against the plain FP64 solver on 32^3 x 64, and the
+    learned-stage solver against the same solver without it on 24^3 x 48."""
+    from paper_1011_0911_amd import workloads as W
+
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    r3 = W.run_solve_workload(3, plain_rhs=1, log=log, U=U)
+    sec = {"tolerance": 1e-10,
+           "mixed_vs_plain": {
+               "workload": "32^3x64, 8 rhs batched, FP16-storage SAP (4^4 blocks, nmr 4, ncy 5), 24 deflation "
+                           "vectors, FP64 outer FGCR and little-Dirac solve",
+               "mixed_s": r3["mixed"]["solve_s"], "mixed_iters": r3["mixed"]["iters"],
+               "mixed_true_res_max": r3["mixed"]["true_res_max"], "mixed_converged": r3["mixed"]["converged"],
+               "plain_fp64_s_per_rhs": r3["plain_fp64"]["solve_s_per_rhs"],
+               "plain_fp64_s_8rhs": r3["plain_fp64"]["solve_s_batch_equiv"],
+               "plain_iters": r3["plain_fp64"]["iters"], "speedup": r3["speedup_vs_plain"],
+               "dfl_build_s": {"mixed": r3.get("dfl_build_s"), "plain_fp64": r3.get("plain_dfl_build_s")}}}
+    if learned_pairs > 0:
+        r5 = W.run_learned(5, train_pairs=learned_pairs, log=log)
+        sec["learned_vs_plain"] = {
+            "workload": f"24^3x48, 12 rhs, FP32 SAP, 20 deflation vectors; network 1-12-12-1 channels trained on "
+                        f"{r5['train_pairs']} pairs ({r5['train_steps']} Adam steps)",
+            "learned_s": r5["learned"]["solve_s"], "learned_iters": r5["learned"]["iters"],
+            "learned_fallbacks": r5["learned"]["fallbacks"], "learned_true_res_max": r5["learned"]["true_res_max"],
+            "learned_converged": r5["learned"]["converged"],
+            "plain_s": r5["plain"]["solve_s"], "plain_iters": r5["plain"]["iters"],
+            "plain_true_res_max": r5["plain"]["true_res_max"],
+            "learned_over_plain_time": r5["learned"]["solve_s"] / r5["plain"]["solve_s"],
+            "loss_first": r5["loss_first"], "loss_last": r5["loss_last"],
+            "harvest_s": r5["harvest_s"], "train_s": r5["train_s"]}
+    return sec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +142,9 @@ def main():
     ap.add_argument("--prec", type=int, default=2, help="0 FP64, 1 FP32, 2 FP16 storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-solve", action="store_true", help="skip the solve timings")
+    ap.add_argument("--learned-pairs", type=int, default=64,
+                    help="training pairs for the learned-stage solve timing (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only (no multi-GPU path); use --gpus 1"}))
@@ -200,18 +236,22 @@ def main():
                                                 "sb": launch[3]},
                    "frac_of_peak_whole_apply": round(value / PEAK_HBM_TBS, 4),
                    "pass_a": {"ms": round(ms_a, 5), "TBs": round(ach_a, 4)},
-                   "copy_reference_TBs": round(copy_tbs, 4), "wall_s_timed": round(wall, 3)},
+                   "copy_reference_TBs": round(copy_tbs, 4), "copy_bytes": nb, "wall_s_timed": round(wall, 3)},
         "roofline": {"bound": "hbm", "kernel": "k_dhat_b (pass B)", "achieved": round(ach_b, 4),
                      "peak": PEAK_HBM_TBS, "unit": "TB/s", "frac": round(ach_b / PEAK_HBM_TBS, 4),
                      "traffic": traffic, "bytes_per_launch": b_b * Vh, "ms_per_launch": round(ms_b, 5)},
         "cpu_baseline": None,
     }
+    del ctx, fin, fout
+    torch.cuda.empty_cache()
+    if not args.no_solve:
+        out["solve"] = solve_section(args.learned_pairs, U)
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(U, nrhs, prec)
         except Exception as e:  # the baseline is reported, never required
             out["cpu_baseline"] = {"error": str(e)}
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, default=float), flush=True)
 
 
 if __name__ == "__main__":

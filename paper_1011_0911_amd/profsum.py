@@ -1,0 +1,136 @@
+"""Summaries of rocprofv3 output for the committed profile records.
+
+  python -m paper_1011_0911_amd.profsum stats DIR --cmd "..."
+      per-kernel call count and average / total duration from a
+      `rocprofv3 --kernel-trace --stats` run (markdown table on stdout)
+
+  python -m paper_1011_0911_amd.profsum traffic --bench-json F --fetch DIR --write DIR --out J --cmd "..."
+      HBM bytes per launch of the Dhat pass-B kernel from two `rocprofv3 --pmc`
+      runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what
+      the same counter reads for the plain copy kernel the benchmark runs on a
+      known number of bytes; merged into the JSON file J under the key
+      prec{P}_nrhs{N} together with the kernel source hash and launch shape, so
+      that the benchmark reports the figure only while both still match.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def kernel_source_hash() -> str:
+    """Hash of the sources the Dhat kernels are compiled from."""
+    h = hashlib.sha256()
+    for f in ("qdd_dirac.hip", "qdd_internal.h"):
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _one(d: str, pattern: str) -> str:
+    hits = sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no {pattern} under {d}")
+    return hits[0]
+
+
+def _short(name: str) -> str:
+    return name.split("(")[0].replace("void ", "")
+
+
+def stats(d: str, cmd: str) -> str:
+    rows = list(csv.DictReader(open(_one(d, "*kernel_stats.csv"))))
+    out = [f"Command: `{cmd}`", "", "| kernel | calls | avg us | min us | max us | total ms | % |",
+           "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        out.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
+    return "\n".join(out)
+
+
+def _counter(d: str, counter: str):
+    """{(short kernel name, grid size): [values per dispatch]} for one counter."""
+    res = {}
+    for r in csv.DictReader(open(_one(d, "*counter_collection.csv"))):
+        if r["Counter_Name"] != counter:
+            continue
+        res.setdefault((_short(r["Kernel_Name"]), int(r["Grid_Size"])), []).append(float(r["Counter_Value"]))
+    return res
+
+
+def traffic(bench_json: str, fetch_dir: str, write_dir: str, out_path: str, cmd: str) -> dict:
+    with open(bench_json) as f:
+        b = json.loads([ln for ln in f if ln.startswith("{")][-1])
+    cfg = b["config"]
+    prec = {"f64": 0, "f32": 1}.get(cfg["storage"], 2)
+    nrhs = cfg["nrhs"]
+    ln = cfg["launch"]
+    launch = [ln["block"], ln["nr"], ln["xcd"], ln["sb"]]
+    copy_bytes = cfg["copy_bytes"]
+    tname = {0: "double", 1: "float", 2: "__half"}[prec]
+    kb = f"qdd::k_dhat_b<{tname}, {ln['nr']}>"
+    fetch, write = _counter(fetch_dir, "FETCH_SIZE"), _counter(write_dir, "WRITE_SIZE")
+
+    def pick(tab, kname):
+        c = [(k, v) for k, v in tab.items() if k[0] == kname]
+        if not c:
+            raise KeyError(f"{kname} not in the counter output")
+        k, v = max(c, key=lambda kv: len(kv[1]))  # the timed launches: most dispatches
+        return sum(v) / len(v), len(v), k[1]
+
+    cf, _, _ = pick(fetch, "qdd::k_copy")
+    cw, _, _ = pick(write, "qdd::k_copy")
+    f_scale = copy_bytes / (cf * 1024.0)
+    w_scale = copy_bytes / (cw * 1024.0)
+    fb, nf, grid = pick(fetch, kb)
+    wb, nw, _ = pick(write, kb)
+    entry = {"kernel": kb, "grid": grid, "launch": launch, "kernel_hash": kernel_source_hash(),
+             "fetch_kib_raw": fb, "write_kib_raw": wb, "dispatches": [nf, nw],
+             "copy_calibration": {"bytes": copy_bytes, "fetch_kib_raw": cf, "write_kib_raw": cw,
+                                  "fetch_scale": f_scale, "write_scale": w_scale},
+             "fetch_bytes": fb * 1024.0 * f_scale, "write_bytes": wb * 1024.0 * w_scale,
+             "algorithmic_bytes": b["roofline"]["bytes_per_launch"], "command": cmd}
+    entry["pass_b_bytes"] = entry["fetch_bytes"] + entry["write_bytes"]
+    entry["traffic_over_algorithmic"] = entry["pass_b_bytes"] / entry["algorithmic_bytes"]
+    try:
+        with open(out_path) as f:
+            doc = json.load(f)
+    except (OSError, ValueError):
+        doc = {"entries": {}}
+    doc["entries"][f"prec{prec}_nrhs{nrhs}"] = entry
+    with open(out_path, "w") as f:
+        json.dump(doc, f, indent=1)
+    return entry
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sp = ap.add_subparsers(dest="what", required=True)
+    a = sp.add_parser("stats")
+    a.add_argument("dir")
+    a.add_argument("--cmd", required=True)
+    t = sp.add_parser("traffic")
+    t.add_argument("--bench-json", required=True)
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--cmd", required=True)
+    o = ap.parse_args(argv)
+    if o.what == "stats":
+        print(stats(o.dir, o.cmd))
+    else:
+        e = traffic(o.bench_json, o.fetch, o.write, o.out, o.cmd)
+        json.dump(e, sys.stdout, indent=1)
+        print()
+
+
+if __name__ == "__main__":
+    main()

@@ -64,9 +64,10 @@ def timed_solve(ctx, eta):
     return psi, info, st, time.time() - t0
 
 
-def run_solve_workload(wid: int, plain_rhs: int = 1, log=print):
+def run_solve_workload(wid: int, plain_rhs: int = 1, log=print, U=None):
     """Mixed-precision batched deflated solve of workload wid next to the plain
-    FP64 solver (one right-hand side, FP64 SAP and deflation).  Returns a dict."""
+    FP64 solver (one right-hand side, FP64 SAP and deflation).  U: the links of
+    the workload if already generated.  Returns a dict."""
     import torch
 
     w = WORKLOADS[wid]
@@ -75,7 +76,8 @@ def run_solve_workload(wid: int, plain_rhs: int = 1, log=print):
     nrhs = w["nrhs"]
     out = {"workload": wid, "lattice": "x".join(map(str, L)), "nrhs": nrhs}
     t0 = time.time()
-    U = S.random_su3_links(L, w["eps"], S.gauge_seed(wid))
+    if U is None:
+        U = S.random_su3_links(L, w["eps"], S.gauge_seed(wid))
     log(f"[w{wid}] links {time.time() - t0:.1f} s")
     eta = np.stack([S.gaussian_field(V, S.source_seed(wid, r)) for r in range(nrhs)])
     init = S.gaussian_field(V, S.dfl_seed(wid), nrhs=w.get("dfl_Ns", 1))
@@ -249,3 +251,30 @@ def run_multi(wid: int = 4, nkv: int = 8, log=print):
     out["concurrency_speedup"] = out["sequential_s"] / out["concurrent_s"]
     log(f"[w{wid}] concurrent {out['concurrent_s']:.3f} s sequential {out['sequential_s']:.3f} s")
     return out
+
+
+def main(argv=None):
+    """Command line: python -m paper_1011_0911_amd.workloads WID [--pairs N]
+    runs one workload driver on cuda:0 and prints its result as one JSON line."""
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("wid", type=int, choices=[2, 3, 4, 5])
+    ap.add_argument("--pairs", type=int, default=None, help="training pairs (workload 5)")
+    ap.add_argument("--chunk", type=int, default=64, help="pairs per streamed training chunk (workload 5)")
+    ap.add_argument("--epochs", type=int, default=1)
+    ap.add_argument("--plain-rhs", type=int, default=1, help="right-hand sides timed with the plain solver")
+    a = ap.parse_args(argv)
+    log = lambda m: print(m, flush=True)  # noqa: E731
+    if a.wid == 5:
+        r = run_learned(5, train_pairs=a.pairs, chunk_pairs=a.chunk, epochs=a.epochs, log=log)
+    elif a.wid == 4:
+        r = run_multi(4, log=log)
+    else:
+        r = run_solve_workload(a.wid, plain_rhs=a.plain_rhs, log=log)
+    print(json.dumps(r, default=float), flush=True)
+
+
+if __name__ == "__main__":
+    main()
