@@ -224,11 +224,15 @@ qdd_status qdd_solve_harvest(qdd_ctx* ctx, const double* eta, double* psi, qdd_s
 
 /* Launch shape of a kernel family (kernel: 0 = Dhat, 1 = D; prec: qdd_prec):
  * block threads (64..256, multiple of 64); nr right-hand sides per lane (1, 2,
- * 4; the links are loaded once for all of them); xcd: block walk (0 linear;
- * 1 every XCD takes a contiguous slab of the lattice; 2 slabs whose tiles are
- * walked time slice first, so time and x1 neighbours stay in the XCD's L2); sb sites per block (0 = block): the block/sb lane groups of a block
- * take further right-hand sides of the same sites, so a wavefront of 64 lanes
- * covers 64/sb right-hand sides and fetches each link once for all of them. */
+ * 4; the links are loaded once for all of them), or nr = 0 (Dhat only): the
+ * staged variant, where a workgroup reads the links and clover of its tile of
+ * sb sites into LDS once and its block/sb lanes per site loop over all
+ * right-hand sides (tile LDS: 108 complex per site, at most 64 KiB); xcd: block
+ * walk (0 linear; 1 every XCD takes a contiguous slab of the lattice; 2 slabs
+ * whose tiles are walked time slice first, so time and x1 neighbours stay in
+ * the XCD's L2); sb sites per block (0 = block): the block/sb lane groups of a
+ * block take further right-hand sides of the same sites.  QDD_EINVAL for shapes
+ * outside these ranges. */
 qdd_status qdd_set_launch(qdd_ctx* ctx, int kernel, qdd_prec prec, int block, int nr, int xcd, int sb);
 qdd_status qdd_get_launch(const qdd_ctx* ctx, int kernel, qdd_prec prec, int* block, int* nr, int* xcd, int* sb);
 

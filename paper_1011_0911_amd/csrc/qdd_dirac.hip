@@ -14,42 +14,50 @@
 
 namespace qdd {
 
-template <class S, int MU, int NR>
+template <class S, int MU, int NR, bool O32>
 __device__ inline void hop_dir(const Geo& g, const LinkV<S>& U, const FieldV<S>& in, int r0, int nr, int p, int i,
-                               const int x[4], cx<typename St<S>::T> (&acc)[NR][12]) {
+                               const int x[4], typename St<S>::T c0, cx<typename St<S>::T> (&acc)[NR][12]) {
   typedef typename St<S>::T T;
   cx<T> u[9], s[12], h[6], gg[6];
   int j = nbr_idx(g, x, MU, +1);
-  ld_link(U, p, MU, i, u);
+  ld_link_u(U, p, MU, i, u);
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     if (q < nr) {
-      ld_spinor(in, r0 + q, j, s);
+      T sc = ld_spinor_raw<S, O32>(in, r0 + q, j, s);
       project<T, MU, +1>(s, h);
       su3_mul_half<T, false>(u, h, gg);
-      reconstruct_add<T, MU, +1>(gg, acc[q]);
+      reconstruct_add<T, MU, +1>(gg, acc[q], c0 * sc);
     }
   }
+  __builtin_amdgcn_sched_barrier(0);
   j = nbr_idx(g, x, MU, -1);
-  ld_link(U, 1 - p, MU, j, u);
+  ld_link_u(U, 1 - p, MU, j, u);
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     if (q < nr) {
-      ld_spinor(in, r0 + q, j, s);
+      T sc = ld_spinor_raw<S, O32>(in, r0 + q, j, s);
       project<T, MU, -1>(s, h);
       su3_mul_half<T, true>(u, h, gg);
-      reconstruct_add<T, MU, -1>(gg, acc[q]);
+      reconstruct_add<T, MU, -1>(gg, acc[q], c0 * sc);
     }
   }
 }
 
-template <class S, int NR>
+// acc += c0 H in (H: the hopping sum over the 8 neighbours)
+template <class S, int NR, bool O32>
 __device__ inline void hop_all(const Geo& g, const LinkV<S>& U, const FieldV<S>& in, int r0, int nr, int p, int i,
-                               const int x[4], cx<typename St<S>::T> (&acc)[NR][12]) {
-  hop_dir<S, 0, NR>(g, U, in, r0, nr, p, i, x, acc);
-  hop_dir<S, 1, NR>(g, U, in, r0, nr, p, i, x, acc);
-  hop_dir<S, 2, NR>(g, U, in, r0, nr, p, i, x, acc);
-  hop_dir<S, 3, NR>(g, U, in, r0, nr, p, i, x, acc);
+                               const int x[4], typename St<S>::T c0, cx<typename St<S>::T> (&acc)[NR][12]) {
+  // scheduling barriers between the directions bound the number of loads in
+  // flight per lane (and so the registers); the other waves hide the latency
+  hop_dir<S, 0, NR, O32>(g, U, in, r0, nr, p, i, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_dir<S, 1, NR, O32>(g, U, in, r0, nr, p, i, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_dir<S, 2, NR, O32>(g, U, in, r0, nr, p, i, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_dir<S, 3, NR, O32>(g, U, in, r0, nr, p, i, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 // block b of nblk (of one parity) -> (site tile, rhs group).
@@ -82,8 +90,8 @@ __device__ inline bool lane_site(const Geo& g, int tile, int rg, int sb, int nrh
   return i < g.Vh && r0 < nrhs;
 }
 
-template <class S, int NR>
-__global__ void __launch_bounds__(256) k_dhat_a(Geo g, LinkV<S> U, CloverV<S> Ai, FieldV<S> in_e, FieldV<S> t_o,
+template <class S, int NR, bool O32>
+__global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k_dhat_a(Geo g, LinkV<S> U, CloverV<S> Ai, FieldV<S> in_e, FieldV<S> t_o,
                                                 int nrhs, int nrg, int order, int sb) {
   typedef typename St<S>::T T;
   int tile, rg, i, r0;
@@ -97,19 +105,19 @@ __global__ void __launch_bounds__(256) k_dhat_a(Geo g, LinkV<S> U, CloverV<S> Ai
   for (int q = 0; q < NR; ++q)
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[q][k] = {T(0), T(0)};
-  hop_all<S, NR>(g, U, in_e, r0, nr, 1, i, x, acc);
+  hop_all<S, NR, O32>(g, U, in_e, r0, nr, 1, i, x, T(1), acc);
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     if (q < nr) {
       cx<T> o[12];
-      clover_apply<S>(Ai, 1, i, acc[q], o);
-      st_spinor(t_o, r0 + q, i, o);
+      clover_apply_u<S>(Ai, 1, i, acc[q], o);
+      st_spinor<S, O32>(t_o, r0 + q, i, o);
     }
   }
 }
 
-template <class S, int NR>
-__global__ void __launch_bounds__(256) k_dhat_b(Geo g, LinkV<S> U, CloverV<S> A, FieldV<S> in_e, FieldV<S> t_o,
+template <class S, int NR, bool O32>
+__global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k_dhat_b(Geo g, LinkV<S> U, CloverV<S> A, FieldV<S> in_e, FieldV<S> t_o,
                                                 FieldV<S> out_e, int nrhs, int nrg, int order, int sb) {
   typedef typename St<S>::T T;
   int tile, rg, i, r0;
@@ -118,29 +126,30 @@ __global__ void __launch_bounds__(256) k_dhat_b(Geo g, LinkV<S> U, CloverV<S> A,
   int nr = min(NR, nrhs - r0);
   int x[4];
   site_coords(g, 0, i, x);
+  // acc = -1/4 H t_o, then out = A_e psi_e + acc
   cx<T> acc[NR][12];
 #pragma unroll
   for (int q = 0; q < NR; ++q)
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[q][k] = {T(0), T(0)};
-  hop_all<S, NR>(g, U, t_o, r0, nr, 0, i, x, acc);
+  hop_all<S, NR, O32>(g, U, t_o, r0, nr, 0, i, x, T(-0.25), acc);
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     if (q < nr) {
       cx<T> s[12], o[12];
-      ld_spinor(in_e, r0 + q, i, s);
-      clover_apply<S>(A, 0, i, s, o);
+      T sc = ld_spinor_raw<S, O32>(in_e, r0 + q, i, s);
+      clover_apply_u<S>(A, 0, i, s, o);
 #pragma unroll
-      for (int k = 0; k < 12; ++k) o[k] = o[k] - T(0.25) * acc[q][k];
-      st_spinor(out_e, r0 + q, i, o);
+      for (int k = 0; k < 12; ++k) o[k] = cacc(acc[q][k], sc, o[k]);
+      st_spinor<S, O32>(out_e, r0 + q, i, o);
     }
   }
 }
 
 // full D on both parities; in/out: full fields (parity p at offset p*poff
 // elements); the two halves of the grid are walked like two Dhat passes
-template <class S, int NR>
-__global__ void __launch_bounds__(256) k_dw(Geo g, LinkV<S> U, CloverV<S> A, FieldV<S> in, FieldV<S> out,
+template <class S, int NR, bool O32>
+__global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k_dw(Geo g, LinkV<S> U, CloverV<S> A, FieldV<S> in, FieldV<S> out,
                                             int64_t poff, int64_t spoff, int nrhs, int nrg, int order, int sb) {
   typedef typename St<S>::T T;
   int nh = gridDim.x >> 1;
@@ -160,27 +169,204 @@ __global__ void __launch_bounds__(256) k_dw(Geo g, LinkV<S> U, CloverV<S> A, Fie
     self.scale += p * spoff;
     dst.scale += p * spoff;
   }
+  // acc = -1/2 H psi_{1-p}, then out = A_p psi_p + acc
   cx<T> acc[NR][12];
 #pragma unroll
   for (int q = 0; q < NR; ++q)
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[q][k] = {T(0), T(0)};
-  hop_all<S, NR>(g, U, src, r0, nr, p, i, x, acc);
+  hop_all<S, NR, O32>(g, U, src, r0, nr, p, i, x, T(-0.5), acc);
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     if (q < nr) {
       cx<T> s[12], o[12];
-      ld_spinor(self, r0 + q, i, s);
-      clover_apply<S>(A, p, i, s, o);
+      T sc = ld_spinor_raw<S, O32>(self, r0 + q, i, s);
+      clover_apply_u<S>(A, p, i, s, o);
 #pragma unroll
-      for (int k = 0; k < 12; ++k) o[k] = o[k] - T(0.5) * acc[q][k];
-      st_spinor(dst, r0 + q, i, o);
+      for (int k = 0; k < 12; ++k) o[k] = cacc(acc[q][k], sc, o[k]);
+      st_spinor<S, O32>(dst, r0 + q, i, o);
     }
+  }
+}
+
+// ------------------------------------------------- LDS-staged batched variant
+// A workgroup owns a tile of sb consecutive sites of one parity and all
+// right-hand sides: blockDim = sb x R lanes, lane (s, rl) takes site s and the
+// right-hand sides rl, rl + R, ...  The tile's 8 links per site (4 forward of its
+// own parity, 4 backward stored at the neighbours of the other parity) and its
+// clover block are read from HBM once, coalesced, into LDS as [slot][site]; every
+// lane then loops over its right-hand sides with the links and the clover taken
+// from LDS and only the spinors from global memory.  Slots: 0..35 forward links
+// (9 per direction), 36..71 backward links, 72..107 clover (2 x 18).
+constexpr int kStageSlots = 108;
+
+template <class S>
+__device__ inline typename St<S>::E stage_elem(const LinkV<S>& U, const CloverV<S>& C, int p, int i, const int nb[4],
+                                               int slot) {
+  if (slot < 36) {
+    int mu = slot / 9, k = slot - 9 * mu;
+    return U.p[((int64_t)(p * 4 + mu) * 9 + k) * U.n + i];
+  }
+  if (slot < 72) {
+    int mu = (slot - 36) / 9, k = slot - 36 - 9 * mu;
+    return U.p[((int64_t)((1 - p) * 4 + mu) * 9 + k) * U.n + nb[mu]];
+  }
+  return C.p[((int64_t)p * 36 + (slot - 72)) * C.n + i];
+}
+
+// lane (s, rl) moves slots rl, rl + R, ... of site s; the loads of a chunk are
+// all issued before the first LDS write so their latencies overlap
+template <class S>
+__device__ inline void stage_tile(const Geo& g, const LinkV<S>& U, const CloverV<S>& C, int p, int i, bool valid,
+                                  int s, int sb, int rl, int R, const int nb[4], typename St<S>::E* lds) {
+  typedef typename St<S>::E E;
+  constexpr int CH = 12;
+  for (int base = rl; base < kStageSlots; base += CH * R) {
+    E v[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      int slot = base + c * R;
+      v[c] = (valid && slot < kStageSlots) ? stage_elem<S>(U, C, p, i, nb, slot) : E{};
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      int slot = base + c * R;
+      if (slot < kStageSlots) lds[slot * sb + s] = v[c];
+    }
+  }
+}
+
+template <class S, int MU, bool O32>
+__device__ inline void hop_dir_lds(const typename St<S>::E* lds, int sb, int s, const FieldV<S>& in, int r, int jf,
+                                   int jb, typename St<S>::T c0, cx<typename St<S>::T> (&acc)[12]) {
+  typedef typename St<S>::T T;
+  cx<T> u[9], sp[12], h[6], gg[6];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) u[k] = St<S>::ldc(lds + (MU * 9 + k) * sb + s);
+  T sc = ld_spinor_raw<S, O32>(in, r, jf, sp);
+  project<T, MU, +1>(sp, h);
+  su3_mul_half<T, false>(u, h, gg);
+  reconstruct_add<T, MU, +1>(gg, acc, c0 * sc);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) u[k] = St<S>::ldc(lds + (36 + MU * 9 + k) * sb + s);
+  sc = ld_spinor_raw<S, O32>(in, r, jb, sp);
+  project<T, MU, -1>(sp, h);
+  su3_mul_half<T, true>(u, h, gg);
+  reconstruct_add<T, MU, -1>(gg, acc, c0 * sc);
+}
+
+template <class S>
+__device__ inline void clover_lds(const typename St<S>::E* lds, int sb, int s, const cx<typename St<S>::T> in[12],
+                                  cx<typename St<S>::T> out[12]) {
+  typedef typename St<S>::T T;
+#pragma unroll
+  for (int blk = 0; blk < 2; ++blk) {
+    cx<T> a[18];
+#pragma unroll
+    for (int k = 0; k < 18; ++k) a[k] = St<S>::ldc(lds + (72 + blk * 18 + k) * sb + s);
+    herm6_mul<T>(a, in + 6 * blk, out + 6 * blk);
+  }
+}
+
+// PASS 0 (pass A, odd sites):  out = A_o^{-1} H in      (in: even field)
+// PASS 1 (pass B, even sites): out = A_e self - 1/4 H in (in: odd field t_o)
+template <class S, int PASS, bool O32>
+__global__ void __launch_bounds__(256, sizeof(S) == 8 ? 2 : 4) k_dhat_staged(Geo g, LinkV<S> U, CloverV<S> C, FieldV<S> in, FieldV<S> self,
+                                                     FieldV<S> out, int nrhs, int order, int sb) {
+  typedef typename St<S>::T T;
+  typedef typename St<S>::E E;
+  extern __shared__ unsigned char smem[];
+  E* lds = reinterpret_cast<E*>(smem);
+  const int p = PASS == 0 ? 1 : 0;
+  int tile, rg;
+  map_block(g, blockIdx.x, gridDim.x, 1, sb, order, tile, rg);
+  const int s = (int)threadIdx.x % sb, rl = (int)threadIdx.x / sb, R = (int)blockDim.x / sb;
+  const int i = tile * sb + s;
+  const bool valid = i < g.Vh;
+  int jf[4], jb[4];
+  if (valid) {
+    int x[4];
+    site_coords(g, p, i, x);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      jf[mu] = nbr_idx(g, x, mu, +1);
+      jb[mu] = nbr_idx(g, x, mu, -1);
+    }
+  }
+  stage_tile<S>(g, U, C, p, i, valid, s, sb, rl, R, jb, lds);
+  __syncthreads();
+  if (!valid) return;
+  for (int r = rl; r < nrhs; r += R) {
+    // the LDS reads are the same for every right-hand side; an opaque copy of
+    // the site offset keeps the compiler from hoisting all 108 of them out of
+    // the loop into registers (which would cut the occupancy to one wave)
+    int so = s;
+    asm volatile("" : "+v"(so));
+    cx<T> acc[12], o[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+    const T c0 = PASS == 0 ? T(1) : T(-0.25);
+    hop_dir_lds<S, 0, O32>(lds, sb, so, in, r, jf[0], jb[0], c0, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    hop_dir_lds<S, 1, O32>(lds, sb, so, in, r, jf[1], jb[1], c0, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    hop_dir_lds<S, 2, O32>(lds, sb, so, in, r, jf[2], jb[2], c0, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    hop_dir_lds<S, 3, O32>(lds, sb, so, in, r, jf[3], jb[3], c0, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (PASS == 0) {
+      clover_lds<S>(lds, sb, so, acc, o);
+    } else {
+      cx<T> v[12];
+      T sc = ld_spinor_raw<S, O32>(self, r, i, v);
+      clover_lds<S>(lds, sb, so, v, o);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) o[k] = cacc(acc[k], sc, o[k]);
+    }
+    st_spinor<S, O32>(out, r, i, o);
   }
 }
 
 // ----------------------------------------------------------------- launchers
 static inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// true if every element offset (r * rs + i, r < nrhs, i < n, plus the parity
+// offset poff of a full field) of f, in bytes, and of its scale array, stays
+// below 2^32: the kernels may then form the offsets in 32 bits
+template <class S>
+static bool fits32(const FieldV<S>& f, int nrhs, int64_t poff = 0, int64_t spoff = 0) {
+  const int64_t lim = (int64_t)1 << 32;
+  int64_t e = ((int64_t)(nrhs - 1) * f.rs + f.n + poff) * (int64_t)sizeof(typename St<S>::E);
+  int64_t sc = f.scale ? ((int64_t)(nrhs - 1) * f.srs + f.n + spoff) * 4 : 0;
+  return e < lim && sc < lim;
+}
+
+template <class S>
+static hipError_t launch_dhat_staged(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> tmp, FieldV<S> out,
+                                     int nrhs, const LaunchCfg& c, hipStream_t st, int pass, hipEvent_t ev) {
+  int sb = c.sb > 0 ? c.sb : c.block;
+  dim3 grid(ceil_div(g.Vh, sb)), blk(c.block);
+  size_t lds = (size_t)kStageSlots * sb * sizeof(typename St<S>::E);
+  const bool o32 = fits32(in, nrhs) && fits32(tmp, nrhs) && fits32(out, nrhs);
+  if (pass & 1) {
+    if (o32)
+      hipLaunchKernelGGL((k_dhat_staged<S, 0, true>), grid, blk, lds, st, g, op.U, op.Ainv, in, in, tmp, nrhs, c.xcd,
+                         sb);
+    else
+      hipLaunchKernelGGL((k_dhat_staged<S, 0, false>), grid, blk, lds, st, g, op.U, op.Ainv, in, in, tmp, nrhs, c.xcd,
+                         sb);
+  }
+  if (ev) (void)hipEventRecord(ev, st);
+  if (pass & 2) {
+    if (o32)
+      hipLaunchKernelGGL((k_dhat_staged<S, 1, true>), grid, blk, lds, st, g, op.U, op.A, tmp, in, out, nrhs, c.xcd, sb);
+    else
+      hipLaunchKernelGGL((k_dhat_staged<S, 1, false>), grid, blk, lds, st, g, op.U, op.A, tmp, in, out, nrhs, c.xcd,
+                         sb);
+  }
+  return hipGetLastError();
+}
 
 template <class S, int NR>
 static hipError_t launch_dhat_nr(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> tmp, FieldV<S> out,
@@ -189,11 +375,21 @@ static hipError_t launch_dhat_nr(const Geo& g, const DevOp<S>& op, FieldV<S> in,
   int nrg = ceil_div(nrhs, NR * (c.block / sb));
   int tiles = ceil_div(g.Vh, sb);
   dim3 grid(tiles * nrg), blk(c.block);
-  if (pass & 1)
-    hipLaunchKernelGGL((k_dhat_a<S, NR>), grid, blk, 0, st, g, op.U, op.Ainv, in, tmp, nrhs, nrg, c.xcd, sb);
-  if (ev) hipEventRecord(ev, st);
-  if (pass & 2)
-    hipLaunchKernelGGL((k_dhat_b<S, NR>), grid, blk, 0, st, g, op.U, op.A, in, tmp, out, nrhs, nrg, c.xcd, sb);
+  const bool o32 = fits32(in, nrhs) && fits32(tmp, nrhs) && fits32(out, nrhs);
+  if (pass & 1) {
+    if (o32)
+      hipLaunchKernelGGL((k_dhat_a<S, NR, true>), grid, blk, 0, st, g, op.U, op.Ainv, in, tmp, nrhs, nrg, c.xcd, sb);
+    else
+      hipLaunchKernelGGL((k_dhat_a<S, NR, false>), grid, blk, 0, st, g, op.U, op.Ainv, in, tmp, nrhs, nrg, c.xcd, sb);
+  }
+  if (ev) (void)hipEventRecord(ev, st);
+  if (pass & 2) {
+    if (o32)
+      hipLaunchKernelGGL((k_dhat_b<S, NR, true>), grid, blk, 0, st, g, op.U, op.A, in, tmp, out, nrhs, nrg, c.xcd, sb);
+    else
+      hipLaunchKernelGGL((k_dhat_b<S, NR, false>), grid, blk, 0, st, g, op.U, op.A, in, tmp, out, nrhs, nrg, c.xcd,
+                         sb);
+  }
   return hipGetLastError();
 }
 
@@ -201,6 +397,7 @@ template <class S>
 hipError_t launch_dhat(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> tmp, FieldV<S> out, int nrhs,
                        const LaunchCfg& c, hipStream_t st, int pass, hipEvent_t ev) {
   switch (c.nr) {
+    case 0: return launch_dhat_staged<S>(g, op, in, tmp, out, nrhs, c, st, pass, ev);
     case 1: return launch_dhat_nr<S, 1>(g, op, in, tmp, out, nrhs, c, st, pass, ev);
     case 2: return launch_dhat_nr<S, 2>(g, op, in, tmp, out, nrhs, c, st, pass, ev);
     case 4: return launch_dhat_nr<S, 4>(g, op, in, tmp, out, nrhs, c, st, pass, ev);
@@ -214,8 +411,12 @@ static hipError_t launch_dw_nr(const Geo& g, const DevOp<S>& op, FieldV<S> in, F
   int sb = c.sb > 0 ? c.sb : c.block;
   int nrg = ceil_div(nrhs, NR * (c.block / sb));
   int tiles = 2 * ceil_div(g.Vh, sb);
-  hipLaunchKernelGGL((k_dw<S, NR>), dim3(tiles * nrg), dim3(c.block), 0, st, g, op.U, op.A, in, out, poff, spoff,
-                     nrhs, nrg, c.xcd, sb);
+  if (fits32(in, nrhs, poff, spoff) && fits32(out, nrhs, poff, spoff))
+    hipLaunchKernelGGL((k_dw<S, NR, true>), dim3(tiles * nrg), dim3(c.block), 0, st, g, op.U, op.A, in, out, poff,
+                       spoff, nrhs, nrg, c.xcd, sb);
+  else
+    hipLaunchKernelGGL((k_dw<S, NR, false>), dim3(tiles * nrg), dim3(c.block), 0, st, g, op.U, op.A, in, out, poff,
+                       spoff, nrhs, nrg, c.xcd, sb);
   return hipGetLastError();
 }
 

@@ -49,13 +49,17 @@ template <class T>
 __device__ __host__ inline cx<T> ti(cx<T> a) { return {-a.im, a.re}; }
 template <class T>
 __device__ __host__ inline cx<T> tmi(cx<T> a) { return {a.im, -a.re}; }
+// real fused multiply-add (one rounding); written out so that a complex
+// multiply-accumulate is exactly two fused operations per real component
+__device__ __host__ inline float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __host__ inline double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
 template <class T>
 __device__ __host__ inline cx<T> fma_c(cx<T> a, cx<T> b, cx<T> c) {  // a*b + c
-  return {a.re * b.re - a.im * b.im + c.re, a.re * b.im + a.im * b.re + c.im};
+  return {fmar(a.re, b.re, fmar(-a.im, b.im, c.re)), fmar(a.re, b.im, fmar(a.im, b.re, c.im))};
 }
 template <class T>
 __device__ __host__ inline cx<T> fmac_c(cx<T> a, cx<T> b, cx<T> c) {  // conj(a)*b + c
-  return {a.re * b.re + a.im * b.im + c.re, a.re * b.im - a.im * b.re + c.im};
+  return {fmar(a.re, b.re, fmar(a.im, b.im, c.re)), fmar(a.re, b.im, fmar(-a.im, b.re, c.im))};
 }
 
 // --------------------------------------------------------------- storage
@@ -71,6 +75,9 @@ struct St<double> {
     return {v.x, v.y};
   }
   static __device__ inline void st(E* p, cx<double> v) { *p = make_double2(v.re, v.im); }
+  static __device__ inline cx<double> from(E v) { return {v.x, v.y}; }
+  static __device__ inline cx<double> from_reg(E v) { return {v.x, v.y}; }
+  static __device__ inline E to(cx<double> v) { return make_double2(v.re, v.im); }
 };
 template <>
 struct St<float> {
@@ -81,6 +88,9 @@ struct St<float> {
     return {v.x, v.y};
   }
   static __device__ inline void st(E* p, cx<float> v) { *p = make_float2(v.re, v.im); }
+  static __device__ inline cx<float> from(E v) { return {v.x, v.y}; }
+  static __device__ inline cx<float> from_reg(E v) { return {v.x, v.y}; }
+  static __device__ inline E to(cx<float> v) { return make_float2(v.re, v.im); }
 };
 template <>
 struct St<__half> {
@@ -92,6 +102,19 @@ struct St<__half> {
     return {f.x, f.y};
   }
   static __device__ inline void st(E* p, cx<float> v) { *p = __floats2half2_rn(v.re, v.im); }
+  static __device__ inline cx<float> from(E v) {
+    float2 f = __half22float2(v);
+    return {f.x, f.y};
+  }
+  // converted once into registers (spinor components feed additions, where a
+  // mixed-precision fused operation cannot absorb the conversion; leaving the
+  // choice to the compiler costs far more registers)
+  static __device__ inline cx<float> from_reg(E v) {
+    float2 f = __half22float2(v);
+    asm("" : "+v"(f.x), "+v"(f.y));
+    return {f.x, f.y};
+  }
+  static __device__ inline E to(cx<float> v) { return __floats2half2_rn(v.re, v.im); }
 };
 
 // --------------------------------------------------------------- geometry
@@ -138,12 +161,63 @@ struct FieldV {
   int n;         // sites (component stride)
 };
 
-// load / store of a 12-component spinor of site i, rhs r
-template <class S>
+// element at a 32-bit byte offset from a base pointer.  With a base that is the
+// same for the whole wavefront (a field pointer plus a component offset) the
+// load or store takes the scalar-base + 32-bit vector-offset form: one offset
+// register serves all components and no 64-bit address arithmetic is needed.
+// The base MUST be the same for every lane of the wavefront: it goes through
+// readfirstlane, which keeps the compiler from folding the per-component
+// offsets into 64-bit per-lane addresses.
+__device__ inline uintptr_t uniform_addr(const void* a) {
+  uintptr_t v = reinterpret_cast<uintptr_t>(a);
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uintptr_t)hi << 32) | lo;
+}
+// raw 4/8/16-byte words moved through global-address-space pointers
+template <int B>
+struct RawW;
+template <>
+struct RawW<4> { typedef unsigned int T; };
+template <>
+struct RawW<8> { typedef unsigned int T __attribute__((ext_vector_type(2))); };
+template <>
+struct RawW<16> { typedef unsigned int T __attribute__((ext_vector_type(4))); };
+
+template <class E>
+__device__ inline E ld_off(const E* base, uint32_t byte_off) {
+  typedef typename RawW<sizeof(E)>::T R;
+  typedef const __attribute__((address_space(1))) R* GP;
+  R raw = *reinterpret_cast<GP>(uniform_addr(base) + byte_off);
+  E v;
+  __builtin_memcpy(&v, &raw, sizeof(E));
+  return v;
+}
+template <class E>
+__device__ inline void st_off(E* base, uint32_t byte_off, E v) {
+  typedef typename RawW<sizeof(E)>::T R;
+  typedef __attribute__((address_space(1))) R* GP;
+  R raw;
+  __builtin_memcpy(&raw, &v, sizeof(E));
+  *reinterpret_cast<GP>(uniform_addr(base) + byte_off) = raw;
+}
+
+// load / store of a 12-component spinor of site i, rhs r.  O32: the caller
+// guarantees that the field view is the same for the whole wavefront and that
+// every element offset of the field, (r * rs + i) elements, is below 2^32
+// bytes, so the offsets are formed in 32 bits from scalar component bases.
+template <class S, bool O32 = false>
 __device__ inline void ld_spinor(const FieldV<S>& f, int r, int i, cx<typename St<S>::T> s[12]) {
-  const typename St<S>::E* b = f.p + r * f.rs + i;
+  typedef typename St<S>::E E;
+  if constexpr (O32) {
+    const uint32_t vo = (uint32_t)(r * f.rs + i) * (uint32_t)sizeof(E);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) s[k] = St<S>::ldc(b + (int64_t)k * f.n);
+    for (int k = 0; k < 12; ++k) s[k] = St<S>::from_reg(ld_off(f.p + (int64_t)k * f.n, vo));
+  } else {
+    const E* b = f.p + r * f.rs + i;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) s[k] = St<S>::from_reg(b[(int64_t)k * f.n]);
+  }
   if constexpr (sizeof(S) == 2) {
     float sc = f.scale[r * f.srs + i];
 #pragma unroll
@@ -151,21 +225,45 @@ __device__ inline void ld_spinor(const FieldV<S>& f, int r, int i, cx<typename S
   }
 }
 
-template <class S>
+// the stored components without the FP16 scale, and the scale (1 for FP32/FP64)
+template <class S, bool O32 = false>
+__device__ inline typename St<S>::T ld_spinor_raw(const FieldV<S>& f, int r, int i, cx<typename St<S>::T> s[12]) {
+  typedef typename St<S>::E E;
+  if constexpr (O32) {
+    const uint32_t vo = (uint32_t)(r * f.rs + i) * (uint32_t)sizeof(E);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) s[k] = St<S>::from_reg(ld_off(f.p + (int64_t)k * f.n, vo));
+    if constexpr (sizeof(S) == 2) return ld_off(f.scale, (uint32_t)(r * f.srs + i) * 4u);
+    else return typename St<S>::T(1);
+  } else {
+    const E* b = f.p + r * f.rs + i;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) s[k] = St<S>::from_reg(b[(int64_t)k * f.n]);
+    if constexpr (sizeof(S) == 2) return f.scale[r * f.srs + i];
+    else return typename St<S>::T(1);
+  }
+}
+
+template <class S, bool O32 = false>
 __device__ inline void st_spinor(const FieldV<S>& f, int r, int i, cx<typename St<S>::T> s[12]) {
-  typename St<S>::E* b = f.p + r * f.rs + i;
+  typedef typename St<S>::E E;
+  auto put = [&](int k, cx<typename St<S>::T> v) {
+    if constexpr (O32) st_off(f.p + (int64_t)k * f.n, (uint32_t)(r * f.rs + i) * (uint32_t)sizeof(E), St<S>::to(v));
+    else St<S>::st(f.p + r * f.rs + i + (int64_t)k * f.n, v);
+  };
   if constexpr (sizeof(S) == 2) {
     float m = 0.f;
 #pragma unroll
     for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(s[k].re), fabsf(s[k].im)));
     float sc = m > 0.f ? m : 1.f;
     float inv = 1.f / sc;
-    f.scale[r * f.srs + i] = sc;
+    if constexpr (O32) st_off(f.scale, (uint32_t)(r * f.srs + i) * 4u, sc);
+    else f.scale[r * f.srs + i] = sc;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) St<S>::st(b + (int64_t)k * f.n, cx<float>{s[k].re * inv, s[k].im * inv});
+    for (int k = 0; k < 12; ++k) put(k, cx<float>{s[k].re * inv, s[k].im * inv});
   } else {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) St<S>::st(b + (int64_t)k * f.n, s[k]);
+    for (int k = 0; k < 12; ++k) put(k, s[k]);
   }
 }
 
@@ -180,6 +278,16 @@ __device__ inline void ld_link(const LinkV<S>& u, int par, int mu, int i, cx<typ
   const typename St<S>::E* b = u.p + ((int64_t)(par * 4 + mu) * 9) * u.n + i;
 #pragma unroll
   for (int k = 0; k < 9; ++k) m[k] = St<S>::ldc(b + (int64_t)k * u.n);
+}
+// the same for a parity and direction that are uniform across the wavefront
+// (scalar component bases, one 32-bit offset)
+template <class S>
+__device__ inline void ld_link_u(const LinkV<S>& u, int par, int mu, int i, cx<typename St<S>::T> m[9]) {
+  typedef typename St<S>::E E;
+  const E* b = u.p + ((int64_t)(par * 4 + mu) * 9) * u.n;
+  const uint32_t vo = (uint32_t)i * (uint32_t)sizeof(E);  // i < n: always within 32 bits
+#pragma unroll
+  for (int k = 0; k < 9; ++k) m[k] = St<S>::from(ld_off(b + (int64_t)k * u.n, vo));
 }
 
 // clover: A[p][slot][i], 36 slots (2 blocks x 18)
@@ -220,6 +328,22 @@ __device__ inline void clover_apply(const CloverV<S>& A, int par, int i, const c
     herm6_mul<T>(a, in + 6 * blk, out + 6 * blk);
   }
 }
+// the same for a parity that is uniform across the wavefront
+template <class S>
+__device__ inline void clover_apply_u(const CloverV<S>& A, int par, int i, const cx<typename St<S>::T> in[12],
+                                      cx<typename St<S>::T> out[12]) {
+  typedef typename St<S>::T T;
+  typedef typename St<S>::E E;
+  const E* b = A.p + (int64_t)par * 36 * A.n;
+  const uint32_t vo = (uint32_t)i * (uint32_t)sizeof(E);
+#pragma unroll
+  for (int blk = 0; blk < 2; ++blk) {
+    cx<T> a[18];
+#pragma unroll
+    for (int k = 0; k < 18; ++k) a[k] = St<S>::from(ld_off(b + (int64_t)(blk * 18 + k) * A.n, vo));
+    herm6_mul<T>(a, in + 6 * blk, out + 6 * blk);
+  }
+}
 
 // --------------------------------------------------------------- spin projection
 // (1 - sg*gamma_mu) psi = [h ; M h] with h = psi_up + P psi_lo (2 spins x 3 colours);
@@ -250,30 +374,35 @@ __device__ inline void project(const cx<T> s[12], cx<T> h[6]) {
   }
 }
 
-// acc += [g ; M g]: M = +P for mu = 0 and M = -P for mu = 1,2,3
+// acc += c [g ; M g]: M = +P for mu = 0 and M = -P for mu = 1,2,3.  The factor c
+// (the -1/4 of Dhat, an FP16 scale) rides on the accumulating fused
+// multiply-adds; c = 1 gives plain additions.
+template <class T>
+__device__ inline cx<T> cacc(cx<T> a, T c, cx<T> b) { return {fmar(c, b.re, a.re), fmar(c, b.im, a.im)}; }
 template <class T, int MU, int SG>
-__device__ inline void reconstruct_add(const cx<T> g[6], cx<T> acc[12]) {
+__device__ inline void reconstruct_add(const cx<T> g[6], cx<T> acc[12], T c = T(1)) {
+  const T m = -c;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    cx<T> g0 = g[c], g1 = g[3 + c];
-    acc[c] = acc[c] + g0;
-    acc[3 + c] = acc[3 + c] + g1;
+  for (int k = 0; k < 3; ++k) {
+    cx<T> g0 = g[k], g1 = g[3 + k];
+    acc[k] = cacc(acc[k], c, g0);
+    acc[3 + k] = cacc(acc[3 + k], c, g1);
     if constexpr (MU == 0) {
       // M = +1 (fwd), -1 (bwd)
-      acc[6 + c] = SG > 0 ? acc[6 + c] + g0 : acc[6 + c] - g0;
-      acc[9 + c] = SG > 0 ? acc[9 + c] + g1 : acc[9 + c] - g1;
+      acc[6 + k] = cacc(acc[6 + k], SG > 0 ? c : m, g0);
+      acc[9 + k] = cacc(acc[9 + k], SG > 0 ? c : m, g1);
     } else if constexpr (MU == 1) {
       // M = -i s1 (fwd): (-i g1, -i g0); +i s1 (bwd)
-      acc[6 + c] = SG > 0 ? acc[6 + c] - ti(g1) : acc[6 + c] + ti(g1);
-      acc[9 + c] = SG > 0 ? acc[9 + c] - ti(g0) : acc[9 + c] + ti(g0);
+      acc[6 + k] = cacc(acc[6 + k], SG > 0 ? m : c, ti(g1));
+      acc[9 + k] = cacc(acc[9 + k], SG > 0 ? m : c, ti(g0));
     } else if constexpr (MU == 2) {
       // M = -i s2 (fwd): -(g1, -g0) = (-g1, g0)
-      acc[6 + c] = SG > 0 ? acc[6 + c] - g1 : acc[6 + c] + g1;
-      acc[9 + c] = SG > 0 ? acc[9 + c] + g0 : acc[9 + c] - g0;
+      acc[6 + k] = cacc(acc[6 + k], SG > 0 ? m : c, g1);
+      acc[9 + k] = cacc(acc[9 + k], SG > 0 ? c : m, g0);
     } else {
       // M = -i s3 (fwd): (-i g0, +i g1)
-      acc[6 + c] = SG > 0 ? acc[6 + c] - ti(g0) : acc[6 + c] + ti(g0);
-      acc[9 + c] = SG > 0 ? acc[9 + c] + ti(g1) : acc[9 + c] - ti(g1);
+      acc[6 + k] = cacc(acc[6 + k], SG > 0 ? m : c, ti(g0));
+      acc[9 + k] = cacc(acc[9 + k], SG > 0 ? c : m, ti(g1));
     }
   }
 }

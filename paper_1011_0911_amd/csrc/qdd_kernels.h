@@ -16,10 +16,18 @@ struct DevOp {
 // launch shape (picked by the autotuner)
 struct LaunchCfg {
   int block = 256;  // threads per block
-  int nr = 1;       // right-hand sides per thread (register reuse of the links)
+  int nr = 1;       // right-hand sides per thread (register reuse of the links); 0 = staged
+                    // variant: the tile's links and clover in LDS, each lane loops over rhs
   int xcd = 2;      // block walk: 0 linear, 1 XCD slabs, 2 XCD slabs walked time-slice first
   int sb = 0;       // sites per block (0 = block); block/sb lane groups take further rhs
 };
+
+// LDS bytes of the staged Dhat variant for a tile of sb sites (108 complex slots
+// per site: 8 links and the clover), and the budget it must stay within
+inline size_t staged_lds_bytes(int prec, int sb) {
+  return (size_t)108 * sb * (prec == 0 ? 16 : prec == 1 ? 8 : 4);
+}
+constexpr size_t kStagedLdsMax = 64 * 1024;
 
 // pass: bit 0 = pass A, bit 1 = pass B; ev (optional) is recorded between them
 template <class S>

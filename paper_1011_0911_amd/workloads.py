@@ -96,6 +96,8 @@ def run_solve_workload(wid: int, plain_rhs: int = 1, log=print, U=None):
     log(f"[w{wid}] mixed: {out['mixed']}")
     del ctx
     torch.cuda.empty_cache()
+    if plain_rhs <= 0:
+        return out
     # plain FP64 reference solver on plain_rhs right-hand sides, one at a time
     pctx, _ = make_context(L, w["eps"], w["kappa"], w["csw"], 0, U=U, **solver_config(w, 1, plain=True))
     if w.get("dfl_Ns"):
@@ -264,7 +266,8 @@ def main(argv=None):
     ap.add_argument("--pairs", type=int, default=None, help="training pairs (workload 5)")
     ap.add_argument("--chunk", type=int, default=64, help="pairs per streamed training chunk (workload 5)")
     ap.add_argument("--epochs", type=int, default=1)
-    ap.add_argument("--plain-rhs", type=int, default=1, help="right-hand sides timed with the plain solver")
+    ap.add_argument("--plain-rhs", type=int, default=1,
+                    help="right-hand sides timed with the plain solver (0: mixed solver only)")
     a = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)  # noqa: E731
     if a.wid == 5:

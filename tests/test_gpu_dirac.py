@@ -70,6 +70,9 @@ def test_config1_field_dhat_and_csw0(Q, orc):
 
 @pytest.mark.parametrize("kernel", [0, 1])
 def test_batched_equals_single_rhs(Q, kernel):
+    # for every launch shape, the batched apply equals single-rhs applies with the
+    # same shape bit for bit; shapes of different kernel variants agree to the
+    # last rounding (the staged variant orders its operations differently)
     L = (8, 6, 4, 4)
     V = int(np.prod(L))
     ctx, U = make_ctx(Q, L, 0.5, 0.1355, 1.9, 301, max_nrhs=5)
@@ -77,13 +80,42 @@ def test_batched_equals_single_rhs(Q, kernel):
     psi = S.gaussian_field(n, 9, nrhs=5)
     app = ctx.apply_dhat if kernel == 0 else ctx.apply_dw
     for prec in (0, 1):
-        ref = np.stack([to_np(app(psi[r:r + 1], prec))[0] for r in range(5)])
-        for block, nr, xcd, sb in [(64, 1, 0, 0), (128, 2, 1, 0), (256, 4, 1, 0), (192, 4, 0, 0), (128, 1, 1, 16),
-                                   (256, 2, 2, 32), (64, 1, 2, 16), (192, 1, 1, 64), (128, 1, 2, 0), (256, 4, 2, 0)]:
+        base = None
+        shapes = [(64, 1, 0, 0), (128, 2, 1, 0), (256, 4, 1, 0), (192, 4, 0, 0), (128, 1, 1, 16),
+                  (256, 2, 2, 32), (64, 1, 2, 16), (192, 1, 1, 64), (128, 1, 2, 0), (256, 4, 2, 0)]
+        if kernel == 0:  # the LDS-staged variant (nr = 0): tiles of sb sites, block/sb lanes per site
+            shapes += [(64, 0, 0, 0), (128, 0, 1, 32), (256, 0, 2, 64), (256, 0, 1, 16), (192, 0, 0, 32)]
+        for block, nr, xcd, sb in shapes:
+            if nr == 0 and 108 * (sb or block) * (16 if prec == 0 else 8) > 65536:
+                continue  # staged tile does not fit the LDS budget in this precision
             ctx.set_launch(kernel, prec, block, nr, xcd, sb)
+            ref = np.stack([to_np(app(psi[r:r + 1], prec))[0] for r in range(5)])
             out = to_np(app(psi, prec))
             assert np.array_equal(out, ref), (prec, block, nr, xcd, sb)
+            if base is None:
+                base = out
+            assert relerr(out, base) <= (1e-15 if prec == 0 else 1e-6), (prec, block, nr, xcd, sb)
         ctx.set_launch(kernel, prec, 256, 1, 1, 0)
+
+
+def test_staged_variant_parity_and_limits(Q, orc):
+    # the staged Dhat against the oracle in every precision on a ragged lattice
+    # (192 even sites: not a multiple of the 64- or 128-site tiles)
+    L = (6, 4, 4, 4)
+    V = int(np.prod(L))
+    ctx, U = make_ctx(Q, L, 0.6, 0.1357, 1.9, 304, max_nrhs=3)
+    A, Ai = orc.clover(L, U, 0.1357, 1.9)
+    pe = S.gaussian_field(V // 2, 12, nrhs=3)
+    ref = np.stack([orc.apply_Dhat(L, U, A, Ai, pe[r]) for r in range(3)])
+    for prec, sb in ((0, 32), (1, 64), (2, 128)):
+        ctx.set_launch(0, prec, 256 if sb < 128 else 128, 0, 1, sb)
+        e = relerr(to_np(ctx.apply_dhat(pe, prec)), ref)
+        assert e < TOL[prec], (prec, e)
+    # tiles whose links + clover exceed 64 KiB of LDS, and the full D, are rejected
+    for kernel, prec, block, sb in ((0, 0, 64, 64), (0, 1, 128, 128), (1, 1, 64, 0)):
+        with pytest.raises(Q.QddError) as e:
+            ctx.set_launch(kernel, prec, block, 0, 1, sb)
+        assert e.value.status == Q.QDD_EINVAL
 
 
 def test_pack_unpack_roundtrip(Q):
