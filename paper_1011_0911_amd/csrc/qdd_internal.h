@@ -245,7 +245,7 @@ __device__ inline typename St<S>::T ld_spinor_raw(const FieldV<S>& f, int r, int
 }
 
 template <class S, bool O32 = false>
-__device__ inline void st_spinor(const FieldV<S>& f, int r, int i, cx<typename St<S>::T> s[12]) {
+__device__ inline void st_spinor(const FieldV<S>& f, int r, int i, const cx<typename St<S>::T> s[12]) {
   typedef typename St<S>::E E;
   auto put = [&](int k, cx<typename St<S>::T> v) {
     if constexpr (O32) st_off(f.p + (int64_t)k * f.n, (uint32_t)(r * f.rs + i) * (uint32_t)sizeof(E), St<S>::to(v));

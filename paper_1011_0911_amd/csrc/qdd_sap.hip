@@ -2,8 +2,7 @@
 // paper's solver, Sect. 3): multiplicative two-colour SAP with minimal-residual
 // block solves on the even-odd block operator.
 //
-// One workgroup per block, one lane per site (even sites in the low lanes, odd
-// sites in the high lanes).  A half-sweep over the blocks of one colour does,
+// One workgroup per block.  A half-sweep over the blocks of one colour does,
 // for every block Lambda and every right-hand side:
 //   rho_L += 1/2 H_face V        (corrections V of the neighbouring blocks of the
 //                                 other colour, made in the previous half-sweep)
@@ -18,9 +17,12 @@
 // Within a block the hopping terms are exchanged as projected half-spinors in
 // LDS: every source site writes, per direction, the projection needed by its
 // forward neighbour and the U^dag-transported projection needed by its backward
-// neighbour, so each lane only ever multiplies with its own forward links.  For
-// FP32 and FP16 storage the own links and the clover block stay in registers for
-// the whole half-sweep and are reused across all MR steps and right-hand sides.
+// neighbour, so each lane only ever multiplies with its own forward links.
+// Two kernels: for FP32 and FP16 storage one lane per site (even sites in the
+// low lanes, odd sites in the high lanes) with the site's own links and clover
+// block held in registers for the whole half-sweep, reused across all MR steps
+// and right-hand sides; for FP64, where those would not fit, one lane per
+// even/odd site pair with links and clover read where they are used.
 #include "qdd_kernels.h"
 #include "qdd_sap.h"
 
@@ -341,14 +343,309 @@ __global__ void __launch_bounds__(256) k_sap_half(SapArgs<S, P> a) {
   }
 }
 
+// One lane per even/odd site pair of the block: lane j owns the j-th even and
+// the j-th odd site (block-local order), so every lane is busy in both halves
+// of a hop (source side: projections into LDS; target side: transport and
+// accumulation) and in both clover applications.  Links and clover are read
+// from memory (L2) where they are used, which keeps the registers for the
+// block-solve vectors.
+template <class S, class P, int DR, bool O32>
+__global__ void __launch_bounds__(kSapMaxHalf, sizeof(S) == 8 ? 1 : 2) k_sap_pair(SapArgs<S, P> a) {
+  typedef typename St<S>::T T;
+  __shared__ Exch<T, 2 * DR> ex;
+  __shared__ T red[2][4];
+  // per-lane vectors parked in LDS (each lane touches only its own column):
+  // the odd-site source rho_o (needed again for the reconstruction) and the
+  // even-site MR solution x
+  __shared__ cx<T> ro_l[12][kSapMaxHalf], xs_l[12][kSapMaxHalf];
+  const Geo& g = a.g;
+  const int j = threadIdx.x;
+  // this block: the blockIdx.x-th block of colour a.col
+  int bc[4];
+  {
+    int bl = 2 * blockIdx.x;
+    bc[3] = bl % a.nb[3];
+    int rr = bl / a.nb[3];
+    bc[2] = rr % a.nb[2];
+    rr /= a.nb[2];
+    bc[1] = rr % a.nb[1];
+    bc[0] = rr / a.nb[1];
+    bc[3] += (a.col + bc[0] + bc[1] + bc[2] + bc[3]) & 1;
+  }
+  // the lane's two sites (q = 0 even, 1 odd): global coordinates, index within
+  // the parity, and neighbour slots inside the block (-1: the hop crosses a face)
+  int x[2][4], ig[2], nin[2][4][2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    int y[4];
+    int l = 2 * j;
+    y[3] = l % a.bs[3];
+    int rr = l / a.bs[3];
+    y[2] = rr % a.bs[2];
+    rr /= a.bs[2];
+    y[1] = rr % a.bs[1];
+    y[0] = rr / a.bs[1];
+    y[3] += (q + y[0] + y[1] + y[2] + y[3]) & 1;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) x[q][m] = bc[m] * a.bs[m] + y[m];
+    ig[q] = lex_of(g, x[q]) >> 1;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        int z[4] = {y[0], y[1], y[2], y[3]};
+        z[m] += d == 0 ? 1 : -1;
+        bool in = z[m] >= 0 && z[m] < a.bs[m];
+        nin[q][m][d] = in ? ((((z[0] * a.bs[1] + z[1]) * a.bs[2] + z[2]) * a.bs[3] + z[3]) >> 1) : -1;
+      }
+    }
+  }
+  // clover: A on even sites, A^{-1} on odd sites
+  // Link and clover addresses are formed from the site index plus an opaque zero
+  // at every use: otherwise the compiler hoists all of them (two sites x 72
+  // components) out of the loops and runs out of registers.
+  auto vsalt = []() {
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    return z;
+  };
+  auto clover = [&](int q, const cx<T> in[12], cx<T> out[12]) {
+    const CloverV<S>& c = q == 0 ? a.A : a.Ai;
+    clover_apply<S>(c, q, ig[q] + vsalt(), in, out);
+  };
+  // acc (at the lane's site of parity 1-sp) = H_L src (src: the lane's site of parity sp)
+  auto hop_block = [&](const int sp, const cx<T> src[12], cx<T> acc[12]) {
+    const int tp = 1 - sp;
+    const LinkV<S>& U = a.U;
+    const int zv = vsalt();
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+#pragma unroll
+    for (int r0 = 0; r0 < 4; r0 += DR) {
+#pragma unroll
+      for (int m = r0; m < r0 + DR; ++m) {
+        cx<T> h[6], gg[6], u[9];
+        // for the backward neighbour's forward hop: (1 - g_m) projection
+        if (m == 0) project<T, 0, +1>(src, h);
+        else if (m == 1) project<T, 1, +1>(src, h);
+        else if (m == 2) project<T, 2, +1>(src, h);
+        else project<T, 3, +1>(src, h);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ex.v[2 * (m - r0)][k][j] = h[k];
+        // for the forward neighbour's backward hop: U^dag (1 + g_m) projection
+        if (m == 0) project<T, 0, -1>(src, h);
+        else if (m == 1) project<T, 1, -1>(src, h);
+        else if (m == 2) project<T, 2, -1>(src, h);
+        else project<T, 3, -1>(src, h);
+        ld_link(U, sp, m, ig[sp] + zv, u);
+        su3_mul_half<T, true>(u, h, gg);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ex.v[2 * (m - r0) + 1][k][j] = gg[k];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = r0; m < r0 + DR; ++m) {
+        const int jf = nin[tp][m][0], jb = nin[tp][m][1];
+        cx<T> h[6], gg[6], u[9];
+        if (jf >= 0) {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) h[k] = ex.v[2 * (m - r0)][k][jf];
+          ld_link(U, tp, m, ig[tp] + zv, u);
+          su3_mul_half<T, false>(u, h, gg);
+          if (m == 0) reconstruct_add<T, 0, +1>(gg, acc);
+          else if (m == 1) reconstruct_add<T, 1, +1>(gg, acc);
+          else if (m == 2) reconstruct_add<T, 2, +1>(gg, acc);
+          else reconstruct_add<T, 3, +1>(gg, acc);
+        }
+        if (jb >= 0) {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) gg[k] = ex.v[2 * (m - r0) + 1][k][jb];
+          if (m == 0) reconstruct_add<T, 0, -1>(gg, acc);
+          else if (m == 1) reconstruct_add<T, 1, -1>(gg, acc);
+          else if (m == 2) reconstruct_add<T, 2, -1>(gg, acc);
+          else reconstruct_add<T, 3, -1>(gg, acc);
+        }
+      }
+      __syncthreads();
+    }
+  };
+  auto block_sum3 = [&](T v0, T v1, T v2, T& s0, T& s1, T& s2) {
+    v0 = wsum(v0);
+    v1 = wsum(v1);
+    v2 = wsum(v2);
+    const int w = j >> 6, nw = (blockDim.x + 63) >> 6;
+    if ((j & 63) == 0) {
+      red[w][0] = v0;
+      red[w][1] = v1;
+      red[w][2] = v2;
+    }
+    __syncthreads();
+    s0 = s1 = s2 = T(0);
+    for (int k = 0; k < nw; ++k) {
+      s0 += red[k][0];
+      s1 += red[k][1];
+      s2 += red[k][2];
+    }
+    __syncthreads();
+  };
+  // parity views of the fields
+  FieldV<S> rho[2] = {a.rho, a.rho}, vf[2] = {a.V, a.V};
+  FieldV<P> psi[2] = {a.psi, a.psi};
+  rho[1].p += a.poff;
+  vf[1].p += a.poff;
+  psi[1].p += a.poff;
+  if (a.rho.scale) {
+    rho[1].scale += a.spoff;
+    vf[1].scale += a.spoff;
+  }
+  if (a.psi.scale) psi[1].scale += a.spoff;
+
+  // rq += 1/2 H_face V at the lane's site of parity q (the sites across the faces
+  // belong to blocks of the other colour, whose corrections V the previous
+  // half-sweep stored)
+  auto bnd = [&](const int q, const int r, cx<T> (&rq)[12]) {
+    const LinkV<S>& U = a.U;
+    const int zv = vsalt();  // opaque per-lane zero: keeps the addresses inside the loop
+    cx<T> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+    const FieldV<S>& vn = vf[1 - q];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      cx<T> sv[12], h[6], gg[6], u[9];
+      if (nin[q][m][0] < 0) {
+        int jn = nbr_idx(g, x[q], m, +1) + zv;
+        ld_spinor<S, O32>(vn, r, jn, sv);
+        ld_link(U, q, m, ig[q] + zv, u);
+        if (m == 0) { project<T, 0, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 0, +1>(gg, acc); }
+        else if (m == 1) { project<T, 1, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 1, +1>(gg, acc); }
+        else if (m == 2) { project<T, 2, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 2, +1>(gg, acc); }
+        else { project<T, 3, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 3, +1>(gg, acc); }
+      }
+      if (nin[q][m][1] < 0) {
+        int jn = nbr_idx(g, x[q], m, -1) + zv;
+        ld_spinor<S, O32>(vn, r, jn, sv);
+        ld_link(a.U, 1 - q, m, jn, u);
+        if (m == 0) { project<T, 0, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 0, -1>(gg, acc); }
+        else if (m == 1) { project<T, 1, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 1, -1>(gg, acc); }
+        else if (m == 2) { project<T, 2, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 2, -1>(gg, acc); }
+        else { project<T, 3, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 3, -1>(gg, acc); }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) rq[k] = cacc(rq[k], T(0.5), acc[k]);
+  };
+  // psi += v, V = v at the lane's site of parity q
+  auto put = [&](const int q, const int r, const cx<T> (&v)[12]) {
+    typedef typename St<P>::T TP;
+    cx<TP> pv[12];
+    if (a.first) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) pv[k] = {(TP)v[k].re, (TP)v[k].im};
+    } else {
+      ld_spinor<P, O32>(psi[q], r, ig[q], pv);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) pv[k] = pv[k] + cx<TP>{(TP)v[k].re, (TP)v[k].im};
+    }
+    st_spinor<P, O32>(psi[q], r, ig[q], pv);
+    if (a.write_v) st_spinor<S, O32>(vf[q], r, ig[q], v);
+  };
+
+  for (int r = 0; r < a.nrhs; ++r) {
+    cx<T> re[12], ro[12];
+    ld_spinor<S, O32>(rho[0], r, ig[0], re);
+    ld_spinor<S, O32>(rho[1], r, ig[1], ro);
+    // boundary: rho += 1/2 H_face V (the sites across the faces belong to blocks
+    // of the other colour, whose corrections V the previous half-sweep stored)
+    if (a.do_bnd) {
+      bnd(0, r, re);
+      bnd(1, r, ro);
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      ro_l[k][j] = ro[k];
+      xs_l[k][j] = {T(0), T(0)};
+    }
+    // source reduction: w = A_o^{-1} rho_o; b = rho_e + 1/2 H_L w
+    cx<T> w[12], acc[12], rr[12], pe[12];
+    clover(1, ro, w);
+    hop_block(1, w, acc);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) rr[k] = cacc(re[k], T(0.5), acc[k]);
+    // minimal-residual steps on Dhat_L (even sites)
+    for (int it = 0; it < a.nmr; ++it) {
+      hop_block(0, rr, acc);  // odd sites: acc = H_L r
+      cx<T> hh[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) hh[k] = T(-0.5) * acc[k];
+      clover(1, hh, w);       // w = A_o^{-1} (-1/2 H r)
+      hop_block(1, w, acc);   // even sites: acc = H_L w
+      clover(0, rr, pe);
+      T pr_re = 0, pr_im = 0, pp = 0;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        pe[k] = cacc(pe[k], T(0.5), acc[k]);
+        pr_re = fmar(pe[k].re, rr[k].re, fmar(pe[k].im, rr[k].im, pr_re));
+        pr_im = fmar(pe[k].re, rr[k].im, fmar(-pe[k].im, rr[k].re, pr_im));
+        pp = fmar(pe[k].re, pe[k].re, fmar(pe[k].im, pe[k].im, pp));
+      }
+      T s0, s1, s2;
+      block_sum3(pr_re, pr_im, pp, s0, s1, s2);
+      cx<T> al = s2 > T(0) ? cx<T>{s0 / s2, s1 / s2} : cx<T>{T(0), T(0)};
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        xs_l[k][j] = fma_c(al, rr[k], xs_l[k][j]);
+        rr[k] = fma_c(cx<T>{-al.re, -al.im}, pe[k], rr[k]);
+      }
+    }
+    // odd reconstruction: v_o = A_o^{-1} (rho_o + 1/2 H_L v_e)
+    cx<T> xs[12], vo[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) xs[k] = xs_l[k][j];
+    hop_block(0, xs, acc);
+    {
+      cx<T> hh[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) hh[k] = cacc(ro_l[k][j], T(0.5), acc[k]);
+      clover(1, hh, vo);
+    }
+    // write back: psi += v, V = v, rho = new block residual (r even, 0 odd)
+    put(0, r, xs);
+    put(1, r, vo);
+    cx<T> zero[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) zero[k] = {T(0), T(0)};
+    st_spinor<S, O32>(rho[0], r, ig[0], rr);
+    st_spinor<S, O32>(rho[1], r, ig[1], zero);
+  }
+}
+
+// every element offset of a field of nrhs right-hand sides (both parities) below 2^32 bytes
+template <class S>
+static bool sap_fits32(const FieldV<S>& f, int nrhs, int64_t poff, int64_t spoff) {
+  const int64_t lim = (int64_t)1 << 32;
+  int64_t e = ((int64_t)(nrhs - 1) * f.rs + poff + f.n) * (int64_t)sizeof(typename St<S>::E);
+  int64_t sc = f.scale ? ((int64_t)(nrhs - 1) * f.srs + spoff + f.n) * 4 : 0;
+  return e < lim && sc < lim;
+}
+
 template <class S, class P>
 hipError_t launch_sap_half(const SapArgs<S, P>& a, int nblk_colour, hipStream_t st) {
   int nsb = a.bs[0] * a.bs[1] * a.bs[2] * a.bs[3];
   if (nsb > 2 * kSapMaxHalf || nblk_colour <= 0) return hipErrorInvalidValue;
-  if constexpr (sizeof(S) == 8)
-    hipLaunchKernelGGL((k_sap_half<S, P, 2>), dim3(nblk_colour), dim3(nsb), 0, st, a);
-  else
+  if constexpr (sizeof(S) == 8) {
+    // FP64: one lane per site pair (the per-site variant would hold links and
+    // clover in registers only for FP32/FP16 storage)
+    const bool o32 = sap_fits32(a.rho, a.nrhs, a.poff, a.spoff) && sap_fits32(a.V, a.nrhs, a.poff, a.spoff) &&
+                     sap_fits32(a.psi, a.nrhs, a.poff, a.spoff);
+    if (o32)
+      hipLaunchKernelGGL((k_sap_pair<S, P, 2, true>), dim3(nblk_colour), dim3(nsb / 2), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_sap_pair<S, P, 2, false>), dim3(nblk_colour), dim3(nsb / 2), 0, st, a);
+  } else {
+    // FP32 / FP16 storage: one lane per site, own links and clover in registers
     hipLaunchKernelGGL((k_sap_half<S, P, 4>), dim3(nblk_colour), dim3(nsb), 0, st, a);
+  }
   return hipGetLastError();
 }
 
