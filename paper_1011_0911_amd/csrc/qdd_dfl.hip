@@ -78,61 +78,54 @@ __device__ inline cx<double> group_sum(cx<double> v, double* sh) {
 
 // Orthonormalise, on every block, the block restrictions of the Ns fields:
 // for l ascending, two passes of w_l -= <w_k, w_l>_b w_k (k < l, sequentially),
-// then w_l /= |w_l|_b.  One workgroup per block, one lane per site (lanes loop
-// when the block has more sites than lanes).  W: FP64 full fields, field l at
-// W + l * vs.
-__global__ void __launch_bounds__(256) k_block_orth(Geo g, DflGeo d, double2* W, int64_t vs, int Ns) {
-  __shared__ double sh[16];
+// then w_l /= |w_l|_b.  One workgroup per block, one lane per site; the field
+// being orthonormalised stays in registers while the earlier ones stream
+// through, so every w_k is read once per pass and w_l written once.  W: FP64
+// full fields, field l at W + l * vs.
+__global__ void __launch_bounds__(1024) k_block_orth(Geo g, DflGeo d, double2* W, int64_t vs, int Ns) {
+  __shared__ double sh[32];
   const int nsb = d.bs[0] * d.bs[1] * d.bs[2] * d.bs[3];
-  const int per = (nsb + blockDim.x - 1) / blockDim.x;  // sites per lane (<= 4)
-  int64_t off[4];
-  int ns = 0;
-  for (int q = 0; q < per && q < 4; ++q) {
-    int s = threadIdx.x + q * blockDim.x;
-    if (s < nsb) {
-      int x[4], p, i;
-      block_site(g, d, blockIdx.x, s, x, p, i);
-      off[ns++] = (int64_t)p * 12 * g.Vh + i;
-    }
+  const int s = threadIdx.x;
+  const bool on = s < nsb;
+  int64_t off = 0;
+  if (on) {
+    int x[4], p, i;
+    block_site(g, d, blockIdx.x, s, x, p, i);
+    off = (int64_t)p * 12 * g.Vh + i;
   }
   for (int l = 0; l < Ns; ++l) {
-    double2* wl = W + l * vs;
+    double2* wl = W + l * vs + off;
+    cx<double> v[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      double2 b = on ? wl[(int64_t)c * g.Vh] : make_double2(0.0, 0.0);
+      v[c] = {b.x, b.y};
+    }
     for (int pass = 0; pass < 2; ++pass)
       for (int k = 0; k < l; ++k) {
-        const double2* wk = W + k * vs;
-        cx<double> acc{0.0, 0.0};
-        for (int q = 0; q < ns; ++q)
+        const double2* wk = W + k * vs + off;
+        cx<double> a[12], acc{0.0, 0.0};
 #pragma unroll
-          for (int c = 0; c < 12; ++c) {
-            double2 a = wk[off[q] + (int64_t)c * g.Vh], b = wl[off[q] + (int64_t)c * g.Vh];
-            acc = fmac_c(cx<double>{a.x, a.y}, cx<double>{b.x, b.y}, acc);
-          }
-        cx<double> pr = group_sum(acc, sh);
-        for (int q = 0; q < ns; ++q)
+        for (int c = 0; c < 12; ++c) {
+          double2 t = on ? wk[(int64_t)c * g.Vh] : make_double2(0.0, 0.0);
+          a[c] = {t.x, t.y};
+          acc = fmac_c(a[c], v[c], acc);
+        }
+        const cx<double> pr = group_sum(acc, sh);
+        const cx<double> mp{-pr.re, -pr.im};
 #pragma unroll
-          for (int c = 0; c < 12; ++c) {
-            double2 a = wk[off[q] + (int64_t)c * g.Vh];
-            double2& b = wl[off[q] + (int64_t)c * g.Vh];
-            cx<double> v = cx<double>{b.x, b.y} - pr * cx<double>{a.x, a.y};
-            b = make_double2(v.re, v.im);
-          }
+        for (int c = 0; c < 12; ++c) v[c] = fma_c(mp, a[c], v[c]);
       }
     cx<double> nn{0.0, 0.0};
-    for (int q = 0; q < ns; ++q)
 #pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        double2 b = wl[off[q] + (int64_t)c * g.Vh];
-        nn.re += b.x * b.x + b.y * b.y;
-      }
-    cx<double> tot = group_sum(nn, sh);
-    double sc = tot.re > 0 ? 1.0 / sqrt(tot.re) : 0.0;
-    for (int q = 0; q < ns; ++q)
+    for (int c = 0; c < 12; ++c) nn.re = fmar(v[c].re, v[c].re, fmar(v[c].im, v[c].im, nn.re));
+    const cx<double> tot = group_sum(nn, sh);
+    const double sc = tot.re > 0 ? 1.0 / sqrt(tot.re) : 0.0;
+    if (on) {
 #pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        double2& b = wl[off[q] + (int64_t)c * g.Vh];
-        b = make_double2(b.x * sc, b.y * sc);
-      }
-    __syncthreads();
+      for (int c = 0; c < 12; ++c) wl[(int64_t)c * g.Vh] = make_double2(v[c].re * sc, v[c].im * sc);
+    }
+    __syncthreads();  // w_l is read by every later l
   }
 }
 
@@ -323,8 +316,8 @@ __global__ void __launch_bounds__(256) k_coarse_apply(DflGeo d, const double2* A
 // ---------------------------------------------------------------- launchers
 hipError_t launch_block_orth(const Geo& g, const DflGeo& d, double2* W, int64_t vs, int Ns, hipStream_t st) {
   int nsb = d.bs[0] * d.bs[1] * d.bs[2] * d.bs[3];
-  int thr = nsb >= 256 ? 256 : ((nsb + 63) / 64) * 64;
   if (nsb > 1024) return hipErrorInvalidValue;
+  int thr = ((nsb + 63) / 64) * 64;  // one lane per site
   hipLaunchKernelGGL(k_block_orth, dim3(d.nblk), dim3(thr), 0, st, g, d, W, vs, Ns);
   return hipGetLastError();
 }
