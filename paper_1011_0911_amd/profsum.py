@@ -66,6 +66,13 @@ def _counter(d: str, counter: str):
     return res
 
 
+def kname_of(tab, prefix):
+    for k in tab:
+        if k[0].startswith(prefix):
+            return k[0]
+    return prefix
+
+
 def traffic(bench_json: str, fetch_dir: str, write_dir: str, out_path: str, cmd: str) -> dict:
     with open(bench_json) as f:
         b = json.loads([ln for ln in f if ln.startswith("{")][-1])
@@ -76,11 +83,13 @@ def traffic(bench_json: str, fetch_dir: str, write_dir: str, out_path: str, cmd:
     launch = [ln["block"], ln["nr"], ln["xcd"], ln["sb"]]
     copy_bytes = cfg["copy_bytes"]
     tname = {0: "double", 1: "float", 2: "__half"}[prec]
-    kb = f"qdd::k_dhat_b<{tname}, {ln['nr']}>"
+    # pass-B kernel of the launch shape (name prefix; the last template argument
+    # is the addressing mode)
+    kb = f"qdd::k_dhat_staged<{tname}, 1," if ln["nr"] == 0 else f"qdd::k_dhat_b<{tname}, {ln['nr']},"
     fetch, write = _counter(fetch_dir, "FETCH_SIZE"), _counter(write_dir, "WRITE_SIZE")
 
     def pick(tab, kname):
-        c = [(k, v) for k, v in tab.items() if k[0] == kname]
+        c = [(k, v) for k, v in tab.items() if k[0] == kname or k[0].startswith(kname)]
         if not c:
             raise KeyError(f"{kname} not in the counter output")
         k, v = max(c, key=lambda kv: len(kv[1]))  # the timed launches: most dispatches
@@ -92,7 +101,7 @@ def traffic(bench_json: str, fetch_dir: str, write_dir: str, out_path: str, cmd:
     w_scale = copy_bytes / (cw * 1024.0)
     fb, nf, grid = pick(fetch, kb)
     wb, nw, _ = pick(write, kb)
-    entry = {"kernel": kb, "grid": grid, "launch": launch, "kernel_hash": kernel_source_hash(),
+    entry = {"kernel": kname_of(fetch, kb), "grid": grid, "launch": launch, "kernel_hash": kernel_source_hash(),
              "fetch_kib_raw": fb, "write_kib_raw": wb, "dispatches": [nf, nw],
              "copy_calibration": {"bytes": copy_bytes, "fetch_kib_raw": cf, "write_kib_raw": cw,
                                   "fetch_scale": f_scale, "write_scale": w_scale},
