@@ -329,12 +329,152 @@ __global__ void k_net_adam(float2* w, const float2* g, float4* mv, int n, float 
   w[t] = v;
 }
 
+// ------------------------------------------ layer on the matrix cores (MFMA)
+// For every site x and colour a the layer is one matrix-vector product
+//   out[(c, sa)](x, a) = sum_{d, c', sb} W[d][c][c'][sa][sb] T_d[(c', sb)](x, a),
+// T_d the link-transported inputs, so a tile of sites is a GEMM with the site
+// and colour as the column index.  In real form (rows (c, sa, re/im), k index
+// (c', sb, re/im)): A = [[Wre, -Wim], [Wim, Wre]] per (c, sa | c', sb) block.
+// A workgroup of 2 wavefronts takes kNetTile sites (3 kNetTile columns = 6
+// column tiles of 16); for each direction d the transported inputs of the
+// tile are computed into LDS as T[k][n] and the waves run
+// v_mfma_f32_16x16x4f32 over them (FP32 operands: the BF16 weights convert
+// exactly, the activations stay FP32), each wave owning 3 column tiles and
+// all MT row tiles.  Operand layout of 16x16x4: lane l holds A[l%16][l/16],
+// B[l/16][l%16] and D rows 4(l/16)+r, column l%16.
+constexpr int kNetTile = 32;
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <int MT>
+__global__ void __launch_bounds__(128) k_net_layer_mx(Geo g, LinkV<float> U, const uint32_t* Wb, int cin, int cout,
+                                                      const float2* in, float2* out, int64_t cs) {
+  extern __shared__ float tl[];  // [8 cin][3 kNetTile]
+  constexpr int N = 3 * kNetTile;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int s0 = blockIdx.x * kNetTile;
+  const int K = 8 * cin;
+  f4v acc[MT][3];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) acc[mt][j] = f4v{0.f, 0.f, 0.f, 0.f};
+  for (int d = 0; d < 9; ++d) {
+    // transported inputs of the tile: one (site, input channel) pair per item
+    __syncthreads();
+    for (int e = threadIdx.x; e < kNetTile * cin; e += blockDim.x) {
+      const int sl = e % kNetTile, cp = e / kNetTile;
+      const int s = s0 + sl;
+      cx<float> tr[12];
+      if (s < g.V) {
+        const int p = s >= g.Vh, i = s - p * g.Vh;
+        const float2* f = in + cp * cs;
+        if (d == 0) {
+#pragma unroll
+          for (int k = 0; k < 12; ++k) {
+            float2 v = f[(int64_t)p * 12 * g.Vh + (int64_t)k * g.Vh + i];
+            tr[k] = {v.x, v.y};
+          }
+        } else {
+          const int mu = (d - 1) >> 1, dir = (d - 1) & 1;
+          int x[4];
+          site_coords(g, p, i, x);
+          const int j = nbr_idx(g, x, mu, dir == 0 ? 1 : -1);
+          cx<float> u[9], sp[12];
+          const float2* fb = f + (int64_t)(1 - p) * 12 * g.Vh + j;
+#pragma unroll
+          for (int k = 0; k < 12; ++k) {
+            float2 v = fb[(int64_t)k * g.Vh];
+            sp[k] = {v.x, v.y};
+          }
+          if (dir == 0) ld_link(U, p, mu, i, u);
+          else ld_link(U, 1 - p, mu, j, u);
+#pragma unroll
+          for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              cx<float> z{0.f, 0.f};
+#pragma unroll
+              for (int b = 0; b < 3; ++b)
+                z = dir == 0 ? fma_c(u[a * 3 + b], sp[sb * 3 + b], z) : fmac_c(u[b * 3 + a], sp[sb * 3 + b], z);
+              tr[sb * 3 + a] = z;
+            }
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) tr[k] = {0.f, 0.f};
+      }
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int n = sl * 3 + a, k0 = cp * 8 + sb * 2;
+          tl[k0 * N + n] = tr[sb * 3 + a].re;
+          tl[(k0 + 1) * N + n] = tr[sb * 3 + a].im;
+        }
+    }
+    __syncthreads();
+    // acc += A_d T_d over k in steps of 4
+    for (int kk = 0; kk < K; kk += 4) {
+      const int k = kk + (lane >> 4);
+      const int cp = k >> 3, sb = (k >> 1) & 3, ri_i = k & 1;
+      f4v bq[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) bq[j] = f4v{tl[k * N + (3 * wv + j) * 16 + (lane & 15)], 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int m = mt * 16 + (lane & 15);
+        const int c = m >> 3, sa = (m >> 1) & 3, ri_o = m & 1;
+        float av = 0.f;
+        if (c < cout) {
+          const uint32_t w = Wb[((int64_t)(d * cout + c) * cin + cp) * 16 + sa * 4 + sb];
+          const float wr = bf16_to_f((uint16_t)(w & 0xffffu)), wi = bf16_to_f((uint16_t)(w >> 16));
+          av = ri_o == ri_i ? wr : (ri_o == 0 ? -wi : wi);
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bq[j][0], acc[mt][j], 0, 0, 0);
+      }
+    }
+  }
+  // lane holds rows m = 16 mt + 4 (lane/16) + r: r = 0,1 are (re, im) of (c, sa),
+  // r = 2,3 those of (c, sa + 1); column n = 16 nt + lane%16 = (site, colour)
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int n = (3 * wv + j) * 16 + (lane & 15);
+    const int sl = n / 3, a = n - 3 * sl, s = s0 + sl;
+    if (s >= g.V) continue;
+    const int p = s >= g.Vh, i = s - p * g.Vh;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int m = mt * 16 + 4 * (lane >> 4) + 2 * h;
+        const int c = m >> 3, sa = (m >> 1) & 3;
+        if (c < cout)
+          out[c * cs + (int64_t)p * 12 * g.Vh + (int64_t)(sa * 3 + a) * g.Vh + i] =
+              make_float2(acc[mt][j][2 * h], acc[mt][j][2 * h + 1]);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 hipError_t launch_net_layer(const Geo& g, const LinkV<float>& U, const uint32_t* Wb, int cin, int cout,
                             const float2* in, float2* out, int64_t cs, hipStream_t st) {
-  constexpr int CG = 4;
-  dim3 grid((g.V + 127) / 128, (cout + CG - 1) / CG);
-  hipLaunchKernelGGL((k_net_layer<CG>), grid, dim3(128), 0, st, g, U, Wb, cin, cout, in, out, cs);
+  // matrix-core path (cout <= 16 -> at most 8 row tiles of 16)
+  const int mt = (8 * cout + 15) / 16;
+  const dim3 grid((g.V + kNetTile - 1) / kNetTile), blk(128);
+  const size_t lds = (size_t)8 * cin * 3 * kNetTile * sizeof(float);
+  switch (mt) {
+#define NET_MX(M) \
+  case M: hipLaunchKernelGGL((k_net_layer_mx<M>), grid, blk, lds, st, g, U, Wb, cin, cout, in, out, cs); break;
+    NET_MX(1) NET_MX(2) NET_MX(3) NET_MX(4) NET_MX(5) NET_MX(6) NET_MX(7) NET_MX(8)
+#undef NET_MX
+    default: {
+      constexpr int CG = 4;
+      dim3 grid2((g.V + 127) / 128, (cout + CG - 1) / CG);
+      hipLaunchKernelGGL((k_net_layer<CG>), grid2, dim3(128), 0, st, g, U, Wb, cin, cout, in, out, cs);
+    }
+  }
   return hipGetLastError();
 }
 
