@@ -230,7 +230,8 @@ qdd_status qdd_solve_harvest(qdd_ctx* ctx, const double* eta, double* psi, qdd_s
  * right-hand sides (tile LDS: 108 complex per site, at most 64 KiB); xcd: block
  * walk (0 linear; 1 every XCD takes a contiguous slab of the lattice; 2 slabs
  * whose tiles are walked time slice first, so time and x1 neighbours stay in
- * the XCD's L2); sb sites per block (0 = block): the block/sb lane groups of a
+ * the XCD's L2; 3 slabs cut into sub-slabs of 4 time slices walked one x1
+ * plane after the other); sb sites per block (0 = block): the block/sb lane groups of a
  * block take further right-hand sides of the same sites.  QDD_EINVAL for shapes
  * outside these ranges. */
 qdd_status qdd_set_launch(qdd_ctx* ctx, int kernel, qdd_prec prec, int block, int nr, int xcd, int sb);

@@ -73,11 +73,27 @@ __device__ inline void map_block(const Geo& g, int b, int nblk, int nrg, int sb,
   rg = b % nrg;
   tile = b / nrg;
   int row = g.L[2] * g.Lh3;  // sites of one (x0, x1) row of a parity
-  if (order == 2 && (g.L[0] & 7) == 0 && row % sb == 0 && (nblk / nrg) * sb == g.Vh) {
+  if (order >= 2 && (g.L[0] & 7) == 0 && row % sb == 0 && (nblk / nrg) * sb == g.Vh) {
     int S = g.L[0] >> 3, tpr = row / sb, per_xcd = S * g.L[1] * tpr;
     int k = tile / per_xcd, t = tile - k * per_xcd;
-    int s = t % S, rest = t / S;
-    int x1 = rest % g.L[1], qd = rest / g.L[1];
+    int s, x1, qd;
+    if (order == 2) {
+      s = t % S;
+      int rest = t / S;
+      x1 = rest % g.L[1];
+      qd = rest / g.L[1];
+    } else {
+      // order 3: sub-slabs of H time slices; inside one, x1 planes one after
+      // the other, each walked time slice by time slice, row by row: the
+      // spinors of three consecutive x1 planes of the sub-slab stay in the L2
+      const int H = (S % 4 == 0) ? 4 : S;
+      qd = t % tpr;
+      int rest = t / tpr;
+      const int si = rest % H;
+      rest /= H;
+      x1 = rest % g.L[1];
+      s = (rest / g.L[1]) * H + si;
+    }
     tile = ((k * S + s) * g.L[1] + x1) * tpr + qd;
   }
 }

@@ -23,11 +23,11 @@ extern "C" qdd_status qdd_autotune(qdd_ctx* x, int kernel, qdd_prec prec, int nr
       for (int nr : {1, 2, 4}) {
         if (lane_groups * nr > 2 * nrhs && !(lane_groups == 1 && nr == 1)) continue;  // mostly idle lanes
         if (nr > nrhs) continue;
-        for (int xcd : {0, 1, 2}) cand.push_back(LaunchCfg{block, nr, xcd, sb == block ? 0 : sb});
+        for (int xcd : {0, 1, 2, 3}) cand.push_back(LaunchCfg{block, nr, xcd, sb == block ? 0 : sb});
       }
       // staged variant (Dhat): R = block / sb lanes per site loop over the right-hand sides
       if (kernel == 0 && lane_groups <= nrhs && staged_lds_bytes(prec, sb) <= kStagedLdsMax)
-        for (int xcd : {0, 1, 2}) cand.push_back(LaunchCfg{block, 0, xcd, sb == block ? 0 : sb});
+        for (int xcd : {0, 1, 2, 3}) cand.push_back(LaunchCfg{block, 0, xcd, sb == block ? 0 : sb});
     }
   hipEvent_t e0, e1;
   HCK(x, hipEventCreate(&e0));

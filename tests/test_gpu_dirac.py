@@ -84,7 +84,8 @@ def test_batched_equals_single_rhs(Q, kernel):
         shapes = [(64, 1, 0, 0), (128, 2, 1, 0), (256, 4, 1, 0), (192, 4, 0, 0), (128, 1, 1, 16),
                   (256, 2, 2, 32), (64, 1, 2, 16), (192, 1, 1, 64), (128, 1, 2, 0), (256, 4, 2, 0)]
         if kernel == 0:  # the LDS-staged variant (nr = 0): tiles of sb sites, block/sb lanes per site
-            shapes += [(64, 0, 0, 0), (128, 0, 1, 32), (256, 0, 2, 64), (256, 0, 1, 16), (192, 0, 0, 32)]
+            shapes += [(64, 0, 0, 0), (128, 0, 1, 32), (256, 0, 2, 64), (256, 0, 1, 16), (192, 0, 0, 32), (128, 0, 3, 32)]
+        shapes += [(128, 1, 3, 0), (256, 1, 3, 32)]
         for block, nr, xcd, sb in shapes:
             if nr == 0 and 108 * (sb or block) * (16 if prec == 0 else 8) > 65536:
                 continue  # staged tile does not fit the LDS budget in this precision
