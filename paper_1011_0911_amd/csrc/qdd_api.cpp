@@ -454,9 +454,18 @@ PackedView qdd_ctx::packed(qdd_prec prec, int nrhs, int even_only, void* field) 
   v.poff = 12 * n;  // parity offset within one rhs (elements)
   v.spoff = n;      // parity offset of the scales
   char* b = (char*)field;
+  float* sc = (float*)(b + (size_t)rs * nrhs * 4);
+  if (even_only && nrhs > 1) {
+    // batches of even-site fields (the Dhat operands): interleaved layout
+    // [12][Vh][nrhs], scales [Vh][nrhs]
+    const int R = nrhs;
+    v.f64 = FieldV<double>{(double2*)b, nullptr, 1, 1, (int)(n * R), R, R};
+    v.f32 = FieldV<float>{(float2*)b, nullptr, 1, 1, (int)(n * R), R, R};
+    v.f16 = FieldV<__half>{(__half2*)b, sc, 1, 1, (int)(n * R), R, R};
+    return v;
+  }
   v.f64 = FieldV<double>{(double2*)b, nullptr, rs, sites, (int)n};
   v.f32 = FieldV<float>{(float2*)b, nullptr, rs, sites, (int)n};
-  float* sc = (float*)(b + (size_t)rs * nrhs * 4);
   v.f16 = FieldV<__half>{(__half2*)b, sc, rs, sites, (int)n};
   return v;
 }
@@ -465,17 +474,21 @@ hipError_t qdd_ctx::dhat(qdd_prec prec, int nrhs, void* in, void* out, hipEvent_
   PackedView a = packed(prec, nrhs, 1, in), b = packed(prec, nrhs, 1, out);
   int64_t n = G.Vh;
   const LaunchCfg& c = launch[0][prec];
+  // the odd-site intermediate in the layout of the operands
+  const bool il = nrhs > 1;
+  const int64_t trs = il ? 1 : 12 * n, tsrs = il ? 1 : n;
+  const int tn = il ? (int)(n * nrhs) : (int)n, tss = il ? nrhs : 1;
   switch (prec) {
     case QDD_F64: {
-      FieldV<double> t{ptr<double2>(lo.tmp_o), nullptr, 12 * n, n, (int)n};
+      FieldV<double> t{ptr<double2>(lo.tmp_o), nullptr, trs, tsrs, tn, tss, tss};
       return launch_dhat<double>(G, op<double>(), a.f64, t, b.f64, nrhs, c, st, 3, mid);
     }
     case QDD_F32: {
-      FieldV<float> t{ptr<float2>(lo.tmp_o), nullptr, 12 * n, n, (int)n};
+      FieldV<float> t{ptr<float2>(lo.tmp_o), nullptr, trs, tsrs, tn, tss, tss};
       return launch_dhat<float>(G, op<float>(), a.f32, t, b.f32, nrhs, c, st, 3, mid);
     }
     default: {
-      FieldV<__half> t{ptr<__half2>(lo.tmp_o), ptr<float>(lo.tmp_o_scale), 12 * n, n, (int)n};
+      FieldV<__half> t{ptr<__half2>(lo.tmp_o), ptr<float>(lo.tmp_o_scale), trs, tsrs, tn, tss, tss};
       return launch_dhat<__half>(G, op<__half>(), a.f16, t, b.f16, nrhs, c, st, 3, mid);
     }
   }

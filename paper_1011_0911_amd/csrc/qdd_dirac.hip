@@ -98,21 +98,25 @@ __device__ inline void map_block(const Geo& g, int b, int nblk, int nrg, int sb,
   }
 }
 
-// lane -> (site i, first rhs r0): sb sites x (blockDim / sb) rhs groups of NR
+// lane -> (site i, first rhs r0): sb sites x G = blockDim / sb rhs groups of NR;
+// site fastest for the blocked field layout, rhs group fastest (rf) for the
+// interleaved one, so that a wavefront reads contiguous memory in both
 template <int NR>
-__device__ inline bool lane_site(const Geo& g, int tile, int rg, int sb, int nrhs, int& i, int& r0) {
-  i = tile * sb + (int)(threadIdx.x % sb);
-  r0 = (rg * (int)(blockDim.x / sb) + (int)(threadIdx.x / sb)) * NR;
+__device__ inline bool lane_site(const Geo& g, int tile, int rg, int sb, int nrhs, int rf, int& i, int& r0) {
+  const int G = (int)(blockDim.x / sb), t = (int)threadIdx.x;
+  const int sl = rf ? t / G : t % sb, gl = rf ? t % G : t / sb;
+  i = tile * sb + sl;
+  r0 = (rg * G + gl) * NR;
   return i < g.Vh && r0 < nrhs;
 }
 
 template <class S, int NR, bool O32>
 __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k_dhat_a(Geo g, LinkV<S> U, CloverV<S> Ai, FieldV<S> in_e, FieldV<S> t_o,
-                                                int nrhs, int nrg, int order, int sb) {
+                                                int nrhs, int nrg, int order, int sb, int rf) {
   typedef typename St<S>::T T;
   int tile, rg, i, r0;
   map_block(g, blockIdx.x, gridDim.x, nrg, sb, order, tile, rg);
-  if (!lane_site<NR>(g, tile, rg, sb, nrhs, i, r0)) return;
+  if (!lane_site<NR>(g, tile, rg, sb, nrhs, rf, i, r0)) return;
   int nr = min(NR, nrhs - r0);
   int x[4];
   site_coords(g, 1, i, x);
@@ -134,11 +138,11 @@ __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k
 
 template <class S, int NR, bool O32>
 __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k_dhat_b(Geo g, LinkV<S> U, CloverV<S> A, FieldV<S> in_e, FieldV<S> t_o,
-                                                FieldV<S> out_e, int nrhs, int nrg, int order, int sb) {
+                                                FieldV<S> out_e, int nrhs, int nrg, int order, int sb, int rf) {
   typedef typename St<S>::T T;
   int tile, rg, i, r0;
   map_block(g, blockIdx.x, gridDim.x, nrg, sb, order, tile, rg);
-  if (!lane_site<NR>(g, tile, rg, sb, nrhs, i, r0)) return;
+  if (!lane_site<NR>(g, tile, rg, sb, nrhs, rf, i, r0)) return;
   int nr = min(NR, nrhs - r0);
   int x[4];
   site_coords(g, 0, i, x);
@@ -168,11 +172,12 @@ template <class S, int NR, bool O32>
 __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k_dw(Geo g, LinkV<S> U, CloverV<S> A, FieldV<S> in, FieldV<S> out,
                                             int64_t poff, int64_t spoff, int nrhs, int nrg, int order, int sb) {
   typedef typename St<S>::T T;
+  const int rf = 0;  // full fields are always in the blocked layout
   int nh = gridDim.x >> 1;
   int p = (int)blockIdx.x >= nh;
   int tile, rg, i, r0;
   map_block(g, blockIdx.x - p * nh, nh, nrg, sb, order, tile, rg);
-  if (!lane_site<NR>(g, tile, rg, sb, nrhs, i, r0)) return;
+  if (!lane_site<NR>(g, tile, rg, sb, nrhs, rf, i, r0)) return;
   int nr = min(NR, nrhs - r0);
   int x[4];
   site_coords(g, p, i, x);
@@ -289,7 +294,7 @@ __device__ inline void clover_lds(const typename St<S>::E* lds, int sb, int s, c
 // PASS 1 (pass B, even sites): out = A_e self - 1/4 H in (in: odd field t_o)
 template <class S, int PASS, bool O32>
 __global__ void __launch_bounds__(256, sizeof(S) == 8 ? 2 : 4) k_dhat_staged(Geo g, LinkV<S> U, CloverV<S> C, FieldV<S> in, FieldV<S> self,
-                                                     FieldV<S> out, int nrhs, int order, int sb) {
+                                                     FieldV<S> out, int nrhs, int order, int sb, int rf) {
   typedef typename St<S>::T T;
   typedef typename St<S>::E E;
   extern __shared__ unsigned char smem[];
@@ -297,7 +302,9 @@ __global__ void __launch_bounds__(256, sizeof(S) == 8 ? 2 : 4) k_dhat_staged(Geo
   const int p = PASS == 0 ? 1 : 0;
   int tile, rg;
   map_block(g, blockIdx.x, gridDim.x, 1, sb, order, tile, rg);
-  const int s = (int)threadIdx.x % sb, rl = (int)threadIdx.x / sb, R = (int)blockDim.x / sb;
+  const int R = (int)blockDim.x / sb;
+  const int s = rf ? (int)threadIdx.x / R : (int)threadIdx.x % sb;
+  const int rl = rf ? (int)threadIdx.x % R : (int)threadIdx.x / sb;
   const int i = tile * sb + s;
   const bool valid = i < g.Vh;
   int jf[4], jb[4];
@@ -351,10 +358,11 @@ static inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 // offset poff of a full field) of f, in bytes, and of its scale array, stays
 // below 2^32: the kernels may then form the offsets in 32 bits
 template <class S>
-static bool fits32(const FieldV<S>& f, int nrhs, int64_t poff = 0, int64_t spoff = 0) {
+static bool fits32(const Geo& g, const FieldV<S>& f, int nrhs, int64_t poff = 0, int64_t spoff = 0) {
   const int64_t lim = (int64_t)1 << 32;
-  int64_t e = ((int64_t)(nrhs - 1) * f.rs + f.n + poff) * (int64_t)sizeof(typename St<S>::E);
-  int64_t sc = f.scale ? ((int64_t)(nrhs - 1) * f.srs + f.n + spoff) * 4 : 0;
+  // largest per-lane offset (r * rs + i * ss; the component offset is scalar) plus the parity offset
+  int64_t e = ((int64_t)(nrhs - 1) * f.rs + (int64_t)(g.Vh - 1) * f.ss + poff + 1) * (int64_t)sizeof(typename St<S>::E);
+  int64_t sc = f.scale ? ((int64_t)(nrhs - 1) * f.srs + (int64_t)(g.Vh - 1) * f.sss + spoff + 1) * 4 : 0;
   return e < lim && sc < lim;
 }
 
@@ -364,22 +372,23 @@ static hipError_t launch_dhat_staged(const Geo& g, const DevOp<S>& op, FieldV<S>
   int sb = c.sb > 0 ? c.sb : c.block;
   dim3 grid(ceil_div(g.Vh, sb)), blk(c.block);
   size_t lds = (size_t)kStageSlots * sb * sizeof(typename St<S>::E);
-  const bool o32 = fits32(in, nrhs) && fits32(tmp, nrhs) && fits32(out, nrhs);
+  const bool o32 = fits32(g, in, nrhs) && fits32(g, tmp, nrhs) && fits32(g, out, nrhs);
+  const int rf = in.ss > 1;  // interleaved operands: rhs fastest across the lanes
   if (pass & 1) {
     if (o32)
       hipLaunchKernelGGL((k_dhat_staged<S, 0, true>), grid, blk, lds, st, g, op.U, op.Ainv, in, in, tmp, nrhs, c.xcd,
-                         sb);
+                         sb, rf);
     else
       hipLaunchKernelGGL((k_dhat_staged<S, 0, false>), grid, blk, lds, st, g, op.U, op.Ainv, in, in, tmp, nrhs, c.xcd,
-                         sb);
+                         sb, rf);
   }
   if (ev) (void)hipEventRecord(ev, st);
   if (pass & 2) {
     if (o32)
-      hipLaunchKernelGGL((k_dhat_staged<S, 1, true>), grid, blk, lds, st, g, op.U, op.A, tmp, in, out, nrhs, c.xcd, sb);
+      hipLaunchKernelGGL((k_dhat_staged<S, 1, true>), grid, blk, lds, st, g, op.U, op.A, tmp, in, out, nrhs, c.xcd, sb, rf);
     else
       hipLaunchKernelGGL((k_dhat_staged<S, 1, false>), grid, blk, lds, st, g, op.U, op.A, tmp, in, out, nrhs, c.xcd,
-                         sb);
+                         sb, rf);
   }
   return hipGetLastError();
 }
@@ -391,20 +400,21 @@ static hipError_t launch_dhat_nr(const Geo& g, const DevOp<S>& op, FieldV<S> in,
   int nrg = ceil_div(nrhs, NR * (c.block / sb));
   int tiles = ceil_div(g.Vh, sb);
   dim3 grid(tiles * nrg), blk(c.block);
-  const bool o32 = fits32(in, nrhs) && fits32(tmp, nrhs) && fits32(out, nrhs);
+  const bool o32 = fits32(g, in, nrhs) && fits32(g, tmp, nrhs) && fits32(g, out, nrhs);
+  const int rf = in.ss > 1;  // interleaved operands: rhs fastest across the lanes
   if (pass & 1) {
     if (o32)
-      hipLaunchKernelGGL((k_dhat_a<S, NR, true>), grid, blk, 0, st, g, op.U, op.Ainv, in, tmp, nrhs, nrg, c.xcd, sb);
+      hipLaunchKernelGGL((k_dhat_a<S, NR, true>), grid, blk, 0, st, g, op.U, op.Ainv, in, tmp, nrhs, nrg, c.xcd, sb, rf);
     else
-      hipLaunchKernelGGL((k_dhat_a<S, NR, false>), grid, blk, 0, st, g, op.U, op.Ainv, in, tmp, nrhs, nrg, c.xcd, sb);
+      hipLaunchKernelGGL((k_dhat_a<S, NR, false>), grid, blk, 0, st, g, op.U, op.Ainv, in, tmp, nrhs, nrg, c.xcd, sb, rf);
   }
   if (ev) (void)hipEventRecord(ev, st);
   if (pass & 2) {
     if (o32)
-      hipLaunchKernelGGL((k_dhat_b<S, NR, true>), grid, blk, 0, st, g, op.U, op.A, in, tmp, out, nrhs, nrg, c.xcd, sb);
+      hipLaunchKernelGGL((k_dhat_b<S, NR, true>), grid, blk, 0, st, g, op.U, op.A, in, tmp, out, nrhs, nrg, c.xcd, sb, rf);
     else
       hipLaunchKernelGGL((k_dhat_b<S, NR, false>), grid, blk, 0, st, g, op.U, op.A, in, tmp, out, nrhs, nrg, c.xcd,
-                         sb);
+                         sb, rf);
   }
   return hipGetLastError();
 }
@@ -427,7 +437,7 @@ static hipError_t launch_dw_nr(const Geo& g, const DevOp<S>& op, FieldV<S> in, F
   int sb = c.sb > 0 ? c.sb : c.block;
   int nrg = ceil_div(nrhs, NR * (c.block / sb));
   int tiles = 2 * ceil_div(g.Vh, sb);
-  if (fits32(in, nrhs, poff, spoff) && fits32(out, nrhs, poff, spoff))
+  if (fits32(g, in, nrhs, poff, spoff) && fits32(g, out, nrhs, poff, spoff))
     hipLaunchKernelGGL((k_dw<S, NR, true>), dim3(tiles * nrg), dim3(c.block), 0, st, g, op.U, op.A, in, out, poff,
                        spoff, nrhs, nrg, c.xcd, sb);
   else

@@ -150,15 +150,22 @@ __device__ __host__ inline int nbr_idx(const Geo& g, const int x[4], int mu, int
 }
 
 // --------------------------------------------------------------- field views
-// A parity-restricted field of `nc` complex components per site, `n` sites,
-// component stride n, right-hand-side stride rs (in elements).
+// A parity-restricted field of 12 complex components per site: element
+// (rhs r, component k, site i) at p[r * rs + k * n + i * ss].  Two layouts:
+//   blocked      [rhs][12][sites]   rs = 12 sites (or more), n = sites, ss = 1
+//   interleaved  [12][sites][rhs]   rs = 1, n = sites * nrhs, ss = nrhs
+// (the interleaved one puts the right-hand sides of a site next to each other,
+// so a wavefront of sites x rhs reads contiguous memory and a neighbour's
+// spinors of all right-hand sides share cache lines).
 template <class S>
 struct FieldV {
   typename St<S>::E* p;
-  float* scale;  // FP16 only: per-site scale, [rhs][i] with stride n (nullptr otherwise)
+  float* scale;  // FP16 only: per-site scale at scale[r * srs + i * sss] (nullptr otherwise)
   int64_t rs;    // element stride between right-hand sides
   int64_t srs;   // scale stride between right-hand sides
-  int n;         // sites (component stride)
+  int n;         // component stride (elements)
+  int ss = 1;    // site stride (elements)
+  int sss = 1;   // site stride of the scales
 };
 
 // element at a 32-bit byte offset from a base pointer.  With a base that is the
@@ -210,16 +217,16 @@ template <class S, bool O32 = false>
 __device__ inline void ld_spinor(const FieldV<S>& f, int r, int i, cx<typename St<S>::T> s[12]) {
   typedef typename St<S>::E E;
   if constexpr (O32) {
-    const uint32_t vo = (uint32_t)(r * f.rs + i) * (uint32_t)sizeof(E);
+    const uint32_t vo = (uint32_t)(r * f.rs + (int64_t)i * f.ss) * (uint32_t)sizeof(E);
 #pragma unroll
     for (int k = 0; k < 12; ++k) s[k] = St<S>::from_reg(ld_off(f.p + (int64_t)k * f.n, vo));
   } else {
-    const E* b = f.p + r * f.rs + i;
+    const E* b = f.p + r * f.rs + (int64_t)i * f.ss;
 #pragma unroll
     for (int k = 0; k < 12; ++k) s[k] = St<S>::from_reg(b[(int64_t)k * f.n]);
   }
   if constexpr (sizeof(S) == 2) {
-    float sc = f.scale[r * f.srs + i];
+    float sc = f.scale[r * f.srs + (int64_t)i * f.sss];
 #pragma unroll
     for (int k = 0; k < 12; ++k) { s[k].re *= sc; s[k].im *= sc; }
   }
@@ -230,16 +237,16 @@ template <class S, bool O32 = false>
 __device__ inline typename St<S>::T ld_spinor_raw(const FieldV<S>& f, int r, int i, cx<typename St<S>::T> s[12]) {
   typedef typename St<S>::E E;
   if constexpr (O32) {
-    const uint32_t vo = (uint32_t)(r * f.rs + i) * (uint32_t)sizeof(E);
+    const uint32_t vo = (uint32_t)(r * f.rs + (int64_t)i * f.ss) * (uint32_t)sizeof(E);
 #pragma unroll
     for (int k = 0; k < 12; ++k) s[k] = St<S>::from_reg(ld_off(f.p + (int64_t)k * f.n, vo));
-    if constexpr (sizeof(S) == 2) return ld_off(f.scale, (uint32_t)(r * f.srs + i) * 4u);
+    if constexpr (sizeof(S) == 2) return ld_off(f.scale, (uint32_t)(r * f.srs + (int64_t)i * f.sss) * 4u);
     else return typename St<S>::T(1);
   } else {
-    const E* b = f.p + r * f.rs + i;
+    const E* b = f.p + r * f.rs + (int64_t)i * f.ss;
 #pragma unroll
     for (int k = 0; k < 12; ++k) s[k] = St<S>::from_reg(b[(int64_t)k * f.n]);
-    if constexpr (sizeof(S) == 2) return f.scale[r * f.srs + i];
+    if constexpr (sizeof(S) == 2) return f.scale[r * f.srs + (int64_t)i * f.sss];
     else return typename St<S>::T(1);
   }
 }
@@ -248,8 +255,8 @@ template <class S, bool O32 = false>
 __device__ inline void st_spinor(const FieldV<S>& f, int r, int i, const cx<typename St<S>::T> s[12]) {
   typedef typename St<S>::E E;
   auto put = [&](int k, cx<typename St<S>::T> v) {
-    if constexpr (O32) st_off(f.p + (int64_t)k * f.n, (uint32_t)(r * f.rs + i) * (uint32_t)sizeof(E), St<S>::to(v));
-    else St<S>::st(f.p + r * f.rs + i + (int64_t)k * f.n, v);
+    if constexpr (O32) st_off(f.p + (int64_t)k * f.n, (uint32_t)(r * f.rs + (int64_t)i * f.ss) * (uint32_t)sizeof(E), St<S>::to(v));
+    else St<S>::st(f.p + r * f.rs + (int64_t)i * f.ss + (int64_t)k * f.n, v);
   };
   if constexpr (sizeof(S) == 2) {
     float m = 0.f;
@@ -257,8 +264,8 @@ __device__ inline void st_spinor(const FieldV<S>& f, int r, int i, const cx<type
     for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(s[k].re), fabsf(s[k].im)));
     float sc = m > 0.f ? m : 1.f;
     float inv = 1.f / sc;
-    if constexpr (O32) st_off(f.scale, (uint32_t)(r * f.srs + i) * 4u, sc);
-    else f.scale[r * f.srs + i] = sc;
+    if constexpr (O32) st_off(f.scale, (uint32_t)(r * f.srs + (int64_t)i * f.sss) * 4u, sc);
+    else f.scale[r * f.srs + (int64_t)i * f.sss] = sc;
 #pragma unroll
     for (int k = 0; k < 12; ++k) put(k, cx<float>{s[k].re * inv, s[k].im * inv});
   } else {
