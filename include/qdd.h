@@ -142,6 +142,12 @@ qdd_status qdd_unpack_field(qdd_ctx* ctx, qdd_prec prec, int nrhs, int even_only
 qdd_status qdd_dw_hat(qdd_ctx* ctx, qdd_prec prec, int nrhs, const void* in_e, void* out_e);
 /* out = D in on packed full fields (Eq. 1). */
 qdd_status qdd_dw(qdd_ctx* ctx, qdd_prec prec, int nrhs, const void* in, void* out);
+/* Full D at one mass per right-hand side in one launch (Eq. 1): out_r = D(kappas[r]) in_r,
+ * using that only the diagonal of the clover term, 1/(2 kappa), depends on kappa, so
+ * D(kappa_r) = D(kappa) + (1/(2 kappa_r) - 1/(2 kappa)) with kappa that of qdd_set_params.
+ * kappas: host array of nrhs positive values (nrhs <= 64); fields as for qdd_dw.
+ * QDD_EINVAL for bad arguments, QDD_ESTATE before qdd_set_params. */
+qdd_status qdd_dw_masses(qdd_ctx* ctx, qdd_prec prec, int nrhs, const double* kappas, const void* in, void* out);
 
 /* psi = M_sap eta: ncy cycles of the two-colour Schwarz procedure with nmr
  * minimal-residual steps on the even-odd block operator of every block, in the

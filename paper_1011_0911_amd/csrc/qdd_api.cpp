@@ -375,6 +375,29 @@ qdd_status qdd_dw(qdd_ctx* x, qdd_prec prec, int nrhs, const void* in, void* out
   return QDD_OK;
 }
 
+qdd_status qdd_dw_masses(qdd_ctx* x, qdd_prec prec, int nrhs, const double* kappas, const void* in, void* out) {
+  if (!x || !in || !out || !kappas || nrhs < 1 || nrhs > x->cfg.max_nrhs || nrhs > kMaxShift || prec < QDD_F64 ||
+      prec > QDD_F16) {
+    if (x) x->fail("qdd_dw_masses: invalid arguments");
+    return QDD_EINVAL;
+  }
+  if (!x->have_clover) { x->fail("qdd_dw_masses before qdd_set_params"); return QDD_ESTATE; }
+  RhsShift sh;
+  sh.on = 1;
+  for (int r = 0; r < nrhs; ++r) {
+    if (!(kappas[r] > 0.0)) { x->fail("qdd_dw_masses: kappa must be positive"); return QDD_EINVAL; }
+    sh.d[r] = 0.5 / kappas[r] - 0.5 / x->kappa;
+  }
+  PackedView a = x->packed(prec, nrhs, 0, (void*)in), b = x->packed(prec, nrhs, 0, out);
+  const LaunchCfg& c = x->launch[1][prec];
+  switch (prec) {
+    case QDD_F64: HCK(x, launch_dw<double>(x->G, x->op<double>(), a.f64, b.f64, a.poff, a.spoff, nrhs, c, x->st, &sh)); break;
+    case QDD_F32: HCK(x, launch_dw<float>(x->G, x->op<float>(), a.f32, b.f32, a.poff, a.spoff, nrhs, c, x->st, &sh)); break;
+    default: HCK(x, launch_dw<__half>(x->G, x->op<__half>(), a.f16, b.f16, a.poff, a.spoff, nrhs, c, x->st, &sh)); break;
+  }
+  return QDD_OK;
+}
+
 qdd_status qdd_set_launch(qdd_ctx* x, int kernel, qdd_prec prec, int block, int nr, int xcd, int sb) {
   bool ok = x && kernel >= 0 && kernel <= 1 && prec >= QDD_F64 && prec <= QDD_F16 && block >= 64 && block <= 256 &&
             (block & 63) == 0 && (nr == 0 || nr == 1 || nr == 2 || nr == 4) && (xcd >= 0 && xcd <= 3) &&

@@ -170,7 +170,8 @@ __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k
 // elements); the two halves of the grid are walked like two Dhat passes
 template <class S, int NR, bool O32>
 __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k_dw(Geo g, LinkV<S> U, CloverV<S> A, FieldV<S> in, FieldV<S> out,
-                                            int64_t poff, int64_t spoff, int nrhs, int nrg, int order, int sb) {
+                                            int64_t poff, int64_t spoff, int nrhs, int nrg, int order, int sb,
+                                            RhsShift sh) {
   typedef typename St<S>::T T;
   const int rf = 0;  // full fields are always in the blocked layout
   int nh = gridDim.x >> 1;
@@ -203,6 +204,11 @@ __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k
       cx<T> s[12], o[12];
       T sc = ld_spinor_raw<S, O32>(self, r0 + q, i, s);
       clover_apply_u<S>(A, p, i, s, o);
+      if (sh.on) {
+        const T dl = (T)sh.d[r0 + q];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) o[k] = cacc(o[k], dl, s[k]);
+      }
 #pragma unroll
       for (int k = 0; k < 12; ++k) o[k] = cacc(acc[q][k], sc, o[k]);
       st_spinor<S, O32>(dst, r0 + q, i, o);
@@ -433,26 +439,30 @@ hipError_t launch_dhat(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S>
 
 template <class S, int NR>
 static hipError_t launch_dw_nr(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> out, int64_t poff,
-                               int64_t spoff, int nrhs, const LaunchCfg& c, hipStream_t st) {
+                               int64_t spoff, int nrhs, const LaunchCfg& c, hipStream_t st, const RhsShift& sh) {
   int sb = c.sb > 0 ? c.sb : c.block;
   int nrg = ceil_div(nrhs, NR * (c.block / sb));
   int tiles = 2 * ceil_div(g.Vh, sb);
   if (fits32(g, in, nrhs, poff, spoff) && fits32(g, out, nrhs, poff, spoff))
     hipLaunchKernelGGL((k_dw<S, NR, true>), dim3(tiles * nrg), dim3(c.block), 0, st, g, op.U, op.A, in, out, poff,
-                       spoff, nrhs, nrg, c.xcd, sb);
+                       spoff, nrhs, nrg, c.xcd, sb, sh);
   else
     hipLaunchKernelGGL((k_dw<S, NR, false>), dim3(tiles * nrg), dim3(c.block), 0, st, g, op.U, op.A, in, out, poff,
-                       spoff, nrhs, nrg, c.xcd, sb);
+                       spoff, nrhs, nrg, c.xcd, sb, sh);
   return hipGetLastError();
 }
 
 template <class S>
 hipError_t launch_dw(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> out, int64_t poff, int64_t spoff,
-                     int nrhs, const LaunchCfg& c, hipStream_t st) {
+                     int nrhs, const LaunchCfg& c, hipStream_t st, const RhsShift* shift) {
+  RhsShift sh;
+  sh.on = 0;
+  if (shift) sh = *shift;
+  if (sh.on && nrhs > kMaxShift) return hipErrorInvalidValue;
   switch (c.nr) {
-    case 1: return launch_dw_nr<S, 1>(g, op, in, out, poff, spoff, nrhs, c, st);
-    case 2: return launch_dw_nr<S, 2>(g, op, in, out, poff, spoff, nrhs, c, st);
-    case 4: return launch_dw_nr<S, 4>(g, op, in, out, poff, spoff, nrhs, c, st);
+    case 1: return launch_dw_nr<S, 1>(g, op, in, out, poff, spoff, nrhs, c, st, sh);
+    case 2: return launch_dw_nr<S, 2>(g, op, in, out, poff, spoff, nrhs, c, st, sh);
+    case 4: return launch_dw_nr<S, 4>(g, op, in, out, poff, spoff, nrhs, c, st, sh);
     default: return hipErrorInvalidValue;
   }
 }
@@ -461,7 +471,7 @@ hipError_t launch_dw(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> o
   template hipError_t launch_dhat<S>(const Geo&, const DevOp<S>&, FieldV<S>, FieldV<S>, FieldV<S>, int,             \
                                      const LaunchCfg&, hipStream_t, int, hipEvent_t);                               \
   template hipError_t launch_dw<S>(const Geo&, const DevOp<S>&, FieldV<S>, FieldV<S>, int64_t, int64_t, int,        \
-                                   const LaunchCfg&, hipStream_t);
+                                   const LaunchCfg&, hipStream_t, const RhsShift*);
 INST(double)
 INST(float)
 INST(__half)

@@ -72,6 +72,7 @@ SIGNATURES = {
     "qdd_unpack_field": (_i, [_vp, _i, _i, _i, _vp, _vp]),
     "qdd_dw_hat": (_i, [_vp, _i, _i, _vp, _vp]),
     "qdd_dw": (_i, [_vp, _i, _i, _vp, _vp]),
+    "qdd_dw_masses": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
     "qdd_sap": (_i, [_vp, _i, _vp, _vp]),
     "qdd_dfl_build": (_i, [_vp, _vp]),
     "qdd_dfl_export": (_i, [_vp, _vp, _vp]),
@@ -226,6 +227,19 @@ class Context:
         fo = self.empty_field(prec, nrhs, True)
         self.dw_hat(prec, nrhs, fi, fo)
         return self.unpack(prec, fo, nrhs, True)
+
+    def dw_masses(self, prec, nrhs, kappas, fin, fout):
+        """out_r = D(kappas[r]) in_r on packed full fields, one launch."""
+        k = (ctypes.c_double * nrhs)(*[float(v) for v in kappas])
+        self._check(lib().qdd_dw_masses(self.h, prec, nrhs, ctypes.cast(k, ctypes.c_void_p), _ptr(fin), _ptr(fout)))
+
+    def apply_dw_masses(self, psi, kappas, prec=F64):
+        c = self._c128(psi)
+        nrhs = c.numel() // (self.V * 12)
+        fi = self.pack(prec, c, False)
+        fo = self.empty_field(prec, nrhs, False)
+        self.dw_masses(prec, nrhs, kappas, fi, fo)
+        return self.unpack(prec, fo, nrhs, False)
 
     def apply_dw(self, psi, prec=F64):
         c = self._c128(psi)

@@ -119,6 +119,22 @@ def test_staged_variant_parity_and_limits(Q, orc):
         assert e.value.status == Q.QDD_EINVAL
 
 
+def test_dw_several_masses_in_one_launch(Q, orc):
+    # out_r = D(kappa_r) psi_r: the clover diagonal 1/(2 kappa) is the only kappa dependence
+    L = (8, 4, 4, 4)
+    V = int(np.prod(L))
+    ctx, U = make_ctx(Q, L, 0.5, 0.1355, 1.9, 305, max_nrhs=3)
+    kappas = [0.1350, 0.1357, 0.13]
+    psi = S.gaussian_field(V, 13, nrhs=3)
+    ref = np.stack([orc.apply_D(L, U, orc.clover(L, U, k, 1.9)[0], psi[r]) for r, k in enumerate(kappas)])
+    for prec in (0, 1, 2):
+        e = relerr(to_np(ctx.apply_dw_masses(psi, kappas, prec)), ref)
+        assert e < TOL[prec], (prec, e)
+    with pytest.raises(Q.QddError) as err:
+        ctx.apply_dw_masses(psi, [0.1355, -1.0, 0.13])
+    assert err.value.status == Q.QDD_EINVAL
+
+
 def test_pack_unpack_roundtrip(Q):
     L = (4, 4, 4, 8)
     ctx, U = make_ctx(Q, L, 0.5, 0.1355, 1.9, 302, max_nrhs=2)
