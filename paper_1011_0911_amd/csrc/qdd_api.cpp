@@ -117,6 +117,7 @@ void compute_layout(const qdd_geom* g, const qdd_config* c, Layout& Lo) {
   }
   Lo.tmp_o = B.take((size_t)nr * 12 * Vh * 16);
   Lo.tmp_o_scale = B.take((size_t)nr * Vh * 4);
+  Lo.dw_shift = B.take((size_t)kMaxShift * 8);
   Lo.flag = B.take(256);
   // FP64 solver fields (full lattice, nr rhs)
   size_t f64 = (size_t)nr * 24 * Vh * 16;
@@ -382,18 +383,20 @@ qdd_status qdd_dw_masses(qdd_ctx* x, qdd_prec prec, int nrhs, const double* kapp
     return QDD_EINVAL;
   }
   if (!x->have_clover) { x->fail("qdd_dw_masses before qdd_set_params"); return QDD_ESTATE; }
-  RhsShift sh;
-  sh.on = 1;
+  x->dw_shift_host.assign(nrhs, 0.0);
   for (int r = 0; r < nrhs; ++r) {
     if (!(kappas[r] > 0.0)) { x->fail("qdd_dw_masses: kappa must be positive"); return QDD_EINVAL; }
-    sh.d[r] = 0.5 / kappas[r] - 0.5 / x->kappa;
+    x->dw_shift_host[r] = 0.5 / kappas[r] - 0.5 / x->kappa;
   }
+  double* sh = x->ptr<double>(x->lo.dw_shift);
+  HCK(x, hipMemcpyAsync(sh, x->dw_shift_host.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, x->st));
+  HCK(x, hipStreamSynchronize(x->st));  // the host copy of the shifts may change with the next call
   PackedView a = x->packed(prec, nrhs, 0, (void*)in), b = x->packed(prec, nrhs, 0, out);
   const LaunchCfg& c = x->launch[1][prec];
   switch (prec) {
-    case QDD_F64: HCK(x, launch_dw<double>(x->G, x->op<double>(), a.f64, b.f64, a.poff, a.spoff, nrhs, c, x->st, &sh)); break;
-    case QDD_F32: HCK(x, launch_dw<float>(x->G, x->op<float>(), a.f32, b.f32, a.poff, a.spoff, nrhs, c, x->st, &sh)); break;
-    default: HCK(x, launch_dw<__half>(x->G, x->op<__half>(), a.f16, b.f16, a.poff, a.spoff, nrhs, c, x->st, &sh)); break;
+    case QDD_F64: HCK(x, launch_dw<double>(x->G, x->op<double>(), a.f64, b.f64, a.poff, a.spoff, nrhs, c, x->st, sh)); break;
+    case QDD_F32: HCK(x, launch_dw<float>(x->G, x->op<float>(), a.f32, b.f32, a.poff, a.spoff, nrhs, c, x->st, sh)); break;
+    default: HCK(x, launch_dw<__half>(x->G, x->op<__half>(), a.f16, b.f16, a.poff, a.spoff, nrhs, c, x->st, sh)); break;
   }
   return QDD_OK;
 }

@@ -19,7 +19,7 @@ constexpr int kNetGradBlocks = 256;
 // byte offsets of every buffer inside the caller's workspace
 struct Layout {
   size_t U[3], A[3], Ai[3];
-  size_t tmp_o, tmp_o_scale, flag;
+  size_t tmp_o, tmp_o_scale, flag, dw_shift;
   size_t eta, psi, res, t64, chi, phi;
   bool phi32;
   size_t s_rho, s_psi, s_v, s_eta, s_scale, s_tmp;
@@ -56,6 +56,7 @@ struct qdd_ctx {
   long coarse_iters = 0;  // little-operator GCR iterations since the last solve began
   int net_step = 0;       // Adam steps taken
   std::vector<int> fallbacks;  // network stage rejected, per rhs of the current solve
+  std::vector<double> dw_shift_host;  // source of the per-rhs mass shifts copied to the device
   struct Harvest* harvest = nullptr;  // pair capture of the next solve (qdd_solve_harvest)
   qdd::LaunchCfg launch[2][3];
   std::string err;

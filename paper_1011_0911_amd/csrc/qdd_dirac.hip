@@ -168,10 +168,10 @@ __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k
 
 // full D on both parities; in/out: full fields (parity p at offset p*poff
 // elements); the two halves of the grid are walked like two Dhat passes
-template <class S, int NR, bool O32>
+template <class S, int NR, bool O32, bool SH>
 __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k_dw(Geo g, LinkV<S> U, CloverV<S> A, FieldV<S> in, FieldV<S> out,
                                             int64_t poff, int64_t spoff, int nrhs, int nrg, int order, int sb,
-                                            RhsShift sh) {
+                                            const double* shift) {
   typedef typename St<S>::T T;
   const int rf = 0;  // full fields are always in the blocked layout
   int nh = gridDim.x >> 1;
@@ -204,8 +204,8 @@ __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k
       cx<T> s[12], o[12];
       T sc = ld_spinor_raw<S, O32>(self, r0 + q, i, s);
       clover_apply_u<S>(A, p, i, s, o);
-      if (sh.on) {
-        const T dl = (T)sh.d[r0 + q];
+      if constexpr (SH) {
+        const T dl = (T)shift[r0 + q];
 #pragma unroll
         for (int k = 0; k < 12; ++k) o[k] = cacc(o[k], dl, s[k]);
       }
@@ -439,30 +439,33 @@ hipError_t launch_dhat(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S>
 
 template <class S, int NR>
 static hipError_t launch_dw_nr(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> out, int64_t poff,
-                               int64_t spoff, int nrhs, const LaunchCfg& c, hipStream_t st, const RhsShift& sh) {
+                               int64_t spoff, int nrhs, const LaunchCfg& c, hipStream_t st, const double* sh) {
   int sb = c.sb > 0 ? c.sb : c.block;
   int nrg = ceil_div(nrhs, NR * (c.block / sb));
   int tiles = 2 * ceil_div(g.Vh, sb);
-  if (fits32(g, in, nrhs, poff, spoff) && fits32(g, out, nrhs, poff, spoff))
-    hipLaunchKernelGGL((k_dw<S, NR, true>), dim3(tiles * nrg), dim3(c.block), 0, st, g, op.U, op.A, in, out, poff,
-                       spoff, nrhs, nrg, c.xcd, sb, sh);
-  else
-    hipLaunchKernelGGL((k_dw<S, NR, false>), dim3(tiles * nrg), dim3(c.block), 0, st, g, op.U, op.A, in, out, poff,
-                       spoff, nrhs, nrg, c.xcd, sb, sh);
+  const dim3 grid(tiles * nrg), blk(c.block);
+  const bool o32 = fits32(g, in, nrhs, poff, spoff) && fits32(g, out, nrhs, poff, spoff);
+#define DW(O, H) \
+  hipLaunchKernelGGL((k_dw<S, NR, O, H>), grid, blk, 0, st, g, op.U, op.A, in, out, poff, spoff, nrhs, nrg, c.xcd, sb, \
+                     sh)
+  if (o32) {
+    if (sh) DW(true, true);
+    else DW(true, false);
+  } else {
+    if (sh) DW(false, true);
+    else DW(false, false);
+  }
+#undef DW
   return hipGetLastError();
 }
 
 template <class S>
 hipError_t launch_dw(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> out, int64_t poff, int64_t spoff,
-                     int nrhs, const LaunchCfg& c, hipStream_t st, const RhsShift* shift) {
-  RhsShift sh;
-  sh.on = 0;
-  if (shift) sh = *shift;
-  if (sh.on && nrhs > kMaxShift) return hipErrorInvalidValue;
+                     int nrhs, const LaunchCfg& c, hipStream_t st, const double* shift) {
   switch (c.nr) {
-    case 1: return launch_dw_nr<S, 1>(g, op, in, out, poff, spoff, nrhs, c, st, sh);
-    case 2: return launch_dw_nr<S, 2>(g, op, in, out, poff, spoff, nrhs, c, st, sh);
-    case 4: return launch_dw_nr<S, 4>(g, op, in, out, poff, spoff, nrhs, c, st, sh);
+    case 1: return launch_dw_nr<S, 1>(g, op, in, out, poff, spoff, nrhs, c, st, shift);
+    case 2: return launch_dw_nr<S, 2>(g, op, in, out, poff, spoff, nrhs, c, st, shift);
+    case 4: return launch_dw_nr<S, 4>(g, op, in, out, poff, spoff, nrhs, c, st, shift);
     default: return hipErrorInvalidValue;
   }
 }
@@ -471,7 +474,7 @@ hipError_t launch_dw(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> o
   template hipError_t launch_dhat<S>(const Geo&, const DevOp<S>&, FieldV<S>, FieldV<S>, FieldV<S>, int,             \
                                      const LaunchCfg&, hipStream_t, int, hipEvent_t);                               \
   template hipError_t launch_dw<S>(const Geo&, const DevOp<S>&, FieldV<S>, FieldV<S>, int64_t, int64_t, int,        \
-                                   const LaunchCfg&, hipStream_t, const RhsShift*);
+                                   const LaunchCfg&, hipStream_t, const double*);
 INST(double)
 INST(float)
 INST(__half)

@@ -36,19 +36,16 @@ hipError_t launch_dhat(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S>
                        const LaunchCfg& c, hipStream_t st, int pass = 3, hipEvent_t ev = nullptr);
 // plain HBM copy (16-byte vectors), the bandwidth reference
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
-// per-rhs diagonal shifts of D (several masses in one launch: D(kappa_r) =
-// D(kappa_0) + (1/(2 kappa_r) - 1/(2 kappa_0)) because only the diagonal of the
-// clover term depends on kappa)
+// shift (device, nrhs doubles, optional): per-rhs diagonal shifts of D, for
+// several masses in one launch: D(kappa_r) = D(kappa_0) + (1/(2 kappa_r) -
+// 1/(2 kappa_0)) because only the diagonal of the clover term depends on kappa
 constexpr int kMaxShift = 64;
-struct RhsShift {
-  double d[kMaxShift];
-  int on;
-};
 template <class S>
 hipError_t launch_dw(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> out, int64_t poff, int64_t spoff,
-                     int nrhs, const LaunchCfg& c, hipStream_t st, const RhsShift* shift = nullptr);
+                     int nrhs, const LaunchCfg& c, hipStream_t st, const double* shift = nullptr);
 
 // ---- packing / conversion (qdd_pack.hip)
+
 // canonical complex128 links [V][4][3][3] -> FP64 internal hopping links (sign folded in)
 hipError_t launch_pack_links(const Geo& g, const double* canon, double2* U, hipStream_t st);
 // element-wise precision conversion of an array of n complex elements
