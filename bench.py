@@ -6,7 +6,8 @@ c_sw 1.9, 8 Gaussian right-hand sides, FP16 storage with FP32 arithmetic).
 
 A step is one Dhat apply of the whole batch (two kernel launches).  Prints one
 JSON line (metric, value in TB/s of algorithmic bytes, roofline of the dominant
-kernel measured with HIP events on the library's stream, CPU-oracle baseline).
+kernel measured with HIP events on the library's stream, CPU-oracle baseline;
+config.one_rhs: the same apply on a single right-hand side in each precision).
 The second half of the metric, seconds to relative residual 1e-10, is measured
 after the timed Dhat steps on the same lattice: the mixed-precision batched
 deflated SAP-GCR solve of the 8 right-hand sides next to the plain FP64 solver,
@@ -66,6 +67,30 @@ def measured_traffic(prec, nrhs, launch):
     if not e or e.get("kernel_hash") != kernel_source_hash() or e.get("launch") != list(launch):
         return None
     return e.get("pass_b_bytes")
+
+
+def one_rhs_rates(ctx, src1, cache, cache_path, reps=20):
+    """Dhat on a single right-hand side in each storage precision (autotuned
+    launch): TB/s of algorithmic bytes for the whole apply, HIP events on the
+    library stream.  Context figures next to the batched headline."""
+    import torch
+    from paper_1011_0911_amd import qdd
+
+    res = {}
+    for prec in (0, 1, 2):
+        fin = ctx.pack(prec, torch.from_numpy(src1), True)
+        fout = ctx.empty_field(prec, 1, True)
+        ctx.autotune(qdd.KERNEL_DHAT, prec, 1, fin, fout, reps=5, cache=cache)
+        ctx.dw_hat_timed(prec, 1, fin, fout, 3)
+        ms_a, ms_b = ctx.dw_hat_timed(prec, 1, fin, fout, reps)
+        a_b, b_b = bytes_per_site(prec, 1)
+        tbs = (a_b + b_b) * ctx.Vh / ((ms_a + ms_b) * 1e-3) / 1e12
+        res[{0: "f64", 1: "f32", 2: "f16"}[prec]] = {"ms": round(ms_a + ms_b, 5), "TBs": round(tbs, 4),
+                                                     "frac": round(tbs / PEAK_HBM_TBS, 4),
+                                                     "launch": list(ctx.get_launch(qdd.KERNEL_DHAT, prec))}
+        del fin, fout
+    qdd.save_tune_cache(cache_path, cache)
+    return res
 
 
 def cpu_baseline(U, nrhs_gpu, prec_gpu, budget_s=12.0):
@@ -178,6 +203,8 @@ def main():
         qdd.save_tune_cache(cache_path, cache)
     launch = ctx.get_launch(qdd.KERNEL_DHAT, prec)
     print(f"[bench] launch {launch} (tuned {tuned_ms})", file=sys.stderr, flush=True)
+    one_rhs = None if args.no_tune else one_rhs_rates(ctx, src[:1], cache, cache_path)
+    ctx.set_launch(qdd.KERNEL_DHAT, prec, *launch)
 
     st = ctx.stream
     for _ in range(args.warmup):
@@ -236,7 +263,8 @@ def main():
                                                 "sb": launch[3]},
                    "frac_of_peak_whole_apply": round(value / PEAK_HBM_TBS, 4),
                    "pass_a": {"ms": round(ms_a, 5), "TBs": round(ach_a, 4)},
-                   "copy_reference_TBs": round(copy_tbs, 4), "copy_bytes": nb, "wall_s_timed": round(wall, 3)},
+                   "copy_reference_TBs": round(copy_tbs, 4), "copy_bytes": nb, "wall_s_timed": round(wall, 3),
+                   "one_rhs": one_rhs},
         "roofline": {"bound": "hbm", "kernel": "k_dhat_b (pass B)", "achieved": round(ach_b, 4),
                      "peak": PEAK_HBM_TBS, "unit": "TB/s", "frac": round(ach_b / PEAK_HBM_TBS, 4),
                      "traffic": traffic, "bytes_per_launch": b_b * Vh, "ms_per_launch": round(ms_b, 5)},

@@ -237,7 +237,11 @@ qdd_status qdd_solve_harvest(qdd_ctx* ctx, const double* eta, double* psi, qdd_s
  * walk (0 linear; 1 every XCD takes a contiguous slab of the lattice; 2 slabs
  * whose tiles are walked time slice first, so time and x1 neighbours stay in
  * the XCD's L2; 3 slabs cut into sub-slabs of 4 time slices walked one x1
- * plane after the other); sb sites per block (0 = block): the block/sb lane groups of a
+ * plane after the other); for Dhat with nr = 1 plus 4: streaming
+ * (non-temporal) loads of the links and clover blocks, plus 8: streaming load
+ * of the site's own spinor and store of the output: data a pass touches once,
+ * kept from evicting the neighbour spinors from the L2; sb sites per block
+ * (0 = block): the block/sb lane groups of a
  * block take further right-hand sides of the same sites.  QDD_EINVAL for shapes
  * outside these ranges. */
 qdd_status qdd_set_launch(qdd_ctx* ctx, int kernel, qdd_prec prec, int block, int nr, int xcd, int sb);

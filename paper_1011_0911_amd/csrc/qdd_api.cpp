@@ -268,6 +268,9 @@ qdd_status qdd_create(const qdd_geom* g, const qdd_config* c, void* ws, size_t w
   G.bc = g->bc_time;
   for (int k = 0; k < 2; ++k)
     for (int p = 0; p < 3; ++p) x->launch[k][p] = LaunchCfg();
+  // Dhat: streaming access to the own spinor and the output (the better or equal
+  // choice for every precision and batch size measured at 32^3x64)
+  for (int p = 0; p < 3; ++p) x->launch[0][p].xcd = 2 | 8;
   *out = x;
   return QDD_OK;
 }
@@ -403,7 +406,7 @@ qdd_status qdd_dw_masses(qdd_ctx* x, qdd_prec prec, int nrhs, const double* kapp
 
 qdd_status qdd_set_launch(qdd_ctx* x, int kernel, qdd_prec prec, int block, int nr, int xcd, int sb) {
   bool ok = x && kernel >= 0 && kernel <= 1 && prec >= QDD_F64 && prec <= QDD_F16 && block >= 64 && block <= 256 &&
-            (block & 63) == 0 && (nr == 0 || nr == 1 || nr == 2 || nr == 4) && (xcd >= 0 && xcd <= 3) &&
+            (block & 63) == 0 && (nr == 0 || nr == 1 || nr == 2 || nr == 4) && xcd >= 0 && xcd <= (kernel == 0 && nr == 1 ? 15 : 3) &&
             (sb == 0 || (sb >= 1 && sb <= block && block % sb == 0));
   // staged variant (nr = 0): Dhat only, and the tile's links + clover must fit the LDS budget
   if (ok && nr == 0) ok = kernel == 0 && staged_lds_bytes(prec, sb > 0 ? sb : block) <= kStagedLdsMax;

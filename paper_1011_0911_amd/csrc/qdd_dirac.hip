@@ -14,13 +14,13 @@
 
 namespace qdd {
 
-template <class S, int MU, int NR, bool O32>
+template <class S, int MU, int NR, bool O32, bool NT = false>
 __device__ inline void hop_dir(const Geo& g, const LinkV<S>& U, const FieldV<S>& in, int r0, int nr, int p, int i,
                                const int x[4], typename St<S>::T c0, cx<typename St<S>::T> (&acc)[NR][12]) {
   typedef typename St<S>::T T;
   cx<T> u[9], s[12], h[6], gg[6];
   int j = nbr_idx(g, x, MU, +1);
-  ld_link_u(U, p, MU, i, u);
+  ld_link_u<S, NT>(U, p, MU, i, u);
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     if (q < nr) {
@@ -32,7 +32,7 @@ __device__ inline void hop_dir(const Geo& g, const LinkV<S>& U, const FieldV<S>&
   }
   __builtin_amdgcn_sched_barrier(0);
   j = nbr_idx(g, x, MU, -1);
-  ld_link_u(U, 1 - p, MU, j, u);
+  ld_link_u<S, NT>(U, 1 - p, MU, j, u);
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     if (q < nr) {
@@ -44,19 +44,20 @@ __device__ inline void hop_dir(const Geo& g, const LinkV<S>& U, const FieldV<S>&
   }
 }
 
-// acc += c0 H in (H: the hopping sum over the 8 neighbours)
-template <class S, int NR, bool O32>
+// acc += c0 H in (H: the hopping sum over the 8 neighbours); NT: links are
+// read with streaming loads (each is read once per pass)
+template <class S, int NR, bool O32, bool NT = false>
 __device__ inline void hop_all(const Geo& g, const LinkV<S>& U, const FieldV<S>& in, int r0, int nr, int p, int i,
                                const int x[4], typename St<S>::T c0, cx<typename St<S>::T> (&acc)[NR][12]) {
   // scheduling barriers between the directions bound the number of loads in
   // flight per lane (and so the registers); the other waves hide the latency
-  hop_dir<S, 0, NR, O32>(g, U, in, r0, nr, p, i, x, c0, acc);
+  hop_dir<S, 0, NR, O32, NT>(g, U, in, r0, nr, p, i, x, c0, acc);
   __builtin_amdgcn_sched_barrier(0);
-  hop_dir<S, 1, NR, O32>(g, U, in, r0, nr, p, i, x, c0, acc);
+  hop_dir<S, 1, NR, O32, NT>(g, U, in, r0, nr, p, i, x, c0, acc);
   __builtin_amdgcn_sched_barrier(0);
-  hop_dir<S, 2, NR, O32>(g, U, in, r0, nr, p, i, x, c0, acc);
+  hop_dir<S, 2, NR, O32, NT>(g, U, in, r0, nr, p, i, x, c0, acc);
   __builtin_amdgcn_sched_barrier(0);
-  hop_dir<S, 3, NR, O32>(g, U, in, r0, nr, p, i, x, c0, acc);
+  hop_dir<S, 3, NR, O32, NT>(g, U, in, r0, nr, p, i, x, c0, acc);
   __builtin_amdgcn_sched_barrier(0);
 }
 
@@ -110,7 +111,10 @@ __device__ inline bool lane_site(const Geo& g, int tile, int rg, int sb, int nrh
   return i < g.Vh && r0 < nrhs;
 }
 
-template <class S, int NR, bool O32>
+// NTM: streaming (non-temporal) access for what the pass touches once; bit 0
+// the links and clover blocks, bit 1 the site's own spinor and the output.  The
+// neighbour spinors, which eight sites read, always take ordinary loads.
+template <class S, int NR, bool O32, int NTM>
 __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k_dhat_a(Geo g, LinkV<S> U, CloverV<S> Ai, FieldV<S> in_e, FieldV<S> t_o,
                                                 int nrhs, int nrg, int order, int sb, int rf) {
   typedef typename St<S>::T T;
@@ -125,18 +129,18 @@ __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k
   for (int q = 0; q < NR; ++q)
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[q][k] = {T(0), T(0)};
-  hop_all<S, NR, O32>(g, U, in_e, r0, nr, 1, i, x, T(1), acc);
+  hop_all<S, NR, O32, (NTM & 1) != 0>(g, U, in_e, r0, nr, 1, i, x, T(1), acc);
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     if (q < nr) {
       cx<T> o[12];
-      clover_apply_u<S>(Ai, 1, i, acc[q], o);
-      st_spinor<S, O32>(t_o, r0 + q, i, o);
+      clover_apply_u<S, (NTM & 1) != 0>(Ai, 1, i, acc[q], o);
+      st_spinor<S, O32, (NTM & 2) != 0>(t_o, r0 + q, i, o);
     }
   }
 }
 
-template <class S, int NR, bool O32>
+template <class S, int NR, bool O32, int NTM>
 __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k_dhat_b(Geo g, LinkV<S> U, CloverV<S> A, FieldV<S> in_e, FieldV<S> t_o,
                                                 FieldV<S> out_e, int nrhs, int nrg, int order, int sb, int rf) {
   typedef typename St<S>::T T;
@@ -152,16 +156,16 @@ __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k
   for (int q = 0; q < NR; ++q)
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[q][k] = {T(0), T(0)};
-  hop_all<S, NR, O32>(g, U, t_o, r0, nr, 0, i, x, T(-0.25), acc);
+  hop_all<S, NR, O32, (NTM & 1) != 0>(g, U, t_o, r0, nr, 0, i, x, T(-0.25), acc);
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     if (q < nr) {
       cx<T> s[12], o[12];
-      T sc = ld_spinor_raw<S, O32>(in_e, r0 + q, i, s);
-      clover_apply_u<S>(A, 0, i, s, o);
+      T sc = ld_spinor_raw<S, O32, (NTM & 2) != 0>(in_e, r0 + q, i, s);
+      clover_apply_u<S, (NTM & 1) != 0>(A, 0, i, s, o);
 #pragma unroll
       for (int k = 0; k < 12; ++k) o[k] = cacc(acc[q][k], sc, o[k]);
-      st_spinor<S, O32>(out_e, r0 + q, i, o);
+      st_spinor<S, O32, (NTM & 2) != 0>(out_e, r0 + q, i, o);
     }
   }
 }
@@ -407,21 +411,21 @@ static hipError_t launch_dhat_nr(const Geo& g, const DevOp<S>& op, FieldV<S> in,
   int tiles = ceil_div(g.Vh, sb);
   dim3 grid(tiles * nrg), blk(c.block);
   const bool o32 = fits32(g, in, nrhs) && fits32(g, tmp, nrhs) && fits32(g, out, nrhs);
+  const int ntm = o32 && NR == 1 ? (c.xcd >> 2) & 3 : 0;  // streaming access to single-use data
+  const int order = c.xcd & 3;
   const int rf = in.ss > 1;  // interleaved operands: rhs fastest across the lanes
-  if (pass & 1) {
-    if (o32)
-      hipLaunchKernelGGL((k_dhat_a<S, NR, true>), grid, blk, 0, st, g, op.U, op.Ainv, in, tmp, nrhs, nrg, c.xcd, sb, rf);
-    else
-      hipLaunchKernelGGL((k_dhat_a<S, NR, false>), grid, blk, 0, st, g, op.U, op.Ainv, in, tmp, nrhs, nrg, c.xcd, sb, rf);
+#define QDD_DHAT_PASS(KER, ...)                                                                       \
+  switch (o32 ? 1 + ntm : 0) {                                                                        \
+    case 0: hipLaunchKernelGGL((KER<S, NR, false, 0>), grid, blk, 0, st, __VA_ARGS__); break;         \
+    case 1: hipLaunchKernelGGL((KER<S, NR, true, 0>), grid, blk, 0, st, __VA_ARGS__); break;          \
+    case 2: hipLaunchKernelGGL((KER<S, NR, true, NR == 1 ? 1 : 0>), grid, blk, 0, st, __VA_ARGS__); break; \
+    case 3: hipLaunchKernelGGL((KER<S, NR, true, NR == 1 ? 2 : 0>), grid, blk, 0, st, __VA_ARGS__); break; \
+    default: hipLaunchKernelGGL((KER<S, NR, true, NR == 1 ? 3 : 0>), grid, blk, 0, st, __VA_ARGS__); break; \
   }
+  if (pass & 1) QDD_DHAT_PASS(k_dhat_a, g, op.U, op.Ainv, in, tmp, nrhs, nrg, order, sb, rf)
   if (ev) (void)hipEventRecord(ev, st);
-  if (pass & 2) {
-    if (o32)
-      hipLaunchKernelGGL((k_dhat_b<S, NR, true>), grid, blk, 0, st, g, op.U, op.A, in, tmp, out, nrhs, nrg, c.xcd, sb, rf);
-    else
-      hipLaunchKernelGGL((k_dhat_b<S, NR, false>), grid, blk, 0, st, g, op.U, op.A, in, tmp, out, nrhs, nrg, c.xcd,
-                         sb, rf);
-  }
+  if (pass & 2) QDD_DHAT_PASS(k_dhat_b, g, op.U, op.A, in, tmp, out, nrhs, nrg, order, sb, rf)
+#undef QDD_DHAT_PASS
   return hipGetLastError();
 }
 

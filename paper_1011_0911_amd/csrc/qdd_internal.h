@@ -191,22 +191,29 @@ struct RawW<8> { typedef unsigned int T __attribute__((ext_vector_type(2))); };
 template <>
 struct RawW<16> { typedef unsigned int T __attribute__((ext_vector_type(4))); };
 
-template <class E>
+// NT: non-temporal (streaming) access, for data a pass touches only once, so
+// that it does not push reused neighbour data out of the L2
+template <class E, bool NT = false>
 __device__ inline E ld_off(const E* base, uint32_t byte_off) {
   typedef typename RawW<sizeof(E)>::T R;
   typedef const __attribute__((address_space(1))) R* GP;
-  R raw = *reinterpret_cast<GP>(uniform_addr(base) + byte_off);
+  GP a = reinterpret_cast<GP>(uniform_addr(base) + byte_off);
+  R raw;
+  if constexpr (NT) raw = __builtin_nontemporal_load(a);
+  else raw = *a;
   E v;
   __builtin_memcpy(&v, &raw, sizeof(E));
   return v;
 }
-template <class E>
+template <class E, bool NT = false>
 __device__ inline void st_off(E* base, uint32_t byte_off, E v) {
   typedef typename RawW<sizeof(E)>::T R;
   typedef __attribute__((address_space(1))) R* GP;
   R raw;
   __builtin_memcpy(&raw, &v, sizeof(E));
-  *reinterpret_cast<GP>(uniform_addr(base) + byte_off) = raw;
+  GP a = reinterpret_cast<GP>(uniform_addr(base) + byte_off);
+  if constexpr (NT) __builtin_nontemporal_store(raw, a);
+  else *a = raw;
 }
 
 // load / store of a 12-component spinor of site i, rhs r.  O32: the caller
@@ -233,14 +240,14 @@ __device__ inline void ld_spinor(const FieldV<S>& f, int r, int i, cx<typename S
 }
 
 // the stored components without the FP16 scale, and the scale (1 for FP32/FP64)
-template <class S, bool O32 = false>
+template <class S, bool O32 = false, bool NT = false>
 __device__ inline typename St<S>::T ld_spinor_raw(const FieldV<S>& f, int r, int i, cx<typename St<S>::T> s[12]) {
   typedef typename St<S>::E E;
   if constexpr (O32) {
     const uint32_t vo = (uint32_t)(r * f.rs + (int64_t)i * f.ss) * (uint32_t)sizeof(E);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) s[k] = St<S>::from_reg(ld_off(f.p + (int64_t)k * f.n, vo));
-    if constexpr (sizeof(S) == 2) return ld_off(f.scale, (uint32_t)(r * f.srs + (int64_t)i * f.sss) * 4u);
+    for (int k = 0; k < 12; ++k) s[k] = St<S>::from_reg(ld_off<E, NT>(f.p + (int64_t)k * f.n, vo));
+    if constexpr (sizeof(S) == 2) return ld_off<float, NT>(f.scale, (uint32_t)(r * f.srs + (int64_t)i * f.sss) * 4u);
     else return typename St<S>::T(1);
   } else {
     const E* b = f.p + r * f.rs + (int64_t)i * f.ss;
@@ -251,11 +258,11 @@ __device__ inline typename St<S>::T ld_spinor_raw(const FieldV<S>& f, int r, int
   }
 }
 
-template <class S, bool O32 = false>
+template <class S, bool O32 = false, bool NT = false>
 __device__ inline void st_spinor(const FieldV<S>& f, int r, int i, const cx<typename St<S>::T> s[12]) {
   typedef typename St<S>::E E;
   auto put = [&](int k, cx<typename St<S>::T> v) {
-    if constexpr (O32) st_off(f.p + (int64_t)k * f.n, (uint32_t)(r * f.rs + (int64_t)i * f.ss) * (uint32_t)sizeof(E), St<S>::to(v));
+    if constexpr (O32) st_off<E, NT>(f.p + (int64_t)k * f.n, (uint32_t)(r * f.rs + (int64_t)i * f.ss) * (uint32_t)sizeof(E), St<S>::to(v));
     else St<S>::st(f.p + r * f.rs + (int64_t)i * f.ss + (int64_t)k * f.n, v);
   };
   if constexpr (sizeof(S) == 2) {
@@ -264,7 +271,7 @@ __device__ inline void st_spinor(const FieldV<S>& f, int r, int i, const cx<type
     for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(s[k].re), fabsf(s[k].im)));
     float sc = m > 0.f ? m : 1.f;
     float inv = 1.f / sc;
-    if constexpr (O32) st_off(f.scale, (uint32_t)(r * f.srs + (int64_t)i * f.sss) * 4u, sc);
+    if constexpr (O32) st_off<float, NT>(f.scale, (uint32_t)(r * f.srs + (int64_t)i * f.sss) * 4u, sc);
     else f.scale[r * f.srs + (int64_t)i * f.sss] = sc;
 #pragma unroll
     for (int k = 0; k < 12; ++k) put(k, cx<float>{s[k].re * inv, s[k].im * inv});
@@ -288,13 +295,13 @@ __device__ inline void ld_link(const LinkV<S>& u, int par, int mu, int i, cx<typ
 }
 // the same for a parity and direction that are uniform across the wavefront
 // (scalar component bases, one 32-bit offset)
-template <class S>
+template <class S, bool NT = false>
 __device__ inline void ld_link_u(const LinkV<S>& u, int par, int mu, int i, cx<typename St<S>::T> m[9]) {
   typedef typename St<S>::E E;
   const E* b = u.p + ((int64_t)(par * 4 + mu) * 9) * u.n;
   const uint32_t vo = (uint32_t)i * (uint32_t)sizeof(E);  // i < n: always within 32 bits
 #pragma unroll
-  for (int k = 0; k < 9; ++k) m[k] = St<S>::from(ld_off(b + (int64_t)k * u.n, vo));
+  for (int k = 0; k < 9; ++k) m[k] = St<S>::from(ld_off<E, NT>(b + (int64_t)k * u.n, vo));
 }
 
 // clover: A[p][slot][i], 36 slots (2 blocks x 18)
@@ -336,7 +343,7 @@ __device__ inline void clover_apply(const CloverV<S>& A, int par, int i, const c
   }
 }
 // the same for a parity that is uniform across the wavefront
-template <class S>
+template <class S, bool NT = false>
 __device__ inline void clover_apply_u(const CloverV<S>& A, int par, int i, const cx<typename St<S>::T> in[12],
                                       cx<typename St<S>::T> out[12]) {
   typedef typename St<S>::T T;
@@ -347,7 +354,7 @@ __device__ inline void clover_apply_u(const CloverV<S>& A, int par, int i, const
   for (int blk = 0; blk < 2; ++blk) {
     cx<T> a[18];
 #pragma unroll
-    for (int k = 0; k < 18; ++k) a[k] = St<S>::from(ld_off(b + (int64_t)(blk * 18 + k) * A.n, vo));
+    for (int k = 0; k < 18; ++k) a[k] = St<S>::from(ld_off<E, NT>(b + (int64_t)(blk * 18 + k) * A.n, vo));
     herm6_mul<T>(a, in + 6 * blk, out + 6 * blk);
   }
 }

@@ -1,5 +1,6 @@
 // Launch-shape autotuner for the stencil kernels: times every candidate
-// (threads per block, sites per block, right-hand sides per lane, XCD remap) with
+// (threads per block, sites per block, right-hand sides per lane, XCD remap,
+// streaming access for Dhat) with
 // HIP events on the context's stream and keeps the fastest one.
 #include "qdd_api_internal.h"
 
@@ -23,7 +24,11 @@ extern "C" qdd_status qdd_autotune(qdd_ctx* x, int kernel, qdd_prec prec, int nr
       for (int nr : {1, 2, 4}) {
         if (lane_groups * nr > 2 * nrhs && !(lane_groups == 1 && nr == 1)) continue;  // mostly idle lanes
         if (nr > nrhs) continue;
-        for (int xcd : {0, 1, 2, 3}) cand.push_back(LaunchCfg{block, nr, xcd, sb == block ? 0 : sb});
+        for (int xcd : {0, 1, 2, 3}) {
+          cand.push_back(LaunchCfg{block, nr, xcd, sb == block ? 0 : sb});
+          if (kernel == 0 && nr == 1)  // streaming access: links + clover (4), own spinor + output (8)
+            for (int ntm : {4, 8, 12}) cand.push_back(LaunchCfg{block, nr, xcd | ntm, sb == block ? 0 : sb});
+        }
       }
       // staged variant (Dhat): R = block / sb lanes per site loop over the right-hand sides
       if (kernel == 0 && lane_groups <= nrhs && staged_lds_bytes(prec, sb) <= kStagedLdsMax)

@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libqdd.so")
 F64, F32, F16 = 0, 1, 2
 PRECOND_NONE, PRECOND_SAP, PRECOND_DFL = 0, 1, 2
 KERNEL_DHAT, KERNEL_DW = 0, 1
+# candidate set of the autotuner (cached choices of an older set are re-measured)
+TUNER_VERSION = "t2"
 
 QDD_OK, QDD_EINVAL, QDD_ESTATE, QDD_ESINGULAR, QDD_ENOCONV, QDD_EHIP, QDD_ENOWS = 0, -1, -2, -3, -4, -5, -6
 _NAMES = {0: "QDD_OK", -1: "QDD_EINVAL", -2: "QDD_ESTATE", -3: "QDD_ESINGULAR", -4: "QDD_ENOCONV",
@@ -380,7 +382,8 @@ class Context:
     def autotune(self, kernel, prec, nrhs, fin, fout, reps=5, cache=None):
         """Picks the fastest launch shape (C++ timing loop in the library).  With a
         cache dict, a previously measured choice for the same key is reused."""
-        key = f"{kernel}/{prec}/{nrhs}/{'x'.join(map(str, self.L))}/{torch.cuda.get_device_properties(self.device).gcnArchName}"
+        key = (f"{TUNER_VERSION}/{kernel}/{prec}/{nrhs}/{'x'.join(map(str, self.L))}/"
+               f"{torch.cuda.get_device_properties(self.device).gcnArchName}")
         if cache is not None and key in cache:
             b, n, x, s = cache[key]["launch"]
             self.set_launch(kernel, prec, b, n, x, s)

@@ -86,6 +86,8 @@ def test_batched_equals_single_rhs(Q, kernel):
         if kernel == 0:  # the LDS-staged variant (nr = 0): tiles of sb sites, block/sb lanes per site
             shapes += [(64, 0, 0, 0), (128, 0, 1, 32), (256, 0, 2, 64), (256, 0, 1, 16), (192, 0, 0, 32), (128, 0, 3, 32)]
         shapes += [(128, 1, 3, 0), (256, 1, 3, 32)]
+        if kernel == 0:  # streaming loads / stores for the single-use data (xcd + 4, + 8)
+            shapes += [(256, 1, 4, 32), (128, 1, 14, 0), (64, 1, 11, 16), (256, 1, 8, 0)]
         for block, nr, xcd, sb in shapes:
             if nr == 0 and 108 * (sb or block) * (16 if prec == 0 else 8) > 65536:
                 continue  # staged tile does not fit the LDS budget in this precision
@@ -116,6 +118,11 @@ def test_staged_variant_parity_and_limits(Q, orc):
     for kernel, prec, block, sb in ((0, 0, 64, 64), (0, 1, 128, 128), (1, 1, 64, 0)):
         with pytest.raises(Q.QddError) as e:
             ctx.set_launch(kernel, prec, block, 0, 1, sb)
+        assert e.value.status == Q.QDD_EINVAL
+    # streaming access (xcd + 4, + 8) exists for the one-rhs-per-lane Dhat kernels only
+    for kernel, nr, xcd in ((1, 1, 4), (0, 0, 5), (0, 2, 8), (0, 1, 16), (0, 1, -1)):
+        with pytest.raises(Q.QddError) as e:
+            ctx.set_launch(kernel, 1, 128, nr, xcd, 32)
         assert e.value.status == Q.QDD_EINVAL
 
 

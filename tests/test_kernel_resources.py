@@ -17,8 +17,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # the stencil kernels the 32-bit-offset variants (every field below 4 GiB, the
 # case of all workloads here)
 HOT = [
-    ("qdd_dirac.hip", r"k_dhat_a<[^,]+, 1, true>"),
-    ("qdd_dirac.hip", r"k_dhat_b<[^,]+, 1, true>"),
+    ("qdd_dirac.hip", r"k_dhat_a<[^,]+, 1, true,"),
+    ("qdd_dirac.hip", r"k_dhat_b<[^,]+, 1, true,"),
     ("qdd_dirac.hip", r"k_dhat_staged<[^>]+, true>"),
     ("qdd_dirac.hip", r"k_dw<[^,]+, 1, true,"),
     ("qdd_net.hip", r"k_net_layer_mx<"),
