@@ -83,13 +83,17 @@ def traffic(bench_json: str, fetch_dir: str, write_dir: str, out_path: str, cmd:
     launch = [ln["block"], ln["nr"], ln["xcd"], ln["sb"]]
     copy_bytes = cfg["copy_bytes"]
     tname = {0: "double", 1: "float", 2: "__half"}[prec]
-    # pass-B kernel of the launch shape (name prefix; the last template argument
-    # is the addressing mode)
-    kb = f"qdd::k_dhat_staged<{tname}, 1," if ln["nr"] == 0 else f"qdd::k_dhat_b<{tname}, {ln['nr']},"
+    # pass-B kernel of the launch shape: staged variant (pass, addressing), or the
+    # per-lane kernel (rhs per lane, 32-bit addressing, streaming-access bits)
+    if ln["nr"] == 0:
+        kb = f"qdd::k_dhat_staged<{tname}, 1, true>"
+    else:
+        ntm = (ln["xcd"] >> 2) & 3 if ln["nr"] == 1 else 0
+        kb = f"qdd::k_dhat_b<{tname}, {ln['nr']}, true, {ntm}>"
     fetch, write = _counter(fetch_dir, "FETCH_SIZE"), _counter(write_dir, "WRITE_SIZE")
 
     def pick(tab, kname):
-        c = [(k, v) for k, v in tab.items() if k[0] == kname or k[0].startswith(kname)]
+        c = [(k, v) for k, v in tab.items() if k[0] == kname or (kname.endswith(",") and k[0].startswith(kname))]
         if not c:
             raise KeyError(f"{kname} not in the counter output")
         k, v = max(c, key=lambda kv: len(kv[1]))  # the timed launches: most dispatches
