@@ -2,6 +2,7 @@
 // operator entry points and the FP64 flexible GCR driver.
 #include "../../include/qdd.h"
 #include "qdd_api_internal.h"
+#include "qdd_net.h"
 
 #include <cmath>
 #include <cstdarg>
@@ -178,6 +179,13 @@ void compute_layout(const qdd_geom* g, const qdd_config* c, Layout& Lo) {
     Lo.net_w = B.take(nw * 8);       // complex FP32 master weights
     Lo.net_wb = B.take(nw * 4);      // complex BF16 compute copy
     Lo.net_wadj = B.take(nw * 4);    // BF16 adjoint weights (backward pass)
+    size_t nmx = 0, nmxa = 0;        // matrix-core operand copies, forward and backward
+    for (int l = 0; l < c->net_nl; ++l) {
+      nmx += net_wmx_elems(c->net_ch[l], c->net_ch[l + 1]);
+      nmxa += net_wmx_elems(c->net_ch[l + 1], c->net_ch[l]);
+    }
+    Lo.net_wmx = B.take(nmx * 2);
+    Lo.net_wmxa = B.take(nmxa * 2);
     Lo.net_act = B.take((size_t)(c->net_nl + 3) * maxch * 24 * Vh * 8);
     Lo.net_grad = B.take(nw * 8);
     Lo.net_adam = B.take(nw * 16);

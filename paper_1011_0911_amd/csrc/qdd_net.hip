@@ -23,84 +23,6 @@ __device__ inline uint16_t f_to_bf16(float f) {
   return (uint16_t)(r >> 16);
 }
 
-// one lane per site and output-channel group of CG channels; blockIdx.y = group
-template <int CG>
-__global__ void __launch_bounds__(128) k_net_layer(Geo g, LinkV<float> U, const uint32_t* Wb, int cin, int cout,
-                                                   const float2* in, float2* out, int64_t cs) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.V) return;
-  int s = (int)t;
-  int p = s >= g.Vh, i = s - p * g.Vh;
-  int c0 = blockIdx.y * CG;
-  int x[4];
-  site_coords(g, p, i, x);
-  cx<float> acc[CG][12];
-#pragma unroll
-  for (int q = 0; q < CG; ++q)
-#pragma unroll
-    for (int k = 0; k < 12; ++k) acc[q][k] = {0.f, 0.f};
-  for (int cp = 0; cp < cin; ++cp) {
-    const float2* f = in + cp * cs;
-    for (int d = 0; d < 9; ++d) {
-      cx<float> tr[12];
-      if (d == 0) {
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          float2 v = f[(int64_t)p * 12 * g.Vh + (int64_t)k * g.Vh + i];
-          tr[k] = {v.x, v.y};
-        }
-      } else {
-        int mu = (d - 1) >> 1, dir = (d - 1) & 1;
-        int j = nbr_idx(g, x, mu, dir == 0 ? 1 : -1);
-        cx<float> u[9], sp[12];
-        const float2* fb = f + (int64_t)(1 - p) * 12 * g.Vh + j;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          float2 v = fb[(int64_t)k * g.Vh];
-          sp[k] = {v.x, v.y};
-        }
-        if (dir == 0) ld_link(U, p, mu, i, u);
-        else ld_link(U, 1 - p, mu, j, u);
-#pragma unroll
-        for (int sp_i = 0; sp_i < 4; ++sp_i)
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            cx<float> z{0.f, 0.f};
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-              z = dir == 0 ? fma_c(u[a * 3 + b], sp[sp_i * 3 + b], z) : fmac_c(u[b * 3 + a], sp[sp_i * 3 + b], z);
-            tr[sp_i * 3 + a] = z;
-          }
-      }
-#pragma unroll
-      for (int q = 0; q < CG; ++q) {
-        int c = c0 + q;
-        if (c < cout) {
-          const uint32_t* w = Wb + ((int64_t)(d * cout + c) * cin + cp) * 16;
-#pragma unroll
-          for (int sa = 0; sa < 4; ++sa)
-#pragma unroll
-            for (int sb = 0; sb < 4; ++sb) {
-              uint32_t wv = w[sa * 4 + sb];
-              cx<float> ww{bf16_to_f((uint16_t)(wv & 0xffffu)), bf16_to_f((uint16_t)(wv >> 16))};
-#pragma unroll
-              for (int a = 0; a < 3; ++a) acc[q][sa * 3 + a] = fma_c(ww, tr[sb * 3 + a], acc[q][sa * 3 + a]);
-            }
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < CG; ++q) {
-    int c = c0 + q;
-    if (c < cout) {
-      float2* o = out + c * cs + (int64_t)p * 12 * g.Vh + i;
-#pragma unroll
-      for (int k = 0; k < 12; ++k) o[(int64_t)k * g.Vh] = make_float2(acc[q][k].re, acc[q][k].im);
-    }
-  }
-}
-
 // weight gradient partial sums: part[wg][((d*cout + c)*cin + c')*16 + s*4 + s'] =
 //   sum over the workgroup's sites and colours of gy_c[s] conj((T_d in_c')[s'])
 // Site chunks of the transported inputs and of gy are staged in LDS.
@@ -333,40 +255,90 @@ __global__ void k_net_adam(float2* w, const float2* g, float4* mv, int n, float 
 // For every site x and colour a the layer is one matrix-vector product
 //   out[(c, sa)](x, a) = sum_{d, c', sb} W[d][c][c'][sa][sb] T_d[(c', sb)](x, a),
 // T_d the link-transported inputs, so a tile of sites is a GEMM with the site
-// and colour as the column index.  In real form (rows (c, sa, re/im), k index
-// (c', sb, re/im)): A = [[Wre, -Wim], [Wim, Wre]] per (c, sa | c', sb) block.
+// and colour as the column index.  In real form, rows m = (c, sa, re/im) and
+// k = ((d, c'), sb, re/im) flattened over all nine transports (K = 72 cin,
+// zero-padded to a multiple of 32): A = [[Wre, -Wim], [Wim, Wre]] per
+// (c, sa | d, c', sb) block.  The weights are BF16 (A exact in BF16); each FP32
+// transported input is split exactly into three BF16 terms, t = hi + mid + lo
+// (8 + 8 + at most 8 significant bits), and A t = A hi + A mid + A lo runs on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation: the products are exact and
+// the result is as accurate as an FP32 product, at three BF16 matrix
+// operations per FP32 one of a quarter the depth.
 // A workgroup of 2 wavefronts takes kNetTile sites (3 kNetTile columns = 6
-// column tiles of 16); for each direction d the transported inputs of the
-// tile are computed into LDS as T[k][n] and the waves run
-// v_mfma_f32_16x16x4f32 over them (FP32 operands: the BF16 weights convert
-// exactly, the activations stay FP32), each wave owning 3 column tiles and
-// all MT row tiles.  Operand layout of 16x16x4: lane l holds A[l%16][l/16],
-// B[l/16][l%16] and D rows 4(l/16)+r, column l%16.
+// column tiles of 16) and walks K in slabs of one MFMA depth: every lane
+// computes one (site, d, c') transported input of the slab into LDS as the
+// three terms, [term][column][k] (k fastest: one 16-byte read per lane and
+// operand), and each wave runs the MFMAs of its 3 column tiles and all MT row
+// tiles.  The small slab (23 KB of LDS) leaves room for several workgroups per
+// compute unit, whose staging loads hide each other's latency.  The
+// A operands come prearranged (k_net_wmx) in the lane order of the
+// instruction: lane l holds A[l%16][8(l/16) .. 8(l/16)+7], B[8(l/16) ..][l%16],
+// and D rows 4(l/16)+r, column l%16 (measured with an in-bounds probe).
 constexpr int kNetTile = 32;
+constexpr int kNetKs = 32;             // k rows per slab (one MFMA depth): 4 (d, c') pairs x 4 spins x re/im
+constexpr int kNetLd = kNetKs + 8;     // LDS row stride of a column (BF16 elements)
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+__host__ __device__ inline int net_mt(int cout) { return (8 * cout + 15) / 16; }
+__host__ __device__ inline int net_kb(int cin) { return (72 * cin + 31) / 32; }
+
+// prearranged A operands of one layer: wmx[(mt * KB + kb) * 64 + lane][0..7]
+__global__ void k_net_wmx(const uint32_t* wb, int cin, int cout, uint16_t* wmx) {
+  const int MT = net_mt(cout), KB = net_kb(cin);
+  const int64_t n = (int64_t)MT * KB * 64 * 8;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int i = (int)(t & 7), lane = (int)((t >> 3) & 63);
+  const int64_t blk = t >> 9;
+  const int kb = (int)(blk % KB), mt = (int)(blk / KB);
+  const int m = 16 * mt + (lane & 15), k = 32 * kb + 8 * (lane >> 4) + i;
+  const int c = m >> 3, sa = (m >> 1) & 3, ri_o = m & 1;
+  uint16_t v = 0;
+  if (c < cout && k < 72 * cin) {
+    const int e = k >> 3, sb = (k >> 1) & 3, ri_i = k & 1;
+    const int d = e / cin, cp = e - d * cin;
+    const uint32_t w = wb[((int64_t)(d * cout + c) * cin + cp) * 16 + sa * 4 + sb];
+    const uint16_t wr = (uint16_t)(w & 0xffffu), wi = (uint16_t)(w >> 16);
+    v = ri_o == ri_i ? wr : (ri_o == 0 ? (uint16_t)(wi ^ 0x8000u) : wi);
+  }
+  wmx[t] = v;
+}
 
 template <int MT>
-__global__ void __launch_bounds__(128) k_net_layer_mx(Geo g, LinkV<float> U, const uint32_t* Wb, int cin, int cout,
+__global__ void __launch_bounds__(128) k_net_layer_mx(Geo g, LinkV<float> U, const uint4* wmx, int cin, int cout,
                                                       const float2* in, float2* out, int64_t cs) {
-  extern __shared__ float tl[];  // [8 cin][3 kNetTile]
+  extern __shared__ uint4 tl4[];  // [3 terms][3 kNetTile columns][kNetLd] BF16
+  uint16_t* tl = reinterpret_cast<uint16_t*>(tl4);
   constexpr int N = 3 * kNetTile;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int s0 = blockIdx.x * kNetTile;
-  const int K = 8 * cin;
+  const int KB = net_kb(cin), npair = 9 * cin;
+  // staging role of this thread: one site and one (d, c') pair of the slab
+  const int sl = threadIdx.x % kNetTile, el = threadIdx.x / kNetTile;
+  const int s = s0 + sl;
+  const bool live = s < g.V;
+  const int p = live && s >= g.Vh, i = live ? s - p * g.Vh : 0;
+  int x[4];
+  site_coords(g, p, i, x);
   f4v acc[MT][3];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int j = 0; j < 3; ++j) acc[mt][j] = f4v{0.f, 0.f, 0.f, 0.f};
-  for (int d = 0; d < 9; ++d) {
-    // transported inputs of the tile: one (site, input channel) pair per item
+  for (int sk = 0; sk < KB; ++sk) {
+    // A operands of the slab (latency hidden behind the staging below)
+    uint4 aop[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) aop[mt] = wmx[((int64_t)mt * KB + sk) * 64 + lane];
     __syncthreads();
-    for (int e = threadIdx.x; e < kNetTile * cin; e += blockDim.x) {
-      const int sl = e % kNetTile, cp = e / kNetTile;
-      const int s = s0 + sl;
+    {
+      const int e = 4 * sk + el;  // pair index
       cx<float> tr[12];
-      if (s < g.V) {
-        const int p = s >= g.Vh, i = s - p * g.Vh;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) tr[k] = {0.f, 0.f};
+      if (live && e < npair) {
+        const int d = e / cin, cp = e - d * cin;
         const float2* f = in + cp * cs;
         if (d == 0) {
 #pragma unroll
@@ -376,18 +348,16 @@ __global__ void __launch_bounds__(128) k_net_layer_mx(Geo g, LinkV<float> U, con
           }
         } else {
           const int mu = (d - 1) >> 1, dir = (d - 1) & 1;
-          int x[4];
-          site_coords(g, p, i, x);
           const int j = nbr_idx(g, x, mu, dir == 0 ? 1 : -1);
           cx<float> u[9], sp[12];
+          if (dir == 0) ld_link(U, p, mu, i, u);
+          else ld_link(U, 1 - p, mu, j, u);
           const float2* fb = f + (int64_t)(1 - p) * 12 * g.Vh + j;
 #pragma unroll
           for (int k = 0; k < 12; ++k) {
             float2 v = fb[(int64_t)k * g.Vh];
             sp[k] = {v.x, v.y};
           }
-          if (dir == 0) ld_link(U, p, mu, i, u);
-          else ld_link(U, 1 - p, mu, j, u);
 #pragma unroll
           for (int sb = 0; sb < 4; ++sb)
 #pragma unroll
@@ -399,39 +369,51 @@ __global__ void __launch_bounds__(128) k_net_layer_mx(Geo g, LinkV<float> U, con
               tr[sb * 3 + a] = z;
             }
         }
-      } else {
-#pragma unroll
-        for (int k = 0; k < 12; ++k) tr[k] = {0.f, 0.f};
       }
+      // exact three-term BF16 split by truncation, 8 consecutive k (sb, re/im)
+      // per column: hi = the top 8 significant bits of t, mid = the top 8 of
+      // t - hi (exact), lo = t - hi - mid (exact, at most 8 significant bits)
 #pragma unroll
-      for (int sb = 0; sb < 4; ++sb)
+      for (int a = 0; a < 3; ++a) {
+        uint32_t hw[3][4];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const int n = sl * 3 + a, k0 = cp * 8 + sb * 2;
-          tl[k0 * N + n] = tr[sb * 3 + a].re;
-          tl[(k0 + 1) * N + n] = tr[sb * 3 + a].im;
+        for (int sb = 0; sb < 4; ++sb) {
+          uint32_t t3[2][3];
+#pragma unroll
+          for (int ri = 0; ri < 2; ++ri) {
+            const float v = ri == 0 ? tr[sb * 3 + a].re : tr[sb * 3 + a].im;
+            const uint32_t h = __float_as_uint(v) & 0xffff0000u;
+            const float r1 = v - __uint_as_float(h);
+            const uint32_t m = __float_as_uint(r1) & 0xffff0000u;
+            t3[ri][0] = h;
+            t3[ri][1] = m;
+            t3[ri][2] = __float_as_uint(r1 - __uint_as_float(m));
+          }
+#pragma unroll
+          for (int tm = 0; tm < 3; ++tm) hw[tm][sb] = (t3[0][tm] >> 16) | (t3[1][tm] & 0xffff0000u);
         }
+        const int n = 3 * sl + a;
+#pragma unroll
+        for (int tm = 0; tm < 3; ++tm)
+          *reinterpret_cast<uint4*>(tl + ((int64_t)tm * N + n) * kNetLd + 8 * el) =
+              make_uint4(hw[tm][0], hw[tm][1], hw[tm][2], hw[tm][3]);
+      }
     }
     __syncthreads();
-    // acc += A_d T_d over k in steps of 4
-    for (int kk = 0; kk < K; kk += 4) {
-      const int k = kk + (lane >> 4);
-      const int cp = k >> 3, sb = (k >> 1) & 3, ri_i = k & 1;
-      f4v bq[3];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) bq[j] = f4v{tl[k * N + (3 * wv + j) * 16 + (lane & 15)], 0.f, 0.f, 0.f};
+    for (int tm = 0; tm < 3; ++tm) {
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const int m = mt * 16 + (lane & 15);
-        const int c = m >> 3, sa = (m >> 1) & 3, ri_o = m & 1;
-        float av = 0.f;
-        if (c < cout) {
-          const uint32_t w = Wb[((int64_t)(d * cout + c) * cin + cp) * 16 + sa * 4 + sb];
-          const float wr = bf16_to_f((uint16_t)(w & 0xffffu)), wi = bf16_to_f((uint16_t)(w >> 16));
-          av = ri_o == ri_i ? wr : (ri_o == 0 ? -wi : wi);
+      for (int j = 0; j < 3; ++j) {
+        const int n = (3 * wv + j) * 16 + (lane & 15);
+        const uint4 bw = *reinterpret_cast<const uint4*>(tl + ((int64_t)tm * N + n) * kNetLd + 8 * (lane >> 4));
+        bf8v b;
+        __builtin_memcpy(&b, &bw, 16);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          bf8v av;
+          __builtin_memcpy(&av, &aop[mt], 16);
+          acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, acc[mt][j], 0, 0, 0);
         }
-#pragma unroll
-        for (int j = 0; j < 3; ++j) acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bq[j][0], acc[mt][j], 0, 0, 0);
       }
     }
   }
@@ -440,9 +422,9 @@ __global__ void __launch_bounds__(128) k_net_layer_mx(Geo g, LinkV<float> U, con
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     const int n = (3 * wv + j) * 16 + (lane & 15);
-    const int sl = n / 3, a = n - 3 * sl, s = s0 + sl;
-    if (s >= g.V) continue;
-    const int p = s >= g.Vh, i = s - p * g.Vh;
+    const int sl2 = n / 3, a = n - 3 * sl2, s2 = s0 + sl2;
+    if (s2 >= g.V) continue;
+    const int p2 = s2 >= g.Vh, i2 = s2 - p2 * g.Vh;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
@@ -450,7 +432,7 @@ __global__ void __launch_bounds__(128) k_net_layer_mx(Geo g, LinkV<float> U, con
         const int m = mt * 16 + 4 * (lane >> 4) + 2 * h;
         const int c = m >> 3, sa = (m >> 1) & 3;
         if (c < cout)
-          out[c * cs + (int64_t)p * 12 * g.Vh + (int64_t)(sa * 3 + a) * g.Vh + i] =
+          out[c * cs + (int64_t)p2 * 12 * g.Vh + (int64_t)(sa * 3 + a) * g.Vh + i2] =
               make_float2(acc[mt][j][2 * h], acc[mt][j][2 * h + 1]);
       }
     }
@@ -458,23 +440,26 @@ __global__ void __launch_bounds__(128) k_net_layer_mx(Geo g, LinkV<float> U, con
 }
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_net_layer(const Geo& g, const LinkV<float>& U, const uint32_t* Wb, int cin, int cout,
+hipError_t launch_net_layer(const Geo& g, const LinkV<float>& U, const uint16_t* wmx, int cin, int cout,
                             const float2* in, float2* out, int64_t cs, hipStream_t st) {
-  // matrix-core path (cout <= 16 -> at most 8 row tiles of 16)
-  const int mt = (8 * cout + 15) / 16;
+  if (cin < 1 || cout < 1 || cout > 16) return hipErrorInvalidValue;
   const dim3 grid((g.V + kNetTile - 1) / kNetTile), blk(128);
-  const size_t lds = (size_t)8 * cin * 3 * kNetTile * sizeof(float);
-  switch (mt) {
+  const size_t lds = (size_t)3 * 3 * kNetTile * kNetLd * sizeof(uint16_t);
+  const uint4* w = reinterpret_cast<const uint4*>(wmx);
+  switch (net_mt(cout)) {
 #define NET_MX(M) \
-  case M: hipLaunchKernelGGL((k_net_layer_mx<M>), grid, blk, lds, st, g, U, Wb, cin, cout, in, out, cs); break;
+  case M: hipLaunchKernelGGL((k_net_layer_mx<M>), grid, blk, lds, st, g, U, w, cin, cout, in, out, cs); break;
     NET_MX(1) NET_MX(2) NET_MX(3) NET_MX(4) NET_MX(5) NET_MX(6) NET_MX(7) NET_MX(8)
 #undef NET_MX
-    default: {
-      constexpr int CG = 4;
-      dim3 grid2((g.V + 127) / 128, (cout + CG - 1) / CG);
-      hipLaunchKernelGGL((k_net_layer<CG>), grid2, dim3(128), 0, st, g, U, Wb, cin, cout, in, out, cs);
-    }
   }
+  return hipGetLastError();
+}
+
+size_t net_wmx_elems(int cin, int cout) { return (size_t)net_mt(cout) * net_kb(cin) * 64 * 8; }
+
+hipError_t launch_net_wmx(const uint32_t* wb, int cin, int cout, uint16_t* wmx, hipStream_t st) {
+  const int64_t n = (int64_t)net_wmx_elems(cin, cout);
+  hipLaunchKernelGGL(k_net_wmx, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, wb, cin, cout, wmx);
   return hipGetLastError();
 }
 

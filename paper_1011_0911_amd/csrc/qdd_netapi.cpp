@@ -18,6 +18,13 @@ static int64_t layer_off(const qdd_ctx* x, int l) {
   for (int k = 0; k < l; ++k) o += layer_nw(x, k);
   return o;
 }
+// matrix-core operands of layer l, forward (adj = false) or backward (adjoint weights)
+static uint16_t* layer_wmx(const qdd_ctx* x, int l, bool adj) {
+  size_t o = 0;
+  for (int k = 0; k < l; ++k)
+    o += adj ? net_wmx_elems(x->cfg.net_ch[k + 1], x->cfg.net_ch[k]) : net_wmx_elems(x->cfg.net_ch[k], x->cfg.net_ch[k + 1]);
+  return x->ptr<uint16_t>(adj ? x->lo.net_wmxa : x->lo.net_wmx) + o;
+}
 static int net_maxch(const qdd_ctx* x) {
   int m = 1;
   for (int l = 0; l <= x->cfg.net_nl; ++l) m = std::max(m, x->cfg.net_ch[l]);
@@ -40,9 +47,8 @@ static qdd_status net_check(qdd_ctx* x, bool need_weights) {
 // forward: act[0] must hold the input; act[nl] receives the output
 static qdd_status net_forward_levels(qdd_ctx* x) {
   int64_t cs = (int64_t)24 * x->G.Vh;
-  const uint32_t* wb = x->ptr<uint32_t>(x->lo.net_wb);
   for (int l = 0; l < net_nl(x); ++l)
-    HCK(x, launch_net_layer(x->G, links32(x), wb + layer_off(x, l), x->cfg.net_ch[l], x->cfg.net_ch[l + 1],
+    HCK(x, launch_net_layer(x->G, links32(x), layer_wmx(x, l, false), x->cfg.net_ch[l], x->cfg.net_ch[l + 1],
                             net_level(x, l), net_level(x, l + 1), cs, x->st));
   return QDD_OK;
 }
@@ -52,9 +58,12 @@ static qdd_status net_refresh_weights(qdd_ctx* x) {
   int nw = (int)x->lo.net_nw;
   uint32_t *wb = x->ptr<uint32_t>(x->lo.net_wb), *wa = x->ptr<uint32_t>(x->lo.net_wadj);
   HCK(x, launch_net_to_bf16(x->ptr<float2>(x->lo.net_w), wb, nw, x->st));
-  for (int l = 0; l < net_nl(x); ++l)
-    HCK(x, launch_net_adjoint(wb + layer_off(x, l), x->cfg.net_ch[l], x->cfg.net_ch[l + 1], wa + layer_off(x, l),
-                              x->st));
+  for (int l = 0; l < net_nl(x); ++l) {
+    const int cin = x->cfg.net_ch[l], cout = x->cfg.net_ch[l + 1];
+    HCK(x, launch_net_adjoint(wb + layer_off(x, l), cin, cout, wa + layer_off(x, l), x->st));
+    HCK(x, launch_net_wmx(wb + layer_off(x, l), cin, cout, layer_wmx(x, l, false), x->st));
+    HCK(x, launch_net_wmx(wa + layer_off(x, l), cout, cin, layer_wmx(x, l, true), x->st));
+  }
   return QDD_OK;
 }
 
@@ -94,7 +103,6 @@ static qdd_status net_loss_grad_packed(qdd_ctx* x, int nb, const float2* r, cons
   if (!(Z > 0)) { x->fail("training pairs with zero error"); return QDD_EINVAL; }
   float2* grad = x->ptr<float2>(x->lo.net_grad);
   HCK(x, hipMemsetAsync(grad, 0, x->lo.net_nw * sizeof(float2), x->st));
-  const uint32_t* wa = x->ptr<uint32_t>(x->lo.net_wadj);
   double* lp = x->ptr<double>(x->lo.net_loss) + 256;
   const int nlb = 256;
   double total = 0;
@@ -112,7 +120,7 @@ static qdd_status net_loss_grad_packed(qdd_ctx* x, int nb, const float2* r, cons
       HCK(x, launch_net_wgrad(x->G, links32(x), cin, cout, net_level(x, l), g0, cs, x->ptr<float2>(x->lo.net_gpart),
                               kNetGradBlocks, grad + layer_off(x, l), x->st));
       if (l > 0) {
-        HCK(x, launch_net_layer(x->G, links32(x), wa + layer_off(x, l), cout, cin, g0, g1, cs, x->st));
+        HCK(x, launch_net_layer(x->G, links32(x), layer_wmx(x, l, true), cout, cin, g0, g1, cs, x->st));
         std::swap(g0, g1);
       }
     }

@@ -37,14 +37,19 @@ def net_ctx(Q, L, ch, seed, **kw):
     return make_ctx(Q, L, 0.5, 0.1355, 1.9, seed, **cfg)
 
 
-def test_net_forward_parity(Q, orc):
+# small channel counts (ragged row tiles, zero-padded k blocks) and the 1-12-12-1 network
+CHS = [CH, [1, 12, 12, 1]]
+
+
+@pytest.mark.parametrize("ch", CHS)
+def test_net_forward_parity(Q, orc, ch):
     L = (4, 4, 4, 8)
-    ctx, U = net_ctx(Q, L, CH, 601)
+    ctx, U = net_ctx(Q, L, ch, 601)
     W = bf16(S.random_weights(ctx.net_num_weights(), 602, 0.3))
     ctx.net_set_weights(W)
     x = S.gaussian_field(512, 603)
     out = to_np(ctx.net_forward(x))
-    ref = orc.net_forward(L, U, CH, W, x[None])[0]
+    ref = orc.net_forward(L, U, ch, W, x[None])[0]
     e = relerr(out, ref)
     print("forward err", e)
     assert e < 1e-5
@@ -67,15 +72,16 @@ def test_net_reproduces_wilson_operator(Q, orc):
     assert relerr(to_np(ctx.net_forward(psi)), orc.apply_D(L, U, A0, psi)) < 1e-6
 
 
-def test_net_loss_gradient_parity(Q, orc):
+@pytest.mark.parametrize("ch", CHS)
+def test_net_loss_gradient_parity(Q, orc, ch):
     L = (4, 4, 4, 8)
-    ctx, U = net_ctx(Q, L, CH, 606)
+    ctx, U = net_ctx(Q, L, ch, 606)
     W = bf16(S.random_weights(ctx.net_num_weights(), 607, 0.3))
     ctx.net_set_weights(W)
     r = S.gaussian_field(512, 608, nrhs=3)
     e = S.gaussian_field(512, 609, nrhs=3)
     loss, grad = ctx.net_loss_grad(r, e)
-    loss_o, grad_o = orc.net_loss_grad(L, U, CH, W, r, e)
+    loss_o, grad_o = orc.net_loss_grad(L, U, ch, W, r, e)
     eg = relerr(to_np(grad), grad_o)
     print("loss", loss, loss_o, "grad err", eg)
     assert abs(loss - loss_o) / loss_o < 1e-5 and eg < 1e-5
