@@ -179,10 +179,12 @@ void compute_layout(const qdd_geom* g, const qdd_config* c, Layout& Lo) {
     Lo.net_w = B.take(nw * 8);       // complex FP32 master weights
     Lo.net_wb = B.take(nw * 4);      // complex BF16 compute copy
     Lo.net_wadj = B.take(nw * 4);    // BF16 adjoint weights (backward pass)
-    size_t nmx = 0, nmxa = 0;        // matrix-core operand copies, forward and backward
+    // matrix-core operand copies, forward (the two gradient levels, 2 maxch
+    // channel fields, serve as scratch there) and backward (no scratch)
+    size_t nmx = 0, nmxa = 0;
     for (int l = 0; l < c->net_nl; ++l) {
-      nmx += net_wmx_elems(c->net_ch[l], c->net_ch[l + 1]);
-      nmxa += net_wmx_elems(c->net_ch[l + 1], c->net_ch[l]);
+      nmx += net_wmx_elems(c->net_ch[l], c->net_ch[l + 1], (int)(2 * maxch));
+      nmxa += net_wmx_elems(c->net_ch[l + 1], c->net_ch[l], 0);
     }
     Lo.net_wmx = B.take(nmx * 2);
     Lo.net_wmxa = B.take(nmxa * 2);

@@ -4,13 +4,16 @@
 
 namespace qdd {
 // one layer: out (cout channels, at most 16) = sum W (T_d in) ; channel stride cs
-// (elements); wmx: the layer's weights arranged by launch_net_wmx
+// (elements); wmx: the layer's weights arranged by launch_net_wmx with the same
+// scratch_ch.  scratch: scratch_ch channel fields the weights-first form of a
+// one-output-channel layer may use (it needs 9; with fewer it is not used)
 hipError_t launch_net_layer(const Geo& g, const LinkV<float>& U, const uint16_t* wmx, int cin, int cout,
-                            const float2* in, float2* out, int64_t cs, hipStream_t st);
+                            const float2* in, float2* out, int64_t cs, float2* scratch, int scratch_ch, hipStream_t st);
+bool net_weights_first(int cin, int cout, int scratch_ch);
 // BF16 matrix-core operands of a layer from its BF16 complex weights wb
-// (net_wmx_elems(cin, cout) 16-bit elements)
-size_t net_wmx_elems(int cin, int cout);
-hipError_t launch_net_wmx(const uint32_t* wb, int cin, int cout, uint16_t* wmx, hipStream_t st);
+// (net_wmx_elems 16-bit elements)
+size_t net_wmx_elems(int cin, int cout, int scratch_ch);
+hipError_t launch_net_wmx(const uint32_t* wb, int cin, int cout, int scratch_ch, uint16_t* wmx, hipStream_t st);
 // grad += dloss/dW of one layer from its input `in` and output gradient `gy`
 hipError_t launch_net_wgrad(const Geo& g, const LinkV<float>& U, int cin, int cout, const float2* in,
                             const float2* gy, int64_t cs, float2* part, int nwg, float2* grad, hipStream_t st);

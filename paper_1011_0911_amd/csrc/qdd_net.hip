@@ -280,12 +280,23 @@ constexpr int kNetLd = kNetKs + 8;     // LDS row stride of a column (BF16 eleme
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
-__host__ __device__ inline int net_mt(int cout) { return (8 * cout + 15) / 16; }
-__host__ __device__ inline int net_kb(int cin) { return (72 * cin + 31) / 32; }
+// Layer forms.  Transport first (the general one): k = (d, c', sb, re/im) over
+// nd = 9 transports, rows (c, sa, re/im).  Weights first, for a layer with one
+// output channel and several inputs: since W acts on spin and channel and T_d
+// on colour and position, out(x) = sum_d T_d z_d(x) with the site-local
+// z_d = sum_c' W[d][0][c'] in_c', so the GEMM takes only the untransported
+// inputs (nd = 1) and has the nine z_d as its output channels (cz = 9), and
+// k_net_gather then applies 8 transports per site instead of 8 per input
+// channel.
+__host__ __device__ inline int net_mt(int cz) { return (8 * cz + 15) / 16; }
+__host__ __device__ inline int net_kb(int cin, int nd) { return (8 * nd * cin + 31) / 32; }
+bool net_weights_first(int cin, int cout, int scratch_ch) { return cout == 1 && cin > 1 && scratch_ch >= 9; }
 
 // prearranged A operands of one layer: wmx[(mt * KB + kb) * 64 + lane][0..7]
-__global__ void k_net_wmx(const uint32_t* wb, int cin, int cout, uint16_t* wmx) {
-  const int MT = net_mt(cout), KB = net_kb(cin);
+// (wf: the weights-first form)
+__global__ void k_net_wmx(const uint32_t* wb, int cin, int cout, int wf, uint16_t* wmx) {
+  const int cz = wf ? 9 * cout : cout, nd = wf ? 1 : 9;
+  const int MT = net_mt(cz), KB = net_kb(cin, nd);
   const int64_t n = (int64_t)MT * KB * 64 * 8;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
@@ -293,11 +304,11 @@ __global__ void k_net_wmx(const uint32_t* wb, int cin, int cout, uint16_t* wmx) 
   const int64_t blk = t >> 9;
   const int kb = (int)(blk % KB), mt = (int)(blk / KB);
   const int m = 16 * mt + (lane & 15), k = 32 * kb + 8 * (lane >> 4) + i;
-  const int c = m >> 3, sa = (m >> 1) & 3, ri_o = m & 1;
+  const int ch = m >> 3, sa = (m >> 1) & 3, ri_o = m & 1;
   uint16_t v = 0;
-  if (c < cout && k < 72 * cin) {
+  if (ch < cz && k < 8 * nd * cin) {
     const int e = k >> 3, sb = (k >> 1) & 3, ri_i = k & 1;
-    const int d = e / cin, cp = e - d * cin;
+    const int d = wf ? ch / cout : e / cin, cp = wf ? e : e - d * cin, c = wf ? ch - d * cout : ch;
     const uint32_t w = wb[((int64_t)(d * cout + c) * cin + cp) * 16 + sa * 4 + sb];
     const uint16_t wr = (uint16_t)(w & 0xffffu), wi = (uint16_t)(w >> 16);
     v = ri_o == ri_i ? wr : (ri_o == 0 ? (uint16_t)(wi ^ 0x8000u) : wi);
@@ -305,15 +316,17 @@ __global__ void k_net_wmx(const uint32_t* wb, int cin, int cout, uint16_t* wmx) 
   wmx[t] = v;
 }
 
+// cz output channels (cout, or the 9 cout z_d of the weights-first form), nd
+// transports per input channel (9, or 1 for the weights-first form)
 template <int MT>
-__global__ void __launch_bounds__(128) k_net_layer_mx(Geo g, LinkV<float> U, const uint4* wmx, int cin, int cout,
-                                                      const float2* in, float2* out, int64_t cs) {
+__global__ void __launch_bounds__(128) k_net_layer_mx(Geo g, LinkV<float> U, const uint4* wmx, int cin, int cz,
+                                                      int nd, const float2* in, float2* out, int64_t cs) {
   extern __shared__ uint4 tl4[];  // [3 terms][3 kNetTile columns][kNetLd] BF16
   uint16_t* tl = reinterpret_cast<uint16_t*>(tl4);
   constexpr int N = 3 * kNetTile;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int s0 = blockIdx.x * kNetTile;
-  const int KB = net_kb(cin), npair = 9 * cin;
+  const int KB = net_kb(cin, nd), npair = nd * cin;
   // staging role of this thread: one site and one (d, c') pair of the slab
   const int sl = threadIdx.x % kNetTile, el = threadIdx.x / kNetTile;
   const int s = s0 + sl;
@@ -431,7 +444,7 @@ __global__ void __launch_bounds__(128) k_net_layer_mx(Geo g, LinkV<float> U, con
       for (int h = 0; h < 2; ++h) {
         const int m = mt * 16 + 4 * (lane >> 4) + 2 * h;
         const int c = m >> 3, sa = (m >> 1) & 3;
-        if (c < cout)
+        if (c < cz)
           out[c * cs + (int64_t)p2 * 12 * g.Vh + (int64_t)(sa * 3 + a) * g.Vh + i2] =
               make_float2(acc[mt][j][2 * h], acc[mt][j][2 * h + 1]);
       }
@@ -439,27 +452,78 @@ __global__ void __launch_bounds__(128) k_net_layer_mx(Geo g, LinkV<float> U, con
   }
 }
 
+// out_c(x) = z_{0,c}(x) + sum_{d=1..8} (T_d z_{d,c})(x), z channel d cout + c:
+// the transports of the weights-first form, one lane per site and channel
+__global__ void __launch_bounds__(256) k_net_gather(Geo g, LinkV<float> U, const float2* z, int cout, float2* out,
+                                                    int64_t cs) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (s >= g.V) return;
+  const int p = s >= g.Vh, i = s - p * g.Vh;
+  int x[4];
+  site_coords(g, p, i, x);
+  cx<float> acc[12];
+  {
+    const float2* f = z + (int64_t)c * cs + (int64_t)p * 12 * g.Vh + i;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {f[(int64_t)k * g.Vh].x, f[(int64_t)k * g.Vh].y};
+  }
+#pragma unroll 1
+  for (int d = 1; d < 9; ++d) {
+    const int mu = (d - 1) >> 1, dir = (d - 1) & 1;
+    const int j = nbr_idx(g, x, mu, dir == 0 ? 1 : -1);
+    cx<float> u[9], sp[12];
+    if (dir == 0) ld_link(U, p, mu, i, u);
+    else ld_link(U, 1 - p, mu, j, u);
+    const float2* f = z + (int64_t)(d * cout + c) * cs + (int64_t)(1 - p) * 12 * g.Vh + j;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) sp[k] = {f[(int64_t)k * g.Vh].x, f[(int64_t)k * g.Vh].y};
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cx<float> t = acc[sb * 3 + a];
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          t = dir == 0 ? fma_c(u[a * 3 + b], sp[sb * 3 + b], t) : fmac_c(u[b * 3 + a], sp[sb * 3 + b], t);
+        acc[sb * 3 + a] = t;
+      }
+  }
+  float2* o = out + (int64_t)c * cs + (int64_t)p * 12 * g.Vh + i;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) o[(int64_t)k * g.Vh] = make_float2(acc[k].re, acc[k].im);
+}
+
 // ------------------------------------------------------------------ launchers
 hipError_t launch_net_layer(const Geo& g, const LinkV<float>& U, const uint16_t* wmx, int cin, int cout,
-                            const float2* in, float2* out, int64_t cs, hipStream_t st) {
+                            const float2* in, float2* out, int64_t cs, float2* scratch, int scratch_ch, hipStream_t st) {
   if (cin < 1 || cout < 1 || cout > 16) return hipErrorInvalidValue;
+  const bool wf = net_weights_first(cin, cout, scratch_ch);
+  if (wf && !scratch) return hipErrorInvalidValue;
+  const int cz = wf ? 9 * cout : cout, nd = wf ? 1 : 9;
+  float2* dst = wf ? scratch : out;
   const dim3 grid((g.V + kNetTile - 1) / kNetTile), blk(128);
   const size_t lds = (size_t)3 * 3 * kNetTile * kNetLd * sizeof(uint16_t);
   const uint4* w = reinterpret_cast<const uint4*>(wmx);
-  switch (net_mt(cout)) {
+  switch (net_mt(cz)) {
 #define NET_MX(M) \
-  case M: hipLaunchKernelGGL((k_net_layer_mx<M>), grid, blk, lds, st, g, U, w, cin, cout, in, out, cs); break;
+  case M: hipLaunchKernelGGL((k_net_layer_mx<M>), grid, blk, lds, st, g, U, w, cin, cz, nd, in, dst, cs); break;
     NET_MX(1) NET_MX(2) NET_MX(3) NET_MX(4) NET_MX(5) NET_MX(6) NET_MX(7) NET_MX(8)
 #undef NET_MX
+    default: return hipErrorInvalidValue;
   }
+  if (wf) hipLaunchKernelGGL(k_net_gather, dim3((g.V + 255) / 256, cout), dim3(256), 0, st, g, U, scratch, cout, out, cs);
   return hipGetLastError();
 }
 
-size_t net_wmx_elems(int cin, int cout) { return (size_t)net_mt(cout) * net_kb(cin) * 64 * 8; }
+size_t net_wmx_elems(int cin, int cout, int scratch_ch) {
+  const bool wf = net_weights_first(cin, cout, scratch_ch);
+  return (size_t)net_mt(wf ? 9 * cout : cout) * net_kb(cin, wf ? 1 : 9) * 64 * 8;
+}
 
-hipError_t launch_net_wmx(const uint32_t* wb, int cin, int cout, uint16_t* wmx, hipStream_t st) {
-  const int64_t n = (int64_t)net_wmx_elems(cin, cout);
-  hipLaunchKernelGGL(k_net_wmx, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, wb, cin, cout, wmx);
+hipError_t launch_net_wmx(const uint32_t* wb, int cin, int cout, int scratch_ch, uint16_t* wmx, hipStream_t st) {
+  const int64_t n = (int64_t)net_wmx_elems(cin, cout, scratch_ch);
+  hipLaunchKernelGGL(k_net_wmx, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, wb, cin, cout,
+                     (int)net_weights_first(cin, cout, scratch_ch), wmx);
   return hipGetLastError();
 }
 

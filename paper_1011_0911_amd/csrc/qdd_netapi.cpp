@@ -18,17 +18,21 @@ static int64_t layer_off(const qdd_ctx* x, int l) {
   for (int k = 0; k < l; ++k) o += layer_nw(x, k);
   return o;
 }
-// matrix-core operands of layer l, forward (adj = false) or backward (adjoint weights)
-static uint16_t* layer_wmx(const qdd_ctx* x, int l, bool adj) {
-  size_t o = 0;
-  for (int k = 0; k < l; ++k)
-    o += adj ? net_wmx_elems(x->cfg.net_ch[k + 1], x->cfg.net_ch[k]) : net_wmx_elems(x->cfg.net_ch[k], x->cfg.net_ch[k + 1]);
-  return x->ptr<uint16_t>(adj ? x->lo.net_wmxa : x->lo.net_wmx) + o;
-}
 static int net_maxch(const qdd_ctx* x) {
   int m = 1;
   for (int l = 0; l <= x->cfg.net_nl; ++l) m = std::max(m, x->cfg.net_ch[l]);
   return m;
+}
+// scratch channel fields of the forward layers: the two gradient levels (free
+// during a forward pass); the backward layers run with none
+static int fwd_scratch_ch(const qdd_ctx* x) { return 2 * net_maxch(x); }
+// matrix-core operands of layer l, forward (adj = false) or backward (adjoint weights)
+static uint16_t* layer_wmx(const qdd_ctx* x, int l, bool adj) {
+  size_t o = 0;
+  for (int k = 0; k < l; ++k)
+    o += adj ? net_wmx_elems(x->cfg.net_ch[k + 1], x->cfg.net_ch[k], 0)
+             : net_wmx_elems(x->cfg.net_ch[k], x->cfg.net_ch[k + 1], fwd_scratch_ch(x));
+  return x->ptr<uint16_t>(adj ? x->lo.net_wmxa : x->lo.net_wmx) + o;
 }
 // activation level k (k = 0..nl), gradient buffers nl+1, nl+2
 static float2* net_level(const qdd_ctx* x, int k) {
@@ -49,7 +53,8 @@ static qdd_status net_forward_levels(qdd_ctx* x) {
   int64_t cs = (int64_t)24 * x->G.Vh;
   for (int l = 0; l < net_nl(x); ++l)
     HCK(x, launch_net_layer(x->G, links32(x), layer_wmx(x, l, false), x->cfg.net_ch[l], x->cfg.net_ch[l + 1],
-                            net_level(x, l), net_level(x, l + 1), cs, x->st));
+                            net_level(x, l), net_level(x, l + 1), cs, net_level(x, net_nl(x) + 1), fwd_scratch_ch(x),
+                            x->st));
   return QDD_OK;
 }
 
@@ -61,8 +66,8 @@ static qdd_status net_refresh_weights(qdd_ctx* x) {
   for (int l = 0; l < net_nl(x); ++l) {
     const int cin = x->cfg.net_ch[l], cout = x->cfg.net_ch[l + 1];
     HCK(x, launch_net_adjoint(wb + layer_off(x, l), cin, cout, wa + layer_off(x, l), x->st));
-    HCK(x, launch_net_wmx(wb + layer_off(x, l), cin, cout, layer_wmx(x, l, false), x->st));
-    HCK(x, launch_net_wmx(wa + layer_off(x, l), cout, cin, layer_wmx(x, l, true), x->st));
+    HCK(x, launch_net_wmx(wb + layer_off(x, l), cin, cout, fwd_scratch_ch(x), layer_wmx(x, l, false), x->st));
+    HCK(x, launch_net_wmx(wa + layer_off(x, l), cout, cin, 0, layer_wmx(x, l, true), x->st));
   }
   return QDD_OK;
 }
@@ -120,7 +125,7 @@ static qdd_status net_loss_grad_packed(qdd_ctx* x, int nb, const float2* r, cons
       HCK(x, launch_net_wgrad(x->G, links32(x), cin, cout, net_level(x, l), g0, cs, x->ptr<float2>(x->lo.net_gpart),
                               kNetGradBlocks, grad + layer_off(x, l), x->st));
       if (l > 0) {
-        HCK(x, launch_net_layer(x->G, links32(x), layer_wmx(x, l, true), cout, cin, g0, g1, cs, x->st));
+        HCK(x, launch_net_layer(x->G, links32(x), layer_wmx(x, l, true), cout, cin, g0, g1, cs, nullptr, 0, x->st));
         std::swap(g0, g1);
       }
     }
