@@ -168,11 +168,10 @@ void compute_layout(const qdd_geom* g, const qdd_config* c, Layout& Lo) {
   // the staging area for training pairs
   Lo.net_nw = 0;
   if (c->use_net) {
-    size_t nw = 0, maxch = 1, maxl = 0;
+    size_t nw = 0, maxch = 1;
     for (int l = 0; l < c->net_nl; ++l) {
       size_t k = (size_t)9 * c->net_ch[l] * c->net_ch[l + 1] * 16;
       nw += k;
-      maxl = std::max(maxl, k);
       maxch = std::max<size_t>(maxch, c->net_ch[l + 1]);
     }
     Lo.net_nw = nw;
@@ -191,7 +190,11 @@ void compute_layout(const qdd_geom* g, const qdd_config* c, Layout& Lo) {
     Lo.net_act = B.take((size_t)(c->net_nl + 3) * maxch * 24 * Vh * 8);
     Lo.net_grad = B.take(nw * 8);
     Lo.net_adam = B.take(nw * 16);
-    Lo.net_gpart = B.take((size_t)kNetGradBlocks * maxl * 8);
+    size_t gpart = 0;  // weight-gradient partial products (floats), the largest layer's need
+    for (int l = 0; l < c->net_nl; ++l)
+      gpart = std::max(gpart, net_wgrad_part_floats(V, c->net_ch[l], c->net_ch[l + 1]));
+    Lo.net_gpart_floats = gpart;
+    Lo.net_gpart = B.take(gpart * 4);
     Lo.net_loss = B.take(4096 * 8);
     Lo.net_tmp = B.take((size_t)nr * 24 * Vh * 8);
     Lo.net_pairs_bytes = (size_t)2 * 8 * 24 * Vh * 8;

@@ -14,7 +14,6 @@ constexpr int kSapMaxSites = 256;  // sites per Schwarz block (one workgroup)
 constexpr int kMaxNs = 64;         // deflation vectors
 constexpr int kMaxNetCh = 16;      // network channels
 constexpr int kCoarseKv = 16;      // Krylov vectors of the little-operator GCR
-constexpr int kNetGradBlocks = 256;
 
 // byte offsets of every buffer inside the caller's workspace
 struct Layout {
@@ -27,7 +26,7 @@ struct Layout {
   size_t dfl_W, dfl_W32, dfl_A, dfl_Ainv, dfl_cvec, dfl_init, dfl_cr, dfl_t;
   size_t cpart, ccoef, crn2, calpha, cbinv, cactive;
   size_t net_nw, net_w, net_wb, net_wadj, net_wmx, net_wmxa, net_act, net_grad, net_adam, net_gpart, net_loss, net_tmp;
-  size_t net_pairs, net_pairs_bytes;
+  size_t net_pairs, net_pairs_bytes, net_gpart_floats;
   size_t part, coef, ahist, bhist, binv, chist, rn2, alpha, active, scal;
   size_t total;
 };

@@ -14,9 +14,13 @@ bool net_weights_first(int cin, int cout, int scratch_ch);
 // (net_wmx_elems 16-bit elements)
 size_t net_wmx_elems(int cin, int cout, int scratch_ch);
 hipError_t launch_net_wmx(const uint32_t* wb, int cin, int cout, int scratch_ch, uint16_t* wmx, hipStream_t st);
-// grad += dloss/dW of one layer from its input `in` and output gradient `gy`
+// grad += dloss/dW of one layer from its input `in` and output gradient `gy`;
+// part: partial-product scratch of part_floats floats, at least
+// net_wgrad_part_floats(V, cin, cout)
+size_t net_wgrad_part_floats(int64_t V, int cin, int cout);
 hipError_t launch_net_wgrad(const Geo& g, const LinkV<float>& U, int cin, int cout, const float2* in,
-                            const float2* gy, int64_t cs, float2* part, int nwg, float2* grad, hipStream_t st);
+                            const float2* gy, int64_t cs, float* part, size_t part_floats, float2* grad,
+                            hipStream_t st);
 hipError_t launch_net_to_bf16(const float2* w, uint32_t* wb, int n, hipStream_t st);
 hipError_t launch_net_adjoint(const uint32_t* wb, int cin, int cout, uint32_t* wa, hipStream_t st);
 hipError_t launch_net_out_grad(const float2* y, const float2* e, float escale, float invZ, float2* gy, int64_t n,

@@ -13,7 +13,11 @@
 #include "qdd_kernels.h"
 #include "qdd_net.h"
 
+#include <algorithm>
+
 namespace qdd {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 __device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 __device__ inline uint16_t f_to_bf16(float f) {
@@ -23,101 +27,174 @@ __device__ inline uint16_t f_to_bf16(float f) {
   return (uint16_t)(r >> 16);
 }
 
-// weight gradient partial sums: part[wg][((d*cout + c)*cin + c')*16 + s*4 + s'] =
-//   sum over the workgroup's sites and colours of gy_c[s] conj((T_d in_c')[s'])
-// Site chunks of the transported inputs and of gy are staged in LDS.
-constexpr int kWgSites = 4;
-// weights are split over blockIdx.y in ranges of 32 per lane (256 lanes)
-__global__ void __launch_bounds__(256) k_net_wgrad(Geo g, LinkV<float> U, int cin, int cout, const float2* in,
-                                                   const float2* gy, int64_t cs, int sites_per_wg, float2* part) {
-  const int w0 = blockIdx.y * 32 * 256;
-  extern __shared__ float2 lds[];
-  float2* tl = lds;                                   // [d][c'][site][12]
-  float2* gl = lds + 9 * cin * kWgSites * 12;         // [c][site][12]
-  const int nw = 9 * cout * cin * 16;
-  float2 acc[32];
+// Weight gradient on the matrix cores.  For each transport d,
+//   dl/dW[d][c][c'][sa][sb] = sum_{x, a} gy_c(x)[sa, a] conj((T_d in_c')(x)[sb, a])
+// is, in real form, the product P = G T over k = (site, colour): rows of G
+// m = (c, sa, re/im) (8 cout), columns of T n = (c', sb, re/im) (8 cin); then
+// Re = P[r][r] + P[i][i], Im = P[i][r] - P[r][i].  A workgroup (4 wavefronts)
+// takes one d and a range of sites, stages 16 sites at a time into LDS (G as
+// [m][k], the transported inputs T as [n][k]; the row stride of 52 words puts
+// the 64 lanes of an operand read on distinct banks) and accumulates its share of the
+// 16x16 output tiles with v_mfma_f32_16x16x4f32 (FP32 products, exact); the
+// per-workgroup partial products are summed in a fixed order in FP64
+// (k_net_wgrad_reduce), so the gradient is deterministic.
+constexpr int kWgTileSites = 16;
+constexpr int kWgLd = 52;  // LDS row stride (floats) of the [m][k] / [n][k] tiles, >= 3 kWgTileSites
+template <int TPW>
+__global__ void __launch_bounds__(256) k_net_wgrad_mx(Geo g, LinkV<float> U, int cin, int cout, const float2* in,
+                                                      const float2* gy, int64_t cs, int sites_per_wg, float* part) {
+  extern __shared__ float wl[];
+  const int M16 = 16 * ((8 * cout + 15) / 16), N16 = 16 * ((8 * cin + 15) / 16);
+  float* gl = wl;                  // [M16][kWgLd]: G[m][k]
+  float* tlw = wl + M16 * kWgLd;   // [N16][kWgLd]: T[n][k]
+  const int d = blockIdx.y;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int ntile = (M16 / 16) * (N16 / 16), ntn = N16 / 16;
+  f4v acc[TPW];
 #pragma unroll
-  for (int q = 0; q < 32; ++q) acc[q] = make_float2(0.f, 0.f);
-  int s_begin = blockIdx.x * sites_per_wg, s_end = min(g.V, s_begin + sites_per_wg);
-  for (int s0 = s_begin; s0 < s_end; s0 += kWgSites) {
-    int nsc = min(kWgSites, s_end - s0);
-    // stage transported inputs: one lane per (d, c', site, colour-spin row)
-    int ntr = 9 * cin * nsc;
-    for (int e = threadIdx.x; e < ntr; e += blockDim.x) {
-      int sl = e % nsc, rest = e / nsc;
-      int cp = rest % cin, d = rest / cin;
-      int s = s0 + sl;
-      int p = s >= g.Vh, i = s - p * g.Vh;
-      const float2* f = in + cp * cs;
-      float2* dst = tl + ((d * cin + cp) * kWgSites + sl) * 12;
+  for (int q = 0; q < TPW; ++q) acc[q] = f4v{0.f, 0.f, 0.f, 0.f};
+  const int s_begin = blockIdx.x * sites_per_wg, s_end = min(g.V, s_begin + sites_per_wg);
+  // staging roles: lane t < 16 cin stages the transported input (site t % 16,
+  // channel t / 16); every lane stages up to 12 output-gradient elements.  The
+  // loads of the next tile are issued before the matrix-core phase of the
+  // current one.
+  const bool has_t = (int)threadIdx.x < kWgTileSites * cin;
+  const int t_sl = threadIdx.x % kWgTileSites, t_cp = threadIdx.x / kWgTileSites;
+  const int ng = kWgTileSites * cout * 12;
+  float2 psp[12], pu[9], pg[12];
+  bool pval = false;
+  auto prefetch = [&](int s0) {
+    pval = false;
+    if (has_t && s0 + t_sl < s_end) {
+      const int s = s0 + t_sl;
+      const int p = s >= g.Vh, i = s - p * g.Vh;
+      const float2* f = in + t_cp * cs;
+      pval = true;
       if (d == 0) {
-        for (int k = 0; k < 12; ++k) dst[k] = f[(int64_t)p * 12 * g.Vh + (int64_t)k * g.Vh + i];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) psp[k] = f[(int64_t)p * 12 * g.Vh + (int64_t)k * g.Vh + i];
       } else {
         int x[4];
         site_coords(g, p, i, x);
-        int mu = (d - 1) >> 1, dir = (d - 1) & 1;
-        int j = nbr_idx(g, x, mu, dir == 0 ? 1 : -1);
-        cx<float> u[9];
-        if (dir == 0) ld_link(U, p, mu, i, u);
-        else ld_link(U, 1 - p, mu, j, u);
+        const int mu = (d - 1) >> 1, dir = (d - 1) & 1;
+        const int j = nbr_idx(g, x, mu, dir == 0 ? 1 : -1);
         const float2* fb = f + (int64_t)(1 - p) * 12 * g.Vh + j;
-        for (int sp = 0; sp < 4; ++sp)
-          for (int a = 0; a < 3; ++a) {
-            cx<float> z{0.f, 0.f};
-            for (int b = 0; b < 3; ++b) {
-              float2 v = fb[(int64_t)(sp * 3 + b) * g.Vh];
-              z = dir == 0 ? fma_c(u[a * 3 + b], cx<float>{v.x, v.y}, z) : fmac_c(u[b * 3 + a], cx<float>{v.x, v.y}, z);
-            }
-            dst[sp * 3 + a] = make_float2(z.re, z.im);
-          }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) psp[k] = fb[(int64_t)k * g.Vh];
+        const float2* ub = U.p + (int64_t)(((dir == 0 ? p : 1 - p) * 4 + mu) * 9) * U.n + (dir == 0 ? i : j);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) pu[k] = ub[(int64_t)k * U.n];
       }
     }
-    int ng = cout * nsc * 12;
-    for (int e = threadIdx.x; e < ng; e += blockDim.x) {
-      int k = e % 12, rest = e / 12;
-      int sl = rest % nsc, c = rest / nsc;
-      int s = s0 + sl;
-      int p = s >= g.Vh, i = s - p * g.Vh;
-      gl[(c * kWgSites + sl) * 12 + k] = gy[c * cs + (int64_t)p * 12 * g.Vh + (int64_t)k * g.Vh + i];
-    }
-    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 32; ++q) {
-      int w = w0 + threadIdx.x + q * blockDim.x;
-      if (w >= nw) continue;
-      int ss = w & 15, rest = w >> 4;
-      int sa = ss >> 2, sb = ss & 3;
-      int cp = rest % cin;
-      rest /= cin;
-      int c = rest % cout, d = rest / cout;
-      cx<float> z{acc[q].x, acc[q].y};
-      for (int sl = 0; sl < nsc; ++sl)
-        for (int a = 0; a < 3; ++a) {
-          float2 gv = gl[(c * kWgSites + sl) * 12 + sa * 3 + a];
-          float2 tv = tl[((d * cin + cp) * kWgSites + sl) * 12 + sb * 3 + a];
-          // gy * conj(t)
-          z = fmac_c(cx<float>{tv.x, tv.y}, cx<float>{gv.x, gv.y}, z);
+    for (int q = 0; q < 12; ++q) {
+      const int e = threadIdx.x + q * 256;
+      pg[q] = make_float2(0.f, 0.f);
+      if (e < ng) {
+        const int sl = e % kWgTileSites, rest = e / kWgTileSites;
+        const int kc = rest % 12, c = rest / 12, s = s0 + sl;
+        if (s < s_end) {
+          const int p = s >= g.Vh, i = s - p * g.Vh;
+          pg[q] = gy[c * cs + (int64_t)p * 12 * g.Vh + (int64_t)kc * g.Vh + i];
         }
-      acc[q] = make_float2(z.re, z.im);
+      }
     }
+  };
+  prefetch(s_begin);
+  for (int s0 = s_begin; s0 < s_end; s0 += kWgTileSites) {
     __syncthreads();
-  }
+    if (has_t) {
+      cx<float> tr[12];
 #pragma unroll
-  for (int q = 0; q < 32; ++q) {
-    int w = w0 + threadIdx.x + q * blockDim.x;
-    if (w < nw) part[(int64_t)blockIdx.x * nw + w] = acc[q];
+      for (int k = 0; k < 12; ++k) tr[k] = {0.f, 0.f};
+      if (pval && d == 0) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) tr[k] = {psp[k].x, psp[k].y};
+      } else if (pval) {
+        const int dir = (d - 1) & 1;
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            cx<float> z{0.f, 0.f};
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              const cx<float> sv{psp[sb * 3 + b].x, psp[sb * 3 + b].y};
+              z = dir == 0 ? fma_c(cx<float>{pu[a * 3 + b].x, pu[a * 3 + b].y}, sv, z)
+                           : fmac_c(cx<float>{pu[b * 3 + a].x, pu[b * 3 + a].y}, sv, z);
+            }
+            tr[sb * 3 + a] = z;
+          }
+      }
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          float* r = tlw + (t_cp * 8 + sb * 2) * kWgLd + 3 * t_sl + a;
+          r[0] = tr[sb * 3 + a].re;
+          r[kWgLd] = tr[sb * 3 + a].im;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      const int e = threadIdx.x + q * 256;
+      if (e < ng) {
+        const int sl = e % kWgTileSites, rest = e / kWgTileSites;
+        const int kc = rest % 12, c = rest / 12;
+        const int sa = kc / 3, a = kc - 3 * sa;
+        float* r = gl + (c * 8 + sa * 2) * kWgLd + 3 * sl + a;
+        r[0] = pg[q].x;
+        r[kWgLd] = pg[q].y;
+      }
+    }
+    if (s0 + kWgTileSites < s_end) prefetch(s0 + kWgTileSites);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int t = wv + 4 * q;
+      if (t >= ntile) break;
+      const int mt = t / ntn, nt = t - mt * ntn;
+      f4v c4 = acc[q];
+      const float* ga = gl + (16 * mt + (lane & 15)) * kWgLd + (lane >> 4);
+      const float* tb = tlw + (16 * nt + (lane & 15)) * kWgLd + (lane >> 4);
+#pragma unroll
+      for (int ks = 0; ks < 3 * kWgTileSites / 4; ++ks)
+        c4 = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[4 * ks], tb[4 * ks], c4, 0, 0, 0);
+      acc[q] = c4;
+    }
+  }
+  // partial product of this workgroup: part[(wg * 9 + d)][m][n]
+  float* pw = part + ((int64_t)blockIdx.x * 9 + d) * M16 * N16;
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int t = wv + 4 * q;
+    if (t >= ntile) break;
+    const int mt = t / ntn, nt = t - mt * ntn;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) pw[(16 * mt + 4 * (lane >> 4) + r) * N16 + 16 * nt + (lane & 15)] = acc[q][r];
   }
 }
 
-// grad[w] += sum over workgroups of part[wg][w] (fixed order: deterministic)
-__global__ void k_net_wgrad_reduce(const float2* part, int nwg, int nw, float2* grad) {
-  int w = blockIdx.x * blockDim.x + threadIdx.x;
+// grad[w] += sum over workgroups (fixed order, FP64) of the complex combination
+// of the real partial products
+__global__ void k_net_wgrad_reduce(const float* part, int nwg, int cin, int cout, float2* grad) {
+  const int nw = 9 * cout * cin * 16;
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= nw) return;
+  const int M16 = 16 * ((8 * cout + 15) / 16), N16 = 16 * ((8 * cin + 15) / 16);
+  const int ss = w & 15, sa = ss >> 2, sb = ss & 3;
+  int rest = w >> 4;
+  const int cp = rest % cin;
+  rest /= cin;
+  const int c = rest % cout, d = rest / cout;
+  const int mr = c * 8 + sa * 2, nr = cp * 8 + sb * 2;
   double re = 0, im = 0;
   for (int b = 0; b < nwg; ++b) {
-    float2 v = part[(int64_t)b * nw + w];
-    re += v.x;
-    im += v.y;
+    const float* P = part + ((int64_t)b * 9 + d) * M16 * N16;
+    const float rr = P[mr * N16 + nr], ri = P[mr * N16 + nr + 1];
+    const float ir = P[(mr + 1) * N16 + nr], ii = P[(mr + 1) * N16 + nr + 1];
+    re += (double)rr + (double)ii;
+    im += (double)ir - (double)ri;
   }
   grad[w] = make_float2(grad[w].x + (float)re, grad[w].y + (float)im);
 }
@@ -277,7 +354,6 @@ __global__ void k_net_adam(float2* w, const float2* g, float4* mv, int n, float 
 constexpr int kNetTile = 32;
 constexpr int kNetKs = 32;             // k rows per slab (one MFMA depth): 4 (d, c') pairs x 4 spins x re/im
 constexpr int kNetLd = kNetKs + 8;     // LDS row stride of a column (BF16 elements)
-typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 // Layer forms.  Transport first (the general one): k = (d, c', sb, re/im) over
@@ -339,6 +415,32 @@ __global__ void __launch_bounds__(128) k_net_layer_mx(Geo g, LinkV<float> U, con
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int j = 0; j < 3; ++j) acc[mt][j] = f4v{0.f, 0.f, 0.f, 0.f};
+  // operands of this lane's staging item (the input spinor, at the neighbour
+  // for a transport, and the link), loaded one slab ahead so that the loads
+  // are in flight during the matrix-core phase of the current slab
+  float2 psp[12], pu[9];
+  int pd = -1;  // transport of the loaded item (-1: none, zero column)
+  auto prefetch = [&](int e) {
+    pd = -1;
+    if (!(live && e < npair)) return;
+    const int d = e / cin, cp = e - d * cin;
+    const float2* f = in + cp * cs;
+    pd = d;
+    if (d == 0) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) psp[k] = f[(int64_t)p * 12 * g.Vh + (int64_t)k * g.Vh + i];
+    } else {
+      const int mu = (d - 1) >> 1, dir = (d - 1) & 1;
+      const int j = nbr_idx(g, x, mu, dir == 0 ? 1 : -1);
+      const float2* fb = f + (int64_t)(1 - p) * 12 * g.Vh + j;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) psp[k] = fb[(int64_t)k * g.Vh];
+      const float2* ub = U.p + (int64_t)(((dir == 0 ? p : 1 - p) * 4 + mu) * 9) * U.n + (dir == 0 ? i : j);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) pu[k] = ub[(int64_t)k * U.n];
+    }
+  };
+  prefetch(el);
   for (int sk = 0; sk < KB; ++sk) {
     // A operands of the slab (latency hidden behind the staging below)
     uint4 aop[MT];
@@ -346,43 +448,29 @@ __global__ void __launch_bounds__(128) k_net_layer_mx(Geo g, LinkV<float> U, con
     for (int mt = 0; mt < MT; ++mt) aop[mt] = wmx[((int64_t)mt * KB + sk) * 64 + lane];
     __syncthreads();
     {
-      const int e = 4 * sk + el;  // pair index
       cx<float> tr[12];
 #pragma unroll
       for (int k = 0; k < 12; ++k) tr[k] = {0.f, 0.f};
-      if (live && e < npair) {
-        const int d = e / cin, cp = e - d * cin;
-        const float2* f = in + cp * cs;
-        if (d == 0) {
+      if (pd == 0) {
 #pragma unroll
-          for (int k = 0; k < 12; ++k) {
-            float2 v = f[(int64_t)p * 12 * g.Vh + (int64_t)k * g.Vh + i];
-            tr[k] = {v.x, v.y};
-          }
-        } else {
-          const int mu = (d - 1) >> 1, dir = (d - 1) & 1;
-          const int j = nbr_idx(g, x, mu, dir == 0 ? 1 : -1);
-          cx<float> u[9], sp[12];
-          if (dir == 0) ld_link(U, p, mu, i, u);
-          else ld_link(U, 1 - p, mu, j, u);
-          const float2* fb = f + (int64_t)(1 - p) * 12 * g.Vh + j;
+        for (int k = 0; k < 12; ++k) tr[k] = {psp[k].x, psp[k].y};
+      } else if (pd > 0) {
+        const int dir = (pd - 1) & 1;
 #pragma unroll
-          for (int k = 0; k < 12; ++k) {
-            float2 v = fb[(int64_t)k * g.Vh];
-            sp[k] = {v.x, v.y};
-          }
+        for (int sb = 0; sb < 4; ++sb)
 #pragma unroll
-          for (int sb = 0; sb < 4; ++sb)
+          for (int a = 0; a < 3; ++a) {
+            cx<float> z{0.f, 0.f};
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              cx<float> z{0.f, 0.f};
-#pragma unroll
-              for (int b = 0; b < 3; ++b)
-                z = dir == 0 ? fma_c(u[a * 3 + b], sp[sb * 3 + b], z) : fmac_c(u[b * 3 + a], sp[sb * 3 + b], z);
-              tr[sb * 3 + a] = z;
+            for (int b = 0; b < 3; ++b) {
+              const cx<float> sv{psp[sb * 3 + b].x, psp[sb * 3 + b].y};
+              z = dir == 0 ? fma_c(cx<float>{pu[a * 3 + b].x, pu[a * 3 + b].y}, sv, z)
+                           : fmac_c(cx<float>{pu[b * 3 + a].x, pu[b * 3 + a].y}, sv, z);
             }
-        }
+            tr[sb * 3 + a] = z;
+          }
       }
+      if (sk + 1 < KB) prefetch(4 * (sk + 1) + el);
       // exact three-term BF16 split by truncation, 8 consecutive k (sb, re/im)
       // per column: hi = the top 8 significant bits of t, mid = the top 8 of
       // t - hi (exact), lo = t - hi - mid (exact, at most 8 significant bits)
@@ -527,14 +615,34 @@ hipError_t launch_net_wmx(const uint32_t* wb, int cin, int cout, int scratch_ch,
   return hipGetLastError();
 }
 
+// workgroups over the sites of the weight-gradient kernel: at most 512, at
+// least 8 tiles of 16 sites each
+static int wgrad_groups(int64_t V) {
+  const int64_t tiles = (V + kWgTileSites - 1) / kWgTileSites;
+  return (int)std::min<int64_t>(512, std::max<int64_t>(1, tiles / 8));
+}
+size_t net_wgrad_part_floats(int64_t V, int cin, int cout) {
+  const int M16 = 16 * ((8 * cout + 15) / 16), N16 = 16 * ((8 * cin + 15) / 16);
+  return (size_t)wgrad_groups(V) * 9 * M16 * N16;
+}
+
 hipError_t launch_net_wgrad(const Geo& g, const LinkV<float>& U, int cin, int cout, const float2* in,
-                            const float2* gy, int64_t cs, float2* part, int nwg, float2* grad, hipStream_t st) {
-  int nw = 9 * cout * cin * 16;
-  int spw = (g.V + nwg - 1) / nwg;
-  size_t lds = (size_t)(9 * cin + cout) * kWgSites * 12 * sizeof(float2);
-  dim3 grid(nwg, (nw + 32 * 256 - 1) / (32 * 256));
-  hipLaunchKernelGGL(k_net_wgrad, grid, dim3(256), lds, st, g, U, cin, cout, in, gy, cs, spw, part);
-  hipLaunchKernelGGL(k_net_wgrad_reduce, dim3((nw + 255) / 256), dim3(256), 0, st, part, nwg, nw, grad);
+                            const float2* gy, int64_t cs, float* part, size_t part_floats, float2* grad,
+                            hipStream_t st) {
+  if (cin < 1 || cout < 1 || cin > 16 || cout > 16 || part_floats < net_wgrad_part_floats(g.V, cin, cout))
+    return hipErrorInvalidValue;
+  const int nw = 9 * cout * cin * 16;
+  const int M16 = 16 * ((8 * cout + 15) / 16), N16 = 16 * ((8 * cin + 15) / 16);
+  const int ntile = (M16 / 16) * (N16 / 16), tpw = (ntile + 3) / 4;
+  const int nwx = wgrad_groups(g.V);
+  const int spw = ((g.V + nwx - 1) / nwx + kWgTileSites - 1) / kWgTileSites * kWgTileSites;
+  const size_t lds = (size_t)(M16 + N16) * kWgLd * sizeof(float);
+  const dim3 grid(nwx, 9), blk(256);
+  if (tpw <= 2) hipLaunchKernelGGL((k_net_wgrad_mx<2>), grid, blk, lds, st, g, U, cin, cout, in, gy, cs, spw, part);
+  else if (tpw <= 4) hipLaunchKernelGGL((k_net_wgrad_mx<4>), grid, blk, lds, st, g, U, cin, cout, in, gy, cs, spw, part);
+  else if (tpw <= 9) hipLaunchKernelGGL((k_net_wgrad_mx<9>), grid, blk, lds, st, g, U, cin, cout, in, gy, cs, spw, part);
+  else hipLaunchKernelGGL((k_net_wgrad_mx<16>), grid, blk, lds, st, g, U, cin, cout, in, gy, cs, spw, part);
+  hipLaunchKernelGGL(k_net_wgrad_reduce, dim3((nw + 255) / 256), dim3(256), 0, st, part, nwx, cin, cout, grad);
   return hipGetLastError();
 }
 

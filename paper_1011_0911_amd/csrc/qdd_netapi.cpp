@@ -122,8 +122,8 @@ static qdd_status net_loss_grad_packed(qdd_ctx* x, int nb, const float2* r, cons
     HCK(x, hipMemcpyAsync(h.data(), lp, nlb * sizeof(double), hipMemcpyDeviceToHost, x->st));
     for (int l = nl - 1; l >= 0; --l) {
       int cin = x->cfg.net_ch[l], cout = x->cfg.net_ch[l + 1];
-      HCK(x, launch_net_wgrad(x->G, links32(x), cin, cout, net_level(x, l), g0, cs, x->ptr<float2>(x->lo.net_gpart),
-                              kNetGradBlocks, grad + layer_off(x, l), x->st));
+      HCK(x, launch_net_wgrad(x->G, links32(x), cin, cout, net_level(x, l), g0, cs, x->ptr<float>(x->lo.net_gpart),
+                              x->lo.net_gpart_floats, grad + layer_off(x, l), x->st));
       if (l > 0) {
         HCK(x, launch_net_layer(x->G, links32(x), layer_wmx(x, l, true), cout, cin, g0, g1, cs, nullptr, 0, x->st));
         std::swap(g0, g1);

@@ -34,8 +34,12 @@ template <>
 __device__ inline cx<double> cvt<double>(double2 e) { return {e.x, e.y}; }
 template <>
 __device__ inline cx<float> cvt<float>(float2 e) { return {e.x, e.y}; }
+// FP16 operands held in registers are converted where used: the opaque move
+// keeps the compiler from hoisting FP32 copies of all links and clover entries
+// out of the solver loops (which would not fit the register file)
 template <>
 __device__ inline cx<float> cvt<__half>(__half2 e) {
+  asm volatile("" : "+v"(e));
   float2 f = __half22float2(e);
   return {f.x, f.y};
 }

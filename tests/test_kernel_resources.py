@@ -22,6 +22,7 @@ HOT = [
     ("qdd_dirac.hip", r"k_dhat_staged<[^>]+, true>"),
     ("qdd_dirac.hip", r"k_dw<[^,]+, 1, true,"),
     ("qdd_net.hip", r"k_net_layer_mx<"),
+    ("qdd_net.hip", r"k_net_wgrad_mx<"),
     ("qdd_dfl.hip", r"k_block_orth"),
     ("qdd_dfl.hip", r"k_block_dots<"),
 ]
