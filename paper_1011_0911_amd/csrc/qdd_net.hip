@@ -341,20 +341,23 @@ __global__ void k_net_adam(float2* w, const float2* g, float4* mv, int n, float 
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation: the products are exact and
 // the result is as accurate as an FP32 product, at three BF16 matrix
 // operations per FP32 one of a quarter the depth.
-// A workgroup of 2 wavefronts takes kNetTile sites (3 kNetTile columns = 6
-// column tiles of 16) and walks K in slabs of one MFMA depth: every lane
-// computes one (site, d, c') transported input of the slab into LDS as the
-// three terms, [term][column][k] (k fastest: one 16-byte read per lane and
-// operand), and each wave runs the MFMAs of its 3 column tiles and all MT row
-// tiles.  The small slab (23 KB of LDS) leaves room for several workgroups per
-// compute unit, whose staging loads hide each other's latency.  The
+// A workgroup of 4 wavefronts takes kNetTile = 64 sites (192 columns = 12
+// column tiles of 16) and walks K in slabs of one MFMA depth: wavefront w
+// computes the transported input of the slab's (d, c') pair w for the 64 sites,
+// one per lane (wave-uniform field and link bases, 32-bit lane offsets), into
+// LDS as the three terms, [term][column][k] (k fastest: one 16-byte read per
+// lane and operand), and runs the MFMAs of its 3 column tiles and all MT row
+// tiles.  The slab takes 46 KB of LDS, leaving room for more than one
+// workgroup per compute unit.  The
 // A operands come prearranged (k_net_wmx) in the lane order of the
 // instruction: lane l holds A[l%16][8(l/16) .. 8(l/16)+7], B[8(l/16) ..][l%16],
 // and D rows 4(l/16)+r, column l%16 (measured with an in-bounds probe).
-constexpr int kNetTile = 32;
+constexpr int kNetTile = 64;
 constexpr int kNetKs = 32;             // k rows per slab (one MFMA depth): 4 (d, c') pairs x 4 spins x re/im
 constexpr int kNetLd = kNetKs + 8;     // LDS row stride of a column (BF16 elements)
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
 
 // Layer forms.  Transport first (the general one): k = (d, c', sb, re/im) over
 // nd = 9 transports, rows (c, sa, re/im).  Weights first, for a layer with one
@@ -395,19 +398,24 @@ __global__ void k_net_wmx(const uint32_t* wb, int cin, int cout, int wf, uint16_
 // cz output channels (cout, or the 9 cout z_d of the weights-first form), nd
 // transports per input channel (9, or 1 for the weights-first form)
 template <int MT>
-__global__ void __launch_bounds__(128) k_net_layer_mx(Geo g, LinkV<float> U, const uint4* wmx, int cin, int cz,
+__global__ void __launch_bounds__(256) k_net_layer_mx(Geo g, LinkV<float> U, const uint4* wmx, int cin, int cz,
                                                       int nd, const float2* in, float2* out, int64_t cs) {
   extern __shared__ uint4 tl4[];  // [3 terms][3 kNetTile columns][kNetLd] BF16
   uint16_t* tl = reinterpret_cast<uint16_t*>(tl4);
   constexpr int N = 3 * kNetTile;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // wv through readfirstlane: the compiler then knows that the pair, the
+  // transport direction and the field bases derived from it are uniform (scalar
+  // address arithmetic, uniform branches instead of selects)
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int s0 = blockIdx.x * kNetTile;
   const int KB = net_kb(cin, nd), npair = nd * cin;
-  // staging role of this thread: one site and one (d, c') pair of the slab
-  const int sl = threadIdx.x % kNetTile, el = threadIdx.x / kNetTile;
-  const int s = s0 + sl;
+  // staging role: wavefront wv stages the (d, c') pair wv of every slab for the
+  // tile's 64 sites, one per lane; the pair, the parity of the tile (the tiles
+  // never straddle the parity boundary, Vh being a multiple of kNetTile) and
+  // so the field and link bases are uniform across the wavefront
+  const int s = s0 + lane;
   const bool live = s < g.V;
-  const int p = live && s >= g.Vh, i = live ? s - p * g.Vh : 0;
+  const int p = s0 >= g.Vh, i = live ? s - p * g.Vh : 0;
   int x[4];
   site_coords(g, p, i, x);
   f4v acc[MT][3];
@@ -420,27 +428,31 @@ __global__ void __launch_bounds__(128) k_net_layer_mx(Geo g, LinkV<float> U, con
   // are in flight during the matrix-core phase of the current slab
   float2 psp[12], pu[9];
   int pd = -1;  // transport of the loaded item (-1: none, zero column)
+  // (lanes past the end of the lattice load site i = 0 of the parity, a valid
+  // address, and stage zeros: no divergent branch around the loads, so the
+  // bases stay scalar)
   auto prefetch = [&](int e) {
-    pd = -1;
-    if (!(live && e < npair)) return;
-    const int d = e / cin, cp = e - d * cin;
+    pd = e < npair ? e / cin : -1;
+    if (pd < 0) return;
+    const int cp = e - pd * cin;
     const float2* f = in + cp * cs;
-    pd = d;
-    if (d == 0) {
+    if (pd == 0) {
+      const float2* fb = f + (int64_t)p * 12 * g.Vh;
 #pragma unroll
-      for (int k = 0; k < 12; ++k) psp[k] = f[(int64_t)p * 12 * g.Vh + (int64_t)k * g.Vh + i];
+      for (int k = 0; k < 12; ++k) psp[k] = ld_off(fb + (int64_t)k * g.Vh, (uint32_t)i * 8u);
     } else {
-      const int mu = (d - 1) >> 1, dir = (d - 1) & 1;
+      const int mu = (pd - 1) >> 1, dir = (pd - 1) & 1;
       const int j = nbr_idx(g, x, mu, dir == 0 ? 1 : -1);
-      const float2* fb = f + (int64_t)(1 - p) * 12 * g.Vh + j;
+      const float2* fb = f + (int64_t)(1 - p) * 12 * g.Vh;
 #pragma unroll
-      for (int k = 0; k < 12; ++k) psp[k] = fb[(int64_t)k * g.Vh];
-      const float2* ub = U.p + (int64_t)(((dir == 0 ? p : 1 - p) * 4 + mu) * 9) * U.n + (dir == 0 ? i : j);
+      for (int k = 0; k < 12; ++k) psp[k] = ld_off(fb + (int64_t)k * g.Vh, (uint32_t)j * 8u);
+      const float2* ub = U.p + (int64_t)(((dir == 0 ? p : 1 - p) * 4 + mu) * 9) * U.n;
+      const uint32_t uo = (uint32_t)(dir == 0 ? i : j) * 8u;
 #pragma unroll
-      for (int k = 0; k < 9; ++k) pu[k] = ub[(int64_t)k * U.n];
+      for (int k = 0; k < 9; ++k) pu[k] = ld_off(ub + (int64_t)k * U.n, uo);
     }
   };
-  prefetch(el);
+  prefetch(wv);
   for (int sk = 0; sk < KB; ++sk) {
     // A operands of the slab (latency hidden behind the staging below)
     uint4 aop[MT];
@@ -451,52 +463,57 @@ __global__ void __launch_bounds__(128) k_net_layer_mx(Geo g, LinkV<float> U, con
       cx<float> tr[12];
 #pragma unroll
       for (int k = 0; k < 12; ++k) tr[k] = {0.f, 0.f};
-      if (pd == 0) {
+      if (live && pd == 0) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) tr[k] = {psp[k].x, psp[k].y};
-      } else if (pd > 0) {
-        const int dir = (pd - 1) & 1;
+      } else if (live && ((pd - 1) & 1) == 0) {  // forward transport U psi(x + mu)
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb)
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             cx<float> z{0.f, 0.f};
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-              const cx<float> sv{psp[sb * 3 + b].x, psp[sb * 3 + b].y};
-              z = dir == 0 ? fma_c(cx<float>{pu[a * 3 + b].x, pu[a * 3 + b].y}, sv, z)
-                           : fmac_c(cx<float>{pu[b * 3 + a].x, pu[b * 3 + a].y}, sv, z);
-            }
+            for (int b = 0; b < 3; ++b)
+              z = fma_c(cx<float>{pu[a * 3 + b].x, pu[a * 3 + b].y}, cx<float>{psp[sb * 3 + b].x, psp[sb * 3 + b].y}, z);
+            tr[sb * 3 + a] = z;
+          }
+      } else if (live && pd > 0) {  // backward transport U^dag psi(x - mu)
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            cx<float> z{0.f, 0.f};
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+              z = fmac_c(cx<float>{pu[b * 3 + a].x, pu[b * 3 + a].y}, cx<float>{psp[sb * 3 + b].x, psp[sb * 3 + b].y}, z);
             tr[sb * 3 + a] = z;
           }
       }
-      if (sk + 1 < KB) prefetch(4 * (sk + 1) + el);
-      // exact three-term BF16 split by truncation, 8 consecutive k (sb, re/im)
-      // per column: hi = the top 8 significant bits of t, mid = the top 8 of
-      // t - hi (exact), lo = t - hi - mid (exact, at most 8 significant bits)
+      if (sk + 1 < KB) prefetch(4 * (sk + 1) + wv);
+      // exact three-term BF16 split of each (re, im) pair, rounded to nearest
+      // by the packed conversion: hi = bf16(t), mid = bf16(t - hi) (exact
+      // difference), lo = t - hi - mid (exact, at most 8 significant bits);
+      // 8 consecutive k (sb, re/im) per column and term
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         uint32_t hw[3][4];
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb) {
-          uint32_t t3[2][3];
+          bf2v t3[3];
+          f2v v = {tr[sb * 3 + a].re, tr[sb * 3 + a].im};
 #pragma unroll
-          for (int ri = 0; ri < 2; ++ri) {
-            const float v = ri == 0 ? tr[sb * 3 + a].re : tr[sb * 3 + a].im;
-            const uint32_t h = __float_as_uint(v) & 0xffff0000u;
-            const float r1 = v - __uint_as_float(h);
-            const uint32_t m = __float_as_uint(r1) & 0xffff0000u;
-            t3[ri][0] = h;
-            t3[ri][1] = m;
-            t3[ri][2] = __float_as_uint(r1 - __uint_as_float(m));
+          for (int tm = 0; tm < 3; ++tm) {
+            t3[tm] = __builtin_convertvector(v, bf2v);
+            uint32_t w;
+            __builtin_memcpy(&w, &t3[tm], 4);
+            hw[tm][sb] = w;
+            if (tm < 2) v = v - f2v{__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u)};
           }
-#pragma unroll
-          for (int tm = 0; tm < 3; ++tm) hw[tm][sb] = (t3[0][tm] >> 16) | (t3[1][tm] & 0xffff0000u);
         }
-        const int n = 3 * sl + a;
+        const int n = 3 * lane + a;
 #pragma unroll
         for (int tm = 0; tm < 3; ++tm)
-          *reinterpret_cast<uint4*>(tl + ((int64_t)tm * N + n) * kNetLd + 8 * el) =
+          *reinterpret_cast<uint4*>(tl + ((int64_t)tm * N + n) * kNetLd + 8 * wv) =
               make_uint4(hw[tm][0], hw[tm][1], hw[tm][2], hw[tm][3]);
       }
     }
@@ -589,7 +606,8 @@ hipError_t launch_net_layer(const Geo& g, const LinkV<float>& U, const uint16_t*
   if (wf && !scratch) return hipErrorInvalidValue;
   const int cz = wf ? 9 * cout : cout, nd = wf ? 1 : 9;
   float2* dst = wf ? scratch : out;
-  const dim3 grid((g.V + kNetTile - 1) / kNetTile), blk(128);
+  if (g.Vh % kNetTile) return hipErrorInvalidValue;  // tiles must not straddle the parity boundary
+  const dim3 grid((g.V + kNetTile - 1) / kNetTile), blk(256);
   const size_t lds = (size_t)3 * 3 * kNetTile * kNetLd * sizeof(uint16_t);
   const uint4* w = reinterpret_cast<const uint4*>(wmx);
   switch (net_mt(cz)) {
