@@ -168,11 +168,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the solve timings")
-    ap.add_argument("--learned-pairs", type=int, default=64,
-                    help="training pairs for the learned-stage solve timing (0 skips it)")
+    ap.add_argument("--learned-pairs", type=int, default=512,
+                    help="training pairs of the learned-stage comparison (harvested from batched plain solves; "
+                         "0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only (no multi-GPU path); use --gpus 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only (no multi-GPU path); use --gpus 1"}))
         sys.exit(2)
 
     import numpy as np

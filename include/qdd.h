@@ -218,15 +218,17 @@ qdd_status qdd_net_loss_grad(qdd_ctx* ctx, int nb, const double* r, const double
 /* One Adam step (lr; beta 0.9, 0.999) on a mini-batch of nb pairs given as
  * packed FP32 full fields (as written by qdd_solve_harvest). */
 qdd_status qdd_net_train_step(qdd_ctx* ctx, int nb, const void* r, const void* e, float lr, double* loss);
-/* Solves one right-hand side like qdd_solve and records, at every outer
- * iteration, r_k and e_k = psi* - psi_k as packed FP32 full fields
- * (qdd_field_bytes(ctx, QDD_F32, 1, 0) bytes each, consecutive) into the
- * caller's buffers, up to max_pairs; *npairs gets the count.  e_pairs must hold
- * max_pairs FP64 fields (qdd_field_bytes(ctx, QDD_F64, 1, 0) each): the
- * iterates stay in FP64 until psi* is known; the FP32 errors are returned
- * packed at its front. */
-qdd_status qdd_solve_harvest(qdd_ctx* ctx, const double* eta, double* psi, qdd_solve_info* info, void* r_pairs,
-                             void* e_pairs, int max_pairs, int* npairs);
+/* Solves nrhs right-hand sides like qdd_solve and records, at every outer
+ * iteration and for every right-hand side still iterating, r_k and
+ * e_k = psi* - psi_k as packed FP32 full fields (qdd_field_bytes(ctx, QDD_F32,
+ * 1, 0) bytes each, consecutive) into the caller's buffers, up to max_pairs;
+ * *npairs gets the count and pair_rhs (host, max_pairs ints, optional) the
+ * right-hand side of each pair.  The iteration that converges is not recorded.
+ * e_pairs must hold max_pairs FP64 fields (qdd_field_bytes(ctx, QDD_F64, 1, 0)
+ * each): the iterates stay in FP64 until psi* is known; the FP32 errors are
+ * returned packed at its front. */
+qdd_status qdd_solve_harvest(qdd_ctx* ctx, int nrhs, const double* eta, double* psi, qdd_solve_info* info,
+                             void* r_pairs, void* e_pairs, int max_pairs, int* npairs, int* pair_rhs);
 
 /* Launch shape of a kernel family (kernel: 0 = Dhat, 1 = D; prec: qdd_prec):
  * block threads (64..256, multiple of 64); nr right-hand sides per lane (1, 2,

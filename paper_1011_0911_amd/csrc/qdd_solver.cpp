@@ -113,36 +113,47 @@ qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qd
       HCK(x, hipStreamSynchronize(st));
       tstage[3] += since(ta);
       // (the iteration that converges is not captured: its iterate is the solution, e = 0)
-      if (F.hv && nr == 1 && F.hv->n < F.hv->max && act[0] && std::sqrt(std::fabs(h2[0].x)) > tol * etan[0]) {
-        // capture r_k and psi_k = psi + sum_{j<=k} alpha_j phi_j (back-substitution over the steps so far)
+      // capture (r_k, psi_k) of every right-hand side still iterating, with
+      // psi_k = psi + sum_{j<=k} alpha_j phi_j (back-substitution over the steps so far)
+      if (F.hv && F.hv->n < F.hv->max) {
         Harvest& hv = *F.hv;
-        HCK(x, launch_scale_to_f<double2>(hv.r + (int64_t)hv.n * n, r, 1.0, n, st));
-        int m = k + 1;
-        HCK(x, hipMemcpyAsync(ah.data(), ahist, (size_t)m * kMaxKv * sizeof(double2), hipMemcpyDeviceToHost, st));
-        HCK(x, hipMemcpyAsync(bh.data(), bhist, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, st));
-        HCK(x, hipMemcpyAsync(chh.data(), chist, (size_t)m * sizeof(double2), hipMemcpyDeviceToHost, st));
-        HCK(x, hipStreamSynchronize(st));
-        std::fill(al.begin(), al.end(), double2{0.0, 0.0});
-        for (int j = m - 1; j >= 0; --j) {
-          double sr = chh[j].x, si = chh[j].y;
-          for (int l = j + 1; l < m; ++l) {
-            double2 a = ah[(size_t)l * kMaxKv + j], b = al[l];
-            sr -= a.x * b.x - a.y * b.y;
-            si -= a.x * b.y + a.y * b.x;
+        std::vector<int> cap;
+        for (int i = 0; i < nr && hv.n + (int)cap.size() < hv.max; ++i)
+          if (act[i] && std::sqrt(std::fabs(h2[i].x)) > tol * etan[i]) cap.push_back(i);
+        if (!cap.empty()) {
+          const int m = k + 1;
+          HCK(x, hipMemcpyAsync(ah.data(), ahist, (size_t)m * nr * kMaxKv * sizeof(double2), hipMemcpyDeviceToHost, st));
+          HCK(x, hipMemcpyAsync(bh.data(), bhist, (size_t)m * nr * sizeof(double), hipMemcpyDeviceToHost, st));
+          HCK(x, hipMemcpyAsync(chh.data(), chist, (size_t)m * nr * sizeof(double2), hipMemcpyDeviceToHost, st));
+          HCK(x, hipStreamSynchronize(st));
+          std::fill(al.begin(), al.end(), double2{0.0, 0.0});
+          for (int i : cap)
+            for (int j = m - 1; j >= 0; --j) {
+              double sr = chh[(size_t)j * nr + i].x, si = chh[(size_t)j * nr + i].y;
+              for (int l = j + 1; l < m; ++l) {
+                double2 a2 = ah[((size_t)l * nr + i) * kMaxKv + j], b2 = al[(size_t)i * kMaxKv + l];
+                sr -= a2.x * b2.x - a2.y * b2.y;
+                si -= a2.x * b2.y + a2.y * b2.x;
+              }
+              double bj = bh[(size_t)j * nr + i];
+              al[(size_t)i * kMaxKv + j] = bj > 0 ? double2{sr / bj, si / bj} : double2{0.0, 0.0};
+            }
+          HCK(x, hipMemcpyAsync(alpha, al.data(), (size_t)nr * kMaxKv * sizeof(double2), hipMemcpyHostToDevice, st));
+          for (int i : cap) {
+            HCK(x, launch_scale_to_f<double2>(hv.r + (int64_t)hv.n * n, r + (int64_t)i * n, 1.0, n, st));
+            double2* pk = (double2*)hv.e + (int64_t)hv.n * n;
+            HCK(x, hipMemcpyAsync(pk, psi + (int64_t)i * n, n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+            const double2* ai = alpha + (size_t)i * kMaxKv;
+            if (F.phi32)
+              HCK(x, launch_axpy_multi<float2>(pk, n, (const float2*)phi + (int64_t)i * n, lstride, n, m, ai, kMaxKv,
+                                               1.0, n, 1, nullptr, st));
+            else
+              HCK(x, launch_axpy_multi<double2>(pk, n, (const double2*)phi + (int64_t)i * n, lstride, n, m, ai,
+                                                kMaxKv, 1.0, n, 1, nullptr, st));
+            hv.rhs.push_back(i);
+            hv.n++;
           }
-          al[j] = bh[j] > 0 ? double2{sr / bh[j], si / bh[j]} : double2{0.0, 0.0};
         }
-        HCK(x, hipMemcpyAsync(alpha, al.data(), kMaxKv * sizeof(double2), hipMemcpyHostToDevice, st));
-        HCK(x, hipMemcpyAsync(t, psi, n * sizeof(double2), hipMemcpyDeviceToDevice, st));
-        if (F.phi32)
-          HCK(x, launch_axpy_multi<float2>(t, n, (const float2*)phi, lstride, n, m, alpha, kMaxKv, 1.0, n, 1,
-                                           nullptr, st));
-        else
-          HCK(x, launch_axpy_multi<double2>(t, n, (const double2*)phi, lstride, n, m, alpha, kMaxKv, 1.0, n, 1,
-                                            nullptr, st));
-        HCK(x, hipMemcpyAsync((double2*)hv.e + (int64_t)hv.n * n, t, n * sizeof(double2), hipMemcpyDeviceToDevice,
-                              st));
-        hv.n++;
       }
       ++total_it;
       bool changed = false, any2 = false;
@@ -217,10 +228,11 @@ qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qd
     if (nonfinite) break;
   }
   if (F.hv)
-    // e_j = psi* - psi_j in FP64, then packed as FP32 at the front of the buffer
-    // (slot j of the FP32 output only overlaps FP64 slots that are already consumed)
+    // e_j = psi*_{rhs(j)} - psi_j in FP64, then packed as FP32 at the front of
+    // the buffer (slot j of the FP32 output only overlaps FP64 slots that are
+    // already consumed)
     for (int j = 0; j < F.hv->n; ++j) {
-      HCK(x, launch_sub(t, psi, (const double2*)F.hv->e + (int64_t)j * n, n, n, 1, st));
+      HCK(x, launch_sub(t, psi + (int64_t)F.hv->rhs[j] * n, (const double2*)F.hv->e + (int64_t)j * n, n, n, 1, st));
       HCK(x, launch_scale_to_f<double2>((float2*)F.hv->e + (int64_t)j * n, t, 1.0, n, st));
     }
   double tot = since(t0);
@@ -308,8 +320,9 @@ extern "C" qdd_status qdd_solve(qdd_ctx* x, int nrhs, const double* eta_c, doubl
 // e_k = psi* - psi_k, both returned as packed FP32 full fields (training data of
 // the network stage).  The e buffer needs FP64-sized slots: the iterates are kept
 // in FP64 until psi* is known, so that the small errors keep their precision.
-extern "C" qdd_status qdd_solve_harvest(qdd_ctx* x, const double* eta_c, double* psi_c, qdd_solve_info* info,
-                                        void* r_pairs, void* e_pairs, int max_pairs, int* npairs) {
+extern "C" qdd_status qdd_solve_harvest(qdd_ctx* x, int nrhs, const double* eta_c, double* psi_c,
+                                        qdd_solve_info* info, void* r_pairs, void* e_pairs, int max_pairs,
+                                        int* npairs, int* pair_rhs) {
   if (!x || !r_pairs || !e_pairs || max_pairs < 1 || !npairs) {
     if (x) x->fail("qdd_solve_harvest: invalid arguments");
     return QDD_EINVAL;
@@ -319,9 +332,11 @@ extern "C" qdd_status qdd_solve_harvest(qdd_ctx* x, const double* eta_c, double*
   hv.e = e_pairs;
   hv.max = max_pairs;
   x->harvest = &hv;
-  qdd_status s = qdd_solve(x, 1, eta_c, psi_c, info);
+  qdd_status s = qdd_solve(x, nrhs, eta_c, psi_c, info);
   x->harvest = nullptr;
   *npairs = hv.n;
+  if (pair_rhs)
+    for (int j = 0; j < hv.n; ++j) pair_rhs[j] = hv.rhs[j];
   return s;
 }
 

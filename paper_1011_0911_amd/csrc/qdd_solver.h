@@ -2,13 +2,16 @@
 #pragma once
 #include "qdd_api_internal.h"
 #include <functional>
+#include <vector>
 
-// optional capture of (residual, iterate) pairs at every iteration (one rhs);
-// after the solve the iterates are turned into errors e_k = psi* - psi_k
+// optional capture of (residual, iterate) pairs at every iteration of every
+// right-hand side; after the solve the iterates are turned into errors
+// e_k = psi* - psi_k
 struct Harvest {
   float2* r = nullptr;  // packed FP32 full fields, one per pair
   void* e = nullptr;    // FP64-sized slots during the solve; FP32 errors packed at the front afterwards
   int max = 0, n = 0;
+  std::vector<int> rhs;  // right-hand side of each pair
 };
 
 struct FgcrOps {

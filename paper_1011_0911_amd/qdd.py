@@ -90,7 +90,7 @@ SIGNATURES = {
     "qdd_net_forward": (_i, [_vp, _vp, _vp]),
     "qdd_net_loss_grad": (_i, [_vp, _i, _vp, _vp, ctypes.POINTER(_d), _vp]),
     "qdd_net_train_step": (_i, [_vp, _i, _vp, _vp, ctypes.c_float, ctypes.POINTER(_d)]),
-    "qdd_solve_harvest": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _i, ctypes.POINTER(_i)]),
+    "qdd_solve_harvest": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _i, ctypes.POINTER(_i), _vp]),
     "qdd_solve_dhat": (_i, [_vp, _i, _vp, _vp, _vp]),
     "qdd_set_launch": (_i, [_vp, _i, _i, _i, _i, _i, _i]),
     "qdd_get_launch": (_i, [_vp, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i),
@@ -360,15 +360,20 @@ class Context:
                 torch.empty(n * self.field_bytes(F64, 1, False), dtype=torch.uint8, device=self.device))
 
     def solve_harvest(self, eta, rbuf, ebuf, max_pairs, check=True):
+        """Solves the right-hand sides of eta (one field or a batch) and records the
+        (residual, error) pairs of their outer iterations.  Returns
+        (psi, infos, npairs, pair_rhs)."""
         c = self._c128(eta)
-        out = torch.empty((1, self.V, 4, 3), dtype=torch.complex128, device=self.device)
-        info = (SolveInfo * 1)()
+        m = c.numel() // (self.V * 12)
+        out = torch.empty((m, self.V, 4, 3), dtype=torch.complex128, device=self.device)
+        info = (SolveInfo * m)()
         npairs = ctypes.c_int()
-        st = lib().qdd_solve_harvest(self.h, _ptr(c), _ptr(out), info, _ptr(rbuf), _ptr(ebuf), int(max_pairs),
-                                     ctypes.byref(npairs))
+        rhs = (ctypes.c_int * int(max_pairs))()
+        st = lib().qdd_solve_harvest(self.h, m, _ptr(c), _ptr(out), info, _ptr(rbuf), _ptr(ebuf), int(max_pairs),
+                                     ctypes.byref(npairs), ctypes.cast(rhs, ctypes.c_void_p))
         if check:
             self._check(st)
-        return out, info[0].as_dict(), npairs.value
+        return out, [i.as_dict() for i in info], npairs.value, list(rhs[:npairs.value])
 
     def set_launch(self, kernel, prec, block, nr, xcd, sb=0):
         self._check(lib().qdd_set_launch(self.h, kernel, prec, block, nr, xcd, sb))

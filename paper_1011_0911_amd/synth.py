@@ -63,6 +63,18 @@ def gaussian_field(nsites: int, seed: int, nrhs: int | None = None) -> np.ndarra
     return np.ascontiguousarray(g[..., 0] + 1j * g[..., 1])
 
 
+def gaussian_field_device(nsites: int, seed: int, nrhs: int, device="cuda"):
+    """Gaussian spinor fields generated on the device (torch, complex128, shape
+    (nrhs, nsites, 4, 3)): Re and Im ~ N(0,1) from a generator seeded with
+    `seed`.  For bulk inputs whose values no CPU check needs (training sources)."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    g = torch.randn((nrhs, nsites, 4, 3, 2), dtype=torch.float64, device=device, generator=gen)
+    return torch.view_as_complex(g).contiguous()
+
+
 def random_gauge_transform(L, seed: int) -> np.ndarray:
     """One random SU(3) matrix per site (for covariance checks), shape (V,3,3)."""
     V = volume(L)

@@ -121,17 +121,20 @@ def run_solve_workload(wid: int, plain_rhs: int = 1, log=print, U=None):
 
 
 def run_learned(wid: int = 5, train_pairs: int | None = None, chunk_pairs: int = 64, batch: int = 4,
-                lr: float = 1e-3, epochs: int = 1, test_rhs: int | None = None, log=print):
+                lr: float = 1e-3, epochs: int = 1, test_rhs: int | None = None, harvest_rhs: int | None = None,
+                log=print):
     """Learned preconditioner workload: harvest (r_k, e_k) pairs from plain
-    deflated SAP-GCR solves on training sources, train the network on them in
-    streamed chunks, then solve fresh test sources with and without the network
-    stage (same deflation subspace).  Returns a dict."""
+    deflated SAP-GCR solves on training sources (harvest_rhs sources per batched
+    solve, default the test batch size), train the network on them in streamed
+    chunks, then solve fresh test sources with and without the network stage
+    (same deflation subspace).  Returns a dict."""
     import torch
 
     w = WORKLOADS[wid]
     L = w["L"]
     V = int(np.prod(L))
     ntest = test_rhs or w["nrhs"]
+    harvest_rhs = min(harvest_rhs or ntest, ntest)
     npairs = train_pairs or w["train_pairs"]
     out = {"workload": wid, "lattice": "x".join(map(str, L)), "train_pairs_target": npairs}
     U = S.random_su3_links(L, w["eps"], S.gauge_seed(wid))
@@ -153,13 +156,14 @@ def run_learned(wid: int = 5, train_pairs: int | None = None, chunk_pairs: int =
         n_chunk = 0
         t0 = time.time()
         while n_chunk < chunk_pairs and got + n_chunk < npairs:
-            eta = S.gaussian_field(V, 3000 + src)
-            src += 1
+            # a batch of plain solves; every iteration of every source gives a pair
+            eta = S.gaussian_field_device(V, 3000 + src, harvest_rhs)
+            src += harvest_rhs
             room = chunk_pairs - n_chunk
             rview = rb[n_chunk * fb32:]
-            # harvest into a staging slot, then move the FP32 pairs next to the previous ones
-            _, info, n = ctx.solve_harvest(eta, rview, eb[n_chunk * fb32:], min(room, npairs - got - n_chunk),
-                                           check=False)
+            # the FP32 pairs of earlier batches sit packed at the front of both buffers
+            _, info, n, _ = ctx.solve_harvest(eta, rview, eb[n_chunk * fb32:], min(room, npairs - got - n_chunk),
+                                              check=False)
             n_chunk += n
         torch.cuda.synchronize()
         t_h += time.time() - t0

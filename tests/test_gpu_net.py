@@ -97,8 +97,9 @@ def test_training_reduces_loss_and_harvest_pairs(Q, orc):
     ctx.net_set_weights(np.zeros(ctx.net_num_weights(), complex))
     rb, eb = ctx.pair_buffers(32)
     eta = S.gaussian_field(512, 612)
-    psi, info, n = ctx.solve_harvest(eta, rb, eb, 32)
-    assert info["converged"] and n == info["iters"] - 1 >= 2
+    psi, infos, n, prhs = ctx.solve_harvest(eta, rb, eb, 32)
+    info = infos[0]
+    assert info["converged"] and n == info["iters"] - 1 >= 2 and prhs == [0] * n
     # every harvested pair satisfies D e_k = r_k - r* exactly (e_k = psi* - psi_k and
     # r* = eta - D psi* the final residual); both fields are stored in FP32
     r_star = eta - orc.apply_D(L, U, A, to_np(psi)[0])
@@ -111,6 +112,29 @@ def test_training_reduces_loss_and_harvest_pairs(Q, orc):
     losses = [ctx.net_train_step(rb, eb, n, 1e-2) for _ in range(30)]
     print("losses", losses[0], losses[-1])
     assert losses[-1] < 0.9 * losses[0]
+
+
+def test_batched_harvest_pairs(Q, orc):
+    # three right-hand sides in one solve: every iteration of every source that is
+    # still iterating gives a pair, tagged with its source; each satisfies
+    # D e_k = r_k - r*_i (r*_i = eta_i - D psi*_i) to FP32 storage
+    L = (4, 4, 4, 8)
+    ctx, U = net_ctx(Q, L, CH, 618, dfl_nit=2, max_nrhs=3)
+    A, _ = orc.clover(L, U, 0.1355, 1.9)
+    ctx.dfl_build(S.gaussian_field(512, 619, nrhs=4))
+    ctx.net_set_weights(np.zeros(ctx.net_num_weights(), complex))
+    rb, eb = ctx.pair_buffers(48)
+    eta = S.gaussian_field(512, 620, nrhs=3)
+    psi, infos, n, prhs = ctx.solve_harvest(eta, rb, eb, 48)
+    assert all(i["converged"] for i in infos)
+    assert [prhs.count(r) for r in range(3)] == [i["iters"] - 1 for i in infos] and n == len(prhs)
+    ps = to_np(psi)
+    r_star = [eta[r] - orc.apply_D(L, U, A, ps[r]) for r in range(3)]
+    fb = ctx.field_bytes(Q.F32, 1, False)
+    for k in range(n):
+        rk = to_np(ctx.unpack(Q.F32, rb[k * fb:(k + 1) * fb], 1, False))[0]
+        ek = to_np(ctx.unpack(Q.F32, eb[k * fb:(k + 1) * fb], 1, False))[0]
+        assert relerr(orc.apply_D(L, U, A, ek), rk - r_star[prhs[k]]) < 1e-5, k
 
 
 @pytest.mark.parametrize("scale,expect_fallback", [(0.0, False), (3.0, True)])
