@@ -536,23 +536,35 @@ __global__ void __launch_bounds__(256) k_net_layer_mx(Geo g, LinkV<float> U, con
     }
   }
   // lane holds rows m = 16 mt + 4 (lane/16) + r: r = 0,1 are (re, im) of (c, sa),
-  // r = 2,3 those of (c, sa + 1); column n = 16 nt + lane%16 = (site, colour)
+  // r = 2,3 those of (c, sa + 1); column n = 16 nt + lane%16 = (site, colour).
+  // The results go out through LDS, eight channels at a time, as [c][component][site]
+  // so that every store covers 64 consecutive sites of one component plane.
+  float2* ob = reinterpret_cast<float2*>(tl4);
 #pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const int n = (3 * wv + j) * 16 + (lane & 15);
-    const int sl2 = n / 3, a = n - 3 * sl2, s2 = s0 + sl2;
-    if (s2 >= g.V) continue;
-    const int p2 = s2 >= g.Vh, i2 = s2 - p2 * g.Vh;
+  for (int half = 0; half < 2; ++half) {
+    if (8 * half >= cz) break;
+    __syncthreads();
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
+    for (int j = 0; j < 3; ++j) {
+      const int n = (3 * wv + j) * 16 + (lane & 15);
+      const int sl2 = n / 3, a = n - 3 * sl2;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int m = mt * 16 + 4 * (lane >> 4) + 2 * h;
-        const int c = m >> 3, sa = (m >> 1) & 3;
-        if (c < cz)
-          out[c * cs + (int64_t)p2 * 12 * g.Vh + (int64_t)(sa * 3 + a) * g.Vh + i2] =
-              make_float2(acc[mt][j][2 * h], acc[mt][j][2 * h + 1]);
+      for (int mt = 4 * half; mt < 4 * half + 4; ++mt) {
+        if (mt >= MT) break;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int m = mt * 16 + 4 * (lane >> 4) + 2 * h;
+          const int c = m >> 3, sa = (m >> 1) & 3;
+          ob[((c - 8 * half) * 12 + sa * 3 + a) * kNetTile + sl2] = make_float2(acc[mt][j][2 * h], acc[mt][j][2 * h + 1]);
+        }
       }
+    }
+    __syncthreads();
+    const int nc = min(8, cz - 8 * half);
+    for (int e = threadIdx.x; e < nc * 12 * kNetTile; e += blockDim.x) {
+      const int sl2 = e % kNetTile, kc = (e / kNetTile) % 12, c = 8 * half + e / (12 * kNetTile);
+      const int s2 = s0 + sl2;
+      if (s2 < g.V) out[c * cs + (int64_t)p * 12 * g.Vh + (int64_t)kc * g.Vh + (s2 - p * g.Vh)] = ob[e];
     }
   }
 }
@@ -608,7 +620,8 @@ hipError_t launch_net_layer(const Geo& g, const LinkV<float>& U, const uint16_t*
   float2* dst = wf ? scratch : out;
   if (g.Vh % kNetTile) return hipErrorInvalidValue;  // tiles must not straddle the parity boundary
   const dim3 grid((g.V + kNetTile - 1) / kNetTile), blk(256);
-  const size_t lds = (size_t)3 * 3 * kNetTile * kNetLd * sizeof(uint16_t);
+  const size_t lds = std::max((size_t)3 * 3 * kNetTile * kNetLd * sizeof(uint16_t),  // K slab
+                              (size_t)8 * 12 * kNetTile * sizeof(float2));           // output, 8 channels
   const uint4* w = reinterpret_cast<const uint4*>(wmx);
   switch (net_mt(cz)) {
 #define NET_MX(M) \
