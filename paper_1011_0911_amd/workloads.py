@@ -259,14 +259,54 @@ def run_multi(wid: int = 4, nkv: int = 8, log=print):
     return out
 
 
+def time_network(wid: int = 5, reps: int = 5, nb: int = 4, log=print):
+    """Timing of the learned stage's kernels on the workload lattice: one
+    forward pass of the network on a Gaussian field and one Adam training step
+    on nb random pairs (mean over reps, after one warm-up each).  Returns a dict."""
+    import torch
+
+    w = WORKLOADS[wid]
+    L = w["L"]
+    V = int(np.prod(L))
+    U = S.random_su3_links(L, w["eps"], S.gauge_seed(wid))
+    ctx, _ = make_context(L, w["eps"], w["kappa"], w["csw"], 0, U=U, **solver_config(w, 1, use_net=True))
+    ctx.net_set_weights(S.random_weights(ctx.net_num_weights(), 3000, 0.05))
+    x = S.gaussian_field_device(V, 5000, 1)[0]
+    ctx.net_forward(x)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(reps):
+        ctx.net_forward(x)
+    torch.cuda.synchronize()
+    fwd = (time.time() - t0) / reps
+    rb, eb = ctx.pair_buffers(nb)
+    fb32 = ctx.field_bytes(qdd.F32, 1, False)
+    for k in range(nb):  # FP32 pairs: random residuals and errors
+        for buf, seed in ((rb, 6000 + k), (eb, 7000 + k)):
+            buf[k * fb32:(k + 1) * fb32].view(torch.float32).copy_(
+                torch.view_as_real(S.gaussian_field_device(V, seed, 1)).flatten().to(torch.float32))
+    ctx.net_train_step(rb, eb, nb, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(reps):
+        ctx.net_train_step(rb, eb, nb, 1e-4)
+    torch.cuda.synchronize()
+    out = {"lattice": "x".join(map(str, L)), "channels": list(w.get("net_ch", (1, 12, 12, 1))),
+           "forward_ms": fwd * 1e3, "train_step_ms": (time.time() - t0) / reps * 1e3, "pairs_per_step": nb}
+    log(f"[net] {out}")
+    return out
+
+
 def main(argv=None):
     """Command line: python -m paper_1011_0911_amd.workloads WID [--pairs N]
-    runs one workload driver on cuda:0 and prints its result as one JSON line."""
+    runs one workload driver on cuda:0 and prints its result as one JSON line;
+    WID = net times the network forward pass and a training step on the
+    workload-5 lattice."""
     import argparse
     import json
 
     ap = argparse.ArgumentParser()
-    ap.add_argument("wid", type=int, choices=[2, 3, 4, 5])
+    ap.add_argument("wid", choices=["2", "3", "4", "5", "net"])
     ap.add_argument("--pairs", type=int, default=None, help="training pairs (workload 5)")
     ap.add_argument("--chunk", type=int, default=64, help="pairs per streamed training chunk (workload 5)")
     ap.add_argument("--epochs", type=int, default=1)
@@ -274,12 +314,14 @@ def main(argv=None):
                     help="right-hand sides timed with the plain solver (0: mixed solver only)")
     a = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)  # noqa: E731
-    if a.wid == 5:
+    if a.wid == "net":
+        r = time_network(5, log=log)
+    elif a.wid == "5":
         r = run_learned(5, train_pairs=a.pairs, chunk_pairs=a.chunk, epochs=a.epochs, log=log)
-    elif a.wid == 4:
+    elif a.wid == "4":
         r = run_multi(4, log=log)
     else:
-        r = run_solve_workload(a.wid, plain_rhs=a.plain_rhs, log=log)
+        r = run_solve_workload(int(a.wid), plain_rhs=a.plain_rhs, log=log)
     print(json.dumps(r, default=float), flush=True)
 
 
