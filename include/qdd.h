@@ -238,8 +238,8 @@ qdd_status qdd_solve_harvest(qdd_ctx* ctx, int nrhs, const double* eta, double* 
  * right-hand sides (tile LDS: 108 complex per site, at most 64 KiB); xcd: block
  * walk (0 linear; 1 every XCD takes a contiguous slab of the lattice; 2 slabs
  * whose tiles are walked time slice first, so time and x1 neighbours stay in
- * the XCD's L2; 3 slabs cut into sub-slabs of 4 time slices walked one x1
- * plane after the other); for Dhat with nr = 1 plus 4: streaming
+ * the XCD's L2; 3 slabs of L1/8 x1 planes through all time slices, walked
+ * one time slice after the other); for Dhat with nr = 1 plus 4: streaming
  * (non-temporal) loads of the links and clover blocks, plus 8: streaming load
  * of the site's own spinor and store of the output: data a pass touches once,
  * kept from evicting the neighbour spinors from the L2; sb sites per block

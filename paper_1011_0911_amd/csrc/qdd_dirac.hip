@@ -64,38 +64,35 @@ __device__ inline void hop_all(const Geo& g, const LinkV<S>& U, const FieldV<S>&
 // block b of nblk (of one parity) -> (site tile, rhs group).
 // order 0: linear.  order >= 1: hardware block ids go round-robin over the 8
 // XCDs, so every XCD is given a contiguous range of tiles (a slab of the
-// lattice whose neighbours share its L2).  order 2 additionally walks the tiles
-// of an XCD's slab of L0/8 time slices with the time slice fastest, then x1,
-// then the tile within the (x2, x3) row: the time and x1 neighbours of a site
-// are then touched within a few tiles, while the lexicographic walk reaches the
-// time neighbours only one whole time slice later, after they have left the L2.
+// lattice whose neighbours share its L2).  order 1: slabs of L0/8 time slices
+// walked lexicographically.  order 2: the same slabs walked with the time slice
+// fastest, then x1, then the tile within the (x2, x3) row: the time and x1
+// neighbours of a site are then touched within a few tiles, while the
+// lexicographic walk reaches the time neighbours only one whole time slice
+// later, after they have left the L2.  order 3: slabs of L1/8 x1 planes
+// (through all time slices), walked one time slice after the other, row by
+// row: a step (one time slice of the slab) touches its own spinors and those of
+// the two neighbouring steps, which stay in the XCD's L2; only the x1 faces of
+// the slab reach into the slabs of other XCDs.
 __device__ inline void map_block(const Geo& g, int b, int nblk, int nrg, int sb, int order, int& tile, int& rg) {
   if (order >= 1 && (nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
   rg = b % nrg;
   tile = b / nrg;
-  int row = g.L[2] * g.Lh3;  // sites of one (x0, x1) row of a parity
-  if (order >= 2 && (g.L[0] & 7) == 0 && row % sb == 0 && (nblk / nrg) * sb == g.Vh) {
-    int S = g.L[0] >> 3, tpr = row / sb, per_xcd = S * g.L[1] * tpr;
-    int k = tile / per_xcd, t = tile - k * per_xcd;
-    int s, x1, qd;
-    if (order == 2) {
-      s = t % S;
-      int rest = t / S;
-      x1 = rest % g.L[1];
-      qd = rest / g.L[1];
-    } else {
-      // order 3: sub-slabs of H time slices; inside one, x1 planes one after
-      // the other, each walked time slice by time slice, row by row: the
-      // spinors of three consecutive x1 planes of the sub-slab stay in the L2
-      const int H = (S % 4 == 0) ? 4 : S;
-      qd = t % tpr;
-      int rest = t / tpr;
-      const int si = rest % H;
-      rest /= H;
-      x1 = rest % g.L[1];
-      s = (rest / g.L[1]) * H + si;
-    }
+  const int row = g.L[2] * g.Lh3;  // sites of one (x0, x1) row of a parity
+  if (row % sb != 0 || (nblk / nrg) * sb != g.Vh) return;
+  const int tpr = row / sb;
+  if (order == 2 && (g.L[0] & 7) == 0) {
+    const int S = g.L[0] >> 3, per_xcd = S * g.L[1] * tpr;
+    const int k = tile / per_xcd, t = tile - k * per_xcd;
+    const int s = t % S, rest = t / S;
+    const int x1 = rest % g.L[1], qd = rest / g.L[1];
     tile = ((k * S + s) * g.L[1] + x1) * tpr + qd;
+  } else if (order == 3 && (g.L[1] & 7) == 0) {
+    const int X = g.L[1] >> 3, per_xcd = g.L[0] * X * tpr;
+    const int k = tile / per_xcd, t = tile - k * per_xcd;
+    const int qd = t % tpr, rest = t / tpr;
+    const int x1l = rest % X, x0 = rest / X;
+    tile = (x0 * g.L[1] + k * X + x1l) * tpr + qd;
   }
 }
 

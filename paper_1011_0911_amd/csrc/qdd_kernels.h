@@ -19,7 +19,7 @@ struct LaunchCfg {
   int nr = 1;       // right-hand sides per thread (register reuse of the links); 0 = staged
                     // variant: the tile's links and clover in LDS, each lane loops over rhs
   int xcd = 2;      // block walk: 0 linear, 1 XCD slabs, 2 XCD slabs walked time-slice first,
-                    // 3 XCD slabs in sub-slabs walked x1 plane by x1 plane; Dhat with nr 1:
+                    // 3 XCD slabs of L1/8 x1 planes walked time slice by time slice; Dhat with nr 1:
                     // + 4 streaming loads of links and clover, + 8 streaming load of the
                     // site's own spinor and store of the output (data a pass touches once)
   int sb = 0;       // sites per block (0 = block); block/sb lane groups take further rhs
