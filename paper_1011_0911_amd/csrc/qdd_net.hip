@@ -19,7 +19,6 @@ namespace qdd {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-__device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 __device__ inline uint16_t f_to_bf16(float f) {
   // round to nearest even (finite inputs)
   uint32_t u = __float_as_uint(f);
