@@ -96,8 +96,11 @@ typedef struct {
   int converged;    /* 1 if true relative residual <= tol */
   int fallbacks;    /* network stage rejected (plain SAP used instead) */
   double true_res;  /* |eta - D psi| / |eta| with FP64 D, at exit */
-  double t_ms[8];   /* stage times: 0 total, 1 preconditioner, 2 operator, 3 Gram-Schmidt,
-                       4 coarse correction, 5 network, 6 SAP, 7 residual restarts */
+  double t_ms[8];   /* host-side stage times: 0 total, 1 preconditioner, 2 operator,
+                       3 Gram-Schmidt, 4 coarse correction, 5 network, 6 SAP, 7 residual
+                       restarts; kernels run asynchronously, so a stage's GPU time is
+                       counted where the host next waits (the Gram-Schmidt reductions);
+                       only index 0 is a GPU-inclusive wall time */
 } qdd_solve_info;
 
 typedef struct qdd_ctx qdd_ctx;
