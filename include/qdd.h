@@ -221,7 +221,8 @@ qdd_status qdd_net_loss_grad(qdd_ctx* ctx, int nb, const double* r, const double
 /* One Adam step (lr; beta 0.9, 0.999) on a mini-batch of nb pairs given as
  * packed FP32 full fields (as written by qdd_solve_harvest). */
 qdd_status qdd_net_train_step(qdd_ctx* ctx, int nb, const void* r, const void* e, float lr, double* loss);
-/* Solves nrhs right-hand sides like qdd_solve and records, at every outer
+/* Solves nrhs right-hand sides like qdd_solve, but with the plain method (no
+ * network stage even where one is configured), and records, at every outer
  * iteration and for every right-hand side still iterating, r_k and
  * e_k = psi* - psi_k as packed FP32 full fields (qdd_field_bytes(ctx, QDD_F32,
  * 1, 0) bytes each, consecutive) into the caller's buffers, up to max_pairs;
