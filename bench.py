@@ -19,6 +19,8 @@ Byte model per even site and right-hand side batch of n (reals; each field
 element read or written once per pass, Hermitian 6x6 clover blocks as 36 reals):
   pass A: psi_e 24n + links 144 + A_o^{-1} 72 + t_o 24n
   pass B: t_o 24n + links 144 + psi_e 24n + A_e 72 + out 24n
+(links 96 instead of 144 where the tuned launch reads compressed links: two rows
+of each link, the third rebuilt)
 times the bytes per real (8 FP64, 4 FP32, 2 FP16) plus, for FP16, one FP32
 scale per site and spinor access (8 per rhs in pass A, 12 in pass B).
 """
@@ -40,15 +42,22 @@ GAUGE_SEED = 1003
 METRIC = "Dirac-apply TB/s (% HBM peak); solve s to rel-res 1e-10, learned vs plain"
 
 
-def bytes_per_site(prec: int, nrhs: int):
-    """(pass A, pass B) algorithmic bytes per even site for a batch of nrhs."""
+def bytes_per_site(prec: int, nrhs: int, compressed_links: bool = False):
+    """(pass A, pass B) algorithmic bytes per even site for a batch of nrhs;
+    with compressed links 8 x 12 reals of links per pass instead of 8 x 18."""
     b = {0: 8, 1: 4, 2: 2}[prec]
-    a = (24 * nrhs + 144 + 72 + 24 * nrhs) * b
-    bb = (24 * nrhs + 144 + 24 * nrhs + 72 + 24 * nrhs) * b
+    lk = 96 if compressed_links else 144
+    a = (24 * nrhs + lk + 72 + 24 * nrhs) * b
+    bb = (24 * nrhs + lk + 24 * nrhs + 72 + 24 * nrhs) * b
     if prec == 2:
         a += 8 * nrhs
         bb += 12 * nrhs
     return a, bb
+
+
+def compressed(launch) -> bool:
+    """Whether a Dhat launch shape (block, nr, xcd, sb) reads compressed links."""
+    return launch[1] == 1 and bool(launch[2] & 16)
 
 
 def measured_traffic(prec, nrhs, launch):
@@ -83,7 +92,7 @@ def one_rhs_rates(ctx, src1, cache, cache_path, reps=20):
         ctx.autotune(qdd.KERNEL_DHAT, prec, 1, fin, fout, reps=5, cache=cache)
         ctx.dw_hat_timed(prec, 1, fin, fout, 3)
         ms_a, ms_b = ctx.dw_hat_timed(prec, 1, fin, fout, reps)
-        a_b, b_b = bytes_per_site(prec, 1)
+        a_b, b_b = bytes_per_site(prec, 1, compressed(ctx.get_launch(qdd.KERNEL_DHAT, prec)))
         tbs = (a_b + b_b) * ctx.Vh / ((ms_a + ms_b) * 1e-3) / 1e12
         res[{0: "f64", 1: "f32", 2: "f16"}[prec]] = {"ms": round(ms_a + ms_b, 5), "TBs": round(tbs, 4),
                                                      "frac": round(tbs / PEAK_HBM_TBS, 4),
@@ -221,7 +230,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.time() - w0
     ms_step = e0.elapsed_time(e1) / args.steps
-    a_b, b_b = bytes_per_site(prec, nrhs)
+    a_b, b_b = bytes_per_site(prec, nrhs, compressed(launch))
     value = (a_b + b_b) * Vh / (ms_step * 1e-3) / 1e12
     # dominant kernel (pass B): per-launch durations from HIP events on the library stream
     ms_a, ms_b = ctx.dw_hat_timed(prec, nrhs, fin, fout, args.steps)

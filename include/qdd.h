@@ -246,7 +246,10 @@ qdd_status qdd_solve_harvest(qdd_ctx* ctx, int nrhs, const double* eta, double* 
  * one time slice after the other); for Dhat with nr = 1 plus 4: streaming
  * (non-temporal) loads of the links and clover blocks, plus 8: streaming load
  * of the site's own spinor and store of the output: data a pass touches once,
- * kept from evicting the neighbour spinors from the L2; sb sites per block
+ * kept from evicting the neighbour spinors from the L2; plus 16: compressed
+ * links, of which only the first two rows are read (12 of 18 reals) and the
+ * third is rebuilt as the conjugate cross product (an SU(3) identity; the time
+ * boundary sign of the stored link is put back); sb sites per block
  * (0 = block): the block/sb lane groups of a
  * block take further right-hand sides of the same sites.  QDD_EINVAL for shapes
  * outside these ranges. */

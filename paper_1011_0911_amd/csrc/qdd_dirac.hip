@@ -14,13 +14,16 @@
 
 namespace qdd {
 
-template <class S, int MU, int NR, bool O32, bool NT = false>
+// COMP: links read as their first two rows (the third rebuilt, with the time
+// boundary sign of the stored link)
+template <class S, int MU, int NR, bool O32, bool NT = false, bool COMP = false>
 __device__ inline void hop_dir(const Geo& g, const LinkV<S>& U, const FieldV<S>& in, int r0, int nr, int p, int i,
                                const int x[4], typename St<S>::T c0, cx<typename St<S>::T> (&acc)[NR][12]) {
   typedef typename St<S>::T T;
   cx<T> u[9], s[12], h[6], gg[6];
   int j = nbr_idx(g, x, MU, +1);
-  ld_link_u<S, NT>(U, p, MU, i, u);
+  if constexpr (COMP) ld_link_u12<S, NT>(U, p, MU, i, T(MU == 0 && x[0] == g.L[0] - 1 ? g.bc : 1), u);
+  else ld_link_u<S, NT>(U, p, MU, i, u);
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     if (q < nr) {
@@ -32,7 +35,8 @@ __device__ inline void hop_dir(const Geo& g, const LinkV<S>& U, const FieldV<S>&
   }
   __builtin_amdgcn_sched_barrier(0);
   j = nbr_idx(g, x, MU, -1);
-  ld_link_u<S, NT>(U, 1 - p, MU, j, u);
+  if constexpr (COMP) ld_link_u12<S, NT>(U, 1 - p, MU, j, T(MU == 0 && x[0] == 0 ? g.bc : 1), u);
+  else ld_link_u<S, NT>(U, 1 - p, MU, j, u);
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     if (q < nr) {
@@ -45,19 +49,19 @@ __device__ inline void hop_dir(const Geo& g, const LinkV<S>& U, const FieldV<S>&
 }
 
 // acc += c0 H in (H: the hopping sum over the 8 neighbours); NT: links are
-// read with streaming loads (each is read once per pass)
-template <class S, int NR, bool O32, bool NT = false>
+// read with streaming loads (each is read once per pass); COMP: see hop_dir
+template <class S, int NR, bool O32, bool NT = false, bool COMP = false>
 __device__ inline void hop_all(const Geo& g, const LinkV<S>& U, const FieldV<S>& in, int r0, int nr, int p, int i,
                                const int x[4], typename St<S>::T c0, cx<typename St<S>::T> (&acc)[NR][12]) {
   // scheduling barriers between the directions bound the number of loads in
   // flight per lane (and so the registers); the other waves hide the latency
-  hop_dir<S, 0, NR, O32, NT>(g, U, in, r0, nr, p, i, x, c0, acc);
+  hop_dir<S, 0, NR, O32, NT, COMP>(g, U, in, r0, nr, p, i, x, c0, acc);
   __builtin_amdgcn_sched_barrier(0);
-  hop_dir<S, 1, NR, O32, NT>(g, U, in, r0, nr, p, i, x, c0, acc);
+  hop_dir<S, 1, NR, O32, NT, COMP>(g, U, in, r0, nr, p, i, x, c0, acc);
   __builtin_amdgcn_sched_barrier(0);
-  hop_dir<S, 2, NR, O32, NT>(g, U, in, r0, nr, p, i, x, c0, acc);
+  hop_dir<S, 2, NR, O32, NT, COMP>(g, U, in, r0, nr, p, i, x, c0, acc);
   __builtin_amdgcn_sched_barrier(0);
-  hop_dir<S, 3, NR, O32, NT>(g, U, in, r0, nr, p, i, x, c0, acc);
+  hop_dir<S, 3, NR, O32, NT, COMP>(g, U, in, r0, nr, p, i, x, c0, acc);
   __builtin_amdgcn_sched_barrier(0);
 }
 
@@ -110,7 +114,8 @@ __device__ inline bool lane_site(const Geo& g, int tile, int rg, int sb, int nrh
 
 // NTM: streaming (non-temporal) access for what the pass touches once; bit 0
 // the links and clover blocks, bit 1 the site's own spinor and the output.  The
-// neighbour spinors, which eight sites read, always take ordinary loads.
+// neighbour spinors, which eight sites read, always take ordinary loads.  Bit 2:
+// compressed links (two rows read, the third rebuilt).
 template <class S, int NR, bool O32, int NTM>
 __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k_dhat_a(Geo g, LinkV<S> U, CloverV<S> Ai, FieldV<S> in_e, FieldV<S> t_o,
                                                 int nrhs, int nrg, int order, int sb, int rf) {
@@ -126,7 +131,7 @@ __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k
   for (int q = 0; q < NR; ++q)
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[q][k] = {T(0), T(0)};
-  hop_all<S, NR, O32, (NTM & 1) != 0>(g, U, in_e, r0, nr, 1, i, x, T(1), acc);
+  hop_all<S, NR, O32, (NTM & 1) != 0, (NTM & 4) != 0>(g, U, in_e, r0, nr, 1, i, x, T(1), acc);
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     if (q < nr) {
@@ -153,7 +158,7 @@ __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k
   for (int q = 0; q < NR; ++q)
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[q][k] = {T(0), T(0)};
-  hop_all<S, NR, O32, (NTM & 1) != 0>(g, U, t_o, r0, nr, 0, i, x, T(-0.25), acc);
+  hop_all<S, NR, O32, (NTM & 1) != 0, (NTM & 4) != 0>(g, U, t_o, r0, nr, 0, i, x, T(-0.25), acc);
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     if (q < nr) {
@@ -408,21 +413,29 @@ static hipError_t launch_dhat_nr(const Geo& g, const DevOp<S>& op, FieldV<S> in,
   int tiles = ceil_div(g.Vh, sb);
   dim3 grid(tiles * nrg), blk(c.block);
   const bool o32 = fits32(g, in, nrhs) && fits32(g, tmp, nrhs) && fits32(g, out, nrhs);
-  const int ntm = o32 && NR == 1 ? (c.xcd >> 2) & 3 : 0;  // streaming access to single-use data
+  // streaming access to single-use data (bits 0, 1) and compressed links (bit 2)
+  const int ntm = o32 && NR == 1 ? (c.xcd >> 2) & 7 : 0;
   const int order = c.xcd & 3;
   const int rf = in.ss > 1;  // interleaved operands: rhs fastest across the lanes
-#define QDD_DHAT_PASS(KER, ...)                                                                       \
-  switch (o32 ? 1 + ntm : 0) {                                                                        \
-    case 0: hipLaunchKernelGGL((KER<S, NR, false, 0>), grid, blk, 0, st, __VA_ARGS__); break;         \
-    case 1: hipLaunchKernelGGL((KER<S, NR, true, 0>), grid, blk, 0, st, __VA_ARGS__); break;          \
-    case 2: hipLaunchKernelGGL((KER<S, NR, true, NR == 1 ? 1 : 0>), grid, blk, 0, st, __VA_ARGS__); break; \
-    case 3: hipLaunchKernelGGL((KER<S, NR, true, NR == 1 ? 2 : 0>), grid, blk, 0, st, __VA_ARGS__); break; \
-    default: hipLaunchKernelGGL((KER<S, NR, true, NR == 1 ? 3 : 0>), grid, blk, 0, st, __VA_ARGS__); break; \
+#define QDD_DHAT_V(KER, M, ...) \
+  hipLaunchKernelGGL((KER<S, NR, true, NR == 1 ? M : 0>), grid, blk, 0, st, __VA_ARGS__)
+#define QDD_DHAT_PASS(KER, ...)                                                                  \
+  switch (o32 ? 1 + ntm : 0) {                                                                   \
+    case 0: hipLaunchKernelGGL((KER<S, NR, false, 0>), grid, blk, 0, st, __VA_ARGS__); break;    \
+    case 1: QDD_DHAT_V(KER, 0, __VA_ARGS__); break;                                              \
+    case 2: QDD_DHAT_V(KER, 1, __VA_ARGS__); break;                                              \
+    case 3: QDD_DHAT_V(KER, 2, __VA_ARGS__); break;                                              \
+    case 4: QDD_DHAT_V(KER, 3, __VA_ARGS__); break;                                              \
+    case 5: QDD_DHAT_V(KER, 4, __VA_ARGS__); break;                                              \
+    case 6: QDD_DHAT_V(KER, 5, __VA_ARGS__); break;                                              \
+    case 7: QDD_DHAT_V(KER, 6, __VA_ARGS__); break;                                              \
+    default: QDD_DHAT_V(KER, 7, __VA_ARGS__); break;                                             \
   }
   if (pass & 1) QDD_DHAT_PASS(k_dhat_a, g, op.U, op.Ainv, in, tmp, nrhs, nrg, order, sb, rf)
   if (ev) (void)hipEventRecord(ev, st);
   if (pass & 2) QDD_DHAT_PASS(k_dhat_b, g, op.U, op.A, in, tmp, out, nrhs, nrg, order, sb, rf)
 #undef QDD_DHAT_PASS
+#undef QDD_DHAT_V
   return hipGetLastError();
 }
 

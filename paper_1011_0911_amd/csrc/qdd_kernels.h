@@ -21,7 +21,8 @@ struct LaunchCfg {
   int xcd = 2;      // block walk: 0 linear, 1 XCD slabs, 2 XCD slabs walked time-slice first,
                     // 3 XCD slabs of L1/8 x1 planes walked time slice by time slice; Dhat with nr 1:
                     // + 4 streaming loads of links and clover, + 8 streaming load of the
-                    // site's own spinor and store of the output (data a pass touches once)
+                    // site's own spinor and store of the output (data a pass touches once),
+                    // + 16 compressed links (two rows read, the third rebuilt)
   int sb = 0;       // sites per block (0 = block); block/sb lane groups take further rhs
 };
 

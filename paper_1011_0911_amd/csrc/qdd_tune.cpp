@@ -26,8 +26,9 @@ extern "C" qdd_status qdd_autotune(qdd_ctx* x, int kernel, qdd_prec prec, int nr
         if (nr > nrhs) continue;
         for (int xcd : {0, 1, 2, 3}) {
           cand.push_back(LaunchCfg{block, nr, xcd, sb == block ? 0 : sb});
-          if (kernel == 0 && nr == 1)  // streaming access: links + clover (4), own spinor + output (8)
-            for (int ntm : {4, 8, 12}) cand.push_back(LaunchCfg{block, nr, xcd | ntm, sb == block ? 0 : sb});
+          if (kernel == 0 && nr == 1)  // streaming access: links + clover (4), own spinor + output (8);
+                                       // compressed links (16)
+            for (int ntm : {4, 8, 12, 16, 20, 24, 28}) cand.push_back(LaunchCfg{block, nr, xcd | ntm, sb == block ? 0 : sb});
         }
       }
       // staged variant (Dhat): R = block / sb lanes per site loop over the right-hand sides

@@ -88,7 +88,7 @@ def traffic(bench_json: str, fetch_dir: str, write_dir: str, out_path: str, cmd:
     if ln["nr"] == 0:
         kb = f"qdd::k_dhat_staged<{tname}, 1, true>"
     else:
-        ntm = (ln["xcd"] >> 2) & 3 if ln["nr"] == 1 else 0
+        ntm = (ln["xcd"] >> 2) & 7 if ln["nr"] == 1 else 0
         kb = f"qdd::k_dhat_b<{tname}, {ln['nr']}, true, {ntm}>"
     fetch, write = _counter(fetch_dir, "FETCH_SIZE"), _counter(write_dir, "WRITE_SIZE")
 

@@ -86,8 +86,9 @@ def test_batched_equals_single_rhs(Q, kernel):
         if kernel == 0:  # the LDS-staged variant (nr = 0): tiles of sb sites, block/sb lanes per site
             shapes += [(64, 0, 0, 0), (128, 0, 1, 32), (256, 0, 2, 64), (256, 0, 1, 16), (192, 0, 0, 32), (128, 0, 3, 32)]
         shapes += [(128, 1, 3, 0), (256, 1, 3, 32)]
-        if kernel == 0:  # streaming loads / stores for the single-use data (xcd + 4, + 8)
-            shapes += [(256, 1, 4, 32), (128, 1, 14, 0), (64, 1, 11, 16), (256, 1, 8, 0)]
+        if kernel == 0:  # streaming loads / stores for the single-use data (xcd + 4, + 8), compressed links (+ 16)
+            shapes += [(256, 1, 4, 32), (128, 1, 14, 0), (64, 1, 11, 16), (256, 1, 8, 0), (256, 1, 16, 32),
+                       (128, 1, 27, 0), (64, 1, 22, 16)]
         for block, nr, xcd, sb in shapes:
             if nr == 0 and 108 * (sb or block) * (16 if prec == 0 else 8) > 65536:
                 continue  # staged tile does not fit the LDS budget in this precision
@@ -99,6 +100,24 @@ def test_batched_equals_single_rhs(Q, kernel):
                 base = out
             assert relerr(out, base) <= (1e-15 if prec == 0 else 1e-6), (prec, block, nr, xcd, sb)
         ctx.set_launch(kernel, prec, 256, 1, 1, 0)
+
+
+def test_compressed_links_parity(Q, orc):
+    # links read as two rows with the third rebuilt (and the antiperiodic time
+    # sign of the boundary links put back): Dhat against the oracle in every
+    # precision, batched and single right-hand side
+    L = (8, 4, 4, 6)
+    V = int(np.prod(L))
+    ctx, U = make_ctx(Q, L, 0.6, 0.1357, 1.9, 307, max_nrhs=3)
+    A, Ai = orc.clover(L, U, 0.1357, 1.9)
+    psi = S.gaussian_field(V // 2, 15, nrhs=3)
+    ref = np.stack([orc.apply_Dhat(L, U, A, Ai, psi[r]) for r in range(3)])
+    for prec in (0, 1, 2):
+        for block, xcd, sb in ((256, 16, 32), (128, 31, 0)):
+            ctx.set_launch(0, prec, block, 1, xcd, sb)
+            assert relerr(to_np(ctx.apply_dhat(psi, prec)), ref) < TOL[prec], (prec, block, xcd)
+            assert relerr(to_np(ctx.apply_dhat(psi[1:2], prec))[0], ref[1]) < TOL[prec], (prec, block, xcd)
+        ctx.set_launch(0, prec, 256, 1, 1, 0)
 
 
 def test_staged_variant_parity_and_limits(Q, orc):
@@ -119,8 +138,9 @@ def test_staged_variant_parity_and_limits(Q, orc):
         with pytest.raises(Q.QddError) as e:
             ctx.set_launch(kernel, prec, block, 0, 1, sb)
         assert e.value.status == Q.QDD_EINVAL
-    # streaming access (xcd + 4, + 8) exists for the one-rhs-per-lane Dhat kernels only
-    for kernel, nr, xcd in ((1, 1, 4), (0, 0, 5), (0, 2, 8), (0, 1, 16), (0, 1, -1)):
+    # streaming access (xcd + 4, + 8) and compressed links (+ 16) exist for the
+    # one-rhs-per-lane Dhat kernels only
+    for kernel, nr, xcd in ((1, 1, 4), (0, 0, 5), (0, 2, 8), (0, 2, 16), (0, 1, 32), (0, 1, -1)):
         with pytest.raises(Q.QddError) as e:
             ctx.set_launch(kernel, 1, 128, nr, xcd, 32)
         assert e.value.status == Q.QDD_EINVAL
