@@ -81,22 +81,33 @@ def measured_traffic(prec, nrhs, launch):
 def one_rhs_rates(ctx, src1, cache, cache_path, reps=20):
     """Dhat on a single right-hand side in each storage precision (autotuned
     launch): TB/s of algorithmic bytes for the whole apply, HIP events on the
-    library stream.  Context figures next to the batched headline."""
+    library stream.  Where the tuned launch reads compressed links, the same
+    launch with 18-real links is timed too (links_18).  Context figures next to
+    the batched headline."""
     import torch
     from paper_1011_0911_amd import qdd
+
+    def timed(prec, fin, fout):
+        launch = ctx.get_launch(qdd.KERNEL_DHAT, prec)
+        ctx.dw_hat_timed(prec, 1, fin, fout, 3)
+        ms_a, ms_b = ctx.dw_hat_timed(prec, 1, fin, fout, reps)
+        a_b, b_b = bytes_per_site(prec, 1, compressed(launch))
+        tbs = (a_b + b_b) * ctx.Vh / ((ms_a + ms_b) * 1e-3) / 1e12
+        return {"ms": round(ms_a + ms_b, 5), "TBs": round(tbs, 4), "frac": round(tbs / PEAK_HBM_TBS, 4),
+                "launch": list(launch)}
 
     res = {}
     for prec in (0, 1, 2):
         fin = ctx.pack(prec, torch.from_numpy(src1), True)
         fout = ctx.empty_field(prec, 1, True)
         ctx.autotune(qdd.KERNEL_DHAT, prec, 1, fin, fout, reps=5, cache=cache)
-        ctx.dw_hat_timed(prec, 1, fin, fout, 3)
-        ms_a, ms_b = ctx.dw_hat_timed(prec, 1, fin, fout, reps)
-        a_b, b_b = bytes_per_site(prec, 1, compressed(ctx.get_launch(qdd.KERNEL_DHAT, prec)))
-        tbs = (a_b + b_b) * ctx.Vh / ((ms_a + ms_b) * 1e-3) / 1e12
-        res[{0: "f64", 1: "f32", 2: "f16"}[prec]] = {"ms": round(ms_a + ms_b, 5), "TBs": round(tbs, 4),
-                                                     "frac": round(tbs / PEAK_HBM_TBS, 4),
-                                                     "launch": list(ctx.get_launch(qdd.KERNEL_DHAT, prec))}
+        r = timed(prec, fin, fout)
+        if compressed(r["launch"]):
+            b, nr, xcd, sb = r["launch"]
+            ctx.set_launch(qdd.KERNEL_DHAT, prec, b, nr, xcd & ~16, sb)
+            r["links_18"] = timed(prec, fin, fout)
+            ctx.set_launch(qdd.KERNEL_DHAT, prec, b, nr, xcd, sb)
+        res[{0: "f64", 1: "f32", 2: "f16"}[prec]] = r
         del fin, fout
     qdd.save_tune_cache(cache_path, cache)
     return res
