@@ -173,6 +173,9 @@ def solve_section(learned_pairs, U=None):
             "plain_s": r5["plain"]["solve_s"], "plain_iters": r5["plain"]["iters"],
             "plain_true_res_max": r5["plain"]["true_res_max"],
             "learned_over_plain_time": r5["learned"]["solve_s"] / r5["plain"]["solve_s"],
+            "learned_terms1": {k: r5["learned_terms1"][k] for k in ("solve_s", "iters", "fallbacks", "true_res_max",
+                                                                     "converged")},
+            "learned_terms1_over_plain_time": r5["learned_terms1"]["solve_s"] / r5["plain"]["solve_s"],
             "loss_first": r5["loss_first"], "loss_last": r5["loss_last"],
             "harvest_s": r5["harvest_s"], "train_s": r5["train_s"]}
     return sec

@@ -88,6 +88,11 @@ typedef struct {
   int use_net;         /* 1: gauge-covariant network stage inside the preconditioner */
   int net_nl;          /* network layers */
   int net_ch[8];       /* channels ch[0] .. ch[nl] (ch[0] = ch[nl] = 1) */
+  int net_terms;       /* BF16 terms per activation in the network's products when it is
+                          applied (qdd_net_forward, the solver's network stage): 3 keeps
+                          FP32 accuracy; 2 or 1 round each transported activation to 16
+                          or 8 significant bits (relative error <= 2^-16, 2^-8), fewer
+                          matrix-core operations; training always uses 3 */
 } qdd_config;
 
 typedef struct {
@@ -107,7 +112,8 @@ typedef struct qdd_ctx qdd_ctx;
 
 /* Fills *cfg with the defaults: max_nrhs 1, SAP 4^4 blocks, ncy 5, nmr 4, F32;
  * no deflation (Ns 0, blocks 4^4, nit 5, coarse tol 1e-6, nmx 2000);
- * nkv 16, nmx 2048, tol 1e-10, precond NONE; no network (3 layers 1-12-12-1). */
+ * nkv 16, nmx 2048, tol 1e-10, precond NONE; no network (3 layers 1-12-12-1,
+ * 3 terms). */
 void qdd_config_default(qdd_config* cfg);
 
 /* Workspace bytes needed for geometry + configuration; 0 if they are invalid. */
@@ -212,6 +218,9 @@ qdd_status qdd_solve_dhat(qdd_ctx* ctx, int nrhs, const double* eta_e, double* p
 qdd_status qdd_net_num_weights(const qdd_ctx* ctx, int64_t* n);
 qdd_status qdd_net_set_weights(qdd_ctx* ctx, const float* w);
 qdd_status qdd_net_get_weights(qdd_ctx* ctx, float* w);
+/* Sets net_terms (1, 2 or 3; see qdd_config) for the later network
+ * applications of this context; QDD_EINVAL otherwise. */
+qdd_status qdd_net_set_terms(qdd_ctx* ctx, int terms);
 /* out = N(in), canonical complex128 full fields (one field). */
 qdd_status qdd_net_forward(qdd_ctx* ctx, const double* in, double* out);
 /* Loss l = sum_i |N(r_i/|r_i|) - e_i/|r_i||^2 / sum_i |e_i/|r_i||^2 over nb pairs

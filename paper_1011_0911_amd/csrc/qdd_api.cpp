@@ -87,6 +87,7 @@ static bool valid_cfg(const qdd_geom* g, const qdd_config* c, std::string* why) 
     }
     for (int l = 1; l < c->net_nl; ++l)
       if (c->net_ch[l] < 1 || c->net_ch[l] > kMaxNetCh) { *why = "network: channels must be in 1..16"; return false; }
+    if (c->net_terms < 1 || c->net_terms > 3) { *why = "network: net_terms must be 1, 2 or 3"; return false; }
     if (c->dfl_Ns == 0) { *why = "network stage needs deflation (dfl_Ns > 0)"; return false; }
     if (c->sap_prec == QDD_F64) { *why = "network stage needs FP32 or FP16 SAP"; return false; }
   }
@@ -238,6 +239,7 @@ void qdd_config_default(qdd_config* c) {
   c->net_ch[1] = 12;
   c->net_ch[2] = 12;
   c->net_ch[3] = 1;
+  c->net_terms = 3;
 }
 
 size_t qdd_workspace_bytes(const qdd_geom* g, const qdd_config* c) {

@@ -6,9 +6,11 @@ namespace qdd {
 // one layer: out (cout channels, at most 16) = sum W (T_d in) ; channel stride cs
 // (elements); wmx: the layer's weights arranged by launch_net_wmx with the same
 // scratch_ch.  scratch: scratch_ch channel fields the weights-first form of a
-// one-output-channel layer may use (it needs 9; with fewer it is not used)
+// one-output-channel layer may use (it needs 9; with fewer it is not used).
+// terms: BF16 terms per transported input, 3 (exact split, FP32 accuracy), 2 or 1
 hipError_t launch_net_layer(const Geo& g, const LinkV<float>& U, const uint16_t* wmx, int cin, int cout,
-                            const float2* in, float2* out, int64_t cs, float2* scratch, int scratch_ch, hipStream_t st);
+                            const float2* in, float2* out, int64_t cs, float2* scratch, int scratch_ch, int terms,
+                            hipStream_t st);
 bool net_weights_first(int cin, int cout, int scratch_ch);
 // BF16 matrix-core operands of a layer from its BF16 complex weights wb
 // (net_wmx_elems 16-bit elements)

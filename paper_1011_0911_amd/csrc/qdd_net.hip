@@ -342,7 +342,7 @@ __global__ void k_net_adam(float2* w, const float2* g, float4* mv, int n, float 
 // operations per FP32 one of a quarter the depth.
 // A workgroup of 4 wavefronts takes kNetTile = 64 sites (192 columns = 12
 // column tiles of 16) and walks K in slabs of one MFMA depth: wavefront w
-// computes the transported input of the slab's (d, c') pair w for the 64 sites,
+// computes the transported input of the slab's (d, c') pair for the 64 sites,
 // one per lane (wave-uniform field and link bases, 32-bit lane offsets), into
 // LDS as the three terms, [term][column][k] (k fastest: one 16-byte read per
 // lane and operand), and runs the MFMAs of its 3 column tiles and all MT row
@@ -351,6 +351,13 @@ __global__ void k_net_adam(float2* w, const float2* g, float4* mv, int n, float 
 // A operands come prearranged (k_net_wmx) in the lane order of the
 // instruction: lane l holds A[l%16][8(l/16) .. 8(l/16)+7], B[8(l/16) ..][l%16],
 // and D rows 4(l/16)+r, column l%16 (measured with an in-bounds probe).
+// K order (net_pair): the k groups g = 0..3 of a slab hold four (d, c') pairs.
+// Per input channel c' one slab takes the four transports along the two
+// fastest-running site coordinates (d = 5..8: their reads of c' fall on nearly
+// the same neighbour sites, so three of four hit the cache) and the next the
+// four along the others (d = 1..4); the untransported d = 0 pairs of four
+// channels share the last slabs.  Wavefront g thus stages only transports 5 + g
+// (even slabs) and 1 + g (odd slabs) and keeps each link across the channels.
 constexpr int kNetTile = 64;
 constexpr int kNetKs = 32;             // k rows per slab (one MFMA depth): 4 (d, c') pairs x 4 spins x re/im
 constexpr int kNetLd = kNetKs + 8;     // LDS row stride of a column (BF16 elements)
@@ -368,6 +375,15 @@ typedef float f2v __attribute__((ext_vector_type(2)));
 // channel.
 __host__ __device__ inline int net_mt(int cz) { return (8 * cz + 15) / 16; }
 __host__ __device__ inline int net_kb(int cin, int nd) { return (8 * nd * cin + 31) / 32; }
+// pair e = d cin + c' of k group g in slab sk, or -1 (zero column); for nd = 9
+// the 2 cin transport slabs and ceil(cin / 4) untransported ones make up
+// net_kb = ceil(9 cin / 4) exactly
+__host__ __device__ inline int net_pair(int sk, int g, int cin, int nd) {
+  if (nd == 1) return 4 * sk + g < cin ? 4 * sk + g : -1;
+  if (sk < 2 * cin) return ((sk & 1) ? 1 + g : 5 + g) * cin + (sk >> 1);
+  const int cp = 4 * (sk - 2 * cin) + g;
+  return cp < cin ? cp : -1;
+}
 bool net_weights_first(int cin, int cout, int scratch_ch) { return cout == 1 && cin > 1 && scratch_ch >= 9; }
 
 // prearranged A operands of one layer: wmx[(mt * KB + kb) * 64 + lane][0..7]
@@ -381,11 +397,11 @@ __global__ void k_net_wmx(const uint32_t* wb, int cin, int cout, int wf, uint16_
   const int i = (int)(t & 7), lane = (int)((t >> 3) & 63);
   const int64_t blk = t >> 9;
   const int kb = (int)(blk % KB), mt = (int)(blk / KB);
-  const int m = 16 * mt + (lane & 15), k = 32 * kb + 8 * (lane >> 4) + i;
+  const int m = 16 * mt + (lane & 15), e = net_pair(kb, lane >> 4, cin, nd);
   const int ch = m >> 3, sa = (m >> 1) & 3, ri_o = m & 1;
   uint16_t v = 0;
-  if (ch < cz && k < 8 * nd * cin) {
-    const int e = k >> 3, sb = (k >> 1) & 3, ri_i = k & 1;
+  if (ch < cz && e >= 0) {
+    const int sb = (i >> 1) & 3, ri_i = i & 1;
     const int d = wf ? ch / cout : e / cin, cp = wf ? e : e - d * cin, c = wf ? ch - d * cout : ch;
     const uint32_t w = wb[((int64_t)(d * cout + c) * cin + cp) * 16 + sa * 4 + sb];
     const uint16_t wr = (uint16_t)(w & 0xffffu), wi = (uint16_t)(w >> 16);
@@ -395,11 +411,14 @@ __global__ void k_net_wmx(const uint32_t* wb, int cin, int cout, int wf, uint16_
 }
 
 // cz output channels (cout, or the 9 cout z_d of the weights-first form), nd
-// transports per input channel (9, or 1 for the weights-first form)
-template <int MT>
+// transports per input channel (9, or 1 for the weights-first form); TM BF16
+// terms per transported input: 3 is the exact split (FP32 accuracy), 2 and 1
+// keep the leading 16 or 8 significant bits (relative rounding error at most
+// 2^-16 or 2^-8 per element), for inference where that suffices
+template <int MT, int TM>
 __global__ void __launch_bounds__(256) k_net_layer_mx(Geo g, LinkV<float> U, const uint4* wmx, int cin, int cz,
                                                       int nd, const float2* in, float2* out, int64_t cs) {
-  extern __shared__ uint4 tl4[];  // [3 terms][3 kNetTile columns][kNetLd] BF16
+  extern __shared__ uint4 tl4[];  // [TM terms][3 kNetTile columns][kNetLd] BF16
   uint16_t* tl = reinterpret_cast<uint16_t*>(tl4);
   constexpr int N = 3 * kNetTile;
   // wv through readfirstlane: the compiler then knows that the pair, the
@@ -407,9 +426,9 @@ __global__ void __launch_bounds__(256) k_net_layer_mx(Geo g, LinkV<float> U, con
   // address arithmetic, uniform branches instead of selects)
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int s0 = blockIdx.x * kNetTile;
-  const int KB = net_kb(cin, nd), npair = nd * cin;
-  // staging role: wavefront wv stages the (d, c') pair wv of every slab for the
-  // tile's 64 sites, one per lane; the pair, the parity of the tile (the tiles
+  const int KB = net_kb(cin, nd);
+  // staging role: wavefront wv stages the (d, c') pair net_pair(sk, wv) of slab sk
+  // for the tile's 64 sites, one per lane; the pair, the parity of the tile (the tiles
   // never straddle the parity boundary, Vh being a multiple of kNetTile) and
   // so the field and link bases are uniform across the wavefront
   const int s = s0 + lane;
@@ -423,49 +442,61 @@ __global__ void __launch_bounds__(256) k_net_layer_mx(Geo g, LinkV<float> U, con
 #pragma unroll
     for (int j = 0; j < 3; ++j) acc[mt][j] = f4v{0.f, 0.f, 0.f, 0.f};
   // operands of this lane's staging item (the input spinor, at the neighbour
-  // for a transport, and the link), loaded one slab ahead so that the loads
-  // are in flight during the matrix-core phase of the current slab
-  float2 psp[12], pu[9];
-  int pd = -1;  // transport of the loaded item (-1: none, zero column)
+  // for a transport, and the link), loaded two slabs ahead into one of two
+  // buffers, so that the loads have two matrix-core phases to arrive in (one
+  // slab ahead from one buffer for MT > 6, where the second buffer would cost
+  // the second wavefront per SIMD)
+  struct Item {
+    float2 psp[12], pu[9];
+    int pd;  // transport of the loaded item (-1: none, zero column)
+    int ud;  // transport whose link pu holds (kept while the next item of the buffer has the same)
+  };
+  Item it0, it1;
+  it0.pd = it1.pd = it0.ud = it1.ud = -1;
   // (lanes past the end of the lattice load site i = 0 of the parity, a valid
   // address, and stage zeros: no divergent branch around the loads, so the
   // bases stay scalar)
-  auto prefetch = [&](int e) {
-    pd = e < npair ? e / cin : -1;
+  auto prefetch = [&](Item& it, int sk) {
+    const int e = net_pair(sk, wv, cin, nd);
+    it.pd = e >= 0 ? e / cin : -1;
+    const int pd = it.pd;
     if (pd < 0) return;
     const int cp = e - pd * cin;
     const float2* f = in + cp * cs;
     if (pd == 0) {
       const float2* fb = f + (int64_t)p * 12 * g.Vh;
 #pragma unroll
-      for (int k = 0; k < 12; ++k) psp[k] = ld_off(fb + (int64_t)k * g.Vh, (uint32_t)i * 8u);
+      for (int k = 0; k < 12; ++k) it.psp[k] = ld_off(fb + (int64_t)k * g.Vh, (uint32_t)i * 8u);
     } else {
       const int mu = (pd - 1) >> 1, dir = (pd - 1) & 1;
       const int j = nbr_idx(g, x, mu, dir == 0 ? 1 : -1);
       const float2* fb = f + (int64_t)(1 - p) * 12 * g.Vh;
 #pragma unroll
-      for (int k = 0; k < 12; ++k) psp[k] = ld_off(fb + (int64_t)k * g.Vh, (uint32_t)j * 8u);
-      const float2* ub = U.p + (int64_t)(((dir == 0 ? p : 1 - p) * 4 + mu) * 9) * U.n;
-      const uint32_t uo = (uint32_t)(dir == 0 ? i : j) * 8u;
+      for (int k = 0; k < 12; ++k) it.psp[k] = ld_off(fb + (int64_t)k * g.Vh, (uint32_t)j * 8u);
+      if (pd != it.ud) {
+        const float2* ub = U.p + (int64_t)(((dir == 0 ? p : 1 - p) * 4 + mu) * 9) * U.n;
+        const uint32_t uo = (uint32_t)(dir == 0 ? i : j) * 8u;
 #pragma unroll
-      for (int k = 0; k < 9; ++k) pu[k] = ld_off(ub + (int64_t)k * U.n, uo);
+        for (int k = 0; k < 9; ++k) it.pu[k] = ld_off(ub + (int64_t)k * U.n, uo);
+        it.ud = pd;
+      }
     }
   };
-  prefetch(wv);
-  for (int sk = 0; sk < KB; ++sk) {
+  auto slab = [&](int sk, Item& it, int ahead) {
     // A operands of the slab (latency hidden behind the staging below)
     uint4 aop[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) aop[mt] = wmx[((int64_t)mt * KB + sk) * 64 + lane];
     __syncthreads();
     {
+      const int pd = it.pd;
       cx<float> tr[12];
 #pragma unroll
       for (int k = 0; k < 12; ++k) tr[k] = {0.f, 0.f};
       if (live && pd == 0) {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) tr[k] = {psp[k].x, psp[k].y};
-      } else if (live && ((pd - 1) & 1) == 0) {  // forward transport U psi(x + mu)
+        for (int k = 0; k < 12; ++k) tr[k] = {it.psp[k].x, it.psp[k].y};
+      } else if (live && pd > 0 && ((pd - 1) & 1) == 0) {  // forward transport U psi(x + mu)
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb)
 #pragma unroll
@@ -473,7 +504,8 @@ __global__ void __launch_bounds__(256) k_net_layer_mx(Geo g, LinkV<float> U, con
             cx<float> z{0.f, 0.f};
 #pragma unroll
             for (int b = 0; b < 3; ++b)
-              z = fma_c(cx<float>{pu[a * 3 + b].x, pu[a * 3 + b].y}, cx<float>{psp[sb * 3 + b].x, psp[sb * 3 + b].y}, z);
+              z = fma_c(cx<float>{it.pu[a * 3 + b].x, it.pu[a * 3 + b].y},
+                        cx<float>{it.psp[sb * 3 + b].x, it.psp[sb * 3 + b].y}, z);
             tr[sb * 3 + a] = z;
           }
       } else if (live && pd > 0) {  // backward transport U^dag psi(x - mu)
@@ -484,41 +516,41 @@ __global__ void __launch_bounds__(256) k_net_layer_mx(Geo g, LinkV<float> U, con
             cx<float> z{0.f, 0.f};
 #pragma unroll
             for (int b = 0; b < 3; ++b)
-              z = fmac_c(cx<float>{pu[b * 3 + a].x, pu[b * 3 + a].y}, cx<float>{psp[sb * 3 + b].x, psp[sb * 3 + b].y}, z);
+              z = fmac_c(cx<float>{it.pu[b * 3 + a].x, it.pu[b * 3 + a].y},
+                         cx<float>{it.psp[sb * 3 + b].x, it.psp[sb * 3 + b].y}, z);
             tr[sb * 3 + a] = z;
           }
       }
-      if (sk + 1 < KB) prefetch(4 * (sk + 1) + wv);
-      // exact three-term BF16 split of each (re, im) pair, rounded to nearest
-      // by the packed conversion: hi = bf16(t), mid = bf16(t - hi) (exact
-      // difference), lo = t - hi - mid (exact, at most 8 significant bits);
-      // 8 consecutive k (sb, re/im) per column and term
+      if (sk + ahead < KB) prefetch(it, sk + ahead);
+      // BF16 split of each (re, im) pair, rounded to nearest by the packed
+      // conversion: hi = bf16(t), mid = bf16(t - hi) (exact difference),
+      // lo = t - hi - mid (exact, at most 8 significant bits), the first TM of
+      // them; 8 consecutive k (sb, re/im) per column and term
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        uint32_t hw[3][4];
+        uint32_t hw[TM][4];
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb) {
-          bf2v t3[3];
           f2v v = {tr[sb * 3 + a].re, tr[sb * 3 + a].im};
 #pragma unroll
-          for (int tm = 0; tm < 3; ++tm) {
-            t3[tm] = __builtin_convertvector(v, bf2v);
+          for (int tm = 0; tm < TM; ++tm) {
+            const bf2v t2 = __builtin_convertvector(v, bf2v);
             uint32_t w;
-            __builtin_memcpy(&w, &t3[tm], 4);
+            __builtin_memcpy(&w, &t2, 4);
             hw[tm][sb] = w;
-            if (tm < 2) v = v - f2v{__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u)};
+            if (tm + 1 < TM) v = v - f2v{__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u)};
           }
         }
         const int n = 3 * lane + a;
 #pragma unroll
-        for (int tm = 0; tm < 3; ++tm)
+        for (int tm = 0; tm < TM; ++tm)
           *reinterpret_cast<uint4*>(tl + ((int64_t)tm * N + n) * kNetLd + 8 * wv) =
               make_uint4(hw[tm][0], hw[tm][1], hw[tm][2], hw[tm][3]);
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int tm = 0; tm < 3; ++tm) {
+    for (int tm = 0; tm < TM; ++tm) {
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         const int n = (3 * wv + j) * 16 + (lane & 15);
@@ -533,6 +565,18 @@ __global__ void __launch_bounds__(256) k_net_layer_mx(Geo g, LinkV<float> U, con
         }
       }
     }
+  };
+  // slabs in pairs, even ones from buffer 0 and odd ones from buffer 1 (KB is
+  // uniform: every wavefront takes the same branches and barriers)
+  prefetch(it0, 0);
+  if constexpr (MT <= 6) {
+    if (KB > 1) prefetch(it1, 1);
+    for (int sk = 0; sk < KB; sk += 2) {
+      slab(sk, it0, 2);
+      if (sk + 1 < KB) slab(sk + 1, it1, 2);
+    }
+  } else {
+    for (int sk = 0; sk < KB; ++sk) slab(sk, it0, 1);
   }
   // lane holds rows m = 16 mt + 4 (lane/16) + r: r = 0,1 are (re, im) of (c, sa),
   // r = 2,3 those of (c, sa + 1); column n = 16 nt + lane%16 = (site, colour).
@@ -611,21 +655,24 @@ __global__ void __launch_bounds__(256) k_net_gather(Geo g, LinkV<float> U, const
 
 // ------------------------------------------------------------------ launchers
 hipError_t launch_net_layer(const Geo& g, const LinkV<float>& U, const uint16_t* wmx, int cin, int cout,
-                            const float2* in, float2* out, int64_t cs, float2* scratch, int scratch_ch, hipStream_t st) {
-  if (cin < 1 || cout < 1 || cout > 16) return hipErrorInvalidValue;
+                            const float2* in, float2* out, int64_t cs, float2* scratch, int scratch_ch, int terms,
+                            hipStream_t st) {
+  if (cin < 1 || cout < 1 || cout > 16 || terms < 1 || terms > 3) return hipErrorInvalidValue;
   const bool wf = net_weights_first(cin, cout, scratch_ch);
   if (wf && !scratch) return hipErrorInvalidValue;
   const int cz = wf ? 9 * cout : cout, nd = wf ? 1 : 9;
   float2* dst = wf ? scratch : out;
   if (g.Vh % kNetTile) return hipErrorInvalidValue;  // tiles must not straddle the parity boundary
   const dim3 grid((g.V + kNetTile - 1) / kNetTile), blk(256);
-  const size_t lds = std::max((size_t)3 * 3 * kNetTile * kNetLd * sizeof(uint16_t),  // K slab
-                              (size_t)8 * 12 * kNetTile * sizeof(float2));           // output, 8 channels
+  const size_t lds = std::max((size_t)terms * 3 * kNetTile * kNetLd * sizeof(uint16_t),  // K slab
+                              (size_t)8 * 12 * kNetTile * sizeof(float2));               // output, 8 channels
   const uint4* w = reinterpret_cast<const uint4*>(wmx);
-  switch (net_mt(cz)) {
-#define NET_MX(M) \
-  case M: hipLaunchKernelGGL((k_net_layer_mx<M>), grid, blk, lds, st, g, U, w, cin, cz, nd, in, dst, cs); break;
-    NET_MX(1) NET_MX(2) NET_MX(3) NET_MX(4) NET_MX(5) NET_MX(6) NET_MX(7) NET_MX(8)
+  switch (net_mt(cz) * 4 + terms) {
+#define NET_MX(M, T) \
+  case M * 4 + T: hipLaunchKernelGGL((k_net_layer_mx<M, T>), grid, blk, lds, st, g, U, w, cin, cz, nd, in, dst, cs); break;
+#define NET_MX3(M) NET_MX(M, 1) NET_MX(M, 2) NET_MX(M, 3)
+    NET_MX3(1) NET_MX3(2) NET_MX3(3) NET_MX3(4) NET_MX3(5) NET_MX3(6) NET_MX3(7) NET_MX3(8)
+#undef NET_MX3
 #undef NET_MX
     default: return hipErrorInvalidValue;
   }

@@ -48,13 +48,14 @@ static qdd_status net_check(qdd_ctx* x, bool need_weights) {
   return QDD_OK;
 }
 
-// forward: act[0] must hold the input; act[nl] receives the output
-static qdd_status net_forward_levels(qdd_ctx* x) {
+// forward: act[0] must hold the input; act[nl] receives the output; terms: BF16
+// terms per activation (3 in training, the configured net_terms when applied)
+static qdd_status net_forward_levels(qdd_ctx* x, int terms) {
   int64_t cs = (int64_t)24 * x->G.Vh;
   for (int l = 0; l < net_nl(x); ++l)
     HCK(x, launch_net_layer(x->G, links32(x), layer_wmx(x, l, false), x->cfg.net_ch[l], x->cfg.net_ch[l + 1],
                             net_level(x, l), net_level(x, l + 1), cs, net_level(x, net_nl(x) + 1), fwd_scratch_ch(x),
-                            x->st));
+                            terms, x->st));
   return QDD_OK;
 }
 
@@ -114,7 +115,7 @@ static qdd_status net_loss_grad_packed(qdd_ctx* x, int nb, const float2* r, cons
   std::vector<double> h(nlb);
   for (int i = 0; i < nb; ++i) {
     HCK(x, launch_scale_to_f<float2>(net_level(x, 0), r + i * ps, 1.0 / rn[i], cs, x->st));
-    qdd_status s = net_forward_levels(x);
+    qdd_status s = net_forward_levels(x, 3);
     if (s != QDD_OK) return s;
     float2 *g0 = net_level(x, nl + 1), *g1 = net_level(x, nl + 2);
     HCK(x, launch_net_out_grad(net_level(x, nl), e + i * ps, (float)(1.0 / rn[i]), (float)(1.0 / Z), g0, cs, lp, nlb,
@@ -125,7 +126,7 @@ static qdd_status net_loss_grad_packed(qdd_ctx* x, int nb, const float2* r, cons
       HCK(x, launch_net_wgrad(x->G, links32(x), cin, cout, net_level(x, l), g0, cs, x->ptr<float>(x->lo.net_gpart),
                               x->lo.net_gpart_floats, grad + layer_off(x, l), x->st));
       if (l > 0) {
-        HCK(x, launch_net_layer(x->G, links32(x), layer_wmx(x, l, true), cout, cin, g0, g1, cs, nullptr, 0, x->st));
+        HCK(x, launch_net_layer(x->G, links32(x), layer_wmx(x, l, true), cout, cin, g0, g1, cs, nullptr, 0, 3, x->st));
         std::swap(g0, g1);
       }
     }
@@ -158,6 +159,15 @@ extern "C" qdd_status qdd_net_set_weights(qdd_ctx* x, const float* w) {
   return QDD_OK;
 }
 
+extern "C" qdd_status qdd_net_set_terms(qdd_ctx* x, int terms) {
+  if (!x) return QDD_EINVAL;
+  qdd_status s = net_check(x, false);
+  if (s != QDD_OK) return s;
+  if (terms < 1 || terms > 3) { x->fail("qdd_net_set_terms: terms must be 1, 2 or 3"); return QDD_EINVAL; }
+  x->cfg.net_terms = terms;
+  return QDD_OK;
+}
+
 extern "C" qdd_status qdd_net_get_weights(qdd_ctx* x, float* w) {
   if (!x || !w) return QDD_EINVAL;
   qdd_status s = net_check(x, true);
@@ -174,7 +184,7 @@ extern "C" qdd_status qdd_net_forward(qdd_ctx* x, const double* in_c, double* ou
   if (s != QDD_OK) return s;
   PackedView pi = x->packed(QDD_F32, 1, 0, net_level(x, 0));
   HCK(x, launch_pack_spinor<float>(x->G, in_c, pi.f32, 1, 0, pi.poff, pi.spoff, x->st));
-  s = net_forward_levels(x);
+  s = net_forward_levels(x, x->cfg.net_terms);
   if (s != QDD_OK) return s;
   PackedView po = x->packed(QDD_F32, 1, 0, net_level(x, net_nl(x)));
   HCK(x, launch_unpack_spinor<float>(x->G, po.f32, out_c, 1, 0, po.poff, po.spoff, x->st));
@@ -241,7 +251,7 @@ qdd_status net_stage(qdd_ctx* x, int nrhs, const double2* r1, float2* vn, double
   int nl = net_nl(x);
   for (int j = 0; j < nrhs; ++j) {
     HCK(x, launch_scale_to_f<double2>(net_level(x, 0), r1 + j * cs, 1.0, cs, x->st));
-    qdd_status s = net_forward_levels(x);
+    qdd_status s = net_forward_levels(x, x->cfg.net_terms);
     if (s != QDD_OK) return s;
     HCK(x, hipMemcpyAsync(vn + j * cs, net_level(x, nl), cs * sizeof(float2), hipMemcpyDeviceToDevice, x->st));
   }
@@ -250,9 +260,10 @@ qdd_status net_stage(qdd_ctx* x, int nrhs, const double2* r1, float2* vn, double
   HCK(x, launch_sub_f(r2, tbuf, (int64_t)nrhs * cs, x->st));
   double2 *part = x->ptr<double2>(x->lo.cpart), *nrm = x->ptr<double2>(x->lo.crn2);
   std::vector<double2> n1(nrhs), n2(nrhs);
+  // both norms with one wait: the second reduction reuses part and nrm after the
+  // first copy in stream order
   HCK(x, launch_dots<double2>(r1, 0, cs, 1, r1, cs, cs, nrhs, part, nrm, x->st));
   HCK(x, hipMemcpyAsync(n1.data(), nrm, nrhs * sizeof(double2), hipMemcpyDeviceToHost, x->st));
-  HCK(x, hipStreamSynchronize(x->st));
   HCK(x, launch_dots<double2>(r2, 0, cs, 1, r2, cs, cs, nrhs, part, nrm, x->st));
   HCK(x, hipMemcpyAsync(n2.data(), nrm, nrhs * sizeof(double2), hipMemcpyDeviceToHost, x->st));
   HCK(x, hipStreamSynchronize(x->st));

@@ -43,6 +43,7 @@ class Config(ctypes.Structure):
         ("dfl_coarse_tol", ctypes.c_double), ("dfl_coarse_nmx", ctypes.c_int),
         ("nkv", ctypes.c_int), ("nmx", ctypes.c_int), ("tol", ctypes.c_double), ("precond", ctypes.c_int),
         ("use_net", ctypes.c_int), ("net_nl", ctypes.c_int), ("net_ch", ctypes.c_int * 8),
+        ("net_terms", ctypes.c_int),
     ]
 
 
@@ -87,6 +88,7 @@ SIGNATURES = {
     "qdd_net_num_weights": (_i, [_vp, ctypes.POINTER(ctypes.c_int64)]),
     "qdd_net_set_weights": (_i, [_vp, _vp]),
     "qdd_net_get_weights": (_i, [_vp, _vp]),
+    "qdd_net_set_terms": (_i, [_vp, _i]),
     "qdd_net_forward": (_i, [_vp, _vp, _vp]),
     "qdd_net_loss_grad": (_i, [_vp, _i, _vp, _vp, ctypes.POINTER(_d), _vp]),
     "qdd_net_train_step": (_i, [_vp, _i, _vp, _vp, ctypes.c_float, ctypes.POINTER(_d)]),
@@ -327,6 +329,10 @@ class Context:
         t = torch.as_tensor(w).to(device=self.device, dtype=torch.complex64).contiguous()
         assert t.numel() == self.net_num_weights()
         self._check(lib().qdd_net_set_weights(self.h, _ptr(t)))
+
+    def net_set_terms(self, terms: int):
+        """BF16 terms per activation in later network applications (3 exact, 2, 1)."""
+        self._check(lib().qdd_net_set_terms(self.h, int(terms)))
 
     def net_get_weights(self):
         t = torch.empty(self.net_num_weights(), dtype=torch.complex64, device=self.device)

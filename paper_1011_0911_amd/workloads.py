@@ -183,6 +183,15 @@ def run_learned(wid: int = 5, train_pairs: int | None = None, chunk_pairs: int =
     psi, info, st, dt = timed_solve(ctx, eta)
     out["learned"] = {"solve_s": dt, "iters": [i["iters"] for i in info], "fallbacks": [i["fallbacks"] for i in info],
                       "true_res_max": max(i["true_res"] for i in info), "converged": all(i["converged"] for i in info)}
+    # the same network applied with activations rounded to one BF16 term (8
+    # significant bits) in its products: a cheaper, inexact preconditioner stage
+    ctx.net_set_terms(1)
+    psi, info, st, dt = timed_solve(ctx, eta)
+    out["learned_terms1"] = {"solve_s": dt, "iters": [i["iters"] for i in info],
+                             "fallbacks": [i["fallbacks"] for i in info],
+                             "true_res_max": max(i["true_res"] for i in info),
+                             "converged": all(i["converged"] for i in info)}
+    ctx.net_set_terms(3)
     ctx.net_set_weights(np.zeros(nw, complex))  # zero network: the stage adds nothing, plain iterates
     psi0, info0, st0, dt0 = timed_solve(ctx, eta)
     out["plain_same_subspace"] = {"solve_s": dt0, "iters": [i["iters"] for i in info0],
@@ -195,7 +204,7 @@ def run_learned(wid: int = 5, train_pairs: int | None = None, chunk_pairs: int =
     psi1, info1, st1, dt1 = timed_solve(pctx, eta)
     out["plain"] = {"solve_s": dt1, "iters": [i["iters"] for i in info1],
                     "true_res_max": max(i["true_res"] for i in info1)}
-    out["learned_vs_plain_time"] = dt1 / dt
+    out["learned_vs_plain_time"] = dt1 / out["learned"]["solve_s"]
     log(f"[w{wid}] learned {out['learned']} plain {out['plain']}")
     return out
 
@@ -262,7 +271,8 @@ def run_multi(wid: int = 4, nkv: int = 8, log=print):
 def time_network(wid: int = 5, reps: int = 5, nb: int = 4, log=print):
     """Timing of the learned stage's kernels on the workload lattice: one
     forward pass of the network on a Gaussian field and one Adam training step
-    on nb random pairs (mean over reps, after one warm-up each).  Returns a dict."""
+    on nb random pairs (mean over reps, after one warm-up each); the forward
+    also with one and two BF16 terms per activation.  Returns a dict."""
     import torch
 
     w = WORKLOADS[wid]
@@ -272,13 +282,17 @@ def time_network(wid: int = 5, reps: int = 5, nb: int = 4, log=print):
     ctx, _ = make_context(L, w["eps"], w["kappa"], w["csw"], 0, U=U, **solver_config(w, 1, use_net=True))
     ctx.net_set_weights(S.random_weights(ctx.net_num_weights(), 3000, 0.05))
     x = S.gaussian_field_device(V, 5000, 1)[0]
-    ctx.net_forward(x)
-    torch.cuda.synchronize()
-    t0 = time.time()
-    for _ in range(reps):
+    fwd_t = {}
+    for terms in (1, 2, 3):
+        ctx.net_set_terms(terms)
         ctx.net_forward(x)
-    torch.cuda.synchronize()
-    fwd = (time.time() - t0) / reps
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for _ in range(reps):
+            ctx.net_forward(x)
+        torch.cuda.synchronize()
+        fwd_t[terms] = (time.time() - t0) / reps
+    fwd = fwd_t[3]
     rb, eb = ctx.pair_buffers(nb)
     fb32 = ctx.field_bytes(qdd.F32, 1, False)
     for k in range(nb):  # FP32 pairs: random residuals and errors
@@ -292,7 +306,8 @@ def time_network(wid: int = 5, reps: int = 5, nb: int = 4, log=print):
         ctx.net_train_step(rb, eb, nb, 1e-4)
     torch.cuda.synchronize()
     out = {"lattice": "x".join(map(str, L)), "channels": list(w.get("net_ch", (1, 12, 12, 1))),
-           "forward_ms": fwd * 1e3, "train_step_ms": (time.time() - t0) / reps * 1e3, "pairs_per_step": nb}
+           "forward_ms": fwd * 1e3, "forward_ms_terms2": fwd_t[2] * 1e3, "forward_ms_terms1": fwd_t[1] * 1e3,
+           "train_step_ms": (time.time() - t0) / reps * 1e3, "pairs_per_step": nb}
     log(f"[net] {out}")
     return out
 

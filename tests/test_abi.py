@@ -49,6 +49,12 @@ def test_invalid_geometry_and_config_rejected_on_host(Q):
     assert Q.workspace_bytes((12, 8, 8, 8), Q.default_config(precond=Q.PRECOND_SAP)) == 0  # 3 blocks in time
     assert Q.workspace_bytes((8, 8, 8, 8), Q.default_config(precond=Q.PRECOND_DFL)) == 0  # no Ns
     assert Q.workspace_bytes((8, 8, 8, 8), Q.default_config(nkv=33)) == 0
+    net = dict(precond=Q.PRECOND_DFL, dfl_Ns=4, dfl_bs=(2, 2, 2, 2), sap_bs=(2, 2, 2, 2), use_net=1)
+    assert cfg.net_terms == 3
+    assert Q.workspace_bytes((8, 8, 8, 8), Q.default_config(**net)) > 0
+    assert Q.workspace_bytes((8, 8, 8, 8), Q.default_config(net_terms=1, **net)) > 0
+    assert Q.workspace_bytes((8, 8, 8, 8), Q.default_config(net_terms=0, **net)) == 0
+    assert Q.workspace_bytes((8, 8, 8, 8), Q.default_config(net_terms=4, **net)) == 0
     g = Q.make_geom((5, 4, 4, 4))
     h = ctypes.c_void_p()
     st = Q.lib().qdd_create(ctypes.byref(g), ctypes.byref(cfg), None, 0, None, ctypes.byref(h))

@@ -41,18 +41,40 @@ def net_ctx(Q, L, ch, seed, **kw):
 CHS = [CH, [1, 12, 12, 1]]
 
 
-@pytest.mark.parametrize("ch", CHS)
-def test_net_forward_parity(Q, orc, ch):
-    L = (4, 4, 4, 8)
+# 8^4: 64 tiles of 64 sites, 16 per time slice, several slabs of channels
+@pytest.mark.parametrize("ch,L", [(CHS[0], (4, 4, 4, 8)), (CHS[1], (4, 4, 4, 8)), (CHS[1], (8, 8, 8, 8))])
+def test_net_forward_parity(Q, orc, ch, L):
     ctx, U = net_ctx(Q, L, ch, 601)
     W = bf16(S.random_weights(ctx.net_num_weights(), 602, 0.3))
     ctx.net_set_weights(W)
-    x = S.gaussian_field(512, 603)
+    x = S.gaussian_field(int(np.prod(L)), 603)
     out = to_np(ctx.net_forward(x))
     ref = orc.net_forward(L, U, ch, W, x[None])[0]
     e = relerr(out, ref)
     print("forward err", e)
     assert e < 1e-5
+
+
+@pytest.mark.parametrize("terms", [1, 2])
+def test_net_forward_reduced_terms(Q, orc, terms):
+    # each transported activation is kept to 8 significant bits per term, a
+    # relative rounding error of at most eps = 2^-8 (one term) or 2^-16 (two)
+    # per element; to first order the three layers add their errors, each about
+    # eps times |W| |T in| / |W T in| (of order one for these weights): bound
+    # 3 layers x 4 x eps.  The exact three-term split stays far below it.
+    L = (4, 4, 4, 8)
+    ch = [1, 12, 12, 1]
+    ctx, U = net_ctx(Q, L, ch, 601, net_terms=terms)
+    W = bf16(S.random_weights(ctx.net_num_weights(), 602, 0.3))
+    ctx.net_set_weights(W)
+    x = S.gaussian_field(512, 603)
+    ref = orc.net_forward(L, U, ch, W, x[None])[0]
+    e = relerr(to_np(ctx.net_forward(x)), ref)
+    eps = 2.0 ** (-8 * terms)
+    print("terms", terms, "forward err", e, "bound", 12 * eps)
+    assert e < 12 * eps
+    if terms == 1:
+        assert e > 1e-4  # the rounding is in effect (the three-term result is within 1e-6)
 
 
 def test_net_reproduces_wilson_operator(Q, orc):
