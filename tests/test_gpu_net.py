@@ -37,12 +37,13 @@ def net_ctx(Q, L, ch, seed, **kw):
     return make_ctx(Q, L, 0.5, 0.1355, 1.9, seed, **cfg)
 
 
-# small channel counts (ragged row tiles, zero-padded k blocks) and the 1-12-12-1 network
-CHS = [CH, [1, 12, 12, 1]]
+# small channel counts (ragged row tiles, zero-padded k blocks), the 1-12-12-1 network,
+# and 16 channels (eight row tiles: the layer kernel's one-buffer staging path)
+CHS = [CH, [1, 12, 12, 1], [1, 16, 1]]
 
 
 # 8^4: 64 tiles of 64 sites, 16 per time slice, several slabs of channels
-@pytest.mark.parametrize("ch,L", [(CHS[0], (4, 4, 4, 8)), (CHS[1], (4, 4, 4, 8)), (CHS[1], (8, 8, 8, 8))])
+@pytest.mark.parametrize("ch,L", [(CHS[0], (4, 4, 4, 8)), (CHS[1], (4, 4, 4, 8)), (CHS[1], (8, 8, 8, 8)), (CHS[2], (4, 4, 4, 8))])
 def test_net_forward_parity(Q, orc, ch, L):
     ctx, U = net_ctx(Q, L, ch, 601)
     W = bf16(S.random_weights(ctx.net_num_weights(), 602, 0.3))
