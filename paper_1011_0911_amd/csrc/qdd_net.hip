@@ -39,20 +39,37 @@ __device__ inline uint16_t f_to_bf16(float f) {
 // (k_net_wgrad_reduce), so the gradient is deterministic.
 constexpr int kWgTileSites = 16;
 constexpr int kWgLd = 52;  // LDS row stride (floats) of the [m][k] / [n][k] tiles, >= 3 kWgTileSites
+// Site range r and transport d of workgroup b (nwx ranges x 9 transports).
+// Workgroups go to the 8 XCDs round-robin (b mod 8), each with its own L2; the
+// nine transports of one range go to consecutive workgroups of one XCD, so the
+// range's output gradient and inputs come from HBM about once instead of nine
+// times.  (Range-major order where nwx is not a multiple of 8.)
+__device__ inline void wgrad_block(int b, int nwx, int& r, int& d) {
+  if (nwx & 7) {
+    r = b % nwx;
+    d = b / nwx;
+    return;
+  }
+  const int q = b >> 3;  // rank within the XCD
+  d = q % 9;
+  r = (q / 9) * 8 + (b & 7);
+}
 template <int TPW>
 __global__ void __launch_bounds__(256) k_net_wgrad_mx(Geo g, LinkV<float> U, int cin, int cout, const float2* in,
-                                                      const float2* gy, int64_t cs, int sites_per_wg, float* part) {
+                                                      const float2* gy, int64_t cs, int nwx, int sites_per_wg,
+                                                      float* part) {
   extern __shared__ float wl[];
   const int M16 = 16 * ((8 * cout + 15) / 16), N16 = 16 * ((8 * cin + 15) / 16);
   float* gl = wl;                  // [M16][kWgLd]: G[m][k]
   float* tlw = wl + M16 * kWgLd;   // [N16][kWgLd]: T[n][k]
-  const int d = blockIdx.y;
+  int rg, d;
+  wgrad_block(blockIdx.x, nwx, rg, d);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int ntile = (M16 / 16) * (N16 / 16), ntn = N16 / 16;
   f4v acc[TPW];
 #pragma unroll
   for (int q = 0; q < TPW; ++q) acc[q] = f4v{0.f, 0.f, 0.f, 0.f};
-  const int s_begin = blockIdx.x * sites_per_wg, s_end = min(g.V, s_begin + sites_per_wg);
+  const int s_begin = rg * sites_per_wg, s_end = min(g.V, s_begin + sites_per_wg);
   // staging roles: lane t < 16 cin stages the transported input (site t % 16,
   // channel t / 16); every lane stages up to 12 output-gradient elements.  The
   // loads of the next tile are issued before the matrix-core phase of the
@@ -162,8 +179,8 @@ __global__ void __launch_bounds__(256) k_net_wgrad_mx(Geo g, LinkV<float> U, int
       acc[q] = c4;
     }
   }
-  // partial product of this workgroup: part[(wg * 9 + d)][m][n]
-  float* pw = part + ((int64_t)blockIdx.x * 9 + d) * M16 * N16;
+  // partial product of this workgroup: part[(range * 9 + d)][m][n]
+  float* pw = part + ((int64_t)rg * 9 + d) * M16 * N16;
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
     const int t = wv + 4 * q;
@@ -714,11 +731,15 @@ hipError_t launch_net_wgrad(const Geo& g, const LinkV<float>& U, int cin, int co
   const int nwx = wgrad_groups(g.V);
   const int spw = ((g.V + nwx - 1) / nwx + kWgTileSites - 1) / kWgTileSites * kWgTileSites;
   const size_t lds = (size_t)(M16 + N16) * kWgLd * sizeof(float);
-  const dim3 grid(nwx, 9), blk(256);
-  if (tpw <= 2) hipLaunchKernelGGL((k_net_wgrad_mx<2>), grid, blk, lds, st, g, U, cin, cout, in, gy, cs, spw, part);
-  else if (tpw <= 4) hipLaunchKernelGGL((k_net_wgrad_mx<4>), grid, blk, lds, st, g, U, cin, cout, in, gy, cs, spw, part);
-  else if (tpw <= 9) hipLaunchKernelGGL((k_net_wgrad_mx<9>), grid, blk, lds, st, g, U, cin, cout, in, gy, cs, spw, part);
-  else hipLaunchKernelGGL((k_net_wgrad_mx<16>), grid, blk, lds, st, g, U, cin, cout, in, gy, cs, spw, part);
+  const dim3 grid(nwx * 9), blk(256);
+  if (tpw <= 2)
+    hipLaunchKernelGGL((k_net_wgrad_mx<2>), grid, blk, lds, st, g, U, cin, cout, in, gy, cs, nwx, spw, part);
+  else if (tpw <= 4)
+    hipLaunchKernelGGL((k_net_wgrad_mx<4>), grid, blk, lds, st, g, U, cin, cout, in, gy, cs, nwx, spw, part);
+  else if (tpw <= 9)
+    hipLaunchKernelGGL((k_net_wgrad_mx<9>), grid, blk, lds, st, g, U, cin, cout, in, gy, cs, nwx, spw, part);
+  else
+    hipLaunchKernelGGL((k_net_wgrad_mx<16>), grid, blk, lds, st, g, U, cin, cout, in, gy, cs, nwx, spw, part);
   hipLaunchKernelGGL(k_net_wgrad_reduce, dim3((nw + 255) / 256), dim3(256), 0, st, part, nwx, cin, cout, grad);
   return hipGetLastError();
 }

@@ -95,14 +95,16 @@ def test_net_reproduces_wilson_operator(Q, orc):
     assert relerr(to_np(ctx.net_forward(psi)), orc.apply_D(L, U, A0, psi)) < 1e-6
 
 
-@pytest.mark.parametrize("ch", CHS)
-def test_net_loss_gradient_parity(Q, orc, ch):
-    L = (4, 4, 4, 8)
+# 8^4: 32 weight-gradient site ranges, a multiple of 8, so the XCD-grouped
+# workgroup order (not the range-major one) is in effect
+@pytest.mark.parametrize("ch,L", [(c, (4, 4, 4, 8)) for c in CHS] + [(CHS[1], (8, 8, 8, 8))])
+def test_net_loss_gradient_parity(Q, orc, ch, L):
     ctx, U = net_ctx(Q, L, ch, 606)
     W = bf16(S.random_weights(ctx.net_num_weights(), 607, 0.3))
     ctx.net_set_weights(W)
-    r = S.gaussian_field(512, 608, nrhs=3)
-    e = S.gaussian_field(512, 609, nrhs=3)
+    V = int(np.prod(L))
+    r = S.gaussian_field(V, 608, nrhs=3)
+    e = S.gaussian_field(V, 609, nrhs=3)
     loss, grad = ctx.net_loss_grad(r, e)
     loss_o, grad_o = orc.net_loss_grad(L, U, ch, W, r, e)
     eg = relerr(to_np(grad), grad_o)
