@@ -182,7 +182,8 @@ def run_learned(wid: int = 5, train_pairs: int | None = None, chunk_pairs: int =
     eta = np.stack([S.gaussian_field(V, 4000 + r) for r in range(ntest)])
     psi, info, st, dt = timed_solve(ctx, eta)
     out["learned"] = {"solve_s": dt, "iters": [i["iters"] for i in info], "fallbacks": [i["fallbacks"] for i in info],
-                      "true_res_max": max(i["true_res"] for i in info), "converged": all(i["converged"] for i in info)}
+                      "true_res_max": max(i["true_res"] for i in info), "converged": all(i["converged"] for i in info),
+                      "t_ms": info[0]["t_ms"]}
     # the same network applied with activations rounded to one BF16 term (8
     # significant bits) in its products: a cheaper, inexact preconditioner stage
     ctx.net_set_terms(1)
@@ -190,7 +191,7 @@ def run_learned(wid: int = 5, train_pairs: int | None = None, chunk_pairs: int =
     out["learned_terms1"] = {"solve_s": dt, "iters": [i["iters"] for i in info],
                              "fallbacks": [i["fallbacks"] for i in info],
                              "true_res_max": max(i["true_res"] for i in info),
-                             "converged": all(i["converged"] for i in info)}
+                             "converged": all(i["converged"] for i in info), "t_ms": info[0]["t_ms"]}
     ctx.net_set_terms(3)
     ctx.net_set_weights(np.zeros(nw, complex))  # zero network: the stage adds nothing, plain iterates
     psi0, info0, st0, dt0 = timed_solve(ctx, eta)
@@ -203,7 +204,7 @@ def run_learned(wid: int = 5, train_pairs: int | None = None, chunk_pairs: int =
     pctx.dfl_build(init)
     psi1, info1, st1, dt1 = timed_solve(pctx, eta)
     out["plain"] = {"solve_s": dt1, "iters": [i["iters"] for i in info1],
-                    "true_res_max": max(i["true_res"] for i in info1)}
+                    "true_res_max": max(i["true_res"] for i in info1), "t_ms": info1[0]["t_ms"]}
     out["learned_vs_plain_time"] = dt1 / out["learned"]["solve_s"]
     log(f"[w{wid}] learned {out['learned']} plain {out['plain']}")
     return out
