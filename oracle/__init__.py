@@ -273,3 +273,70 @@ def net_loss_grad(L, U, ch, W, r, e, with_grad=True, bc=-1):
     loss = lib().orc_net_loss_grad(_ivec(L), bc, _c(_cc(U)), len(ch) - 1, _ivec(ch), _c(_cc(W)), nb, _c(r), _c(e),
                                    _c(grad) if with_grad else None)
     return loss, grad
+
+
+# ----------------------------------------------------------- mass preconditioning
+# Eq. 2-5: Q = gamma5 D, its even-odd blocks Q_xy = gamma5 D_xy, the Schur
+# complement Q_S = 1 - Q_ee^{-1} Q_eo Q_oo^{-1} Q_oe, W(dm) = Q_S + dm, and the
+# determinant factors det Q_ee, det Q_oo.  Written from those definitions with
+# the full operator of apply_D and numpy's dense solves; nothing here goes
+# through the Schur-complement kernels (apply_Dhat).
+
+def parity(L):
+    """(x0 + x1 + x2 + x3) mod 2 of every site in lex order."""
+    x = np.indices(tuple(int(l) for l in L)).reshape(4, -1)
+    return (x.sum(0) & 1).astype(np.int64)
+
+
+def _sites(L):
+    """lex indices of the even and of the odd sites; the even field index of
+    an even site is lex >> 1, which numbers them 0 .. V/2 - 1 in lex order."""
+    par = parity(L)
+    ev, od = np.nonzero(par == 0)[0], np.nonzero(par == 1)[0]
+    assert np.array_equal(ev >> 1, np.arange(ev.size)) and np.array_equal(od >> 1, np.arange(od.size))
+    return ev, od
+
+
+def gamma5_12():
+    """gamma5 on the 12 components k = 3 spin + colour of a site."""
+    return np.kron(gamma()[4], np.eye(3))
+
+
+def clover_logdet(L, U, kappa, csw, bc=-1):
+    """(log det Q_ee, log det Q_oo) of Eq. 2: Q_ee = gamma5 A_e is site-diagonal
+    and det gamma5 = 1 on a site's 12 components, so log det Q_ee is the sum of
+    log det A(x) over the even sites (likewise odd).  A(x) is Hermitian positive
+    definite for these fields; a non-positive determinant raises."""
+    A, _ = clover(L, U, kappa, csw, bc)
+    sign, ld = np.linalg.slogdet(A)
+    if np.any(np.abs(sign - 1.0) > 1e-9):
+        raise ArithmeticError("clover block with a non-positive determinant")
+    par = parity(L)
+    return float(ld[par == 0].sum()), float(ld[par == 1].sum())
+
+
+def apply_W(L, U, A, dm, pe, bc=-1):
+    """W(dm) pe = Q_S pe + dm pe (Eq. 3), Q_S = 1 - Q_ee^{-1} Q_eo Q_oo^{-1} Q_oe
+    (Eq. 2), on even fields pe (..., V/2, 4, 3); A: the clover of clover()."""
+    pe = _cc(pe)
+    lead = pe.shape[:-3]
+    pe2 = pe.reshape((-1,) + pe.shape[-3:])
+    V = int(np.prod(L))
+    ev, od = _sites(L)
+    g5 = gamma5_12()
+    Qee = g5[None] @ A[ev]  # gamma5 A on the even sites
+    Qoo = g5[None] @ A[od]
+    out = np.empty_like(pe2)
+    for r in range(pe2.shape[0]):
+        full = np.zeros((V, 4, 3), np.complex128)
+        full[ev] = pe2[r]
+        t = apply_D(L, U, A, full, bc).reshape(V, 12)  # D_oe pe on the odd sites
+        q = (g5 @ t[od].T).T                           # Q_oe pe
+        q = np.linalg.solve(Qoo, q[..., None])[..., 0]  # Q_oo^{-1} Q_oe pe
+        full = np.zeros((V, 4, 3), np.complex128)
+        full[od] = q.reshape(-1, 4, 3)
+        t = apply_D(L, U, A, full, bc).reshape(V, 12)  # D_eo (...) on the even sites
+        q = (g5 @ t[ev].T).T                           # Q_eo Q_oo^{-1} Q_oe pe
+        q = np.linalg.solve(Qee, q[..., None])[..., 0]
+        out[r] = pe2[r] - q.reshape(-1, 4, 3) + dm * pe2[r]
+    return out.reshape(lead + pe.shape[-3:])
