@@ -113,6 +113,45 @@ def one_rhs_rates(ctx, src1, cache, cache_path, reps=20):
     return res
 
 
+def action_rates(ctx, src1, reps=20):
+    """Mass-preconditioning calls on the bench lattice (Eqs. 2-3): the clover
+    log determinants (one FP64 reduction over both parities: 2 blocks x 18
+    complex FP64 slots = 576 B per site) and W(dm) = A_e^{-1} Dhat + dm on one
+    FP64 right-hand side (the Dhat bytes of its launch, then 1152 B per even
+    site: the Dhat output, the inverse clover blocks and the input read, the
+    result written).  HIP events on the library stream; each log-det call ends
+    with its own host synchronisation, which its time includes."""
+    import torch
+    from paper_1011_0911_amd import qdd
+
+    st = ctx.stream
+
+    def events_ms(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(n):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    ld = ctx.clover_logdet()
+    ms_ld = events_ms(ctx.clover_logdet, reps)
+    fin = ctx.pack(0, torch.from_numpy(src1), True)
+    fout = ctx.empty_field(0, 1, True)
+    ms_w = events_ms(lambda: ctx.apply_w_packed(1, 0.25, fin, fout), reps)
+    a_b, b_b = bytes_per_site(0, 1, compressed(ctx.get_launch(qdd.KERNEL_DHAT, 0)))
+    w_bytes = (a_b + b_b + 1152) * ctx.Vh
+    ld_bytes = 576 * 2 * ctx.Vh
+    del fin, fout
+    return {"logdet_even": ld[0], "logdet_odd": ld[1], "logdet_ms": round(ms_ld, 5),
+            "logdet_TBs": round(ld_bytes / (ms_ld * 1e-3) / 1e12, 4), "logdet_bytes": ld_bytes,
+            "apply_w_f64_1rhs_ms": round(ms_w, 5), "apply_w_TBs": round(w_bytes / (ms_w * 1e-3) / 1e12, 4),
+            "apply_w_bytes": w_bytes}
+
+
 def cpu_baseline(U, nrhs_gpu, prec_gpu, budget_s=12.0):
     """FP64 oracle Dhat on the same lattice, one rhs per apply, as many applies as
     fit in the time budget; converted to the GPU's unit with its byte model."""
@@ -229,6 +268,7 @@ def main():
     print(f"[bench] launch {launch} (tuned {tuned_ms})", file=sys.stderr, flush=True)
     one_rhs = None if args.no_tune else one_rhs_rates(ctx, src[:1], cache, cache_path)
     ctx.set_launch(qdd.KERNEL_DHAT, prec, *launch)
+    action = action_rates(ctx, src[:1])
 
     st = ctx.stream
     for _ in range(args.warmup):
@@ -288,7 +328,7 @@ def main():
                    "frac_of_peak_whole_apply": round(value / PEAK_HBM_TBS, 4),
                    "pass_a": {"ms": round(ms_a, 5), "TBs": round(ach_a, 4)},
                    "copy_reference_TBs": round(copy_tbs, 4), "copy_bytes": nb, "wall_s_timed": round(wall, 3),
-                   "one_rhs": one_rhs},
+                   "one_rhs": one_rhs, "mass_preconditioning": action},
         "roofline": {"bound": "hbm", "kernel": "k_dhat_b (pass B)", "achieved": round(ach_b, 4),
                      "peak": PEAK_HBM_TBS, "unit": "TB/s", "frac": round(ach_b / PEAK_HBM_TBS, 4),
                      "traffic": traffic, "bytes_per_launch": b_b * Vh, "ms_per_launch": round(ms_b, 5)},

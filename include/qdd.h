@@ -204,6 +204,25 @@ qdd_status qdd_solve_multi(qdd_ctx* const* ctxs, int nsys, const int* nrhs, cons
 /* Solves Dhat psi_e = eta_e (canonical even fields) with unpreconditioned FP64 FGCR. */
 qdd_status qdd_solve_dhat(qdd_ctx* ctx, int nrhs, const double* eta_e, double* psi_e, qdd_solve_info* info);
 
+/* ---- mass preconditioning (Sect. 2, Eqs. 2-5) ----
+ * With Q = gamma5 D, Eq. 2 factorises det Q = det Q_ee det Q_oo det Q_S,
+ * Q_S = 1 - Q_ee^{-1} Q_eo Q_oo^{-1} Q_oe, and Eq. 3 introduces
+ * W(dm) = Q_S + dm; the effective action of Eq. 4 carries
+ * -2 (log det Q_ee + log det Q_oo). */
+/* *logdet_even, *logdet_odd (host) = log det Q_ee and log det Q_oo of the
+ * current operator (qdd_set_params): the sums over the even and over the odd
+ * sites of log det A(x) (det gamma5 = 1 on a site's 12 components), from the
+ * Cholesky factors of the FP64 clover blocks, summed in a fixed order
+ * (deterministic).  Synchronises.  QDD_ESTATE before qdd_set_params,
+ * QDD_ESINGULAR if a block is not positive definite. */
+qdd_status qdd_clover_logdet(qdd_ctx* ctx, double* logdet_even, double* logdet_odd);
+/* out_e = W(dm) in_e = Q_S in_e + dm in_e (Eq. 3) on packed FP64 even fields
+ * (qdd_pack_field, prec F64, even_only 1), nrhs right-hand sides.  Since the
+ * gamma5 factors cancel, Q_S = A_e^{-1} Dhat: the FP64 Dhat apply, then the
+ * even-site inverse clover blocks and the shift.  in_e and out_e must not
+ * overlap (QDD_EINVAL otherwise); QDD_ESTATE before qdd_set_params. */
+qdd_status qdd_apply_w(qdd_ctx* ctx, int nrhs, double dm, const void* in_e, void* out_e);
+
 /* ---- learned preconditioner stage (configuration use_net = 1) ----
  * A gauge-covariant parallel-transport convolution network N with net_nl
  * layers and channels net_ch[0..nl]; layer: out_c(x) = sum_{c',d} W[d][c][c']

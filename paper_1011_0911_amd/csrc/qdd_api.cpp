@@ -547,3 +547,40 @@ hipError_t qdd_ctx::dw(qdd_prec prec, int nrhs, void* in, void* out) {
     default: return launch_dw<__half>(G, op<__half>(), a.f16, b.f16, a.poff, a.spoff, nrhs, c, st);
   }
 }
+
+// ------------------------------------------------------------ mass preconditioning
+qdd_status qdd_clover_logdet(qdd_ctx* x, double* logdet_even, double* logdet_odd) {
+  if (!x || !logdet_even || !logdet_odd) {
+    if (x) x->fail("qdd_clover_logdet: invalid arguments");
+    return QDD_EINVAL;
+  }
+  if (!x->have_clover) { x->fail("qdd_clover_logdet before qdd_set_params"); return QDD_ESTATE; }
+  const int nb = clover_logdet_blocks(x->G.Vh);
+  double* part = x->ptr<double>(x->lo.part);
+  std::vector<double> h(2 * (size_t)nb);
+  HCK(x, launch_clover_logdet(x->G, x->op<double>().A, part, x->st));
+  HCK(x, hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, x->st));
+  HCK(x, hipStreamSynchronize(x->st));
+  double s[2] = {0.0, 0.0};
+  for (int p = 0; p < 2; ++p)
+    for (int b = 0; b < nb; ++b) s[p] += h[(size_t)p * nb + b];  // fixed order: deterministic
+  if (!std::isfinite(s[0]) || !std::isfinite(s[1])) {
+    x->fail("qdd_clover_logdet: a clover block is not positive definite");
+    return QDD_ESINGULAR;
+  }
+  *logdet_even = s[0];
+  *logdet_odd = s[1];
+  return QDD_OK;
+}
+
+qdd_status qdd_apply_w(qdd_ctx* x, int nrhs, double dm, const void* in, void* out) {
+  if (!x || !in || !out || in == out || nrhs < 1 || nrhs > x->cfg.max_nrhs || !std::isfinite(dm)) {
+    if (x) x->fail("qdd_apply_w: invalid arguments");
+    return QDD_EINVAL;
+  }
+  if (!x->have_clover) { x->fail("qdd_apply_w before qdd_set_params"); return QDD_ESTATE; }
+  HCK(x, x->dhat(QDD_F64, nrhs, (void*)in, out));
+  PackedView vi = x->packed(QDD_F64, nrhs, 1, (void*)in), vo = x->packed(QDD_F64, nrhs, 1, out);
+  HCK(x, launch_apply_w_finish(x->G, vi.f64, vo.f64, x->op<double>().Ainv, nrhs, dm, x->st));
+  return QDD_OK;
+}

@@ -73,4 +73,13 @@ hipError_t launch_field_convert(FieldV<SI> in, FieldV<SO> out, int nvec, hipStre
 hipError_t launch_clover(const Geo& g, const double2* U, double diag, double csw, double2* A, double2* Ai, int* bad,
                          hipStream_t st);
 
+// ---- mass preconditioning (qdd_action.hip)
+// part[p * nb + b], nb = clover_logdet_blocks(Vh): partial sums over parity p of
+// log det A(x) (NaN where a block is not positive definite)
+int clover_logdet_blocks(int64_t Vh);
+hipError_t launch_clover_logdet(const Geo& g, const CloverV<double>& A, double* part, hipStream_t st);
+// out = A_e^{-1} out + dm in on even sites, nrhs right-hand sides (out holding Dhat in)
+hipError_t launch_apply_w_finish(const Geo& g, const FieldV<double>& in, const FieldV<double>& out,
+                                 const CloverV<double>& Ai, int nrhs, double dm, hipStream_t st);
+
 }  // namespace qdd

@@ -74,6 +74,8 @@ SIGNATURES = {
     "qdd_pack_field": (_i, [_vp, _i, _i, _i, _vp, _vp]),
     "qdd_unpack_field": (_i, [_vp, _i, _i, _i, _vp, _vp]),
     "qdd_dw_hat": (_i, [_vp, _i, _i, _vp, _vp]),
+    "qdd_clover_logdet": (_i, [_vp, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
+    "qdd_apply_w": (_i, [_vp, _i, _d, _vp, _vp]),
     "qdd_dw": (_i, [_vp, _i, _i, _vp, _vp]),
     "qdd_dw_masses": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
     "qdd_sap": (_i, [_vp, _i, _vp, _vp]),
@@ -219,6 +221,25 @@ class Context:
     # -- operators on packed fields
     def dw_hat(self, prec, nrhs, fin, fout):
         self._check(lib().qdd_dw_hat(self.h, prec, nrhs, _ptr(fin), _ptr(fout)))
+
+    def clover_logdet(self):
+        """(log det Q_ee, log det Q_oo) of the current operator (Eq. 2)."""
+        le, lo = _d(), _d()
+        self._check(lib().qdd_clover_logdet(self.h, ctypes.byref(le), ctypes.byref(lo)))
+        return le.value, lo.value
+
+    def apply_w_packed(self, nrhs, dm, fin, fout):
+        """fout = W(dm) fin = Q_S fin + dm fin (Eq. 3) on packed FP64 even fields."""
+        self._check(lib().qdd_apply_w(self.h, nrhs, float(dm), _ptr(fin), _ptr(fout)))
+
+    def apply_w(self, dm, psi_e):
+        """W(dm) on canonical even fields (pack, apply, unpack)."""
+        c = self._c128(psi_e)
+        nrhs = c.numel() // (self.Vh * 12)
+        fi = self.pack(F64, c, True)
+        fo = self.empty_field(F64, nrhs, True)
+        self.apply_w_packed(nrhs, dm, fi, fo)
+        return self.unpack(F64, fo, nrhs, True)
 
     def dw(self, prec, nrhs, fin, fout):
         self._check(lib().qdd_dw(self.h, prec, nrhs, _ptr(fin), _ptr(fout)))
