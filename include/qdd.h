@@ -222,6 +222,13 @@ qdd_status qdd_clover_logdet(qdd_ctx* ctx, double* logdet_even, double* logdet_o
  * even-site inverse clover blocks and the shift.  in_e and out_e must not
  * overlap (QDD_EINVAL otherwise); QDD_ESTATE before qdd_set_params. */
 qdd_status qdd_apply_w(qdd_ctx* ctx, int nrhs, double dm, const void* in_e, void* out_e);
+/* out_e = Q_S^{-1} phi_e by Eq. 5, Q_S^{-1} = P_e Q^{-1} Q_ee P_e: the configured
+ * solver (as qdd_solve: FP64 flexible GCR, with deflation and SAP when
+ * configured) solves D psi = (A_e phi_e on the even sites, 0 on the odd ones)
+ * and out_e is the even half of psi.  phi_e, out_e: canonical complex128 even
+ * fields (device), nrhs of them; info as for qdd_solve (the residual is that of
+ * D).  Errors as for qdd_solve. */
+qdd_status qdd_solve_qs(qdd_ctx* ctx, int nrhs, const double* phi_e, double* out_e, qdd_solve_info* info);
 
 /* ---- learned preconditioner stage (configuration use_net = 1) ----
  * A gauge-covariant parallel-transport convolution network N with net_nl

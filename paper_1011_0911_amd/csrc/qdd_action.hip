@@ -118,4 +118,28 @@ hipError_t launch_apply_w_finish(const Geo& g, const FieldV<double>& in, const F
   return hipGetLastError();
 }
 
+// even part of the source of Eq. 5: eta_e = A_e phi (phi a canonical even field,
+// [rhs][site][12] complex, its site index that of the packed even sites); one
+// lane per (site, rhs).  The odd part of eta is zeroed by the caller.
+__global__ void __launch_bounds__(256) k_qs_source(const double2* phi, FieldV<double> eta, CloverV<double> A,
+                                                   int nrhs, int Vh) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)Vh * nrhs) return;
+  const int r = (int)(t / Vh), i = (int)(t % Vh);
+  const double2* src = phi + t * 12;
+  cx<double> v[12], y[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) v[k] = {src[k].x, src[k].y};
+  clover_apply<double>(A, 0, i, v, y);
+  st_spinor<double>(eta, r, i, y);
+}
+
+hipError_t launch_qs_source(const Geo& g, const double* phi_c, const FieldV<double>& eta, const CloverV<double>& A,
+                            int nrhs, hipStream_t st) {
+  const int64_t n = (int64_t)g.Vh * nrhs;
+  hipLaunchKernelGGL(k_qs_source, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const double2*)phi_c, eta, A,
+                     nrhs, g.Vh);
+  return hipGetLastError();
+}
+
 }  // namespace qdd

@@ -81,5 +81,9 @@ hipError_t launch_clover_logdet(const Geo& g, const CloverV<double>& A, double* 
 // out = A_e^{-1} out + dm in on even sites, nrhs right-hand sides (out holding Dhat in)
 hipError_t launch_apply_w_finish(const Geo& g, const FieldV<double>& in, const FieldV<double>& out,
                                  const CloverV<double>& Ai, int nrhs, double dm, hipStream_t st);
+// even sites of the full field eta (view with parity 0 at its base) = A_e phi,
+// phi canonical even complex128 [rhs][site][4][3] (device)
+hipError_t launch_qs_source(const Geo& g, const double* phi_c, const FieldV<double>& eta, const CloverV<double>& A,
+                            int nrhs, hipStream_t st);
 
 }  // namespace qdd

@@ -315,6 +315,40 @@ extern "C" qdd_status qdd_solve(qdd_ctx* x, int nrhs, const double* eta_c, doubl
   return s;
 }
 
+// Q_S^{-1} phi = P_e Q^{-1} Q_ee P_e phi (Eq. 5) = [D^{-1} (A_e phi (+) 0)]_e: the
+// source A_e phi on the even sites and 0 on the odd ones goes straight into the
+// solver's packed source field, the configured solver (deflated SAP-GCR or
+// the plain method) solves D psi = eta, and the even half of psi is returned.
+extern "C" qdd_status qdd_solve_qs(qdd_ctx* x, int nrhs, const double* phi_c, double* out_c, qdd_solve_info* info) {
+  if (!x || !phi_c || !out_c || nrhs < 1 || nrhs > x->cfg.max_nrhs) {
+    if (x) x->fail("qdd_solve_qs: invalid arguments");
+    return QDD_EINVAL;
+  }
+  if (!x->have_clover) { x->fail("qdd_solve_qs before qdd_set_params"); return QDD_ESTATE; }
+  if (x->cfg.precond == QDD_PRECOND_DFL && !x->have_dfl) {
+    x->fail("deflated solve before qdd_dfl_build");
+    return QDD_ESTATE;
+  }
+  const Layout& lo = x->lo;
+  const int64_t n = (int64_t)24 * x->G.Vh;
+  double2 *eta = x->ptr<double2>(lo.eta), *psi = x->ptr<double2>(lo.psi);
+  PackedView pe = x->packed(QDD_F64, nrhs, 0, eta);
+  HCK(x, hipMemsetAsync(eta, 0, (size_t)nrhs * n * sizeof(double2), x->st));
+  HCK(x, launch_qs_source(x->G, phi_c, pe.f64, x->op<double>().A, nrhs, x->st));
+  FgcrOps F;
+  x->fallbacks.assign(nrhs, 0);
+  x->coarse_iters = 0;
+  qdd_status s0 = make_solver_ops(x, nrhs, F);
+  if (s0 != QDD_OK) return s0;
+  F.fallbacks = x->fallbacks.data();
+  F.hv = nullptr;
+  qdd_status s = run_fgcr(x, F, eta, psi, info);
+  PackedView pp = x->packed(QDD_F64, nrhs, 0, psi);
+  HCK(x, launch_unpack_spinor<double>(x->G, pp.f64, out_c, nrhs, 1, pp.poff, pp.spoff, x->st));
+  HCK(x, hipStreamSynchronize(x->st));
+  return s;
+}
+
 // Plain solve of one right-hand side that records a (residual, error) pair at
 // every outer iteration: r_k = eta - D psi_k (the recursive residual) and
 // e_k = psi* - psi_k, both returned as packed FP32 full fields (training data of

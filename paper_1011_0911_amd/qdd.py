@@ -96,6 +96,7 @@ SIGNATURES = {
     "qdd_net_train_step": (_i, [_vp, _i, _vp, _vp, ctypes.c_float, ctypes.POINTER(_d)]),
     "qdd_solve_harvest": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _i, ctypes.POINTER(_i), _vp]),
     "qdd_solve_dhat": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "qdd_solve_qs": (_i, [_vp, _i, _vp, _vp, _vp]),
     "qdd_set_launch": (_i, [_vp, _i, _i, _i, _i, _i, _i]),
     "qdd_get_launch": (_i, [_vp, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i),
                             ctypes.POINTER(_i)]),
@@ -325,6 +326,17 @@ class Context:
         out = torch.empty((nrhs, self.V, 4, 3), dtype=torch.complex128, device=self.device)
         info = (SolveInfo * nrhs)()
         st = lib().qdd_solve(self.h, nrhs, _ptr(c), _ptr(out), info)
+        if check:
+            self._check(st)
+        return out, [i.as_dict() for i in info], st
+
+    def solve_qs(self, phi_e, check=True):
+        """Q_S^{-1} phi_e (Eq. 5) on canonical even fields through the configured solver."""
+        c = self._c128(phi_e)
+        nrhs = c.numel() // (self.Vh * 12)
+        out = torch.empty((nrhs, self.Vh, 4, 3), dtype=torch.complex128, device=self.device)
+        info = (SolveInfo * nrhs)()
+        st = lib().qdd_solve_qs(self.h, nrhs, _ptr(c), _ptr(out), info)
         if check:
             self._check(st)
         return out, [i.as_dict() for i in info], st

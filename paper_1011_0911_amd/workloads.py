@@ -94,6 +94,15 @@ def run_solve_workload(wid: int, plain_rhs: int = 1, log=print, U=None):
                     "true_res_max": max(i["true_res"] for i in info), "converged": all(i["converged"] for i in info),
                     "sap_prec": {0: "f64", 1: "f32", 2: "f16"}[ctx.cfg.sap_prec]}
     log(f"[w{wid}] mixed: {out['mixed']}")
+    # Q_S^{-1} (Eq. 5) on fresh even sources through the same solver and subspace
+    phi = S.gaussian_field_device(V // 2, 6000, nrhs)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    _, qinfo, _ = ctx.solve_qs(phi, check=False)
+    torch.cuda.synchronize()
+    out["qs_inverse"] = {"solve_s": time.time() - t0, "iters": [i["iters"] for i in qinfo],
+                         "converged": all(i["converged"] for i in qinfo)}
+    log(f"[w{wid}] Q_S inverse: {out['qs_inverse']}")
     del ctx
     torch.cuda.empty_cache()
     if plain_rhs <= 0:

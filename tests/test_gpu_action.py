@@ -66,3 +66,27 @@ def test_apply_w_rejects_aliasing_and_bad_shift(Q):
     assert lib.qdd_apply_w(ctx.h, 1, 0.1, Q._ptr(f), Q._ptr(f)) == Q.QDD_EINVAL
     assert lib.qdd_apply_w(ctx.h, 1, float("nan"), Q._ptr(f), Q._ptr(g)) == Q.QDD_EINVAL
     assert lib.qdd_apply_w(ctx.h, 1, 0.1, Q._ptr(f), Q._ptr(g)) == Q.QDD_OK
+
+
+@pytest.mark.parametrize("deflated", [False, True])
+def test_solve_qs_eq5(Q, orc, deflated):
+    # Q_S^{-1} phi through Eq. 5 with the configured solver, checked by the
+    # residual of the oracle's Q_S (the paper's form from the blocks of Q).  The
+    # D solve stops at relative residual 1e-10; on the even sites that becomes a
+    # Q_S residual of at most about cond(A) (1 + |D_eo A_o^{-1}|) 1e-10 ~ 1e-9
+    L, BS = (8, 8, 8, 8), (4, 4, 4, 4)
+    V = int(np.prod(L))
+    kw = dict(max_nrhs=2)
+    if deflated:
+        kw.update(sap_bs=BS, sap_prec=1, dfl_Ns=8, dfl_bs=BS, dfl_nit=3, precond=Q.PRECOND_DFL)
+    ctx, U = make_ctx(Q, L, 0.6, 0.1357, 1.9, 708, **kw)
+    A, _ = orc.clover(L, U, 0.1357, 1.9)
+    if deflated:
+        ctx.dfl_build(S.gaussian_field(V, 709, nrhs=8))
+    phi = S.gaussian_field(V // 2, 710, nrhs=2)
+    x, info, st = ctx.solve_qs(phi)
+    x = to_np(x)
+    for r in range(2):
+        res = np.linalg.norm(orc.apply_W(L, U, A, 0.0, x[r]) - phi[r]) / np.linalg.norm(phi[r])
+        print("deflated", deflated, "rhs", r, "iters", info[r]["iters"], "Q_S residual", res)
+        assert info[r]["converged"] and res < 1e-8
