@@ -305,6 +305,21 @@ qdd_status qdd_autotune(qdd_ctx* ctx, int kernel, qdd_prec prec, int nrhs, const
 qdd_status qdd_dw_hat_timed(qdd_ctx* ctx, qdd_prec prec, int nrhs, const void* in_e, void* out_e, int reps,
                             float* ms_pass_a, float* ms_pass_b);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same apply as
+ * qdd_dw_hat (same kernels, bit-identical result), but the odd-site
+ * intermediate of the two passes lives in a static device array of the library
+ * (64 MiB per GPU, held from the first call on a GPU until the process ends)
+ * instead of the context's workspace.  It needs nrhs * V/2 * 12 complex
+ * elements of the precision (plus one FP32 scale per site and rhs for F16,
+ * after a 256-byte aligned offset); QDD_EINVAL if that exceeds 64 MiB, or if
+ * the current device is not the context's.  Calls no allocating routine.
+ * Every call on one GPU shares the array: calls that overlap on one GPU (on
+ * different streams, or from several host threads) race; calls ordered on one
+ * stream do not.  Nothing needs clearing between calls (pass A writes all of
+ * the intermediate before pass B reads it). */
+qdd_status qdd_dw_hat_static(qdd_ctx* ctx, qdd_prec prec, int nrhs, const void* in_e, void* out_e);
+
 /* Plain device-to-device copy of `bytes` (multiple of 16) with 16-byte vector
  * loads and stores on `stream`: the HBM bandwidth reference of the benchmarks. */
 qdd_status qdd_copy(void* dst, const void* src, size_t bytes, void* stream);

@@ -269,7 +269,13 @@ qdd_status qdd_create(const qdd_geom* g, const qdd_config* c, void* ws, size_t w
     qdd_ctx::last_global() = "workspace must be 256-byte aligned";
     return QDD_EINVAL;
   }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    qdd_ctx::last_global() = "hipGetDevice failed";
+    return QDD_EHIP;
+  }
   qdd_ctx* x = new qdd_ctx();
+  x->device = dev;
   x->geom = *g;
   x->cfg = *c;
   x->lo = Lo;
@@ -514,25 +520,39 @@ PackedView qdd_ctx::packed(qdd_prec prec, int nrhs, int even_only, void* field) 
   return v;
 }
 
-hipError_t qdd_ctx::dhat(qdd_prec prec, int nrhs, void* in, void* out, hipEvent_t mid) {
+size_t qdd_ctx::dhat_tmp_bytes(qdd_prec prec, int nrhs, size_t* scale_off) const {
+  // values [12][Vh][nrhs] (or [12][Vh] for one rhs), then the FP16 scales at a
+  // 256-byte aligned offset
+  const size_t vals = (size_t)nrhs * 12 * G.Vh * (prec == QDD_F64 ? 16 : prec == QDD_F32 ? 8 : 4);
+  const size_t so = (vals + 255) & ~size_t(255);
+  if (scale_off) *scale_off = so;
+  return prec == QDD_F16 ? so + (size_t)nrhs * G.Vh * 4 : vals;
+}
+
+hipError_t qdd_ctx::dhat(qdd_prec prec, int nrhs, void* in, void* out, hipEvent_t mid, void* tmp) {
   PackedView a = packed(prec, nrhs, 1, in), b = packed(prec, nrhs, 1, out);
   int64_t n = G.Vh;
   const LaunchCfg& c = launch[0][prec];
-  // the odd-site intermediate in the layout of the operands
+  // the odd-site intermediate in the layout of the operands: in the workspace,
+  // or in the buffer the caller names (dhat_tmp_bytes bytes)
+  char* tv = tmp ? (char*)tmp : ptr<char>(lo.tmp_o);
+  size_t so = 0;
+  dhat_tmp_bytes(prec, nrhs, &so);
+  float* ts = tmp ? (float*)(tv + so) : ptr<float>(lo.tmp_o_scale);
   const bool il = nrhs > 1;
   const int64_t trs = il ? 1 : 12 * n, tsrs = il ? 1 : n;
   const int tn = il ? (int)(n * nrhs) : (int)n, tss = il ? nrhs : 1;
   switch (prec) {
     case QDD_F64: {
-      FieldV<double> t{ptr<double2>(lo.tmp_o), nullptr, trs, tsrs, tn, tss, tss};
+      FieldV<double> t{(double2*)tv, nullptr, trs, tsrs, tn, tss, tss};
       return launch_dhat<double>(G, op<double>(), a.f64, t, b.f64, nrhs, c, st, 3, mid);
     }
     case QDD_F32: {
-      FieldV<float> t{ptr<float2>(lo.tmp_o), nullptr, trs, tsrs, tn, tss, tss};
+      FieldV<float> t{(float2*)tv, nullptr, trs, tsrs, tn, tss, tss};
       return launch_dhat<float>(G, op<float>(), a.f32, t, b.f32, nrhs, c, st, 3, mid);
     }
     default: {
-      FieldV<__half> t{ptr<__half2>(lo.tmp_o), ptr<float>(lo.tmp_o_scale), trs, tsrs, tn, tss, tss};
+      FieldV<__half> t{(__half2*)tv, ts, trs, tsrs, tn, tss, tss};
       return launch_dhat<__half>(G, op<__half>(), a.f16, t, b.f16, nrhs, c, st, 3, mid);
     }
   }

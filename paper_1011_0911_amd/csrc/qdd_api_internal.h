@@ -50,6 +50,7 @@ struct qdd_ctx {
   qdd::Layout lo;
   char* ws = nullptr;
   hipStream_t st = nullptr;
+  int device = 0;  // HIP device current at qdd_create
   bool have_gauge = false, have_clover = false, have_dfl = false, have_net = false;
   double kappa = 0, csw = 0;
   long coarse_iters = 0;  // little-operator GCR iterations since the last solve began
@@ -73,7 +74,10 @@ struct qdd_ctx {
                          qdd::CloverV<S>{ptr<E>(lo.Ai[p]), G.Vh}};
   }
   qdd::PackedView packed(qdd_prec prec, int nrhs, int even_only, void* field) const;
-  hipError_t dhat(qdd_prec prec, int nrhs, void* in, void* out, hipEvent_t mid = nullptr);
+  // tmp: device buffer of dhat_tmp_bytes() for the odd-site intermediate (nullptr:
+  // the workspace's)
+  hipError_t dhat(qdd_prec prec, int nrhs, void* in, void* out, hipEvent_t mid = nullptr, void* tmp = nullptr);
+  size_t dhat_tmp_bytes(qdd_prec prec, int nrhs, size_t* scale_off = nullptr) const;
   hipError_t dw(qdd_prec prec, int nrhs, void* in, void* out);
 };
 

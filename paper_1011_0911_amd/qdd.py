@@ -74,6 +74,7 @@ SIGNATURES = {
     "qdd_pack_field": (_i, [_vp, _i, _i, _i, _vp, _vp]),
     "qdd_unpack_field": (_i, [_vp, _i, _i, _i, _vp, _vp]),
     "qdd_dw_hat": (_i, [_vp, _i, _i, _vp, _vp]),
+    "qdd_dw_hat_static": (_i, [_vp, _i, _i, _vp, _vp]),
     "qdd_clover_logdet": (_i, [_vp, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "qdd_apply_w": (_i, [_vp, _i, _d, _vp, _vp]),
     "qdd_dw": (_i, [_vp, _i, _i, _vp, _vp]),
@@ -222,6 +223,11 @@ class Context:
     # -- operators on packed fields
     def dw_hat(self, prec, nrhs, fin, fout):
         self._check(lib().qdd_dw_hat(self.h, prec, nrhs, _ptr(fin), _ptr(fout)))
+
+    def dw_hat_static(self, prec, nrhs, fin, fout):
+        """As dw_hat, with the odd-site intermediate in the library's static device
+        scratch (no workspace use; for callers that cannot allocate)."""
+        self._check(lib().qdd_dw_hat_static(self.h, prec, nrhs, _ptr(fin), _ptr(fout)))
 
     def clover_logdet(self):
         """(log det Q_ee, log det Q_oo) of the current operator (Eq. 2)."""
