@@ -254,15 +254,29 @@ void apply_Dhat(const Geom& g, const cplx* U, const cplx* A, const cplx* Ainv, c
   }
 }
 
+// sum_i conj(a_i) b_i over 64 fixed index ranges, each summed in index order,
+// then the range sums in range order: the rounding does not depend on the
+// thread count or schedule, so equal inputs give equal results
 cplx dot(const cplx* a, const cplx* b, int64_t n) {
-  double re = 0, im = 0;
-#pragma omp parallel for reduction(+ : re, im) schedule(static)
-  for (int64_t i = 0; i < n; ++i) {
-    cplx p = std::conj(a[i]) * b[i];
-    re += p.real();
-    im += p.imag();
+  constexpr int64_t kParts = 64;
+  double re[kParts], im[kParts];
+#pragma omp parallel for schedule(static)
+  for (int64_t c = 0; c < kParts; ++c) {
+    double sr = 0, si = 0;
+    for (int64_t i = n * c / kParts; i < n * (c + 1) / kParts; ++i) {
+      cplx p = std::conj(a[i]) * b[i];
+      sr += p.real();
+      si += p.imag();
+    }
+    re[c] = sr;
+    im[c] = si;
   }
-  return cplx(re, im);
+  double sr = 0, si = 0;
+  for (int64_t c = 0; c < kParts; ++c) {
+    sr += re[c];
+    si += im[c];
+  }
+  return cplx(sr, si);
 }
 
 double norm2(const cplx* a, int64_t n) { return dot(a, a, n).real(); }
