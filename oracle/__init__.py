@@ -23,6 +23,7 @@ _lib = None
 _d = ctypes.POINTER(ctypes.c_double)
 _i = ctypes.POINTER(ctypes.c_int)
 _vp = ctypes.c_void_p
+_l = ctypes.POINTER(ctypes.c_int64)
 
 
 def build() -> None:
@@ -46,6 +47,11 @@ def lib():
             "orc_apply_Dhat": (None, [_i, ctypes.c_int, _d, _d, _d, _d, _d]),
             "orc_sap": (None, [_i, ctypes.c_int, _d, _d, _d, _i, ctypes.c_int, ctypes.c_int, _d, _d]),
             "orc_sap_half_sweep": (None, [_i, ctypes.c_int, _d, _d, _d, _i, ctypes.c_int, ctypes.c_int, _d, _d, _d]),
+            "orc_sap_one_cycle_on_blocks": (ctypes.c_int, [_i, ctypes.c_int, _d, _d, _d, _i, ctypes.c_int, _d, _l,
+                                                           ctypes.c_int, _d]),
+            "orc_dfl_set_fields_on_blocks": (None, [_vp, _d, _d, _d, _l, ctypes.c_int]),
+            "orc_net_forward_on_sites": (None, [_i, ctypes.c_int, _d, ctypes.c_int, _i, _d, _d, _l, ctypes.c_int,
+                                                _d]),
             "orc_dfl_new": (_vp, [_i, ctypes.c_int, _i, ctypes.c_int]),
             "orc_dfl_free": (None, [_vp]),
             "orc_dfl_nblocks": (ctypes.c_int64, [_vp]),
@@ -58,6 +64,8 @@ def lib():
             "orc_dfl_coarse_apply": (None, [_vp, _d, _d]),
             "orc_dfl_coarse_solve": (ctypes.c_int, [_vp, _d, _d, ctypes.c_double]),
             "orc_dfl_precond": (None, [_vp, _d, _d, _d, _i, ctypes.c_int, ctypes.c_int, ctypes.c_double, _d, _d]),
+            "orc_dfl_net_precond": (ctypes.c_int, [_vp, _d, _d, _d, _i, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                                   ctypes.c_int, _i, _d, _d, _d]),
             "orc_fgcr": (ctypes.c_int, [_i, ctypes.c_int, _d, _d, _d, ctypes.c_int, ctypes.c_int, _i, ctypes.c_int,
                                         ctypes.c_int, _vp, ctypes.c_double, ctypes.c_int, _i, _d, _d, _d,
                                         ctypes.c_int, ctypes.c_int, ctypes.c_double, _i, _d, _d, ctypes.c_int, _i]),
@@ -77,6 +85,10 @@ def lib():
 def _c(a: np.ndarray):
     assert a.dtype == np.complex128 and a.flags["C_CONTIGUOUS"], (a.dtype, a.flags)
     return a.ctypes.data_as(_d)
+
+
+def _lvec(v):
+    return (ctypes.c_int64 * len(v))(*[int(x) for x in v])
 
 
 def _ivec(v):
@@ -151,6 +163,26 @@ def sap_half_sweep(L, U, A, Ai, bs, nmr, col, eta, psi, rho, bc=-1):
     return psi, rho
 
 
+def sap_one_cycle_on_blocks(L, U, A, Ai, eta, bs, nmr, blocks, bc=-1):
+    """One Schwarz cycle (ncy = 1) evaluated on the listed colour-1 blocks and their
+    face neighbours only; equals sap(..., ncy=1, ...) there (zero elsewhere)."""
+    eta = _cc(eta)
+    out = np.zeros_like(eta)
+    st = lib().orc_sap_one_cycle_on_blocks(_ivec(L), bc, _c(_cc(U)), _c(_cc(A)), _c(_cc(Ai)), _ivec(bs), nmr,
+                                           _c(eta), _lvec(blocks), len(blocks), _c(out))
+    if st != 0:
+        raise ValueError("blocks must be of colour 1 with colour-0 face neighbours")
+    return out
+
+
+def net_forward_on_sites(L, U, ch, W, x, sites, bc=-1):
+    """Network output (one channel) at the listed sites only, shape (len(sites), 4, 3)."""
+    out = np.zeros((len(sites), 4, 3), np.complex128)
+    lib().orc_net_forward_on_sites(_ivec(L), bc, _c(_cc(U)), len(ch) - 1, _ivec(ch), _c(_cc(W)), _c(_cc(x)),
+                                   _lvec(sites), len(sites), _c(out))
+    return out
+
+
 class Deflation:
     """Local deflation subspace + little Dirac operator (oracle)."""
 
@@ -174,6 +206,12 @@ class Deflation:
 
     def set_fields(self, U, A, fields):
         lib().orc_dfl_set_fields(self.h, _c(_cc(U)), _c(_cc(A)), _c(_cc(fields)))
+
+    def set_fields_on_blocks(self, U, A, fields, blocks):
+        """set_fields restricted to the listed blocks: their basis (with their face
+        neighbours') is orthonormalised and their little-operator rows computed."""
+        lib().orc_dfl_set_fields_on_blocks(self.h, _c(_cc(U)), _c(_cc(A)), _c(_cc(fields)), _lvec(blocks),
+                                           len(blocks))
 
     def basis(self):
         out = np.zeros((self.Ns, self.V, 4, 3), np.complex128)
@@ -210,6 +248,15 @@ class Deflation:
         lib().orc_dfl_precond(self.h, _c(_cc(U)), _c(_cc(A)), _c(_cc(Ai)), _ivec(sap_bs), ncy, nmr, coarse_tol,
                               _c(_cc(r)), _c(out))
         return out
+
+    def net_precond(self, U, A, Ai, sap_bs, ncy, nmr, coarse_tol, ch, W, r):
+        """Two-level preconditioner with the network stage N (channels ch, weights W):
+        returns (C r + N(r1) + M_sap(r2), fallback), r1 = r - D C r, r2 = r1 - D N(r1);
+        on fallback (|r2| > |r1| or not finite) N is dropped and r2 = r1."""
+        out = np.zeros((self.V, 4, 3), np.complex128)
+        fb = lib().orc_dfl_net_precond(self.h, _c(_cc(U)), _c(_cc(A)), _c(_cc(Ai)), _ivec(sap_bs), ncy, nmr,
+                                       coarse_tol, len(ch) - 1, _ivec(ch), _c(_cc(W)), _c(_cc(r)), _c(out))
+        return out, bool(fb)
 
 
 def fgcr(L, U, A, Ai, eta, *, op="D", prec="none", sap_bs=(4, 4, 4, 4), ncy=5, nmr=4, dfl=None,

@@ -66,6 +66,15 @@ void orc_sap_half_sweep(const int* L, int bc, const double* U, const double* A, 
   sap_half_sweep(g, CC(U), CC(A), CC(Ainv), bs, nmr, col, CC(eta), C(psi), C(rho));
 }
 
+// psi = the first Schwarz cycle (ncy = 1) on the listed colour-1 blocks and their
+// face neighbours (see sap_one_cycle_on_blocks); returns -1 on a bad block list
+int orc_sap_one_cycle_on_blocks(const int* L, int bc, const double* U, const double* A, const double* Ainv,
+                                const int* bs, int nmr, const double* eta, const int64_t* blocks, int nblocks,
+                                double* psi) {
+  Geom g(L, bc);
+  return sap_one_cycle_on_blocks(g, CC(U), CC(A), CC(Ainv), bs, nmr, CC(eta), blocks, nblocks, C(psi));
+}
+
 // ---- deflation handle ----
 void* orc_dfl_new(const int* L, int bc, const int* bs, int Ns) {
   Geom* g = new Geom(L, bc);
@@ -85,6 +94,11 @@ void orc_dfl_build(void* h, const double* U, const double* A, const double* Ainv
 void orc_dfl_set_fields(void* h, const double* U, const double* A, const double* fields) {
   DflHandle* d = (DflHandle*)h;
   dfl_set_fields(*d->d, CC(U), CC(A), CC(fields));
+}
+void orc_dfl_set_fields_on_blocks(void* h, const double* U, const double* A, const double* fields,
+                                  const int64_t* blocks, int nblocks) {
+  DflHandle* d = (DflHandle*)h;
+  dfl_set_fields_on_blocks(*d->d, CC(U), CC(A), CC(fields), blocks, nblocks);
 }
 void orc_dfl_get_basis(void* h, double* out) {
   DflHandle* d = (DflHandle*)h;
@@ -106,6 +120,16 @@ int orc_dfl_coarse_solve(void* h, const double* f, double* c, double tol) {
 void orc_dfl_precond(void* h, const double* U, const double* A, const double* Ainv, const int* sap_bs, int ncy,
                      int nmr, double coarse_tol, const double* r, double* out) {
   dfl_precond(*((DflHandle*)h)->d, CC(U), CC(A), CC(Ainv), sap_bs, ncy, nmr, coarse_tol, CC(r), C(out));
+}
+
+// Two-level preconditioner with the network stage: out = C r + N(r1) + M_sap(r2),
+// r1 = r - D C r, r2 = r1 - D N(r1); N dropped (fallback) if |r2| > |r1|.
+// Returns 1 on fallback, else 0.
+int orc_dfl_net_precond(void* h, const double* U, const double* A, const double* Ainv, const int* sap_bs, int ncy,
+                        int nmr, double coarse_tol, int nl, const int* ch, const double* W, const double* r,
+                        double* out) {
+  return dfl_net_precond(*((DflHandle*)h)->d, CC(U), CC(A), CC(Ainv), sap_bs, ncy, nmr, coarse_tol, nl, ch, CC(W),
+                         CC(r), C(out));
 }
 
 // ---- solver ----
@@ -162,6 +186,11 @@ void orc_net_forward(const int* L, int bc, const double* U, int nl, const int* c
                      const double* in, double* out) {
   Geom g(L, bc);
   net_forward(g, CC(U), nl, ch, CC(W), CC(in), C(out));
+}
+void orc_net_forward_on_sites(const int* L, int bc, const double* U, int nl, const int* ch, const double* W,
+                              const double* in, const int64_t* sites, int nsites, double* out) {
+  Geom g(L, bc);
+  net_forward_on_sites(g, CC(U), nl, ch, CC(W), CC(in), sites, nsites, C(out));
 }
 double orc_net_loss_grad(const int* L, int bc, const double* U, int nl, const int* ch, const double* W, int nb,
                          const double* r, const double* e, double* grad) {

@@ -2,7 +2,9 @@
 parallel-transport network) against the oracle: forward pass and loss gradient
 at the same BF16-rounded weights (GPU: FP32 activations and accumulation,
 tolerance 1e-5 relative), the Wilson-operator special case, training, pair
-harvesting (r_k = D e_k) and the fallback to plain SAP."""
+harvesting (r_k = D e_k), the stage inside the two-level preconditioner with an
+accepted network output (v = C r + N(r1) + M_sap(r2)) and the fallback to plain
+SAP."""
 import numpy as np
 import pytest
 
@@ -183,3 +185,89 @@ def test_network_stage_never_worse_than_plain(Q, scale, expect_fallback):
         assert info[r]["converged"] and info[r]["iters"] == info2[r]["iters"]
         assert info[r]["fallbacks"] == (info[r]["iters"] if expect_fallback else 0)
     assert np.array_equal(to_np(psi), to_np(psi2))
+
+
+def stage_weights(seed, scale):
+    """[1, 2, 1] network, BF16-exact: an identity path 0.5*0.25 + 0.25*0.25 on
+    d = 0 plus BF16-rounded Gaussian perturbations (the oracle pins use the same
+    construction); its output reduces the residual, so the stage accepts it."""
+    W = S.random_weights(9 * 2 * 16 * 2, seed, scale)
+    w1 = W[:288].reshape(9, 2, 1, 4, 4)
+    w2 = W[288:].reshape(9, 1, 2, 4, 4)
+    w1[0, 0, 0] += 0.5 * np.eye(4)
+    w1[0, 1, 0] += 0.25 * np.eye(4)
+    w2[0, 0, 0] += 0.25 * np.eye(4)
+    w2[0, 0, 1] += 0.25 * np.eye(4)
+    return bf16(np.concatenate([w1.reshape(-1), w2.reshape(-1)]))
+
+
+def test_network_stage_accept_path_parity(Q, orc):
+    # qdd_dfl_precond with the network stage on, FP32 SAP, a non-zero network output
+    # that is accepted: element-wise against the oracle's composition
+    # C r + N(r1) + M_sap(r2) on the same start fields (nit 0), at 1e-5
+    L = (4, 4, 4, 8)
+    V = 512
+    ch = [1, 2, 1]
+    bs = (2, 2, 2, 2)
+    ctx, U = net_ctx(Q, L, ch, 621, max_nrhs=2, dfl_nit=0, dfl_coarse_tol=1e-12, ncy=2, nmr=4)
+    A, Ai = orc.clover(L, U, 0.1355, 1.9)
+    init = S.gaussian_field(V, 622, nrhs=4)
+    ctx.dfl_build(init)
+    d = orc.Deflation(L, bs, 4)
+    d.set_fields(U, A, init)
+    W = stage_weights(623, 0.02)
+    ctx.net_set_weights(W)
+    r = S.gaussian_field(V, 624, nrhs=2)
+    out = to_np(ctx.dfl_precond(r))
+    for k in range(2):
+        ref, fb = d.net_precond(U, A, Ai, bs, 2, 4, 1e-12, ch, W, r[k])
+        assert not fb
+        plain = d.precond(U, A, Ai, bs, 2, 4, 1e-12, r[k])
+        e = relerr(out[k], ref)
+        print(f"rhs {k}: accept-path err {e:.2e}, distance to the plain preconditioner {relerr(out[k], plain):.2e}")
+        assert e < 1e-5
+        assert relerr(out[k], plain) > 1e-3  # the network term is present
+
+
+def test_trained_network_cuts_outer_iterations(Q, orc):
+    # What the trained network gains: harvest (r_k, e_k) pairs from plain deflated
+    # solves of training sources, train the 1-12-12-1 network on the GPU, then solve
+    # fresh sources (disjoint seeds) with the stage and with a solver that has no
+    # network at all (same links, same deflation start fields).  A deliberately
+    # light Schwarz stage (2 cycles, 2 MR steps) leaves room for it: the learned
+    # solver must take fewer outer iterations on every source, and every solution
+    # must reach a true relative residual of 1e-10 under the oracle's D.
+    L = (8, 8, 8, 8)
+    V = 4096
+    base = dict(max_nrhs=8, sap_bs=(4, 4, 4, 4), ncy=2, nmr=2, sap_prec=1, dfl_Ns=4, dfl_bs=(4, 4, 4, 4),
+                dfl_nit=3, precond=Q.PRECOND_DFL)
+    ch = [1, 12, 12, 1]
+    ctx, U = make_ctx(Q, L, 0.6, 0.1357, 1.9, 1601, use_net=1, net_nl=3, net_ch=ch, **base)
+    init = S.gaussian_field(V, 1602, nrhs=4)
+    ctx.dfl_build(init)
+    nw = ctx.net_num_weights()
+    ctx.net_set_weights(bf16(S.random_weights(nw, 1603, 0.02)))
+    rb, eb = ctx.pair_buffers(64)
+    fb = ctx.field_bytes(Q.F32, 1, False)
+    losses = []
+    for b in range(4):
+        _, _, n, _ = ctx.solve_harvest(S.gaussian_field(V, 1800 + 8 * b, nrhs=8), rb, eb, 64)
+        assert n >= 8
+        for s in range(40):
+            k0 = (4 * s) % (n - 3)
+            losses.append(ctx.net_train_step(rb[k0 * fb:], eb[k0 * fb:], 4, 2e-3))
+    test = S.gaussian_field(V, 1700, nrhs=4)
+    psi, info, _ = ctx.solve(test)
+    plain, _ = make_ctx(Q, L, 0.6, 0.1357, 1.9, 1601, **base)
+    plain.dfl_build(init)
+    psi0, info0, _ = plain.solve(test)
+    A, _ = orc.clover(L, U, 0.1357, 1.9)
+    for r in range(4):
+        for x, inf in ((to_np(psi)[r], info[r]), (to_np(psi0)[r], info0[r])):
+            res = np.linalg.norm(test[r] - orc.apply_D(L, U, A, x)) / np.linalg.norm(test[r])
+            assert inf["converged"] and res <= 1e-10
+    it, it0 = [i["iters"] for i in info], [i["iters"] for i in info0]
+    print(f"loss {losses[0]:.3f} -> {losses[-1]:.3f}; outer iterations learned {it} plain {it0}; "
+          f"fallbacks {[i['fallbacks'] for i in info]}")
+    assert losses[-1] < 0.5 * losses[0]
+    assert all(a < b for a, b in zip(it, it0))
