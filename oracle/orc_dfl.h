@@ -75,6 +75,12 @@ FgcrResult coarse_solve(const Deflation& d, const cplx* f, cplx* c, double coars
 void dfl_build(Deflation& d, const cplx* U, const cplx* A, const cplx* Ainv, const int* sap_bs, int ncy,
                int nmr, int nit, const cplx* init);
 void dfl_set_fields(Deflation& d, const cplx* U, const cplx* A, const cplx* fields);
+void dfl_set_fields_on_blocks(Deflation& d, const cplx* U, const cplx* A, const cplx* fields,
+                              const int64_t* blocks, int nblocks);
+int sap_one_cycle_on_blocks(const Geom& g, const cplx* U, const cplx* A, const cplx* Ainv, const int* bs, int nmr,
+                            const cplx* eta, const int64_t* blocks, int nblocks, cplx* psi);
+void net_forward_on_sites(const Geom& g, const cplx* U, int nl, const int* ch, const cplx* W, const cplx* in,
+                          const int64_t* sites, int nsites, cplx* out);
 void dfl_precond(const Deflation& d, const cplx* U, const cplx* A, const cplx* Ainv, const int* sap_bs, int ncy,
                  int nmr, double coarse_tol, const cplx* r, cplx* out);
 int dfl_net_precond(const Deflation& d, const cplx* U, const cplx* A, const cplx* Ainv, const int* sap_bs,

@@ -35,29 +35,33 @@ static void transport(const Geom& g, const cplx* U, const cplx* psi, int64_t x, 
 // adjoint of T_d: T_{+mu}^dag = T_{-mu}, T_0^dag = T_0
 static int adjoint_path(int d) { return d == 0 ? 0 : ((d - 1) % 2 == 0 ? d + 1 : d - 1); }
 
+// One output site of a layer: out_c(x) for every output channel c.
 // weights of layer: W[((d*cout + c)*cin + c')*16 + s*4 + s']
-void net_layer_forward(const Geom& g, const cplx* U, int cin, int cout, const cplx* W, const cplx* in, cplx* out) {
+static void layer_site(const Geom& g, const cplx* U, int cin, int cout, const cplx* W, const cplx* in, int64_t x,
+                       cplx* out) {
   int64_t V = g.V;
-#pragma omp parallel for schedule(static)
-  for (int64_t x = 0; x < V; ++x) {
-    std::vector<cplx> acc(cout * 12, 0.0);
-    cplx t[12];
-    for (int cp = 0; cp < cin; ++cp)
-      for (int d = 0; d < 9; ++d) {
-        transport(g, U, in + cp * V * 12, x, d, t);
-        for (int c = 0; c < cout; ++c) {
-          const cplx* w = W + ((d * cout + c) * cin + cp) * 16;
-          for (int s = 0; s < 4; ++s)
-            for (int a = 0; a < 3; ++a) {
-              cplx z = 0;
-              for (int sp = 0; sp < 4; ++sp) z += w[s * 4 + sp] * t[sp * 3 + a];
-              acc[c * 12 + s * 3 + a] += z;
-            }
-        }
+  std::vector<cplx> acc(cout * 12, 0.0);
+  cplx t[12];
+  for (int cp = 0; cp < cin; ++cp)
+    for (int d = 0; d < 9; ++d) {
+      transport(g, U, in + cp * V * 12, x, d, t);
+      for (int c = 0; c < cout; ++c) {
+        const cplx* w = W + ((d * cout + c) * cin + cp) * 16;
+        for (int s = 0; s < 4; ++s)
+          for (int a = 0; a < 3; ++a) {
+            cplx z = 0;
+            for (int sp = 0; sp < 4; ++sp) z += w[s * 4 + sp] * t[sp * 3 + a];
+            acc[c * 12 + s * 3 + a] += z;
+          }
       }
-    for (int c = 0; c < cout; ++c)
-      for (int i = 0; i < 12; ++i) out[(c * V + x) * 12 + i] = acc[c * 12 + i];
-  }
+    }
+  for (int c = 0; c < cout; ++c)
+    for (int i = 0; i < 12; ++i) out[(c * V + x) * 12 + i] = acc[c * 12 + i];
+}
+
+void net_layer_forward(const Geom& g, const cplx* U, int cin, int cout, const cplx* W, const cplx* in, cplx* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t x = 0; x < g.V; ++x) layer_site(g, U, cin, cout, W, in, x, out);
 }
 
 // Backward of one layer.  gy: complex gradient dl/dRe(y) + i dl/dIm(y) of the
@@ -124,6 +128,41 @@ void net_forward(const Geom& g, const cplx* U, int nl, const int* ch, const cplx
     a.swap(b);
   }
   std::memcpy((void*)out, a.data(), sizeof(cplx) * a.size());
+}
+
+// The network output (one channel) at a list of sites only, for checks at sizes
+// where the full forward pass is too slow: layer l is evaluated on the sites
+// within nl - l hops of the listed ones (the only activations the output there
+// depends on), with the per-site arithmetic of net_layer_forward.  out: [nsites][12].
+void net_forward_on_sites(const Geom& g, const cplx* U, int nl, const int* ch, const cplx* W, const cplx* in,
+                          const int64_t* sites, int nsites, cplx* out) {
+  const int64_t V = g.V;
+  // need[l]: sites where the activation of level l is needed
+  std::vector<std::vector<uint8_t>> need(nl + 1, std::vector<uint8_t>(V, 0));
+  for (int i = 0; i < nsites; ++i) need[nl][sites[i]] = 1;
+  for (int l = nl - 1; l >= 1; --l)
+    for (int64_t x = 0; x < V; ++x) {
+      if (!need[l + 1][x]) continue;
+      need[l][x] = 1;
+      for (int mu = 0; mu < 4; ++mu) {
+        need[l][g.up(x, mu)] = 1;
+        need[l][g.dn(x, mu)] = 1;
+      }
+    }
+  std::vector<cplx> a(in, in + (size_t)ch[0] * V * 12), b;
+  int64_t off = 0;
+  for (int l = 0; l < nl; ++l) {
+    b.assign((size_t)ch[l + 1] * V * 12, 0.0);
+    std::vector<int64_t> xs;
+    for (int64_t x = 0; x < V; ++x)
+      if (need[l + 1][x]) xs.push_back(x);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < (int64_t)xs.size(); ++k) layer_site(g, U, ch[l], ch[l + 1], W + off, a.data(), xs[k], b.data());
+    off += layer_wsize(ch[l], ch[l + 1]);
+    a.swap(b);
+  }
+  for (int i = 0; i < nsites; ++i)
+    for (int k = 0; k < 12; ++k) out[i * 12 + k] = a[sites[i] * 12 + k];
 }
 
 // Loss l = sum_i |N(r_i/|r_i|) - e_i/|r_i||^2 / sum_i |e_i/|r_i||^2 over a batch of

@@ -149,6 +149,50 @@ void sap_half_sweep(const Geom& g, const cplx* U, const cplx* A, const cplx* Ain
   for (int64_t i = 0; i < n; ++i) rho[i] = eta[i] - Dpsi[i];
 }
 
+// The first cycle of the Schwarz procedure (ncy = 1) evaluated only where a
+// list of colour-1 blocks needs it, for checks at sizes where the full sweep is
+// too slow: the face neighbours of the listed blocks (colour 0) are solved from
+// rho = eta, the residual eta - D psi is formed on the listed blocks exactly as
+// sap() forms it (per site, the clover term and then the hops), and the listed
+// blocks are solved from it.  psi (full field, zeroed here) then holds the
+// values sap(ncy = 1) gives on the listed blocks and on their face neighbours.
+// Returns -1 (psi untouched) if a listed block is not of colour 1 or a face
+// neighbour is not of colour 0, else 0.
+int sap_one_cycle_on_blocks(const Geom& g, const cplx* U, const cplx* A, const cplx* Ainv, const int* bs, int nmr,
+                            const cplx* eta, const int64_t* blocks, int nblocks, cplx* psi) {
+  Blocks B(g, bs);
+  int64_t n = g.V * 12;
+  std::vector<int64_t> black;
+  for (int i = 0; i < nblocks; ++i) {
+    if (blocks[i] < 0 || blocks[i] >= B.nblk || B.colour[blocks[i]] != 1) return -1;
+    for (int d = 1; d <= 8; ++d) {
+      int64_t nb = B.nbr(blocks[i], d);
+      if (B.colour[nb] != 0) return -1;
+      if (std::find(black.begin(), black.end(), nb) == black.end()) black.push_back(nb);
+    }
+  }
+  std::fill(psi, psi + n, cplx(0));
+  std::vector<cplx> rho(eta, eta + n), v(n, 0.0), w1(n), w2(n), w3(n), w4(n);
+  for (int64_t b : black) {
+    block_mr(B, b, U, A, Ainv, rho.data(), v.data(), nmr, w1, w2, w3, w4);
+    for (int64_t x : B.sites[b])
+      for (int k = 0; k < 12; ++k) psi[x * 12 + k] += v[x * 12 + k];
+  }
+  for (int i = 0; i < nblocks; ++i)
+    for (int64_t x : B.sites[blocks[i]]) {
+      cplx o[12];
+      apply_clover_site(A + x * 144, psi + x * 12, o);
+      hop_site(g, U, psi, x, -0.5, o, nullptr);
+      for (int k = 0; k < 12; ++k) rho[x * 12 + k] = eta[x * 12 + k] - o[k];
+    }
+  for (int i = 0; i < nblocks; ++i) {
+    block_mr(B, blocks[i], U, A, Ainv, rho.data(), v.data(), nmr, w1, w2, w3, w4);
+    for (int64_t x : B.sites[blocks[i]])
+      for (int k = 0; k < 12; ++k) psi[x * 12 + k] += v[x * 12 + k];
+  }
+  return 0;
+}
+
 // ---------------------------------------------------------------------------
 // Flexible GCR (textbook restarted FGCR; reading of the paper's outer solver):
 // phi_k = M(r_k), chi_k = A phi_k, classical Gram-Schmidt of chi_k against the
@@ -225,11 +269,18 @@ FgcrResult fgcr(int64_t n, const LinOp& op, const LinOp* prec, const cplx* eta, 
 // The little Dirac operator A_{bk, b'l} = <w_bk, D w_b'l> is stored per block as
 // 9 Ns x Ns matrices: index 0 = the block with itself (hops inside the block),
 // 1+2mu / 2+2mu = the coupling through the block's upper / lower face in mu.
-static void dfl_orthonormalise(Deflation& d) {
+static std::vector<int64_t> all_blocks(const Blocks& B) {
+  std::vector<int64_t> b(B.nblk);
+  for (int64_t i = 0; i < B.nblk; ++i) b[i] = i;
+  return b;
+}
+
+static void dfl_orthonormalise(Deflation& d, const std::vector<int64_t>& blocks) {
   const Geom& g = d.B.g;
   int64_t V12 = g.V * 12;
 #pragma omp parallel for schedule(dynamic)
-  for (int64_t b = 0; b < d.B.nblk; ++b) {
+  for (int64_t bi = 0; bi < (int64_t)blocks.size(); ++bi) {
+    const int64_t b = blocks[bi];
     const std::vector<int64_t>& st = d.B.sites[b];
     for (int l = 0; l < d.Ns; ++l) {
       cplx* wl = &d.W[l * V12];
@@ -248,14 +299,15 @@ static void dfl_orthonormalise(Deflation& d) {
   }
 }
 
-static void dfl_little(Deflation& d, const cplx* U, const cplx* A) {
+static void dfl_little(Deflation& d, const cplx* U, const cplx* A, const std::vector<int64_t>& blocks) {
   const Geom& g = d.B.g;
   const Blocks& B = d.B;
   int Ns = d.Ns;
   int64_t V12 = g.V * 12;
   d.little.assign(B.nblk * 9 * Ns * Ns, 0.0);
 #pragma omp parallel for schedule(dynamic)
-  for (int64_t b = 0; b < B.nblk; ++b) {
+  for (int64_t bi = 0; bi < (int64_t)blocks.size(); ++bi) {
+    const int64_t b = blocks[bi];
     const std::vector<int64_t>& st = B.sites[b];
     for (int l = 0; l < Ns; ++l) {
       const cplx* wl = &d.W[l * V12];
@@ -359,8 +411,8 @@ void dfl_build(Deflation& d, const cplx* U, const cplx* A, const cplx* Ainv, con
       double s = 1.0 / std::sqrt(norm2(tmp.data(), V12));
       for (int64_t i = 0; i < V12; ++i) d.W[l * V12 + i] = tmp[i] * s;
     }
-  dfl_orthonormalise(d);
-  dfl_little(d, U, A);
+  dfl_orthonormalise(d, all_blocks(d.B));
+  dfl_little(d, U, A, all_blocks(d.B));
 }
 
 // Two-level preconditioner (reading: inexact deflation): M(r) = C r + M_sap(r - D C r),
@@ -385,8 +437,28 @@ void dfl_precond(const Deflation& d, const cplx* U, const cplx* A, const cplx* A
 void dfl_set_fields(Deflation& d, const cplx* U, const cplx* A, const cplx* fields) {
   int64_t V12 = d.B.g.V * 12;
   d.W.assign(fields, fields + d.Ns * V12);
-  dfl_orthonormalise(d);
-  dfl_little(d, U, A);
+  dfl_orthonormalise(d, all_blocks(d.B));
+  dfl_little(d, U, A, all_blocks(d.B));
+}
+
+// The same restricted to a list of blocks, for checks at sizes where the full
+// little operator is too slow: the listed blocks and their face neighbours are
+// orthonormalised, and the little-operator rows of the listed blocks (self and
+// the 8 face couplings) are computed; they equal those of dfl_set_fields.  Basis
+// values on other blocks stay un-orthonormalised, other rows zero.
+void dfl_set_fields_on_blocks(Deflation& d, const cplx* U, const cplx* A, const cplx* fields,
+                              const int64_t* blocks, int nblocks) {
+  int64_t V12 = d.B.g.V * 12;
+  d.W.assign(fields, fields + d.Ns * V12);
+  std::vector<int64_t> rows(blocks, blocks + nblocks), orth;
+  for (int64_t b : rows) {
+    orth.push_back(b);
+    for (int f = 1; f <= 8; ++f) orth.push_back(d.B.nbr(b, f));
+  }
+  std::sort(orth.begin(), orth.end());
+  orth.erase(std::unique(orth.begin(), orth.end()), orth.end());
+  dfl_orthonormalise(d, orth);
+  dfl_little(d, U, A, rows);
 }
 
 // Two-level preconditioner with the network stage (reading of the learned

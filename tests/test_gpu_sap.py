@@ -6,9 +6,13 @@ The GPU keeps the residual up to date incrementally (the block residual is the
 MR residual on even sites and zero on odd sites; the faces are corrected from
 the neighbours' last corrections) where the oracle recomputes eta - D psi after
 every half-sweep: the same numbers in exact arithmetic.  Tolerances (max-abs
-error / max-abs reference): FP64 1e-12, FP32 1e-5, FP16 storage 2e-2 (the FP16
-rounding of rho, V, links and clover, ~2^-11 each, enters every one of the
-2 ncy nmr = 40 MR steps of a 5-cycle sweep)."""
+error / max-abs reference): FP64 1e-12, FP32 1e-5, FP16 storage 3e-3: six
+quantities are stored in FP16 (the source, the links, the two clover blocks A_e
+and A_o^{-1}, the residual rho and the block corrections V), each rounded with
+unit 2^-11 = 4.9e-4 relative to its site maximum, so a half-sweep's result is
+off by at most about 6 x 4.9e-4; the procedure contracts the error of earlier
+half-sweeps, so the bound does not grow with the number of cycles (observed
+3.6e-4 .. 6.0e-4 for 1 to 5 cycles)."""
 import numpy as np
 import pytest
 
@@ -16,7 +20,7 @@ from paper_1011_0911_amd import synth as S
 from tests.gpu_util import make_ctx, relerr, to_np
 
 pytestmark = pytest.mark.gpu
-TOL = {0: 1e-12, 1: 1e-5, 2: 2e-2}
+TOL = {0: 1e-12, 1: 1e-5, 2: 3e-3}
 
 
 @pytest.fixture(scope="module")
