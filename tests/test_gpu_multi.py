@@ -36,26 +36,52 @@ def test_dfl_share_equals_little_operator_at_new_mass(Q):
     assert relerr(to_np(Ab), to_np(Ac)) < 1e-12
 
 
-def test_solve_multi_matches_single_solves(Q, orc):
+def _system(Q, L, kappa, seed, nrhs, **cfg):
     import torch
 
-    systems = [((8, 8, 8, 8), 0.1350), ((8, 8, 8, 8), 0.1357), ((8, 4, 4, 8), 0.1355)]
+    V = int(np.prod(L))
+    U = S.random_su3_links(L, 0.6, seed)
+    c = Q.Context(L, Q.default_config(max_nrhs=nrhs, **cfg), stream=torch.cuda.Stream())
+    c.set_gauge(torch.from_numpy(U))
+    c.set_params(kappa, 1.9)
+    return c, U
+
+
+@pytest.mark.parametrize("kind", ["sap", "dfl"])
+def test_solve_multi_matches_single_solves(Q, orc, kind):
+    # several systems (lattice sizes, masses and batch sizes differ) solved
+    # concurrently give bit for bit the solutions and iteration counts of the same
+    # systems solved one at a time, and every solution has true residual <= 1e-10
+    import torch
+
+    if kind == "sap":
+        systems = [((8, 8, 8, 8), 0.1350, (4, 4, 4, 4)), ((8, 8, 8, 8), 0.1357, (4, 4, 4, 4)),
+                   ((8, 4, 4, 8), 0.1355, (4, 2, 2, 4))]
+    else:
+        systems = [((8, 8, 8, 8), 0.1357, (4, 4, 4, 4)), ((16, 8, 8, 8), 0.1355, (4, 4, 4, 4)),
+                   ((8, 8, 8, 8), 0.1350, (4, 4, 4, 4))]
     ctxs, etas, refs = [], [], []
-    for k, (L, kappa) in enumerate(systems):
+    for k, (L, kappa, bs) in enumerate(systems):
         V = int(np.prod(L))
-        U = S.random_su3_links(L, 0.6, 710 + k)
-        c = Q.Context(L, Q.default_config(max_nrhs=2, sap_bs=(4, 4, 4, 4) if L[1] == 8 else (4, 2, 2, 4),
-                                          precond=Q.PRECOND_SAP, sap_prec=1), stream=torch.cuda.Stream())
-        c.set_gauge(torch.from_numpy(U))
-        c.set_params(kappa, 1.9)
-        eta = S.gaussian_field(V, 720 + k, nrhs=1 + k % 2)
+        cfg = dict(sap_bs=bs, sap_prec=1, precond=Q.PRECOND_SAP)
+        if kind == "dfl":
+            cfg.update(precond=Q.PRECOND_DFL, dfl_Ns=4, dfl_bs=bs, dfl_nit=2)
+        c, U = _system(Q, L, kappa, 710 + k, 2, **cfg)
+        if kind == "dfl":
+            c.dfl_build(S.gaussian_field(V, 730 + k, nrhs=4))
         ctxs.append(c)
-        etas.append(eta)
+        etas.append(S.gaussian_field(V, 720 + k, nrhs=1 + k % 2))
         A, _ = orc.clover(L, U, kappa, 1.9)
         refs.append((L, U, A))
     psis, infos, st = Q.solve_multi(ctxs, etas)
     assert st == 0
-    for (L, U, A), eta, psi, inf in zip(refs, etas, psis, infos):
+    torch.cuda.synchronize()
+    for c, eta, psi, inf, (L, U, A) in zip(ctxs, etas, psis, infos, refs):
+        single, sinf, sst = c.solve(eta)
+        torch.cuda.synchronize()
+        assert sst == 0
+        assert torch.equal(psi, single)
+        assert [i["iters"] for i in inf] == [i["iters"] for i in sinf]
         psi = to_np(psi)
         for r in range(eta.shape[0]):
             res = np.linalg.norm(eta[r] - orc.apply_D(L, U, A, psi[r])) / np.linalg.norm(eta[r])
