@@ -83,7 +83,8 @@ def one_rhs_rates(ctx, src1, cache, cache_path, reps=20):
     launch): TB/s of algorithmic bytes for the whole apply, HIP events on the
     library stream.  Where the tuned launch reads compressed links, the same
     launch with 18-real links is timed too (links_18).  Context figures next to
-    the batched headline."""
+    the batched headline.  Also returns the outputs (host complex128) for the
+    comparison with the oracle."""
     import torch
     from paper_1011_0911_amd import qdd
 
@@ -97,11 +98,13 @@ def one_rhs_rates(ctx, src1, cache, cache_path, reps=20):
                 "launch": list(launch)}
 
     res = {}
+    outs = {}
     for prec in (0, 1, 2):
         fin = ctx.pack(prec, torch.from_numpy(src1), True)
         fout = ctx.empty_field(prec, 1, True)
         ctx.autotune(qdd.KERNEL_DHAT, prec, 1, fin, fout, reps=5, cache=cache)
         r = timed(prec, fin, fout)
+        outs[{0: "f64", 1: "f32", 2: "f16"}[prec]] = ctx.unpack(prec, fout, 1, True).cpu().numpy()[0]
         if compressed(r["launch"]):
             b, nr, xcd, sb = r["launch"]
             ctx.set_launch(qdd.KERNEL_DHAT, prec, b, nr, xcd & ~16, sb)
@@ -110,7 +113,7 @@ def one_rhs_rates(ctx, src1, cache, cache_path, reps=20):
         res[{0: "f64", 1: "f32", 2: "f16"}[prec]] = r
         del fin, fout
     qdd.save_tune_cache(cache_path, cache)
-    return res
+    return res, outs
 
 
 def action_rates(ctx, src1, reps=20):
@@ -152,35 +155,47 @@ def action_rates(ctx, src1, reps=20):
             "apply_w_bytes": w_bytes}
 
 
-def cpu_baseline(U, nrhs_gpu, prec_gpu, budget_s=12.0):
-    """FP64 oracle Dhat on the same lattice, one rhs per apply, as many applies as
-    fit in the time budget; converted to the GPU's unit with its byte model."""
+def cpu_baseline(U, pe, gpu_out, nrhs_gpu, prec_gpu, budget_s=12.0):
+    """FP64 oracle Dhat on the same lattice and field (the headline batch's first
+    right-hand side pe), one rhs per apply, as many applies as fit in the time
+    budget, at 8 threads and at 1 thread; converted to the GPU's unit with its byte
+    model.  Returns (baseline, errors of the GPU outputs gpu_out against the
+    oracle's Dhat pe: max |gpu - oracle| / max |oracle|)."""
     import numpy as np
 
     import oracle
-    from paper_1011_0911_amd import synth as S
 
     L = LATTICE
     V = int(np.prod(L))
     t0 = time.time()
     A, Ai = oracle.clover(L, U, KAPPA, CSW)
     t_setup = time.time() - t0
-    pe = S.gaussian_field(V // 2, 77)
-    oracle.apply_Dhat(L, U, A, Ai, pe)  # warm
-    n, t0 = 0, time.time()
-    while True:
-        oracle.apply_Dhat(L, U, A, Ai, pe)
-        n += 1
-        if time.time() - t0 > budget_s or n >= 50:
-            break
-    dt = (time.time() - t0) / n
+    ref = oracle.apply_Dhat(L, U, A, Ai, pe)  # also the warm-up
+    errs = {k: float(np.abs(v - ref).max() / np.abs(ref).max()) for k, v in gpu_out.items()}
     a, b = bytes_per_site(prec_gpu, nrhs_gpu)
     per_rhs = (a + b) / nrhs_gpu
-    tbs = per_rhs * (V // 2) / dt / 1e12
-    return {"value": round(tbs, 6), "unit": "TB/s", "cores": oracle.get_threads(), "kind": "oracle",
-            "sample": (f"FP64 CPU oracle Dhat on the same 32^3x64 field, 1 rhs per apply, {n} applies of "
-                       f"{dt * 1e3:.0f} ms (clover set-up {t_setup:.1f} s untimed); rate converted with the "
-                       f"GPU's per-rhs byte model ({per_rhs:.0f} B/site)")}
+
+    def rate(threads):
+        oracle.set_threads(threads)
+        n, t0 = 0, time.time()
+        while True:
+            oracle.apply_Dhat(L, U, A, Ai, pe)
+            n += 1
+            if time.time() - t0 > budget_s or n >= 50:
+                break
+        dt = (time.time() - t0) / n
+        return per_rhs * (V // 2) / dt / 1e12, n, dt, oracle.get_threads()
+
+    tbs, n, dt, cores = rate(8)
+    tbs1, n1, dt1, _ = rate(1)
+    base = {"value": round(tbs, 6), "unit": "TB/s", "cores": cores, "kind": "oracle",
+            "sample": (f"FP64 CPU oracle Dhat on the same 32^3x64 field (the first rhs of the headline batch), 1 rhs "
+                       f"per apply, {n} applies of {dt * 1e3:.0f} ms on {cores} threads (clover set-up "
+                       f"{t_setup:.1f} s untimed); rate converted with the GPU's per-rhs byte model "
+                       f"({per_rhs:.0f} B/site)"),
+            "one_thread": {"value": round(tbs1, 6), "cores": 1, "ms_per_apply": round(dt1 * 1e3, 1),
+                           "applies": n1}}
+    return base, errs
 
 
 def solve_section(learned_pairs, U=None):
@@ -267,7 +282,7 @@ def main():
         qdd.save_tune_cache(cache_path, cache)
     launch = ctx.get_launch(qdd.KERNEL_DHAT, prec)
     print(f"[bench] launch {launch} (tuned {tuned_ms})", file=sys.stderr, flush=True)
-    one_rhs = None if args.no_tune else one_rhs_rates(ctx, src[:1], cache, cache_path)
+    one_rhs, one_out = (None, {}) if args.no_tune else one_rhs_rates(ctx, src[:1], cache, cache_path)
     ctx.set_launch(qdd.KERNEL_DHAT, prec, *launch)
     action = action_rates(ctx, src[:1])
 
@@ -335,13 +350,19 @@ def main():
                      "traffic": traffic, "bytes_per_launch": b_b * Vh, "ms_per_launch": round(ms_b, 5)},
         "cpu_baseline": None,
     }
+    # the headline batch's first right-hand side, for the comparison with the oracle
+    gpu_out = {"headline_rhs0": ctx.unpack(prec, fout, nrhs, True)[0].cpu().numpy()}
+    gpu_out.update({f"one_rhs_{k}": v for k, v in one_out.items()})
     del ctx, fin, fout
     torch.cuda.empty_cache()
     if not args.no_solve:
         out["solve"] = solve_section(args.learned_pairs, U)
     if not args.no_cpu_baseline:
         try:
-            out["cpu_baseline"] = cpu_baseline(U, nrhs, prec)
+            out["cpu_baseline"], errs = cpu_baseline(U, src[0], gpu_out, nrhs, prec)
+            out["err_vs_oracle"] = {
+                "measure": "max |gpu - oracle| / max |oracle| over all even sites, oracle = FP64 CPU Dhat",
+                **{k: float(f"{v:.3e}") for k, v in errs.items()}}
         except Exception as e:  # the baseline is reported, never required
             out["cpu_baseline"] = {"error": str(e)}
     print(json.dumps(out, default=float), flush=True)
