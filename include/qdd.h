@@ -269,7 +269,17 @@ qdd_status qdd_net_train_step(qdd_ctx* ctx, int nb, const void* r, const void* e
 qdd_status qdd_solve_harvest(qdd_ctx* ctx, int nrhs, const double* eta, double* psi, qdd_solve_info* info,
                              void* r_pairs, void* e_pairs, int max_pairs, int* npairs, int* pair_rhs);
 
-/* Launch shape of a kernel family (kernel: 0 = Dhat, 1 = D; prec: qdd_prec):
+/* Launch shape of a kernel family (kernel: 0 = Dhat, 1 = D, 2 = the Schwarz
+ * half-sweep; prec: qdd_prec).  For kernel 2 only nr is used, the kernel variant
+ * of FP32 / FP16 storage (block, xcd and sb must be 0): 1 one lane per site with
+ * its links and clover block in registers, the right-hand sides one after
+ * another; 2 one workgroup per (block, right-hand side), a lane per even/odd
+ * site pair; 3 (FP16 only) one workgroup per block and group of 4 right-hand
+ * sides with the block's links and clover blocks staged in LDS; 4 (FP16 only)
+ * one workgroup per block and pair of right-hand sides with the block's links
+ * staged in LDS (two workgroups per CU).  FP64 has a
+ * single kernel (qdd_get_launch reports nr 0).  The default is 3 for FP16 and 1
+ * for FP32.  For kernels 0 and 1:
  * block threads (64..256, multiple of 64); nr right-hand sides per lane (1, 2,
  * 4; the links are loaded once for all of them), or nr = 0 (Dhat only): the
  * staged variant, where a workgroup reads the links and clover of its tile of
@@ -295,7 +305,10 @@ qdd_status qdd_get_launch(const qdd_ctx* ctx, int kernel, qdd_prec prec, int* bl
  * even fields, 1 = D on packed full fields) for this precision and batch size
  * on the given packed fields (`reps` timed repetitions each, HIP events on the
  * context stream), installs the fastest in the context and returns its mean
- * duration in *best_ms.  `out` is overwritten; synchronises. */
+ * duration in *best_ms.  Kernel 2 times each Schwarz half-sweep variant on whole
+ * preconditioner calls M_sap in (in: packed FP64 full fields, out: packed FP32
+ * full fields of nrhs right-hand sides; prec must be the configured FP32 or FP16
+ * SAP precision).  `out` is overwritten; synchronises. */
 qdd_status qdd_autotune(qdd_ctx* ctx, int kernel, qdd_prec prec, int nrhs, const void* in, void* out, int reps,
                         float* best_ms);
 

@@ -3,6 +3,7 @@
 #include "../../include/qdd.h"
 #include "qdd_api_internal.h"
 #include "qdd_net.h"
+#include "qdd_sap.h"
 
 #include <cmath>
 #include <cstdarg>
@@ -426,6 +427,15 @@ qdd_status qdd_dw_masses(qdd_ctx* x, qdd_prec prec, int nrhs, const double* kapp
 }
 
 qdd_status qdd_set_launch(qdd_ctx* x, int kernel, qdd_prec prec, int block, int nr, int xcd, int sb) {
+  if (x && kernel == 2) {
+    // Schwarz half-sweep kernel variant (nr), FP32 / FP16 storage only
+    if (!sap_variant_ok(prec, nr) || block != 0 || xcd != 0 || sb != 0) {
+      x->fail("qdd_set_launch: Schwarz variant must be 1 or 2 (FP32), 1..4 (FP16), other fields 0");
+      return QDD_EINVAL;
+    }
+    x->sap_variant[prec] = nr;
+    return QDD_OK;
+  }
   bool ok = x && kernel >= 0 && kernel <= 1 && prec >= QDD_F64 && prec <= QDD_F16 && block >= 64 && block <= 256 &&
             (block & 63) == 0 && (nr == 0 || nr == 1 || nr == 2 || nr == 4) && xcd >= 0 && xcd <= (kernel == 0 && nr == 1 ? 31 : 3) &&
             (sb == 0 || (sb >= 1 && sb <= block && block % sb == 0));
@@ -440,7 +450,14 @@ qdd_status qdd_set_launch(qdd_ctx* x, int kernel, qdd_prec prec, int block, int 
 }
 
 qdd_status qdd_get_launch(const qdd_ctx* x, int kernel, qdd_prec prec, int* block, int* nr, int* xcd, int* sb) {
-  if (!x || kernel < 0 || kernel > 1 || prec < QDD_F64 || prec > QDD_F16) return QDD_EINVAL;
+  if (!x || kernel < 0 || kernel > 2 || prec < QDD_F64 || prec > QDD_F16) return QDD_EINVAL;
+  if (kernel == 2) {
+    if (block) *block = 0;
+    if (nr) *nr = prec == QDD_F64 ? 0 : (x->sap_variant[prec] ? x->sap_variant[prec] : sap_default_variant(prec));
+    if (xcd) *xcd = 0;
+    if (sb) *sb = 0;
+    return QDD_OK;
+  }
   const LaunchCfg& c = x->launch[kernel][prec];
   if (block) *block = c.block;
   if (nr) *nr = c.nr;

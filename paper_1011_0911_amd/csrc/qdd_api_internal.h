@@ -59,6 +59,7 @@ struct qdd_ctx {
   std::vector<double> dw_shift_host;  // source of the per-rhs mass shifts copied to the device
   struct Harvest* harvest = nullptr;  // pair capture of the next solve (qdd_solve_harvest)
   qdd::LaunchCfg launch[2][3];
+  int sap_variant[3] = {0, 0, 0};  // Schwarz kernel per storage precision (0 = default)
   std::string err;
 
   template <class T>

@@ -43,6 +43,7 @@ static qdd_status sap_run(qdd_ctx* x, int nrhs, const double2* eta, typename St<
   }
   a.nrhs = nrhs;
   a.nmr = c.nmr;
+  a.variant = x->sap_variant[c.sap_prec];
   DevOp<S> op = x->op<S>();
   a.U = op.U;
   a.A = op.A;

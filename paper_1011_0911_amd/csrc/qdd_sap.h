@@ -14,12 +14,21 @@ struct SapArgs {
   int do_bnd;   // apply the face corrections of the previous half-sweep
   int first;    // psi not yet written on these blocks (first cycle)
   int write_v;  // store the correction for the next half-sweep
+  int variant;  // FP32/FP16 kernel: 1 per-site (registers), 2 per (block, rhs), 3 LDS-staged links and
+                // clover, 4 LDS-staged links (3 and 4: FP16)
   LinkV<S> U;
   CloverV<S> A, Ai;
   FieldV<S> rho, V;  // full fields [rhs][parity][12][Vh]
   FieldV<P> psi;
   int64_t poff, spoff;  // parity offsets (elements, scales)
 };
+
+// variants of the FP32 / FP16 half-sweep kernel (FP64 has one)
+constexpr int kSapPerSite = 1, kSapPerRhs = 2, kSapStaged = 3, kSapStagedLinks = 4;
+// the variant used when none was set: the LDS-staged kernel for FP16 storage,
+// the per-site one for FP32
+inline int sap_default_variant(int prec) { return prec == 2 ? kSapStaged : kSapPerSite; }
+inline bool sap_variant_ok(int prec, int v) { return prec != 0 && v >= 1 && v <= (prec == 2 ? 4 : 2); }
 
 template <class S, class P>
 hipError_t launch_sap_half(const SapArgs<S, P>& a, int nblk_colour, hipStream_t st);

@@ -2,8 +2,8 @@
 // paper's solver, Sect. 3): multiplicative two-colour SAP with minimal-residual
 // block solves on the even-odd block operator.
 //
-// One workgroup per block.  A half-sweep over the blocks of one colour does,
-// for every block Lambda and every right-hand side:
+// A half-sweep over the blocks of one colour does, for every block Lambda and
+// every right-hand side:
 //   rho_L += 1/2 H_face V        (corrections V of the neighbouring blocks of the
 //                                 other colour, made in the previous half-sweep)
 //   b      = rho_e + 1/2 H_L A_o^{-1} rho_o
@@ -14,15 +14,12 @@
 // The new block residual needs no extra operator application: on odd sites it is
 // zero by construction and on even sites it is the MR residual r.
 //
-// Within a block the hopping terms are exchanged as projected half-spinors in
-// LDS: every source site writes, per direction, the projection needed by its
-// forward neighbour and the U^dag-transported projection needed by its backward
-// neighbour, so each lane only ever multiplies with its own forward links.
-// Two kernels: for FP32 and FP16 storage one lane per site (even sites in the
-// low lanes, odd sites in the high lanes) with the site's own links and clover
-// block held in registers for the whole half-sweep, reused across all MR steps
-// and right-hand sides; for FP64, where those would not fit, one lane per
-// even/odd site pair with links and clover read where they are used.
+// Two kernels, both with one lane per even/odd site pair of the block (every
+// lane busy in both halves of a hop): for FP32 and FP16 storage one workgroup per
+// (block, right-hand side), hop sources exchanged as whole spinors in LDS; for
+// FP64 one workgroup per block looping over the right-hand sides, with projected
+// half-spinors exchanged in LDS.  Links and clover blocks are read where they
+// are used.
 #include "qdd_kernels.h"
 #include "qdd_sap.h"
 
@@ -57,6 +54,13 @@ struct Exch {
   cx<T> v[NSLOT][6][kSapMaxHalf];
 };
 
+// Per-site variant for FP32 and FP16 storage: one workgroup per block, one lane
+// per site (even sites in the low lanes, odd sites in the high lanes), the
+// site's own links and clover block held in registers for the whole half-sweep
+// and reused across all MR steps and right-hand sides, which are solved one
+// after the other; hops exchange projected half-spinors (the forward
+// projection, and the U^dag-transported backward one) through LDS, so every lane
+// multiplies only with its own forward links.
 template <class S, class P, int DR>
 __global__ void __launch_bounds__(256) k_sap_half(SapArgs<S, P> a) {
   typedef typename St<S>::T T;
@@ -345,6 +349,578 @@ __global__ void __launch_bounds__(256) k_sap_half(SapArgs<S, P> a) {
     if (a.write_v) st_spinor(vf, r, i, v);
     st_spinor(rho, r, i, rnew);
   }
+}
+
+// One workgroup per (block, right-hand side): the right-hand sides of a block
+// are solved by concurrent workgroups instead of one after the other, and the
+// workgroup ids are ordered so that all of them land on the same XCD at about
+// the same time (hardware ids go round-robin over the 8 XCDs), where the block's
+// links and clover blocks are then fetched from HBM once and served from the L2.
+// Lane j owns the j-th even and the j-th odd site of the block (block-local
+// order), so every lane works in both halves of a hop.  A hop onto parity tp
+// reads the source spinors of parity 1 - tp that all lanes wrote to LDS (one
+// 12-component spinor per site, the smallest exchange) and applies the
+// projection, the link and the reconstruction for each in-block neighbour of its
+// own site (target side).  Links and clover blocks are read where they are used
+// (L1/L2 hits), behind an opaque per-lane zero so that the compiler does not
+// hoist them out of the MR loop into registers.
+template <class S, class P, bool O32>
+__global__ void __launch_bounds__(kSapMaxHalf, 2) k_sap_rhs(SapArgs<S, P> a) {
+  typedef typename St<S>::T T;
+  __shared__ cx<T> ex[12][kSapMaxHalf];    // hop sources (one parity of the block)
+  __shared__ cx<T> ro_l[12][kSapMaxHalf];  // the odd-site source, own column only
+  __shared__ int ig_l[2][kSapMaxHalf];     // index within its parity of every block site
+  __shared__ T red[2][3][kSapMaxHalf / 64];  // per-wave partial sums, by MR-step parity
+  const Geo& g = a.g;
+  const int j = threadIdx.x;
+  const int nw = (blockDim.x + 63) >> 6;
+  // workgroup -> (block of colour a.col, right-hand side)
+  int bi, r;
+  {
+    const int id = blockIdx.x, nbc = gridDim.x / a.nrhs;
+    if ((nbc & 7) == 0) {
+      const int rest = id >> 3;
+      r = rest % a.nrhs;
+      bi = (rest / a.nrhs) * 8 + (id & 7);
+    } else {
+      r = id % a.nrhs;
+      bi = id / a.nrhs;
+    }
+  }
+  int bc[4];
+  {
+    int bl = 2 * bi;
+    bc[3] = bl % a.nb[3];
+    int rr = bl / a.nb[3];
+    bc[2] = rr % a.nb[2];
+    rr /= a.nb[2];
+    bc[1] = rr % a.nb[1];
+    bc[0] = rr / a.nb[1];
+    bc[3] += (a.col + bc[0] + bc[1] + bc[2] + bc[3]) & 1;
+  }
+  // the lane's two sites (q = 0 even, 1 odd): global coordinates, index within
+  // the parity, and neighbour slots inside the block (-1: the hop crosses a face)
+  int x[2][4], ig[2], nin[2][4][2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    int y[4];
+    int l = 2 * j;
+    y[3] = l % a.bs[3];
+    int rr = l / a.bs[3];
+    y[2] = rr % a.bs[2];
+    rr /= a.bs[2];
+    y[1] = rr % a.bs[1];
+    y[0] = rr / a.bs[1];
+    y[3] += (q + y[0] + y[1] + y[2] + y[3]) & 1;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) x[q][m] = bc[m] * a.bs[m] + y[m];
+    ig[q] = lex_of(g, x[q]) >> 1;
+    ig_l[q][j] = ig[q];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        int z[4] = {y[0], y[1], y[2], y[3]};
+        z[m] += d == 0 ? 1 : -1;
+        bool in = z[m] >= 0 && z[m] < a.bs[m];
+        nin[q][m][d] = in ? ((((z[0] * a.bs[1] + z[1]) * a.bs[2] + z[2]) * a.bs[3] + z[3]) >> 1) : -1;
+      }
+    }
+  }
+  auto vsalt = []() {
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    return z;
+  };
+  // clover: A on even sites, A^{-1} on odd sites
+  auto clover = [&](int q, const cx<T> in[12], cx<T> out[12]) __attribute__((always_inline)) {
+    clover_apply_u<S>(q == 0 ? a.A : a.Ai, q, ig[q] + vsalt(), in, out);
+  };
+  // all lanes: src (the lane's site of parity 1 - tp) -> LDS; then acc (at the
+  // lane's site of parity tp) = H_L src.  The barrier before the writes keeps
+  // them from overtaking the reads of the previous hop.
+  auto hop = [&](const int tp, const cx<T> src[12], cx<T> acc[12]) __attribute__((always_inline)) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 12; ++k) ex[k][j] = src[k];
+    __syncthreads();
+    const int zv = vsalt();
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int jf = nin[tp][m][0], jb = nin[tp][m][1];
+      cx<T> sv[12], h[6], gg[6], u[9];
+      if (jf >= 0) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) sv[k] = ex[k][jf];
+        ld_link_u<S>(a.U, tp, m, ig[tp] + zv, u);
+        if (m == 0) { project<T, 0, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 0, +1>(gg, acc); }
+        else if (m == 1) { project<T, 1, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 1, +1>(gg, acc); }
+        else if (m == 2) { project<T, 2, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 2, +1>(gg, acc); }
+        else { project<T, 3, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 3, +1>(gg, acc); }
+      }
+      if (jb >= 0) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) sv[k] = ex[k][jb];
+        ld_link_u<S>(a.U, 1 - tp, m, ig_l[1 - tp][jb] + zv, u);
+        if (m == 0) { project<T, 0, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 0, -1>(gg, acc); }
+        else if (m == 1) { project<T, 1, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 1, -1>(gg, acc); }
+        else if (m == 2) { project<T, 2, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 2, -1>(gg, acc); }
+        else { project<T, 3, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 3, -1>(gg, acc); }
+      }
+    }
+  };
+  // parity views of the fields
+  FieldV<S> rho[2] = {a.rho, a.rho}, vf[2] = {a.V, a.V};
+  FieldV<P> psi[2] = {a.psi, a.psi};
+  rho[1].p += a.poff;
+  vf[1].p += a.poff;
+  psi[1].p += a.poff;
+  if (a.rho.scale) {
+    rho[1].scale += a.spoff;
+    vf[1].scale += a.spoff;
+  }
+  if (a.psi.scale) psi[1].scale += a.spoff;
+  // rq += 1/2 H_face V at the lane's site of parity q (the sites across the faces
+  // belong to blocks of the other colour, whose corrections V the previous
+  // half-sweep stored)
+  auto bnd = [&](const int q, cx<T> (&rq)[12]) __attribute__((always_inline)) {
+    const int zv = vsalt();
+    cx<T> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+    const FieldV<S>& vn = vf[1 - q];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      cx<T> sv[12], h[6], gg[6], u[9];
+      if (nin[q][m][0] < 0) {
+        int jn = nbr_idx(g, x[q], m, +1) + zv;
+        ld_spinor<S, O32>(vn, r, jn, sv);
+        ld_link_u<S>(a.U, q, m, ig[q] + zv, u);
+        if (m == 0) { project<T, 0, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 0, +1>(gg, acc); }
+        else if (m == 1) { project<T, 1, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 1, +1>(gg, acc); }
+        else if (m == 2) { project<T, 2, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 2, +1>(gg, acc); }
+        else { project<T, 3, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 3, +1>(gg, acc); }
+      }
+      if (nin[q][m][1] < 0) {
+        int jn = nbr_idx(g, x[q], m, -1) + zv;
+        ld_spinor<S, O32>(vn, r, jn, sv);
+        ld_link_u<S>(a.U, 1 - q, m, jn, u);
+        if (m == 0) { project<T, 0, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 0, -1>(gg, acc); }
+        else if (m == 1) { project<T, 1, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 1, -1>(gg, acc); }
+        else if (m == 2) { project<T, 2, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 2, -1>(gg, acc); }
+        else { project<T, 3, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 3, -1>(gg, acc); }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) rq[k] = cacc(rq[k], T(0.5), acc[k]);
+  };
+  // psi += v, V = v at the lane's site of parity q
+  auto put = [&](const int q, const cx<T> (&v)[12]) __attribute__((always_inline)) {
+    typedef typename St<P>::T TP;
+    cx<TP> pv[12];
+    if (a.first) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) pv[k] = {(TP)v[k].re, (TP)v[k].im};
+    } else {
+      ld_spinor<P, O32>(psi[q], r, ig[q], pv);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) pv[k] = pv[k] + cx<TP>{(TP)v[k].re, (TP)v[k].im};
+    }
+    st_spinor<P, O32>(psi[q], r, ig[q], pv);
+    if (a.write_v) st_spinor<S, O32>(vf[q], r, ig[q], v);
+  };
+
+  cx<T> re[12], ro[12], rr[12], xs[12], w[12], acc[12];
+  ld_spinor<S, O32>(rho[0], r, ig[0], re);
+  ld_spinor<S, O32>(rho[1], r, ig[1], ro);
+  if (a.do_bnd) {
+    bnd(0, re);
+    bnd(1, ro);
+  }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) ro_l[k][j] = ro[k];
+  // source reduction: w = A_o^{-1} rho_o (odd sites); b = rho_e + 1/2 H_L w
+  clover(1, ro, w);
+  hop(0, w, acc);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    rr[k] = cacc(re[k], T(0.5), acc[k]);
+    xs[k] = {T(0), T(0)};
+  }
+  // minimal-residual steps on Dhat_L: p = A_e r + 1/2 H_L A_o^{-1} (-1/2 H_L r),
+  // alpha = <p, r> / <p, p>, x += alpha r, r -= alpha p
+  for (int it = 0; it < a.nmr; ++it) {
+    hop(1, rr, acc);  // odd sites: acc = H_L r
+    {
+      cx<T> hh[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) hh[k] = T(-0.5) * acc[k];
+      clover(1, hh, w);  // w = A_o^{-1} (-1/2 H_L r)
+    }
+    hop(0, w, acc);  // even sites: acc = H_L w
+    cx<T> pe[12];
+    clover(0, rr, pe);
+    T pr_re = 0, pr_im = 0, pp = 0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      pe[k] = cacc(pe[k], T(0.5), acc[k]);
+      pr_re = fmar(pe[k].re, rr[k].re, fmar(pe[k].im, rr[k].im, pr_re));
+      pr_im = fmar(pe[k].re, rr[k].im, fmar(-pe[k].im, rr[k].re, pr_im));
+      pp = fmar(pe[k].re, pe[k].re, fmar(pe[k].im, pe[k].im, pp));
+    }
+    pr_re = wsum(pr_re);
+    pr_im = wsum(pr_im);
+    pp = wsum(pp);
+    // per-wave partials in alternating slots, so that one barrier per step
+    // suffices: a slot is rewritten two steps later, after the hops' barriers
+    const int sl = it & 1;
+    if ((j & 63) == 0) {
+      red[sl][0][j >> 6] = pr_re;
+      red[sl][1][j >> 6] = pr_im;
+      red[sl][2][j >> 6] = pp;
+    }
+    __syncthreads();
+    T s0 = 0, s1 = 0, s2 = 0;
+    for (int k = 0; k < nw; ++k) {
+      s0 += red[sl][0][k];
+      s1 += red[sl][1][k];
+      s2 += red[sl][2][k];
+    }
+    const cx<T> al = s2 > T(0) ? cx<T>{s0 / s2, s1 / s2} : cx<T>{T(0), T(0)};
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      xs[k] = fma_c(al, rr[k], xs[k]);
+      rr[k] = fma_c(cx<T>{-al.re, -al.im}, pe[k], rr[k]);
+    }
+  }
+  // odd reconstruction: v_o = A_o^{-1} (rho_o + 1/2 H_L v_e)
+  hop(1, xs, acc);
+  cx<T> vo[12];
+  {
+    cx<T> hh[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) hh[k] = cacc(ro_l[k][j], T(0.5), acc[k]);
+    clover(1, hh, vo);
+  }
+  // write back: psi += v, V = v, rho = new block residual (r even, 0 odd)
+  put(0, xs);
+  put(1, vo);
+  cx<T> zero[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) zero[k] = {T(0), T(0)};
+  st_spinor<S, O32>(rho[0], r, ig[0], rr);
+  st_spinor<S, O32>(rho[1], r, ig[1], zero);
+}
+
+// LDS-staged variants for FP16 storage: one workgroup per (block, group of R
+// right-hand sides).  The block's forward links (4 x 9 per site) and, with CL,
+// its clover blocks (A_e on the even, A_o^{-1} on the odd sites, 36 slots each)
+// are copied into LDS once and shared by the R right-hand sides the workgroup
+// solves side by side, so the hops of the MR loop read only LDS and registers.
+// With CL (R = 4, 124 KB of LDS) one workgroup fills a CU; without it (R = 2,
+// the clover read from memory at its ten uses per half-sweep, 62 KB) two
+// workgroups share a CU and overlap each other's barriers and staging.  Lane (q, j): right-hand side g0 + q of the group, site pair j (the j-th
+// even and the j-th odd site of the block); each right-hand side takes whole
+// wavefronts (nh rounded up to a multiple of 64 lanes), so its inner products
+// are wavefront sums plus one LDS step.  Hops are taken on the target side:
+// every lane writes its source spinor to the LDS exchange of its right-hand side,
+// then applies projection, link (its own forward link, or the neighbour's for a
+// backward hop, both in LDS) and reconstruction for each in-block neighbour.
+template <class S, class P, int R, bool CL, bool O32>
+__global__ void __launch_bounds__(R * kSapMaxHalf, CL ? 1 : 2) k_sap_lds(SapArgs<S, P> a) {
+  typedef typename St<S>::T T;
+  typedef typename St<S>::E E;
+  constexpr int H = kSapMaxHalf;
+  __shared__ E su[36][2 * H];           // forward links, [mu * 9 + k][parity * H + pair]
+  __shared__ E sc[CL ? 36 : 1][CL ? 2 * H : 1];  // clover slots, [slot][parity * H + pair] (CL)
+  __shared__ cx<T> ex[R][12][H];        // hop sources, per right-hand side
+  __shared__ int ig_l[2][H];            // index within its parity of every block site
+  __shared__ T red[2][3][R * H / 64];   // per-wave partial sums, by MR-step parity
+  const Geo& g = a.g;
+  const int nh = (a.bs[0] * a.bs[1] * a.bs[2] * a.bs[3]) >> 1;
+  const int nhp = (nh + 63) & ~63;  // lanes per right-hand side
+  const int t = threadIdx.x, q = t / nhp, j = t - q * nhp;
+  const bool on = j < nh;
+  const int nrg = (a.nrhs + R - 1) / R;
+  // workgroup -> (block of colour a.col, group of right-hand sides); the groups
+  // of a block go to the same XCD one after the other
+  int bi, rg;
+  {
+    const int id = blockIdx.x, nbc = gridDim.x / nrg;
+    if ((nbc & 7) == 0) {
+      const int rest = id >> 3;
+      rg = rest % nrg;
+      bi = (rest / nrg) * 8 + (id & 7);
+    } else {
+      rg = id % nrg;
+      bi = id / nrg;
+    }
+  }
+  const int r = rg * R + q;
+  const bool act = on && r < a.nrhs;
+  const int rs = act ? r : 0;
+  int bc[4];
+  {
+    int bl = 2 * bi;
+    bc[3] = bl % a.nb[3];
+    int rr = bl / a.nb[3];
+    bc[2] = rr % a.nb[2];
+    rr /= a.nb[2];
+    bc[1] = rr % a.nb[1];
+    bc[0] = rr / a.nb[1];
+    bc[3] += (a.col + bc[0] + bc[1] + bc[2] + bc[3]) & 1;
+  }
+  // the lane's two sites (pair jj; lanes beyond the block take pair 0 and only
+  // feed barriers): coordinates, index within the parity, in-block neighbour slots
+  const int jj = on ? j : 0;
+  int x[2][4], ig[2], nin[2][4][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    int y[4];
+    int l = 2 * jj;
+    y[3] = l % a.bs[3];
+    int rr = l / a.bs[3];
+    y[2] = rr % a.bs[2];
+    rr /= a.bs[2];
+    y[1] = rr % a.bs[1];
+    y[0] = rr / a.bs[1];
+    y[3] += (p + y[0] + y[1] + y[2] + y[3]) & 1;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) x[p][m] = bc[m] * a.bs[m] + y[m];
+    ig[p] = lex_of(g, x[p]) >> 1;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        int z[4] = {y[0], y[1], y[2], y[3]};
+        z[m] += d == 0 ? 1 : -1;
+        bool in = z[m] >= 0 && z[m] < a.bs[m];
+        nin[p][m][d] = in ? ((((z[0] * a.bs[1] + z[1]) * a.bs[2] + z[2]) * a.bs[3] + z[3]) >> 1) : -1;
+      }
+    }
+  }
+  if (q == 0 && on) {
+    ig_l[0][j] = ig[0];
+    ig_l[1][j] = ig[1];
+  }
+  __syncthreads();
+  // stage the block's links and clover blocks (once for the R right-hand sides):
+  // element (slot, site) of (CL ? 72 : 36) x 2 nh; when the workgroup size is a
+  // multiple of 2 nh every lane keeps one site and steps through the slots
+  constexpr int NSLOT = CL ? 72 : 36;
+  auto stage = [&](int slot, int par, int js, int gi) __attribute__((always_inline)) {
+    if (slot < 36) {
+      su[slot][par * H + js] = a.U.p[((int64_t)par * 36 + slot) * a.U.n + gi];
+    } else if constexpr (CL) {
+      const CloverV<S>& c = par == 0 ? a.A : a.Ai;
+      sc[slot - 36][par * H + js] = c.p[((int64_t)par * 36 + (slot - 36)) * c.n + gi];
+    }
+  };
+  const int ns2 = 2 * nh;
+  if ((int)blockDim.x % ns2 == 0) {
+    const int site = t % ns2, par = site >= nh, js = site - par * nh, gi = ig_l[par][js];
+    const int step = (int)blockDim.x / ns2;
+    for (int slot = t / ns2; slot < NSLOT; slot += step) stage(slot, par, js, gi);
+  } else {
+    for (int e = t; e < NSLOT * ns2; e += blockDim.x) {
+      const int site = e % ns2, slot = e / ns2;
+      const int par = site >= nh, js = site - par * nh;
+      stage(slot, par, js, ig_l[par][js]);
+    }
+  }
+  auto link = [&](int par, int m, int js, cx<T> u[9]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = St<S>::from(su[m * 9 + k][par * H + js]);
+  };
+  auto clover = [&](int par, const cx<T> in[12], cx<T> out[12]) __attribute__((always_inline)) {
+    if constexpr (CL) {
+#pragma unroll
+      for (int blk = 0; blk < 2; ++blk) {
+        cx<T> c[18];
+#pragma unroll
+        for (int k = 0; k < 18; ++k) c[k] = St<S>::from(sc[blk * 18 + k][par * H + jj]);
+        herm6_mul<T>(c, in + 6 * blk, out + 6 * blk);
+      }
+    } else {
+      // from memory (L2), behind an opaque zero so that the loads stay at their use
+      int z = 0;
+      asm volatile("" : "+v"(z));
+      clover_apply_u<S>(par == 0 ? a.A : a.Ai, par, ig[par] + z, in, out);
+    }
+  };
+  // src (the lane's site of parity 1 - tp) -> LDS; acc (its site of parity tp) = H_L src
+  auto hop = [&](const int tp, const cx<T> src[12], cx<T> acc[12]) __attribute__((always_inline)) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 12; ++k) ex[q][k][j] = src[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int jf = nin[tp][m][0], jb = nin[tp][m][1];
+      cx<T> sv[12], h[6], gg[6], u[9];
+      if (jf >= 0) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) sv[k] = ex[q][k][jf];
+        link(tp, m, jj, u);
+        if (m == 0) { project<T, 0, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 0, +1>(gg, acc); }
+        else if (m == 1) { project<T, 1, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 1, +1>(gg, acc); }
+        else if (m == 2) { project<T, 2, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 2, +1>(gg, acc); }
+        else { project<T, 3, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 3, +1>(gg, acc); }
+      }
+      if (jb >= 0) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) sv[k] = ex[q][k][jb];
+        link(1 - tp, m, jb, u);
+        if (m == 0) { project<T, 0, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 0, -1>(gg, acc); }
+        else if (m == 1) { project<T, 1, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 1, -1>(gg, acc); }
+        else if (m == 2) { project<T, 2, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 2, -1>(gg, acc); }
+        else { project<T, 3, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 3, -1>(gg, acc); }
+      }
+    }
+  };
+  FieldV<S> rho[2] = {a.rho, a.rho}, vf[2] = {a.V, a.V};
+  FieldV<P> psi[2] = {a.psi, a.psi};
+  rho[1].p += a.poff;
+  vf[1].p += a.poff;
+  psi[1].p += a.poff;
+  if (a.rho.scale) {
+    rho[1].scale += a.spoff;
+    vf[1].scale += a.spoff;
+  }
+  if (a.psi.scale) psi[1].scale += a.spoff;
+  // rp += 1/2 H_face V at the lane's site of parity p (the sites across the faces
+  // belong to blocks of the other colour, whose corrections V the previous
+  // half-sweep stored; a backward link across a face lies outside the block)
+  auto bnd = [&](const int p, cx<T> (&rp)[12]) __attribute__((always_inline)) {
+    cx<T> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+    const FieldV<S>& vn = vf[1 - p];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      cx<T> sv[12], h[6], gg[6], u[9];
+      if (nin[p][m][0] < 0) {
+        ld_spinor<S, O32>(vn, rs, nbr_idx(g, x[p], m, +1), sv);
+        link(p, m, jj, u);
+        if (m == 0) { project<T, 0, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 0, +1>(gg, acc); }
+        else if (m == 1) { project<T, 1, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 1, +1>(gg, acc); }
+        else if (m == 2) { project<T, 2, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 2, +1>(gg, acc); }
+        else { project<T, 3, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 3, +1>(gg, acc); }
+      }
+      if (nin[p][m][1] < 0) {
+        const int jn = nbr_idx(g, x[p], m, -1);
+        ld_spinor<S, O32>(vn, rs, jn, sv);
+        ld_link_u<S>(a.U, 1 - p, m, jn, u);
+        if (m == 0) { project<T, 0, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 0, -1>(gg, acc); }
+        else if (m == 1) { project<T, 1, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 1, -1>(gg, acc); }
+        else if (m == 2) { project<T, 2, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 2, -1>(gg, acc); }
+        else { project<T, 3, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 3, -1>(gg, acc); }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) rp[k] = cacc(rp[k], T(0.5), acc[k]);
+  };
+  auto put = [&](const int p, const cx<T> (&v)[12]) __attribute__((always_inline)) {
+    typedef typename St<P>::T TP;
+    cx<TP> pv[12];
+    if (a.first) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) pv[k] = {(TP)v[k].re, (TP)v[k].im};
+    } else {
+      ld_spinor<P, O32>(psi[p], r, ig[p], pv);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) pv[k] = pv[k] + cx<TP>{(TP)v[k].re, (TP)v[k].im};
+    }
+    st_spinor<P, O32>(psi[p], r, ig[p], pv);
+    if (a.write_v) st_spinor<S, O32>(vf[p], r, ig[p], v);
+  };
+
+  cx<T> re[12], ro[12], rr[12], xs[12], w[12], acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) re[k] = ro[k] = {T(0), T(0)};
+  if (act) {
+    ld_spinor<S, O32>(rho[0], r, ig[0], re);
+    ld_spinor<S, O32>(rho[1], r, ig[1], ro);
+    if (a.do_bnd) {
+      bnd(0, re);
+      bnd(1, ro);
+    }
+  }
+  __syncthreads();  // the staged links and clover are complete
+  // source reduction: w = A_o^{-1} rho_o (odd sites); b = rho_e + 1/2 H_L w
+  clover(1, ro, w);
+  hop(0, w, acc);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    rr[k] = cacc(re[k], T(0.5), acc[k]);
+    xs[k] = {T(0), T(0)};
+  }
+  const int wpr = nhp >> 6;  // wavefronts per right-hand side
+  for (int it = 0; it < a.nmr; ++it) {
+    hop(1, rr, acc);  // odd sites: acc = H_L r
+    {
+      cx<T> hh[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) hh[k] = T(-0.5) * acc[k];
+      clover(1, hh, w);  // w = A_o^{-1} (-1/2 H_L r)
+    }
+    hop(0, w, acc);  // even sites: acc = H_L w
+    cx<T> pe[12];
+    clover(0, rr, pe);
+    T pr_re = 0, pr_im = 0, pp = 0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      pe[k] = cacc(pe[k], T(0.5), acc[k]);
+      pr_re = fmar(pe[k].re, rr[k].re, fmar(pe[k].im, rr[k].im, pr_re));
+      pr_im = fmar(pe[k].re, rr[k].im, fmar(-pe[k].im, rr[k].re, pr_im));
+      pp = fmar(pe[k].re, pe[k].re, fmar(pe[k].im, pe[k].im, pp));
+    }
+    if (!act) pr_re = pr_im = pp = T(0);
+    pr_re = wsum(pr_re);
+    pr_im = wsum(pr_im);
+    pp = wsum(pp);
+    // per-wave partials in alternating slots: one barrier per step
+    const int sl = it & 1;
+    if ((t & 63) == 0) {
+      red[sl][0][t >> 6] = pr_re;
+      red[sl][1][t >> 6] = pr_im;
+      red[sl][2][t >> 6] = pp;
+    }
+    __syncthreads();
+    T s0 = 0, s1 = 0, s2 = 0;
+    for (int k = q * wpr; k < (q + 1) * wpr; ++k) {
+      s0 += red[sl][0][k];
+      s1 += red[sl][1][k];
+      s2 += red[sl][2][k];
+    }
+    const cx<T> al = s2 > T(0) ? cx<T>{s0 / s2, s1 / s2} : cx<T>{T(0), T(0)};
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      xs[k] = fma_c(al, rr[k], xs[k]);
+      rr[k] = fma_c(cx<T>{-al.re, -al.im}, pe[k], rr[k]);
+    }
+  }
+  // odd reconstruction: v_o = A_o^{-1} (rho_o + 1/2 H_L v_e)
+  hop(1, xs, acc);
+  cx<T> vo[12];
+  {
+    cx<T> hh[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) hh[k] = cacc(ro[k], T(0.5), acc[k]);
+    clover(1, hh, vo);
+  }
+  if (!act) return;
+  put(0, xs);
+  put(1, vo);
+  cx<T> zero[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) zero[k] = {T(0), T(0)};
+  st_spinor<S, O32>(rho[0], r, ig[0], rr);
+  st_spinor<S, O32>(rho[1], r, ig[1], zero);
 }
 
 // One lane per even/odd site pair of the block: lane j owns the j-th even and
@@ -647,8 +1223,39 @@ hipError_t launch_sap_half(const SapArgs<S, P>& a, int nblk_colour, hipStream_t 
     else
       hipLaunchKernelGGL((k_sap_pair<S, P, 2, false>), dim3(nblk_colour), dim3(nsb / 2), 0, st, a);
   } else {
-    // FP32 / FP16 storage: one lane per site, own links and clover in registers
-    hipLaunchKernelGGL((k_sap_half<S, P, 4>), dim3(nblk_colour), dim3(nsb), 0, st, a);
+    const int v = a.variant ? a.variant : sap_default_variant(sizeof(S) == 2 ? 2 : 1);
+    const bool o32 = sap_fits32(a.rho, a.nrhs, a.poff, a.spoff) && sap_fits32(a.V, a.nrhs, a.poff, a.spoff) &&
+                     sap_fits32(a.psi, a.nrhs, a.poff, a.spoff);
+    if (v == kSapPerSite) {
+      // one lane per site, own links and clover in registers, rhs one after another
+      hipLaunchKernelGGL((k_sap_half<S, P, 4>), dim3(nblk_colour), dim3(nsb), 0, st, a);
+    } else if (v == kSapPerRhs) {
+      // one workgroup per (block, right-hand side)
+      const dim3 grid((unsigned)nblk_colour * (unsigned)a.nrhs), blk(nsb / 2);
+      if (o32) hipLaunchKernelGGL((k_sap_rhs<S, P, true>), grid, blk, 0, st, a);
+      else hipLaunchKernelGGL((k_sap_rhs<S, P, false>), grid, blk, 0, st, a);
+    } else if constexpr (sizeof(S) == 2) {
+      const int nhp = ((nsb / 2) + 63) & ~63;
+      if (v == kSapStaged) {
+        // one workgroup per (block, group of 4 right-hand sides), the block's links
+        // and clover staged in LDS
+        constexpr int R = 4;
+        const dim3 grid((unsigned)nblk_colour * (unsigned)((a.nrhs + R - 1) / R)), blk(R * nhp);
+        if (o32) hipLaunchKernelGGL((k_sap_lds<S, P, R, true, true>), grid, blk, 0, st, a);
+        else hipLaunchKernelGGL((k_sap_lds<S, P, R, true, false>), grid, blk, 0, st, a);
+      } else if (v == kSapStagedLinks) {
+        // one workgroup per (block, pair of right-hand sides), the links staged
+        // in LDS, two workgroups per CU
+        constexpr int R = 2;
+        const dim3 grid((unsigned)nblk_colour * (unsigned)((a.nrhs + R - 1) / R)), blk(R * nhp);
+        if (o32) hipLaunchKernelGGL((k_sap_lds<S, P, R, false, true>), grid, blk, 0, st, a);
+        else hipLaunchKernelGGL((k_sap_lds<S, P, R, false, false>), grid, blk, 0, st, a);
+      } else {
+        return hipErrorInvalidValue;
+      }
+    } else {
+      return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }

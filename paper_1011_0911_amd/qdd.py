@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libqdd.so")
 
 F64, F32, F16 = 0, 1, 2
 PRECOND_NONE, PRECOND_SAP, PRECOND_DFL = 0, 1, 2
-KERNEL_DHAT, KERNEL_DW = 0, 1
+KERNEL_DHAT, KERNEL_DW, KERNEL_SAP = 0, 1, 2
 # candidate set of the autotuner (cached choices of an older set are re-measured)
 TUNER_VERSION = "t4"
 
@@ -434,6 +434,8 @@ class Context:
         cache dict, a previously measured choice for the same key is reused."""
         key = (f"{TUNER_VERSION}/{kernel}/{prec}/{nrhs}/{'x'.join(map(str, self.L))}/"
                f"{torch.cuda.get_device_properties(self.device).gcnArchName}")
+        if kernel == KERNEL_SAP:  # the variants' relative cost depends on the block and the MR steps
+            key += f"/bs{'x'.join(str(b) for b in self.cfg.sap_bs)}/nmr{self.cfg.nmr}"
         if cache is not None and key in cache:
             b, n, x, s = cache[key]["launch"]
             self.set_launch(kernel, prec, b, n, x, s)
@@ -443,6 +445,20 @@ class Context:
         if cache is not None:
             cache[key] = {"launch": list(self.get_launch(kernel, prec)), "ms": ms.value}
         return ms.value
+
+    def tune_sap(self, nrhs, reps=2, cache=None):
+        """Picks the fastest Schwarz half-sweep kernel variant for the configured SAP
+        precision and a batch of nrhs (timed on whole preconditioner calls with
+        Gaussian sources).  Returns the mean duration of the fastest (ms), or None
+        for FP64, which has a single kernel."""
+        if self.cfg.sap_prec == F64:
+            return None
+        g = torch.Generator(device=self.device)
+        g.manual_seed(9000)
+        eta = torch.randn((nrhs, self.V, 12, 2), dtype=torch.float64, device=self.device, generator=g)
+        fin = self.pack(F64, torch.view_as_complex(eta), False)
+        fout = self.empty_field(F32, nrhs, False)
+        return self.autotune(KERNEL_SAP, self.cfg.sap_prec, nrhs, fin, fout, reps=reps, cache=cache)
 
     def dw_hat_timed(self, prec, nrhs, fin, fout, reps):
         """Mean per-pass durations (ms) of `reps` Dhat applies, HIP events on the context stream."""

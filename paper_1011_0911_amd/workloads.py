@@ -9,6 +9,7 @@ sources 4000+; deflation start fields 5000 + i.
 """
 from __future__ import annotations
 
+import os
 import time
 
 import numpy as np
@@ -30,15 +31,24 @@ WORKLOADS = {
 }
 
 
-def make_context(L, eps, kappa, csw, gauge_seed, U=None, **cfg):
-    """Context with the gauge field and clover set up; returns (ctx, links)."""
+TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+
+def make_context(L, eps, kappa, csw, gauge_seed, U=None, tune_nrhs=0, stream=None, **cfg):
+    """Context with the gauge field and clover set up; returns (ctx, links).
+    tune_nrhs > 0: the Schwarz kernel variant is tuned for that batch size (the
+    choice is cached in the package's tuner cache)."""
     import torch
 
     if U is None:
         U = S.random_su3_links(L, eps, gauge_seed)
-    c = qdd.Context(L, qdd.default_config(**cfg))
+    c = qdd.Context(L, qdd.default_config(**cfg), stream=stream)
     c.set_gauge(torch.from_numpy(U))
     c.set_params(kappa, csw)
+    if tune_nrhs > 0 and c.cfg.sap_prec != qdd.F64 and c.cfg.precond != qdd.PRECOND_NONE:
+        cache = qdd.load_tune_cache(TUNE_CACHE)
+        c.tune_sap(tune_nrhs, cache=cache)
+        qdd.save_tune_cache(TUNE_CACHE, cache)
     return c, U
 
 
@@ -82,7 +92,7 @@ def run_solve_workload(wid: int, plain_rhs: int = 1, log=print, U=None):
     eta = np.stack([S.gaussian_field(V, S.source_seed(wid, r)) for r in range(nrhs)])
     init = S.gaussian_field(V, S.dfl_seed(wid), nrhs=w.get("dfl_Ns", 1))
     # mixed precision, batched
-    ctx, _ = make_context(L, w["eps"], w["kappa"], w["csw"], 0, U=U, **solver_config(w, nrhs))
+    ctx, _ = make_context(L, w["eps"], w["kappa"], w["csw"], 0, U=U, tune_nrhs=nrhs, **solver_config(w, nrhs))
     if w.get("dfl_Ns"):
         torch.cuda.synchronize()
         t0 = time.time()
@@ -148,7 +158,7 @@ def run_learned(wid: int = 5, train_pairs: int | None = None, chunk_pairs: int =
     out = {"workload": wid, "lattice": "x".join(map(str, L)), "train_pairs_target": npairs}
     U = S.random_su3_links(L, w["eps"], S.gauge_seed(wid))
     init = S.gaussian_field(V, S.dfl_seed(wid), nrhs=w["dfl_Ns"])
-    ctx, _ = make_context(L, w["eps"], w["kappa"], w["csw"], 0, U=U,
+    ctx, _ = make_context(L, w["eps"], w["kappa"], w["csw"], 0, U=U, tune_nrhs=ntest,
                           **solver_config(w, ntest, use_net=True))
     t0 = time.time()
     ctx.dfl_build(init)
@@ -209,7 +219,7 @@ def run_learned(wid: int = 5, train_pairs: int | None = None, chunk_pairs: int =
     del ctx
     torch.cuda.empty_cache()
     # plain method proper: no network stage at all
-    pctx, _ = make_context(L, w["eps"], w["kappa"], w["csw"], 0, U=U, **solver_config(w, ntest))
+    pctx, _ = make_context(L, w["eps"], w["kappa"], w["csw"], 0, U=U, tune_nrhs=ntest, **solver_config(w, ntest))
     pctx.dfl_build(init)
     psi1, info1, st1, dt1 = timed_solve(pctx, eta)
     out["plain"] = {"solve_s": dt1, "iters": [i["iters"] for i in info1],
@@ -238,9 +248,8 @@ def run_multi(wid: int = 4, nkv: int = 8, log=print):
         init = S.gaussian_field(V, S.dfl_seed(wid) + 10 * li, nrhs=w["dfl_Ns"])
         group = []
         for ki, kappa in enumerate(w["kappas"]):
-            c = qdd.Context(L, qdd.default_config(**solver_config(w, nrhs, nkv=nkv)), stream=torch.cuda.Stream())
-            c.set_gauge(torch.from_numpy(U))
-            c.set_params(kappa, w["csw"])
+            c, _ = make_context(L, w["eps"], kappa, w["csw"], 0, U=U, tune_nrhs=nrhs, stream=torch.cuda.Stream(),
+                                **solver_config(w, nrhs, nkv=nkv))
             group.append(c)
             etas.append(np.stack([S.gaussian_field(V, S.source_seed(wid, 10 * li + r) + ki) for r in range(nrhs)]))
             names.append(f"{'x'.join(map(str, L))}/k{kappa}")
@@ -322,16 +331,43 @@ def time_network(wid: int = 5, reps: int = 5, nb: int = 4, log=print):
     return out
 
 
+def time_sap(L=(64, 32, 32, 32), prec=qdd.F16, nrhs=8, reps=3, log=print):
+    """Every Schwarz half-sweep kernel variant on one lattice (random links
+    exp(i 0.6 H), kappa 0.1357, c_sw 1.9, 4^4 blocks, nmr 4, ncy 5): mean wall time
+    of reps preconditioner calls M_sap on nrhs Gaussian sources (canonical fields
+    in and out, so packing included).  Returns a dict; run it under rocprofv3 for
+    the per-kernel times."""
+    import torch
+
+    V = int(np.prod(L))
+    ctx, _ = make_context(L, 0.6, 0.1357, 1.9, S.gauge_seed(3) if L == (64, 32, 32, 32) else 1600,
+                          max_nrhs=nrhs, sap_prec=prec, precond=qdd.PRECOND_SAP, nkv=1)
+    eta = S.gaussian_field_device(V, 77, nrhs)
+    out = {"lattice": "x".join(map(str, L)), "prec": prec, "nrhs": nrhs, "ms_per_call": {}}
+    for v in ((1, 2, 3, 4) if prec == qdd.F16 else (1, 2)):
+        ctx.set_launch(qdd.KERNEL_SAP, prec, 0, v, 0, 0)
+        ctx.sap(eta)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for _ in range(reps):
+            ctx.sap(eta)
+        torch.cuda.synchronize()
+        out["ms_per_call"][v] = (time.time() - t0) / reps * 1e3
+        log(f"[sap] variant {v}: {out['ms_per_call'][v]:.1f} ms per call")
+    return out
+
+
 def main(argv=None):
     """Command line: python -m paper_1011_0911_amd.workloads WID [--pairs N]
     runs one workload driver on cuda:0 and prints its result as one JSON line;
     WID = net times the network forward pass and a training step on the
-    workload-5 lattice."""
+    workload-5 lattice, WID = sap every Schwarz kernel variant on the workload-3
+    lattice (FP16 storage, 8 right-hand sides)."""
     import argparse
     import json
 
     ap = argparse.ArgumentParser()
-    ap.add_argument("wid", choices=["2", "3", "4", "5", "net"])
+    ap.add_argument("wid", choices=["2", "3", "4", "5", "net", "sap"])
     ap.add_argument("--pairs", type=int, default=None, help="training pairs (workload 5)")
     ap.add_argument("--chunk", type=int, default=64, help="pairs per streamed training chunk (workload 5)")
     ap.add_argument("--epochs", type=int, default=1)
@@ -341,6 +377,8 @@ def main(argv=None):
     log = lambda m: print(m, flush=True)  # noqa: E731
     if a.wid == "net":
         r = time_network(5, log=log)
+    elif a.wid == "sap":
+        r = time_sap(log=log)
     elif a.wid == "5":
         r = run_learned(5, train_pairs=a.pairs, chunk_pairs=a.chunk, epochs=a.epochs, log=log)
     elif a.wid == "4":

@@ -31,20 +31,53 @@ def Q():
     return qdd
 
 
+# every kernel variant of each storage precision (FP64 has one): 1 per site with
+# links in registers, 2 per (block, rhs), for FP16 also 3 (links and clover staged
+# in LDS, 4 rhs per workgroup) and 4 (links staged, 2 rhs per workgroup); 5 rhs so
+# that the staged variants also run a partly filled group
+VARIANTS = [(0, 0), (1, 1), (1, 2), (2, 1), (2, 2), (2, 3), (2, 4)]
+
+
 @pytest.mark.parametrize("L,bs,ncy,nmr", [((8, 8, 8, 8), (4, 4, 4, 4), 5, 4), ((8, 4, 4, 8), (2, 2, 2, 2), 3, 2),
                                           ((4, 8, 4, 4), (2, 4, 2, 2), 1, 1)])
-@pytest.mark.parametrize("prec", [0, 1, 2])
-def test_sap_parity(Q, orc, L, bs, ncy, nmr, prec):
+@pytest.mark.parametrize("prec,variant", VARIANTS)
+def test_sap_parity(Q, orc, L, bs, ncy, nmr, prec, variant):
     V = int(np.prod(L))
-    ctx, U = make_ctx(Q, L, 0.6, 0.1357, 1.9, 500 + V, sap_bs=bs, ncy=ncy, nmr=nmr, sap_prec=prec, max_nrhs=2)
+    nr = 5
+    ctx, U = make_ctx(Q, L, 0.6, 0.1357, 1.9, 500 + V, sap_bs=bs, ncy=ncy, nmr=nmr, sap_prec=prec, max_nrhs=nr)
+    if variant:
+        ctx.set_launch(Q.KERNEL_SAP, prec, 0, variant, 0, 0)
+    assert ctx.get_launch(Q.KERNEL_SAP, prec)[1] == variant
     A, Ai = orc.clover(L, U, 0.1357, 1.9)
-    eta = S.gaussian_field(V, 501, nrhs=2)
+    eta = S.gaussian_field(V, 501, nrhs=nr)
     out = to_np(ctx.sap(eta))
-    for r in range(2):
+    for r in (0, 1, nr - 1):
         ref = orc.sap(L, U, A, Ai, eta[r], bs, ncy, nmr)
         e = relerr(out[r], ref)
-        print(f"SAP L={L} bs={bs} prec={prec} rhs={r} err={e:.2e}")
+        print(f"SAP L={L} bs={bs} prec={prec} variant={variant} rhs={r} err={e:.2e}")
         assert e < TOL[prec], e
+
+
+def test_sap_variants_rejected_where_missing(Q):
+    ctx, _ = make_ctx(Q, (4, 4, 4, 4), 0.6, 0.1357, 1.9, 509, sap_bs=(2, 2, 2, 2), sap_prec=1)
+    for prec, v in ((1, 3), (0, 1), (2, 5), (1, 0)):
+        with pytest.raises(Q.QddError):
+            ctx.set_launch(Q.KERNEL_SAP, prec, 0, v, 0, 0)
+    with pytest.raises(Q.QddError):
+        ctx.set_launch(Q.KERNEL_SAP, 1, 64, 1, 0, 0)
+
+
+def test_sap_autotune_picks_a_variant(Q, orc):
+    L, bs = (8, 8, 8, 8), (4, 4, 4, 4)
+    ctx, U = make_ctx(Q, L, 0.6, 0.1357, 1.9, 506, sap_bs=bs, sap_prec=2, precond=Q.PRECOND_SAP, max_nrhs=4)
+    ms = ctx.tune_sap(4)
+    v = ctx.get_launch(Q.KERNEL_SAP, 2)[1]
+    print("tuned Schwarz variant", v, "ms", ms)
+    assert v in (1, 2, 3, 4) and ms > 0
+    A, Ai = orc.clover(L, U, 0.1357, 1.9)
+    eta = S.gaussian_field(4096, 507, nrhs=4)
+    out = to_np(ctx.sap(eta))
+    assert relerr(out[3], orc.sap(L, U, A, Ai, eta[3], bs, 5, 4)) < TOL[2]
 
 
 def test_sap_is_deterministic(Q):
