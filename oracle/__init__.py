@@ -387,3 +387,46 @@ def apply_W(L, U, A, dm, pe, bc=-1):
         q = np.linalg.solve(Qee, q[..., None])[..., 0]
         out[r] = pe2[r] - q.reshape(-1, 4, 3) + dm * pe2[r]
     return out.reshape(lead + pe.shape[-3:])
+
+
+def solve_W(L, U, A, dm, phi, tol=1e-12, bc=-1):
+    """chi with W(dm) chi = phi (Eq. 3) for even fields phi (..., V/2, 4, 3): W is
+    built as a dense matrix from apply_W on unit vectors and solved by LU when it
+    has at most 1536 rows; larger systems use restarted GMRES (scipy) on the
+    operator apply_W to relative residual tol.  dm = 0 gives Q_S^{-1} phi."""
+    phi = _cc(phi)
+    lead = phi.shape[:-3]
+    p2 = phi.reshape((-1,) + phi.shape[-3:])
+    n = p2[0].size
+    out = np.empty_like(p2)
+    if n <= 1536:
+        eye = np.eye(n, dtype=np.complex128).reshape((n,) + p2.shape[1:])
+        Wd = apply_W(L, U, A, dm, eye, bc).reshape(n, n).T
+        for r in range(p2.shape[0]):
+            out[r] = np.linalg.solve(Wd, p2[r].reshape(-1)).reshape(p2.shape[1:])
+    else:
+        from scipy.sparse.linalg import LinearOperator, gmres
+
+        op = LinearOperator((n, n), dtype=np.complex128,
+                            matvec=lambda v: apply_W(L, U, A, dm, v.reshape(p2.shape[1:]), bc).reshape(-1))
+        for r in range(p2.shape[0]):
+            x, info = gmres(op, p2[r].reshape(-1), rtol=tol, atol=0.0, restart=200, maxiter=50)
+            if info != 0:
+                raise ArithmeticError(f"GMRES on W did not reach {tol}")
+            out[r] = x.reshape(p2.shape[1:])
+    return out.reshape(lead + phi.shape[-3:])
+
+
+def s_eff(L, U, kappa, csw, dm, phi1, phi2, tol=1e-12, bc=-1):
+    """The effective action of Eq. 4 with two pseudofermion fields (even fields):
+    S = -2 (log det Q_ee + log det Q_oo) + |W^{-1}(dm) phi1|^2 + |(1 + dm Q_S^{-1}) phi2|^2,
+    reading the dm/Q_S of Eq. 4 as dm Q_S^{-1}.  Returns (S, (the log-det term,
+    the phi1 term, the phi2 term))."""
+    le, lo = clover_logdet(L, U, kappa, csw, bc)
+    A, _ = clover(L, U, kappa, csw, bc)
+    chi1 = solve_W(L, U, A, dm, phi1, tol, bc)
+    chi2 = solve_W(L, U, A, 0.0, phi2, tol, bc)
+    t0 = -2.0 * (le + lo)
+    t1 = float(np.vdot(chi1, chi1).real)
+    t2 = float(np.vdot(_cc(phi2) + dm * chi2, _cc(phi2) + dm * chi2).real)
+    return t0 + t1 + t2, (t0, t1, t2)

@@ -71,3 +71,68 @@ def test_w_is_shifted_schur_complement_of_dhat(setup):
     dh = np.stack([O.apply_Dhat(L, U, A, Ai, f) for f in pe])  # one field per call
     ref = np.einsum("iab,rib->ria", Ai[ev], dh.reshape(2, -1, 12)).reshape(pe.shape) + dm * pe
     assert np.abs(w - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def dense_blocks(Q):
+    """Even-even, even-odd, odd-even, odd-odd blocks of a dense site-major matrix."""
+    ev, od = O._sites(L)
+    ie = (12 * ev[:, None] + np.arange(12)[None]).reshape(-1)
+    io = (12 * od[:, None] + np.arange(12)[None]).reshape(-1)
+    return Q[np.ix_(ie, ie)], Q[np.ix_(ie, io)], Q[np.ix_(io, ie)], Q[np.ix_(io, io)]
+
+
+def test_eq4_action_against_dense_matrices(setup):
+    # every term of Eq. 4 from the dense blocks of Q = gamma5 D, independently of the
+    # oracle's per-site log determinants and its W and Q_S routines
+    U, A, Ai, Q, _ = setup
+    Qee, Qeo, Qoe, Qoo = dense_blocks(Q)
+    n = Qee.shape[0]
+    QS = np.eye(n) - np.linalg.solve(Qee, Qeo @ np.linalg.solve(Qoo, Qoe))
+    V = int(np.prod(L))
+    phi = S.gaussian_field(V // 2, 24, nrhs=2)
+    for dm in (0.09, 0.5):
+        W = QS + dm * np.eye(n)
+        t0 = -2.0 * (np.linalg.slogdet(Qee)[1] + np.linalg.slogdet(Qoo)[1])
+        t1 = np.linalg.norm(np.linalg.solve(W, phi[0].reshape(-1))) ** 2
+        t2 = np.linalg.norm(phi[1].reshape(-1) + dm * np.linalg.solve(QS, phi[1].reshape(-1))) ** 2
+        s, parts = O.s_eff(L, U, KAPPA, CSW, dm, phi[0], phi[1])
+        for a, b in zip(parts, (t0, t1, t2)):
+            assert abs(a - b) < 1e-10 * abs(b)
+        assert abs(s - (t0 + t1 + t2)) < 1e-10 * abs(t0 + t1 + t2)
+
+
+def test_eq4_action_at_zero_mass_difference(setup):
+    # dm = 0: W = Q_S, so the phi1 term is |Q_S^{-1} phi1|^2 and the phi2 term |phi2|^2
+    U, A, Ai, Q, QS = setup
+    V = int(np.prod(L))
+    phi = S.gaussian_field(V // 2, 25, nrhs=2)
+    s, (t0, t1, t2) = O.s_eff(L, U, KAPPA, CSW, 0.0, phi[0], phi[1])
+    assert abs(t1 - np.linalg.norm(np.linalg.solve(QS, phi[0].reshape(-1))) ** 2) < 1e-10 * t1
+    assert abs(t2 - np.linalg.norm(phi[1]) ** 2) < 1e-12 * t2
+    # continuous in dm
+    s2, _ = O.s_eff(L, U, KAPPA, CSW, 1e-7, phi[0], phi[1])
+    assert abs(s2 - s) < 1e-5 * abs(t1 + t2)
+
+
+def test_eq4_action_on_constructed_pseudofermions(setup):
+    # phi1 = W(dm) chi1 gives |chi1|^2 for the phi1 term; phi2 = Q_S chi2 gives
+    # (1 + dm Q_S^{-1}) Q_S chi2 = W(dm) chi2 for the phi2 term
+    U, A, Ai, Q, QS = setup
+    V = int(np.prod(L))
+    chi = S.gaussian_field(V // 2, 26, nrhs=2)
+    dm = 0.3
+    phi1 = O.apply_W(L, U, A, dm, chi[0])
+    phi2 = O.apply_W(L, U, A, 0.0, chi[1])
+    _, (t0, t1, t2) = O.s_eff(L, U, KAPPA, CSW, dm, phi1, phi2)
+    assert abs(t1 - np.linalg.norm(chi[0]) ** 2) < 1e-10 * t1
+    assert abs(t2 - np.linalg.norm(O.apply_W(L, U, A, dm, chi[1])) ** 2) < 1e-10 * t2
+
+
+def test_w_solve_gmres_branch():
+    # lattices above the dense limit go through GMRES on the same operator
+    L8 = (4, 4, 4, 8)
+    U = S.random_su3_links(L8, 0.6, 27)
+    A, _ = O.clover(L8, U, 0.1357, 1.9)
+    phi = S.gaussian_field(256, 28)
+    x = O.solve_W(L8, U, A, 0.09, phi)
+    assert np.linalg.norm(O.apply_W(L8, U, A, 0.09, x) - phi) < 1e-11 * np.linalg.norm(phi)
