@@ -216,7 +216,7 @@ def solve_section(learned_pairs, U=None):
                "plain_fp64_s_8rhs": r3["plain_fp64"]["solve_s_batch_equiv"],
                "plain_iters": r3["plain_fp64"]["iters"], "speedup": r3["speedup_vs_plain"],
                "dfl_build_s": {"mixed": r3.get("dfl_build_s"), "plain_fp64": r3.get("plain_dfl_build_s")},
-               "qs_inverse_eq5": r3.get("qs_inverse")}}
+               "qs_inverse_eq5": r3.get("qs_inverse"), "action_eq4": r3.get("action_eq4")}}
     if learned_pairs > 0:
         r5 = W.run_learned(5, train_pairs=learned_pairs, log=log)
         sec["learned_vs_plain"] = {

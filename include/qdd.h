@@ -225,10 +225,33 @@ qdd_status qdd_apply_w(qdd_ctx* ctx, int nrhs, double dm, const void* in_e, void
 /* out_e = Q_S^{-1} phi_e by Eq. 5, Q_S^{-1} = P_e Q^{-1} Q_ee P_e: the configured
  * solver (as qdd_solve: FP64 flexible GCR, with deflation and SAP when
  * configured) solves D psi = (A_e phi_e on the even sites, 0 on the odd ones)
- * and out_e is the even half of psi.  phi_e, out_e: canonical complex128 even
- * fields (device), nrhs of them; info as for qdd_solve (the residual is that of
- * D).  Errors as for qdd_solve. */
+ * and out_e is the even half of psi.  The residual reported and tested is that
+ * of Q_S itself, |phi_e - Q_S out_e| / |phi_e| (FP64 Dhat, inverse even clover
+ * blocks); where it is above tol the same solve is run on it and the correction
+ * added (at most twice); info.iters counts all of them.  phi_e, out_e:
+ * canonical complex128 even fields (device), nrhs of them.  QDD_ENOCONV if a
+ * residual stays above tol; other errors as for qdd_solve. */
 qdd_status qdd_solve_qs(qdd_ctx* ctx, int nrhs, const double* phi_e, double* out_e, qdd_solve_info* info);
+/* out_e = W(dm)^{-1} phi_e (Eq. 3, W(dm) = Q_S + dm, dm >= 0).  Since
+ * W = A_e^{-1} (Dhat + dm A_e) and Dhat + dm A_e is the even-odd Schur complement
+ * of D' = D with the even sites' clover term scaled by 1 + dm, the configured
+ * solver solves D' psi = (A_e phi_e (+) 0) (its preconditioner is the one built
+ * for D) and out_e is the even half of psi; residual, refinement, arguments and
+ * errors as for qdd_solve_qs, with W(dm) in place of Q_S. */
+qdd_status qdd_solve_w(qdd_ctx* ctx, int nrhs, double dm, const double* phi_e, double* out_e, qdd_solve_info* info);
+/* Effective action of Eq. 4 with two pseudofermion fields phi1, phi2 (canonical
+ * complex128 even fields, device):
+ *   S_eff = -2 (log det Q_ee + log det Q_oo) + |W^{-1}(dm) phi1|^2 + |(1 + dm Q_S^{-1}) phi2|^2
+ * (the dm/Q_S of Eq. 4 read as dm Q_S^{-1}).  chi1 = W^{-1}(dm) phi1 and
+ * chi2 = Q_S^{-1} phi2 are returned in the caller's buffers (even fields; they are
+ * what the pseudofermion forces consume); the two solves run as one batch of two
+ * right-hand sides, so the context needs max_nrhs >= 2.  *s_eff (host) gets the
+ * total, parts (host, 3 doubles, optional) the log-det term and the two
+ * pseudofermion terms, info (2 entries, optional) the solves as in qdd_solve_w.
+ * QDD_EINVAL for dm < 0, max_nrhs < 2 or chi1 == chi2; else errors as for
+ * qdd_clover_logdet and qdd_solve_w. */
+qdd_status qdd_action(qdd_ctx* ctx, double dm, const double* phi1, const double* phi2, double* chi1, double* chi2,
+                      double* s_eff, double* parts, qdd_solve_info* info);
 
 /* ---- learned preconditioner stage (configuration use_net = 1) ----
  * A gauge-covariant parallel-transport convolution network N with net_nl

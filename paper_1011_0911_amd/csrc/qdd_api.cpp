@@ -121,6 +121,7 @@ void compute_layout(const qdd_geom* g, const qdd_config* c, Layout& Lo) {
   Lo.tmp_o = B.take((size_t)nr * 12 * Vh * 16);
   Lo.tmp_o_scale = B.take((size_t)nr * Vh * 4);
   Lo.dw_shift = B.take((size_t)kMaxShift * 8);
+  Lo.dw_ce = B.take((size_t)kMaxShift * 8);
   Lo.flag = B.take(256);
   // FP64 solver fields (full lattice, nr rhs)
   size_t f64 = (size_t)nr * 24 * Vh * 16;
@@ -575,13 +576,13 @@ hipError_t qdd_ctx::dhat(qdd_prec prec, int nrhs, void* in, void* out, hipEvent_
   }
 }
 
-hipError_t qdd_ctx::dw(qdd_prec prec, int nrhs, void* in, void* out) {
+hipError_t qdd_ctx::dw(qdd_prec prec, int nrhs, void* in, void* out, const double* ce) {
   PackedView a = packed(prec, nrhs, 0, in), b = packed(prec, nrhs, 0, out);
   const LaunchCfg& c = launch[1][prec];
   switch (prec) {
-    case QDD_F64: return launch_dw<double>(G, op<double>(), a.f64, b.f64, a.poff, a.spoff, nrhs, c, st);
-    case QDD_F32: return launch_dw<float>(G, op<float>(), a.f32, b.f32, a.poff, a.spoff, nrhs, c, st);
-    default: return launch_dw<__half>(G, op<__half>(), a.f16, b.f16, a.poff, a.spoff, nrhs, c, st);
+    case QDD_F64: return launch_dw<double>(G, op<double>(), a.f64, b.f64, a.poff, a.spoff, nrhs, c, st, nullptr, ce);
+    case QDD_F32: return launch_dw<float>(G, op<float>(), a.f32, b.f32, a.poff, a.spoff, nrhs, c, st, nullptr, ce);
+    default: return launch_dw<__half>(G, op<__half>(), a.f16, b.f16, a.poff, a.spoff, nrhs, c, st, nullptr, ce);
   }
 }
 

@@ -18,7 +18,7 @@ constexpr int kCoarseKv = 16;      // Krylov vectors of the little-operator GCR
 // byte offsets of every buffer inside the caller's workspace
 struct Layout {
   size_t U[3], A[3], Ai[3];
-  size_t tmp_o, tmp_o_scale, flag, dw_shift;
+  size_t tmp_o, tmp_o_scale, flag, dw_shift, dw_ce;
   size_t eta, psi, res, t64, chi, phi;
   bool phi32;
   size_t s_rho, s_psi, s_v, s_eta, s_scale, s_tmp;
@@ -79,7 +79,8 @@ struct qdd_ctx {
   // the workspace's)
   hipError_t dhat(qdd_prec prec, int nrhs, void* in, void* out, hipEvent_t mid = nullptr, void* tmp = nullptr);
   size_t dhat_tmp_bytes(qdd_prec prec, int nrhs, size_t* scale_off = nullptr) const;
-  hipError_t dw(qdd_prec prec, int nrhs, void* in, void* out);
+  // ce (device, nrhs doubles, optional): factor on the even sites' clover term per rhs
+  hipError_t dw(qdd_prec prec, int nrhs, void* in, void* out, const double* ce = nullptr);
 };
 
 #define HCK(x, ...)                                                                   \

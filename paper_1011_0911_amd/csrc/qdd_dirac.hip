@@ -173,8 +173,12 @@ __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k
 }
 
 // full D on both parities; in/out: full fields (parity p at offset p*poff
-// elements); the two halves of the grid are walked like two Dhat passes
-template <class S, int NR, bool O32, bool SH>
+// elements); the two halves of the grid are walked like two Dhat passes.
+// The per-rhs array `shift` holds, with SH, a diagonal shift (out += shift[r]
+// psi) and, with CE, a factor on the even sites' clover term (out_e =
+// shift[r] A_e psi_e - 1/2 H psi_o: with shift[r] = 1 + dm the operator whose
+// Schur complement is Dhat + dm A_e)
+template <class S, int NR, bool O32, bool SH, bool CE = false>
 __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k_dw(Geo g, LinkV<S> U, CloverV<S> A, FieldV<S> in, FieldV<S> out,
                                             int64_t poff, int64_t spoff, int nrhs, int nrg, int order, int sb,
                                             const double* shift) {
@@ -214,6 +218,13 @@ __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k
         const T dl = (T)shift[r0 + q];
 #pragma unroll
         for (int k = 0; k < 12; ++k) o[k] = cacc(o[k], dl, s[k]);
+      }
+      if constexpr (CE) {
+        if (p == 0) {
+          const T f = (T)shift[r0 + q];
+#pragma unroll
+          for (int k = 0; k < 12; ++k) o[k] = {f * o[k].re, f * o[k].im};
+        }
       }
 #pragma unroll
       for (int k = 0; k < 12; ++k) o[k] = cacc(acc[q][k], sc, o[k]);
@@ -453,21 +464,25 @@ hipError_t launch_dhat(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S>
 
 template <class S, int NR>
 static hipError_t launch_dw_nr(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> out, int64_t poff,
-                               int64_t spoff, int nrhs, const LaunchCfg& c, hipStream_t st, const double* sh) {
+                               int64_t spoff, int nrhs, const LaunchCfg& c, hipStream_t st, const double* sh,
+                               const double* ce) {
   int sb = c.sb > 0 ? c.sb : c.block;
   int nrg = ceil_div(nrhs, NR * (c.block / sb));
   int tiles = 2 * ceil_div(g.Vh, sb);
   const dim3 grid(tiles * nrg), blk(c.block);
   const bool o32 = fits32(g, in, nrhs, poff, spoff) && fits32(g, out, nrhs, poff, spoff);
-#define DW(O, H) \
-  hipLaunchKernelGGL((k_dw<S, NR, O, H>), grid, blk, 0, st, g, op.U, op.A, in, out, poff, spoff, nrhs, nrg, c.xcd, sb, \
-                     sh)
-  if (o32) {
-    if (sh) DW(true, true);
-    else DW(true, false);
+#define DW(O, H, E, P) \
+  hipLaunchKernelGGL((k_dw<S, NR, O, H, E>), grid, blk, 0, st, g, op.U, op.A, in, out, poff, spoff, nrhs, nrg, c.xcd, \
+                     sb, P)
+  if (ce) {
+    if (o32) DW(true, false, true, ce);
+    else DW(false, false, true, ce);
+  } else if (o32) {
+    if (sh) DW(true, true, false, sh);
+    else DW(true, false, false, sh);
   } else {
-    if (sh) DW(false, true);
-    else DW(false, false);
+    if (sh) DW(false, true, false, sh);
+    else DW(false, false, false, sh);
   }
 #undef DW
   return hipGetLastError();
@@ -475,11 +490,12 @@ static hipError_t launch_dw_nr(const Geo& g, const DevOp<S>& op, FieldV<S> in, F
 
 template <class S>
 hipError_t launch_dw(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> out, int64_t poff, int64_t spoff,
-                     int nrhs, const LaunchCfg& c, hipStream_t st, const double* shift) {
+                     int nrhs, const LaunchCfg& c, hipStream_t st, const double* shift, const double* ce) {
+  if (shift && ce) return hipErrorInvalidValue;
   switch (c.nr) {
-    case 1: return launch_dw_nr<S, 1>(g, op, in, out, poff, spoff, nrhs, c, st, shift);
-    case 2: return launch_dw_nr<S, 2>(g, op, in, out, poff, spoff, nrhs, c, st, shift);
-    case 4: return launch_dw_nr<S, 4>(g, op, in, out, poff, spoff, nrhs, c, st, shift);
+    case 1: return launch_dw_nr<S, 1>(g, op, in, out, poff, spoff, nrhs, c, st, shift, ce);
+    case 2: return launch_dw_nr<S, 2>(g, op, in, out, poff, spoff, nrhs, c, st, shift, ce);
+    case 4: return launch_dw_nr<S, 4>(g, op, in, out, poff, spoff, nrhs, c, st, shift, ce);
     default: return hipErrorInvalidValue;
   }
 }
@@ -488,7 +504,7 @@ hipError_t launch_dw(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> o
   template hipError_t launch_dhat<S>(const Geo&, const DevOp<S>&, FieldV<S>, FieldV<S>, FieldV<S>, int,             \
                                      const LaunchCfg&, hipStream_t, int, hipEvent_t);                               \
   template hipError_t launch_dw<S>(const Geo&, const DevOp<S>&, FieldV<S>, FieldV<S>, int64_t, int64_t, int,        \
-                                   const LaunchCfg&, hipStream_t, const double*);
+                                   const LaunchCfg&, hipStream_t, const double*, const double*);
 INST(double)
 INST(float)
 INST(__half)

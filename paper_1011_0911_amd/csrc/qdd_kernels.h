@@ -43,9 +43,12 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st)
 // several masses in one launch: D(kappa_r) = D(kappa_0) + (1/(2 kappa_r) -
 // 1/(2 kappa_0)) because only the diagonal of the clover term depends on kappa
 constexpr int kMaxShift = 64;
+// ce (device, nrhs doubles, optional; not together with shift): per-rhs factor
+// on the even sites' clover term, D'(r) = D + (ce[r] - 1) A_e on the even sites
 template <class S>
 hipError_t launch_dw(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> out, int64_t poff, int64_t spoff,
-                     int nrhs, const LaunchCfg& c, hipStream_t st, const double* shift = nullptr);
+                     int nrhs, const LaunchCfg& c, hipStream_t st, const double* shift = nullptr,
+                     const double* ce = nullptr);
 
 // ---- packing / conversion (qdd_pack.hip)
 

@@ -8,6 +8,7 @@
 #include "qdd_api_internal.h"
 #include "qdd_solver.h"
 #include "qdd_net.h"
+#include "qdd_dfl_kernels.h"
 
 #include <chrono>
 #include <cmath>
@@ -315,38 +316,230 @@ extern "C" qdd_status qdd_solve(qdd_ctx* x, int nrhs, const double* eta_c, doubl
   return s;
 }
 
-// Q_S^{-1} phi = P_e Q^{-1} Q_ee P_e phi (Eq. 5) = [D^{-1} (A_e phi (+) 0)]_e: the
-// source A_e phi on the even sites and 0 on the odd ones goes straight into the
-// solver's packed source field, the configured solver (deflated SAP-GCR or
-// the plain method) solves D psi = eta, and the even half of psi is returned.
+// W(dm_r)^{-1} phi_r for nrhs even fields (Eq. 3; dm_r = 0 gives Q_S^{-1} phi_r,
+// Eq. 5).  W = Q_S + dm = A_e^{-1} (Dhat + dm A_e), and Dhat + dm A_e is the Schur
+// complement of D' = D with the even sites' clover term scaled by 1 + dm, so
+// W^{-1} phi = [D'^{-1} (A_e phi (+) 0)]_e: flexible GCR on D' (FP64) with the
+// configured preconditioner, which is built for D, and the even half of the
+// solution.  The residual that counts is that of W: phi - W x is formed with the
+// FP64 Dhat, the even-site inverse clover blocks and the shift, and where it is
+// above tol |phi| the same solve is run on it and the correction added (at most
+// two such passes).  Since the W residual is a few times the D' residual, the
+// first pass stops at tol / 5 and a correction pass only at the reduction its
+// residual still needs (with the same margin).  info[r]: iterations of all
+// passes, the W residual.
+static qdd_status solve_w_impl(qdd_ctx* x, int nrhs, const double* dm, const double* const* phi, double* const* out,
+                               qdd_solve_info* info) {
+  const Layout& lo = x->lo;
+  const Geo& G = x->G;
+  hipStream_t st = x->st;
+  const int64_t n = (int64_t)24 * G.Vh, ne = (int64_t)12 * G.Vh;
+  const double tol = x->cfg.tol;
+  double2 *eta = x->ptr<double2>(lo.eta), *psi = x->ptr<double2>(lo.psi);
+  double* ce = x->ptr<double>(lo.dw_ce);
+  // scratch: canonical residuals and one W image in the Krylov space (consumed
+  // before each solve overwrites it), one packed even field and its W image in
+  // t64 / res, canonical corrections in s_tmp
+  double2* resc = x->ptr<double2>(lo.chi);
+  double2* wxc = resc + (int64_t)nrhs * ne;
+  double2* xe = x->ptr<double2>(lo.t64);
+  double2* we = x->ptr<double2>(lo.res);
+  double2* corr = x->ptr<double2>(lo.s_tmp);
+  double2 *part = x->ptr<double2>(lo.part), *rn2 = x->ptr<double2>(lo.rn2);
+  const CloverV<double> A = x->op<double>().A, Ai = x->op<double>().Ainv;
+  std::vector<double> ceh(nrhs), pn(nrhs), rn(nrhs);
+  for (int r = 0; r < nrhs; ++r) ceh[r] = 1.0 + dm[r];
+  HCK(x, hipMemcpyAsync(ce, ceh.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+  std::vector<double2> h2(nrhs);
+  for (int r = 0; r < nrhs; ++r)
+    HCK(x, launch_dots<double2>((const double2*)phi[r], 0, ne, 1, (const double2*)phi[r], ne, ne, 1, part, rn2 + r, st));
+  HCK(x, hipMemcpyAsync(h2.data(), rn2, nrhs * sizeof(double2), hipMemcpyDeviceToHost, st));
+  HCK(x, hipStreamSynchronize(st));
+  for (int r = 0; r < nrhs; ++r) pn[r] = std::sqrt(h2[r].x);
+  std::vector<int> need(nrhs, 1), iters(nrhs, 0), restarts(nrhs, 0), fallbacks(nrhs, 0);
+  std::vector<qdd_solve_info> pi(nrhs);
+  double t_ms = 0.0, pass_tol = 0.2 * tol;
+  qdd_status solve_status = QDD_OK;
+  struct TolGuard {  // the outer solver reads its tolerance from the configuration
+    qdd_ctx* x;
+    double keep;
+    ~TolGuard() { x->cfg.tol = keep; }
+  } guard{x, x->cfg.tol};
+  for (int pass = 0; pass < 3; ++pass) {
+    x->cfg.tol = pass_tol;
+    // source: A_e rho_r on the even sites, 0 on the odd ones (rho = phi, then the
+    // W residual; zero for the right-hand sides that need no correction)
+    HCK(x, hipMemsetAsync(eta, 0, (size_t)nrhs * n * sizeof(double2), st));
+    PackedView pe = x->packed(QDD_F64, nrhs, 0, eta);
+    for (int r = 0; r < nrhs; ++r)
+      if (need[r]) {
+        FieldV<double> er = pe.f64;
+        er.p += r * er.rs;
+        HCK(x, launch_qs_source(G, pass == 0 ? phi[r] : (const double*)(resc + r * ne), er, A, 1, st));
+      }
+    FgcrOps F;
+    x->fallbacks.assign(nrhs, 0);
+    x->coarse_iters = 0;
+    qdd_status s0 = make_solver_ops(x, nrhs, F);
+    if (s0 != QDD_OK) return s0;
+    F.op = [x, nrhs, ce](const double2* in, double2* o) -> qdd_status {
+      HCK(x, x->dw(QDD_F64, nrhs, (void*)in, o, ce));
+      return QDD_OK;
+    };
+    F.fallbacks = x->fallbacks.data();
+    F.hv = nullptr;
+    qdd_status s = run_fgcr(x, F, eta, psi, pi.data());
+    if (s != QDD_OK && s != QDD_ENOCONV) return s;
+    if (s == QDD_ENOCONV) solve_status = s;
+    for (int r = 0; r < nrhs; ++r) {
+      iters[r] += pi[r].iters;
+      restarts[r] += pi[r].restarts;
+      fallbacks[r] += pi[r].fallbacks;
+    }
+    t_ms += pi[0].t_ms[0];
+    // the even half of the solution becomes (pass 0) or corrects the result
+    PackedView pp = x->packed(QDD_F64, nrhs, 0, psi);
+    for (int r = 0; r < nrhs; ++r) {
+      if (!need[r]) continue;
+      FieldV<double> v = pp.f64;
+      v.p += r * v.rs;
+      if (pass == 0) {
+        HCK(x, launch_unpack_spinor<double>(G, v, out[r], 1, 1, pp.poff, pp.spoff, st));
+      } else {
+        HCK(x, launch_unpack_spinor<double>(G, v, (double*)(corr + r * ne), 1, 1, pp.poff, pp.spoff, st));
+        HCK(x, launch_add<double2>((double2*)out[r], corr + r * ne, 1.0, ne, st));
+      }
+    }
+    // W residual phi - W(dm) x
+    PackedView px = x->packed(QDD_F64, 1, 1, xe), pw = x->packed(QDD_F64, 1, 1, we);
+    for (int r = 0; r < nrhs; ++r) {
+      HCK(x, launch_pack_spinor<double>(G, out[r], px.f64, 1, 1, px.poff, px.spoff, st));
+      HCK(x, x->dhat(QDD_F64, 1, xe, we));
+      HCK(x, launch_apply_w_finish(G, px.f64, pw.f64, Ai, 1, dm[r], st));
+      HCK(x, launch_unpack_spinor<double>(G, pw.f64, (double*)wxc, 1, 1, pw.poff, pw.spoff, st));
+      HCK(x, launch_sub(resc + r * ne, (const double2*)phi[r], wxc, ne, ne, 1, st));
+    }
+    HCK(x, launch_dots<double2>(resc, 0, ne, 1, resc, ne, ne, nrhs, part, rn2, st));
+    HCK(x, hipMemcpyAsync(h2.data(), rn2, nrhs * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HCK(x, hipStreamSynchronize(st));
+    bool any = false;
+    pass_tol = 0.5;
+    for (int r = 0; r < nrhs; ++r) {
+      rn[r] = std::sqrt(std::fabs(h2[r].x));
+      need[r] = !(rn[r] <= tol * pn[r]) && std::isfinite(h2[r].x);
+      any |= need[r] != 0;
+      if (need[r]) pass_tol = std::min(pass_tol, 0.2 * tol * pn[r] / rn[r]);
+    }
+    if (!any) break;
+  }
+  qdd_status status = QDD_OK;
+  for (int r = 0; r < nrhs; ++r) {
+    const bool conv = pn[r] > 0 ? rn[r] <= tol * pn[r] : true;
+    if (!conv) status = QDD_ENOCONV;
+    if (info) {
+      info[r] = pi[r];
+      info[r].iters = iters[r];
+      info[r].restarts = restarts[r];
+      info[r].fallbacks = fallbacks[r];
+      info[r].converged = conv;
+      info[r].true_res = pn[r] > 0 ? rn[r] / pn[r] : 0.0;
+      info[r].t_ms[0] = t_ms;
+    }
+  }
+  if (status != QDD_OK)
+    x->fail(solve_status != QDD_OK ? "no convergence within nmx iterations" : "W residual above tol after refinement");
+  return status;
+}
+
+static qdd_status solve_w_check(qdd_ctx* x, int nrhs, const char* name) {
+  if (!x->have_clover) { x->fail("%s before qdd_set_params", name); return QDD_ESTATE; }
+  if (x->cfg.precond == QDD_PRECOND_DFL && !x->have_dfl) {
+    x->fail("%s: deflated solve before qdd_dfl_build", name);
+    return QDD_ESTATE;
+  }
+  (void)nrhs;
+  return QDD_OK;
+}
+
+// Q_S^{-1} phi = P_e Q^{-1} Q_ee P_e phi (Eq. 5)
 extern "C" qdd_status qdd_solve_qs(qdd_ctx* x, int nrhs, const double* phi_c, double* out_c, qdd_solve_info* info) {
   if (!x || !phi_c || !out_c || nrhs < 1 || nrhs > x->cfg.max_nrhs) {
     if (x) x->fail("qdd_solve_qs: invalid arguments");
     return QDD_EINVAL;
   }
-  if (!x->have_clover) { x->fail("qdd_solve_qs before qdd_set_params"); return QDD_ESTATE; }
-  if (x->cfg.precond == QDD_PRECOND_DFL && !x->have_dfl) {
-    x->fail("deflated solve before qdd_dfl_build");
-    return QDD_ESTATE;
+  qdd_status s = solve_w_check(x, nrhs, "qdd_solve_qs");
+  if (s != QDD_OK) return s;
+  const int64_t ne = (int64_t)24 * x->G.Vh;  // doubles per canonical even field
+  std::vector<const double*> ph(nrhs);
+  std::vector<double*> o(nrhs);
+  std::vector<double> dm(nrhs, 0.0);
+  for (int r = 0; r < nrhs; ++r) {
+    ph[r] = phi_c + r * ne;
+    o[r] = out_c + r * ne;
   }
-  const Layout& lo = x->lo;
-  const int64_t n = (int64_t)24 * x->G.Vh;
-  double2 *eta = x->ptr<double2>(lo.eta), *psi = x->ptr<double2>(lo.psi);
-  PackedView pe = x->packed(QDD_F64, nrhs, 0, eta);
-  HCK(x, hipMemsetAsync(eta, 0, (size_t)nrhs * n * sizeof(double2), x->st));
-  HCK(x, launch_qs_source(x->G, phi_c, pe.f64, x->op<double>().A, nrhs, x->st));
-  FgcrOps F;
-  x->fallbacks.assign(nrhs, 0);
-  x->coarse_iters = 0;
-  qdd_status s0 = make_solver_ops(x, nrhs, F);
-  if (s0 != QDD_OK) return s0;
-  F.fallbacks = x->fallbacks.data();
-  F.hv = nullptr;
-  qdd_status s = run_fgcr(x, F, eta, psi, info);
-  PackedView pp = x->packed(QDD_F64, nrhs, 0, psi);
-  HCK(x, launch_unpack_spinor<double>(x->G, pp.f64, out_c, nrhs, 1, pp.poff, pp.spoff, x->st));
-  HCK(x, hipStreamSynchronize(x->st));
-  return s;
+  return solve_w_impl(x, nrhs, dm.data(), ph.data(), o.data(), info);
+}
+
+// W(dm)^{-1} phi (Eq. 3)
+extern "C" qdd_status qdd_solve_w(qdd_ctx* x, int nrhs, double dm, const double* phi_c, double* out_c,
+                                  qdd_solve_info* info) {
+  if (!x || !phi_c || !out_c || nrhs < 1 || nrhs > x->cfg.max_nrhs || !std::isfinite(dm) || dm < 0) {
+    if (x) x->fail("qdd_solve_w: invalid arguments");
+    return QDD_EINVAL;
+  }
+  qdd_status s = solve_w_check(x, nrhs, "qdd_solve_w");
+  if (s != QDD_OK) return s;
+  const int64_t ne = (int64_t)24 * x->G.Vh;
+  std::vector<const double*> ph(nrhs);
+  std::vector<double*> o(nrhs);
+  std::vector<double> dms(nrhs, dm);
+  for (int r = 0; r < nrhs; ++r) {
+    ph[r] = phi_c + r * ne;
+    o[r] = out_c + r * ne;
+  }
+  return solve_w_impl(x, nrhs, dms.data(), ph.data(), o.data(), info);
+}
+
+// S_eff of Eq. 4 with two pseudofermions: -2 (log det Q_ee + log det Q_oo)
+// + |W^{-1}(dm) phi1|^2 + |(1 + dm Q_S^{-1}) phi2|^2; the two solves run as one
+// batch of two right-hand sides (masses dm and 0)
+extern "C" qdd_status qdd_action(qdd_ctx* x, double dm, const double* phi1, const double* phi2, double* chi1,
+                                 double* chi2, double* s_eff, double* parts, qdd_solve_info* info) {
+  if (!x || !phi1 || !phi2 || !chi1 || !chi2 || !s_eff || !std::isfinite(dm) || dm < 0 || x->cfg.max_nrhs < 2 ||
+      chi1 == chi2) {
+    if (x) x->fail("qdd_action: invalid arguments (max_nrhs must be >= 2)");
+    return QDD_EINVAL;
+  }
+  qdd_status s = solve_w_check(x, 2, "qdd_action");
+  if (s != QDD_OK) return s;
+  double le = 0, lo_ = 0;
+  s = qdd_clover_logdet(x, &le, &lo_);
+  if (s != QDD_OK) return s;
+  const double dms[2] = {dm, 0.0};
+  const double* ph[2] = {phi1, phi2};
+  double* o[2] = {chi1, chi2};
+  s = solve_w_impl(x, 2, dms, ph, o, info);
+  if (s != QDD_OK) return s;
+  // |chi1|^2 and |phi2 + dm chi2|^2 (the sum formed in the correction scratch)
+  const int64_t ne = (int64_t)12 * x->G.Vh;
+  hipStream_t st = x->st;
+  double2* tmp = x->ptr<double2>(x->lo.s_tmp);
+  double2 *part = x->ptr<double2>(x->lo.part), *rn2 = x->ptr<double2>(x->lo.rn2);
+  HCK(x, hipMemcpyAsync(tmp, phi2, ne * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  HCK(x, launch_add<double2>(tmp, (const double2*)chi2, dm, ne, st));
+  HCK(x, launch_dots<double2>((const double2*)chi1, 0, ne, 1, (const double2*)chi1, ne, ne, 1, part, rn2, st));
+  HCK(x, launch_dots<double2>(tmp, 0, ne, 1, tmp, ne, ne, 1, part, rn2 + 1, st));
+  double2 h[2];
+  HCK(x, hipMemcpyAsync(h, rn2, sizeof(h), hipMemcpyDeviceToHost, st));
+  HCK(x, hipStreamSynchronize(st));
+  const double t0 = -2.0 * (le + lo_), t1 = h[0].x, t2 = h[1].x;
+  if (parts) {
+    parts[0] = t0;
+    parts[1] = t1;
+    parts[2] = t2;
+  }
+  *s_eff = t0 + t1 + t2;
+  return QDD_OK;
 }
 
 // Plain solve of one right-hand side that records a (residual, error) pair at

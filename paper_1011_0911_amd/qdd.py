@@ -98,6 +98,8 @@ SIGNATURES = {
     "qdd_solve_harvest": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _i, ctypes.POINTER(_i), _vp]),
     "qdd_solve_dhat": (_i, [_vp, _i, _vp, _vp, _vp]),
     "qdd_solve_qs": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "qdd_solve_w": (_i, [_vp, _i, _d, _vp, _vp, _vp]),
+    "qdd_action": (_i, [_vp, _d, _vp, _vp, _vp, _vp, ctypes.POINTER(_d), ctypes.POINTER(_d), _vp]),
     "qdd_set_launch": (_i, [_vp, _i, _i, _i, _i, _i, _i]),
     "qdd_get_launch": (_i, [_vp, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i),
                             ctypes.POINTER(_i)]),
@@ -346,6 +348,31 @@ class Context:
         if check:
             self._check(st)
         return out, [i.as_dict() for i in info], st
+
+    def solve_w(self, dm, phi_e, check=True):
+        """W(dm)^{-1} phi_e (Eq. 3) on canonical even fields; info carries the W residual."""
+        c = self._c128(phi_e)
+        nrhs = c.numel() // (self.Vh * 12)
+        out = torch.empty((nrhs, self.Vh, 4, 3), dtype=torch.complex128, device=self.device)
+        info = (SolveInfo * nrhs)()
+        st = lib().qdd_solve_w(self.h, nrhs, float(dm), _ptr(c), _ptr(out), info)
+        if check:
+            self._check(st)
+        return out, [i.as_dict() for i in info], st
+
+    def action(self, dm, phi1, phi2):
+        """S_eff of Eq. 4: returns (S, (log-det term, phi1 term, phi2 term), chi1 =
+        W^{-1}(dm) phi1, chi2 = Q_S^{-1} phi2, infos of the two solves)."""
+        p1, p2 = self._c128(phi1), self._c128(phi2)
+        assert p1.numel() == p2.numel() == self.Vh * 12
+        c1 = torch.empty((self.Vh, 4, 3), dtype=torch.complex128, device=self.device)
+        c2 = torch.empty_like(c1)
+        s = _d()
+        parts = (_d * 3)()
+        info = (SolveInfo * 2)()
+        self._check(lib().qdd_action(self.h, float(dm), _ptr(p1), _ptr(p2), _ptr(c1), _ptr(c2), ctypes.byref(s),
+                                     parts, info))
+        return s.value, tuple(parts), c1, c2, [i.as_dict() for i in info]
 
     def solve_dhat(self, eta_e, check=True):
         c = self._c128(eta_e)

@@ -113,6 +113,18 @@ def run_solve_workload(wid: int, plain_rhs: int = 1, log=print, U=None):
     out["qs_inverse"] = {"solve_s": time.time() - t0, "iters": [i["iters"] for i in qinfo],
                          "converged": all(i["converged"] for i in qinfo)}
     log(f"[w{wid}] Q_S inverse: {out['qs_inverse']}")
+    # the effective action of Eq. 4 with two pseudofermions at dm = 0.09 (the mass
+    # difference of the paper's runs): clover log determinants, W^{-1}(dm) phi1 and
+    # Q_S^{-1} phi2 as one batch of two solves through the same solver
+    if nrhs >= 2:
+        ph = S.gaussian_field_device(V // 2, 6100, 2)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        s_eff, parts, _, _, ainfo = ctx.action(0.09, ph[0], ph[1])
+        torch.cuda.synchronize()
+        out["action_eq4"] = {"dm": 0.09, "s_eff": s_eff, "parts": list(parts), "s": time.time() - t0,
+                             "iters": [i["iters"] for i in ainfo], "residuals": [i["true_res"] for i in ainfo]}
+        log(f"[w{wid}] action: {out['action_eq4']}")
     del ctx
     torch.cuda.empty_cache()
     if plain_rhs <= 0:
