@@ -430,3 +430,19 @@ def s_eff(L, U, kappa, csw, dm, phi1, phi2, tol=1e-12, bc=-1):
     t1 = float(np.vdot(chi1, chi1).real)
     t2 = float(np.vdot(_cc(phi2) + dm * chi2, _cc(phi2) + dm * chi2).real)
     return t0 + t1 + t2, (t0, t1, t2)
+
+
+# ----------------------------------------------------------- chronological inversion
+# Sect. 3: the solutions of earlier inversions predict the next one (the
+# chronological inversion method the paper cites).  Reading: the prediction is
+# the combination of the stored solutions with the smallest residual,
+# min_c |eta - D sum_i c_i psi_i|, a linear least-squares problem in the vectors
+# D psi_i.
+
+def chrono_guess(L, U, A, prev, eta, bc=-1):
+    """sum_i c_i prev_i minimising |eta - D sum_i c_i prev_i| (numpy least squares
+    on the columns D prev_i); prev: (k, V, 4, 3), eta: (V, 4, 3)."""
+    prev = _cc(prev)
+    M = np.stack([apply_D(L, U, A, p, bc).reshape(-1) for p in prev], 1)
+    c = np.linalg.lstsq(M, _cc(eta).reshape(-1), rcond=None)[0]
+    return np.tensordot(c, prev, 1)
