@@ -93,6 +93,16 @@ typedef struct {
                           FP32 accuracy; 2 or 1 round each transported activation to 16
                           or 8 significant bits (relative error <= 2^-16, 2^-8), fewer
                           matrix-core operations; training always uses 3 */
+  /* chronological inversion (Sect. 3): the solver keeps the last chrono_nv
+     solutions of every right-hand-side slot and starts each qdd_solve from their
+     least-squares combination (0 = off; at most 16 and at most nkv * max_nrhs) */
+  int chrono_nv;
+  /* deflation-subspace refresh: when a deflated qdd_solve needs more than
+     dfl_refresh_iters outer iterations (0 = never) the subspace is refreshed
+     after it, with dfl_refresh_nit rounds of SAP inverse iteration started from
+     the current basis (as qdd_dfl_refresh) */
+  int dfl_refresh_iters;
+  int dfl_refresh_nit;
 } qdd_config;
 
 typedef struct {
@@ -113,7 +123,8 @@ typedef struct qdd_ctx qdd_ctx;
 /* Fills *cfg with the defaults: max_nrhs 1, SAP 4^4 blocks, ncy 5, nmr 4, F32;
  * no deflation (Ns 0, blocks 4^4, nit 5, coarse tol 1e-6, nmx 2000);
  * nkv 16, nmx 2048, tol 1e-10, precond NONE; no network (3 layers 1-12-12-1,
- * 3 terms). */
+ * 3 terms); no chronological inversion; no automatic refresh (2 rounds when
+ * enabled). */
 void qdd_config_default(qdd_config* cfg);
 
 /* Workspace bytes needed for geometry + configuration; 0 if they are invalid. */
@@ -191,9 +202,33 @@ qdd_status qdd_dfl_share(qdd_ctx* dst, const qdd_ctx* src);
 qdd_status qdd_dfl_precond(qdd_ctx* ctx, int nrhs, const double* r, double* out);
 
 /* Solves D psi = eta (canonical full fields, nrhs right-hand sides, psi
- * overwritten) with FP64 flexible GCR and the configured preconditioner.
- * info: nrhs entries (host memory) or NULL.  QDD_ENOCONV if any rhs fails. */
+ * overwritten) with FP64 flexible GCR and the configured preconditioner (the
+ * locally deflated Schwarz-preconditioned GCR of Sect. 3-4 with precond DFL).
+ * With chrono_nv > 0 the solve starts from the chronological guess and stores
+ * its solutions; with dfl_refresh_iters > 0 a deflated solve that took more outer
+ * iterations refreshes the subspace afterwards.  info: nrhs entries (host
+ * memory) or NULL.  QDD_ENOCONV if any rhs fails. */
 qdd_status qdd_solve(qdd_ctx* ctx, int nrhs, const double* eta, double* psi, qdd_solve_info* info);
+/* As qdd_solve, but psi holds an initial guess on entry (warm start: the first
+ * residual is eta - D psi; a guess that already meets tol returns at once with
+ * 0 iterations). */
+qdd_status qdd_solve_guess(qdd_ctx* ctx, int nrhs, const double* eta, double* psi, qdd_solve_info* info);
+/* The chronological guess for eta from the stored solutions (what qdd_solve
+ * would start from), written to psi without solving; QDD_EINVAL with
+ * chrono_nv = 0.  psi = 0 for a rhs slot with no stored solution. */
+qdd_status qdd_chrono_guess(qdd_ctx* ctx, int nrhs, const double* eta, double* psi);
+/* Forgets the solutions stored for the chronological inversion (chrono_nv > 0;
+ * Sect. 3): the next qdd_solve starts from 0. */
+qdd_status qdd_chrono_reset(qdd_ctx* ctx);
+/* Refreshes the deflation subspace for the current operator (after qdd_set_gauge
+ * or qdd_set_params changed it): dfl_refresh_nit rounds of SAP inverse iteration
+ * started from the current basis, normalised after each round, then the block
+ * orthonormalisation and the little operator as in qdd_dfl_build (Sect. 4,
+ * Fig. 1: the subspace is updated along the trajectory).  QDD_ESTATE without a
+ * basis built or shared before. */
+qdd_status qdd_dfl_refresh(qdd_ctx* ctx);
+/* Numbers of subspace builds and refreshes (automatic ones included) of ctx. */
+qdd_status qdd_dfl_stats(const qdd_ctx* ctx, int* builds, int* refreshes);
 /* Solves nsys independent systems (lattices, masses and batch sizes may all
  * differ) concurrently: each context (with its own stream) runs its solve on a
  * host thread of its own, so the work of all systems is in flight at once and

@@ -81,6 +81,11 @@ static bool valid_cfg(const qdd_geom* g, const qdd_config* c, std::string* why) 
     }
   }
   if (c->precond == QDD_PRECOND_DFL && c->dfl_Ns == 0) { *why = "precond DFL needs dfl_Ns > 0"; return false; }
+  if (c->chrono_nv < 0 || c->chrono_nv > 16 || c->chrono_nv > c->nkv * c->max_nrhs) {
+    *why = "chrono_nv must be in 0..min(16, nkv * max_nrhs)";
+    return false;
+  }
+  if (c->dfl_refresh_iters < 0 || c->dfl_refresh_nit < 0) { *why = "invalid refresh parameters"; return false; }
   if (c->use_net) {
     if (c->net_nl < 1 || c->net_nl > 7 || c->net_ch[0] != 1 || c->net_ch[c->net_nl] != 1) {
       *why = "network: 1..7 layers, one input and one output channel";
@@ -203,6 +208,8 @@ void compute_layout(const qdd_geom* g, const qdd_config* c, Layout& Lo) {
     Lo.net_pairs_bytes = (size_t)2 * 8 * 24 * Vh * 8;
     Lo.net_pairs = B.take(Lo.net_pairs_bytes);
   }
+  // chronological inversion: the last chrono_nv solutions of every rhs slot (FP64 full fields)
+  Lo.chrono = c->chrono_nv > 0 ? B.take((size_t)c->chrono_nv * nr * 24 * Vh * 16) : 0;
   // reductions and small solver arrays
   Lo.part = B.take((size_t)kDotBlocks * kMaxKv * nr * 16 + 4096);
   Lo.coef = B.take((size_t)nr * kMaxKv * 16);
@@ -242,6 +249,9 @@ void qdd_config_default(qdd_config* c) {
   c->net_ch[2] = 12;
   c->net_ch[3] = 1;
   c->net_terms = 3;
+  c->chrono_nv = 0;
+  c->dfl_refresh_iters = 0;
+  c->dfl_refresh_nit = 2;
 }
 
 size_t qdd_workspace_bytes(const qdd_geom* g, const qdd_config* c) {
@@ -278,6 +288,8 @@ qdd_status qdd_create(const qdd_geom* g, const qdd_config* c, void* ws, size_t w
   }
   qdd_ctx* x = new qdd_ctx();
   x->device = dev;
+  x->chrono_count.assign(c->max_nrhs, 0);
+  x->chrono_head.assign(c->max_nrhs, 0);
   x->geom = *g;
   x->cfg = *c;
   x->lo = Lo;

@@ -27,7 +27,7 @@ struct Layout {
   size_t cpart, ccoef, crn2, calpha, cbinv, cactive;
   size_t net_nw, net_w, net_wb, net_wadj, net_wmx, net_wmxa, net_act, net_grad, net_adam, net_gpart, net_loss, net_tmp;
   size_t net_pairs, net_pairs_bytes, net_gpart_floats;
-  size_t part, coef, ahist, bhist, binv, chist, rn2, alpha, active, scal;
+  size_t part, coef, ahist, bhist, binv, chist, rn2, alpha, active, scal, chrono;
   size_t total;
 };
 
@@ -60,6 +60,9 @@ struct qdd_ctx {
   struct Harvest* harvest = nullptr;  // pair capture of the next solve (qdd_solve_harvest)
   qdd::LaunchCfg launch[2][3];
   int sap_variant[3] = {0, 0, 0};  // Schwarz kernel per storage precision (0 = default)
+  std::vector<int> chrono_count, chrono_head;  // stored solutions per rhs slot, next slot to write
+  int dfl_builds = 0, dfl_refreshes = 0;
+  bool have_basis = false;  // the workspace holds a deflation basis (kept across set_gauge / set_params)
   std::string err;
 
   template <class T>

@@ -110,13 +110,9 @@ static qdd_status coarse_gcr(qdd_ctx* x, int nrhs, const double2* f, double2* c,
 }
 
 // ------------------------------------------------------------------ build
-extern "C" qdd_status qdd_dfl_build(qdd_ctx* x, const double* init) {
-  if (!x || !init) {
-    if (x) x->fail("qdd_dfl_build: invalid arguments");
-    return QDD_EINVAL;
-  }
-  if (x->cfg.dfl_Ns <= 0) { x->fail("qdd_dfl_build: dfl_Ns is 0"); return QDD_EINVAL; }
-  if (!x->have_clover) { x->fail("qdd_dfl_build before qdd_set_params"); return QDD_ESTATE; }
+// nit rounds of SAP inverse iteration on the fields in W (normalised after each
+// round), block orthonormalisation and the little operator
+static qdd_status dfl_build_from_W(qdd_ctx* x, int nit) {
   const Layout& lo = x->lo;
   const Geo& G = x->G;
   hipStream_t st = x->st;
@@ -124,13 +120,11 @@ extern "C" qdd_status qdd_dfl_build(qdd_ctx* x, const double* init) {
   int Ns = x->cfg.dfl_Ns, nr = x->cfg.max_nrhs;
   int64_t vs = (int64_t)24 * G.Vh;
   double2* W = x->ptr<double2>(lo.dfl_W);
-  PackedView pw = x->packed(QDD_F64, Ns, 0, W);
-  HCK(x, launch_pack_spinor<double>(G, init, pw.f64, Ns, 0, pw.poff, pw.spoff, st));
   // SAP inverse iteration, nr fields at a time, each normalised after every round
   double2 *part = x->ptr<double2>(lo.part), *rn2 = x->ptr<double2>(lo.rn2);
   double *bn = x->ptr<double>(lo.bhist), *binv = x->ptr<double>(lo.binv);
   void* tmp = x->ptr<void>(lo.phi);
-  for (int it = 0; it < x->cfg.dfl_nit; ++it)
+  for (int it = 0; it < nit; ++it)
     for (int l0 = 0; l0 < Ns; l0 += nr) {
       int nb = std::min(nr, Ns - l0);
       double2* w = W + l0 * vs;
@@ -159,7 +153,48 @@ extern "C" qdd_status qdd_dfl_build(qdd_ctx* x, const double* init) {
   if (!dfl_fp64(x)) HCK(x, launch_convert(W, x->ptr<float2>(lo.dfl_W32), (int64_t)Ns * vs, st));
   HCK(x, hipStreamSynchronize(st));
   x->have_dfl = true;
-  (void)nr;
+  return QDD_OK;
+}
+
+extern "C" qdd_status qdd_dfl_build(qdd_ctx* x, const double* init) {
+  if (!x || !init) {
+    if (x) x->fail("qdd_dfl_build: invalid arguments");
+    return QDD_EINVAL;
+  }
+  if (x->cfg.dfl_Ns <= 0) { x->fail("qdd_dfl_build: dfl_Ns is 0"); return QDD_EINVAL; }
+  if (!x->have_clover) { x->fail("qdd_dfl_build before qdd_set_params"); return QDD_ESTATE; }
+  double2* W = x->ptr<double2>(x->lo.dfl_W);
+  PackedView pw = x->packed(QDD_F64, x->cfg.dfl_Ns, 0, W);
+  HCK(x, launch_pack_spinor<double>(x->G, init, pw.f64, x->cfg.dfl_Ns, 0, pw.poff, pw.spoff, x->st));
+  qdd_status s = dfl_build_from_W(x, x->cfg.dfl_nit);
+  if (s == QDD_OK) {
+    x->dfl_builds++;
+    x->have_basis = true;
+  }
+  return s;
+}
+
+// Refresh of the subspace for the current operator (after the gauge field or the
+// mass changed): dfl_refresh_nit rounds of SAP inverse iteration started from the
+// current basis, then orthonormalisation and little operator as in a build.
+qdd_status dfl_refresh_impl(qdd_ctx* x) {
+  qdd_status s = dfl_build_from_W(x, x->cfg.dfl_refresh_nit);
+  if (s == QDD_OK) x->dfl_refreshes++;
+  return s;
+}
+
+extern "C" qdd_status qdd_dfl_refresh(qdd_ctx* x) {
+  if (!x) return QDD_EINVAL;
+  if (x->cfg.dfl_Ns <= 0) { x->fail("qdd_dfl_refresh: dfl_Ns is 0"); return QDD_EINVAL; }
+  if (!x->have_clover) { x->fail("qdd_dfl_refresh before qdd_set_params"); return QDD_ESTATE; }
+  if (!x->have_basis) { x->fail("qdd_dfl_refresh before a subspace was built or shared"); return QDD_ESTATE; }
+  return dfl_refresh_impl(x);
+}
+
+extern "C" qdd_status qdd_dfl_stats(const qdd_ctx* x, int* builds, int* refreshes) {
+  if (!x) return QDD_EINVAL;
+  if (builds) *builds = x->dfl_builds;
+  if (refreshes) *refreshes = x->dfl_refreshes;
   return QDD_OK;
 }
 
@@ -340,5 +375,6 @@ extern "C" qdd_status qdd_dfl_share(qdd_ctx* dst, const qdd_ctx* src) {
   HCK(dst, hipGetLastError());
   HCK(dst, hipStreamSynchronize(dst->st));
   dst->have_dfl = true;
+  dst->have_basis = true;
   return QDD_OK;
 }

@@ -49,14 +49,29 @@ qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qd
   HCK(x, hipMemcpyAsync(h2.data(), rn2, nr * sizeof(double2), hipMemcpyDeviceToHost, st));
   HCK(x, hipStreamSynchronize(st));
   for (int i = 0; i < nr; ++i) etan[i] = std::sqrt(h2[i].x);
-  // psi = 0, r = eta
-  HCK(x, hipMemsetAsync(psi, 0, (size_t)nr * n * sizeof(double2), st));
-  HCK(x, hipMemcpyAsync(r, eta, (size_t)nr * n * sizeof(double2), hipMemcpyDeviceToDevice, st));
   std::vector<int> act(nr), conv(nr, 0), iters(nr, 0), restarts(nr, 0);
-  for (int i = 0; i < nr; ++i) {
-    rn[i] = etan[i];
-    conv[i] = !(etan[i] > 0);
-    act[i] = !conv[i];
+  if (F.warm) {
+    // psi holds the initial guess: r = eta - D psi
+    qdd_status s0 = F.op(psi, t);
+    if (s0 != QDD_OK) return s0;
+    HCK(x, launch_sub(r, eta, t, n, n, nr, st));
+    HCK(x, launch_dots<double2>(r, 0, n, 1, r, n, n, nr, part, rn2, st));
+    HCK(x, hipMemcpyAsync(h2.data(), rn2, nr * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HCK(x, hipStreamSynchronize(st));
+    for (int i = 0; i < nr; ++i) {
+      rn[i] = std::sqrt(std::fabs(h2[i].x));
+      conv[i] = !(etan[i] > 0) || rn[i] <= tol * etan[i];
+      act[i] = !conv[i];
+    }
+  } else {
+    // psi = 0, r = eta
+    HCK(x, hipMemsetAsync(psi, 0, (size_t)nr * n * sizeof(double2), st));
+    HCK(x, hipMemcpyAsync(r, eta, (size_t)nr * n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    for (int i = 0; i < nr; ++i) {
+      rn[i] = etan[i];
+      conv[i] = !(etan[i] > 0);
+      act[i] = !conv[i];
+    }
   }
   std::vector<double2> ah((size_t)kMaxKv * nr * kMaxKv), chh((size_t)kMaxKv * nr), al((size_t)nr * kMaxKv);
   std::vector<double> bh((size_t)kMaxKv * nr);
@@ -287,7 +302,137 @@ extern "C" qdd_status qdd_solve_dhat(qdd_ctx* x, int nrhs, const double* eta_e, 
   return s;
 }
 
-extern "C" qdd_status qdd_solve(qdd_ctx* x, int nrhs, const double* eta_c, double* psi_c, qdd_solve_info* info) {
+// ------------------------------------------------------------------ chronological inversion
+// The initial guess of a solve from the solutions of earlier ones (Sect. 3, the
+// chronological inversion method the paper uses for all inversions): for each
+// right-hand side with k stored solutions psi_j, the images z_j = D psi_j are
+// orthonormalised by Gram-Schmidt (two passes, FP64), z = q R, and the guess is
+// sum_j c_j psi_j with R c = q^dag eta, the combination with the smallest
+// residual |eta - D sum c_j psi_j|.  Images that are (numerically) dependent on
+// the earlier ones are dropped.  The images are formed in the Krylov space.
+static qdd_status chrono_guess(qdd_ctx* x, int nrhs, const double2* eta, double2* psi) {
+  const Layout& lo = x->lo;
+  hipStream_t st = x->st;
+  const int nv = x->cfg.chrono_nv;
+  const int64_t n = (int64_t)24 * x->G.Vh;
+  double2* hist = x->ptr<double2>(lo.chrono);
+  double2* z = x->ptr<double2>(lo.chi);
+  double2 *part = x->ptr<double2>(lo.part), *coef = x->ptr<double2>(lo.coef), *rn2 = x->ptr<double2>(lo.rn2);
+  HCK(x, hipMemsetAsync(psi, 0, (size_t)nrhs * n * sizeof(double2), st));
+  std::vector<double2> hc(kMaxKv);
+  for (int r = 0; r < nrhs; ++r) {
+    const int k = std::min(x->chrono_count[r], nv);
+    if (k == 0) continue;
+    const double2* ps = hist + (int64_t)r * nv * n;
+    HCK(x, x->dw(QDD_F64, k, (void*)ps, z));
+    std::vector<double> z0(k), R((size_t)k * k, 0.0);
+    std::vector<double2> Rc((size_t)k * k, double2{0.0, 0.0});
+    HCK(x, launch_dots<double2>(z, 0, n, 1, z, n, n, k, part, rn2, st));
+    HCK(x, hipMemcpyAsync(hc.data(), rn2, k * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HCK(x, hipStreamSynchronize(st));
+    for (int j = 0; j < k; ++j) z0[j] = std::sqrt(hc[j].x);
+    std::vector<int> keep(k, 1);
+    double* binv = x->ptr<double>(lo.binv);
+    for (int i = 0; i < k; ++i) {
+      double2* zi = z + (int64_t)i * n;
+      if (i > 0)
+        for (int pass = 0; pass < 2; ++pass) {
+          HCK(x, launch_dots<double2>(z, n, n, i, zi, n, n, 1, part, coef, st));
+          HCK(x, hipMemcpyAsync(hc.data(), coef, i * sizeof(double2), hipMemcpyDeviceToHost, st));
+          HCK(x, hipStreamSynchronize(st));
+          for (int j = 0; j < i; ++j) {
+            if (!keep[j]) hc[j] = double2{0.0, 0.0};
+            Rc[(size_t)j * k + i].x += hc[j].x;
+            Rc[(size_t)j * k + i].y += hc[j].y;
+          }
+          HCK(x, hipMemcpyAsync(coef, hc.data(), i * sizeof(double2), hipMemcpyHostToDevice, st));
+          HCK(x, launch_axpy_multi<double2>(zi, n, z, n, n, i, coef, i, -1.0, n, 1, nullptr, st));
+        }
+      HCK(x, launch_dots<double2>(zi, 0, n, 1, zi, n, n, 1, part, rn2, st));
+      HCK(x, hipMemcpyAsync(hc.data(), rn2, sizeof(double2), hipMemcpyDeviceToHost, st));
+      HCK(x, hipStreamSynchronize(st));
+      const double nrm = std::sqrt(std::fabs(hc[0].x));
+      if (!(nrm > 1e-10 * z0[i])) {  // dependent on the earlier images: drop it
+        keep[i] = 0;
+        HCK(x, hipMemsetAsync(zi, 0, n * sizeof(double2), st));
+        continue;
+      }
+      R[(size_t)i * k + i] = nrm;
+      const double inv = 1.0 / nrm;
+      HCK(x, hipMemcpyAsync(binv, &inv, sizeof(double), hipMemcpyHostToDevice, st));
+      HCK(x, launch_axpby(zi, n, zi, n, binv, nullptr, n, 1, nullptr, st));
+    }
+    // d = q^dag eta, back substitution R c = d over the kept columns
+    HCK(x, launch_dots<double2>(z, n, n, k, eta + (int64_t)r * n, n, n, 1, part, coef, st));
+    HCK(x, hipMemcpyAsync(hc.data(), coef, k * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HCK(x, hipStreamSynchronize(st));
+    std::vector<double2> c(k, double2{0.0, 0.0});
+    for (int i = k - 1; i >= 0; --i) {
+      if (!keep[i]) continue;
+      double sr = hc[i].x, si = hc[i].y;
+      for (int j = i + 1; j < k; ++j) {
+        if (!keep[j]) continue;
+        const double2 a = Rc[(size_t)i * k + j], b = c[j];
+        sr -= a.x * b.x - a.y * b.y;
+        si -= a.x * b.y + a.y * b.x;
+      }
+      c[i] = double2{sr / R[(size_t)i * k + i], si / R[(size_t)i * k + i]};
+    }
+    HCK(x, hipMemcpyAsync(coef, c.data(), k * sizeof(double2), hipMemcpyHostToDevice, st));
+    HCK(x, launch_axpy_multi<double2>(psi + (int64_t)r * n, n, ps, n, n, k, coef, k, 1.0, n, 1, nullptr, st));
+    HCK(x, hipStreamSynchronize(st));  // the host copies of c, R are reused by the next rhs
+  }
+  return QDD_OK;
+}
+
+// the solutions of this solve into the history of their rhs slots (ring buffer)
+static qdd_status chrono_store(qdd_ctx* x, int nrhs, const double2* psi, const qdd_solve_info* info) {
+  const int nv = x->cfg.chrono_nv;
+  const int64_t n = (int64_t)24 * x->G.Vh;
+  double2* hist = x->ptr<double2>(x->lo.chrono);
+  for (int r = 0; r < nrhs; ++r) {
+    if (info && !info[r].converged) continue;
+    int& h = x->chrono_head[r];
+    HCK(x, hipMemcpyAsync(hist + ((int64_t)r * nv + h) * n, psi + (int64_t)r * n, n * sizeof(double2),
+                          hipMemcpyDeviceToDevice, x->st));
+    h = (h + 1) % nv;
+    x->chrono_count[r] = std::min(x->chrono_count[r] + 1, nv);
+  }
+  return QDD_OK;
+}
+
+// the chronological guess itself (inspection): psi_c = sum_j c_j psi_j for the
+// source eta_c from the stored solutions, without solving
+extern "C" qdd_status qdd_chrono_guess(qdd_ctx* x, int nrhs, const double* eta_c, double* psi_c) {
+  if (!x || !eta_c || !psi_c || nrhs < 1 || nrhs > x->cfg.max_nrhs || x->cfg.chrono_nv < 1) {
+    if (x) x->fail("qdd_chrono_guess: invalid arguments (needs chrono_nv > 0)");
+    return QDD_EINVAL;
+  }
+  if (!x->have_clover) { x->fail("qdd_chrono_guess before qdd_set_params"); return QDD_ESTATE; }
+  double2 *eta = x->ptr<double2>(x->lo.eta), *psi = x->ptr<double2>(x->lo.psi);
+  PackedView pe = x->packed(QDD_F64, nrhs, 0, eta);
+  HCK(x, launch_pack_spinor<double>(x->G, eta_c, pe.f64, nrhs, 0, pe.poff, pe.spoff, x->st));
+  qdd_status s = chrono_guess(x, nrhs, eta, psi);
+  if (s != QDD_OK) return s;
+  PackedView pp = x->packed(QDD_F64, nrhs, 0, psi);
+  HCK(x, launch_unpack_spinor<double>(x->G, pp.f64, psi_c, nrhs, 0, pp.poff, pp.spoff, x->st));
+  HCK(x, hipStreamSynchronize(x->st));
+  return QDD_OK;
+}
+
+extern "C" qdd_status qdd_chrono_reset(qdd_ctx* x) {
+  if (!x) return QDD_EINVAL;
+  std::fill(x->chrono_count.begin(), x->chrono_count.end(), 0);
+  std::fill(x->chrono_head.begin(), x->chrono_head.end(), 0);
+  return QDD_OK;
+}
+
+qdd_status dfl_refresh_impl(qdd_ctx* x);
+
+// guess: 0 start from 0 (or the chronological guess when configured), 1 psi_c holds
+// the caller's initial guess
+static qdd_status solve_impl(qdd_ctx* x, int nrhs, const double* eta_c, double* psi_c, qdd_solve_info* info,
+                             int guess) {
   if (!x || !eta_c || !psi_c || nrhs < 1 || nrhs > x->cfg.max_nrhs) {
     if (x) x->fail("qdd_solve: invalid arguments");
     return QDD_EINVAL;
@@ -298,7 +443,6 @@ extern "C" qdd_status qdd_solve(qdd_ctx* x, int nrhs, const double* eta_c, doubl
     return QDD_ESTATE;
   }
   const Layout& lo = x->lo;
-  int64_t n = (int64_t)24 * x->G.Vh;
   double2 *eta = x->ptr<double2>(lo.eta), *psi = x->ptr<double2>(lo.psi);
   PackedView pe = x->packed(QDD_F64, nrhs, 0, eta);
   HCK(x, launch_pack_spinor<double>(x->G, eta_c, pe.f64, nrhs, 0, pe.poff, pe.spoff, x->st));
@@ -309,11 +453,47 @@ extern "C" qdd_status qdd_solve(qdd_ctx* x, int nrhs, const double* eta_c, doubl
   if (s0 != QDD_OK) return s0;
   F.fallbacks = x->fallbacks.data();
   F.hv = x->harvest;
-  qdd_status s = run_fgcr(x, F, eta, psi, info);
+  const bool chrono = x->cfg.chrono_nv > 0 && !x->harvest;
+  if (guess) {
+    PackedView pg = x->packed(QDD_F64, nrhs, 0, psi);
+    HCK(x, launch_pack_spinor<double>(x->G, psi_c, pg.f64, nrhs, 0, pg.poff, pg.spoff, x->st));
+    F.warm = true;
+  } else if (chrono) {
+    s0 = chrono_guess(x, nrhs, eta, psi);
+    if (s0 != QDD_OK) return s0;
+    F.warm = true;
+  }
+  std::vector<qdd_solve_info> own(nrhs);
+  qdd_solve_info* inf = info ? info : own.data();
+  qdd_status s = run_fgcr(x, F, eta, psi, inf);
   PackedView pp = x->packed(QDD_F64, nrhs, 0, psi);
   HCK(x, launch_unpack_spinor<double>(x->G, pp.f64, psi_c, nrhs, 0, pp.poff, pp.spoff, x->st));
+  if (chrono && (s == QDD_OK || s == QDD_ENOCONV)) {
+    qdd_status sc = chrono_store(x, nrhs, psi, inf);
+    if (sc != QDD_OK) return sc;
+  }
   HCK(x, hipStreamSynchronize(x->st));
+  // refresh the deflation subspace when this solve took too many iterations
+  if ((s == QDD_OK || s == QDD_ENOCONV) && x->cfg.precond == QDD_PRECOND_DFL && x->cfg.dfl_refresh_iters > 0 &&
+      !x->harvest) {
+    int mx = 0;
+    for (int r = 0; r < nrhs; ++r) mx = std::max(mx, inf[r].iters);
+    if (mx > x->cfg.dfl_refresh_iters) {
+      qdd_status sr = dfl_refresh_impl(x);
+      if (sr != QDD_OK) return sr;
+    }
+  }
   return s;
+}
+
+extern "C" qdd_status qdd_solve(qdd_ctx* x, int nrhs, const double* eta_c, double* psi_c, qdd_solve_info* info) {
+  return solve_impl(x, nrhs, eta_c, psi_c, info, 0);
+}
+
+// psi_c holds the initial guess on entry
+extern "C" qdd_status qdd_solve_guess(qdd_ctx* x, int nrhs, const double* eta_c, double* psi_c,
+                                      qdd_solve_info* info) {
+  return solve_impl(x, nrhs, eta_c, psi_c, info, 1);
 }
 
 // W(dm_r)^{-1} phi_r for nrhs even fields (Eq. 3; dm_r = 0 gives Q_S^{-1} phi_r,

@@ -19,6 +19,7 @@ struct FgcrOps {
   int nrhs = 1;
   bool phi32 = false;  // preconditioner output stored as float2 (else double2)
   bool sync_stages = false;
+  bool warm = false;  // psi holds an initial guess (else the solve starts from 0)
   std::function<qdd_status(const double2* in, double2* out)> op;  // FP64 operator, whole batch
   std::function<qdd_status(const double2* r, void* phi)> prec;    // phi = M(r), whole batch
   int* fallbacks = nullptr;  // per rhs (network stage)

@@ -44,6 +44,7 @@ class Config(ctypes.Structure):
         ("nkv", ctypes.c_int), ("nmx", ctypes.c_int), ("tol", ctypes.c_double), ("precond", ctypes.c_int),
         ("use_net", ctypes.c_int), ("net_nl", ctypes.c_int), ("net_ch", ctypes.c_int * 8),
         ("net_terms", ctypes.c_int),
+        ("chrono_nv", ctypes.c_int), ("dfl_refresh_iters", ctypes.c_int), ("dfl_refresh_nit", ctypes.c_int),
     ]
 
 
@@ -88,6 +89,11 @@ SIGNATURES = {
     "qdd_solve_multi": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(_i), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                              ctypes.POINTER(_vp)]),
     "qdd_solve": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "qdd_solve_guess": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "qdd_chrono_reset": (_i, [_vp]),
+    "qdd_chrono_guess": (_i, [_vp, _i, _vp, _vp]),
+    "qdd_dfl_refresh": (_i, [_vp]),
+    "qdd_dfl_stats": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "qdd_net_num_weights": (_i, [_vp, ctypes.POINTER(ctypes.c_int64)]),
     "qdd_net_set_weights": (_i, [_vp, _vp]),
     "qdd_net_get_weights": (_i, [_vp, _vp]),
@@ -337,6 +343,35 @@ class Context:
         if check:
             self._check(st)
         return out, [i.as_dict() for i in info], st
+
+    def solve_guess(self, eta, guess, check=True):
+        """Solve starting from the initial guess (canonical full fields)."""
+        c = self._c128(eta)
+        nrhs = c.numel() // (self.V * 12)
+        out = self._c128(guess).clone().reshape(nrhs, self.V, 4, 3)
+        info = (SolveInfo * nrhs)()
+        st = lib().qdd_solve_guess(self.h, nrhs, _ptr(c), _ptr(out), info)
+        if check:
+            self._check(st)
+        return out, [i.as_dict() for i in info], st
+
+    def chrono_guess(self, eta):
+        c = self._c128(eta)
+        nrhs = c.numel() // (self.V * 12)
+        out = torch.empty((nrhs, self.V, 4, 3), dtype=torch.complex128, device=self.device)
+        self._check(lib().qdd_chrono_guess(self.h, nrhs, _ptr(c), _ptr(out)))
+        return out
+
+    def chrono_reset(self):
+        self._check(lib().qdd_chrono_reset(self.h))
+
+    def dfl_refresh(self):
+        self._check(lib().qdd_dfl_refresh(self.h))
+
+    def dfl_stats(self):
+        b, r = ctypes.c_int(), ctypes.c_int()
+        self._check(lib().qdd_dfl_stats(self.h, ctypes.byref(b), ctypes.byref(r)))
+        return b.value, r.value
 
     def solve_qs(self, phi_e, check=True):
         """Q_S^{-1} phi_e (Eq. 5) on canonical even fields through the configured solver."""
