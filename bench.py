@@ -57,7 +57,7 @@ def bytes_per_site(prec: int, nrhs: int, compressed_links: bool = False):
 
 def compressed(launch) -> bool:
     """Whether a Dhat launch shape (block, nr, xcd, sb) reads compressed links."""
-    return launch[1] == 1 and bool(launch[2] & 16)
+    return (launch[1] == 1 or bool(launch[2] & 32)) and bool(launch[2] & 16)
 
 
 def measured_traffic(prec, nrhs, launch):

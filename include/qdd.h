@@ -352,7 +352,12 @@ qdd_status qdd_solve_harvest(qdd_ctx* ctx, int nrhs, const double* eta, double* 
  * kept from evicting the neighbour spinors from the L2; plus 16: compressed
  * links, of which only the first two rows are read (12 of 18 reals) and the
  * third is rebuilt as the conjugate cross product (an SU(3) identity; the time
- * boundary sign of the stored link is put back); sb sites per block
+ * boundary sign of the stored link is put back); for Dhat with nr = 2 or 4
+ * in FP32 (nr 2) or FP16 (nr 2, 4), plus 32: rhs-vector loads, a lane reads
+ * the nr right-hand sides of a spinor component (and their FP16 scales) as one
+ * word of at most 16 bytes, with the streaming and compression bits (4, 8, 16)
+ * as for nr = 1; it applies to interleaved batches whose size is a multiple of
+ * nr, other operands take the plain kernels; sb sites per block
  * (0 = block): the block/sb lane groups of a
  * block take further right-hand sides of the same sites.  QDD_EINVAL for shapes
  * outside these ranges. */

@@ -450,7 +450,8 @@ qdd_status qdd_set_launch(qdd_ctx* x, int kernel, qdd_prec prec, int block, int 
     return QDD_OK;
   }
   bool ok = x && kernel >= 0 && kernel <= 1 && prec >= QDD_F64 && prec <= QDD_F16 && block >= 64 && block <= 256 &&
-            (block & 63) == 0 && (nr == 0 || nr == 1 || nr == 2 || nr == 4) && xcd >= 0 && xcd <= (kernel == 0 && nr == 1 ? 31 : 3) &&
+            (block & 63) == 0 && (nr == 0 || nr == 1 || nr == 2 || nr == 4) && xcd >= 0 &&
+            (xcd <= (kernel == 0 && nr == 1 ? 31 : 3) || (kernel == 0 && xcd >= 32 && xcd <= 63 && dhat_vec_ok(prec, nr))) &&
             (sb == 0 || (sb >= 1 && sb <= block && block % sb == 0));
   // staged variant (nr = 0): Dhat only, and the tile's links + clover must fit the LDS budget
   if (ok && nr == 0) ok = kernel == 0 && staged_lds_bytes(prec, sb > 0 ? sb : block) <= kStagedLdsMax;

@@ -172,6 +172,205 @@ __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k
   }
 }
 
+// --------------------------------------------- rhs-vector variant of the passes
+// For batches in the interleaved layout (rhs stride one element) a lane takes
+// one site and V consecutive right-hand sides: each spinor component of the V
+// is one V*sizeof(E)-byte load (16 bytes for V = 4 in FP16), their FP16 scales
+// one more, and every link and clover element is loaded once per lane for all
+// V.  Lanes are (site, rhs group) with the group fastest, so each load of a
+// wavefront covers one contiguous run of memory.  The per-rhs arithmetic is
+// that of the kernels above, in the same order.  The host guarantees rhs
+// stride 1 (elements and scales), nrhs % V == 0, site strides and component
+// strides that are multiples of V, V*sizeof(E)-aligned bases and 32-bit offsets.
+template <class S, int V>
+struct alignas(V * sizeof(typename St<S>::E)) VecE {
+  typename St<S>::E e[V];
+};
+template <int V>
+struct alignas(4 * V) VecF {
+  float e[V];
+};
+
+template <class S, int V, bool NT>
+__device__ inline void ld_spinor_v(const FieldV<S>& f, uint32_t eo, uint32_t so, VecE<S, V> (&raw)[12],
+                                   typename St<S>::T (&sc)[V]) {
+  typedef VecE<S, V> W;
+  const uint32_t vo = eo * (uint32_t)sizeof(typename St<S>::E);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) raw[k] = ld_off<W, NT>(reinterpret_cast<const W*>(f.p + (int64_t)k * f.n), vo);
+  if constexpr (sizeof(S) == 2) {
+    VecF<V> w = ld_off<VecF<V>, NT>(reinterpret_cast<const VecF<V>*>(f.scale), so * 4u);
+#pragma unroll
+    for (int q = 0; q < V; ++q) sc[q] = w.e[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < V; ++q) sc[q] = typename St<S>::T(1);
+  }
+}
+
+template <class S, int V, bool NT>
+__device__ inline void st_spinor_v(const FieldV<S>& f, uint32_t eo, uint32_t so,
+                                   const cx<typename St<S>::T> (&o)[V][12]) {
+  typedef VecE<S, V> W;
+  const uint32_t vo = eo * (uint32_t)sizeof(typename St<S>::E);
+  W w[12];
+  if constexpr (sizeof(S) == 2) {
+    VecF<V> scs;
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      float m = 0.f;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(o[q][k].re), fabsf(o[q][k].im)));
+      const float sc = m > 0.f ? m : 1.f;
+      const float inv = 1.f / sc;
+      scs.e[q] = sc;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) w[k].e[q] = St<S>::to(cx<float>{o[q][k].re * inv, o[q][k].im * inv});
+    }
+    st_off<VecF<V>, NT>(reinterpret_cast<VecF<V>*>(f.scale), so * 4u, scs);
+  } else {
+#pragma unroll
+    for (int q = 0; q < V; ++q)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) w[k].e[q] = St<S>::to(o[q][k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) st_off<W, NT>(reinterpret_cast<W*>(f.p + (int64_t)k * f.n), vo, w[k]);
+}
+
+// one neighbour (direction MU, SG = +1 forward, -1 backward) for all V
+template <class S, int V, int MU, int SG, bool NTL, bool COMP>
+__device__ inline void hop_one_v(const Geo& g, const LinkV<S>& U, const FieldV<S>& in, int r0, int p, int i,
+                                 const int x[4], typename St<S>::T c0, cx<typename St<S>::T> (&acc)[V][12]) {
+  typedef typename St<S>::T T;
+  cx<T> u[9];
+  VecE<S, V> raw[12];
+  T sc[V];
+  const int j = nbr_idx(g, x, MU, SG);
+  const int par = SG > 0 ? p : 1 - p, li = SG > 0 ? i : j;
+  if constexpr (COMP) {
+    const bool edge = MU == 0 && x[0] == (SG > 0 ? g.L[0] - 1 : 0);
+    ld_link_u12<S, NTL>(U, par, MU, li, T(edge ? g.bc : 1), u);
+  } else {
+    ld_link_u<S, NTL>(U, par, MU, li, u);
+  }
+  ld_spinor_v<S, V, false>(in, (uint32_t)((int64_t)j * in.ss + r0), (uint32_t)((int64_t)j * in.sss + r0), raw, sc);
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    cx<T> s[12], h[6], gg[6];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) s[k] = St<S>::from_reg(raw[k].e[q]);
+    project<T, MU, SG>(s, h);
+    su3_mul_half<T, (SG < 0)>(u, h, gg);
+    reconstruct_add<T, MU, SG>(gg, acc[q], c0 * sc[q]);
+  }
+}
+
+template <class S, int V, bool NTL, bool COMP>
+__device__ inline void hop_all_v(const Geo& g, const LinkV<S>& U, const FieldV<S>& in, int r0, int p, int i,
+                                 const int x[4], typename St<S>::T c0, cx<typename St<S>::T> (&acc)[V][12]) {
+  hop_one_v<S, V, 0, +1, NTL, COMP>(g, U, in, r0, p, i, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_one_v<S, V, 0, -1, NTL, COMP>(g, U, in, r0, p, i, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_one_v<S, V, 1, +1, NTL, COMP>(g, U, in, r0, p, i, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_one_v<S, V, 1, -1, NTL, COMP>(g, U, in, r0, p, i, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_one_v<S, V, 2, +1, NTL, COMP>(g, U, in, r0, p, i, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_one_v<S, V, 2, -1, NTL, COMP>(g, U, in, r0, p, i, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_one_v<S, V, 3, +1, NTL, COMP>(g, U, in, r0, p, i, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_one_v<S, V, 3, -1, NTL, COMP>(g, U, in, r0, p, i, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// waves per SIMD the register budget is sized for
+template <int V>
+constexpr int vec_waves() { return V >= 4 ? 2 : 3; }
+
+// pass A: t_o = A_o^{-1} H_oe psi_e for V right-hand sides per lane
+template <class S, int V, int NTM>
+__global__ void __launch_bounds__(256, vec_waves<V>()) k_dhat_va(Geo g, LinkV<S> U, CloverV<S> Ai, FieldV<S> in_e,
+                                                                 FieldV<S> t_o, int nrhs, int nrg, int order, int sb) {
+  typedef typename St<S>::T T;
+  typedef typename St<S>::E E;
+  int tile, rg, i, r0;
+  map_block(g, blockIdx.x, gridDim.x, nrg, sb, order, tile, rg);
+  if (!lane_site<V>(g, tile, rg, sb, nrhs, 1, i, r0)) return;
+  int x[4];
+  site_coords(g, 1, i, x);
+  cx<T> acc[V][12];
+#pragma unroll
+  for (int q = 0; q < V; ++q)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[q][k] = {T(0), T(0)};
+  hop_all_v<S, V, (NTM & 1) != 0, (NTM & 4) != 0>(g, U, in_e, r0, 1, i, x, T(1), acc);
+  // acc <- A_o^{-1} acc, one 6x6 block at a time for all V
+  const E* b = Ai.p + (int64_t)36 * Ai.n;
+  const uint32_t vo = (uint32_t)i * (uint32_t)sizeof(E);
+#pragma unroll
+  for (int blk = 0; blk < 2; ++blk) {
+    cx<T> a[18];
+#pragma unroll
+    for (int k = 0; k < 18; ++k) a[k] = St<S>::from(ld_off<E, (NTM & 1) != 0>(b + (int64_t)(blk * 18 + k) * Ai.n, vo));
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      cx<T> y[6];
+      herm6_mul<T>(a, acc[q] + 6 * blk, y);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc[q][6 * blk + k] = y[k];
+    }
+  }
+  st_spinor_v<S, V, (NTM & 2) != 0>(t_o, (uint32_t)((int64_t)i * t_o.ss + r0), (uint32_t)((int64_t)i * t_o.sss + r0),
+                                    acc);
+}
+
+// pass B: out_e = A_e psi_e - 1/4 H_eo t_o for V right-hand sides per lane
+template <class S, int V, int NTM>
+__global__ void __launch_bounds__(256, vec_waves<V>()) k_dhat_vb(Geo g, LinkV<S> U, CloverV<S> A, FieldV<S> in_e,
+                                                                 FieldV<S> t_o, FieldV<S> out_e, int nrhs, int nrg,
+                                                                 int order, int sb) {
+  typedef typename St<S>::T T;
+  typedef typename St<S>::E E;
+  int tile, rg, i, r0;
+  map_block(g, blockIdx.x, gridDim.x, nrg, sb, order, tile, rg);
+  if (!lane_site<V>(g, tile, rg, sb, nrhs, 1, i, r0)) return;
+  int x[4];
+  site_coords(g, 0, i, x);
+  cx<T> acc[V][12];
+#pragma unroll
+  for (int q = 0; q < V; ++q)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[q][k] = {T(0), T(0)};
+  hop_all_v<S, V, (NTM & 1) != 0, (NTM & 4) != 0>(g, U, t_o, r0, 0, i, x, T(-0.25), acc);
+  VecE<S, V> raw[12];
+  T sc[V];
+  ld_spinor_v<S, V, (NTM & 2) != 0>(in_e, (uint32_t)((int64_t)i * in_e.ss + r0),
+                                    (uint32_t)((int64_t)i * in_e.sss + r0), raw, sc);
+  const E* b = A.p;
+  const uint32_t vo = (uint32_t)i * (uint32_t)sizeof(E);
+#pragma unroll
+  for (int blk = 0; blk < 2; ++blk) {
+    cx<T> a[18];
+#pragma unroll
+    for (int k = 0; k < 18; ++k) a[k] = St<S>::from(ld_off<E, (NTM & 1) != 0>(b + (int64_t)(blk * 18 + k) * A.n, vo));
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      cx<T> v[6], y[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v[k] = St<S>::from_reg(raw[6 * blk + k].e[q]);
+      herm6_mul<T>(a, v, y);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc[q][6 * blk + k] = cacc(acc[q][6 * blk + k], sc[q], y[k]);
+    }
+  }
+  st_spinor_v<S, V, (NTM & 2) != 0>(out_e, (uint32_t)((int64_t)i * out_e.ss + r0),
+                                    (uint32_t)((int64_t)i * out_e.sss + r0), acc);
+}
+
 // full D on both parities; in/out: full fields (parity p at offset p*poff
 // elements); the two halves of the grid are walked like two Dhat passes.
 // The per-rhs array `shift` holds, with SH, a diagonal shift (out += shift[r]
@@ -219,12 +418,10 @@ __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k
 #pragma unroll
         for (int k = 0; k < 12; ++k) o[k] = cacc(o[k], dl, s[k]);
       }
+      // the even clover factor rides on the spinor's scale (SH and CE never meet)
       if constexpr (CE) {
-        if (p == 0) {
-          const T f = (T)shift[r0 + q];
-#pragma unroll
-          for (int k = 0; k < 12; ++k) o[k] = {f * o[k].re, f * o[k].im};
-        }
+        const T f = (T)shift[r0 + q];
+        sc = p ? sc : sc * f;
       }
 #pragma unroll
       for (int k = 0; k < 12; ++k) o[k] = cacc(acc[q][k], sc, o[k]);
@@ -416,6 +613,42 @@ static hipError_t launch_dhat_staged(const Geo& g, const DevOp<S>& op, FieldV<S>
   return hipGetLastError();
 }
 
+// the rhs-vector kernels apply to an operand that keeps V consecutive right-hand
+// sides of a site in one aligned V*sizeof(E)-byte word (and their FP16 scales
+// in one 4V-byte word)
+template <class S, int V>
+static bool vec_ok(const FieldV<S>& f, int nrhs) {
+  constexpr size_t W = V * sizeof(typename St<S>::E);
+  bool ok = f.rs == 1 && f.ss % V == 0 && f.n % V == 0 && nrhs % V == 0 && ((uintptr_t)f.p % W) == 0;
+  if constexpr (sizeof(S) == 2) ok = ok && f.scale && f.srs == 1 && f.sss % V == 0 && ((uintptr_t)f.scale % (4 * V)) == 0;
+  return ok;
+}
+
+template <class S, int V>
+static hipError_t launch_dhat_vec(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> tmp, FieldV<S> out,
+                                  int nrhs, const LaunchCfg& c, hipStream_t st, int pass, hipEvent_t ev) {
+  int sb = c.sb > 0 ? c.sb : c.block;
+  int nrg = ceil_div(nrhs, V * (c.block / sb));
+  dim3 grid(ceil_div(g.Vh, sb) * nrg), blk(c.block);
+  const int ntm = (c.xcd >> 2) & 7, order = c.xcd & 3;
+#define QDD_VEC(KER, ...)                                                                  \
+  switch (ntm) {                                                                           \
+    case 0: hipLaunchKernelGGL((KER<S, V, 0>), grid, blk, 0, st, __VA_ARGS__); break;      \
+    case 1: hipLaunchKernelGGL((KER<S, V, 1>), grid, blk, 0, st, __VA_ARGS__); break;      \
+    case 2: hipLaunchKernelGGL((KER<S, V, 2>), grid, blk, 0, st, __VA_ARGS__); break;      \
+    case 3: hipLaunchKernelGGL((KER<S, V, 3>), grid, blk, 0, st, __VA_ARGS__); break;      \
+    case 4: hipLaunchKernelGGL((KER<S, V, 4>), grid, blk, 0, st, __VA_ARGS__); break;      \
+    case 5: hipLaunchKernelGGL((KER<S, V, 5>), grid, blk, 0, st, __VA_ARGS__); break;      \
+    case 6: hipLaunchKernelGGL((KER<S, V, 6>), grid, blk, 0, st, __VA_ARGS__); break;      \
+    default: hipLaunchKernelGGL((KER<S, V, 7>), grid, blk, 0, st, __VA_ARGS__); break;     \
+  }
+  if (pass & 1) QDD_VEC(k_dhat_va, g, op.U, op.Ainv, in, tmp, nrhs, nrg, order, sb)
+  if (ev) (void)hipEventRecord(ev, st);
+  if (pass & 2) QDD_VEC(k_dhat_vb, g, op.U, op.A, in, tmp, out, nrhs, nrg, order, sb)
+#undef QDD_VEC
+  return hipGetLastError();
+}
+
 template <class S, int NR>
 static hipError_t launch_dhat_nr(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> tmp, FieldV<S> out,
                                  int nrhs, const LaunchCfg& c, hipStream_t st, int pass, hipEvent_t ev) {
@@ -424,6 +657,10 @@ static hipError_t launch_dhat_nr(const Geo& g, const DevOp<S>& op, FieldV<S> in,
   int tiles = ceil_div(g.Vh, sb);
   dim3 grid(tiles * nrg), blk(c.block);
   const bool o32 = fits32(g, in, nrhs) && fits32(g, tmp, nrhs) && fits32(g, out, nrhs);
+  // rhs-vector loads (bit 5 of the walk field) where the operands allow them
+  if constexpr (NR > 1 && NR * sizeof(typename St<S>::E) <= 16)
+    if ((c.xcd & 32) && o32 && vec_ok<S, NR>(in, nrhs) && vec_ok<S, NR>(tmp, nrhs) && vec_ok<S, NR>(out, nrhs))
+      return launch_dhat_vec<S, NR>(g, op, in, tmp, out, nrhs, c, st, pass, ev);
   // streaming access to single-use data (bits 0, 1) and compressed links (bit 2)
   const int ntm = o32 && NR == 1 ? (c.xcd >> 2) & 7 : 0;
   const int order = c.xcd & 3;

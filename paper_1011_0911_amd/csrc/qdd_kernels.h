@@ -22,9 +22,15 @@ struct LaunchCfg {
                     // 3 XCD slabs of L1/8 x1 planes walked time slice by time slice; Dhat with nr 1:
                     // + 4 streaming loads of links and clover, + 8 streaming load of the
                     // site's own spinor and store of the output (data a pass touches once),
-                    // + 16 compressed links (two rows read, the third rebuilt)
+                    // + 16 compressed links (two rows read, the third rebuilt); Dhat with nr 2, 4:
+                    // + 32 a lane loads its nr right-hand sides of a component in one word
+                    // (interleaved batches; the streaming and compression bits then apply too)
   int sb = 0;       // sites per block (0 = block); block/sb lane groups take further rhs
 };
+
+// Dhat with the rhs-vector loads (walk field + 32): nr consecutive right-hand
+// sides of a site in one load of at most 16 bytes (FP32: nr 2; FP16: nr 2, 4)
+inline bool dhat_vec_ok(int prec, int nr) { return (prec == 1 && nr == 2) || (prec == 2 && (nr == 2 || nr == 4)); }
 
 // LDS bytes of the staged Dhat variant for a tile of sb sites (108 complex slots
 // per site: 8 links and the clover), and the budget it must stay within

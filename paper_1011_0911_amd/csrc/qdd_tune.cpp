@@ -80,6 +80,8 @@ extern "C" qdd_status qdd_autotune(qdd_ctx* x, int kernel, qdd_prec prec, int nr
           if (kernel == 0 && nr == 1)  // streaming access: links + clover (4), own spinor + output (8);
                                        // compressed links (16)
             for (int ntm : {4, 8, 12, 16, 20, 24, 28}) cand.push_back(LaunchCfg{block, nr, xcd | ntm, sb == block ? 0 : sb});
+          if (kernel == 0 && nr > 1 && dhat_vec_ok(prec, nr) && nrhs % nr == 0)  // rhs-vector loads
+            for (int ntm : {0, 8, 16, 24}) cand.push_back(LaunchCfg{block, nr, xcd | 32 | ntm, sb == block ? 0 : sb});
         }
       }
       // staged variant (Dhat): R = block / sb lanes per site loop over the right-hand sides

@@ -18,7 +18,7 @@ F64, F32, F16 = 0, 1, 2
 PRECOND_NONE, PRECOND_SAP, PRECOND_DFL = 0, 1, 2
 KERNEL_DHAT, KERNEL_DW, KERNEL_SAP = 0, 1, 2
 # candidate set of the autotuner (cached choices of an older set are re-measured)
-TUNER_VERSION = "t4"
+TUNER_VERSION = "t5"
 
 QDD_OK, QDD_EINVAL, QDD_ESTATE, QDD_ESINGULAR, QDD_ENOCONV, QDD_EHIP, QDD_ENOWS = 0, -1, -2, -3, -4, -5, -6
 _NAMES = {0: "QDD_OK", -1: "QDD_EINVAL", -2: "QDD_ESTATE", -3: "QDD_ESINGULAR", -4: "QDD_ENOCONV",

@@ -120,6 +120,39 @@ def test_compressed_links_parity(Q, orc):
         ctx.set_launch(0, prec, 256, 1, 1, 0)
 
 
+@pytest.mark.parametrize("nrhs", [4, 8, 6])
+def test_rhs_vector_variant(Q, orc, nrhs):
+    # walk field + 32: a lane loads nr consecutive right-hand sides of a component
+    # in one word (FP32 nr 2; FP16 nr 2, 4).  Against the oracle, and equal bit
+    # for bit to the one-rhs-per-lane kernels (same per-rhs arithmetic and order);
+    # 6 rhs with nr 4 leaves the vector condition unmet and takes the plain path.
+    # Ragged lattice (192 even sites) so the last tile is partly empty.
+    L = (6, 4, 4, 4)
+    V = int(np.prod(L))
+    ctx, U = make_ctx(Q, L, 0.6, 0.1357, 1.9, 308, max_nrhs=nrhs)
+    A, Ai = orc.clover(L, U, 0.1357, 1.9)
+    pe = S.gaussian_field(V // 2, 13, nrhs=nrhs)
+    ref = np.stack([orc.apply_Dhat(L, U, A, Ai, pe[r]) for r in range(nrhs)])
+    for prec, nrs in ((1, (2,)), (2, (2, 4))):
+        for nr in nrs:
+            for block, xcd, sb in ((256, 32 + 1, 0), (128, 32 + 3 + 8, 32), (256, 32 + 2 + 16, 64), (64, 32 + 24, 16)):
+                if (block // (sb or block)) * nr > 2 * nrhs:
+                    continue
+                # the one-rhs-per-lane kernel with the same link storage and access bits
+                ctx.set_launch(0, prec, 256, 1, xcd - 32, 0)
+                scalar = to_np(ctx.apply_dhat(pe, prec))
+                ctx.set_launch(0, prec, block, nr, xcd, sb)
+                out = to_np(ctx.apply_dhat(pe, prec))
+                e = relerr(out, ref)
+                assert e < TOL[prec], (prec, nr, block, xcd, sb, e)
+                assert np.array_equal(out, scalar), (prec, nr, block, xcd, sb, relerr(out, scalar))
+        ctx.set_launch(0, prec, 256, 1, 1, 0)
+    with pytest.raises(Q.QddError):  # no rhs-vector loads in FP64 (a 16-byte element already)
+        ctx.set_launch(0, 0, 256, 2, 33, 0)
+    with pytest.raises(Q.QddError):  # nor for 4 FP32 right-hand sides (32 bytes)
+        ctx.set_launch(0, 1, 256, 4, 33, 0)
+
+
 def test_staged_variant_parity_and_limits(Q, orc):
     # the staged Dhat against the oracle in every precision on a ragged lattice
     # (192 even sites: not a multiple of the 64- or 128-site tiles)
