@@ -69,6 +69,10 @@ def lib():
             "orc_fgcr": (ctypes.c_int, [_i, ctypes.c_int, _d, _d, _d, ctypes.c_int, ctypes.c_int, _i, ctypes.c_int,
                                         ctypes.c_int, _vp, ctypes.c_double, ctypes.c_int, _i, _d, _d, _d,
                                         ctypes.c_int, ctypes.c_int, ctypes.c_double, _i, _d, _d, ctypes.c_int, _i]),
+            "orc_clover_force": (None, [_i, ctypes.c_int, _d, ctypes.c_double, _d, _d]),
+            "orc_hop_force": (None, [_i, ctypes.c_int, _d, _d, _d, ctypes.c_double, _d]),
+            "orc_hop_adj": (None, [_i, ctypes.c_int, _d, _d, _d]),
+            "orc_force_components": (None, [ctypes.c_int64, _d, ctypes.POINTER(ctypes.c_double)]),
             "orc_net_layer_forward": (None, [_i, ctypes.c_int, _d, ctypes.c_int, ctypes.c_int, _d, _d, _d]),
             "orc_net_layer_backward": (None, [_i, ctypes.c_int, _d, ctypes.c_int, ctypes.c_int, _d, _d, _d, _d, _d]),
             "orc_net_forward": (None, [_i, ctypes.c_int, _d, ctypes.c_int, _i, _d, _d, _d]),
@@ -430,6 +434,131 @@ def s_eff(L, U, kappa, csw, dm, phi1, phi2, tol=1e-12, bc=-1):
     t1 = float(np.vdot(chi1, chi1).real)
     t2 = float(np.vdot(_cc(phi2) + dm * chi2, _cc(phi2) + dm * chi2).real)
     return t0 + t1 + t2, (t0, t1, t2)
+
+
+def solve_W_adj(L, U, A, dm, v, tol=1e-12, bc=-1):
+    """chi with W(dm)^dag chi = v for even fields v (..., V/2, 4, 3): the conjugate
+    transpose of the dense W of solve_W, by LU, up to 1536 rows; larger systems
+    use GMRES on W^dag x = gamma5 A_e W(gamma5 A_e^{-1} x), which is the adjoint
+    because Dhat + dm A_e = A_e W is gamma5-Hermitian and A_e commutes with gamma5."""
+    v = _cc(v)
+    lead = v.shape[:-3]
+    p2 = v.reshape((-1,) + v.shape[-3:])
+    n = p2[0].size
+    out = np.empty_like(p2)
+    if n <= 1536:
+        eye = np.eye(n, dtype=np.complex128).reshape((n,) + p2.shape[1:])
+        Wd = apply_W(L, U, A, dm, eye, bc).reshape(n, n).T
+        for r in range(p2.shape[0]):
+            out[r] = np.linalg.solve(Wd.conj().T, p2[r].reshape(-1)).reshape(p2.shape[1:])
+    else:
+        from scipy.sparse.linalg import LinearOperator, gmres
+
+        ev, _ = _sites(L)
+        g5 = gamma5_12()
+        Ae = A[ev]
+        Aei = np.linalg.inv(Ae)
+
+        def adj(x):
+            t = (Aei @ x.reshape(-1, 12)[..., None])[..., 0] @ g5.T
+            w = apply_W(L, U, A, dm, t.reshape(p2.shape[1:]), bc).reshape(-1, 12)
+            return ((Ae @ w[..., None])[..., 0] @ g5.T).reshape(-1)
+
+        op = LinearOperator((n, n), dtype=np.complex128, matvec=adj)
+        for r in range(p2.shape[0]):
+            x, info = gmres(op, p2[r].reshape(-1), rtol=tol, atol=0.0, restart=200, maxiter=50)
+            if info != 0:
+                raise ArithmeticError(f"GMRES on W^dag did not reach {tol}")
+            out[r] = x.reshape(p2.shape[1:])
+    return out.reshape(lead + v.shape[-3:])
+
+
+# ----------------------------------------------------------- forces
+# Sect. 2: the molecular-dynamics evolution of the mass-preconditioned HMC moves
+# the links with the derivatives of the effective action of Eq. 4.  A link is
+# varied as U_mu(x) -> exp(eps w) U_mu(x), w traceless anti-Hermitian; the force
+# component f^a is the derivative of S_eff along the generator T^a = i lambda^a/2.
+#
+# With D = A - H/2 (H the hopping sum), Dhat_s = Dhat + s A_e and W = A_e^{-1} Dhat_s:
+#   S_1 = |W^{-1} phi1|^2, psi = W^{-1} phi1, X = Dhat_s^{-dag} psi (s = dm):
+#     dS_1 = -2 Re[X^dag dDhat_s psi - X^dag dA_e phi1]
+#   S_2 = |(1 + dm Q_S^{-1}) phi2|^2, xi = Q_S^{-1} phi2, v = phi2 + dm xi,
+#     X = Dhat^{-dag} v: dS_2 = -2 dm Re[X^dag dDhat xi - X^dag dA_e phi2]
+#   dDhat_s = (1+s) dA_e - 1/4 d(H_eo A_o^{-1} H_oe), so with Y_o = A_o^{-1} H_oe Y and
+#   X_o = A_o^{-1} H_eo^dag X, a term -2c Re[X^dag dDhat_s Y - X^dag dA_e phi] is
+#     -2c Re[X^dag dA_e ((1+s) Y - phi)] - c/2 Re[X_o^dag dA_o Y_o]
+#     + c/2 Re[X^dag dH_eo Y_o] + c/2 Re[X_o^dag dH_oe Y]
+#   S_det = -2 sum_x log det A(x): dS_det = Re sum_x tr(-2 A(x)^{-1} dA(x)).
+
+def clover_force(L, U, csw, K, bc=-1):
+    """Per-link matrices M (V, 4, 3, 3) of the quantity sum_x Re tr(K(x) A(x)),
+    K (V, 12, 12) a weight per site."""
+    U = _cc(U)
+    M = np.zeros((U.shape[0], 4, 3, 3), np.complex128)
+    lib().orc_clover_force(_ivec(L), bc, _c(U), float(csw), _c(_cc(K)), _c(M))
+    return M
+
+
+def hop_force(L, U, X, Y, coef, M, bc=-1):
+    """Adds to M the per-link matrices of coef Re sum_x X(x)^dag (H Y)(x) (full fields)."""
+    lib().orc_hop_force(_ivec(L), bc, _c(_cc(U)), _c(_cc(X)), _c(_cc(Y)), float(coef), _c(M))
+
+
+def hop_adj(L, U, X, bc=-1):
+    """H^dag X for a full field X (V, 4, 3)."""
+    X = _cc(X)
+    out = np.zeros_like(X)
+    lib().orc_hop_adj(_ivec(L), bc, _c(_cc(U)), _c(X), _c(out))
+    return out
+
+
+def force_components(M):
+    """f^a = Re tr(T^a M), T^a = i lambda^a / 2, for per-link matrices M (..., 3, 3)."""
+    M = _cc(M)
+    n = M.size // 9
+    f = np.zeros(M.shape[:-2] + (8,), np.float64)
+    lib().orc_force_components(n, _c(M), f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return f
+
+
+def force(L, U, kappa, csw, dm, phi1, phi2, parts=7, tol=1e-12, bc=-1):
+    """Force components f (V, 4, 8) of S_eff (Eq. 4, the terms of s_eff):
+    bit 0 of parts the log-det term, bit 1 the phi1 term, bit 2 the phi2 term."""
+    U = _cc(U)
+    V = U.shape[0]
+    A, Ai = clover(L, U, kappa, csw, bc)
+    ev, od = _sites(L)
+    K = np.zeros((V, 12, 12), np.complex128)
+    M = np.zeros((V, 4, 3, 3), np.complex128)
+    if parts & 1:
+        K += -2.0 * Ai
+    terms = []
+    if parts & 2:
+        psi = solve_W(L, U, A, dm, phi1, tol, bc)
+        terms.append((1.0, dm, psi, _cc(phi1), psi))
+    if parts & 4 and dm != 0:
+        xi = solve_W(L, U, A, 0.0, phi2, tol, bc)
+        terms.append((dm, 0.0, xi, _cc(phi2), _cc(phi2) + dm * xi))
+    for c, s, Y, phi, w in terms:
+        # X = Dhat_s^{-dag} w = A_e^{-1} W(s)^{-dag} w
+        Xe = (Ai[ev] @ solve_W_adj(L, U, A, s, w, tol, bc).reshape(-1, 12)[..., None])[..., 0]
+        Xf = np.zeros((V, 12), np.complex128)
+        Yf = np.zeros((V, 12), np.complex128)
+        Xf[ev], Yf[ev] = Xe, Y.reshape(-1, 12)
+        # (H Y)_o = -2 (D Y)_o for Y supported on the even sites
+        HY = -2.0 * apply_D(L, U, A, Yf.reshape(V, 4, 3), bc).reshape(V, 12)
+        Yo = np.zeros((V, 12), np.complex128)
+        Yo[od] = (Ai[od] @ HY[od][..., None])[..., 0]
+        HX = hop_adj(L, U, Xf.reshape(V, 4, 3), bc).reshape(V, 12)
+        Xo = np.zeros((V, 12), np.complex128)
+        Xo[od] = (Ai[od] @ HX[od][..., None])[..., 0]
+        Yt = (1.0 + s) * Y.reshape(-1, 12) - phi.reshape(-1, 12)
+        K[ev] += -2.0 * c * Yt[:, :, None] * Xe.conj()[:, None, :]
+        K[od] += -0.5 * c * Yo[od][:, :, None] * Xo[od].conj()[:, None, :]
+        hop_force(L, U, Xf.reshape(V, 4, 3), Yo.reshape(V, 4, 3), 0.5 * c, M, bc)
+        hop_force(L, U, Xo.reshape(V, 4, 3), Yf.reshape(V, 4, 3), 0.5 * c, M, bc)
+    M += clover_force(L, U, csw, K, bc)
+    return force_components(M)
 
 
 # ----------------------------------------------------------- chronological inversion

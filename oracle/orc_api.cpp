@@ -38,6 +38,23 @@ void orc_field_strength(const int* L, int bc, const double* U, int64_t x, int mu
   field_strength(g, CC(U), x, mu, nu, C(F));
 }
 
+void orc_clover_force(const int* L, int bc, const double* U, double csw, const double* K, double* M) {
+  Geom g(L, bc);
+  clover_force(g, CC(U), csw, CC(K), C(M));
+}
+
+void orc_hop_force(const int* L, int bc, const double* U, const double* X, const double* Y, double coef, double* M) {
+  Geom g(L, bc);
+  hop_force(g, CC(U), CC(X), CC(Y), coef, C(M));
+}
+
+void orc_hop_adj(const int* L, int bc, const double* U, const double* X, double* out) {
+  Geom g(L, bc);
+  hop_adj(g, CC(U), CC(X), C(out));
+}
+
+void orc_force_components(int64_t nlinks, const double* M, double* f) { force_components(nlinks, CC(M), f); }
+
 void orc_gamma(double* out /* 5 x 4 x 4 complex */) {
   const Gamma& G = gammas();
   std::memcpy(out, G.g, sizeof(G.g));

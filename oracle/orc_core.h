@@ -97,6 +97,18 @@ void apply_clover_site(const cplx* A12x12, const cplx* in12, cplx* out12);
 void apply_Dhat(const Geom& g, const cplx* U, const cplx* A, const cplx* Ainv, const cplx* pe, cplx* oe);
 void lex_of_parity(const Geom& g, int p, std::vector<int64_t>& out);
 
+// ---- link derivatives (orc_force.cpp) ----
+// Each adds to M (per link, [(lex*4+mu)*9]) the 3x3 matrix whose Re tr(w M) is
+// the first-order change of its quantity under U_mu(x) -> exp(eps w) U_mu(x).
+// clover_force: quantity sum_x Re tr(K(x) A(x)), K a 12x12 weight per site.
+void clover_force(const Geom& g, const cplx* U, double csw, const cplx* K, cplx* M);
+// hop_force: quantity coef Re sum_x X(x)^dag (H Y)(x) (H the hopping sum of hop_site).
+void hop_force(const Geom& g, const cplx* U, const cplx* X, const cplx* Y, double coef, cplx* M);
+// out = H^dag X (full fields)
+void hop_adj(const Geom& g, const cplx* U, const cplx* X, cplx* out);
+// f[l*8+a] = Re tr(T^a M_l), T^a = i lambda^a / 2
+void force_components(int64_t nlinks, const cplx* M, double* f);
+
 // ---- vector helpers ----
 cplx dot(const cplx* a, const cplx* b, int64_t n);  // sum conj(a) b
 double norm2(const cplx* a, int64_t n);
