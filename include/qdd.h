@@ -103,6 +103,9 @@ typedef struct {
      the current basis (as qdd_dfl_refresh) */
   int dfl_refresh_iters;
   int dfl_refresh_nit;
+  /* 1: the workspace also holds the buffers of qdd_force (4 FP64 fields, the
+     per-plane clover insertions and 2 even fields: 1392 bytes per site) */
+  int force;
 } qdd_config;
 
 typedef struct {
@@ -287,6 +290,24 @@ qdd_status qdd_solve_w(qdd_ctx* ctx, int nrhs, double dm, const double* phi_e, d
  * qdd_clover_logdet and qdd_solve_w. */
 qdd_status qdd_action(qdd_ctx* ctx, double dm, const double* phi1, const double* phi2, double* chi1, double* chi2,
                       double* s_eff, double* parts, qdd_solve_info* info);
+/* Forces of the effective action of Eq. 4 (the molecular-dynamics forces of
+ * Sect. 2): the derivative of S_eff (as qdd_action, same phi1, phi2, dm) with
+ * respect to every link, U_mu(x) -> exp(eps T^a) U_mu(x), along the eight
+ * generators T^a = i lambda^a / 2 (Gell-Mann lambda^a).  terms selects the parts
+ * of S_eff: bit 0 the log-det term (the clover-term force), bit 1 the phi1 term,
+ * bit 2 the phi2 term (nothing for dm = 0).  The pseudofermion terms take two
+ * batched solves of two right-hand sides with the configured solver: psi =
+ * W(dm)^{-1} phi1 and xi = Q_S^{-1} phi2, then X = (Dhat + s A_e)^{-dag} w for
+ * (s, w) = (dm, psi) and (0, phi2 + dm xi) through gamma5-hermiticity
+ * (X = gamma5 W(s)^{-1} A_e^{-1} gamma5 w); the hopping and clover parts of the
+ * derivative follow from these fields and their odd-site images.  force (device,
+ * FP64): [V][4][8] in lexicographic site order, f^a of U_mu(x) at
+ * (lex * 4 + mu) * 8 + a, overwritten.  info: 4 entries (psi, xi, X_1, X_2) or
+ * NULL.  QDD_EINVAL for dm < 0, terms outside 1..7, a context created without
+ * config.force or with max_nrhs < 2; QDD_ESTATE before qdd_set_params; solver
+ * errors as for qdd_solve_w. */
+qdd_status qdd_force(qdd_ctx* ctx, double dm, const double* phi1, const double* phi2, int terms, double* force,
+                     qdd_solve_info* info);
 
 /* ---- learned preconditioner stage (configuration use_net = 1) ----
  * A gauge-covariant parallel-transport convolution network N with net_nl

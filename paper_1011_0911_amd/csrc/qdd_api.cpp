@@ -86,6 +86,7 @@ static bool valid_cfg(const qdd_geom* g, const qdd_config* c, std::string* why) 
     return false;
   }
   if (c->dfl_refresh_iters < 0 || c->dfl_refresh_nit < 0) { *why = "invalid refresh parameters"; return false; }
+  if (c->force != 0 && c->force != 1) { *why = "force must be 0 or 1"; return false; }
   if (c->use_net) {
     if (c->net_nl < 1 || c->net_nl > 7 || c->net_ch[0] != 1 || c->net_ch[c->net_nl] != 1) {
       *why = "network: 1..7 layers, one input and one output channel";
@@ -210,6 +211,16 @@ void compute_layout(const qdd_geom* g, const qdd_config* c, Layout& Lo) {
   }
   // chronological inversion: the last chrono_nv solutions of every rhs slot (FP64 full fields)
   Lo.chrono = c->chrono_nv > 0 ? B.take((size_t)c->chrono_nv * nr * 24 * Vh * 16) : 0;
+  // force buffers: X- and Y-type full fields of the two pseudofermion terms
+  // ([term][parity][site][12] complex), the clover insertions ([parity][plane][9][site])
+  // and two canonical even fields
+  Lo.frc_x = Lo.frc_y = Lo.frc_lt = Lo.frc_src = 0;
+  if (c->force) {
+    Lo.frc_x = B.take((size_t)2 * 24 * Vh * 16);
+    Lo.frc_y = B.take((size_t)2 * 24 * Vh * 16);
+    Lo.frc_lt = B.take((size_t)2 * 6 * 9 * Vh * 8);
+    Lo.frc_src = B.take((size_t)2 * 12 * Vh * 16);
+  }
   // reductions and small solver arrays
   Lo.part = B.take((size_t)kDotBlocks * kMaxKv * nr * 16 + 4096);
   Lo.coef = B.take((size_t)nr * kMaxKv * 16);
@@ -252,6 +263,7 @@ void qdd_config_default(qdd_config* c) {
   c->chrono_nv = 0;
   c->dfl_refresh_iters = 0;
   c->dfl_refresh_nit = 2;
+  c->force = 0;
 }
 
 size_t qdd_workspace_bytes(const qdd_geom* g, const qdd_config* c) {

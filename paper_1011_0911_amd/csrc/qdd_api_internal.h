@@ -28,6 +28,7 @@ struct Layout {
   size_t net_nw, net_w, net_wb, net_wadj, net_wmx, net_wmxa, net_act, net_grad, net_adam, net_gpart, net_loss, net_tmp;
   size_t net_pairs, net_pairs_bytes, net_gpart_floats;
   size_t part, coef, ahist, bhist, binv, chist, rn2, alpha, active, scal, chrono;
+  size_t frc_x, frc_y, frc_lt, frc_src;
   size_t total;
 };
 

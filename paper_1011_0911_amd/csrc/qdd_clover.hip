@@ -6,76 +6,9 @@
 //   B_1 = F_23, B_2 = F_31, B_3 = F_12.
 // Each block and its inverse (Cholesky, FP64) are stored as 18 slots.
 #include "qdd_kernels.h"
+#include "qdd_su3.h"
 
 namespace qdd {
-
-typedef cx<double> zd;
-
-struct M3 {
-  zd a[9];
-};
-
-__device__ inline M3 mul(const M3& x, const M3& y) {
-  M3 r;
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      zd s{0, 0};
-#pragma unroll
-      for (int k = 0; k < 3; ++k) s = fma_c(x.a[i * 3 + k], y.a[k * 3 + j], s);
-      r.a[i * 3 + j] = s;
-    }
-  return r;
-}
-// x y^dag
-__device__ inline M3 mul_nd(const M3& x, const M3& y) {
-  M3 r;
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      zd s{0, 0};
-#pragma unroll
-      for (int k = 0; k < 3; ++k) s = s + x.a[i * 3 + k] * conj(y.a[j * 3 + k]);
-      r.a[i * 3 + j] = s;
-    }
-  return r;
-}
-// x^dag y
-__device__ inline M3 mul_dn(const M3& x, const M3& y) {
-  M3 r;
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      zd s{0, 0};
-#pragma unroll
-      for (int k = 0; k < 3; ++k) s = fmac_c(x.a[k * 3 + i], y.a[k * 3 + j], s);
-      r.a[i * 3 + j] = s;
-    }
-  return r;
-}
-
-// bare link U_mu(y) (boundary sign removed again) at coordinates y
-__device__ inline M3 bare_link(const Geo& g, const double2* U, const int y[4], int mu) {
-  int lex = lex_of(g, y);
-  int p = (y[0] + y[1] + y[2] + y[3]) & 1;
-  double s = (mu == 0 && y[0] == g.L[0] - 1) ? (double)g.bc : 1.0;
-  const double2* b = U + (int64_t)(p * 4 + mu) * 9 * g.Vh + (lex >> 1);
-  M3 m;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    double2 v = b[(int64_t)k * g.Vh];
-    m.a[k] = {s * v.x, s * v.y};
-  }
-  return m;
-}
-
-__device__ inline void shift(const Geo& g, const int x[4], int mu, int d, int y[4]) {
-  for (int k = 0; k < 4; ++k) y[k] = x[k];
-  y[mu] = (y[mu] + d + g.L[mu]) % g.L[mu];
-}
 
 // F_{mu nu}(x) from the four leaves (same orientation, all starting at x)
 __device__ M3 field_strength(const Geo& g, const double2* U, const int x[4], int mu, int nu) {

@@ -79,6 +79,21 @@ hipError_t launch_field_convert(FieldV<SI> in, FieldV<SO> out, int nvec, hipStre
 // ---- clover (qdd_clover.hip)
 // builds A and A^{-1} (FP64, both parities) from the FP64 internal links; counts
 // blocks whose Cholesky factorisation fails into *bad (device int)
+// pseudofermion terms of the force: fields [parity][Vh][12] complex (X, Y and
+// their odd-site images), the even source phi, weight c and clover shift s
+struct FrcTerms {
+  int nt = 0;
+  const double2* X[2] = {nullptr, nullptr};
+  const double2* Y[2] = {nullptr, nullptr};
+  const double2* phi[2] = {nullptr, nullptr};
+  double c[2] = {0, 0}, s[2] = {0, 0};
+};
+hipError_t launch_force_odd(const Geo& g, const DevOp<double>& op, int nt, double2* X, double2* Y, hipStream_t st);
+hipError_t launch_force_src(const Geo& g, const DevOp<double>& op, const double2* psi, const double2* xi,
+                            const double2* phi2, double dm, double2* src, hipStream_t st);
+hipError_t launch_force(const Geo& g, const DevOp<double>& op, const double2* U, double det_w, double csw,
+                        const FrcTerms& T, double* lt, double* force, hipStream_t st);
+
 hipError_t launch_clover(const Geo& g, const double2* U, double diag, double csw, double2* A, double2* Ai, int* bad,
                          hipStream_t st);
 

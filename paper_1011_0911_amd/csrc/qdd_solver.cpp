@@ -722,6 +722,62 @@ extern "C" qdd_status qdd_action(qdd_ctx* x, double dm, const double* phi1, cons
   return QDD_OK;
 }
 
+// Forces of S_eff (Eq. 4; the molecular-dynamics forces of Sect. 2).  With
+// W(s) = A_e^{-1} (Dhat + s A_e), a pseudofermion term -2c Re[X^dag d(Dhat + s A_e) Y
+// - X^dag dA_e phi] has Y = W^{-1} phi (psi for phi1 with s = dm, c = 1; xi for phi2
+// with s = 0, c = dm) and X = (Dhat + s A_e)^{-dag} w, w = psi or phi2 + dm xi,
+// computed as g5 W(s)^{-1} A_e^{-1} g5 w (Dhat + s A_e is g5-Hermitian and A_e
+// commutes with g5).  Both solves of each kind run as one batch of two.
+extern "C" qdd_status qdd_force(qdd_ctx* x, double dm, const double* phi1, const double* phi2, int terms,
+                                double* force, qdd_solve_info* info) {
+  if (!x || !force || terms < 1 || terms > 7 || !std::isfinite(dm) || dm < 0 || !x->cfg.force ||
+      ((terms & 6) && (!phi1 || !phi2 || x->cfg.max_nrhs < 2))) {
+    if (x) x->fail("qdd_force: invalid arguments (needs config.force = 1; max_nrhs >= 2 for the pseudofermion terms)");
+    return QDD_EINVAL;
+  }
+  if (!x->have_clover) {
+    x->fail("qdd_force before qdd_set_params");
+    return QDD_ESTATE;
+  }
+  const int64_t Vh = x->G.Vh, ts = 2 * 12 * Vh;  // complex entries of one term's full field
+  double2 *fx = x->ptr<double2>(x->lo.frc_x), *fy = x->ptr<double2>(x->lo.frc_y);
+  double2* src = x->ptr<double2>(x->lo.frc_src);
+  hipStream_t st = x->st;
+  const DevOp<double> op = x->op<double>();
+  FrcTerms T;
+  if (info)
+    for (int r = 0; r < 4; ++r) info[r] = qdd_solve_info{};
+  if (terms & 6) {
+    qdd_status s = solve_w_check(x, 2, "qdd_force");
+    if (s != QDD_OK) return s;
+    const double dms[2] = {dm, 0.0};
+    const double* ph[2] = {phi1, phi2};
+    double* y[2] = {(double*)fy, (double*)(fy + ts)};
+    s = solve_w_impl(x, 2, dms, ph, y, info);
+    if (s != QDD_OK) return s;
+    HCK(x, launch_force_src(x->G, op, fy, fy + ts, (const double2*)phi2, dm, src, st));
+    const double* us[2] = {(const double*)src, (const double*)(src + 12 * Vh)};
+    double* z[2] = {(double*)fx, (double*)(fx + ts)};
+    s = solve_w_impl(x, 2, dms, us, z, info ? info + 2 : nullptr);
+    if (s != QDD_OK) return s;
+    HCK(x, launch_force_odd(x->G, op, 2, fx, fy, st));
+    for (int t = 0; t < 2; ++t) {
+      const bool on = t == 0 ? (terms & 2) != 0 : ((terms & 4) != 0 && dm != 0.0);
+      if (!on) continue;
+      T.X[T.nt] = fx + t * ts;
+      T.Y[T.nt] = fy + t * ts;
+      T.phi[T.nt] = (const double2*)(t == 0 ? phi1 : phi2);
+      T.c[T.nt] = t == 0 ? 1.0 : dm;
+      T.s[T.nt] = t == 0 ? dm : 0.0;
+      ++T.nt;
+    }
+  }
+  HCK(x, launch_force(x->G, op, x->ptr<double2>(x->lo.U[0]), (terms & 1) ? -2.0 : 0.0, x->csw, T,
+                      x->ptr<double>(x->lo.frc_lt), force, st));
+  HCK(x, hipStreamSynchronize(st));
+  return QDD_OK;
+}
+
 // Plain solve of one right-hand side that records a (residual, error) pair at
 // every outer iteration: r_k = eta - D psi_k (the recursive residual) and
 // e_k = psi* - psi_k, both returned as packed FP32 full fields (training data of

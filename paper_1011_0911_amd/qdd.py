@@ -45,6 +45,7 @@ class Config(ctypes.Structure):
         ("use_net", ctypes.c_int), ("net_nl", ctypes.c_int), ("net_ch", ctypes.c_int * 8),
         ("net_terms", ctypes.c_int),
         ("chrono_nv", ctypes.c_int), ("dfl_refresh_iters", ctypes.c_int), ("dfl_refresh_nit", ctypes.c_int),
+        ("force", ctypes.c_int),
     ]
 
 
@@ -106,6 +107,7 @@ SIGNATURES = {
     "qdd_solve_qs": (_i, [_vp, _i, _vp, _vp, _vp]),
     "qdd_solve_w": (_i, [_vp, _i, _d, _vp, _vp, _vp]),
     "qdd_action": (_i, [_vp, _d, _vp, _vp, _vp, _vp, ctypes.POINTER(_d), ctypes.POINTER(_d), _vp]),
+    "qdd_force": (_i, [_vp, _d, _vp, _vp, _i, _vp, _vp]),
     "qdd_set_launch": (_i, [_vp, _i, _i, _i, _i, _i, _i]),
     "qdd_get_launch": (_i, [_vp, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i),
                             ctypes.POINTER(_i)]),
@@ -408,6 +410,17 @@ class Context:
         self._check(lib().qdd_action(self.h, float(dm), _ptr(p1), _ptr(p2), _ptr(c1), _ptr(c2), ctypes.byref(s),
                                      parts, info))
         return s.value, tuple(parts), c1, c2, [i.as_dict() for i in info]
+
+    def force(self, dm, phi1, phi2, terms=7):
+        """Link derivatives of S_eff (Eq. 4, as action()): f (V, 4, 8) float64, f[lex, mu, a]
+        along T^a = i lambda^a / 2; terms: bit 0 log-det, bit 1 phi1, bit 2 phi2 term.
+        Returns (f, infos of the four solves)."""
+        p1, p2 = self._c128(phi1), self._c128(phi2)
+        assert p1.numel() == p2.numel() == self.Vh * 12
+        f = torch.empty((self.V, 4, 8), dtype=torch.float64, device=self.device)
+        info = (SolveInfo * 4)()
+        self._check(lib().qdd_force(self.h, float(dm), _ptr(p1), _ptr(p2), int(terms), _ptr(f), info))
+        return f, [i.as_dict() for i in info]
 
     def solve_dhat(self, eta_e, check=True):
         c = self._c128(eta_e)
