@@ -38,6 +38,13 @@ void orc_field_strength(const int* L, int bc, const double* U, int64_t x, int mu
   field_strength(g, CC(U), x, mu, nu, C(F));
 }
 
+void orc_block_bicgstab(const int* L, int bc, const double* U, const double* A, const double* Ainv, const int* bs,
+                        const int64_t* blks, int64_t nlist, const double* eta, double* psi, double tol, int maxit,
+                        int* iters, double* res) {
+  Geom g(L, bc);
+  block_bicgstab(g, CC(U), CC(A), CC(Ainv), bs, blks, nlist, CC(eta), C(psi), tol, maxit, iters, res);
+}
+
 void orc_clover_force(const int* L, int bc, const double* U, double csw, const double* K, double* M) {
   Geom g(L, bc);
   clover_force(g, CC(U), csw, CC(K), C(M));

@@ -62,6 +62,10 @@ struct Deflation {
 };
 
 
+// Dirichlet block solves by BiCGstab on a list of blocks (orc_solve.cpp)
+void block_bicgstab(const Geom& g, const cplx* U, const cplx* A, const cplx* Ainv, const int* bs,
+                    const int64_t* blks, int64_t nlist, const cplx* eta, cplx* psi, double tol, int maxit, int* iters,
+                    double* res);
 FgcrResult fgcr(int64_t n, const LinOp& op, const LinOp* prec, const cplx* eta, cplx* psi, int nkv, int nmx,
                 double tol, double* history, int nhist);
 void sap(const Geom& g, const cplx* U, const cplx* A, const cplx* Ainv, const int* bs, int ncy, int nmr,

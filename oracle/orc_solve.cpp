@@ -104,6 +104,156 @@ static void block_mr(const Blocks& B, int64_t blk, const cplx* U, const cplx* A,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Dirichlet block solves D_Lambda psi = eta on a list of blocks: the block
+// inversions of the DD-HMC forces, which the paper does with BiCGstab (Sect. 3).
+// D_Lambda is D restricted to the block (hops that cross a block face dropped).
+// The source is reduced to the block's even sites, b = eta_e - D_eo,L A_o^{-1} eta_o;
+// BiCGstab (van der Vorst) on Dhat_Lambda = A_e - D_eo,L A_o^{-1} D_oe,L runs from
+// zero until |r| <= tol |b| or maxit iterations; then
+// psi_o = A_o^{-1}(eta_o - D_oe,L psi_e).  Fields are full-lattice; only the
+// listed blocks' sites of psi are written.  iters[k] gets the iterations of the
+// k-th listed block (-1 after a breakdown, a zero denominator), res[k] |r|/|b|.
+namespace {
+struct BlockLocal {
+  const Blocks& B;
+  int o[4];
+  int64_t nsb;
+  BlockLocal(const Blocks& B_, int64_t blk) : B(B_) {
+    int c[4];
+    B.bcoords(blk, c);
+    nsb = 1;
+    for (int i = 0; i < 4; ++i) { o[i] = c[i] * B.bs[i]; nsb *= B.bs[i]; }
+  }
+  int64_t local(int64_t x) const {  // block-local lexicographic index of site x
+    int c[4];
+    B.g.coords(x, c);
+    return (((int64_t)(c[0] - o[0]) * B.bs[1] + (c[1] - o[1])) * B.bs[2] + (c[2] - o[2])) * B.bs[3] + (c[3] - o[3]);
+  }
+};
+
+// out += scale * H_Lambda f at site x; f holds the block's sites by local index
+void hop_local(const BlockLocal& L, const cplx* U, const cplx* f, int64_t x, double scale, cplx* out) {
+  const Geom& g = L.B.g;
+  const Gamma& G = gammas();
+  for (int mu = 0; mu < 4; ++mu)
+    for (int dir = 0; dir < 2; ++dir) {
+      if (!L.B.internal(x, mu, dir)) continue;
+      const int64_t y = dir == 0 ? g.up(x, mu) : g.dn(x, mu);
+      const double s = dir == 0 ? g.sign_up(x, mu) : g.sign_up(y, mu);
+      const cplx* u = dir == 0 ? link(U, x, mu) : link(U, y, mu);
+      const cplx* v = f + L.local(y) * 12;
+      cplx t[12];
+      for (int sp = 0; sp < 4; ++sp)
+        for (int a = 0; a < 3; ++a) {
+          cplx acc = 0;
+          for (int b = 0; b < 3; ++b) acc += (dir == 0 ? u[a * 3 + b] : std::conj(u[b * 3 + a])) * v[sp * 3 + b];
+          t[sp * 3 + a] = acc;
+        }
+      const double pm = dir == 0 ? -1.0 : 1.0;
+      for (int sa = 0; sa < 4; ++sa)
+        for (int a = 0; a < 3; ++a) {
+          cplx acc = t[sa * 3 + a];
+          for (int sb = 0; sb < 4; ++sb) acc += pm * G.g[mu][sa][sb] * t[sb * 3 + a];
+          out[sa * 3 + a] += scale * s * acc;
+        }
+    }
+}
+}  // namespace
+
+void block_bicgstab(const Geom& g, const cplx* U, const cplx* A, const cplx* Ainv, const int* bs,
+                    const int64_t* blks, int64_t nlist, const cplx* eta, cplx* psi, double tol, int maxit, int* iters,
+                    double* res) {
+  Blocks B(g, bs);
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t k = 0; k < nlist; ++k) {
+    const int64_t blk = blks[k];
+    BlockLocal L(B, blk);
+    const std::vector<int64_t>& st = B.sites[blk];
+    std::vector<int64_t> ev, od;
+    for (int64_t x : st) (g.parity(x) == 0 ? ev : od).push_back(x);
+    const int64_t n = L.nsb * 12;
+    // local vectors (even entries used for the Krylov vectors, odd for the intermediates)
+    std::vector<cplx> w(n), b(n), x(n), r(n), rh(n), p(n), v(n), sv(n), t(n);
+    auto local = [&](int64_t y) { return L.local(y) * 12; };
+    // Dhat_Lambda in (even) -> out (even), with D_eo,L = -1/2 H_L:
+    // w_o = A_o^{-1} D_oe,L in = A_o^{-1} (-1/2 H_L in), out_e = A_e in - D_eo,L w_o = A_e in + 1/2 H_L w_o
+    auto dhat = [&](const std::vector<cplx>& in, std::vector<cplx>& out) {
+      for (int64_t y : od) {
+        cplx h[12] = {};
+        hop_local(L, U, in.data(), y, -0.5, h);
+        apply_clover_site(Ainv + y * 144, h, &w[local(y)]);
+      }
+      for (int64_t z : ev) {
+        cplx o[12];
+        apply_clover_site(A + z * 144, &in[local(z)], o);
+        hop_local(L, U, w.data(), z, 0.5, o);
+        for (int c = 0; c < 12; ++c) out[local(z) + c] = o[c];
+      }
+    };
+    auto dotp = [&](const std::vector<cplx>& a, const std::vector<cplx>& c) {
+      cplx acc = 0;
+      for (int64_t z : ev)
+        for (int q = 0; q < 12; ++q) acc += std::conj(a[local(z) + q]) * c[local(z) + q];
+      return acc;
+    };
+    // b = eta_e - D_eo,L A_o^{-1} eta_o = eta_e + 1/2 H_L (A_o^{-1} eta_o)
+    for (int64_t y : od) apply_clover_site(Ainv + y * 144, eta + y * 12, &w[local(y)]);
+    for (int64_t z : ev) {
+      cplx h[12] = {};
+      hop_local(L, U, w.data(), z, 0.5, h);
+      for (int c = 0; c < 12; ++c) b[local(z) + c] = eta[z * 12 + c] + h[c];
+    }
+    // BiCGstab from x = 0
+    r = b;
+    rh = b;
+    const double bn = std::sqrt(dotp(b, b).real());
+    cplx rho = 1, alpha = 1, omega = 1;
+    int it = 0;
+    double rn = bn;
+    bool broke = false;
+    while (rn > tol * bn && it < maxit) {
+      const cplx rho_new = dotp(rh, r);
+      const cplx beta = (rho_new / rho) * (alpha / omega);
+      for (int64_t z : ev)
+        for (int q = 0; q < 12; ++q) {
+          const int64_t i = local(z) + q;
+          p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        }
+      dhat(p, v);
+      const cplx rv = dotp(rh, v);
+      if (rv == cplx(0)) { broke = true; break; }
+      alpha = rho_new / rv;
+      for (int64_t z : ev)
+        for (int q = 0; q < 12; ++q) sv[local(z) + q] = r[local(z) + q] - alpha * v[local(z) + q];
+      dhat(sv, t);
+      const double tt = dotp(t, t).real();
+      if (tt == 0) { broke = true; break; }
+      omega = dotp(t, sv) / tt;
+      for (int64_t z : ev)
+        for (int q = 0; q < 12; ++q) {
+          const int64_t i = local(z) + q;
+          x[i] += alpha * p[i] + omega * sv[i];
+          r[i] = sv[i] - omega * t[i];
+        }
+      rho = rho_new;
+      rn = std::sqrt(dotp(r, r).real());
+      ++it;
+    }
+    iters[k] = broke ? -1 : it;
+    res[k] = bn > 0 ? rn / bn : 0.0;
+    // psi_e = x, psi_o = A_o^{-1}(eta_o - D_oe,L psi_e) = A_o^{-1}(eta_o + 1/2 H_L psi_e)
+    for (int64_t z : ev)
+      for (int c = 0; c < 12; ++c) psi[z * 12 + c] = x[local(z) + c];
+    for (int64_t y : od) {
+      cplx h[12];
+      for (int c = 0; c < 12; ++c) h[c] = eta[y * 12 + c];
+      hop_local(L, U, x.data(), y, 0.5, h);
+      apply_clover_site(Ainv + y * 144, h, &psi[y * 12]);
+    }
+  }
+}
+
 // Multiplicative two-colour Schwarz procedure (reading): psi = 0, rho = eta;
 // ncy cycles, each over colour 0 then colour 1; all blocks of one colour are
 // solved independently from the current residual, psi += v on those blocks,
