@@ -106,6 +106,10 @@ typedef struct {
   /* 1: the workspace also holds the buffers of qdd_force (4 FP64 fields, the
      per-plane clover insertions and 2 even fields: 1392 bytes per site) */
   int force;
+  /* Dirichlet block solver (qdd_block_solve): block extents (even, dividing the
+     lattice); all 0 = no block solver.  Reserves the block-major links and clover
+     blocks and eight FP64 vectors per rhs (about 2.1 KB per site per rhs) */
+  int blk_bs[4];
 } qdd_config;
 
 typedef struct {
@@ -120,6 +124,15 @@ typedef struct {
                        counted where the host next waits (the Gram-Schmidt reductions);
                        only index 0 is a GPU-inclusive wall time */
 } qdd_solve_info;
+
+typedef struct {
+  int nblk;          /* blocks times right-hand sides solved */
+  int converged;     /* how many reached |r| <= tol |b| */
+  int breakdowns;    /* how many stopped on a zero BiCGstab denominator */
+  int iters_max;     /* largest iteration count */
+  double res_max;    /* largest final |r| / |b| */
+  double t_ms;       /* GPU time of the solve (HIP events) */
+} qdd_block_info;
 
 typedef struct qdd_ctx qdd_ctx;
 
@@ -308,6 +321,21 @@ qdd_status qdd_action(qdd_ctx* ctx, double dm, const double* phi1, const double*
  * errors as for qdd_solve_w. */
 qdd_status qdd_force(qdd_ctx* ctx, double dm, const double* phi1, const double* phi2, int terms, double* force,
                      qdd_solve_info* info);
+/* Dirichlet block solves (the block inversions of the DD-HMC forces, which the
+ * paper does with BiCGstab, Sect. 3): D_Lambda psi = eta on every block Lambda of
+ * extent config.blk_bs, D_Lambda being D restricted to the block (hops that leave
+ * the block dropped).  Each block's source is reduced to its even sites
+ * (b = eta_e - D_eo,L A_o^{-1} eta_o), BiCGstab on the block's even-odd Schur
+ * complement runs from zero until |r| <= tol |b| or maxit iterations, and the odd
+ * sites are reconstructed; FP64.  One workgroup solves one (block, rhs) in a
+ * single launch.  eta, psi: nrhs canonical complex128 full fields (device).
+ * blk_iters / blk_res (host, nrhs * nblk entries, rhs-major, blocks in
+ * lexicographic block order, or NULL): iterations (-1 after a breakdown) and final
+ * |r|/|b| per block.  QDD_EINVAL for a context without blk_bs, nrhs outside
+ * 1..max_nrhs, tol <= 0 or maxit < 1; QDD_ESTATE before qdd_set_params; QDD_ENOCONV
+ * if a block did not converge (psi holds the last iterate, info the counts). */
+qdd_status qdd_block_solve(qdd_ctx* ctx, int nrhs, const double* eta, double* psi, double tol, int maxit,
+                           int* blk_iters, double* blk_res, qdd_block_info* info);
 
 /* ---- learned preconditioner stage (configuration use_net = 1) ----
  * A gauge-covariant parallel-transport convolution network N with net_nl

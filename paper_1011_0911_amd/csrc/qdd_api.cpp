@@ -87,6 +87,11 @@ static bool valid_cfg(const qdd_geom* g, const qdd_config* c, std::string* why) 
   }
   if (c->dfl_refresh_iters < 0 || c->dfl_refresh_nit < 0) { *why = "invalid refresh parameters"; return false; }
   if (c->force != 0 && c->force != 1) { *why = "force must be 0 or 1"; return false; }
+  if (c->blk_bs[0] || c->blk_bs[1] || c->blk_bs[2] || c->blk_bs[3]) {
+    if (!valid_blocks(g, c->blk_bs, false, why, "block-solver")) return false;
+    for (int i = 0; i < 4; ++i)
+      if (c->blk_bs[i] & 1) { *why = "block-solver block extents must be even"; return false; }
+  }
   if (c->use_net) {
     if (c->net_nl < 1 || c->net_nl > 7 || c->net_ch[0] != 1 || c->net_ch[c->net_nl] != 1) {
       *why = "network: 1..7 layers, one input and one output channel";
@@ -221,6 +226,19 @@ void compute_layout(const qdd_geom* g, const qdd_config* c, Layout& Lo) {
     Lo.frc_lt = B.take((size_t)2 * 6 * 9 * Vh * 8);
     Lo.frc_src = B.take((size_t)2 * 12 * Vh * 16);
   }
+  // block solver: block-major links and clover blocks (both parities), eight
+  // FP64 even-site vectors per rhs, per-block iteration counts and residuals
+  Lo.blk_U = Lo.blk_A = Lo.blk_Ai = Lo.blk_work = Lo.blk_it = Lo.blk_res = 0;
+  if (c->blk_bs[0]) {
+    int64_t nblk = 1;
+    for (int i = 0; i < 4; ++i) nblk *= g->L[i] / c->blk_bs[i];
+    Lo.blk_U = B.take(links * 16);
+    Lo.blk_A = B.take(clov * 16);
+    Lo.blk_Ai = B.take(clov * 16);
+    Lo.blk_work = B.take((size_t)nr * 8 * 12 * Vh * 16);
+    Lo.blk_it = B.take((size_t)nr * nblk * 4);
+    Lo.blk_res = B.take((size_t)nr * nblk * 8);
+  }
   // reductions and small solver arrays
   Lo.part = B.take((size_t)kDotBlocks * kMaxKv * nr * 16 + 4096);
   Lo.coef = B.take((size_t)nr * kMaxKv * 16);
@@ -264,6 +282,7 @@ void qdd_config_default(qdd_config* c) {
   c->dfl_refresh_iters = 0;
   c->dfl_refresh_nit = 2;
   c->force = 0;
+  for (int i = 0; i < 4; ++i) c->blk_bs[i] = 0;
 }
 
 size_t qdd_workspace_bytes(const qdd_geom* g, const qdd_config* c) {
@@ -338,6 +357,7 @@ qdd_status qdd_set_gauge(qdd_ctx* x, const double* links) {
   x->have_gauge = true;
   x->have_clover = false;
   x->have_dfl = false;
+  x->blk_ready = false;
   return QDD_OK;
 }
 
@@ -361,6 +381,7 @@ qdd_status qdd_set_params(qdd_ctx* x, double kappa, double csw) {
   x->kappa = kappa;
   x->csw = csw;
   x->have_dfl = false;
+  x->blk_ready = false;
   if (bad) {
     x->have_clover = false;
     x->fail("%d clover blocks are not positive definite", bad);

@@ -29,6 +29,7 @@ struct Layout {
   size_t net_pairs, net_pairs_bytes, net_gpart_floats;
   size_t part, coef, ahist, bhist, binv, chist, rn2, alpha, active, scal, chrono;
   size_t frc_x, frc_y, frc_lt, frc_src;
+  size_t blk_U, blk_A, blk_Ai, blk_work, blk_it, blk_res;
   size_t total;
 };
 
@@ -64,6 +65,7 @@ struct qdd_ctx {
   std::vector<int> chrono_count, chrono_head;  // stored solutions per rhs slot, next slot to write
   int dfl_builds = 0, dfl_refreshes = 0;
   bool have_basis = false;  // the workspace holds a deflation basis (kept across set_gauge / set_params)
+  bool blk_ready = false;   // block-major links and clover of the block solver are current
   std::string err;
 
   template <class T>

@@ -79,6 +79,18 @@ hipError_t launch_field_convert(FieldV<SI> in, FieldV<SO> out, int nvec, hipStre
 // ---- clover (qdd_clover.hip)
 // builds A and A^{-1} (FP64, both parities) from the FP64 internal links; counts
 // blocks whose Cholesky factorisation fails into *bad (device int)
+// Dirichlet blocks of the block solver: extents, blocks per direction, count,
+// sites of one parity per block
+struct BlkGeo {
+  int bs[4], nb[4];
+  int nblk, neb;
+};
+hipError_t launch_blk_gather(const Geo& g, const BlkGeo& B, const double2* U, const double2* A, const double2* Ai,
+                             double2* BU, double2* BA, double2* BAi, hipStream_t st);
+hipError_t launch_blk_bicgstab(const Geo& g, const BlkGeo& B, const double2* BU, const double2* BA,
+                               const double2* BAi, double2* work, const double2* eta, double2* psi, int nrhs,
+                               double tol, int maxit, int* iters, double* res, hipStream_t st);
+
 // pseudofermion terms of the force: fields [parity][Vh][12] complex (X, Y and
 // their odd-site images), the even source phi, weight c and clover shift s
 struct FrcTerms {

@@ -46,7 +46,16 @@ class Config(ctypes.Structure):
         ("net_terms", ctypes.c_int),
         ("chrono_nv", ctypes.c_int), ("dfl_refresh_iters", ctypes.c_int), ("dfl_refresh_nit", ctypes.c_int),
         ("force", ctypes.c_int),
+        ("blk_bs", ctypes.c_int * 4),
     ]
+
+
+class BlockInfo(ctypes.Structure):
+    _fields_ = [("nblk", ctypes.c_int), ("converged", ctypes.c_int), ("breakdowns", ctypes.c_int),
+                ("iters_max", ctypes.c_int), ("res_max", ctypes.c_double), ("t_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class SolveInfo(ctypes.Structure):
@@ -108,6 +117,7 @@ SIGNATURES = {
     "qdd_solve_w": (_i, [_vp, _i, _d, _vp, _vp, _vp]),
     "qdd_action": (_i, [_vp, _d, _vp, _vp, _vp, _vp, ctypes.POINTER(_d), ctypes.POINTER(_d), _vp]),
     "qdd_force": (_i, [_vp, _d, _vp, _vp, _i, _vp, _vp]),
+    "qdd_block_solve": (_i, [_vp, _i, _vp, _vp, _d, _i, _vp, _vp, _vp]),
     "qdd_set_launch": (_i, [_vp, _i, _i, _i, _i, _i, _i]),
     "qdd_get_launch": (_i, [_vp, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i),
                             ctypes.POINTER(_i)]),
@@ -137,7 +147,7 @@ def default_config(**kw) -> Config:
     c = Config()
     lib().qdd_config_default(ctypes.byref(c))
     for k, v in kw.items():
-        if k in ("sap_bs", "dfl_bs", "net_ch"):
+        if k in ("sap_bs", "dfl_bs", "net_ch", "blk_bs"):
             arr = getattr(c, k)
             for j, x in enumerate(v):
                 arr[j] = int(x)
@@ -421,6 +431,26 @@ class Context:
         info = (SolveInfo * 4)()
         self._check(lib().qdd_force(self.h, float(dm), _ptr(p1), _ptr(p2), int(terms), _ptr(f), info))
         return f, [i.as_dict() for i in info]
+
+    def block_solve(self, eta, tol=1e-10, maxit=1000, check=True):
+        """Dirichlet block solves D_Lambda psi = eta on every block of extent
+        config.blk_bs (BiCGstab on each block): returns (psi (nrhs, V, 4, 3), iterations
+        (nrhs, nblk), |r|/|b| (nrhs, nblk), summary dict, status)."""
+        c = self._c128(eta)
+        nrhs = c.numel() // (self.V * 12)
+        nblk = 1
+        for j in range(4):  # (no block extents: the library rejects the call)
+            nblk *= self.L[j] // self.cfg.blk_bs[j] if self.cfg.blk_bs[j] else 1
+        out = torch.empty((nrhs, self.V, 4, 3), dtype=torch.complex128, device=self.device)
+        it = (ctypes.c_int * (nrhs * nblk))()
+        res = (ctypes.c_double * (nrhs * nblk))()
+        info = BlockInfo()
+        st = lib().qdd_block_solve(self.h, nrhs, _ptr(c), _ptr(out), float(tol), int(maxit), it, res,
+                                   ctypes.byref(info))
+        if check:
+            self._check(st)
+        return (out, torch.tensor(it[:], dtype=torch.int32).reshape(nrhs, nblk),
+                torch.tensor(res[:], dtype=torch.float64).reshape(nrhs, nblk), info.as_dict(), st)
 
     def solve_dhat(self, eta_e, check=True):
         c = self._c128(eta_e)
