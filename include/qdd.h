@@ -406,7 +406,9 @@ qdd_status qdd_solve_harvest(qdd_ctx* ctx, int nrhs, const double* eta, double* 
  * the nr right-hand sides of a spinor component (and their FP16 scales) as one
  * word of at most 16 bytes, with the streaming and compression bits (4, 8, 16)
  * as for nr = 1; it applies to interleaved batches whose size is a multiple of
- * nr, other operands take the plain kernels; sb sites per block
+ * nr, other operands take the plain kernels; for Dhat with nr >= 1, plus 64:
+ * pass B walks its tiles backwards (every XCD's range from its end), so it
+ * starts with the odd-site intermediate pass A wrote last; sb sites per block
  * (0 = block): the block/sb lane groups of a
  * block take further right-hand sides of the same sites.  QDD_EINVAL for shapes
  * outside these ranges. */

@@ -482,9 +482,11 @@ qdd_status qdd_set_launch(qdd_ctx* x, int kernel, qdd_prec prec, int block, int 
     x->sap_variant[prec] = nr;
     return QDD_OK;
   }
+  // Dhat (not staged): + 64 walks pass B backwards
+  const int xb = kernel == 0 && nr != 0 && xcd >= 64 ? xcd - 64 : xcd;
   bool ok = x && kernel >= 0 && kernel <= 1 && prec >= QDD_F64 && prec <= QDD_F16 && block >= 64 && block <= 256 &&
-            (block & 63) == 0 && (nr == 0 || nr == 1 || nr == 2 || nr == 4) && xcd >= 0 &&
-            (xcd <= (kernel == 0 && nr == 1 ? 31 : 3) || (kernel == 0 && xcd >= 32 && xcd <= 63 && dhat_vec_ok(prec, nr))) &&
+            (block & 63) == 0 && (nr == 0 || nr == 1 || nr == 2 || nr == 4) && xb >= 0 &&
+            (xb <= (kernel == 0 && nr == 1 ? 31 : 3) || (kernel == 0 && xb >= 32 && xb <= 63 && dhat_vec_ok(prec, nr))) &&
             (sb == 0 || (sb >= 1 && sb <= block && block % sb == 0));
   // staged variant (nr = 0): Dhat only, and the tile's links + clover must fit the LDS budget
   if (ok && nr == 0) ok = kernel == 0 && staged_lds_bytes(prec, sb > 0 ? sb : block) <= kStagedLdsMax;

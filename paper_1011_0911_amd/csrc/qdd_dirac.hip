@@ -78,8 +78,18 @@ __device__ inline void hop_all(const Geo& g, const LinkV<S>& U, const FieldV<S>&
 // row: a step (one time slice of the slab) touches its own spinors and those of
 // the two neighbouring steps, which stay in the XCD's L2; only the x1 faces of
 // the slab reach into the slabs of other XCDs.
+// order + 4: the walk runs backwards (every XCD's range from its end), so a
+// pass that reads what the previous pass wrote starts with the most recently
+// written data, which the memory-side cache may still hold.
 __device__ inline void map_block(const Geo& g, int b, int nblk, int nrg, int sb, int order, int& tile, int& rg) {
-  if (order >= 1 && (nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
+  const bool rev = (order & 4) != 0;
+  order &= 3;
+  if (order >= 1 && (nblk & 7) == 0) {
+    const int per = nblk >> 3, j = b >> 3;
+    b = (b & 7) * per + (rev ? per - 1 - j : j);
+  } else if (rev) {
+    b = nblk - 1 - b;
+  }
   rg = b % nrg;
   tile = b / nrg;
   const int row = g.L[2] * g.Lh3;  // sites of one (x0, x1) row of a parity
@@ -630,7 +640,7 @@ static hipError_t launch_dhat_vec(const Geo& g, const DevOp<S>& op, FieldV<S> in
   int sb = c.sb > 0 ? c.sb : c.block;
   int nrg = ceil_div(nrhs, V * (c.block / sb));
   dim3 grid(ceil_div(g.Vh, sb) * nrg), blk(c.block);
-  const int ntm = (c.xcd >> 2) & 7, order = c.xcd & 3;
+  const int ntm = (c.xcd >> 2) & 7, order = c.xcd & 3, order_b = order | ((c.xcd & 64) ? 4 : 0);
 #define QDD_VEC(KER, ...)                                                                  \
   switch (ntm) {                                                                           \
     case 0: hipLaunchKernelGGL((KER<S, V, 0>), grid, blk, 0, st, __VA_ARGS__); break;      \
@@ -644,7 +654,7 @@ static hipError_t launch_dhat_vec(const Geo& g, const DevOp<S>& op, FieldV<S> in
   }
   if (pass & 1) QDD_VEC(k_dhat_va, g, op.U, op.Ainv, in, tmp, nrhs, nrg, order, sb)
   if (ev) (void)hipEventRecord(ev, st);
-  if (pass & 2) QDD_VEC(k_dhat_vb, g, op.U, op.A, in, tmp, out, nrhs, nrg, order, sb)
+  if (pass & 2) QDD_VEC(k_dhat_vb, g, op.U, op.A, in, tmp, out, nrhs, nrg, order_b, sb)
 #undef QDD_VEC
   return hipGetLastError();
 }
@@ -663,7 +673,7 @@ static hipError_t launch_dhat_nr(const Geo& g, const DevOp<S>& op, FieldV<S> in,
       return launch_dhat_vec<S, NR>(g, op, in, tmp, out, nrhs, c, st, pass, ev);
   // streaming access to single-use data (bits 0, 1) and compressed links (bit 2)
   const int ntm = o32 && NR == 1 ? (c.xcd >> 2) & 7 : 0;
-  const int order = c.xcd & 3;
+  const int order = c.xcd & 3, order_b = order | ((c.xcd & 64) ? 4 : 0);
   const int rf = in.ss > 1;  // interleaved operands: rhs fastest across the lanes
 #define QDD_DHAT_V(KER, M, ...) \
   hipLaunchKernelGGL((KER<S, NR, true, NR == 1 ? M : 0>), grid, blk, 0, st, __VA_ARGS__)
@@ -681,7 +691,7 @@ static hipError_t launch_dhat_nr(const Geo& g, const DevOp<S>& op, FieldV<S> in,
   }
   if (pass & 1) QDD_DHAT_PASS(k_dhat_a, g, op.U, op.Ainv, in, tmp, nrhs, nrg, order, sb, rf)
   if (ev) (void)hipEventRecord(ev, st);
-  if (pass & 2) QDD_DHAT_PASS(k_dhat_b, g, op.U, op.A, in, tmp, out, nrhs, nrg, order, sb, rf)
+  if (pass & 2) QDD_DHAT_PASS(k_dhat_b, g, op.U, op.A, in, tmp, out, nrhs, nrg, order_b, sb, rf)
 #undef QDD_DHAT_PASS
 #undef QDD_DHAT_V
   return hipGetLastError();

@@ -24,7 +24,8 @@ struct LaunchCfg {
                     // site's own spinor and store of the output (data a pass touches once),
                     // + 16 compressed links (two rows read, the third rebuilt); Dhat with nr 2, 4:
                     // + 32 a lane loads its nr right-hand sides of a component in one word
-                    // (interleaved batches; the streaming and compression bits then apply too)
+                    // (interleaved batches; the streaming and compression bits then apply too);
+                    // Dhat (nr >= 1): + 64 pass B walks the tiles backwards
   int sb = 0;       // sites per block (0 = block); block/sb lane groups take further rhs
 };
 

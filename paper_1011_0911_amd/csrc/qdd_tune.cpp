@@ -88,6 +88,11 @@ extern "C" qdd_status qdd_autotune(qdd_ctx* x, int kernel, qdd_prec prec, int nr
       if (kernel == 0 && lane_groups <= nrhs && staged_lds_bytes(prec, sb) <= kStagedLdsMax)
         for (int xcd : {0, 1, 2, 3}) cand.push_back(LaunchCfg{block, 0, xcd, sb == block ? 0 : sb});
     }
+  if (kernel == 0) {  // the same shapes with pass B walking backwards
+    const size_t n = cand.size();
+    for (size_t k = 0; k < n; ++k)
+      if (cand[k].nr != 0) cand.push_back(LaunchCfg{cand[k].block, cand[k].nr, cand[k].xcd | 64, cand[k].sb});
+  }
   hipEvent_t e0, e1;
   HCK(x, hipEventCreate(&e0));
   HCK(x, hipEventCreate(&e1));
