@@ -217,6 +217,29 @@ def solve_section(learned_pairs, U=None):
                "plain_iters": r3["plain_fp64"]["iters"], "speedup": r3["speedup_vs_plain"],
                "dfl_build_s": {"mixed": r3.get("dfl_build_s"), "plain_fp64": r3.get("plain_dfl_build_s")},
                "qs_inverse_eq5": r3.get("qs_inverse"), "action_eq4": r3.get("action_eq4")}}
+    r2 = W.run_solve_workload(2, plain_rhs=1, log=log)
+    sec["workload2"] = {
+        "workload": "16^3x32, 12 rhs batched, FP32 SAP (4^4 blocks, nmr 4, ncy 5), 20 deflation vectors, FP64 "
+                    "outer FGCR", "mixed_s": r2["mixed"]["solve_s"], "mixed_iters": r2["mixed"]["iters"],
+        "mixed_true_res_max": r2["mixed"]["true_res_max"], "mixed_converged": r2["mixed"]["converged"],
+        "plain_fp64_s_per_rhs": r2["plain_fp64"]["solve_s_per_rhs"], "plain_iters": r2["plain_fp64"]["iters"],
+        "speedup": r2["speedup_vs_plain"], "dfl_build_s": r2.get("dfl_build_s"),
+        "note": "16^3x32 fits in the 256 MB Infinity Cache: cache-resident, not an HBM measurement"}
+    r4 = W.run_multi(4, log=log)
+    sec["workload4"] = {
+        "workload": "8^4, 16^4, 24^3x48, 32^3x64 x kappa {0.1350, 0.1355, 0.1357}, 4 rhs each, FP32 SAP, 20 "
+                    "deflation vectors (one build per lattice, shared across kappa), FP64 outer FGCR; systems on "
+                    "their own streams, launched from one process",
+        "systems": r4["systems"], "concurrent_s": r4["concurrent_s"], "sequential_s": r4["sequential_s"],
+        "concurrency_speedup": r4["concurrency_speedup"], "all_converged": r4["all_converged"],
+        "dfl_build_s": r4["dfl_build_s"],
+        "iters": {d["system"]: d["iters"] for d in r4["systems_detail"]},
+        "true_res_max": max(d["true_res_max"] for d in r4["systems_detail"])}
+    rb = W.run_block_solve(5, log=log)
+    sec["dd_block_solves"] = {
+        "workload": f"DD-HMC block inversions: 24^3x48, {rb['blocks']} Dirichlet blocks of {rb['block']}, "
+                    f"{rb['nrhs']} rhs, BiCGstab to {rb['tol']} per block, FP64, one launch",
+        **{k: rb[k] for k in ("kernel_ms", "iters_min", "iters_max", "res_max", "converged", "model_TBs")}}
     if learned_pairs > 0:
         r5 = W.run_learned(5, train_pairs=learned_pairs, log=log)
         sec["learned_vs_plain"] = {
@@ -246,7 +269,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the solve timings")
-    ap.add_argument("--learned-pairs", type=int, default=512,
+    ap.add_argument("--learned-pairs", type=int, default=4096,
                     help="training pairs of the learned-stage comparison (harvested from batched plain solves; "
                          "0 skips it)")
     args = ap.parse_args()

@@ -299,6 +299,44 @@ def run_multi(wid: int = 4, nkv: int = 8, log=print):
     return out
 
 
+def run_block_solve(wid: int = 5, bs=(12, 12, 6, 6), nrhs: int = 2, tol: float = 1e-10, U=None, log=print):
+    """Dirichlet block solves of the DD-HMC forces (BiCGstab on every block, one
+    launch) on the lattice and field of workload wid with blocks of extent bs
+    (the paper's 6^2 x 12^2 blocks of the 48 x 24^3 lattice), nrhs Gaussian
+    sources.  Model bytes per iteration and even site: two block Dhat at the
+    2-pass model (4416 B in FP64) plus 16 FP64 vector passes (192 B each); the
+    rate divides the iterations every block took by the GPU time of the launch.
+    Returns a dict."""
+    import torch
+
+    w = WORKLOADS[wid]
+    L = w["L"]
+    V = int(np.prod(L))
+    if U is None:
+        U = S.random_su3_links(L, w["eps"], S.gauge_seed(wid))
+    ctx = qdd.Context(L, qdd.default_config(max_nrhs=nrhs, blk_bs=bs))
+    ctx.set_gauge(torch.from_numpy(U))
+    ctx.set_params(w["kappa"], w["csw"])
+    eta = torch.from_numpy(np.stack([S.gaussian_field(V, S.source_seed(wid, 50 + r)) for r in range(nrhs)])).cuda()
+    ctx.block_solve(eta, tol=tol)  # first call also gathers links and clover into the block-major layout
+    torch.cuda.synchronize()
+    t0 = time.time()
+    _, it, res, info, st = ctx.block_solve(eta, tol=tol, check=False)
+    torch.cuda.synchronize()
+    wall = time.time() - t0
+    neb = V // 2 // info["nblk"] * nrhs
+    per_iter = 2 * 4416 + 16 * 192
+    model = float(it.clamp(min=0).sum()) * neb * per_iter
+    out = {"lattice": "x".join(map(str, L)), "block": "x".join(map(str, bs)), "blocks": info["nblk"] // nrhs,
+           "nrhs": nrhs, "tol": tol, "kernel_ms": info["t_ms"], "wall_s": wall, "iters_min": int(it.min()),
+           "iters_max": int(it.max()), "res_max": info["res_max"], "converged": info["converged"] == info["nblk"],
+           "model_bytes": model, "model_TBs": model / (info["t_ms"] * 1e-3) / 1e12, "status": st}
+    log(f"[blk] {out}")
+    del ctx
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_network(wid: int = 5, reps: int = 5, nb: int = 4, log=print):
     """Timing of the learned stage's kernels on the workload lattice: one
     forward pass of the network on a Gaussian field and one Adam training step
