@@ -368,7 +368,9 @@ def main():
                    "pass_a": {"ms": round(ms_a, 5), "TBs": round(ach_a, 4)},
                    "copy_reference_TBs": round(copy_tbs, 4), "copy_bytes": nb, "wall_s_timed": round(wall, 3),
                    "one_rhs": one_rhs, "mass_preconditioning": action},
-        "roofline": {"bound": "hbm", "kernel": "k_dhat_b (pass B)", "achieved": round(ach_b, 4),
+        "roofline": {"bound": "hbm", "kernel": ("k_dhat_vb" if launch[1] > 1 and launch[2] & 32 else
+                                                "k_dhat_staged" if launch[1] == 0 else "k_dhat_b") + " (pass B)",
+                     "achieved": round(ach_b, 4),
                      "peak": PEAK_HBM_TBS, "unit": "TB/s", "frac": round(ach_b / PEAK_HBM_TBS, 4),
                      "traffic": traffic, "bytes_per_launch": b_b * Vh, "ms_per_launch": round(ms_b, 5)},
         "cpu_baseline": None,

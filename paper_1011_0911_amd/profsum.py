@@ -83,10 +83,13 @@ def traffic(bench_json: str, fetch_dir: str, write_dir: str, out_path: str, cmd:
     launch = [ln["block"], ln["nr"], ln["xcd"], ln["sb"]]
     copy_bytes = cfg["copy_bytes"]
     tname = {0: "double", 1: "float", 2: "__half"}[prec]
-    # pass-B kernel of the launch shape: staged variant (pass, addressing), or the
+    # pass-B kernel of the launch shape: staged variant (pass, addressing), the
+    # rhs-vector kernel (rhs per lane, streaming / compression bits), or the
     # per-lane kernel (rhs per lane, 32-bit addressing, streaming-access bits)
     if ln["nr"] == 0:
         kb = f"qdd::k_dhat_staged<{tname}, 1, true>"
+    elif ln["nr"] > 1 and ln["xcd"] & 32:  # rhs-vector kernels
+        kb = f"qdd::k_dhat_vb<{tname}, {ln['nr']}, {(ln['xcd'] >> 2) & 7}>"
     else:
         ntm = (ln["xcd"] >> 2) & 7 if ln["nr"] == 1 else 0
         kb = f"qdd::k_dhat_b<{tname}, {ln['nr']}, true, {ntm}>"
