@@ -187,13 +187,15 @@ qdd_status qdd_dw_masses(qdd_ctx* ctx, qdd_prec prec, int nrhs, const double* ka
 
 /* psi = M_sap eta: ncy cycles of the two-colour Schwarz procedure with nmr
  * minimal-residual steps on the even-odd block operator of every block, in the
- * configured SAP precision.  Canonical complex128 full fields. */
+ * configured SAP precision (the Schwarz preconditioner of the solver the paper
+ * uses for its inversions, Sect. 3).  Canonical complex128 full fields. */
 qdd_status qdd_sap(qdd_ctx* ctx, int nrhs, const double* eta, double* psi);
 
-/* Local deflation subspace: init holds dfl_Ns canonical full fields (the random
- * start vectors, supplied by the caller); dfl_nit rounds of SAP inverse
- * iteration, block orthonormalisation (FP64) and the little Dirac operator
- * (self + 8 face couplings per block, FP64). */
+/* Local deflation subspace of the solver's deflation (Sect. 3; its cost is
+ * counted in the solve times of Sect. 4, Table 1): init holds dfl_Ns canonical
+ * full fields (the random start vectors, supplied by the caller); dfl_nit rounds
+ * of SAP inverse iteration, block orthonormalisation (FP64) and the little Dirac
+ * operator (self + 8 face couplings per block, FP64). */
 qdd_status qdd_dfl_build(qdd_ctx* ctx, const double* init);
 
 /* Inspection of the deflation data (device pointers, either may be NULL): the
@@ -246,9 +248,10 @@ qdd_status qdd_dfl_refresh(qdd_ctx* ctx);
 /* Numbers of subspace builds and refreshes (automatic ones included) of ctx. */
 qdd_status qdd_dfl_stats(const qdd_ctx* ctx, int* builds, int* refreshes);
 /* Solves nsys independent systems (lattices, masses and batch sizes may all
- * differ) concurrently: each context (with its own stream) runs its solve on a
- * host thread of its own, so the work of all systems is in flight at once and
- * each stops at its own convergence.  eta[s], psi[s]: canonical fields of
+ * differ) concurrently, each as qdd_solve does (the solver of Sect. 3-4; several
+ * masses share one deflation subspace through qdd_dfl_share): each context (with
+ * its own stream) runs its solve on a host thread of its own, so the work of all
+ * systems is in flight at once and each stops at its own convergence.  eta[s], psi[s]: canonical fields of
  * system s; info[s]: nrhs[s] entries or NULL.  Returns the first failure. */
 qdd_status qdd_solve_multi(qdd_ctx* const* ctxs, int nsys, const int* nrhs, const double* const* eta,
                            double* const* psi, qdd_solve_info* const* info);
