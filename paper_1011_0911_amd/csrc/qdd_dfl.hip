@@ -51,6 +51,15 @@ __device__ inline int block_nbr(const DflGeo& d, int b, int f) {
   return ((bc[0] * d.nb[1] + bc[1]) * d.nb[2] + bc[2]) * d.nb[3] + bc[3];
 }
 
+// deflation block of a workgroup: hardware workgroup ids go round-robin over the
+// 8 XCDs, so every XCD is given a contiguous range of blocks.  With 4^4 blocks a
+// block row holds 2 sites of a parity, and the blocks next to each other in x3
+// share the cache lines of the parity-split fields: walked on one XCD they are
+// fetched once into its L2 instead of once per XCD.
+__device__ inline int xcd_block(int bid, int nblk) {
+  return (nblk & 7) == 0 ? (bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
+}
+
 template <class T>
 __device__ inline T wave_sum(T v) {
 #pragma unroll
@@ -87,10 +96,11 @@ __global__ void __launch_bounds__(1024) k_block_orth(Geo g, DflGeo d, double2* W
   const int nsb = d.bs[0] * d.bs[1] * d.bs[2] * d.bs[3];
   const int s = threadIdx.x;
   const bool on = s < nsb;
+  const int blk = xcd_block(blockIdx.x, d.nblk);
   int64_t off = 0;
   if (on) {
     int x[4], p, i;
-    block_site(g, d, blockIdx.x, s, x, p, i);
+    block_site(g, d, blk, s, x, p, i);
     off = (int64_t)p * 12 * g.Vh + i;
   }
   for (int l = 0; l < Ns; ++l) {
@@ -205,7 +215,7 @@ __global__ void __launch_bounds__(256) k_block_dots(Geo g, DflGeo d, const EX* X
   double2* xs = lds;                   // [nx][cs][12]
   double2* ys = lds + nx * cs * 12;    // [ny][cs][12]
   const int nsb = d.bs[0] * d.bs[1] * d.bs[2] * d.bs[3];
-  const int np = nx * ny;
+  const int np = nx * ny, blk = xcd_block(blockIdx.x, d.nblk);
   cx<double> acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
   for (int s0 = 0; s0 < nsb; s0 += cs) {
     int nsc = min(cs, nsb - s0);
@@ -214,7 +224,7 @@ __global__ void __launch_bounds__(256) k_block_dots(Geo g, DflGeo d, const EX* X
       int c = e % 12, rest = e / 12;
       int s = rest % nsc, v = rest / nsc;
       int x[4], p, i;
-      block_site(g, d, blockIdx.x, s0 + s, x, p, i);
+      block_site(g, d, blk, s0 + s, x, p, i);
       int64_t o = (int64_t)p * 12 * g.Vh + (int64_t)c * g.Vh + i;
       if (v < nx) {
         cx<double> z = cvt_any(X[v * xvs + o]);
@@ -245,7 +255,7 @@ __global__ void __launch_bounds__(256) k_block_dots(Geo g, DflGeo d, const EX* X
     int pr = threadIdx.x + q * blockDim.x;
     if (pr < np) {
       int kx = pr / ny, ky = pr % ny;
-      out[(int64_t)blockIdx.x * bso + (int64_t)kx * ldo + (int64_t)ky * kys] = make_double2(acc[q].re, acc[q].im);
+      out[(int64_t)blk * bso + (int64_t)kx * ldo + (int64_t)ky * kys] = make_double2(acc[q].re, acc[q].im);
     }
   }
 }

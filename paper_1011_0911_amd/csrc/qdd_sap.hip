@@ -61,6 +61,15 @@ struct Exch {
 // after the other; hops exchange projected half-spinors (the forward
 // projection, and the U^dag-transported backward one) through LDS, so every lane
 // multiplies only with its own forward links.
+// block of one colour taken by a workgroup: hardware workgroup ids go round-robin
+// over the 8 XCDs, so every XCD gets a contiguous range of blocks.  With 4^4
+// blocks a block row holds 2 sites of a parity, and the blocks of one x3 row
+// share the cache lines of the parity-split fields and links: walked on one XCD
+// they are fetched into its L2 once instead of once per XCD.
+__device__ inline int sap_xcd_block(int id, int nbc) {
+  return (nbc & 7) == 0 ? (id & 7) * (nbc >> 3) + (id >> 3) : id;
+}
+
 template <class S, class P, int DR>
 __global__ void __launch_bounds__(256) k_sap_half(SapArgs<S, P> a) {
   typedef typename St<S>::T T;
@@ -73,10 +82,10 @@ __global__ void __launch_bounds__(256) k_sap_half(SapArgs<S, P> a) {
   const int t = threadIdx.x;
   const int q = t >= nsh;  // parity of this lane's site
   const int j = t - q * nsh;
-  // this block: the blockIdx.x-th block of colour a.col
+  // this block: the sap_xcd_block(blockIdx.x)-th block of colour a.col
   int bc[4];
   {
-    int bl = 2 * blockIdx.x;
+    int bl = 2 * sap_xcd_block(blockIdx.x, gridDim.x);
     int nbh3 = a.nb[3];
     bc[3] = bl % nbh3;
     int rr = bl / nbh3;
@@ -378,10 +387,10 @@ __global__ void __launch_bounds__(kSapMaxHalf, 2) k_sap_rhs(SapArgs<S, P> a) {
   int bi, r;
   {
     const int id = blockIdx.x, nbc = gridDim.x / a.nrhs;
-    if ((nbc & 7) == 0) {
+    if ((nbc & 7) == 0) {  // every XCD a contiguous range of blocks (see sap_xcd_block)
       const int rest = id >> 3;
       r = rest % a.nrhs;
-      bi = (rest / a.nrhs) * 8 + (id & 7);
+      bi = (id & 7) * (nbc >> 3) + rest / a.nrhs;
     } else {
       r = id % a.nrhs;
       bi = id / a.nrhs;
@@ -649,10 +658,10 @@ __global__ void __launch_bounds__(R * kSapMaxHalf, CL ? 1 : 2) k_sap_lds(SapArgs
   int bi, rg;
   {
     const int id = blockIdx.x, nbc = gridDim.x / nrg;
-    if ((nbc & 7) == 0) {
+    if ((nbc & 7) == 0) {  // every XCD a contiguous range of blocks (see sap_xcd_block)
       const int rest = id >> 3;
       rg = rest % nrg;
-      bi = (rest / nrg) * 8 + (id & 7);
+      bi = (id & 7) * (nbc >> 3) + rest / nrg;
     } else {
       rg = id % nrg;
       bi = id / nrg;
@@ -940,10 +949,10 @@ __global__ void __launch_bounds__(kSapMaxHalf, sizeof(S) == 8 ? 1 : 2) k_sap_pai
   __shared__ cx<T> ro_l[12][kSapMaxHalf], xs_l[12][kSapMaxHalf];
   const Geo& g = a.g;
   const int j = threadIdx.x;
-  // this block: the blockIdx.x-th block of colour a.col
+  // this block: the sap_xcd_block(blockIdx.x)-th block of colour a.col
   int bc[4];
   {
-    int bl = 2 * blockIdx.x;
+    int bl = 2 * sap_xcd_block(blockIdx.x, gridDim.x);
     bc[3] = bl % a.nb[3];
     int rr = bl / a.nb[3];
     bc[2] = rr % a.nb[2];
