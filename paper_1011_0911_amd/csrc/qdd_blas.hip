@@ -2,8 +2,8 @@
 // contiguous array of n complex numbers (one right-hand side of an internal
 // field); several right-hand sides sit at a fixed stride.  Reductions are
 // two-pass and deterministic: per-block partial sums in a fixed order, then one
-// thread per result sums the partials in block order (no floating-point atomics),
-// so repeated runs give bitwise identical results.
+// wavefront per result sums the partials in a fixed order (no floating-point
+// atomics), so repeated runs give bitwise identical results.
 #include "qdd_kernels.h"
 #include "qdd_blas.h"
 
@@ -69,16 +69,21 @@ __global__ void __launch_bounds__(256) k_dots(const E* x, int64_t lstride, int64
   }
 }
 
-__global__ void k_dots_final(const double2* part, int nb, int total, double2* out) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
+// one wavefront per result: lane j sums the partials j, j+64, ... in order, then a
+// fixed shuffle tree adds the 64 lane sums (the same order on every run)
+__global__ void __launch_bounds__(256) k_dots_final(const double2* part, int nb, int total, double2* out) {
+  int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (t >= total) return;
+  const double2* p = part + (int64_t)t * nb;
   double re = 0, im = 0;
-  for (int b = 0; b < nb; ++b) {
-    double2 v = part[(int64_t)t * nb + b];
+  for (int b = lane; b < nb; b += 64) {
+    double2 v = p[b];
     re += v.x;
     im += v.y;
   }
-  out[t] = make_double2(re, im);
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if (lane == 0) out[t] = make_double2(re, im);
 }
 
 template <class E>
@@ -94,7 +99,7 @@ hipError_t launch_dots(const E* x, int64_t lstride, int64_t xrs, int m, const do
   else if (m <= 32) hipLaunchKernelGGL((k_dots<E, 32>), grid, dim3(256), 0, st, x, lstride, xrs, m, y, yrs, n, part);
   else return hipErrorInvalidValue;
   int total = nrhs * m;
-  hipLaunchKernelGGL(k_dots_final, dim3((total + 63) / 64), dim3(64), 0, st, part, nb, total, out);
+  hipLaunchKernelGGL(k_dots_final, dim3((total + 3) / 4), dim3(256), 0, st, part, nb, total, out);
   return hipGetLastError();
 }
 

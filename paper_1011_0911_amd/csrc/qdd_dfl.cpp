@@ -141,14 +141,16 @@ static qdd_status dfl_build_from_W(qdd_ctx* x, int nit) {
       HCK(x, launch_norm_finish(rn2, bn, binv, nb, st));
       HCK(x, launch_axpby(w, vs, w, vs, binv, nullptr, vs, nb, nullptr, st));
     }
-  HCK(x, launch_block_orth(G, d, W, vs, Ns, st));
-  // little operator: self (hops inside blocks) and the 8 face couplings
-  double2* F = x->ptr<double2>(lo.dfl_init);
+  // block orthonormalisation (the little-operator storage is its work space)
   double2* Am = x->ptr<double2>(lo.dfl_A);
+  HCK(x, launch_block_orth(G, d, W, vs, Ns, Am, st));
+  // little operator: self (hops inside blocks) and the 8 face couplings; a face
+  // term is non-zero only on that face of every block
+  double2* F = x->ptr<double2>(lo.dfl_init);
   for (int mode = 0; mode < 9; ++mode) {
     HCK(x, launch_dfl_hops(G, d, x->op<double>(), W, vs, F, Ns, mode, st));
     HCK(x, launch_block_dots<double2, double2>(G, d, W, vs, Ns, F, vs, Ns, Am + (int64_t)mode * Ns * Ns,
-                                               (int64_t)9 * Ns * Ns, Ns, 1, st));
+                                               (int64_t)9 * Ns * Ns, Ns, 1, st, mode));
   }
   if (!dfl_fp64(x)) HCK(x, launch_convert(W, x->ptr<float2>(lo.dfl_W32), (int64_t)Ns * vs, st));
   HCK(x, hipStreamSynchronize(st));

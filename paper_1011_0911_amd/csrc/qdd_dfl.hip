@@ -260,6 +260,246 @@ __global__ void __launch_bounds__(256) k_block_dots(Geo g, DflGeo d, const EX* X
   }
 }
 
+// ---------------------------------------------------------------- block products on the matrix cores
+// C_b = X_b^dag Y_b for every block b as one real GEMM on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64).  Over k' = (site, component, re/im) the rows of the
+// left operand are the x fields [Re X | Im X], the columns of the right operand
+// are (Re Y, Im Y) for Re C and (Im Y, -Re Y) for Im C:
+//   Re C = sum (Xr Yr + Xi Yi),   Im C = sum (Xr Yi - Xi Yr).
+// The block is walked one x3 row at a time: the row's sites of either parity are
+// bs3/2 consecutive entries of that parity's array, so one staging unit (field,
+// parity, component) is a contiguous run.  Any fixed order of k' serves, as long
+// as X and Y use the same one.  The four wavefronts take a quarter of the k'
+// steps of every row each, and their partial tiles are added in wavefront order,
+// so the result is deterministic.  Face products (face = 1 + 2 mu + dir, mu < 3)
+// visit only the block rows on that face, where the face fields are non-zero.
+typedef double dv4 __attribute__((ext_vector_type(4)));
+constexpr int kMmMaxT = 8;  // 16 x 16 output tiles per workgroup
+
+struct MmShape {
+  int MT, NT;   // row tiles (x fields), column tiles (2 ny real columns)
+  int rows;     // staged LDS rows: 16 MT x-rows (+ ny y-rows) + one zero row
+  int ybase;    // first y-row (0 when Y is X)
+  int ld;       // LDS row stride in doubles
+};
+
+__host__ __device__ inline MmShape mm_shape(int nx, int ny, int sym, int h) {
+  MmShape m;
+  m.MT = (nx + 15) / 16;
+  m.NT = (2 * ny + 15) / 16;
+  m.ybase = sym ? 0 : 16 * m.MT;
+  m.rows = 16 * m.MT + (sym ? 0 : ny) + 1;
+  // 48 h doubles of one row plus 4: 8 x odd words between rows, so the 16 rows
+  // of an operand read fall on distinct bank groups
+  m.ld = 48 * h + 4;
+  return m;
+}
+
+template <class EX, class EY>
+__global__ void __launch_bounds__(256) k_block_mm(Geo g, DflGeo d, const EX* X, int64_t xvs, int nx, const EY* Y,
+                                                  int64_t yvs, int ny, int sym, double2* out, int64_t bso,
+                                                  int64_t ldo, int64_t kys, int face) {
+  extern __shared__ double sm[];
+  const int h = d.bs[3] >> 1;
+  const MmShape m = mm_shape(nx, ny, sym, h);
+  const int T = m.MT * m.NT, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int blk = xcd_block(blockIdx.x, d.nblk);
+  int bc[4];
+  {
+    int r = blk;
+    bc[3] = r % d.nb[3];
+    r /= d.nb[3];
+    bc[2] = r % d.nb[2];
+    r /= d.nb[2];
+    bc[1] = r % d.nb[1];
+    bc[0] = r / d.nb[1];
+  }
+  // rows of the walk: all (y0, y1, y2), or those on the face
+  int ext[3] = {d.bs[0], d.bs[1], d.bs[2]}, fmu = -1, fpos = 0;
+  if (face > 0 && ((face - 1) >> 1) < 3) {
+    fmu = (face - 1) >> 1;
+    fpos = ((face - 1) & 1) == 0 ? d.bs[fmu] - 1 : 0;
+    ext[fmu] = 1;
+  }
+  const int nrow = ext[0] * ext[1] * ext[2];
+  // zero the padding rows (x rows nx..16MT-1 and the last row), never staged
+  for (int e = threadIdx.x; e < (16 * m.MT - nx + 1) * m.ld; e += blockDim.x) {
+    const int r = e / m.ld, c = e - r * m.ld;
+    sm[(r < 16 * m.MT - nx ? nx + r : m.rows - 1) * m.ld + c] = 0.0;
+  }
+  // per-lane operand addresses of every tile
+  int acol[kMmMaxT], bcol[kMmMaxT];
+  double bsg[kMmMaxT];
+#pragma unroll
+  for (int t = 0; t < kMmMaxT; ++t) {
+    const int mt = t < T ? t / m.NT : 0, nt = t < T ? t - (t / m.NT) * m.NT : 0;
+    acol[t] = (16 * mt + (lane & 15)) * m.ld + (lane >> 4);
+    const int j = 16 * nt + (lane & 15), kq = lane >> 4;
+    if (j < ny) {
+      bcol[t] = (m.ybase + j) * m.ld + kq;
+      bsg[t] = 1.0;
+    } else if (j < 2 * ny) {
+      bcol[t] = (m.ybase + j - ny) * m.ld + (kq ^ 1);
+      bsg[t] = (kq & 1) ? -1.0 : 1.0;
+    } else {
+      bcol[t] = (m.rows - 1) * m.ld + kq;
+      bsg[t] = 1.0;
+    }
+  }
+  dv4 acc[kMmMaxT];
+#pragma unroll
+  for (int t = 0; t < kMmMaxT; ++t) acc[t] = dv4{0.0, 0.0, 0.0, 0.0};
+  const int nf = sym ? nx : nx + ny, units = nf * 24;
+  const int spw = 3 * h;  // k' steps of 4 per wavefront and row
+  for (int q = 0; q < nrow; ++q) {
+    int y[3];
+    y[2] = q % ext[2];
+    y[1] = (q / ext[2]) % ext[1];
+    y[0] = q / (ext[2] * ext[1]);
+    if (fmu >= 0) y[fmu] = fpos;
+    const int row = ((bc[0] * d.bs[0] + y[0]) * g.L[1] + bc[1] * d.bs[1] + y[1]) * g.L[2] + bc[2] * d.bs[2] + y[2];
+    const int i0 = row * g.Lh3 + bc[3] * h;
+    __syncthreads();  // the previous row's operands are consumed
+    for (int e = threadIdx.x; e < units; e += blockDim.x) {
+      const int c = e % 12, t = e / 12, p = t & 1, v = t >> 1;
+      const int64_t o = (int64_t)p * 12 * g.Vh + (int64_t)c * g.Vh + i0;
+      double* dst = sm + (v < nx ? v : m.ybase + v - nx) * m.ld + 2 * (p * 12 + c) * h;
+      for (int k = 0; k < h; ++k) {
+        const cx<double> z = v < nx ? cvt_any(X[v * xvs + o + k]) : cvt_any(Y[(v - nx) * yvs + o + k]);
+        dst[2 * k] = z.re;
+        dst[2 * k + 1] = z.im;
+      }
+    }
+    __syncthreads();
+    for (int ks = w * spw; ks < (w + 1) * spw; ++ks) {
+#pragma unroll
+      for (int t = 0; t < kMmMaxT; ++t) {
+        if (t < T) {
+          const double a = sm[acol[t] + 4 * ks], b = bsg[t] * sm[bcol[t] + 4 * ks];
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // partial tiles of the four wavefronts, added in wavefront order into P
+  double* ex = sm;                       // [4][256]
+  double* P = sm + 1024;                 // [16 MT][16 NT]
+  const int pn = 16 * m.NT;
+#pragma unroll
+  for (int t = 0; t < kMmMaxT; ++t) {
+    if (t < T) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ex[w * 256 + lane * 4 + r] = acc[t][r];
+      __syncthreads();
+      const int e = threadIdx.x, l = e >> 2, r = e & 3, mt = t / m.NT, nt = t - mt * m.NT;
+      // FP64 16x16x4 output: register r of lane l holds row 4 r + l / 16, column l mod 16
+      P[(16 * mt + 4 * r + (l >> 4)) * pn + 16 * nt + (l & 15)] = ex[e] + ex[256 + e] + ex[512 + e] + ex[768 + e];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nx * ny; e += blockDim.x) {
+    const int i = e / ny, j = e - i * ny;
+    out[(int64_t)blk * bso + (int64_t)i * ldo + (int64_t)j * kys] = make_double2(P[i * pn + j], P[i * pn + ny + j]);
+  }
+}
+
+// ---------------------------------------------------------------- block orthonormalisation (CholeskyQR)
+// For every block the Gram matrix G = W_b^dag W_b (from k_block_mm) is factored
+// as G = R^dag R (R upper triangular, positive diagonal) and R^{-1} formed; then
+// W_b <- W_b R^{-1} gives the same orthonormal fields as Gram-Schmidt in field
+// order (the QR factorisation with positive diagonal is unique).  Two rounds
+// make the result orthonormal to working precision for block condition numbers
+// up to ~1e7.  A non-positive pivot (fields dependent on the block) drops that
+// field on the block (its column of R^{-1} is zero).
+// One wavefront per block; G and R in LDS (Ns <= 32).
+__global__ void __launch_bounds__(64) k_block_chol(const double2* G, int Ns, double2* Rinv) {
+  __shared__ double2 R[32 * 33], Xl[32 * 33];
+  const int b = blockIdx.x, lane = threadIdx.x, ldr = 33;
+  const double2* Gb = G + (int64_t)b * Ns * Ns;
+  for (int e = lane; e < Ns * Ns; e += 64) R[(e / Ns) * ldr + e % Ns] = Gb[e];
+  __syncthreads();
+  for (int j = 0; j < Ns; ++j) {
+    const double piv = R[j * ldr + j].x;
+    const double dj = piv > 0 ? sqrt(piv) : 0.0, inv = piv > 0 ? 1.0 / dj : 0.0;
+    __syncthreads();
+    // row j of R: R[j][l] = A[j][l] / d for l >= j
+    for (int l = j + lane; l < Ns; l += 64) {
+      const double2 a = R[j * ldr + l];
+      R[j * ldr + l] = l == j ? make_double2(dj, 0.0) : make_double2(a.x * inv, a.y * inv);
+    }
+    __syncthreads();
+    // trailing update A[i][l] -= conj(R[j][i]) R[j][l], j < i <= l
+    const int n = Ns - j - 1;
+    for (int e = lane; e < n * n; e += 64) {
+      const int i = j + 1 + e / n, l = j + 1 + e % n;
+      if (l < i) continue;
+      const double2 ri = R[j * ldr + i], rl = R[j * ldr + l];
+      double2 a = R[i * ldr + l];
+      a.x -= ri.x * rl.x + ri.y * rl.y;
+      a.y -= ri.x * rl.y - ri.y * rl.x;
+      R[i * ldr + l] = a;
+    }
+    __syncthreads();
+  }
+  // R^{-1} column by column (lane l, column in LDS): X[l][l] = 1 / R[l][l],
+  // X[i][l] = -(sum_{k=i+1..l} R[i][k] X[k][l]) / R[i][i]
+  double2* Xb = Rinv + (int64_t)b * Ns * Ns;
+  for (int l = lane; l < Ns; l += 64) {
+    for (int i = 0; i < Ns; ++i) Xl[i * ldr + l] = make_double2(0.0, 0.0);
+    const double dl = R[l * ldr + l].x;
+    if (dl > 0) {
+      Xl[l * ldr + l] = make_double2(1.0 / dl, 0.0);
+      for (int i = l - 1; i >= 0; --i) {
+        double sr = 0, si = 0;
+        for (int k = i + 1; k <= l; ++k) {
+          const double2 r = R[i * ldr + k], x = Xl[k * ldr + l];
+          sr += r.x * x.x - r.y * x.y;
+          si += r.x * x.y + r.y * x.x;
+        }
+        const double di = R[i * ldr + i].x;
+        Xl[i * ldr + l] = di > 0 ? make_double2(-sr / di, -si / di) : make_double2(0.0, 0.0);
+      }
+    }
+    for (int i = 0; i < Ns; ++i) Xb[i * Ns + l] = Xl[i * ldr + l];
+  }
+}
+
+// W_b <- W_b R^{-1} on every block: out_l = sum_{k<=l} W_k X[k][l] at every
+// (site, component); one workgroup per block, one lane per site, X in LDS.
+template <int NSM>
+__global__ void __launch_bounds__(256) k_block_rmul(Geo g, DflGeo d, double2* W, int64_t vs, int Ns,
+                                                    const double2* Rinv) {
+  __shared__ double2 Xs[NSM * NSM];
+  const int blk = xcd_block(blockIdx.x, d.nblk);
+  for (int e = threadIdx.x; e < Ns * Ns; e += blockDim.x) Xs[e] = Rinv[(int64_t)blk * Ns * Ns + e];
+  __syncthreads();
+  const int nsb = d.bs[0] * d.bs[1] * d.bs[2] * d.bs[3];
+  for (int s = threadIdx.x; s < nsb; s += blockDim.x) {
+    int x[4], p, i;
+    block_site(g, d, blk, s, x, p, i);
+    double2* base = W + (int64_t)p * 12 * g.Vh + i;
+    for (int c = 0; c < 12; ++c) {
+      cx<double> v[NSM];
+#pragma unroll
+      for (int k = 0; k < NSM; ++k)
+        if (k < Ns) v[k] = cvt_any(base[k * vs + (int64_t)c * g.Vh]);
+#pragma unroll
+      for (int l = NSM - 1; l >= 0; --l) {
+        if (l < Ns) {
+          cx<double> a{0.0, 0.0};
+#pragma unroll
+          for (int k = 0; k <= l; ++k) a = fma_c(v[k], cvt_any(Xs[k * Ns + l]), a);
+          v[l] = a;  // v[k], k < l, still hold the input fields
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NSM; ++k)
+        if (k < Ns) base[k * vs + (int64_t)c * g.Vh] = make_double2(v[k].re, v[k].im);
+    }
+  }
+}
+
 // out_r(x) = sum_k W_k(x) c[r][b(x)][k] (+ optional add of out), for nrhs rhs;
 // c: [rhs][nblk][Ns] FP64; W fields at stride wvs; out fields at stride ovs
 template <class EW, class EO>
@@ -323,9 +563,90 @@ __global__ void __launch_bounds__(256) k_coarse_apply(DflGeo d, const double2* A
   out[r * nc + (int64_t)b * Ns + k] = make_double2(acc.re, acc.im);
 }
 
+// The same apply with one wavefront per block: for each of the 9 couplings the
+// Ns x Ns block of A (rows padded to Ns + 1 so that lanes on consecutive rows
+// read distinct LDS banks) and the neighbour's coarse vectors of all right-hand
+// sides are staged in LDS with coalesced loads; each lane then accumulates one
+// row k for 4 right-hand sides.  The sums run in the same order as above.
+template <int NG>
+__global__ void __launch_bounds__(64) k_coarse_apply_lds(DflGeo d, const double2* Am, int Ns, const double2* in,
+                                                         double2* out, int64_t nc, int nrhs) {
+  extern __shared__ double2 cl[];
+  const int lda = Ns + 1;
+  double2* As = cl;             // [Ns][Ns + 1]
+  double2* Is = cl + Ns * lda;  // [nrhs][Ns]
+  const int b = xcd_block(blockIdx.x, d.nblk), lane = threadIdx.x;
+  const int ngr = Ns * ((nrhs + 3) >> 2);
+  cx<double> acc[NG][4];
+#pragma unroll
+  for (int j = 0; j < NG; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[j][i] = {0.0, 0.0};
+  for (int f = 0; f < 9; ++f) {
+    const int bb = f == 0 ? b : block_nbr(d, b, f);
+    const double2* Ab = Am + ((int64_t)b * 9 + f) * Ns * Ns;
+    __syncthreads();  // the previous coupling's operands are consumed
+    for (int e = lane; e < Ns * Ns; e += 64) {
+      const int k = e / Ns;
+      As[k * lda + e - k * Ns] = Ab[e];
+    }
+    for (int e = lane; e < nrhs * Ns; e += 64) {
+      const int r = e / Ns;
+      Is[e] = in[r * nc + (int64_t)bb * Ns + e - r * Ns];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+      const int gi = lane + 64 * j;
+      if (gi < ngr) {
+        const int k = gi % Ns, r0 = 4 * (gi / Ns);
+        for (int l = 0; l < Ns; ++l) {
+          const double2 a = As[k * lda + l];
+          const cx<double> av{a.x, a.y};
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (r0 + i < nrhs) acc[j][i] = fma_c(av, cvt_any(Is[(r0 + i) * Ns + l]), acc[j][i]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NG; ++j) {
+    const int gi = lane + 64 * j;
+    if (gi < ngr) {
+      const int k = gi % Ns, r0 = 4 * (gi / Ns);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (r0 + i < nrhs) out[(r0 + i) * nc + (int64_t)b * Ns + k] = make_double2(acc[j][i].re, acc[j][i].im);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launchers
-hipError_t launch_block_orth(const Geo& g, const DflGeo& d, double2* W, int64_t vs, int Ns, hipStream_t st) {
+template <class EX, class EY>
+hipError_t launch_block_mm(const Geo& g, const DflGeo& d, const EX* X, int64_t xvs, int nx, const EY* Y, int64_t yvs,
+                           int ny, int sym, double2* out, int64_t bso, int64_t ldo, int64_t kys, int face,
+                           hipStream_t st);
+
+hipError_t launch_block_orth(const Geo& g, const DflGeo& d, double2* W, int64_t vs, int Ns, double2* work,
+                             hipStream_t st) {
   int nsb = d.bs[0] * d.bs[1] * d.bs[2] * d.bs[3];
+  if (work && Ns <= 32 && block_mm_fits(Ns, Ns, 1, d)) {
+    // CholeskyQR, two rounds: Gram on the matrix cores, factor and R^{-1} per
+    // block, W <- W R^{-1}
+    double2 *G = work, *Ri = work + (int64_t)d.nblk * Ns * Ns;
+    for (int round = 0; round < 2; ++round) {
+      hipError_t e = launch_block_mm<double2, double2>(g, d, W, vs, Ns, W, vs, Ns, 1, G, (int64_t)Ns * Ns, Ns, 1, 0,
+                                                       st);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_block_chol, dim3(d.nblk), dim3(64), 0, st, G, Ns, Ri);
+      if (Ns <= 8) hipLaunchKernelGGL((k_block_rmul<8>), dim3(d.nblk), dim3(256), 0, st, g, d, W, vs, Ns, Ri);
+      else if (Ns <= 16) hipLaunchKernelGGL((k_block_rmul<16>), dim3(d.nblk), dim3(256), 0, st, g, d, W, vs, Ns, Ri);
+      else if (Ns <= 24) hipLaunchKernelGGL((k_block_rmul<24>), dim3(d.nblk), dim3(256), 0, st, g, d, W, vs, Ns, Ri);
+      else hipLaunchKernelGGL((k_block_rmul<32>), dim3(d.nblk), dim3(256), 0, st, g, d, W, vs, Ns, Ri);
+    }
+    return hipGetLastError();
+  }
   if (nsb > 1024) return hipErrorInvalidValue;
   int thr = ((nsb + 63) / 64) * 64;  // one lane per site
   hipLaunchKernelGGL(k_block_orth, dim3(d.nblk), dim3(thr), 0, st, g, d, W, vs, Ns);
@@ -346,17 +667,58 @@ hipError_t launch_dfl_hops(const Geo& g, const DflGeo& d, const DevOp<double>& o
   return hipGetLastError();
 }
 
+// LDS bytes of the matrix-core block product (0 if it does not apply)
+static size_t block_mm_lds(int nx, int ny, int sym, const DflGeo& d) {
+  const int h = d.bs[3] / 2;
+  const MmShape m = mm_shape(nx, ny, sym, h);
+  if (m.MT * m.NT > kMmMaxT || h < 1 || (d.bs[3] & 1)) return 0;  // rows of even length only
+  const size_t stage = (size_t)m.rows * m.ld, red = 1024 + (size_t)256 * m.MT * m.NT;
+  const size_t bytes = 8 * (stage > red ? stage : red);
+  return bytes <= 96 * 1024 ? bytes : 0;
+}
+bool block_mm_fits(int nx, int ny, int sym, const DflGeo& d) { return block_mm_lds(nx, ny, sym, d) != 0; }
+
+template <class EX, class EY>
+hipError_t launch_block_mm(const Geo& g, const DflGeo& d, const EX* X, int64_t xvs, int nx, const EY* Y, int64_t yvs,
+                           int ny, int sym, double2* out, int64_t bso, int64_t ldo, int64_t kys, int face,
+                           hipStream_t st) {
+  const size_t lds = block_mm_lds(nx, ny, sym, d);
+  if (!lds) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_block_mm<EX, EY>), dim3(d.nblk), dim3(256), lds, st, g, d, X, xvs, nx, Y, yvs, ny, sym, out,
+                     bso, ldo, kys, face);
+  return hipGetLastError();
+}
+
+// The matrix-core product takes at most kMmMaxT output tiles and the VALU one
+// 1024 field pairs, so wider products run in chunks of Y fields.
 template <class EX, class EY>
 hipError_t launch_block_dots(const Geo& g, const DflGeo& d, const EX* X, int64_t xvs, int nx, const EY* Y,
                              int64_t yvs, int ny, double2* out, int64_t bso, int64_t ldo, int64_t kys,
-                             hipStream_t st) {
-  if (nx * ny > 1024) return hipErrorInvalidValue;
-  int cs = (int)(65536 / ((size_t)(nx + ny) * 12 * sizeof(double2)));
-  if (cs < 1) return hipErrorInvalidValue;
-  cs = cs > 16 ? 16 : cs;
-  size_t lds = (size_t)(nx + ny) * cs * 12 * sizeof(double2);
-  hipLaunchKernelGGL((k_block_dots<EX, EY>), dim3(d.nblk), dim3(256), lds, st, g, d, X, xvs, nx, Y, yvs, ny, out,
-                     bso, ldo, kys, cs);
+                             hipStream_t st, int face) {
+  if (nx < 1 || ny < 1) return hipErrorInvalidValue;
+  const bool mm = block_mm_fits(nx, 1, 0, d);
+  int nyc = ny;
+  if (mm)
+    while (!block_mm_fits(nx, nyc, 0, d)) nyc = (nyc + 1) / 2;
+  else
+    nyc = std::min(ny, std::max(1, 1024 / nx));
+  for (int j0 = 0; j0 < ny; j0 += nyc) {
+    const int n = std::min(nyc, ny - j0);
+    const EY* Yc = Y + j0 * yvs;
+    double2* oc = out + j0 * kys;
+    if (mm) {
+      hipError_t e = launch_block_mm<EX, EY>(g, d, X, xvs, nx, Yc, yvs, n, 0, oc, bso, ldo, kys, face, st);
+      if (e != hipSuccess) return e;
+      continue;
+    }
+    if (nx * n > 1024) return hipErrorInvalidValue;
+    int cs = (int)(65536 / ((size_t)(nx + n) * 12 * sizeof(double2)));
+    if (cs < 1) return hipErrorInvalidValue;
+    cs = cs > 16 ? 16 : cs;
+    size_t lds = (size_t)(nx + n) * cs * 12 * sizeof(double2);
+    hipLaunchKernelGGL((k_block_dots<EX, EY>), dim3(d.nblk), dim3(256), lds, st, g, d, X, xvs, nx, Yc, yvs, n, oc,
+                       bso, ldo, kys, cs);
+  }
   return hipGetLastError();
 }
 
@@ -370,6 +732,17 @@ hipError_t launch_prolong(const Geo& g, const DflGeo& d, const EW* W, int64_t wv
 
 hipError_t launch_coarse_apply(const DflGeo& d, const double2* A, int Ns, const double2* in, double2* out,
                                int64_t nc, int nrhs, hipStream_t st) {
+  const int ngr = Ns * ((nrhs + 3) / 4);
+  const size_t lds = ((size_t)Ns * (Ns + 1) + (size_t)nrhs * Ns) * sizeof(double2);
+  if (ngr <= 256 && lds <= 48 * 1024) {
+    if (ngr <= 64)
+      hipLaunchKernelGGL((k_coarse_apply_lds<1>), dim3(d.nblk), dim3(64), lds, st, d, A, Ns, in, out, nc, nrhs);
+    else if (ngr <= 128)
+      hipLaunchKernelGGL((k_coarse_apply_lds<2>), dim3(d.nblk), dim3(64), lds, st, d, A, Ns, in, out, nc, nrhs);
+    else
+      hipLaunchKernelGGL((k_coarse_apply_lds<4>), dim3(d.nblk), dim3(64), lds, st, d, A, Ns, in, out, nc, nrhs);
+    return hipGetLastError();
+  }
   int64_t tot = (int64_t)nrhs * d.nblk * Ns;
   hipLaunchKernelGGL(k_coarse_apply, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, d, A, Ns, in, out, nc,
                      nrhs);
@@ -378,13 +751,13 @@ hipError_t launch_coarse_apply(const DflGeo& d, const double2* A, int Ns, const 
 
 template hipError_t launch_block_dots<double2, double2>(const Geo&, const DflGeo&, const double2*, int64_t, int,
                                                         const double2*, int64_t, int, double2*, int64_t, int64_t,
-                                                        int64_t, hipStream_t);
+                                                        int64_t, hipStream_t, int);
 template hipError_t launch_block_dots<float2, double2>(const Geo&, const DflGeo&, const float2*, int64_t, int,
                                                        const double2*, int64_t, int, double2*, int64_t, int64_t,
-                                                       int64_t, hipStream_t);
+                                                       int64_t, hipStream_t, int);
 template hipError_t launch_block_dots<float2, float2>(const Geo&, const DflGeo&, const float2*, int64_t, int,
                                                       const float2*, int64_t, int, double2*, int64_t, int64_t,
-                                                      int64_t, hipStream_t);
+                                                      int64_t, hipStream_t, int);
 
 template <class E>
 __global__ void k_add(E* y, const E* x, double a, int64_t n) {

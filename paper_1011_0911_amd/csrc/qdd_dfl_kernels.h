@@ -19,14 +19,21 @@ __device__ inline double2 to_elem<double2>(cx<double> v) { return make_double2(v
 template <>
 __device__ inline float2 to_elem<float2>(cx<double> v) { return make_float2((float)v.re, (float)v.im); }
 
-hipError_t launch_block_orth(const Geo& g, const DflGeo& d, double2* W, int64_t vs, int Ns, hipStream_t st);
+// block orthonormalisation of the Ns fields of W; work: 2 nblk Ns^2 complex
+// (CholeskyQR on the matrix cores; Gram-Schmidt kernel where it does not apply)
+hipError_t launch_block_orth(const Geo& g, const DflGeo& d, double2* W, int64_t vs, int Ns, double2* work,
+                             hipStream_t st);
 hipError_t launch_dfl_hops(const Geo& g, const DflGeo& d, const DevOp<double>& op, const double2* W, int64_t vs,
                            double2* F, int Ns, int mode, hipStream_t st);
-// out[b*bso + kx*ldo + ky*kys] = sum over block b of conj(X_kx) Y_ky
+// out[b*bso + kx*ldo + ky*kys] = sum over block b of conj(X_kx) Y_ky.  face =
+// 1 + 2 mu + dir when Y vanishes off that face of every block (only the face's
+// sites are then visited), else 0.
 template <class EX, class EY>
 hipError_t launch_block_dots(const Geo& g, const DflGeo& d, const EX* X, int64_t xvs, int nx, const EY* Y,
                              int64_t yvs, int ny, double2* out, int64_t bso, int64_t ldo, int64_t kys,
-                             hipStream_t st);
+                             hipStream_t st, int face = 0);
+// whether the matrix-core block product takes nx x ny (sym: Y is X)
+bool block_mm_fits(int nx, int ny, int sym, const DflGeo& d);
 template <class EW, class EO>
 hipError_t launch_prolong(const Geo& g, const DflGeo& d, const EW* W, int64_t wvs, int Ns, const double2* c,
                           int64_t nc, EO* out, int64_t ovs, int nrhs, hipStream_t st);

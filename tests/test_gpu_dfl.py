@@ -93,3 +93,47 @@ def test_deflated_solve(Q, orc, prec):
         assert info[r]["converged"] and res <= 1e-10
     x_o, _ = orc.fgcr(L, U, A, Ai, eta[0], op="D", prec="sap", sap_bs=BS, ncy=5, nmr=4, tol=1e-12)
     assert np.linalg.norm(psi[0] - x_o) / np.linalg.norm(x_o) < 1e-8
+
+
+@pytest.mark.parametrize("Lw,bs,ns,nrhs", [((8, 8, 8, 8), (4, 4, 4, 4), 24, 8),   # matrix-core products, 6 tiles
+                                           ((8, 8, 8, 8), (4, 2, 4, 2), 12, 3),   # one site per parity and row
+                                           ((4, 4, 8, 12), (2, 2, 4, 6), 16, 5),  # three sites per parity and row
+                                           ((8, 8, 8, 8), (4, 4, 4, 4), 40, 2),   # Gram-Schmidt / VALU fallback
+                                           ((8, 8, 8, 8), (4, 4, 2, 1), 8, 2)])   # odd rows: VALU fallback
+def test_dfl_wide_bases(Q, orc, Lw, bs, ns, nrhs):
+    # basis (block orthonormalisation), little operator (face products), restriction,
+    # coarse apply and prolongation at the workload's Ns and rhs counts and at odd row
+    # lengths, against the oracle on the same start fields
+    V = int(np.prod(Lw))
+    sbs = bs if bs[3] % 2 == 0 else (4, 4, 4, 4)
+    ctx, U = make_ctx(Q, Lw, 0.6, 0.1357, 1.9, 61, sap_bs=sbs, ncy=2, nmr=4, sap_prec=0, dfl_Ns=ns, dfl_bs=bs,
+                      dfl_nit=1, dfl_coarse_tol=1e-12, precond=Q.PRECOND_DFL, max_nrhs=nrhs)
+    A, Ai = orc.clover(Lw, U, 0.1357, 1.9)
+    init = S.gaussian_field(V, 62, nrhs=ns)
+    ctx.dfl_build(init)
+    d = orc.Deflation(Lw, bs, ns)
+    d.build(U, A, Ai, sbs, 2, 4, 1, init)
+    basis, little = ctx.dfl_export()
+    basis, little = to_np(basis), to_np(little)
+    eb, el = relerr(basis, d.basis()), relerr(little, d.little())
+    print(f"{Lw} {bs} Ns {ns}: basis err {eb:.2e} little err {el:.2e}")
+    assert eb < 1e-10 and el < 1e-10
+    nb = np.array(Lw) // np.array(bs)
+    x = np.array(np.unravel_index(np.arange(V), Lw)).T
+    bid = np.ravel_multi_index((x // np.array(bs)).T, nb)
+    for b in (0, d.nblk - 1):
+        Wb = basis[:, bid == b].reshape(ns, -1)
+        assert np.abs(Wb.conj() @ Wb.T - np.eye(ns)).max() < 1e-13
+    # coarse operator on several right-hand sides (one solve = many applies)
+    f = S.gaussian_field(d.nblk * ns * nrhs // 12 + 1, 63).reshape(-1)[: d.nblk * ns * nrhs].reshape(nrhs, d.nblk, ns)
+    c_g, _ = ctx.dfl_coarse_solve(f, 1e-13)
+    for k in range(nrhs):
+        c_o, _ = d.coarse_solve(f[k], 1e-13)
+        assert relerr(to_np(c_g)[k], c_o) < 1e-10
+    # two-level preconditioner (restriction, coarse solve, prolongation, SAP)
+    r = S.gaussian_field(V, 64, nrhs=nrhs)
+    out = to_np(ctx.dfl_precond(r))
+    for k in (0, nrhs - 1):
+        e = relerr(out[k], d.precond(U, A, Ai, sbs, 2, 4, 1e-12, r[k]))
+        print("precond err", e)
+        assert e < 1e-9
