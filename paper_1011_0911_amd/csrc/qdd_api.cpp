@@ -161,6 +161,7 @@ void compute_layout(const qdd_geom* g, const qdd_config* c, Layout& Lo) {
     int Ns = c->dfl_Ns;
     Lo.dfl_W = B.take((size_t)Ns * 24 * Vh * 16);
     Lo.dfl_W32 = B.take((size_t)Ns * 24 * Vh * 8);
+    Lo.dfl_W32b = B.take((size_t)Ns * 24 * Vh * 8);  // block-major copy for the restriction
     Lo.dfl_A = B.take((size_t)nb * 9 * Ns * Ns * 16);
     Lo.dfl_Ainv = B.take((size_t)nb * Ns * Ns * 16);
     size_t cv = (size_t)nr * nb * Ns * 16;

@@ -23,7 +23,7 @@ struct Layout {
   bool phi32;
   size_t s_rho, s_psi, s_v, s_eta, s_scale, s_tmp;
   int64_t nblk_dfl;
-  size_t dfl_W, dfl_W32, dfl_A, dfl_Ainv, dfl_cvec, dfl_init, dfl_cr, dfl_t;
+  size_t dfl_W, dfl_W32, dfl_W32b, dfl_A, dfl_Ainv, dfl_cvec, dfl_init, dfl_cr, dfl_t;
   size_t cpart, ccoef, crn2, calpha, cbinv, cactive;
   size_t net_nw, net_w, net_wb, net_wadj, net_wmx, net_wmxa, net_act, net_grad, net_adam, net_gpart, net_loss, net_tmp;
   size_t net_pairs, net_pairs_bytes, net_gpart_floats;

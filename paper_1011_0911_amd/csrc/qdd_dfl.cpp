@@ -152,7 +152,10 @@ static qdd_status dfl_build_from_W(qdd_ctx* x, int nit) {
     HCK(x, launch_block_dots<double2, double2>(G, d, W, vs, Ns, F, vs, Ns, Am + (int64_t)mode * Ns * Ns,
                                                (int64_t)9 * Ns * Ns, Ns, 1, st, mode));
   }
-  if (!dfl_fp64(x)) HCK(x, launch_convert(W, x->ptr<float2>(lo.dfl_W32), (int64_t)Ns * vs, st));
+  if (!dfl_fp64(x)) {
+    HCK(x, launch_convert(W, x->ptr<float2>(lo.dfl_W32), (int64_t)Ns * vs, st));
+    if (block_major_ok(d)) HCK(x, launch_to_blocks(G, d, W, vs, Ns, x->ptr<float2>(lo.dfl_W32b), st));
+  }
   HCK(x, hipStreamSynchronize(st));
   x->have_dfl = true;
   return QDD_OK;
@@ -218,6 +221,8 @@ static qdd_status dfl_apply(qdd_ctx* x, int nrhs, const double2* r, EP* phi, dou
   if constexpr (F64)
     HCK(x, launch_block_dots<double2, double2>(G, d, x->ptr<double2>(lo.dfl_W), vs, Ns, r, vs, nrhs, cf, Ns, 1, nc,
                                                st));
+  else if (block_major_ok(d) && block_mm_fits(Ns, 1, 0, d))
+    HCK(x, launch_block_dots_xb(G, d, x->ptr<float2>(lo.dfl_W32b), Ns, r, vs, nrhs, cf, Ns, 1, nc, st));
   else
     HCK(x, launch_block_dots<float2, double2>(G, d, x->ptr<float2>(lo.dfl_W32), vs, Ns, r, vs, nrhs, cf, Ns, 1, nc,
                                               st));
@@ -366,9 +371,12 @@ extern "C" qdd_status qdd_dfl_share(qdd_ctx* dst, const qdd_ctx* src) {
   // the same gauge field is assumed; the caller guarantees it (the links are not compared)
   HCK(dst, hipMemcpyAsync(dst->ptr<double2>(ld.dfl_W), src->ptr<double2>(ls.dfl_W), (size_t)Ns * vs * 16,
                           hipMemcpyDeviceToDevice, dst->st));
-  if (!dfl_fp64(dst))
+  if (!dfl_fp64(dst)) {
+    HCK(dst, hipMemcpyAsync(dst->ptr<float2>(ld.dfl_W32b), src->ptr<float2>(ls.dfl_W32b), (size_t)Ns * vs * 8,
+                            hipMemcpyDeviceToDevice, dst->st));
     HCK(dst, hipMemcpyAsync(dst->ptr<float2>(ld.dfl_W32), src->ptr<float2>(ls.dfl_W32), (size_t)Ns * vs * 8,
                             hipMemcpyDeviceToDevice, dst->st));
+  }
   HCK(dst, hipMemcpyAsync(dst->ptr<double2>(ld.dfl_A), src->ptr<double2>(ls.dfl_A),
                           (size_t)d.nblk * 9 * Ns * Ns * 16, hipMemcpyDeviceToDevice, dst->st));
   double delta = 1.0 / (2.0 * dst->kappa) - 1.0 / (2.0 * src->kappa);

@@ -274,7 +274,8 @@ __global__ void __launch_bounds__(256) k_block_dots(Geo g, DflGeo d, const EX* X
 // so the result is deterministic.  Face products (face = 1 + 2 mu + dir, mu < 3)
 // visit only the block rows on that face, where the face fields are non-zero.
 typedef double dv4 __attribute__((ext_vector_type(4)));
-constexpr int kMmMaxT = 8;  // 16 x 16 output tiles per workgroup
+constexpr int kMmMaxT = 8;   // 16 x 16 output tiles per workgroup
+constexpr int kMmPre = 9;    // staged elements of X (and of Y) per lane and row, at most
 
 struct MmShape {
   int MT, NT;   // row tiles (x fields), column tiles (2 ny real columns)
@@ -295,7 +296,13 @@ __host__ __device__ inline MmShape mm_shape(int nx, int ny, int sym, int h) {
   return m;
 }
 
-template <class EX, class EY>
+// X in the parity-split field layout (field v at X + v * xvs), or block-major
+// (XB): block b, field v, row q, element (p * 12 + c) * h + k at
+// X[((b * nx + v) * nrow + q) * 24 h + (p * 12 + c) * h + k], so that a row of
+// a field is one contiguous run.  PX / PY: staged elements of X / Y per lane and
+// row, held in registers; the loads are issued unconditionally (slots past the
+// end reload element 0 and skip the store), so no branch separates them.
+template <class EX, class EY, int MAXT, int PX, int PY, bool XB>
 __global__ void __launch_bounds__(256) k_block_mm(Geo g, DflGeo d, const EX* X, int64_t xvs, int nx, const EY* Y,
                                                   int64_t yvs, int ny, int sym, double2* out, int64_t bso,
                                                   int64_t ldo, int64_t kys, int face) {
@@ -304,6 +311,7 @@ __global__ void __launch_bounds__(256) k_block_mm(Geo g, DflGeo d, const EX* X, 
   const MmShape m = mm_shape(nx, ny, sym, h);
   const int T = m.MT * m.NT, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int blk = xcd_block(blockIdx.x, d.nblk);
+  const int nsb12 = d.bs[0] * d.bs[1] * d.bs[2] * d.bs[3] * 12;
   int bc[4];
   {
     int r = blk;
@@ -328,10 +336,10 @@ __global__ void __launch_bounds__(256) k_block_mm(Geo g, DflGeo d, const EX* X, 
     sm[(r < 16 * m.MT - nx ? nx + r : m.rows - 1) * m.ld + c] = 0.0;
   }
   // per-lane operand addresses of every tile
-  int acol[kMmMaxT], bcol[kMmMaxT];
-  double bsg[kMmMaxT];
+  int acol[MAXT], bcol[MAXT];
+  double bsg[MAXT];
 #pragma unroll
-  for (int t = 0; t < kMmMaxT; ++t) {
+  for (int t = 0; t < MAXT; ++t) {
     const int mt = t < T ? t / m.NT : 0, nt = t < T ? t - (t / m.NT) * m.NT : 0;
     acol[t] = (16 * mt + (lane & 15)) * m.ld + (lane >> 4);
     const int j = 16 * nt + (lane & 15), kq = lane >> 4;
@@ -346,47 +354,100 @@ __global__ void __launch_bounds__(256) k_block_mm(Geo g, DflGeo d, const EX* X, 
       bsg[t] = 1.0;
     }
   }
-  dv4 acc[kMmMaxT];
+  dv4 acc[MAXT];
 #pragma unroll
-  for (int t = 0; t < kMmMaxT; ++t) acc[t] = dv4{0.0, 0.0, 0.0, 0.0};
-  const int nf = sym ? nx : nx + ny, units = nf * 24;
-  const int spw = 3 * h;  // k' steps of 4 per wavefront and row
-  for (int q = 0; q < nrow; ++q) {
+  for (int t = 0; t < MAXT; ++t) acc[t] = dv4{0.0, 0.0, 0.0, 0.0};
+  // Staging of one row.  Element e of a field set = ((v * 2 + p) * 12 + c) * h + k
+  // (field v, parity p, component c, k-th site of the row's run); its offset from
+  // the row's start and its LDS slot do not depend on the row.
+  const int nex = nx * 24 * h, ney = sym ? 0 : ny * 24 * h;
+  constexpr int PY1 = PY > 0 ? PY : 1;
+  int goffx[PX], loffx[PX], goffy[PY1], loffy[PY1];
+#pragma unroll
+  for (int j = 0; j < PX; ++j) {
+    const int e = threadIdx.x + 256 * j;
+    const int k = e % h, u = e / h, c = u % 12, t = u / 12, p = t & 1, v = t >> 1;
+    const int el = (p * 12 + c) * h + k;
+    goffx[j] = e < nex ? (XB ? v * nsb12 + el : (int)(v * xvs + p * 12 * g.Vh + c * g.Vh + k)) : 0;
+    loffx[j] = e < nex ? v * m.ld + 2 * el : -1;
+  }
+#pragma unroll
+  for (int j = 0; j < PY1; ++j) {
+    const int e = threadIdx.x + 256 * j;
+    const int k = e % h, u = e / h, c = u % 12, t = u / 12, p = t & 1, v = t >> 1;
+    goffy[j] = PY > 0 && e < ney ? (int)(v * yvs + p * 12 * g.Vh + c * g.Vh + k) : 0;
+    loffy[j] = PY > 0 && e < ney ? (m.ybase + v) * m.ld + 2 * ((p * 12 + c) * h + k) : -1;
+  }
+  // parity-split start index of a row, and its index in the full walk
+  auto row_start = [&](int q, int& qf) {
     int y[3];
     y[2] = q % ext[2];
     y[1] = (q / ext[2]) % ext[1];
     y[0] = q / (ext[2] * ext[1]);
     if (fmu >= 0) y[fmu] = fpos;
+    qf = (y[0] * d.bs[1] + y[1]) * d.bs[2] + y[2];
     const int row = ((bc[0] * d.bs[0] + y[0]) * g.L[1] + bc[1] * d.bs[1] + y[1]) * g.L[2] + bc[2] * d.bs[2] + y[2];
-    const int i0 = row * g.Lh3 + bc[3] * h;
+    return row * g.Lh3 + bc[3] * h;
+  };
+  EX px[2][PX];
+  EY py[2][PY1];
+  auto prefetch = [&](EX* bx, EY* by, int q) {
+    int qf;
+    const int i0 = row_start(q, qf);
+    const EX* xr = XB ? X + (int64_t)blk * nx * nsb12 + qf * 24 * h : X + i0;
+#pragma unroll
+    for (int j = 0; j < PX; ++j) bx[j] = xr[goffx[j]];
+    if (PY > 0) {
+      const EY* yr = Y + i0;
+#pragma unroll
+      for (int j = 0; j < PY; ++j) by[j] = yr[goffy[j]];
+    }
+  };
+  const int spw = 3 * h;  // k' steps of 4 per wavefront and row
+  auto row_step = [&](EX* bx, EY* by, int q) {
     __syncthreads();  // the previous row's operands are consumed
-    for (int e = threadIdx.x; e < units; e += blockDim.x) {
-      const int c = e % 12, t = e / 12, p = t & 1, v = t >> 1;
-      const int64_t o = (int64_t)p * 12 * g.Vh + (int64_t)c * g.Vh + i0;
-      double* dst = sm + (v < nx ? v : m.ybase + v - nx) * m.ld + 2 * (p * 12 + c) * h;
-      for (int k = 0; k < h; ++k) {
-        const cx<double> z = v < nx ? cvt_any(X[v * xvs + o + k]) : cvt_any(Y[(v - nx) * yvs + o + k]);
-        dst[2 * k] = z.re;
-        dst[2 * k + 1] = z.im;
+#pragma unroll
+    for (int j = 0; j < PX; ++j) {
+      const cx<double> z = cvt_any(bx[j]);
+      if (loffx[j] >= 0) {
+        sm[loffx[j]] = z.re;
+        sm[loffx[j] + 1] = z.im;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PY; ++j) {
+      const cx<double> z = cvt_any(by[j]);
+      if (loffy[j] >= 0) {
+        sm[loffy[j]] = z.re;
+        sm[loffy[j] + 1] = z.im;
       }
     }
     __syncthreads();
+    // issued on every row (the last rows reload the last one, unused) so that no
+    // branch separates the loads
+    prefetch(bx, by, min(q + 2, nrow - 1));
     for (int ks = w * spw; ks < (w + 1) * spw; ++ks) {
 #pragma unroll
-      for (int t = 0; t < kMmMaxT; ++t) {
+      for (int t = 0; t < MAXT; ++t) {
         if (t < T) {
           const double a = sm[acol[t] + 4 * ks], b = bsg[t] * sm[bcol[t] + 4 * ks];
           acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
         }
       }
     }
+  };
+  prefetch(px[0], py[0], 0);
+  prefetch(px[1], py[1], min(1, nrow - 1));
+  for (int q = 0; q < nrow; q += 2) {
+    row_step(px[0], py[0], q);
+    if (q + 1 < nrow) row_step(px[1], py[1], q + 1);
   }
   // partial tiles of the four wavefronts, added in wavefront order into P
   double* ex = sm;                       // [4][256]
   double* P = sm + 1024;                 // [16 MT][16 NT]
   const int pn = 16 * m.NT;
 #pragma unroll
-  for (int t = 0; t < kMmMaxT; ++t) {
+  for (int t = 0; t < MAXT; ++t) {
     if (t < T) {
       __syncthreads();
 #pragma unroll
@@ -401,6 +462,33 @@ __global__ void __launch_bounds__(256) k_block_mm(Geo g, DflGeo d, const EX* X, 
   for (int e = threadIdx.x; e < nx * ny; e += blockDim.x) {
     const int i = e / ny, j = e - i * ny;
     out[(int64_t)blk * bso + (int64_t)i * ldo + (int64_t)j * kys] = make_double2(P[i * pn + j], P[i * pn + ny + j]);
+  }
+}
+
+// Block-major copy of Ns fields (the X layout of k_block_mm with XB), one
+// thread per output element.
+template <class EO>
+__global__ void k_to_blocks(Geo g, DflGeo d, const double2* W, int64_t vs, int Ns, EO* out) {
+  const int h = d.bs[3] >> 1, rl = 24 * h, nrow = d.bs[0] * d.bs[1] * d.bs[2];
+  const int64_t n = (int64_t)d.nblk * Ns * nrow * rl;
+  for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
+    const int el = (int)(o % rl);
+    int64_t t = o / rl;
+    const int q = (int)(t % nrow);
+    t /= nrow;
+    const int v = (int)(t % Ns), b = (int)(t / Ns);
+    const int k = el % h, pc = el / h, c = pc % 12, p = pc / 12;
+    int r = b, bc[4];
+    bc[3] = r % d.nb[3];
+    r /= d.nb[3];
+    bc[2] = r % d.nb[2];
+    r /= d.nb[2];
+    bc[1] = r % d.nb[1];
+    bc[0] = r / d.nb[1];
+    const int y2 = q % d.bs[2], y1 = (q / d.bs[2]) % d.bs[1], y0 = q / (d.bs[2] * d.bs[1]);
+    const int row = ((bc[0] * d.bs[0] + y0) * g.L[1] + bc[1] * d.bs[1] + y1) * g.L[2] + bc[2] * d.bs[2] + y2;
+    const int i = row * g.Lh3 + bc[3] * h + k;
+    out[o] = to_elem<EO>(cvt_any(W[v * vs + (int64_t)p * 12 * g.Vh + (int64_t)c * g.Vh + i]));
   }
 }
 
@@ -628,10 +716,12 @@ hipError_t launch_block_mm(const Geo& g, const DflGeo& d, const EX* X, int64_t x
                            int ny, int sym, double2* out, int64_t bso, int64_t ldo, int64_t kys, int face,
                            hipStream_t st);
 
+static bool mm_offsets_ok(int nx, int64_t xvs, int ny, int64_t yvs);
+
 hipError_t launch_block_orth(const Geo& g, const DflGeo& d, double2* W, int64_t vs, int Ns, double2* work,
                              hipStream_t st) {
   int nsb = d.bs[0] * d.bs[1] * d.bs[2] * d.bs[3];
-  if (work && Ns <= 32 && block_mm_fits(Ns, Ns, 1, d)) {
+  if (work && Ns <= 32 && block_mm_fits(Ns, Ns, 1, d) && mm_offsets_ok(Ns, vs, 0, 0)) {
     // CholeskyQR, two rounds: Gram on the matrix cores, factor and R^{-1} per
     // block, W <- W R^{-1}
     double2 *G = work, *Ri = work + (int64_t)d.nblk * Ns * Ns;
@@ -672,11 +762,42 @@ static size_t block_mm_lds(int nx, int ny, int sym, const DflGeo& d) {
   const int h = d.bs[3] / 2;
   const MmShape m = mm_shape(nx, ny, sym, h);
   if (m.MT * m.NT > kMmMaxT || h < 1 || (d.bs[3] & 1)) return 0;  // rows of even length only
+  if ((std::max(nx, sym ? 0 : ny) * 24 * h + 255) / 256 > kMmPre) return 0;  // a row in the register set
+
   const size_t stage = (size_t)m.rows * m.ld, red = 1024 + (size_t)256 * m.MT * m.NT;
   const size_t bytes = 8 * (stage > red ? stage : red);
   return bytes <= 96 * 1024 ? bytes : 0;
 }
 bool block_mm_fits(int nx, int ny, int sym, const DflGeo& d) { return block_mm_lds(nx, ny, sym, d) != 0; }
+// the staging keeps element offsets in 32 bits
+static bool mm_offsets_ok(int nx, int64_t xvs, int ny, int64_t yvs) {
+  return (int64_t)nx * xvs < ((int64_t)1 << 31) && (int64_t)ny * yvs < ((int64_t)1 << 31);
+}
+
+template <class EX, class EY, bool XB>
+static hipError_t mm_dispatch(const Geo& g, const DflGeo& d, const EX* X, int64_t xvs, int nx, const EY* Y,
+                              int64_t yvs, int ny, int sym, double2* out, int64_t bso, int64_t ldo, int64_t kys,
+                              int face, size_t lds, hipStream_t st) {
+  const int h = d.bs[3] / 2;
+  const MmShape m = mm_shape(nx, ny, sym, h);
+  // register sets sized to the shape: tiles, and staged elements of X and Y per lane and row
+  const int T = m.MT * m.NT, px = (nx * 24 * h + 255) / 256, py = sym ? 0 : (ny * 24 * h + 255) / 256;
+  const int PXs = px <= 2 ? 2 : px <= 5 ? 5 : 9;
+  const int PYs = py == 0 ? 0 : py <= 2 ? 2 : py <= PXs ? PXs : 9;
+  const int key = (T <= 2 ? 0 : 100) + PXs * 10 + PYs;
+#define MM(MT_, PX_, PY_)                                                                                            \
+  case (MT_ == 2 ? 0 : 100) + PX_ * 10 + PY_:                                                                        \
+    hipLaunchKernelGGL((k_block_mm<EX, EY, MT_, PX_, PY_, XB>), dim3(d.nblk), dim3(256), lds, st, g, d, X, xvs, nx, \
+                       Y, yvs, ny, sym, out, bso, ldo, kys, face);                                                  \
+    break;
+  switch (key) {
+    MM(2, 2, 0) MM(2, 2, 2) MM(2, 5, 0) MM(2, 5, 2) MM(2, 5, 5) MM(2, 9, 0) MM(2, 9, 2) MM(2, 9, 9)
+    MM(8, 2, 0) MM(8, 2, 2) MM(8, 5, 0) MM(8, 5, 2) MM(8, 5, 5) MM(8, 9, 0) MM(8, 9, 2) MM(8, 9, 9)
+    default: return hipErrorInvalidValue;
+  }
+#undef MM
+  return hipGetLastError();
+}
 
 template <class EX, class EY>
 hipError_t launch_block_mm(const Geo& g, const DflGeo& d, const EX* X, int64_t xvs, int nx, const EY* Y, int64_t yvs,
@@ -684,19 +805,19 @@ hipError_t launch_block_mm(const Geo& g, const DflGeo& d, const EX* X, int64_t x
                            hipStream_t st) {
   const size_t lds = block_mm_lds(nx, ny, sym, d);
   if (!lds) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_block_mm<EX, EY>), dim3(d.nblk), dim3(256), lds, st, g, d, X, xvs, nx, Y, yvs, ny, sym, out,
-                     bso, ldo, kys, face);
-  return hipGetLastError();
+  return mm_dispatch<EX, EY, false>(g, d, X, xvs, nx, Y, yvs, ny, sym, out, bso, ldo, kys, face, lds, st);
 }
 
 // The matrix-core product takes at most kMmMaxT output tiles and the VALU one
-// 1024 field pairs, so wider products run in chunks of Y fields.
-template <class EX, class EY>
-hipError_t launch_block_dots(const Geo& g, const DflGeo& d, const EX* X, int64_t xvs, int nx, const EY* Y,
-                             int64_t yvs, int ny, double2* out, int64_t bso, int64_t ldo, int64_t kys,
-                             hipStream_t st, int face) {
+// 1024 field pairs, so wider products run in chunks of Y fields.  X block-major
+// (XB) takes the matrix-core product only.
+template <class EX, class EY, bool XB>
+static hipError_t block_dots_impl(const Geo& g, const DflGeo& d, const EX* X, int64_t xvs, int nx, const EY* Y,
+                                  int64_t yvs, int ny, double2* out, int64_t bso, int64_t ldo, int64_t kys,
+                                  hipStream_t st, int face) {
   if (nx < 1 || ny < 1) return hipErrorInvalidValue;
-  const bool mm = block_mm_fits(nx, 1, 0, d);
+  const bool mm = block_mm_fits(nx, 1, 0, d) && mm_offsets_ok(XB ? 0 : nx, xvs, ny, yvs);
+  if (XB && !mm) return hipErrorInvalidValue;
   int nyc = ny;
   if (mm)
     while (!block_mm_fits(nx, nyc, 0, d)) nyc = (nyc + 1) / 2;
@@ -707,18 +828,45 @@ hipError_t launch_block_dots(const Geo& g, const DflGeo& d, const EX* X, int64_t
     const EY* Yc = Y + j0 * yvs;
     double2* oc = out + j0 * kys;
     if (mm) {
-      hipError_t e = launch_block_mm<EX, EY>(g, d, X, xvs, nx, Yc, yvs, n, 0, oc, bso, ldo, kys, face, st);
+      hipError_t e = mm_dispatch<EX, EY, XB>(g, d, X, xvs, nx, Yc, yvs, n, 0, oc, bso, ldo, kys, face,
+                                             block_mm_lds(nx, n, 0, d), st);
       if (e != hipSuccess) return e;
       continue;
     }
-    if (nx * n > 1024) return hipErrorInvalidValue;
-    int cs = (int)(65536 / ((size_t)(nx + n) * 12 * sizeof(double2)));
-    if (cs < 1) return hipErrorInvalidValue;
-    cs = cs > 16 ? 16 : cs;
-    size_t lds = (size_t)(nx + n) * cs * 12 * sizeof(double2);
-    hipLaunchKernelGGL((k_block_dots<EX, EY>), dim3(d.nblk), dim3(256), lds, st, g, d, X, xvs, nx, Yc, yvs, n, oc,
-                       bso, ldo, kys, cs);
+    if constexpr (!XB) {
+      if (nx * n > 1024) return hipErrorInvalidValue;
+      int cs = (int)(65536 / ((size_t)(nx + n) * 12 * sizeof(double2)));
+      if (cs < 1) return hipErrorInvalidValue;
+      cs = cs > 16 ? 16 : cs;
+      size_t lds = (size_t)(nx + n) * cs * 12 * sizeof(double2);
+      hipLaunchKernelGGL((k_block_dots<EX, EY>), dim3(d.nblk), dim3(256), lds, st, g, d, X, xvs, nx, Yc, yvs, n, oc,
+                         bso, ldo, kys, cs);
+    }
   }
+  return hipGetLastError();
+}
+
+template <class EX, class EY>
+hipError_t launch_block_dots(const Geo& g, const DflGeo& d, const EX* X, int64_t xvs, int nx, const EY* Y,
+                             int64_t yvs, int ny, double2* out, int64_t bso, int64_t ldo, int64_t kys,
+                             hipStream_t st, int face) {
+  return block_dots_impl<EX, EY, false>(g, d, X, xvs, nx, Y, yvs, ny, out, bso, ldo, kys, st, face);
+}
+
+hipError_t launch_block_dots_xb(const Geo& g, const DflGeo& d, const float2* Xb, int nx, const double2* Y,
+                                int64_t yvs, int ny, double2* out, int64_t bso, int64_t ldo, int64_t kys,
+                                hipStream_t st) {
+  return block_dots_impl<float2, double2, true>(g, d, Xb, 0, nx, Y, yvs, ny, out, bso, ldo, kys, st, 0);
+}
+
+bool block_major_ok(const DflGeo& d) { return (d.bs[3] & 1) == 0; }
+
+hipError_t launch_to_blocks(const Geo& g, const DflGeo& d, const double2* W, int64_t vs, int Ns, float2* out,
+                            hipStream_t st) {
+  if (!block_major_ok(d)) return hipErrorInvalidValue;
+  const int64_t n = (int64_t)Ns * 24 * g.Vh;
+  hipLaunchKernelGGL((k_to_blocks<float2>), dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)), dim3(256), 0,
+                     st, g, d, W, vs, Ns, out);
   return hipGetLastError();
 }
 
@@ -755,10 +903,6 @@ template hipError_t launch_block_dots<double2, double2>(const Geo&, const DflGeo
 template hipError_t launch_block_dots<float2, double2>(const Geo&, const DflGeo&, const float2*, int64_t, int,
                                                        const double2*, int64_t, int, double2*, int64_t, int64_t,
                                                        int64_t, hipStream_t, int);
-template hipError_t launch_block_dots<float2, float2>(const Geo&, const DflGeo&, const float2*, int64_t, int,
-                                                      const float2*, int64_t, int, double2*, int64_t, int64_t,
-                                                      int64_t, hipStream_t, int);
-
 template <class E>
 __global__ void k_add(E* y, const E* x, double a, int64_t n) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {

@@ -34,6 +34,16 @@ hipError_t launch_block_dots(const Geo& g, const DflGeo& d, const EX* X, int64_t
                              hipStream_t st, int face = 0);
 // whether the matrix-core block product takes nx x ny (sym: Y is X)
 bool block_mm_fits(int nx, int ny, int sym, const DflGeo& d);
+// Block-major copy of Ns FP64 fields in FP32: block b, field v, x3 row q of the
+// block, element (p * 12 + c) * bs3/2 + k at ((b * Ns + v) * rows + q) * 12 bs3 + ..
+// (rows of even length only: block_major_ok)
+bool block_major_ok(const DflGeo& d);
+hipError_t launch_to_blocks(const Geo& g, const DflGeo& d, const double2* W, int64_t vs, int Ns, float2* out,
+                            hipStream_t st);
+// launch_block_dots with X block-major (Xb from launch_to_blocks)
+hipError_t launch_block_dots_xb(const Geo& g, const DflGeo& d, const float2* Xb, int nx, const double2* Y,
+                                int64_t yvs, int ny, double2* out, int64_t bso, int64_t ldo, int64_t kys,
+                                hipStream_t st);
 template <class EW, class EO>
 hipError_t launch_prolong(const Geo& g, const DflGeo& d, const EW* W, int64_t wvs, int Ns, const double2* c,
                           int64_t nc, EO* out, int64_t ovs, int nrhs, hipStream_t st);
