@@ -220,3 +220,57 @@ def test_state_and_singular_errors(Q):
         c.set_params(0.1357, 200.0)
     assert e.value.status == Q.QDD_ESINGULAR
     c.set_params(0.1357, 1.9)
+
+
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (8, 6, 4, 4)])
+def test_fp16_against_quantised_inputs(Q, orc, L):
+    # FP16 storage against the oracle fed the same FP16-rounded spinor, links and
+    # clover blocks: D (one kernel, FP32 arithmetic) then differs only by the
+    # rounding of its output, at most half an FP16 unit of the site's scale; Dhat
+    # also rounds its odd-site intermediate t_o = A_o^{-1} H psi_e, emulated here
+    # from the FP64 t_o: a component whose FP32 value rounds the other way moves by
+    # one unit (2 u_h of its site's scale) and reaches an even neighbour through
+    # -1/4 (1 -+ gamma) U, of norm <= 1/2, so by at most u_h times the scale of t_o.
+    # Such flips are rare: nearly every site is within the output rounding alone.
+    from tests.fp16_util import U_H, q16_clover, q16_links, q16_spinor
+
+    V = int(np.prod(L))
+    ctx, U = make_ctx(Q, L, 0.6, 0.1357, 1.9, 500 + V)
+    A, Ai = orc.clover(L, U, 0.1357, 1.9)
+    Uq, Aq, Aiq = q16_links(U), q16_clover(A), q16_clover(Ai)
+    # D on a full field
+    psi = S.gaussian_field(V, 501)
+    ref = orc.apply_D(L, Uq, Aq, q16_spinor(psi))
+    out = to_np(ctx.apply_dw(psi[None], 2))[0]
+    site_err = np.abs(out - ref).reshape(V, 12).max(1)
+    site_max = np.abs(ref).reshape(V, 12).max(1)
+    e_d = (site_err / site_max).max()
+    print(f"D FP16 vs quantised inputs {L}: max error / site scale {e_d:.3e} (u_h {U_H:.3e}), "
+          f"global {relerr(out, ref):.2e}")
+    assert np.all(site_err <= 1.01 * U_H * site_max + 1e-6 * np.abs(ref).max())
+    # Dhat
+    ev = S.even_sites(L)
+    od = np.setdiff1d(np.arange(V), ev)
+    pe = S.gaussian_field(V // 2, 502)
+    peq = q16_spinor(pe)
+    full = np.zeros((V, 4, 3), np.complex128)
+    full[ev] = peq
+    h_o = -2.0 * orc.apply_D(L, Uq, Aq, full)[od]                      # (H psi_e) on the odd sites
+    t_o = np.einsum("vab,vb->va", Aiq[od], h_o.reshape(-1, 12)).reshape(-1, 4, 3)
+    t_q = q16_spinor(t_o)
+    tf = np.zeros((V, 4, 3), np.complex128)
+    tf[od] = t_q
+    ref_h = (np.einsum("vab,vb->va", Aq[ev], peq.reshape(-1, 12)).reshape(-1, 4, 3)
+             + 0.5 * orc.apply_D(L, Uq, Aq, tf)[ev])                   # A_e psi_e - 1/4 H t_o
+    out_h = to_np(ctx.apply_dhat(pe[None], 2))[0]
+    Vh = V // 2
+    err_h = np.abs(out_h - ref_h).reshape(Vh, 12).max(1)
+    smax_h = np.abs(ref_h).reshape(Vh, 12).max(1)
+    t_scale = np.abs(t_o).max()
+    out_bound = 1.01 * U_H * smax_h + 1e-6 * np.abs(ref_h).max()
+    print(f"Dhat FP16 vs quantised inputs {L}: max error / site scale {(err_h / smax_h).max():.3e}, "
+          f"sites beyond the output rounding {(err_h > out_bound).mean():.2%}, global {relerr(out_h, ref_h):.2e} "
+          f"(unquantised inputs {relerr(out_h, orc.apply_Dhat(L, U, A, Ai, pe)):.2e})")
+    assert (err_h > out_bound).mean() <= 0.02
+    assert np.all(err_h <= out_bound + 2 * U_H * t_scale)
+    assert relerr(out_h, ref_h) < 1e-3
