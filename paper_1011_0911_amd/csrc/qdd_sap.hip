@@ -803,7 +803,9 @@ __global__ void __launch_bounds__(R * kSapMaxHalf, CL ? 1 : 2) k_sap_lds(SapArgs
   if (a.psi.scale) psi[1].scale += a.spoff;
   // rp += 1/2 H_face V at the lane's site of parity p (the sites across the faces
   // belong to blocks of the other colour, whose corrections V the previous
-  // half-sweep stored; a backward link across a face lies outside the block)
+  // half-sweep stored).  Both links across a face come from memory: this runs
+  // before the barrier that completes the staging, so the staged links, which
+  // other wavefronts write, are not read here.
   auto bnd = [&](const int p, cx<T> (&rp)[12]) __attribute__((always_inline)) {
     cx<T> acc[12];
 #pragma unroll
@@ -814,7 +816,7 @@ __global__ void __launch_bounds__(R * kSapMaxHalf, CL ? 1 : 2) k_sap_lds(SapArgs
       cx<T> sv[12], h[6], gg[6], u[9];
       if (nin[p][m][0] < 0) {
         ld_spinor<S, O32>(vn, rs, nbr_idx(g, x[p], m, +1), sv);
-        link(p, m, jj, u);
+        ld_link_u<S>(a.U, p, m, ig[p], u);
         if (m == 0) { project<T, 0, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 0, +1>(gg, acc); }
         else if (m == 1) { project<T, 1, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 1, +1>(gg, acc); }
         else if (m == 2) { project<T, 2, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 2, +1>(gg, acc); }
