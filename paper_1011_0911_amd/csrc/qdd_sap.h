@@ -11,7 +11,8 @@ struct SapArgs {
   int bs[4], nb[4];  // block extents, blocks per direction
   int col;           // colour of the blocks of this half-sweep
   int nrhs, nmr;
-  int do_bnd;   // apply the face corrections of the previous half-sweep
+  int do_bnd;   // apply the face corrections of the previous half-sweep inside the half-sweep
+                // (the solver applies them with launch_sap_face first and clears it)
   int first;    // psi not yet written on these blocks (first cycle)
   int write_v;  // store the correction for the next half-sweep
   int variant;  // FP32/FP16 kernel: 1 per-site (registers), 2 per (block, rhs), 3 LDS-staged links and
@@ -32,4 +33,8 @@ inline bool sap_variant_ok(int prec, int v) { return prec != 0 && v >= 1 && v <=
 
 template <class S, class P>
 hipError_t launch_sap_half(const SapArgs<S, P>& a, int nblk_colour, hipStream_t st);
+// rho += 1/2 H_face V on the sites of the blocks of colour a.col (the face
+// corrections of a half-sweep, applied before it with do_bnd off)
+template <class S, class P>
+hipError_t launch_sap_face(const SapArgs<S, P>& a, hipStream_t st);
 }  // namespace qdd

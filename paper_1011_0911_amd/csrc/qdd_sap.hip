@@ -1220,6 +1220,80 @@ static bool sap_fits32(const FieldV<S>& f, int nrhs, int64_t poff, int64_t spoff
   return e < lim && sc < lim;
 }
 
+// Face corrections of a half-sweep as a kernel of their own: for every site of
+// the blocks of colour a.col (both parities) and every right-hand side,
+//   rho += 1/2 H_face V,
+// the hops across the block faces from the sites of the neighbouring blocks
+// (the other colour), whose corrections V the previous half-sweep stored.  One
+// lane per site and right-hand side, consecutive lanes on consecutive sites of a
+// parity, so the loads of rho and V are coalesced; the half-sweep then runs
+// without its own face terms.
+template <class S, class P>
+__global__ void __launch_bounds__(256) k_sap_face(SapArgs<S, P> a) {
+  typedef typename St<S>::T T;
+  const Geo& g = a.g;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, p = blockIdx.y, r = blockIdx.z;
+  if (i >= g.Vh) return;
+  int x[4];
+  site_coords(g, p, i, x);
+  int colour = 0;
+  int y[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int b = x[m] / a.bs[m];
+    y[m] = x[m] - b * a.bs[m];
+    colour += b;
+  }
+  if ((colour & 1) != a.col) return;
+  FieldV<S> rho = a.rho, vn = a.V;
+  rho.p += (int64_t)p * a.poff;
+  vn.p += (int64_t)(1 - p) * a.poff;
+  if (a.rho.scale) {
+    rho.scale += (int64_t)p * a.spoff;
+    vn.scale += (int64_t)(1 - p) * a.spoff;
+  }
+  cx<T> acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
+  bool any = false;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    cx<T> sv[12], h[6], gg[6], u[9];
+    if (y[m] == a.bs[m] - 1) {  // forward neighbour in the next block
+      any = true;
+      ld_spinor<S>(vn, r, nbr_idx(g, x, m, +1), sv);
+      ld_link(a.U, p, m, i, u);
+      if (m == 0) { project<T, 0, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 0, +1>(gg, acc); }
+      else if (m == 1) { project<T, 1, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 1, +1>(gg, acc); }
+      else if (m == 2) { project<T, 2, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 2, +1>(gg, acc); }
+      else { project<T, 3, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 3, +1>(gg, acc); }
+    }
+    if (y[m] == 0) {  // backward neighbour in the previous block
+      any = true;
+      const int jn = nbr_idx(g, x, m, -1);
+      ld_spinor<S>(vn, r, jn, sv);
+      ld_link(a.U, 1 - p, m, jn, u);
+      if (m == 0) { project<T, 0, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 0, -1>(gg, acc); }
+      else if (m == 1) { project<T, 1, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 1, -1>(gg, acc); }
+      else if (m == 2) { project<T, 2, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 2, -1>(gg, acc); }
+      else { project<T, 3, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 3, -1>(gg, acc); }
+    }
+  }
+  if (!any) return;  // an interior site: nothing crosses a face
+  cx<T> rv[12];
+  ld_spinor<S>(rho, r, i, rv);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) rv[k] = cacc(rv[k], T(0.5), acc[k]);
+  st_spinor<S>(rho, r, i, rv);
+}
+
+template <class S, class P>
+hipError_t launch_sap_face(const SapArgs<S, P>& a, hipStream_t st) {
+  const dim3 grid((unsigned)((a.g.Vh + 255) / 256), 2, (unsigned)a.nrhs), blk(256);
+  hipLaunchKernelGGL((k_sap_face<S, P>), grid, blk, 0, st, a);
+  return hipGetLastError();
+}
+
 template <class S, class P>
 hipError_t launch_sap_half(const SapArgs<S, P>& a, int nblk_colour, hipStream_t st) {
   int nsb = a.bs[0] * a.bs[1] * a.bs[2] * a.bs[3];
@@ -1272,6 +1346,9 @@ hipError_t launch_sap_half(const SapArgs<S, P>& a, int nblk_colour, hipStream_t 
 }
 
 template hipError_t launch_sap_half<double, double>(const SapArgs<double, double>&, int, hipStream_t);
+template hipError_t launch_sap_face<double, double>(const SapArgs<double, double>&, hipStream_t);
+template hipError_t launch_sap_face<float, float>(const SapArgs<float, float>&, hipStream_t);
+template hipError_t launch_sap_face<__half, float>(const SapArgs<__half, float>&, hipStream_t);
 template hipError_t launch_sap_half<float, float>(const SapArgs<float, float>&, int, hipStream_t);
 template hipError_t launch_sap_half<__half, float>(const SapArgs<__half, float>&, int, hipStream_t);
 
