@@ -255,6 +255,22 @@ qdd_status qdd_dfl_stats(const qdd_ctx* ctx, int* builds, int* refreshes);
  * system s; info[s]: nrhs[s] entries or NULL.  Returns the first failure. */
 qdd_status qdd_solve_multi(qdd_ctx* const* ctxs, int nsys, const int* nrhs, const double* const* eta,
                            double* const* psi, qdd_solve_info* const* info);
+/* The same systems solved by one outer flexible GCR loop (Sect. 3) in which
+ * every stage is ONE launch over the workgroups of all systems still iterating:
+ * the Schwarz face and half-sweep kernels, the full D, the precision
+ * conversions and each Gram-Schmidt reduction and update.  A table in the
+ * kernel arguments maps each workgroup to (system, its own workgroup number);
+ * systems advance in lockstep through a restart cycle, a system whose
+ * right-hand sides have all converged leaves the tables until the cycle ends,
+ * and per-rhs device masks freeze converged right-hand sides.  Each system gets
+ * exactly the result its own qdd_solve gives (same kernels, same reduction
+ * blocking).  All work runs on the stream of ctxs[0].  Needs 1 to 8 contexts on
+ * one device, all with the Schwarz preconditioner in FP32 storage (equal block
+ * volume and kernel variant) or all with none, chrono_nv = 0; QDD_EINVAL with
+ * the reason in ctxs[0]'s error text otherwise.  eta[s], psi[s], info[s] as for
+ * qdd_solve_multi; QDD_ENOCONV if any rhs fails (its context holds the text). */
+qdd_status qdd_solve_group(qdd_ctx* const* ctxs, int nsys, const int* nrhs, const double* const* eta,
+                           double* const* psi, qdd_solve_info* const* info);
 /* Solves Dhat psi_e = eta_e (canonical even fields) with unpreconditioned FP64 FGCR. */
 qdd_status qdd_solve_dhat(qdd_ctx* ctx, int nrhs, const double* eta_e, double* psi_e, qdd_solve_info* info);
 

@@ -1,6 +1,6 @@
 // Vector-kernel launchers of the outer FGCR (qdd_blas.hip).
 #pragma once
-#include "qdd_internal.h"
+#include "qdd_kernels.h"
 
 namespace qdd {
 
@@ -19,5 +19,67 @@ hipError_t launch_sub(double2* z, const double2* x, const double2* y, int64_t rs
                       hipStream_t st);
 hipError_t launch_norm_finish(const double2* nrm2, double* b, double* binv, int nrhs, hipStream_t st);
 hipError_t launch_acc_coef(double2* acc, int lda, const double2* src, int m, int nrhs, hipStream_t st);
+
+// ---- the same for several systems in one launch (Grp, qdd_kernels.h): one
+// argument record per system, each computing exactly what its own launch of the
+// single-system kernel computes (the same partial-sum blocking)
+template <class E>
+struct DotsArgs {
+  const E* x;
+  int64_t lstride, xrs;
+  int m;
+  const double2* y;
+  int64_t yrs, n;
+  int nrhs;
+  int nb;  // set by the launcher
+  double2 *part, *out;
+};
+template <class E>
+struct AxpyArgs {
+  double2* y;
+  int64_t yrs;
+  const E* x;
+  int64_t lstride, xrs;
+  int m;
+  const double2* coef;
+  int ldc;
+  double sgn;
+  int64_t n;
+  const int* active;
+  int nrhs;
+};
+struct AxpbyArgs {
+  double2* y;
+  int64_t yrs;
+  const double2* x;
+  int64_t xrs;
+  const double *a, *b;
+  int64_t n;
+  const int* active;
+  int nrhs;
+};
+struct SubArgs {
+  double2* z;
+  const double2 *x, *y;
+  int64_t rs, n;
+  int nrhs;
+};
+struct CoefArgs {
+  double2* acc;  // op 0, 2
+  int lda;
+  const double2* src;  // op 2: src[r*m + l]
+  int m;
+  const double2* nrm2;  // op 1
+  double *b, *binv;
+  int nrhs;
+};
+template <class E>
+hipError_t launch_dots_grp(const DotsArgs<E>* a, int ns, hipStream_t st);
+template <class E>
+hipError_t launch_axpy_multi_grp(const AxpyArgs<E>* a, int ns, hipStream_t st);
+hipError_t launch_axpby_grp(const AxpbyArgs* a, int ns, hipStream_t st);
+hipError_t launch_sub_grp(const SubArgs* a, int ns, hipStream_t st);
+// op 0: acc[0 .. nrhs*lda) = 0; op 1: b = |nrm2|^(1/2), binv = 1/b; op 2: acc[r*lda + l] += src[r*m + l]
+hipError_t launch_coef_grp(const CoefArgs* a, int ns, int op, hipStream_t st);
 
 }  // namespace qdd

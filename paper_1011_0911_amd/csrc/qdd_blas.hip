@@ -30,16 +30,15 @@ __device__ inline double wave_sum(double v) {
 
 // partial sums: part[(r*m + l) * nb + b] = sum over block b of conj(x_l[r]) y[r]
 template <class E, int MM>
-__global__ void __launch_bounds__(256) k_dots(const E* x, int64_t lstride, int64_t xrs, int m, const double2* y,
-                                              int64_t yrs, int64_t n, double2* part) {
+__device__ __forceinline__ void dots_body(const E* x, int64_t lstride, int64_t xrs, int m, const double2* y,
+                                          int64_t yrs, int64_t n, double2* part, int r, int bid, int nb) {
   __shared__ double sh[MM][4][2];
-  int r = blockIdx.y, nb = gridDim.x;
   const E* xr = x + r * xrs;
   const double2* yr = y + r * yrs;
   cx<double> acc[MM];
 #pragma unroll
   for (int l = 0; l < MM; ++l) acc[l] = {0.0, 0.0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)nb * blockDim.x) {
+  for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < n; i += (int64_t)nb * blockDim.x) {
     double2 yv = yr[i];
     cx<double> yy{yv.x, yv.y};
 #pragma unroll
@@ -65,14 +64,27 @@ __global__ void __launch_bounds__(256) k_dots(const E* x, int64_t lstride, int64
       re += sh[l][k][0];
       im += sh[l][k][1];
     }
-    part[((int64_t)r * m + l) * nb + blockIdx.x] = make_double2(re, im);
+    part[((int64_t)r * m + l) * nb + bid] = make_double2(re, im);
   }
+}
+template <class E, int MM>
+__global__ void __launch_bounds__(256) k_dots(const E* x, int64_t lstride, int64_t xrs, int m, const double2* y,
+                                              int64_t yrs, int64_t n, double2* part) {
+  dots_body<E, MM>(x, lstride, xrs, m, y, yrs, n, part, blockIdx.y, blockIdx.x, gridDim.x);
+}
+template <class E, int MM>
+__global__ void __launch_bounds__(256) k_dots_grp(Grp<DotsArgs<E>> G) {
+  const int s = grp_sys(G.start, G.ns, blockIdx.x);
+  const DotsArgs<E>& a = G.a[s];
+  if ((int)blockIdx.y >= a.nrhs) return;
+  dots_body<E, MM>(a.x, a.lstride, a.xrs, a.m, a.y, a.yrs, a.n, a.part, blockIdx.y, blockIdx.x - G.start[s],
+                   G.start[s + 1] - G.start[s]);
 }
 
 // one wavefront per result: lane j sums the partials j, j+64, ... in order, then a
 // fixed shuffle tree adds the 64 lane sums (the same order on every run)
-__global__ void __launch_bounds__(256) k_dots_final(const double2* part, int nb, int total, double2* out) {
-  int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+__device__ __forceinline__ void dots_final_body(const double2* part, int nb, int total, double2* out, int bid) {
+  int t = bid * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (t >= total) return;
   const double2* p = part + (int64_t)t * nb;
   double re = 0, im = 0;
@@ -85,12 +97,23 @@ __global__ void __launch_bounds__(256) k_dots_final(const double2* part, int nb,
   im = wave_sum(im);
   if (lane == 0) out[t] = make_double2(re, im);
 }
+__global__ void __launch_bounds__(256) k_dots_final(const double2* part, int nb, int total, double2* out) {
+  dots_final_body(part, nb, total, out, blockIdx.x);
+}
+template <class E>
+__global__ void __launch_bounds__(256) k_dots_final_grp(Grp<DotsArgs<E>> G) {
+  const int s = grp_sys(G.start, G.ns, blockIdx.x);
+  const DotsArgs<E>& a = G.a[s];
+  dots_final_body(a.part, a.nb, a.nrhs * a.m, a.out, blockIdx.x - G.start[s]);
+}
+
+static int dots_blocks(int64_t n) { return (int)std::min<int64_t>(kDotBlocks, (n + 255) / 256); }
 
 template <class E>
 hipError_t launch_dots(const E* x, int64_t lstride, int64_t xrs, int m, const double2* y, int64_t yrs, int64_t n,
                        int nrhs, double2* part, double2* out, hipStream_t st) {
   if (m <= 0) return hipSuccess;
-  int nb = (int)std::min<int64_t>(kDotBlocks, (n + 255) / 256);
+  int nb = dots_blocks(n);
   dim3 grid(nb, nrhs);
   if (m <= 1) hipLaunchKernelGGL((k_dots<E, 1>), grid, dim3(256), 0, st, x, lstride, xrs, m, y, yrs, n, part);
   else if (m <= 4) hipLaunchKernelGGL((k_dots<E, 4>), grid, dim3(256), 0, st, x, lstride, xrs, m, y, yrs, n, part);
@@ -103,12 +126,35 @@ hipError_t launch_dots(const E* x, int64_t lstride, int64_t xrs, int m, const do
   return hipGetLastError();
 }
 
+template <class E>
+hipError_t launch_dots_grp(const DotsArgs<E>* a, int ns, hipStream_t st) {
+  if (ns < 1 || ns > kGrpMax) return hipErrorInvalidValue;
+  Grp<DotsArgs<E>> G = grp_new<DotsArgs<E>>(), F = grp_new<DotsArgs<E>>();
+  int mm = 0;
+  for (int s = 0; s < ns; ++s) {
+    if (a[s].m < 1) return hipErrorInvalidValue;
+    DotsArgs<E> b = a[s];
+    b.nb = dots_blocks(b.n);
+    grp_add(G, b, b.nb, b.nrhs);
+    grp_add(F, b, (b.nrhs * b.m + 3) / 4);
+    mm = std::max(mm, b.m);
+  }
+  const dim3 grid(G.start[ns], G.ny), blk(256);
+  if (mm <= 1) hipLaunchKernelGGL((k_dots_grp<E, 1>), grid, blk, 0, st, G);
+  else if (mm <= 4) hipLaunchKernelGGL((k_dots_grp<E, 4>), grid, blk, 0, st, G);
+  else if (mm <= 8) hipLaunchKernelGGL((k_dots_grp<E, 8>), grid, blk, 0, st, G);
+  else if (mm <= 16) hipLaunchKernelGGL((k_dots_grp<E, 16>), grid, blk, 0, st, G);
+  else if (mm <= 32) hipLaunchKernelGGL((k_dots_grp<E, 32>), grid, blk, 0, st, G);
+  else return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dots_final_grp<E>, dim3(F.start[ns]), blk, 0, st, F);
+  return hipGetLastError();
+}
+
 // y[r] += sgn * sum_l coef[r*ldc + l] * x_l[r]    (active[r] == 0 skips rhs r)
 template <class E, int MM>
-__global__ void __launch_bounds__(256) k_axpy_multi(double2* y, int64_t yrs, const E* x, int64_t lstride,
-                                                    int64_t xrs, int m, const double2* coef, int ldc, double sgn,
-                                                    int64_t n, const int* active) {
-  int r = blockIdx.y;
+__device__ __forceinline__ void axpy_multi_body(double2* y, int64_t yrs, const E* x, int64_t lstride, int64_t xrs,
+                                                int m, const double2* coef, int ldc, double sgn, int64_t n,
+                                                const int* active, int r, int bid, int nb) {
   if (active && !active[r]) return;
   __shared__ cx<double> c[MM];
   if ((int)threadIdx.x < m) {
@@ -118,7 +164,7 @@ __global__ void __launch_bounds__(256) k_axpy_multi(double2* y, int64_t yrs, con
   __syncthreads();
   double2* yr = y + r * yrs;
   const E* xr = x + r * xrs;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < n; i += (int64_t)nb * blockDim.x) {
     double2 yv = yr[i];
     cx<double> acc{yv.x, yv.y};
 #pragma unroll
@@ -127,13 +173,28 @@ __global__ void __launch_bounds__(256) k_axpy_multi(double2* y, int64_t yrs, con
     yr[i] = make_double2(acc.re, acc.im);
   }
 }
+template <class E, int MM>
+__global__ void __launch_bounds__(256) k_axpy_multi(double2* y, int64_t yrs, const E* x, int64_t lstride,
+                                                    int64_t xrs, int m, const double2* coef, int ldc, double sgn,
+                                                    int64_t n, const int* active) {
+  axpy_multi_body<E, MM>(y, yrs, x, lstride, xrs, m, coef, ldc, sgn, n, active, blockIdx.y, blockIdx.x, gridDim.x);
+}
+template <class E, int MM>
+__global__ void __launch_bounds__(256) k_axpy_multi_grp(Grp<AxpyArgs<E>> G) {
+  const int s = grp_sys(G.start, G.ns, blockIdx.x);
+  const AxpyArgs<E>& a = G.a[s];
+  if ((int)blockIdx.y >= a.nrhs) return;
+  axpy_multi_body<E, MM>(a.y, a.yrs, a.x, a.lstride, a.xrs, a.m, a.coef, a.ldc, a.sgn, a.n, a.active, blockIdx.y,
+                         blockIdx.x - G.start[s], G.start[s + 1] - G.start[s]);
+}
+static int vec_blocks(int64_t n) { return (int)std::min<int64_t>(2048, (n + 255) / 256); }
 
 template <class E>
 hipError_t launch_axpy_multi(double2* y, int64_t yrs, const E* x, int64_t lstride, int64_t xrs, int m,
                              const double2* coef, int ldc, double sgn, int64_t n, int nrhs, const int* active,
                              hipStream_t st) {
   if (m <= 0) return hipSuccess;
-  int nb = (int)std::min<int64_t>(2048, (n + 255) / 256);
+  int nb = vec_blocks(n);
   dim3 grid(nb, nrhs);
   if (m <= 1) hipLaunchKernelGGL((k_axpy_multi<E, 1>), grid, dim3(256), 0, st, y, yrs, x, lstride, xrs, m, coef, ldc, sgn, n, active);
   else if (m <= 4) hipLaunchKernelGGL((k_axpy_multi<E, 4>), grid, dim3(256), 0, st, y, yrs, x, lstride, xrs, m, coef, ldc, sgn, n, active);
@@ -144,37 +205,92 @@ hipError_t launch_axpy_multi(double2* y, int64_t yrs, const E* x, int64_t lstrid
   return hipGetLastError();
 }
 
+// systems with m = 0 take no part
+template <class E>
+hipError_t launch_axpy_multi_grp(const AxpyArgs<E>* a, int ns, hipStream_t st) {
+  if (ns < 1 || ns > kGrpMax) return hipErrorInvalidValue;
+  Grp<AxpyArgs<E>> G = grp_new<AxpyArgs<E>>();
+  int mm = 0;
+  for (int s = 0; s < ns; ++s) {
+    if (a[s].m <= 0) continue;
+    grp_add(G, a[s], vec_blocks(a[s].n), a[s].nrhs);
+    mm = std::max(mm, a[s].m);
+  }
+  if (G.ns == 0) return hipSuccess;
+  const dim3 grid(G.start[G.ns], G.ny), blk(256);
+  if (mm <= 1) hipLaunchKernelGGL((k_axpy_multi_grp<E, 1>), grid, blk, 0, st, G);
+  else if (mm <= 4) hipLaunchKernelGGL((k_axpy_multi_grp<E, 4>), grid, blk, 0, st, G);
+  else if (mm <= 8) hipLaunchKernelGGL((k_axpy_multi_grp<E, 8>), grid, blk, 0, st, G);
+  else if (mm <= 16) hipLaunchKernelGGL((k_axpy_multi_grp<E, 16>), grid, blk, 0, st, G);
+  else if (mm <= 32) hipLaunchKernelGGL((k_axpy_multi_grp<E, 32>), grid, blk, 0, st, G);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 // y[r] = a * x[r] + b * y[r] with per-rhs real scalars (device arrays, may be null = 1/0)
-__global__ void k_axpby(double2* y, int64_t yrs, const double2* x, int64_t xrs, const double* a, const double* b,
-                        int64_t n, const int* active) {
-  int r = blockIdx.y;
+__device__ __forceinline__ void axpby_body(double2* y, int64_t yrs, const double2* x, int64_t xrs, const double* a,
+                                           const double* b, int64_t n, const int* active, int r, int bid, int nb) {
   if (active && !active[r]) return;
   double av = a ? a[r] : 1.0, bv = b ? b[r] : 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < n; i += (int64_t)nb * blockDim.x) {
     double2 xv = x[r * xrs + i], yv = y[r * yrs + i];
     y[r * yrs + i] = make_double2(av * xv.x + bv * yv.x, av * xv.y + bv * yv.y);
   }
 }
+__global__ void k_axpby(double2* y, int64_t yrs, const double2* x, int64_t xrs, const double* a, const double* b,
+                        int64_t n, const int* active) {
+  axpby_body(y, yrs, x, xrs, a, b, n, active, blockIdx.y, blockIdx.x, gridDim.x);
+}
+__global__ void k_axpby_grp(Grp<AxpbyArgs> G) {
+  const int s = grp_sys(G.start, G.ns, blockIdx.x);
+  const AxpbyArgs& a = G.a[s];
+  if ((int)blockIdx.y >= a.nrhs) return;
+  axpby_body(a.y, a.yrs, a.x, a.xrs, a.a, a.b, a.n, a.active, blockIdx.y, blockIdx.x - G.start[s],
+             G.start[s + 1] - G.start[s]);
+}
 
 hipError_t launch_axpby(double2* y, int64_t yrs, const double2* x, int64_t xrs, const double* a, const double* b,
                         int64_t n, int nrhs, const int* active, hipStream_t st) {
-  int nb = (int)std::min<int64_t>(2048, (n + 255) / 256);
+  int nb = vec_blocks(n);
   hipLaunchKernelGGL(k_axpby, dim3(nb, nrhs), dim3(256), 0, st, y, yrs, x, xrs, a, b, n, active);
+  return hipGetLastError();
+}
+hipError_t launch_axpby_grp(const AxpbyArgs* a, int ns, hipStream_t st) {
+  if (ns < 1 || ns > kGrpMax) return hipErrorInvalidValue;
+  Grp<AxpbyArgs> G = grp_new<AxpbyArgs>();
+  for (int s = 0; s < ns; ++s) grp_add(G, a[s], vec_blocks(a[s].n), a[s].nrhs);
+  hipLaunchKernelGGL(k_axpby_grp, dim3(G.start[ns], G.ny), dim3(256), 0, st, G);
   return hipGetLastError();
 }
 
 // z[r] = x[r] - y[r]
-__global__ void k_sub(double2* z, const double2* x, const double2* y, int64_t rs, int64_t n) {
-  int r = blockIdx.y;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+__device__ __forceinline__ void sub_body(double2* z, const double2* x, const double2* y, int64_t rs, int64_t n, int r,
+                                         int bid, int nb) {
+  for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < n; i += (int64_t)nb * blockDim.x) {
     double2 a = x[r * rs + i], b = y[r * rs + i];
     z[r * rs + i] = make_double2(a.x - b.x, a.y - b.y);
   }
 }
+__global__ void k_sub(double2* z, const double2* x, const double2* y, int64_t rs, int64_t n) {
+  sub_body(z, x, y, rs, n, blockIdx.y, blockIdx.x, gridDim.x);
+}
+__global__ void k_sub_grp(Grp<SubArgs> G) {
+  const int s = grp_sys(G.start, G.ns, blockIdx.x);
+  const SubArgs& a = G.a[s];
+  if ((int)blockIdx.y >= a.nrhs) return;
+  sub_body(a.z, a.x, a.y, a.rs, a.n, blockIdx.y, blockIdx.x - G.start[s], G.start[s + 1] - G.start[s]);
+}
 hipError_t launch_sub(double2* z, const double2* x, const double2* y, int64_t rs, int64_t n, int nrhs,
                       hipStream_t st) {
-  int nb = (int)std::min<int64_t>(2048, (n + 255) / 256);
+  int nb = vec_blocks(n);
   hipLaunchKernelGGL(k_sub, dim3(nb, nrhs), dim3(256), 0, st, z, x, y, rs, n);
+  return hipGetLastError();
+}
+hipError_t launch_sub_grp(const SubArgs* a, int ns, hipStream_t st) {
+  if (ns < 1 || ns > kGrpMax) return hipErrorInvalidValue;
+  Grp<SubArgs> G = grp_new<SubArgs>();
+  for (int s = 0; s < ns; ++s) grp_add(G, a[s], vec_blocks(a[s].n), a[s].nrhs);
+  hipLaunchKernelGGL(k_sub_grp, dim3(G.start[ns], G.ny), dim3(256), 0, st, G);
   return hipGetLastError();
 }
 
@@ -207,6 +323,34 @@ hipError_t launch_acc_coef(double2* acc, int lda, const double2* src, int m, int
   return hipGetLastError();
 }
 
+// the per-rhs Gram-Schmidt bookkeeping of several systems, one workgroup each:
+// op 0 zero acc[0 .. nrhs*lda), op 1 the norm step, op 2 the coefficient sum
+__global__ void __launch_bounds__(256) k_coef_grp(Grp<CoefArgs> G, int op) {
+  const CoefArgs& a = G.a[blockIdx.x];
+  if (op == 0) {
+    for (int t = threadIdx.x; t < a.nrhs * a.lda; t += blockDim.x) a.acc[t] = make_double2(0.0, 0.0);
+  } else if (op == 1) {
+    for (int r = threadIdx.x; r < a.nrhs; r += blockDim.x) {
+      double v = sqrt(fmax(a.nrm2[r].x, 0.0));
+      a.b[r] = v;
+      a.binv[r] = v > 0 ? 1.0 / v : 0.0;
+    }
+  } else {
+    for (int t = threadIdx.x; t < a.m * a.nrhs; t += blockDim.x) {
+      int r = t / a.m, l = t % a.m;
+      double2 x = a.acc[r * a.lda + l], y = a.src[t];
+      a.acc[r * a.lda + l] = make_double2(x.x + y.x, x.y + y.y);
+    }
+  }
+}
+hipError_t launch_coef_grp(const CoefArgs* a, int ns, int op, hipStream_t st) {
+  if (ns < 1 || ns > kGrpMax || op < 0 || op > 2) return hipErrorInvalidValue;
+  Grp<CoefArgs> G = grp_new<CoefArgs>();
+  for (int s = 0; s < ns; ++s) grp_add(G, a[s], 1);
+  hipLaunchKernelGGL(k_coef_grp, dim3(ns), dim3(256), 0, st, G, op);
+  return hipGetLastError();
+}
+
 template hipError_t launch_dots<double2>(const double2*, int64_t, int64_t, int, const double2*, int64_t, int64_t, int,
                                          double2*, double2*, hipStream_t);
 template hipError_t launch_dots<float2>(const float2*, int64_t, int64_t, int, const double2*, int64_t, int64_t, int,
@@ -215,5 +359,8 @@ template hipError_t launch_axpy_multi<double2>(double2*, int64_t, const double2*
                                                const double2*, int, double, int64_t, int, const int*, hipStream_t);
 template hipError_t launch_axpy_multi<float2>(double2*, int64_t, const float2*, int64_t, int64_t, int,
                                               const double2*, int, double, int64_t, int, const int*, hipStream_t);
+template hipError_t launch_dots_grp<double2>(const DotsArgs<double2>*, int, hipStream_t);
+template hipError_t launch_axpy_multi_grp<double2>(const AxpyArgs<double2>*, int, hipStream_t);
+template hipError_t launch_axpy_multi_grp<float2>(const AxpyArgs<float2>*, int, hipStream_t);
 
 }  // namespace qdd

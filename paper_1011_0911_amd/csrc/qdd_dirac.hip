@@ -387,16 +387,16 @@ __global__ void __launch_bounds__(256, vec_waves<V>()) k_dhat_vb(Geo g, LinkV<S>
 // psi) and, with CE, a factor on the even sites' clover term (out_e =
 // shift[r] A_e psi_e - 1/2 H psi_o: with shift[r] = 1 + dm the operator whose
 // Schur complement is Dhat + dm A_e)
-template <class S, int NR, bool O32, bool SH, bool CE = false>
-__global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k_dw(Geo g, LinkV<S> U, CloverV<S> A, FieldV<S> in, FieldV<S> out,
-                                            int64_t poff, int64_t spoff, int nrhs, int nrg, int order, int sb,
-                                            const double* shift) {
+template <class S, int NR, bool O32, bool SH, bool CE>
+__device__ __forceinline__ void dw_body(const Geo& g, const LinkV<S>& U, const CloverV<S>& A, const FieldV<S>& in,
+                                        const FieldV<S>& out, int64_t poff, int64_t spoff, int nrhs, int nrg,
+                                        int order, int sb, const double* shift, int bid, int nbid) {
   typedef typename St<S>::T T;
   const int rf = 0;  // full fields are always in the blocked layout
-  int nh = gridDim.x >> 1;
-  int p = (int)blockIdx.x >= nh;
+  int nh = nbid >> 1;
+  int p = bid >= nh;
   int tile, rg, i, r0;
-  map_block(g, blockIdx.x - p * nh, nh, nrg, sb, order, tile, rg);
+  map_block(g, bid - p * nh, nh, nrg, sb, order, tile, rg);
   if (!lane_site<NR>(g, tile, rg, sb, nrhs, rf, i, r0)) return;
   int nr = min(NR, nrhs - r0);
   int x[4];
@@ -438,6 +438,22 @@ __global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k
       st_spinor<S, O32>(dst, r0 + q, i, o);
     }
   }
+}
+
+template <class S, int NR, bool O32, bool SH, bool CE = false>
+__global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k_dw(Geo g, LinkV<S> U, CloverV<S> A, FieldV<S> in, FieldV<S> out,
+                                            int64_t poff, int64_t spoff, int nrhs, int nrg, int order, int sb,
+                                            const double* shift) {
+  dw_body<S, NR, O32, SH, CE>(g, U, A, in, out, poff, spoff, nrhs, nrg, order, sb, shift, blockIdx.x, gridDim.x);
+}
+
+// the full D of several systems in one launch (no shifts)
+template <class S, int NR, bool O32>
+__global__ void __launch_bounds__(256, NR == 1 ? (sizeof(S) == 8 ? 2 : 4) : 1) k_dw_grp(Grp<DwArgs<S>> G) {
+  const int s = grp_sys(G.start, G.ns, blockIdx.x);
+  const DwArgs<S>& a = G.a[s];
+  dw_body<S, NR, O32, false, false>(a.g, a.U, a.A, a.in, a.out, a.poff, a.spoff, a.nrhs, a.nrg, a.order, a.sb,
+                                    nullptr, blockIdx.x - G.start[s], G.start[s + 1] - G.start[s]);
 }
 
 // ------------------------------------------------- LDS-staged batched variant
@@ -734,6 +750,36 @@ static hipError_t launch_dw_nr(const Geo& g, const DevOp<S>& op, FieldV<S> in, F
 #undef DW
   return hipGetLastError();
 }
+
+template <class S, int NR>
+static hipError_t launch_dw_grp_nr(const DwArgs<S>* a, int ns, const LaunchCfg& c, hipStream_t st) {
+  Grp<DwArgs<S>> G = grp_new<DwArgs<S>>();
+  bool o32 = true;
+  for (int s = 0; s < ns; ++s) {
+    DwArgs<S> b = a[s];
+    b.sb = c.sb > 0 ? c.sb : c.block;
+    b.nrg = ceil_div(b.nrhs, NR * (c.block / b.sb));
+    b.order = c.xcd;
+    o32 = o32 && fits32(b.g, b.in, b.nrhs, b.poff, b.spoff) && fits32(b.g, b.out, b.nrhs, b.poff, b.spoff);
+    grp_add(G, b, 2 * ceil_div(b.g.Vh, b.sb) * b.nrg);
+  }
+  const dim3 grid(G.start[ns]), blk(c.block);
+  if (o32) hipLaunchKernelGGL((k_dw_grp<S, NR, true>), grid, blk, 0, st, G);
+  else hipLaunchKernelGGL((k_dw_grp<S, NR, false>), grid, blk, 0, st, G);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_dw_grp(const DwArgs<S>* a, int ns, const LaunchCfg& c, hipStream_t st) {
+  if (ns < 1 || ns > kGrpMax) return hipErrorInvalidValue;
+  switch (c.nr) {
+    case 1: return launch_dw_grp_nr<S, 1>(a, ns, c, st);
+    case 2: return launch_dw_grp_nr<S, 2>(a, ns, c, st);
+    case 4: return launch_dw_grp_nr<S, 4>(a, ns, c, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+template hipError_t launch_dw_grp<double>(const DwArgs<double>*, int, const LaunchCfg&, hipStream_t);
 
 template <class S>
 hipError_t launch_dw(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> out, int64_t poff, int64_t spoff,

@@ -57,6 +57,64 @@ hipError_t launch_dw(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> o
                      int nrhs, const LaunchCfg& c, hipStream_t st, const double* shift = nullptr,
                      const double* ce = nullptr);
 
+// ---- several systems in one launch (the grouped solve of qdd_solve_multi)
+// The workgroups of one launch are split among up to kGrpMax independent systems
+// (different lattices, masses, batch sizes): system s owns the workgroups
+// [start[s], start[s+1]) and runs the single-system kernel body on its own
+// arguments a[s], with its own workgroup numbering, so every system computes
+// exactly what its own launch would.  The table travels by value in the
+// kernel-argument segment; ny is the extent of the second grid dimension (the
+// largest right-hand-side count), whose surplus workgroups exit at once.
+constexpr int kGrpMax = 8;
+template <class A>
+struct Grp {
+  A a[kGrpMax];
+  int start[kGrpMax + 1];
+  int ns;
+  int ny;
+};
+__device__ inline int grp_sys(const int* start, int ns, int b) {
+  int s = 0;
+  for (int j = 1; j < ns; ++j) s += b >= start[j];
+  return s;
+}
+template <class A>
+inline void grp_add(Grp<A>& G, const A& a, int nblk, int ny = 1) {
+  static_assert(sizeof(Grp<A>) <= 4096, "a group table must fit the kernel-argument segment");
+  if (G.ns == 0) {
+    G.start[0] = 0;
+    G.ny = 1;
+  }
+  G.a[G.ns] = a;
+  G.start[G.ns + 1] = G.start[G.ns] + nblk;
+  G.ny = ny > G.ny ? ny : G.ny;
+  ++G.ns;
+}
+template <class A>
+inline Grp<A> grp_new() {
+  Grp<A> G;
+  G.ns = 0;
+  G.ny = 1;
+  G.start[0] = 0;
+  return G;
+}
+
+// full D of one system in a grouped launch (poff, spoff: parity offsets of the
+// full fields; the launch fills in its walk of the tiles)
+template <class S>
+struct DwArgs {
+  Geo g;
+  LinkV<S> U;
+  CloverV<S> A;
+  FieldV<S> in, out;
+  int64_t poff, spoff;
+  int nrhs, nrg, order, sb;
+};
+// one launch of the full D over ns systems with the common launch shape c
+// (block and rhs per lane shared, walk and tile size per system as c gives them)
+template <class S>
+hipError_t launch_dw_grp(const DwArgs<S>* a, int ns, const LaunchCfg& c, hipStream_t st);
+
 // ---- packing / conversion (qdd_pack.hip)
 
 // canonical complex128 links [V][4][3][3] -> FP64 internal hopping links (sign folded in)
@@ -76,6 +134,10 @@ hipError_t launch_unpack_spinor(const Geo& g, FieldV<S> f, double* canon, int nr
 // convert between internal precisions (same layout): n sites per component, rhs count * parities
 template <class SI, class SO>
 hipError_t launch_field_convert(FieldV<SI> in, FieldV<SO> out, int nvec, hipStream_t st);
+// the same over ns systems in one launch (in[s], out[s], nvec[s])
+template <class SI, class SO>
+hipError_t launch_field_convert_grp(const FieldV<SI>* in, const FieldV<SO>* out, const int* nvec, int ns,
+                                    hipStream_t st);
 
 // ---- clover (qdd_clover.hip)
 // builds A and A^{-1} (FP64, both parities) from the FP64 internal links; counts

@@ -134,8 +134,8 @@ hipError_t launch_unpack_spinor(const Geo& g, FieldV<S> f, double* canon, int nr
 // precision conversion of nvec vectors of n sites (layout [vec][12][n] with the
 // views' rhs strides)
 template <class SI, class SO>
-__global__ void k_field_convert(FieldV<SI> in, FieldV<SO> out, int nvec) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void field_convert_body(const FieldV<SI>& in, const FieldV<SO>& out, int nvec, int bid) {
+  int64_t t = (int64_t)bid * blockDim.x + threadIdx.x;
   if (t >= (int64_t)in.n * nvec) return;
   int v = (int)(t / in.n), i = (int)(t % in.n);
   cx<typename St<SI>::T> a[12];
@@ -145,6 +145,36 @@ __global__ void k_field_convert(FieldV<SI> in, FieldV<SO> out, int nvec) {
   for (int k = 0; k < 12; ++k) b[k] = {(typename St<SO>::T)a[k].re, (typename St<SO>::T)a[k].im};
   st_spinor(out, v, i, b);
 }
+template <class SI, class SO>
+__global__ void k_field_convert(FieldV<SI> in, FieldV<SO> out, int nvec) {
+  field_convert_body<SI, SO>(in, out, nvec, blockIdx.x);
+}
+template <class SI, class SO>
+struct ConvArgs {
+  FieldV<SI> in;
+  FieldV<SO> out;
+  int nvec;
+};
+template <class SI, class SO>
+__global__ void k_field_convert_grp(Grp<ConvArgs<SI, SO>> G) {
+  const int s = grp_sys(G.start, G.ns, blockIdx.x);
+  const ConvArgs<SI, SO>& a = G.a[s];
+  field_convert_body<SI, SO>(a.in, a.out, a.nvec, blockIdx.x - G.start[s]);
+}
+template <class SI, class SO>
+hipError_t launch_field_convert_grp(const FieldV<SI>* in, const FieldV<SO>* out, const int* nvec, int ns,
+                                    hipStream_t st) {
+  if (ns < 1 || ns > kGrpMax) return hipErrorInvalidValue;
+  Grp<ConvArgs<SI, SO>> G = grp_new<ConvArgs<SI, SO>>();
+  for (int s = 0; s < ns; ++s)
+    grp_add(G, ConvArgs<SI, SO>{in[s], out[s], nvec[s]}, (int)(((int64_t)in[s].n * nvec[s] + 255) / 256));
+  hipLaunchKernelGGL((k_field_convert_grp<SI, SO>), dim3(G.start[ns]), dim3(256), 0, st, G);
+  return hipGetLastError();
+}
+template hipError_t launch_field_convert_grp<double, float>(const FieldV<double>*, const FieldV<float>*, const int*,
+                                                            int, hipStream_t);
+template hipError_t launch_field_convert_grp<float, double>(const FieldV<float>*, const FieldV<double>*, const int*,
+                                                            int, hipStream_t);
 
 template <class SI, class SO>
 hipError_t launch_field_convert(FieldV<SI> in, FieldV<SO> out, int nvec, hipStream_t st) {

@@ -4,7 +4,9 @@
 #include "qdd_sap.h"
 #include "qdd_dfl.h"
 
+#include <algorithm>
 #include <string>
+#include <vector>
 
 using namespace qdd;
 
@@ -21,18 +23,15 @@ static FieldV<S> vec_view(const qdd_ctx* x, const void* p, float* scale) {
   return FieldV<S>{(typename St<S>::E*)p, scale, 12 * n, n, (int)n};
 }
 
-// psi (P storage, full fields, rhs stride 24 Vh) = M_sap eta (FP64 internal full fields)
+// arguments of the half-sweeps of one context (colour and cycle flags unset)
 template <class S, class P>
-static qdd_status sap_run(qdd_ctx* x, int nrhs, const double2* eta, typename St<P>::E* psi) {
+static SapArgs<S, P> sap_args(const qdd_ctx* x, int nrhs, typename St<P>::E* psi, int* nblk_out) {
   const Layout& lo = x->lo;
   const qdd_config& c = x->cfg;
   int64_t Vh = x->G.Vh;
   float* sc = x->ptr<float>(lo.s_scale);
   float* rho_sc = sizeof(S) == 2 ? sc : nullptr;
   float* v_sc = sizeof(S) == 2 ? sc + (size_t)c.max_nrhs * 2 * Vh : nullptr;
-  FieldV<S> rho = full_view<S>(x, lo.s_rho, rho_sc), V = full_view<S>(x, lo.s_v, v_sc);
-  HCK(x, launch_field_convert<double, S>(vec_view<double>(x, eta, nullptr), vec_view<S>(x, rho.p, rho_sc), 2 * nrhs,
-                                          x->st));
   SapArgs<S, P> a;
   a.g = x->G;
   int nblk = 1;
@@ -48,11 +47,24 @@ static qdd_status sap_run(qdd_ctx* x, int nrhs, const double2* eta, typename St<
   a.U = op.U;
   a.A = op.A;
   a.Ai = op.Ainv;
-  a.rho = rho;
-  a.V = V;
+  a.rho = full_view<S>(x, lo.s_rho, rho_sc);
+  a.V = full_view<S>(x, lo.s_v, v_sc);
   a.psi = FieldV<P>{psi, nullptr, 24 * Vh, 2 * Vh, (int)Vh};
   a.poff = 12 * Vh;
   a.spoff = Vh;
+  a.col = a.first = a.do_bnd = a.write_v = 0;
+  *nblk_out = nblk;
+  return a;
+}
+
+// psi (P storage, full fields, rhs stride 24 Vh) = M_sap eta (FP64 internal full fields)
+template <class S, class P>
+static qdd_status sap_run(qdd_ctx* x, int nrhs, const double2* eta, typename St<P>::E* psi) {
+  const qdd_config& c = x->cfg;
+  int nblk = 1;
+  SapArgs<S, P> a = sap_args<S, P>(x, nrhs, psi, &nblk);
+  HCK(x, launch_field_convert<double, S>(vec_view<double>(x, eta, nullptr), vec_view<S>(x, a.rho.p, a.rho.scale),
+                                          2 * nrhs, x->st));
   for (int cy = 0; cy < c.ncy; ++cy)
     for (int col = 0; col < 2; ++col) {
       a.col = col;
@@ -66,6 +78,50 @@ static qdd_status sap_run(qdd_ctx* x, int nrhs, const double2* eta, typename St<
         a.do_bnd = 0;
       }
       HCK(x, launch_sap_half<S, P>(a, nblk / 2, x->st));
+    }
+  return QDD_OK;
+}
+
+// the same for ns systems with FP32 storage, every step one launch over the
+// systems that still take part in it (systems may differ in lattice, mass,
+// batch size, block shape of equal volume and cycle count)
+qdd_status sap_apply_grp(qdd_ctx* const* xs, const int* nrhs, const double2* const* eta, void* const* psi, int ns,
+                         hipStream_t st) {
+  qdd_ctx* x0 = xs[0];
+  if (ns < 1 || ns > kGrpMax) {
+    x0->fail("grouped Schwarz: 1 to %d systems", kGrpMax);
+    return QDD_EINVAL;
+  }
+  std::vector<SapArgs<float, float>> a(ns), sel;
+  std::vector<FieldV<double>> cin(ns);
+  std::vector<FieldV<float>> cvo(ns);
+  std::vector<int> nvec(ns);
+  int ncy = 0;
+  for (int s = 0; s < ns; ++s) {
+    int nblk = 0;
+    a[s] = sap_args<float, float>(xs[s], nrhs[s], (float2*)psi[s], &nblk);
+    cin[s] = vec_view<double>(xs[s], eta[s], nullptr);
+    cvo[s] = vec_view<float>(xs[s], a[s].rho.p, nullptr);
+    nvec[s] = 2 * nrhs[s];
+    ncy = std::max(ncy, xs[s]->cfg.ncy);
+  }
+  HCK(x0, launch_field_convert_grp<double, float>(cin.data(), cvo.data(), nvec.data(), ns, st));
+  for (int cy = 0; cy < ncy; ++cy)
+    for (int col = 0; col < 2; ++col) {
+      sel.clear();
+      for (int s = 0; s < ns; ++s) {
+        const int nc = xs[s]->cfg.ncy;
+        if (cy >= nc) continue;
+        SapArgs<float, float> b = a[s];
+        b.col = col;
+        b.first = cy == 0;
+        b.do_bnd = !(cy == 0 && col == 0);
+        b.write_v = !(cy == nc - 1 && col == 1);
+        sel.push_back(b);
+      }
+      if (cy > 0 || col > 0) HCK(x0, launch_sap_face_grp<float, float>(sel.data(), (int)sel.size(), st));
+      for (auto& b : sel) b.do_bnd = 0;
+      HCK(x0, launch_sap_half_grp<float, float>(sel.data(), (int)sel.size(), st));
     }
   return QDD_OK;
 }

@@ -37,4 +37,10 @@ hipError_t launch_sap_half(const SapArgs<S, P>& a, int nblk_colour, hipStream_t 
 // corrections of a half-sweep, applied before it with do_bnd off)
 template <class S, class P>
 hipError_t launch_sap_face(const SapArgs<S, P>& a, hipStream_t st);
+// the same two steps for ns systems in one launch each (FP32 storage; every
+// system with the same block volume and variant, 1 or 2)
+template <class S, class P>
+hipError_t launch_sap_face_grp(const SapArgs<S, P>* a, int ns, hipStream_t st);
+template <class S, class P>
+hipError_t launch_sap_half_grp(const SapArgs<S, P>* a, int ns, hipStream_t st);
 }  // namespace qdd

@@ -71,7 +71,7 @@ __device__ inline int sap_xcd_block(int id, int nbc) {
 }
 
 template <class S, class P, int DR>
-__global__ void __launch_bounds__(256) k_sap_half(SapArgs<S, P> a) {
+__device__ __forceinline__ void sap_half_body(const SapArgs<S, P>& a, int bid, int nbid) {
   typedef typename St<S>::T T;
   typedef typename St<S>::E E;
   constexpr bool REG = sizeof(S) <= 4;  // FP32 / FP16: own links + clover in registers
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(256) k_sap_half(SapArgs<S, P> a) {
   // this block: the sap_xcd_block(blockIdx.x)-th block of colour a.col
   int bc[4];
   {
-    int bl = 2 * sap_xcd_block(blockIdx.x, gridDim.x);
+    int bl = 2 * sap_xcd_block(bid, nbid);
     int nbh3 = a.nb[3];
     bc[3] = bl % nbh3;
     int rr = bl / nbh3;
@@ -360,6 +360,17 @@ __global__ void __launch_bounds__(256) k_sap_half(SapArgs<S, P> a) {
   }
 }
 
+template <class S, class P, int DR>
+__global__ void __launch_bounds__(256) k_sap_half(SapArgs<S, P> a) {
+  sap_half_body<S, P, DR>(a, blockIdx.x, gridDim.x);
+}
+// the same half-sweep for several systems in one launch
+template <class S, class P, int DR>
+__global__ void __launch_bounds__(256) k_sap_half_grp(Grp<SapArgs<S, P>> G) {
+  const int s = grp_sys(G.start, G.ns, blockIdx.x);
+  sap_half_body<S, P, DR>(G.a[s], blockIdx.x - G.start[s], G.start[s + 1] - G.start[s]);
+}
+
 // One workgroup per (block, right-hand side): the right-hand sides of a block
 // are solved by concurrent workgroups instead of one after the other, and the
 // workgroup ids are ordered so that all of them land on the same XCD at about
@@ -374,7 +385,7 @@ __global__ void __launch_bounds__(256) k_sap_half(SapArgs<S, P> a) {
 // (L1/L2 hits), behind an opaque per-lane zero so that the compiler does not
 // hoist them out of the MR loop into registers.
 template <class S, class P, bool O32>
-__global__ void __launch_bounds__(kSapMaxHalf, 2) k_sap_rhs(SapArgs<S, P> a) {
+__device__ __forceinline__ void sap_rhs_body(const SapArgs<S, P>& a, int bid, int nbid) {
   typedef typename St<S>::T T;
   __shared__ cx<T> ex[12][kSapMaxHalf];    // hop sources (one parity of the block)
   __shared__ cx<T> ro_l[12][kSapMaxHalf];  // the odd-site source, own column only
@@ -386,7 +397,7 @@ __global__ void __launch_bounds__(kSapMaxHalf, 2) k_sap_rhs(SapArgs<S, P> a) {
   // workgroup -> (block of colour a.col, right-hand side)
   int bi, r;
   {
-    const int id = blockIdx.x, nbc = gridDim.x / a.nrhs;
+    const int id = bid, nbc = nbid / a.nrhs;
     if ((nbc & 7) == 0) {  // every XCD a contiguous range of blocks (see sap_xcd_block)
       const int rest = id >> 3;
       r = rest % a.nrhs;
@@ -621,6 +632,16 @@ __global__ void __launch_bounds__(kSapMaxHalf, 2) k_sap_rhs(SapArgs<S, P> a) {
   for (int k = 0; k < 12; ++k) zero[k] = {T(0), T(0)};
   st_spinor<S, O32>(rho[0], r, ig[0], rr);
   st_spinor<S, O32>(rho[1], r, ig[1], zero);
+}
+
+template <class S, class P, bool O32>
+__global__ void __launch_bounds__(kSapMaxHalf, 2) k_sap_rhs(SapArgs<S, P> a) {
+  sap_rhs_body<S, P, O32>(a, blockIdx.x, gridDim.x);
+}
+template <class S, class P, bool O32>
+__global__ void __launch_bounds__(kSapMaxHalf, 2) k_sap_rhs_grp(Grp<SapArgs<S, P>> G) {
+  const int s = grp_sys(G.start, G.ns, blockIdx.x);
+  sap_rhs_body<S, P, O32>(G.a[s], blockIdx.x - G.start[s], G.start[s + 1] - G.start[s]);
 }
 
 // LDS-staged variants for FP16 storage: one workgroup per (block, group of R
@@ -1229,11 +1250,11 @@ static bool sap_fits32(const FieldV<S>& f, int nrhs, int64_t poff, int64_t spoff
 // parity, so the loads of rho and V are coalesced; the half-sweep then runs
 // without its own face terms.
 template <class S, class P>
-__global__ void __launch_bounds__(256) k_sap_face(SapArgs<S, P> a) {
+__device__ __forceinline__ void sap_face_body(const SapArgs<S, P>& a, int bx) {
   typedef typename St<S>::T T;
   const Geo& g = a.g;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x, p = blockIdx.y, r = blockIdx.z;
-  if (i >= g.Vh) return;
+  const int i = bx * blockDim.x + threadIdx.x, p = blockIdx.y, r = blockIdx.z;
+  if (i >= g.Vh || r >= a.nrhs) return;
   int x[4];
   site_coords(g, p, i, x);
   int colour = 0;
@@ -1285,6 +1306,16 @@ __global__ void __launch_bounds__(256) k_sap_face(SapArgs<S, P> a) {
 #pragma unroll
   for (int k = 0; k < 12; ++k) rv[k] = cacc(rv[k], T(0.5), acc[k]);
   st_spinor<S>(rho, r, i, rv);
+}
+
+template <class S, class P>
+__global__ void __launch_bounds__(256) k_sap_face(SapArgs<S, P> a) {
+  sap_face_body<S, P>(a, blockIdx.x);
+}
+template <class S, class P>
+__global__ void __launch_bounds__(256) k_sap_face_grp(Grp<SapArgs<S, P>> G) {
+  const int s = grp_sys(G.start, G.ns, blockIdx.x);
+  sap_face_body<S, P>(G.a[s], blockIdx.x - G.start[s]);
 }
 
 template <class S, class P>
@@ -1344,6 +1375,48 @@ hipError_t launch_sap_half(const SapArgs<S, P>& a, int nblk_colour, hipStream_t 
   }
   return hipGetLastError();
 }
+
+// several systems, FP32 storage, variants 1 and 2 (every system the same
+// variant and block volume)
+template <class S, class P>
+hipError_t launch_sap_face_grp(const SapArgs<S, P>* a, int ns, hipStream_t st) {
+  if (ns < 1 || ns > kGrpMax) return hipErrorInvalidValue;
+  Grp<SapArgs<S, P>> G = grp_new<SapArgs<S, P>>();
+  for (int s = 0; s < ns; ++s) grp_add(G, a[s], (a[s].g.Vh + 255) / 256, a[s].nrhs);
+  hipLaunchKernelGGL((k_sap_face_grp<S, P>), dim3(G.start[ns], 2, G.ny), dim3(256), 0, st, G);
+  return hipGetLastError();
+}
+
+template <class S, class P>
+hipError_t launch_sap_half_grp(const SapArgs<S, P>* a, int ns, hipStream_t st) {
+  static_assert(sizeof(S) == 4, "grouped half-sweeps: FP32 storage");
+  if (ns < 1 || ns > kGrpMax) return hipErrorInvalidValue;
+  const int nsb = a[0].bs[0] * a[0].bs[1] * a[0].bs[2] * a[0].bs[3];
+  const int v = a[0].variant ? a[0].variant : kSapPerSite;
+  if (nsb > 2 * kSapMaxHalf) return hipErrorInvalidValue;
+  Grp<SapArgs<S, P>> G = grp_new<SapArgs<S, P>>();
+  bool o32 = true;
+  for (int s = 0; s < ns; ++s) {
+    const SapArgs<S, P>& b = a[s];
+    const int vs = b.variant ? b.variant : kSapPerSite;
+    if (b.bs[0] * b.bs[1] * b.bs[2] * b.bs[3] != nsb || vs != v) return hipErrorInvalidValue;
+    const int nblk = b.nb[0] * b.nb[1] * b.nb[2] * b.nb[3] / 2;
+    o32 = o32 && sap_fits32(b.rho, b.nrhs, b.poff, b.spoff) && sap_fits32(b.V, b.nrhs, b.poff, b.spoff) &&
+          sap_fits32(b.psi, b.nrhs, b.poff, b.spoff);
+    grp_add(G, b, v == kSapPerRhs ? nblk * b.nrhs : nblk);
+  }
+  if (v == kSapPerSite) {
+    hipLaunchKernelGGL((k_sap_half_grp<S, P, 4>), dim3(G.start[ns]), dim3(nsb), 0, st, G);
+  } else if (v == kSapPerRhs) {
+    if (o32) hipLaunchKernelGGL((k_sap_rhs_grp<S, P, true>), dim3(G.start[ns]), dim3(nsb / 2), 0, st, G);
+    else hipLaunchKernelGGL((k_sap_rhs_grp<S, P, false>), dim3(G.start[ns]), dim3(nsb / 2), 0, st, G);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_sap_face_grp<float, float>(const SapArgs<float, float>*, int, hipStream_t);
+template hipError_t launch_sap_half_grp<float, float>(const SapArgs<float, float>*, int, hipStream_t);
 
 template hipError_t launch_sap_half<double, double>(const SapArgs<double, double>&, int, hipStream_t);
 template hipError_t launch_sap_face<double, double>(const SapArgs<double, double>&, hipStream_t);

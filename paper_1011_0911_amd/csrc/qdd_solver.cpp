@@ -17,6 +17,22 @@
 
 using namespace qdd;
 
+// back substitution of one right-hand side's m steps: R alpha = c with the
+// Gram-Schmidt coefficients of chi_l on chi_0 .. chi_{l-1} (ah, row stride kMaxKv
+// per rhs and step), the norms b_j and c_j = <chi_j, r_j>; al: kMaxKv entries
+void fgcr_backsub(const double2* ah, const double* bh, const double2* chh, int nr, int i, int m, double2* al) {
+  for (int j = m - 1; j >= 0; --j) {
+    double sr = chh[(size_t)j * nr + i].x, si = chh[(size_t)j * nr + i].y;
+    for (int l = j + 1; l < m; ++l) {
+      double2 a2 = ah[((size_t)l * nr + i) * kMaxKv + j], b2 = al[l];
+      sr -= a2.x * b2.x - a2.y * b2.y;
+      si -= a2.x * b2.y + a2.y * b2.x;
+    }
+    double bj = bh[(size_t)j * nr + i];
+    al[j] = bj > 0 ? double2{sr / bj, si / bj} : double2{0.0, 0.0};
+  }
+}
+
 qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qdd_solve_info* info) {
   const Layout& lo = x->lo;
   hipStream_t st = x->st;
@@ -143,17 +159,7 @@ qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qd
           HCK(x, hipMemcpyAsync(chh.data(), chist, (size_t)m * nr * sizeof(double2), hipMemcpyDeviceToHost, st));
           HCK(x, hipStreamSynchronize(st));
           std::fill(al.begin(), al.end(), double2{0.0, 0.0});
-          for (int i : cap)
-            for (int j = m - 1; j >= 0; --j) {
-              double sr = chh[(size_t)j * nr + i].x, si = chh[(size_t)j * nr + i].y;
-              for (int l = j + 1; l < m; ++l) {
-                double2 a2 = ah[((size_t)l * nr + i) * kMaxKv + j], b2 = al[(size_t)i * kMaxKv + l];
-                sr -= a2.x * b2.x - a2.y * b2.y;
-                si -= a2.x * b2.y + a2.y * b2.x;
-              }
-              double bj = bh[(size_t)j * nr + i];
-              al[(size_t)i * kMaxKv + j] = bj > 0 ? double2{sr / bj, si / bj} : double2{0.0, 0.0};
-            }
+          for (int i : cap) fgcr_backsub(ah.data(), bh.data(), chh.data(), nr, i, m, al.data() + (size_t)i * kMaxKv);
           HCK(x, hipMemcpyAsync(alpha, al.data(), (size_t)nr * kMaxKv * sizeof(double2), hipMemcpyHostToDevice, st));
           for (int i : cap) {
             HCK(x, launch_scale_to_f<double2>(hv.r + (int64_t)hv.n * n, r + (int64_t)i * n, 1.0, n, st));
@@ -199,19 +205,7 @@ qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qd
     HCK(x, hipMemcpyAsync(chh.data(), chist, (size_t)kk * nr * sizeof(double2), hipMemcpyDeviceToHost, st));
     HCK(x, hipStreamSynchronize(st));
     std::fill(al.begin(), al.end(), double2{0.0, 0.0});
-    for (int i = 0; i < nr; ++i) {
-      int m = ks[i];
-      for (int j = m - 1; j >= 0; --j) {
-        double sr = chh[(size_t)j * nr + i].x, si = chh[(size_t)j * nr + i].y;
-        for (int l = j + 1; l < m; ++l) {
-          double2 a = ah[((size_t)l * nr + i) * kMaxKv + j], b = al[(size_t)i * kMaxKv + l];
-          sr -= a.x * b.x - a.y * b.y;
-          si -= a.x * b.y + a.y * b.x;
-        }
-        double bj = bh[(size_t)j * nr + i];
-        al[(size_t)i * kMaxKv + j] = bj > 0 ? double2{sr / bj, si / bj} : double2{0.0, 0.0};
-      }
-    }
+    for (int i = 0; i < nr; ++i) fgcr_backsub(ah.data(), bh.data(), chh.data(), nr, i, ks[i], al.data() + (size_t)i * kMaxKv);
     HCK(x, hipMemcpyAsync(alpha, al.data(), (size_t)nr * kMaxKv * sizeof(double2), hipMemcpyHostToDevice, st));
     if (F.phi32)
       HCK(x, launch_axpy_multi<float2>(psi, n, (const float2*)phi, lstride, n, kk, alpha, kMaxKv, 1.0, n, nr, nullptr,

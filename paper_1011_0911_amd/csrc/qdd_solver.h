@@ -28,5 +28,12 @@ struct FgcrOps {
 };
 
 qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qdd_solve_info* info);
+// alpha (al[0 .. m)) of right-hand side i from the host copies of the Gram-Schmidt
+// coefficients (ah), the norms (bh) and the projections (chh) of m steps
+void fgcr_backsub(const double2* ah, const double* bh, const double2* chh, int nr, int i, int m, double2* al);
+// the Schwarz preconditioner of ns systems (FP32 storage), every stage one launch
+// over all systems: psi[s] = M_sap eta[s] (st: the stream of the whole group)
+qdd_status sap_apply_grp(qdd_ctx* const* xs, const int* nrhs, const double2* const* eta, void* const* psi, int ns,
+                         hipStream_t st);
 // operator D (FP64) and the configured preconditioner for qdd_solve
 qdd_status make_solver_ops(qdd_ctx* x, int nrhs, FgcrOps& F);

@@ -98,6 +98,8 @@ SIGNATURES = {
     "qdd_dfl_share": (_i, [_vp, _vp]),
     "qdd_solve_multi": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(_i), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                              ctypes.POINTER(_vp)]),
+    "qdd_solve_group": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(_i), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                             ctypes.POINTER(_vp)]),
     "qdd_solve": (_i, [_vp, _i, _vp, _vp, _vp]),
     "qdd_solve_guess": (_i, [_vp, _i, _vp, _vp, _vp]),
     "qdd_chrono_reset": (_i, [_vp]),
@@ -576,6 +578,16 @@ class Context:
 def solve_multi(ctxs, etas):
     """Solves several systems concurrently (each context needs its own stream).
     Returns (psis, infos, status)."""
+    return _solve_systems("qdd_solve_multi", ctxs, etas)
+
+
+def solve_group(ctxs, etas):
+    """Solves several systems with one launch per solver stage over all of them
+    (qdd_solve_group; all on the stream of ctxs[0]).  Returns (psis, infos, status)."""
+    return _solve_systems("qdd_solve_group", ctxs, etas)
+
+
+def _solve_systems(entry, ctxs, etas):
     n = len(ctxs)
     H = (ctypes.c_void_p * n)(*[c.h for c in ctxs])
     nr = (ctypes.c_int * n)()
@@ -597,7 +609,7 @@ def solve_multi(ctxs, etas):
         I[k] = ctypes.cast(inf, ctypes.c_void_p)
     for c in ctxs:
         torch.cuda.current_stream(c.device).synchronize()
-    st = lib().qdd_solve_multi(H, n, nr, E, P, I)
+    st = getattr(lib(), entry)(H, n, nr, E, P, I)
     return psis, [[i.as_dict() for i in inf] for inf in infos], st
 
 

@@ -86,3 +86,65 @@ def test_solve_multi_matches_single_solves(Q, orc, kind):
         for r in range(eta.shape[0]):
             res = np.linalg.norm(eta[r] - orc.apply_D(L, U, A, psi[r])) / np.linalg.norm(eta[r])
             assert inf[r]["converged"] and res <= 1e-10
+
+
+@pytest.mark.parametrize("kind", ["sap1", "sap2", "none"])
+def test_solve_group_matches_single_solves(Q, orc, kind):
+    # one launch per stage over all systems (lattice sizes, masses, batch sizes and
+    # Schwarz block shapes of one volume differ; one system needs far fewer
+    # iterations and leaves the lockstep cycles early): every system gets bit for
+    # bit the solution and iteration counts of its own solve, true residual <= 1e-10
+    import torch
+
+    systems = [((8, 8, 8, 8), 0.1357, (4, 4, 4, 4), 3), ((16, 8, 8, 8), 0.1355, (4, 4, 4, 4), 1),
+               ((8, 4, 8, 16), 0.1350, (4, 2, 4, 8), 2), ((8, 8, 8, 8), 0.1200, (4, 4, 4, 4), 2)]
+    ctxs, etas, refs = [], [], []
+    for k, (L, kappa, bs, nr) in enumerate(systems):
+        V = int(np.prod(L))
+        cfg = dict(sap_bs=bs, sap_prec=1, precond=Q.PRECOND_SAP, nkv=6, nmx=400)
+        if kind == "none":
+            cfg.update(precond=Q.PRECOND_NONE, nkv=12, nmx=2000)
+        c, U = _system(Q, L, kappa, 740 + k, nr, **cfg)
+        if kind == "sap2":
+            c.set_launch(Q.KERNEL_SAP, Q.F32, 0, 2, 0, 0)
+        ctxs.append(c)
+        etas.append(S.gaussian_field(V, 750 + k, nrhs=nr))
+        A, _ = orc.clover(L, U, kappa, 1.9)
+        refs.append((L, U, A))
+    print(f"group solve {kind}: {[s[0] for s in systems]}", flush=True)
+    psis, infos, st = Q.solve_group(ctxs, etas)
+    assert st == 0
+    torch.cuda.synchronize()
+    for c, eta, psi, inf, (L, U, A) in zip(ctxs, etas, psis, infos, refs):
+        single, sinf, sst = c.solve(eta)
+        torch.cuda.synchronize()
+        assert sst == 0
+        assert [i["iters"] for i in inf] == [i["iters"] for i in sinf]
+        assert torch.equal(psi, single)
+        psi = to_np(psi)
+        for r in range(eta.shape[0]):
+            res = np.linalg.norm(eta[r] - orc.apply_D(L, U, A, psi[r])) / np.linalg.norm(eta[r])
+            assert inf[r]["converged"] and res <= 1e-10 and abs(inf[r]["true_res"] - res) < 1e-11
+
+
+def test_solve_group_twice_and_rejections(Q):
+    # a second grouped call on the same contexts (state left by the first) gives the
+    # same result; systems that cannot be grouped are refused with a reason
+    import torch
+
+    a, _ = _system(Q, (8, 8, 8, 8), 0.1357, 761, 2, sap_bs=(4, 4, 4, 4), sap_prec=1, precond=Q.PRECOND_SAP)
+    b, _ = _system(Q, (8, 4, 8, 16), 0.1350, 762, 2, sap_bs=(4, 2, 4, 8), sap_prec=1, precond=Q.PRECOND_SAP)
+    ea, eb = S.gaussian_field(4096, 763, nrhs=2), S.gaussian_field(4096, 764, nrhs=1)
+    p1, i1, s1 = Q.solve_group([a, b], [ea, eb])
+    p2, i2, s2 = Q.solve_group([a, b], [ea, eb])
+    torch.cuda.synchronize()
+    assert s1 == 0 and s2 == 0
+    assert all(torch.equal(x, y) for x, y in zip(p1, p2))
+    c, _ = _system(Q, (8, 8, 8, 8), 0.1357, 765, 2, sap_bs=(4, 4, 4, 4), sap_prec=2, precond=Q.PRECOND_SAP)
+    _, _, st = Q.solve_group([a, c], [ea, ea])
+    assert st == Q.QDD_EINVAL and "FP32" in Q.lib().qdd_last_error(a.h).decode()
+    d, _ = _system(Q, (8, 8, 8, 8), 0.1357, 766, 2, sap_bs=(4, 4, 4, 4), precond=Q.PRECOND_NONE)
+    _, _, st = Q.solve_group([a, d], [ea, ea])
+    assert st == Q.QDD_EINVAL and "preconditioner" in Q.lib().qdd_last_error(a.h).decode()
+    _, _, st = Q.solve_group([a, a], [ea, ea])
+    assert st == Q.QDD_EINVAL and "twice" in Q.lib().qdd_last_error(a.h).decode()
