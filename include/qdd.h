@@ -264,7 +264,7 @@ qdd_status qdd_solve_multi(qdd_ctx* const* ctxs, int nsys, const int* nrhs, cons
  * right-hand sides have all converged leaves the tables until the cycle ends,
  * and per-rhs device masks freeze converged right-hand sides.  Each system gets
  * exactly the result its own qdd_solve gives (same kernels, same reduction
- * blocking).  All work runs on the stream of ctxs[0].  Needs 1 to 8 contexts on
+ * blocking).  All work runs on the stream of ctxs[0].  Needs 1 to 12 contexts on
  * one device, all with the Schwarz preconditioner in FP32 storage (equal block
  * volume and kernel variant) or all with none, chrono_nv = 0; QDD_EINVAL with
  * the reason in ctxs[0]'s error text otherwise.  eta[s], psi[s], info[s] as for

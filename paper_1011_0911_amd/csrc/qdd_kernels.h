@@ -65,7 +65,7 @@ hipError_t launch_dw(const Geo& g, const DevOp<S>& op, FieldV<S> in, FieldV<S> o
 // exactly what its own launch would.  The table travels by value in the
 // kernel-argument segment; ny is the extent of the second grid dimension (the
 // largest right-hand-side count), whose surplus workgroups exit at once.
-constexpr int kGrpMax = 8;
+constexpr int kGrpMax = 12;
 template <class A>
 struct Grp {
   A a[kGrpMax];

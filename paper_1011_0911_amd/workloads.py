@@ -241,61 +241,97 @@ def run_learned(wid: int = 5, train_pairs: int | None = None, chunk_pairs: int =
     return out
 
 
-def run_multi(wid: int = 4, nkv: int = 8, log=print):
+def run_multi(wid: int = 4, nkv: int = 8, precond: str = "sap", log=print):
     """Batched uneven solves: every lattice of the workload at every mass, nrhs
-    right-hand sides each, all systems solved concurrently (own context and
-    stream each).  The deflation subspace is built once per lattice at the middle
-    mass and shared with the other masses.  The same systems are then solved one
-    after the other for comparison.  Returns a dict."""
+    right-hand sides each.  precond "sap": FP32 Schwarz preconditioner, no
+    deflation; the systems are solved (1) as one group, every solver stage one
+    launch over all systems (qdd_solve_group), (2) concurrently on their own
+    streams from host threads (qdd_solve_multi) and (3) one after the other.
+    precond "dfl": the deflated solver (subspace built once per lattice at the
+    middle mass and shared with the other masses), modes (2) and (3).  The
+    Schwarz kernel variant tuned for the largest lattice is used by all systems.
+    Returns a dict."""
     import torch
 
     w = WORKLOADS[wid]
     nrhs = w["nrhs"]
+    dfl = precond == "dfl"
     ctxs, etas, names = [], [], []
     t_setup = time.time()
     t_build = 0.0
+    extra = dict(nkv=nkv) if dfl else dict(nkv=nkv, precond=qdd.PRECOND_SAP, dfl_Ns=0)
     for li, L in enumerate(w["lattices"]):
         V = int(np.prod(L))
         U = S.random_su3_links(L, w["eps"], S.gauge_seed(wid) + 10 * li)
-        init = S.gaussian_field(V, S.dfl_seed(wid) + 10 * li, nrhs=w["dfl_Ns"])
         group = []
         for ki, kappa in enumerate(w["kappas"]):
             c, _ = make_context(L, w["eps"], kappa, w["csw"], 0, U=U, tune_nrhs=nrhs, stream=torch.cuda.Stream(),
-                                **solver_config(w, nrhs, nkv=nkv))
+                                **solver_config(w, nrhs, **extra))
             group.append(c)
             etas.append(np.stack([S.gaussian_field(V, S.source_seed(wid, 10 * li + r) + ki) for r in range(nrhs)]))
             names.append(f"{'x'.join(map(str, L))}/k{kappa}")
-        mid = len(group) // 2
-        torch.cuda.synchronize()
-        t0 = time.time()
-        group[mid].dfl_build(init)
-        for k, c in enumerate(group):
-            if k != mid:
-                c.dfl_share(group[mid])
-        torch.cuda.synchronize()
-        t_build += time.time() - t0
+        if dfl:
+            init = S.gaussian_field(V, S.dfl_seed(wid) + 10 * li, nrhs=w["dfl_Ns"])
+            mid = len(group) // 2
+            torch.cuda.synchronize()
+            t0 = time.time()
+            group[mid].dfl_build(init)
+            for k, c in enumerate(group):
+                if k != mid:
+                    c.dfl_share(group[mid])
+            torch.cuda.synchronize()
+            t_build += time.time() - t0
         ctxs += group
         del U
         log(f"[w{wid}] lattice {L} ready")
-    out = {"workload": wid, "systems": len(ctxs), "nrhs_each": nrhs, "setup_s": time.time() - t_setup,
-           "dfl_build_s": t_build}
-    torch.cuda.synchronize()
-    t0 = time.time()
-    psis, infos, st = qdd.solve_multi(ctxs, etas)
-    torch.cuda.synchronize()
-    out["concurrent_s"] = time.time() - t0
-    out["status"] = st
-    out["systems_detail"] = [{"system": n, "iters": [i["iters"] for i in inf], "converged": all(i["converged"] for i in inf),
-                              "true_res_max": max(i["true_res"] for i in inf)} for n, inf in zip(names, infos)]
-    out["all_converged"] = all(d["converged"] for d in out["systems_detail"])
-    torch.cuda.synchronize()
-    t0 = time.time()
-    for c, eta in zip(ctxs, etas):
-        c.solve(eta, check=False)
-        torch.cuda.synchronize()
-    out["sequential_s"] = time.time() - t0
-    out["concurrency_speedup"] = out["sequential_s"] / out["concurrent_s"]
-    log(f"[w{wid}] concurrent {out['concurrent_s']:.3f} s sequential {out['sequential_s']:.3f} s")
+    big = max(range(len(ctxs)), key=lambda k: ctxs[k].V)
+    variant = ctxs[big].get_launch(qdd.KERNEL_SAP, w["sap_prec"])[1]
+    for c in ctxs:
+        c.set_launch(qdd.KERNEL_SAP, w["sap_prec"], 0, variant, 0, 0)
+    out = {"workload": wid, "precond": precond, "systems": len(ctxs), "nrhs_each": nrhs,
+           "setup_s": time.time() - t_setup, "sap_variant": variant}
+    if dfl:
+        out["dfl_build_s"] = t_build
+
+    def record(key, psis, infos, st, dt):
+        out[key + "_s"] = dt
+        out[key + "_status"] = st
+        out[key + "_systems"] = [{"system": n, "iters": [i["iters"] for i in inf],
+                                  "converged": all(i["converged"] for i in inf),
+                                  "true_res_max": max(i["true_res"] for i in inf)} for n, inf in zip(names, infos)]
+
+    def solve(mode):
+        if mode == "sequential":
+            psis, infos, st = [], [], 0
+            for c, eta in zip(ctxs, etas):
+                p, i, s1 = c.solve(eta, check=False)
+                torch.cuda.synchronize()
+                psis.append(p)
+                infos.append(i)
+                st = st or s1
+            return psis, infos, st
+        if mode == "threads":
+            return qdd.solve_multi(ctxs, etas)
+        return qdd.solve_group(ctxs, etas)
+
+    results = {}
+    modes = ["threads", "sequential"] if dfl else ["group", "threads", "sequential"]
+    for mode in modes:
+        # the second of two runs is timed (the first loads the kernels it uses)
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.time()
+            psis, infos, st = solve(mode)
+            torch.cuda.synchronize()
+            dt = time.time() - t0
+        record(mode, psis, infos, st, dt)
+        results[mode] = psis
+        log(f"[w{wid}] {precond} {mode}: {out[mode + '_s']:.3f} s status {st}")
+    seq = results["sequential"]
+    for mode in modes[:-1]:
+        out[mode + "_equals_sequential"] = all(torch.equal(a, b) for a, b in zip(results[mode], seq))
+    out["all_converged"] = all(d["converged"] for m in modes for d in out[m + "_systems"])
+    out["true_res_max"] = max(d["true_res_max"] for m in modes for d in out[m + "_systems"])
     return out
 
 
@@ -421,6 +457,7 @@ def main(argv=None):
     ap.add_argument("--pairs", type=int, default=None, help="training pairs (workload 5)")
     ap.add_argument("--chunk", type=int, default=64, help="pairs per streamed training chunk (workload 5)")
     ap.add_argument("--epochs", type=int, default=1)
+    ap.add_argument("--precond", choices=["sap", "dfl"], default="sap", help="workload 4: preconditioner")
     ap.add_argument("--plain-rhs", type=int, default=1,
                     help="right-hand sides timed with the plain solver (0: mixed solver only)")
     a = ap.parse_args(argv)
@@ -432,7 +469,7 @@ def main(argv=None):
     elif a.wid == "5":
         r = run_learned(5, train_pairs=a.pairs, chunk_pairs=a.chunk, epochs=a.epochs, log=log)
     elif a.wid == "4":
-        r = run_multi(4, log=log)
+        r = run_multi(4, precond=a.precond, log=log)
     else:
         r = run_solve_workload(int(a.wid), plain_rhs=a.plain_rhs, log=log)
     print(json.dumps(r, default=float), flush=True)
