@@ -400,8 +400,8 @@ qdd_status qdd_solve_harvest(qdd_ctx* ctx, int nrhs, const double* eta, double* 
  * of FP32 / FP16 storage (block, xcd and sb must be 0): 1 one lane per site with
  * its links and clover block in registers, the right-hand sides one after
  * another; 2 one workgroup per (block, right-hand side), a lane per even/odd
- * site pair; 3 (FP16 only) one workgroup per block and group of 4 right-hand
- * sides with the block's links and clover blocks staged in LDS; 4 (FP16 only)
+ * site pair; 3 one workgroup per block and group of 4 right-hand sides with
+ * the block's links (FP16: and clover blocks) staged in LDS; 4 (FP16 only)
  * one workgroup per block and pair of right-hand sides with the block's links
  * staged in LDS (two workgroups per CU).  FP64 has a
  * single kernel (qdd_get_launch reports nr 0).  The default is 3 for FP16 and 1

@@ -477,7 +477,7 @@ qdd_status qdd_set_launch(qdd_ctx* x, int kernel, qdd_prec prec, int block, int 
   if (x && kernel == 2) {
     // Schwarz half-sweep kernel variant (nr), FP32 / FP16 storage only
     if (!sap_variant_ok(prec, nr) || block != 0 || xcd != 0 || sb != 0) {
-      x->fail("qdd_set_launch: Schwarz variant must be 1 or 2 (FP32), 1..4 (FP16), other fields 0");
+      x->fail("qdd_set_launch: Schwarz variant must be 1..3 (FP32), 1..4 (FP16), other fields 0");
       return QDD_EINVAL;
     }
     x->sap_variant[prec] = nr;

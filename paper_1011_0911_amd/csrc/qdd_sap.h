@@ -16,7 +16,7 @@ struct SapArgs {
   int first;    // psi not yet written on these blocks (first cycle)
   int write_v;  // store the correction for the next half-sweep
   int variant;  // FP32/FP16 kernel: 1 per-site (registers), 2 per (block, rhs), 3 LDS-staged links and
-                // clover, 4 LDS-staged links (3 and 4: FP16)
+                // (FP16) clover, 4 rhs per workgroup, 4 LDS-staged links, 2 rhs (FP16 only)
   LinkV<S> U;
   CloverV<S> A, Ai;
   FieldV<S> rho, V;  // full fields [rhs][parity][12][Vh]
@@ -29,7 +29,7 @@ constexpr int kSapPerSite = 1, kSapPerRhs = 2, kSapStaged = 3, kSapStagedLinks =
 // the variant used when none was set: the LDS-staged kernel for FP16 storage,
 // the per-site one for FP32
 inline int sap_default_variant(int prec) { return prec == 2 ? kSapStaged : kSapPerSite; }
-inline bool sap_variant_ok(int prec, int v) { return prec != 0 && v >= 1 && v <= (prec == 2 ? 4 : 2); }
+inline bool sap_variant_ok(int prec, int v) { return prec != 0 && v >= 1 && v <= (prec == 2 ? 4 : 3); }
 
 template <class S, class P>
 hipError_t launch_sap_half(const SapArgs<S, P>& a, int nblk_colour, hipStream_t st);
@@ -38,7 +38,7 @@ hipError_t launch_sap_half(const SapArgs<S, P>& a, int nblk_colour, hipStream_t 
 template <class S, class P>
 hipError_t launch_sap_face(const SapArgs<S, P>& a, hipStream_t st);
 // the same two steps for ns systems in one launch each (FP32 storage; every
-// system with the same block volume and variant, 1 or 2)
+// system with the same block volume and variant, 1, 2 or 3)
 template <class S, class P>
 hipError_t launch_sap_face_grp(const SapArgs<S, P>* a, int ns, hipStream_t st);
 template <class S, class P>

@@ -658,8 +658,13 @@ __global__ void __launch_bounds__(kSapMaxHalf, 2) k_sap_rhs_grp(Grp<SapArgs<S, P
 // every lane writes its source spinor to the LDS exchange of its right-hand side,
 // then applies projection, link (its own forward link, or the neighbour's for a
 // backward hop, both in LDS) and reconstruction for each in-block neighbour.
+// FP32 storage (R = 4, links staged, clover from memory): the links alone take
+// 72 KB, so one workgroup fills a CU as with CL.
+template <class S, class P, int R, bool CL>
+constexpr int sap_lds_wgs() { return (CL || sizeof(S) == 4) ? 1 : 2; }
+
 template <class S, class P, int R, bool CL, bool O32>
-__global__ void __launch_bounds__(R * kSapMaxHalf, CL ? 1 : 2) k_sap_lds(SapArgs<S, P> a) {
+__device__ __forceinline__ void sap_lds_body(const SapArgs<S, P>& a, int bid, int nbid) {
   typedef typename St<S>::T T;
   typedef typename St<S>::E E;
   constexpr int H = kSapMaxHalf;
@@ -678,7 +683,7 @@ __global__ void __launch_bounds__(R * kSapMaxHalf, CL ? 1 : 2) k_sap_lds(SapArgs
   // of a block go to the same XCD one after the other
   int bi, rg;
   {
-    const int id = blockIdx.x, nbc = gridDim.x / nrg;
+    const int id = bid, nbc = nbid / nrg;
     if ((nbc & 7) == 0) {  // every XCD a contiguous range of blocks (see sap_xcd_block)
       const int rest = id >> 3;
       rg = rest % nrg;
@@ -953,6 +958,16 @@ __global__ void __launch_bounds__(R * kSapMaxHalf, CL ? 1 : 2) k_sap_lds(SapArgs
   for (int k = 0; k < 12; ++k) zero[k] = {T(0), T(0)};
   st_spinor<S, O32>(rho[0], r, ig[0], rr);
   st_spinor<S, O32>(rho[1], r, ig[1], zero);
+}
+
+template <class S, class P, int R, bool CL, bool O32>
+__global__ void __launch_bounds__(R * kSapMaxHalf, (sap_lds_wgs<S, P, R, CL>())) k_sap_lds(SapArgs<S, P> a) {
+  sap_lds_body<S, P, R, CL, O32>(a, blockIdx.x, gridDim.x);
+}
+template <class S, class P, int R, bool CL, bool O32>
+__global__ void __launch_bounds__(R * kSapMaxHalf, (sap_lds_wgs<S, P, R, CL>())) k_sap_lds_grp(Grp<SapArgs<S, P>> G) {
+  const int s = grp_sys(G.start, G.ns, blockIdx.x);
+  sap_lds_body<S, P, R, CL, O32>(G.a[s], blockIdx.x - G.start[s], G.start[s + 1] - G.start[s]);
 }
 
 // One lane per even/odd site pair of the block: lane j owns the j-th even and
@@ -1350,6 +1365,15 @@ hipError_t launch_sap_half(const SapArgs<S, P>& a, int nblk_colour, hipStream_t 
       const dim3 grid((unsigned)nblk_colour * (unsigned)a.nrhs), blk(nsb / 2);
       if (o32) hipLaunchKernelGGL((k_sap_rhs<S, P, true>), grid, blk, 0, st, a);
       else hipLaunchKernelGGL((k_sap_rhs<S, P, false>), grid, blk, 0, st, a);
+    } else if constexpr (sizeof(S) == 4) {
+      if (v != kSapStaged) return hipErrorInvalidValue;
+      // FP32: one workgroup per (block, group of 4 right-hand sides), the block's
+      // links staged in LDS, the clover blocks read from memory
+      constexpr int R = 4;
+      const int nhp = ((nsb / 2) + 63) & ~63;
+      const dim3 grid((unsigned)nblk_colour * (unsigned)((a.nrhs + R - 1) / R)), blk(R * nhp);
+      if (o32) hipLaunchKernelGGL((k_sap_lds<S, P, R, false, true>), grid, blk, 0, st, a);
+      else hipLaunchKernelGGL((k_sap_lds<S, P, R, false, false>), grid, blk, 0, st, a);
     } else if constexpr (sizeof(S) == 2) {
       const int nhp = ((nsb / 2) + 63) & ~63;
       if (v == kSapStaged) {
@@ -1376,7 +1400,7 @@ hipError_t launch_sap_half(const SapArgs<S, P>& a, int nblk_colour, hipStream_t 
   return hipGetLastError();
 }
 
-// several systems, FP32 storage, variants 1 and 2 (every system the same
+// several systems, FP32 storage, variants 1, 2 and 3 (every system the same
 // variant and block volume)
 template <class S, class P>
 hipError_t launch_sap_face_grp(const SapArgs<S, P>* a, int ns, hipStream_t st) {
@@ -1403,13 +1427,17 @@ hipError_t launch_sap_half_grp(const SapArgs<S, P>* a, int ns, hipStream_t st) {
     const int nblk = b.nb[0] * b.nb[1] * b.nb[2] * b.nb[3] / 2;
     o32 = o32 && sap_fits32(b.rho, b.nrhs, b.poff, b.spoff) && sap_fits32(b.V, b.nrhs, b.poff, b.spoff) &&
           sap_fits32(b.psi, b.nrhs, b.poff, b.spoff);
-    grp_add(G, b, v == kSapPerRhs ? nblk * b.nrhs : nblk);
+    grp_add(G, b, v == kSapPerRhs ? nblk * b.nrhs : v == kSapStaged ? nblk * ((b.nrhs + 3) / 4) : nblk);
   }
   if (v == kSapPerSite) {
     hipLaunchKernelGGL((k_sap_half_grp<S, P, 4>), dim3(G.start[ns]), dim3(nsb), 0, st, G);
   } else if (v == kSapPerRhs) {
     if (o32) hipLaunchKernelGGL((k_sap_rhs_grp<S, P, true>), dim3(G.start[ns]), dim3(nsb / 2), 0, st, G);
     else hipLaunchKernelGGL((k_sap_rhs_grp<S, P, false>), dim3(G.start[ns]), dim3(nsb / 2), 0, st, G);
+  } else if (v == kSapStaged) {
+    const dim3 blk(4 * (((nsb / 2) + 63) & ~63));
+    if (o32) hipLaunchKernelGGL((k_sap_lds_grp<S, P, 4, false, true>), dim3(G.start[ns]), blk, 0, st, G);
+    else hipLaunchKernelGGL((k_sap_lds_grp<S, P, 4, false, false>), dim3(G.start[ns]), blk, 0, st, G);
   } else {
     return hipErrorInvalidValue;
   }

@@ -430,7 +430,7 @@ def time_sap(L=(64, 32, 32, 32), prec=qdd.F16, nrhs=8, reps=3, log=print):
                           max_nrhs=nrhs, sap_prec=prec, precond=qdd.PRECOND_SAP, nkv=1)
     eta = S.gaussian_field_device(V, 77, nrhs)
     out = {"lattice": "x".join(map(str, L)), "prec": prec, "nrhs": nrhs, "ms_per_call": {}}
-    for v in ((1, 2, 3, 4) if prec == qdd.F16 else (1, 2)):
+    for v in ((1, 2, 3, 4) if prec == qdd.F16 else (1, 2, 3)):
         ctx.set_launch(qdd.KERNEL_SAP, prec, 0, v, 0, 0)
         ctx.sap(eta)
         torch.cuda.synchronize()
@@ -458,6 +458,8 @@ def main(argv=None):
     ap.add_argument("--chunk", type=int, default=64, help="pairs per streamed training chunk (workload 5)")
     ap.add_argument("--epochs", type=int, default=1)
     ap.add_argument("--precond", choices=["sap", "dfl"], default="sap", help="workload 4: preconditioner")
+    ap.add_argument("--sap-prec", type=int, default=qdd.F16, help="sap: storage precision (1 FP32, 2 FP16)")
+    ap.add_argument("--nrhs", type=int, default=8, help="sap: right-hand sides")
     ap.add_argument("--plain-rhs", type=int, default=1,
                     help="right-hand sides timed with the plain solver (0: mixed solver only)")
     a = ap.parse_args(argv)
@@ -465,7 +467,7 @@ def main(argv=None):
     if a.wid == "net":
         r = time_network(5, log=log)
     elif a.wid == "sap":
-        r = time_sap(log=log)
+        r = time_sap(prec=a.sap_prec, nrhs=a.nrhs, log=log)
     elif a.wid == "5":
         r = run_learned(5, train_pairs=a.pairs, chunk_pairs=a.chunk, epochs=a.epochs, log=log)
     elif a.wid == "4":

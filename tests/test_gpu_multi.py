@@ -88,10 +88,10 @@ def test_solve_multi_matches_single_solves(Q, orc, kind):
             assert inf[r]["converged"] and res <= 1e-10
 
 
-@pytest.mark.parametrize("kind", ["sap1", "sap2", "none"])
+@pytest.mark.parametrize("kind", ["sap1", "sap2", "sap3", "none"])
 def test_solve_group_matches_single_solves(Q, orc, kind):
     # one launch per stage over all systems (lattice sizes, masses, batch sizes and
-    # Schwarz block shapes of one volume differ; one system needs far fewer
+    # Schwarz block shapes of one volume differ, every FP32 Schwarz variant; one system needs far fewer
     # iterations and leaves the lockstep cycles early): every system gets bit for
     # bit the solution and iteration counts of its own solve, true residual <= 1e-10
     import torch
@@ -105,8 +105,8 @@ def test_solve_group_matches_single_solves(Q, orc, kind):
         if kind == "none":
             cfg.update(precond=Q.PRECOND_NONE, nkv=12, nmx=2000)
         c, U = _system(Q, L, kappa, 740 + k, nr, **cfg)
-        if kind == "sap2":
-            c.set_launch(Q.KERNEL_SAP, Q.F32, 0, 2, 0, 0)
+        if kind in ("sap2", "sap3"):
+            c.set_launch(Q.KERNEL_SAP, Q.F32, 0, int(kind[-1]), 0, 0)
         ctxs.append(c)
         etas.append(S.gaussian_field(V, 750 + k, nrhs=nr))
         A, _ = orc.clover(L, U, kappa, 1.9)

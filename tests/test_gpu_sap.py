@@ -32,10 +32,10 @@ def Q():
 
 
 # every kernel variant of each storage precision (FP64 has one): 1 per site with
-# links in registers, 2 per (block, rhs), for FP16 also 3 (links and clover staged
-# in LDS, 4 rhs per workgroup) and 4 (links staged, 2 rhs per workgroup); 5 rhs so
-# that the staged variants also run a partly filled group
-VARIANTS = [(0, 0), (1, 1), (1, 2), (2, 1), (2, 2), (2, 3), (2, 4)]
+# links in registers, 2 per (block, rhs), 3 (links, for FP16 also the clover,
+# staged in LDS, 4 rhs per workgroup) and for FP16 4 (links staged, 2 rhs per
+# workgroup); 5 rhs so that the staged variants also run a partly filled group
+VARIANTS = [(0, 0), (1, 1), (1, 2), (1, 3), (2, 1), (2, 2), (2, 3), (2, 4)]
 
 
 @pytest.mark.parametrize("L,bs,ncy,nmr", [((8, 8, 8, 8), (4, 4, 4, 4), 5, 4), ((8, 4, 4, 8), (2, 2, 2, 2), 3, 2),
@@ -60,7 +60,7 @@ def test_sap_parity(Q, orc, L, bs, ncy, nmr, prec, variant):
 
 def test_sap_variants_rejected_where_missing(Q):
     ctx, _ = make_ctx(Q, (4, 4, 4, 4), 0.6, 0.1357, 1.9, 509, sap_bs=(2, 2, 2, 2), sap_prec=1)
-    for prec, v in ((1, 3), (0, 1), (2, 5), (1, 0)):
+    for prec, v in ((1, 4), (0, 1), (2, 5), (1, 0)):
         with pytest.raises(Q.QddError):
             ctx.set_launch(Q.KERNEL_SAP, prec, 0, v, 0, 0)
     with pytest.raises(Q.QddError):
