@@ -1256,31 +1256,53 @@ static bool sap_fits32(const FieldV<S>& f, int nrhs, int64_t poff, int64_t spoff
   return e < lim && sc < lim;
 }
 
-// Face corrections of a half-sweep as a kernel of their own: for every site of
-// the blocks of colour a.col (both parities) and every right-hand side,
-//   rho += 1/2 H_face V,
-// the hops across the block faces from the sites of the neighbouring blocks
-// (the other colour), whose corrections V the previous half-sweep stored.  One
-// lane per site and right-hand side, consecutive lanes on consecutive sites of a
-// parity, so the loads of rho and V are coalesced; the half-sweep then runs
+// Face corrections of a half-sweep (the hops across the block faces from the
+// sites of the neighbouring blocks, the other colour, whose corrections V the
+// previous half-sweep stored):
+//   rho += 1/2 H_face V.
+// One lane per site of the blocks of colour a.col: the lanes enumerate only
+// those sites (in an x3 row of a parity they are the runs of bs3/2 consecutive
+// sites of every other block), load the links of the site's faces once and loop
+// over the right-hand sides; consecutive lanes take consecutive sites, so the
+// loads of rho and V are coalesced in runs of bs3/2.  The half-sweep then runs
 // without its own face terms.
 template <class S, class P>
 __device__ __forceinline__ void sap_face_body(const SapArgs<S, P>& a, int bx) {
   typedef typename St<S>::T T;
   const Geo& g = a.g;
-  const int i = bx * blockDim.x + threadIdx.x, p = blockIdx.y, r = blockIdx.z;
-  if (i >= g.Vh || r >= a.nrhs) return;
+  const int t = bx * blockDim.x + threadIdx.x, p = blockIdx.y;
+  const int hb = a.bs[3] >> 1, per_row = g.Lh3 >> 1;  // colour sites of a parity per x3 row
+  if (t >= (g.Vh >> 1)) return;
+  const int row = t / per_row, jr = t - row * per_row;
   int x[4];
-  site_coords(g, p, i, x);
-  int colour = 0;
+  x[2] = row % g.L[2];
+  x[1] = (row / g.L[2]) % g.L[1];
+  x[0] = row / (g.L[2] * g.L[1]);
+  const int k = jr / hb, o = jr - k * hb;
+  const int bc3 = 2 * k + ((a.col + x[0] / a.bs[0] + x[1] / a.bs[1] + x[2] / a.bs[2]) & 1);
+  const int i = row * g.Lh3 + bc3 * hb + o;
+  x[3] = 2 * (bc3 * hb + o) + ((p + x[0] + x[1] + x[2]) & 1);
   int y[4];
 #pragma unroll
+  for (int m = 0; m < 4; ++m) y[m] = x[m] - (x[m] / a.bs[m]) * a.bs[m];
+  // the faces of the site: at most one per direction (even block extents >= 2);
+  // their links kept in the storage type (FP16: half the registers)
+  typedef typename St<S>::E E;
+  E ur[4][9];
+  int nb[4], dir[4];
+  bool any = false;
+#pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const int b = x[m] / a.bs[m];
-    y[m] = x[m] - b * a.bs[m];
-    colour += b;
+    dir[m] = y[m] == a.bs[m] - 1 ? 1 : (y[m] == 0 ? -1 : 0);
+    nb[m] = 0;
+    // forward neighbour in the next block: the site's own link; backward: the neighbour's
+    if (dir[m] != 0) nb[m] = nbr_idx(g, x, m, dir[m]);
+    const E* ub = a.U.p + (int64_t)((dir[m] > 0 ? p : 1 - p) * 4 + m) * 9 * a.U.n + (dir[m] > 0 ? i : nb[m]);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) ur[m][c] = dir[m] != 0 ? ub[(int64_t)c * a.U.n] : E{};
+    any = any || dir[m] != 0;
   }
-  if ((colour & 1) != a.col) return;
+  if (!any) return;  // an interior site: nothing crosses a face
   FieldV<S> rho = a.rho, vn = a.V;
   rho.p += (int64_t)p * a.poff;
   vn.p += (int64_t)(1 - p) * a.poff;
@@ -1288,54 +1310,64 @@ __device__ __forceinline__ void sap_face_body(const SapArgs<S, P>& a, int bx) {
     rho.scale += (int64_t)p * a.spoff;
     vn.scale += (int64_t)(1 - p) * a.spoff;
   }
-  cx<T> acc[12];
+#pragma unroll 1
+  for (int r = 0; r < a.nrhs; ++r) {
+    cx<T> acc[12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = {T(0), T(0)};
-  bool any = false;
+    for (int c = 0; c < 12; ++c) acc[c] = {T(0), T(0)};
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    cx<T> sv[12], h[6], gg[6], u[9];
-    if (y[m] == a.bs[m] - 1) {  // forward neighbour in the next block
-      any = true;
-      ld_spinor<S>(vn, r, nbr_idx(g, x, m, +1), sv);
-      ld_link(a.U, p, m, i, u);
-      if (m == 0) { project<T, 0, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 0, +1>(gg, acc); }
-      else if (m == 1) { project<T, 1, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 1, +1>(gg, acc); }
-      else if (m == 2) { project<T, 2, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 2, +1>(gg, acc); }
-      else { project<T, 3, +1>(sv, h); su3_mul_half<T, false>(u, h, gg); reconstruct_add<T, 3, +1>(gg, acc); }
+    for (int m = 0; m < 4; ++m) {
+      cx<T> sv[12], h[6], gg[6], u[4][9];
+      // FP16: convert at every use (an opaque copy of the stored link per
+      // right-hand side keeps the compiler from holding all converted links)
+      if constexpr (sizeof(S) == 2) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          uint32_t w = __builtin_bit_cast(uint32_t, ur[m][c]);
+          asm volatile("" : "+v"(w));
+          u[m][c] = St<S>::from(__builtin_bit_cast(E, w));
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) u[m][c] = St<S>::from(ur[m][c]);
+      }
+      if (dir[m] > 0) {
+        ld_spinor<S>(vn, r, nb[m], sv);
+        if (m == 0) { project<T, 0, +1>(sv, h); su3_mul_half<T, false>(u[m], h, gg); reconstruct_add<T, 0, +1>(gg, acc); }
+        else if (m == 1) { project<T, 1, +1>(sv, h); su3_mul_half<T, false>(u[m], h, gg); reconstruct_add<T, 1, +1>(gg, acc); }
+        else if (m == 2) { project<T, 2, +1>(sv, h); su3_mul_half<T, false>(u[m], h, gg); reconstruct_add<T, 2, +1>(gg, acc); }
+        else { project<T, 3, +1>(sv, h); su3_mul_half<T, false>(u[m], h, gg); reconstruct_add<T, 3, +1>(gg, acc); }
+      } else if (dir[m] < 0) {
+        ld_spinor<S>(vn, r, nb[m], sv);
+        if (m == 0) { project<T, 0, -1>(sv, h); su3_mul_half<T, true>(u[m], h, gg); reconstruct_add<T, 0, -1>(gg, acc); }
+        else if (m == 1) { project<T, 1, -1>(sv, h); su3_mul_half<T, true>(u[m], h, gg); reconstruct_add<T, 1, -1>(gg, acc); }
+        else if (m == 2) { project<T, 2, -1>(sv, h); su3_mul_half<T, true>(u[m], h, gg); reconstruct_add<T, 2, -1>(gg, acc); }
+        else { project<T, 3, -1>(sv, h); su3_mul_half<T, true>(u[m], h, gg); reconstruct_add<T, 3, -1>(gg, acc); }
+      }
     }
-    if (y[m] == 0) {  // backward neighbour in the previous block
-      any = true;
-      const int jn = nbr_idx(g, x, m, -1);
-      ld_spinor<S>(vn, r, jn, sv);
-      ld_link(a.U, 1 - p, m, jn, u);
-      if (m == 0) { project<T, 0, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 0, -1>(gg, acc); }
-      else if (m == 1) { project<T, 1, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 1, -1>(gg, acc); }
-      else if (m == 2) { project<T, 2, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 2, -1>(gg, acc); }
-      else { project<T, 3, -1>(sv, h); su3_mul_half<T, true>(u, h, gg); reconstruct_add<T, 3, -1>(gg, acc); }
-    }
+    cx<T> rv[12];
+    ld_spinor<S>(rho, r, i, rv);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) rv[c] = cacc(rv[c], T(0.5), acc[c]);
+    st_spinor<S>(rho, r, i, rv);
   }
-  if (!any) return;  // an interior site: nothing crosses a face
-  cx<T> rv[12];
-  ld_spinor<S>(rho, r, i, rv);
-#pragma unroll
-  for (int k = 0; k < 12; ++k) rv[k] = cacc(rv[k], T(0.5), acc[k]);
-  st_spinor<S>(rho, r, i, rv);
 }
 
+// (FP32 / FP16: at least two wavefronts per SIMD; the loop over the right-hand
+// sides keeps the face links and up to four neighbour spinors live)
 template <class S, class P>
-__global__ void __launch_bounds__(256) k_sap_face(SapArgs<S, P> a) {
+__global__ void __launch_bounds__(256, sizeof(S) == 8 ? 1 : 2) k_sap_face(SapArgs<S, P> a) {
   sap_face_body<S, P>(a, blockIdx.x);
 }
 template <class S, class P>
-__global__ void __launch_bounds__(256) k_sap_face_grp(Grp<SapArgs<S, P>> G) {
+__global__ void __launch_bounds__(256, sizeof(S) == 8 ? 1 : 2) k_sap_face_grp(Grp<SapArgs<S, P>> G) {
   const int s = grp_sys(G.start, G.ns, blockIdx.x);
   sap_face_body<S, P>(G.a[s], blockIdx.x - G.start[s]);
 }
 
 template <class S, class P>
 hipError_t launch_sap_face(const SapArgs<S, P>& a, hipStream_t st) {
-  const dim3 grid((unsigned)((a.g.Vh + 255) / 256), 2, (unsigned)a.nrhs), blk(256);
+  const dim3 grid((unsigned)((a.g.Vh / 2 + 255) / 256), 2), blk(256);
   hipLaunchKernelGGL((k_sap_face<S, P>), grid, blk, 0, st, a);
   return hipGetLastError();
 }
@@ -1406,8 +1438,8 @@ template <class S, class P>
 hipError_t launch_sap_face_grp(const SapArgs<S, P>* a, int ns, hipStream_t st) {
   if (ns < 1 || ns > kGrpMax) return hipErrorInvalidValue;
   Grp<SapArgs<S, P>> G = grp_new<SapArgs<S, P>>();
-  for (int s = 0; s < ns; ++s) grp_add(G, a[s], (a[s].g.Vh + 255) / 256, a[s].nrhs);
-  hipLaunchKernelGGL((k_sap_face_grp<S, P>), dim3(G.start[ns], 2, G.ny), dim3(256), 0, st, G);
+  for (int s = 0; s < ns; ++s) grp_add(G, a[s], (a[s].g.Vh / 2 + 255) / 256);
+  hipLaunchKernelGGL((k_sap_face_grp<S, P>), dim3(G.start[ns], 2), dim3(256), 0, st, G);
   return hipGetLastError();
 }
 
