@@ -4,6 +4,11 @@
       per-kernel call count and average / total duration from a
       `rocprofv3 --kernel-trace --stats` run (markdown table on stdout)
 
+  python -m paper_1011_0911_amd.profsum phases DIR [--gap-ms 50] [--top 5] [--names a,b,...]
+      the kernel trace of a `rocprofv3 --kernel-trace` run cut into phases where
+      the GPU idles longer than the gap between kernels: span, kernel-busy time
+      and the largest kernels of each phase (markdown table on stdout)
+
   python -m paper_1011_0911_amd.profsum traffic --bench-json F --fetch DIR --write DIR --out J --cmd "..."
       HBM bytes per launch of the Dhat pass-B kernel from two `rocprofv3 --pmc`
       runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what
@@ -127,12 +132,44 @@ def traffic(bench_json: str, fetch_dir: str, write_dir: str, out_path: str, cmd:
     return entry
 
 
+def phases(d: str, gap_ms: float = 50.0, top: int = 5, names=None) -> str:
+    with open(_one(d, "*kernel_trace.csv")) as f:
+        rows = sorted(csv.DictReader(f), key=lambda r: int(r["Start_Timestamp"]))
+    segs, cur, prev = [], [], None
+    for r in rows:
+        s0, e0 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        if prev is not None and s0 - prev > gap_ms * 1e6:
+            segs.append(cur)
+            cur = []
+        cur.append(r)
+        prev = e0 if prev is None else max(prev, e0)
+    if cur:
+        segs.append(cur)
+    out = ["| phase | span ms | kernel busy ms | largest kernels (ms) |", "|---|---|---|---|"]
+    for k, sg in enumerate(segs):
+        span = (max(int(r["End_Timestamp"]) for r in sg) - int(sg[0]["Start_Timestamp"])) / 1e6
+        per = {}
+        for r in sg:
+            n = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            per[n] = per.get(n, 0.0) + (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+        busy = sum(per.values())
+        big = ", ".join(f"{n} {v:.1f}" for n, v in sorted(per.items(), key=lambda x: -x[1])[:top])
+        label = names[k] if names and k < len(names) else str(k)
+        out.append(f"| {label} | {span:.1f} | {busy:.1f} | {big} |")
+    return "\n".join(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sp = ap.add_subparsers(dest="what", required=True)
     a = sp.add_parser("stats")
     a.add_argument("dir")
     a.add_argument("--cmd", required=True)
+    h = sp.add_parser("phases")
+    h.add_argument("dir")
+    h.add_argument("--gap-ms", type=float, default=50.0)
+    h.add_argument("--top", type=int, default=5)
+    h.add_argument("--names", default=None)
     t = sp.add_parser("traffic")
     t.add_argument("--bench-json", required=True)
     t.add_argument("--fetch", required=True)
@@ -142,6 +179,8 @@ def main(argv=None):
     o = ap.parse_args(argv)
     if o.what == "stats":
         print(stats(o.dir, o.cmd))
+    elif o.what == "phases":
+        print(phases(o.dir, o.gap_ms, o.top, o.names.split(",") if o.names else None))
     else:
         e = traffic(o.bench_json, o.fetch, o.write, o.out, o.cmd)
         json.dump(e, sys.stdout, indent=1)
