@@ -254,6 +254,11 @@ def solve_section(learned_pairs, U=None):
             "learned_terms1": {k: r5["learned_terms1"][k] for k in ("solve_s", "iters", "fallbacks", "true_res_max",
                                                                      "converged")},
             "learned_terms1_over_plain_time": r5["learned_terms1"]["solve_s"] / r5["plain"]["solve_s"],
+            "learned_first_calls": {
+                f"calls{c}_terms{t}": {k: r5[f"learned_calls{c}_terms{t}"][k]
+                                        for k in ("solve_s", "iters", "true_res_max", "converged")}
+                for c in (1, 2) for t in (3, 1)},
+            "learned_calls2_terms1_over_plain_time": r5["learned_calls2_terms1"]["solve_s"] / r5["plain"]["solve_s"],
             "loss_first": r5["loss_first"], "loss_last": r5["loss_last"],
             "harvest_s": r5["harvest_s"], "train_s": r5["train_s"]}
     return sec

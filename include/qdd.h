@@ -373,6 +373,12 @@ qdd_status qdd_net_get_weights(qdd_ctx* ctx, float* w);
 /* Sets net_terms (1, 2 or 3; see qdd_config) for the later network
  * applications of this context; QDD_EINVAL otherwise. */
 qdd_status qdd_net_set_terms(qdd_ctx* ctx, int terms);
+/* The solver's network stage runs in the first `calls` preconditioner
+ * applications of every solve (each outer FGCR iteration applies the
+ * preconditioner once to the whole batch) and is skipped after them, so that
+ * later iterations cost what the method without the network costs; 0 (the
+ * default) = every application.  QDD_EINVAL for calls < 0. */
+qdd_status qdd_net_set_calls(qdd_ctx* ctx, int calls);
 /* out = N(in), canonical complex128 full fields (one field). */
 qdd_status qdd_net_forward(qdd_ctx* ctx, const double* in, double* out);
 /* Loss l = sum_i |N(r_i/|r_i|) - e_i/|r_i||^2 / sum_i |e_i/|r_i||^2 over nb pairs

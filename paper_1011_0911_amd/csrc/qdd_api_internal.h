@@ -57,6 +57,8 @@ struct qdd_ctx {
   double kappa = 0, csw = 0;
   long coarse_iters = 0;  // little-operator GCR iterations since the last solve began
   int net_step = 0;       // Adam steps taken
+  int net_calls = 0;      // network stage in the first net_calls preconditioner applications of a solve (0 = all)
+  int net_calls_done = 0;  // network-stage applications in the current solve
   std::vector<int> fallbacks;  // network stage rejected, per rhs of the current solve
   std::vector<double> dw_shift_host;  // source of the per-rhs mass shifts copied to the device
   struct Harvest* harvest = nullptr;  // pair capture of the next solve (qdd_solve_harvest)

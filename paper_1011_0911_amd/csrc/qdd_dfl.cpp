@@ -250,7 +250,8 @@ static qdd_status dfl_apply(qdd_ctx* x, int nrhs, const double2* r, EP* phi, dou
   (void)tcoarse;
   if constexpr (!F64) {
     // the network stage; not during a pair harvest, whose pairs are those of the plain method
-    if (x->cfg.use_net && x->have_net && !x->harvest) {
+    if (x->cfg.use_net && x->have_net && !x->harvest && (x->net_calls == 0 || x->net_calls_done < x->net_calls)) {
+      ++x->net_calls_done;
       float2* vn = x->ptr<float2>(lo.net_tmp);
       double2* r2 = x->ptr<double2>(lo.t64);
       std::vector<int> fb;

@@ -168,6 +168,15 @@ extern "C" qdd_status qdd_net_set_terms(qdd_ctx* x, int terms) {
   return QDD_OK;
 }
 
+extern "C" qdd_status qdd_net_set_calls(qdd_ctx* x, int calls) {
+  if (!x) return QDD_EINVAL;
+  qdd_status s = net_check(x, false);
+  if (s != QDD_OK) return s;
+  if (calls < 0) { x->fail("qdd_net_set_calls: calls must be >= 0"); return QDD_EINVAL; }
+  x->net_calls = calls;
+  return QDD_OK;
+}
+
 extern "C" qdd_status qdd_net_get_weights(qdd_ctx* x, float* w) {
   if (!x || !w) return QDD_EINVAL;
   qdd_status s = net_check(x, true);

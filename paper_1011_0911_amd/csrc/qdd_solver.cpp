@@ -52,6 +52,7 @@ qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qd
   auto chi_k = [&](int k) { return chi + (size_t)k * lstride; };
 
   auto t0 = std::chrono::steady_clock::now();
+  x->net_calls_done = 0;  // a new solve: the network stage counts its applications afresh
   std::vector<double> tstage(8, 0.0);
   auto tic = [&]() { return std::chrono::steady_clock::now(); };
   auto since = [&](std::chrono::steady_clock::time_point a) {

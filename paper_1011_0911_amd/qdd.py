@@ -110,6 +110,7 @@ SIGNATURES = {
     "qdd_net_set_weights": (_i, [_vp, _vp]),
     "qdd_net_get_weights": (_i, [_vp, _vp]),
     "qdd_net_set_terms": (_i, [_vp, _i]),
+    "qdd_net_set_calls": (_i, [_vp, _i]),
     "qdd_net_forward": (_i, [_vp, _vp, _vp]),
     "qdd_net_loss_grad": (_i, [_vp, _i, _vp, _vp, ctypes.POINTER(_d), _vp]),
     "qdd_net_train_step": (_i, [_vp, _i, _vp, _vp, ctypes.c_float, ctypes.POINTER(_d)]),
@@ -479,6 +480,11 @@ class Context:
     def net_set_terms(self, terms: int):
         """BF16 terms per activation in later network applications (3 exact, 2, 1)."""
         self._check(lib().qdd_net_set_terms(self.h, int(terms)))
+
+    def net_set_calls(self, calls: int):
+        """Network stage only in the first `calls` preconditioner applications of
+        each solve (0 = every application)."""
+        self._check(lib().qdd_net_set_calls(self.h, int(calls)))
 
     def net_get_weights(self):
         t = torch.empty(self.net_num_weights(), dtype=torch.complex64, device=self.device)

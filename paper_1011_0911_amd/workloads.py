@@ -223,6 +223,16 @@ def run_learned(wid: int = 5, train_pairs: int | None = None, chunk_pairs: int =
                              "fallbacks": [i["fallbacks"] for i in info],
                              "true_res_max": max(i["true_res"] for i in info),
                              "converged": all(i["converged"] for i in info), "t_ms": info[0]["t_ms"]}
+    # the network stage only in the first 1 or 2 outer iterations of the solve
+    for calls in (1, 2):
+        ctx.net_set_calls(calls)
+        for terms in (3, 1):
+            ctx.net_set_terms(terms)
+            psi, info, st, dt = timed_solve(ctx, eta)
+            out[f"learned_calls{calls}_terms{terms}"] = {
+                "solve_s": dt, "iters": [i["iters"] for i in info], "fallbacks": [i["fallbacks"] for i in info],
+                "true_res_max": max(i["true_res"] for i in info), "converged": all(i["converged"] for i in info)}
+    ctx.net_set_calls(0)
     ctx.net_set_terms(3)
     ctx.net_set_weights(np.zeros(nw, complex))  # zero network: the stage adds nothing, plain iterates
     psi0, info0, st0, dt0 = timed_solve(ctx, eta)

@@ -271,3 +271,23 @@ def test_trained_network_cuts_outer_iterations(Q, orc):
           f"fallbacks {[i['fallbacks'] for i in info]}")
     assert losses[-1] < 0.5 * losses[0]
     assert all(a < b for a, b in zip(it, it0))
+    # the stage limited to the first preconditioner applications of each solve:
+    # a limit above the iteration count changes nothing (bit for bit), a limit of
+    # 2 still converges to 1e-10 under the oracle's D, in no more iterations than
+    # the plain solver
+    import torch
+
+    ctx.net_set_calls(1000)
+    psi_l, info_l, _ = ctx.solve(test)
+    assert torch.equal(psi_l, psi) and [i["iters"] for i in info_l] == it
+    ctx.net_set_calls(2)
+    psi2, info2, _ = ctx.solve(test)
+    it2 = [i["iters"] for i in info2]
+    for r in range(4):
+        res = np.linalg.norm(test[r] - orc.apply_D(L, U, A, to_np(psi2)[r])) / np.linalg.norm(test[r])
+        assert info2[r]["converged"] and res <= 1e-10
+    print(f"outer iterations with the stage in the first 2 applications: {it2}")
+    assert all(a <= b for a, b in zip(it2, it0))
+    with pytest.raises(Q.QddError):
+        ctx.net_set_calls(-1)
+    ctx.net_set_calls(0)
