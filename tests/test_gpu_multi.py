@@ -148,3 +148,35 @@ def test_solve_group_twice_and_rejections(Q):
     assert st == Q.QDD_EINVAL and "preconditioner" in Q.lib().qdd_last_error(a.h).decode()
     _, _, st = Q.solve_group([a, a], [ea, ea])
     assert st == Q.QDD_EINVAL and "twice" in Q.lib().qdd_last_error(a.h).decode()
+
+
+def test_solve_group_restarts_and_iteration_cap(Q):
+    # systems with different restart lengths (restart cycles end at different
+    # steps) and an iteration cap reached in the middle of a cycle: every system
+    # still gets bit for bit its own solve's iterate, iteration count and status
+    import torch
+
+    L, bs = (8, 8, 8, 8), (4, 4, 4, 4)
+    specs = [(0.1357, dict(nkv=2, nmx=400)), (0.1355, dict(nkv=5, nmx=400)), (0.1350, dict(nkv=6, nmx=3))]
+    ctxs, etas = [], []
+    for k, (kappa, extra) in enumerate(specs):
+        c, _ = _system(Q, L, kappa, 770 + k, 2, sap_bs=bs, sap_prec=1, precond=Q.PRECOND_SAP, ncy=1, nmr=1, **extra)
+        ctxs.append(c)
+        etas.append(S.gaussian_field(4096, 780 + k, nrhs=2))
+    psis, infos, st = Q.solve_group(ctxs, etas)
+    torch.cuda.synchronize()
+    assert st == Q.QDD_ENOCONV  # the capped system does not converge
+    for k, (c, eta, psi, inf) in enumerate(zip(ctxs, etas, psis, infos)):
+        single, sinf, sst = c.solve(eta, check=False)
+        torch.cuda.synchronize()
+        print(f"system {k}: group iters {[i['iters'] for i in inf]} restarts {[i['restarts'] for i in inf]}, "
+              f"single {[i['iters'] for i in sinf]}")
+        assert torch.equal(psi, single)
+        for a, b in zip(inf, sinf):
+            assert (a["iters"], a["restarts"], a["converged"]) == (b["iters"], b["restarts"], b["converged"])
+            assert a["true_res"] == b["true_res"]
+        if k < 2:
+            assert sst == 0 and all(i["converged"] for i in inf)
+            assert k == 1 or max(i["restarts"] for i in inf) > 0  # nkv 2: restarts for sure
+        else:
+            assert sst == Q.QDD_ENOCONV and all(i["iters"] == 3 and not i["converged"] for i in inf)
