@@ -265,8 +265,9 @@ qdd_status qdd_solve_multi(qdd_ctx* const* ctxs, int nsys, const int* nrhs, cons
  * and per-rhs device masks freeze converged right-hand sides.  Each system gets
  * exactly the result its own qdd_solve gives (same kernels, same reduction
  * blocking).  All work runs on the stream of ctxs[0].  Needs 1 to 12 contexts on
- * one device, all with the Schwarz preconditioner in FP32 storage (equal block
- * volume and kernel variant) or all with none, chrono_nv = 0; QDD_EINVAL with
+ * one device, all with the Schwarz preconditioner in one storage precision,
+ * FP32 or FP16 (equal block volume and kernel variant), or all with none,
+ * chrono_nv = 0; QDD_EINVAL with
  * the reason in ctxs[0]'s error text otherwise.  eta[s], psi[s], info[s] as for
  * qdd_solve_multi; QDD_ENOCONV if any rhs fails (its context holds the text). */
 qdd_status qdd_solve_group(qdd_ctx* const* ctxs, int nsys, const int* nrhs, const double* const* eta,

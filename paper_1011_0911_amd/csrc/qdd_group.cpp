@@ -61,12 +61,14 @@ std::string group_check(qdd_ctx* const* xs, int ns, const int* nrhs) {
     if (x->cfg.precond != QDD_PRECOND_NONE && x->cfg.precond != QDD_PRECOND_SAP)
       return "grouped solves take the Schwarz preconditioner or none";
     if (x->cfg.precond == QDD_PRECOND_SAP) {
-      if (x->cfg.sap_prec != QDD_F32) return "grouped Schwarz solves run with FP32 storage";
+      if (x->cfg.sap_prec == QDD_F64) return "grouped Schwarz solves run with FP32 or FP16 storage";
+      if (x->cfg.sap_prec != a->cfg.sap_prec) return "Schwarz storage precisions differ";
       const int* b = x->cfg.sap_bs;
       const int* b0 = a->cfg.sap_bs;
       if (b[0] * b[1] * b[2] * b[3] != b0[0] * b0[1] * b0[2] * b0[3]) return "Schwarz blocks of different volumes";
-      const int v = x->sap_variant[QDD_F32] ? x->sap_variant[QDD_F32] : kSapPerSite;
-      const int v0 = a->sap_variant[QDD_F32] ? a->sap_variant[QDD_F32] : kSapPerSite;
+      const int p = x->cfg.sap_prec;
+      const int v = x->sap_variant[p] ? x->sap_variant[p] : sap_default_variant(p);
+      const int v0 = a->sap_variant[p] ? a->sap_variant[p] : sap_default_variant(p);
       if (v != v0) return "different Schwarz kernel variants";
     }
     if (x->lo.phi32 != a->lo.phi32) return "different preconditioner output precisions";

@@ -175,6 +175,8 @@ template hipError_t launch_field_convert_grp<double, float>(const FieldV<double>
                                                             int, hipStream_t);
 template hipError_t launch_field_convert_grp<float, double>(const FieldV<float>*, const FieldV<double>*, const int*,
                                                             int, hipStream_t);
+template hipError_t launch_field_convert_grp<double, __half>(const FieldV<double>*, const FieldV<__half>*,
+                                                             const int*, int, hipStream_t);
 
 template <class SI, class SO>
 hipError_t launch_field_convert(FieldV<SI> in, FieldV<SO> out, int nvec, hipStream_t st) {

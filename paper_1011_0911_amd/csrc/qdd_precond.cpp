@@ -82,48 +82,58 @@ static qdd_status sap_run(qdd_ctx* x, int nrhs, const double2* eta, typename St<
   return QDD_OK;
 }
 
-// the same for ns systems with FP32 storage, every step one launch over the
-// systems that still take part in it (systems may differ in lattice, mass,
-// batch size, block shape of equal volume and cycle count)
-qdd_status sap_apply_grp(qdd_ctx* const* xs, const int* nrhs, const double2* const* eta, void* const* psi, int ns,
-                         hipStream_t st) {
+// the same for ns systems with FP32 or FP16 storage (psi FP32), every step one
+// launch over the systems that still take part in it (systems may differ in
+// lattice, mass, batch size, block shape of equal volume and cycle count)
+template <class S>
+static qdd_status sap_grp_run(qdd_ctx* const* xs, const int* nrhs, const double2* const* eta, void* const* psi,
+                              int ns, hipStream_t st) {
   qdd_ctx* x0 = xs[0];
-  if (ns < 1 || ns > kGrpMax) {
-    x0->fail("grouped Schwarz: 1 to %d systems", kGrpMax);
-    return QDD_EINVAL;
-  }
-  std::vector<SapArgs<float, float>> a(ns), sel;
+  std::vector<SapArgs<S, float>> a(ns), sel;
   std::vector<FieldV<double>> cin(ns);
-  std::vector<FieldV<float>> cvo(ns);
+  std::vector<FieldV<S>> cvo(ns);
   std::vector<int> nvec(ns);
   int ncy = 0;
   for (int s = 0; s < ns; ++s) {
     int nblk = 0;
-    a[s] = sap_args<float, float>(xs[s], nrhs[s], (float2*)psi[s], &nblk);
+    a[s] = sap_args<S, float>(xs[s], nrhs[s], (float2*)psi[s], &nblk);
     cin[s] = vec_view<double>(xs[s], eta[s], nullptr);
-    cvo[s] = vec_view<float>(xs[s], a[s].rho.p, nullptr);
+    cvo[s] = vec_view<S>(xs[s], a[s].rho.p, a[s].rho.scale);
     nvec[s] = 2 * nrhs[s];
     ncy = std::max(ncy, xs[s]->cfg.ncy);
   }
-  HCK(x0, launch_field_convert_grp<double, float>(cin.data(), cvo.data(), nvec.data(), ns, st));
+  HCK(x0, launch_field_convert_grp<double, S>(cin.data(), cvo.data(), nvec.data(), ns, st));
   for (int cy = 0; cy < ncy; ++cy)
     for (int col = 0; col < 2; ++col) {
       sel.clear();
       for (int s = 0; s < ns; ++s) {
         const int nc = xs[s]->cfg.ncy;
         if (cy >= nc) continue;
-        SapArgs<float, float> b = a[s];
+        SapArgs<S, float> b = a[s];
         b.col = col;
         b.first = cy == 0;
         b.do_bnd = !(cy == 0 && col == 0);
         b.write_v = !(cy == nc - 1 && col == 1);
         sel.push_back(b);
       }
-      if (cy > 0 || col > 0) HCK(x0, launch_sap_face_grp<float, float>(sel.data(), (int)sel.size(), st));
+      if (cy > 0 || col > 0) HCK(x0, launch_sap_face_grp<S, float>(sel.data(), (int)sel.size(), st));
       for (auto& b : sel) b.do_bnd = 0;
-      HCK(x0, launch_sap_half_grp<float, float>(sel.data(), (int)sel.size(), st));
+      HCK(x0, launch_sap_half_grp<S, float>(sel.data(), (int)sel.size(), st));
     }
   return QDD_OK;
+}
+
+qdd_status sap_apply_grp(qdd_ctx* const* xs, const int* nrhs, const double2* const* eta, void* const* psi, int ns,
+                         hipStream_t st) {
+  if (ns < 1 || ns > kGrpMax) {
+    xs[0]->fail("grouped Schwarz: 1 to %d systems", kGrpMax);
+    return QDD_EINVAL;
+  }
+  switch (xs[0]->cfg.sap_prec) {
+    case QDD_F32: return sap_grp_run<float>(xs, nrhs, eta, psi, ns, st);
+    case QDD_F16: return sap_grp_run<__half>(xs, nrhs, eta, psi, ns, st);
+    default: xs[0]->fail("grouped Schwarz: FP32 or FP16 storage"); return QDD_EINVAL;
+  }
 }
 
 // dispatch on the configured SAP precision; psi storage: FP64 for F64, else FP32

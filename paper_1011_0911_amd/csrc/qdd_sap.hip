@@ -1432,8 +1432,8 @@ hipError_t launch_sap_half(const SapArgs<S, P>& a, int nblk_colour, hipStream_t 
   return hipGetLastError();
 }
 
-// several systems, FP32 storage, variants 1, 2 and 3 (every system the same
-// variant and block volume)
+// several systems, FP32 storage (variants 1, 2, 3) or FP16 storage (1 to 4),
+// every system with the same variant and block volume
 template <class S, class P>
 hipError_t launch_sap_face_grp(const SapArgs<S, P>* a, int ns, hipStream_t st) {
   if (ns < 1 || ns > kGrpMax) return hipErrorInvalidValue;
@@ -1445,21 +1445,24 @@ hipError_t launch_sap_face_grp(const SapArgs<S, P>* a, int ns, hipStream_t st) {
 
 template <class S, class P>
 hipError_t launch_sap_half_grp(const SapArgs<S, P>* a, int ns, hipStream_t st) {
-  static_assert(sizeof(S) == 4, "grouped half-sweeps: FP32 storage");
+  static_assert(sizeof(S) <= 4, "grouped half-sweeps: FP32 or FP16 storage");
   if (ns < 1 || ns > kGrpMax) return hipErrorInvalidValue;
   const int nsb = a[0].bs[0] * a[0].bs[1] * a[0].bs[2] * a[0].bs[3];
-  const int v = a[0].variant ? a[0].variant : kSapPerSite;
+  const int vdef = sap_default_variant(sizeof(S) == 2 ? 2 : 1);
+  const int v = a[0].variant ? a[0].variant : vdef;
   if (nsb > 2 * kSapMaxHalf) return hipErrorInvalidValue;
   Grp<SapArgs<S, P>> G = grp_new<SapArgs<S, P>>();
   bool o32 = true;
   for (int s = 0; s < ns; ++s) {
     const SapArgs<S, P>& b = a[s];
-    const int vs = b.variant ? b.variant : kSapPerSite;
+    const int vs = b.variant ? b.variant : vdef;
     if (b.bs[0] * b.bs[1] * b.bs[2] * b.bs[3] != nsb || vs != v) return hipErrorInvalidValue;
     const int nblk = b.nb[0] * b.nb[1] * b.nb[2] * b.nb[3] / 2;
     o32 = o32 && sap_fits32(b.rho, b.nrhs, b.poff, b.spoff) && sap_fits32(b.V, b.nrhs, b.poff, b.spoff) &&
           sap_fits32(b.psi, b.nrhs, b.poff, b.spoff);
-    grp_add(G, b, v == kSapPerRhs ? nblk * b.nrhs : v == kSapStaged ? nblk * ((b.nrhs + 3) / 4) : nblk);
+    const int per = v == kSapPerRhs ? b.nrhs : v == kSapStaged ? (b.nrhs + 3) / 4
+                    : v == kSapStagedLinks ? (b.nrhs + 1) / 2 : 1;
+    grp_add(G, b, nblk * per);
   }
   if (v == kSapPerSite) {
     hipLaunchKernelGGL((k_sap_half_grp<S, P, 4>), dim3(G.start[ns]), dim3(nsb), 0, st, G);
@@ -1467,9 +1470,19 @@ hipError_t launch_sap_half_grp(const SapArgs<S, P>* a, int ns, hipStream_t st) {
     if (o32) hipLaunchKernelGGL((k_sap_rhs_grp<S, P, true>), dim3(G.start[ns]), dim3(nsb / 2), 0, st, G);
     else hipLaunchKernelGGL((k_sap_rhs_grp<S, P, false>), dim3(G.start[ns]), dim3(nsb / 2), 0, st, G);
   } else if (v == kSapStaged) {
+    // 4 rhs per workgroup; FP16 also stages the clover blocks
+    constexpr bool CL = sizeof(S) == 2;
     const dim3 blk(4 * (((nsb / 2) + 63) & ~63));
-    if (o32) hipLaunchKernelGGL((k_sap_lds_grp<S, P, 4, false, true>), dim3(G.start[ns]), blk, 0, st, G);
-    else hipLaunchKernelGGL((k_sap_lds_grp<S, P, 4, false, false>), dim3(G.start[ns]), blk, 0, st, G);
+    if (o32) hipLaunchKernelGGL((k_sap_lds_grp<S, P, 4, CL, true>), dim3(G.start[ns]), blk, 0, st, G);
+    else hipLaunchKernelGGL((k_sap_lds_grp<S, P, 4, CL, false>), dim3(G.start[ns]), blk, 0, st, G);
+  } else if (v == kSapStagedLinks) {
+    if constexpr (sizeof(S) == 2) {
+      const dim3 blk(2 * (((nsb / 2) + 63) & ~63));
+      if (o32) hipLaunchKernelGGL((k_sap_lds_grp<S, P, 2, false, true>), dim3(G.start[ns]), blk, 0, st, G);
+      else hipLaunchKernelGGL((k_sap_lds_grp<S, P, 2, false, false>), dim3(G.start[ns]), blk, 0, st, G);
+    } else {
+      return hipErrorInvalidValue;
+    }
   } else {
     return hipErrorInvalidValue;
   }
@@ -1477,6 +1490,8 @@ hipError_t launch_sap_half_grp(const SapArgs<S, P>* a, int ns, hipStream_t st) {
 }
 template hipError_t launch_sap_face_grp<float, float>(const SapArgs<float, float>*, int, hipStream_t);
 template hipError_t launch_sap_half_grp<float, float>(const SapArgs<float, float>*, int, hipStream_t);
+template hipError_t launch_sap_face_grp<__half, float>(const SapArgs<__half, float>*, int, hipStream_t);
+template hipError_t launch_sap_half_grp<__half, float>(const SapArgs<__half, float>*, int, hipStream_t);
 
 template hipError_t launch_sap_half<double, double>(const SapArgs<double, double>&, int, hipStream_t);
 template hipError_t launch_sap_face<double, double>(const SapArgs<double, double>&, hipStream_t);

@@ -88,7 +88,7 @@ def test_solve_multi_matches_single_solves(Q, orc, kind):
             assert inf[r]["converged"] and res <= 1e-10
 
 
-@pytest.mark.parametrize("kind", ["sap1", "sap2", "sap3", "none"])
+@pytest.mark.parametrize("kind", ["sap1", "sap2", "sap3", "f16v3", "f16v4", "none"])
 def test_solve_group_matches_single_solves(Q, orc, kind):
     # one launch per stage over all systems (lattice sizes, masses, batch sizes and
     # Schwarz block shapes of one volume differ, every FP32 Schwarz variant; one system needs far fewer
@@ -101,12 +101,14 @@ def test_solve_group_matches_single_solves(Q, orc, kind):
     ctxs, etas, refs = [], [], []
     for k, (L, kappa, bs, nr) in enumerate(systems):
         V = int(np.prod(L))
-        cfg = dict(sap_bs=bs, sap_prec=1, precond=Q.PRECOND_SAP, nkv=6, nmx=400)
+        cfg = dict(sap_bs=bs, sap_prec=2 if kind.startswith("f16") else 1, precond=Q.PRECOND_SAP, nkv=6, nmx=400)
         if kind == "none":
             cfg.update(precond=Q.PRECOND_NONE, nkv=12, nmx=2000)
         c, U = _system(Q, L, kappa, 740 + k, nr, **cfg)
         if kind in ("sap2", "sap3"):
             c.set_launch(Q.KERNEL_SAP, Q.F32, 0, int(kind[-1]), 0, 0)
+        if kind == "f16v4":
+            c.set_launch(Q.KERNEL_SAP, Q.F16, 0, 4, 0, 0)
         ctxs.append(c)
         etas.append(S.gaussian_field(V, 750 + k, nrhs=nr))
         A, _ = orc.clover(L, U, kappa, 1.9)
@@ -142,7 +144,10 @@ def test_solve_group_twice_and_rejections(Q):
     assert all(torch.equal(x, y) for x, y in zip(p1, p2))
     c, _ = _system(Q, (8, 8, 8, 8), 0.1357, 765, 2, sap_bs=(4, 4, 4, 4), sap_prec=2, precond=Q.PRECOND_SAP)
     _, _, st = Q.solve_group([a, c], [ea, ea])
-    assert st == Q.QDD_EINVAL and "FP32" in Q.lib().qdd_last_error(a.h).decode()
+    assert st == Q.QDD_EINVAL and "precisions differ" in Q.lib().qdd_last_error(a.h).decode()
+    f, _ = _system(Q, (8, 8, 8, 8), 0.1357, 767, 2, sap_bs=(4, 4, 4, 4), sap_prec=0, precond=Q.PRECOND_SAP)
+    _, _, st = Q.solve_group([f, a], [ea, ea])
+    assert st == Q.QDD_EINVAL and "FP32 or FP16" in Q.lib().qdd_last_error(f.h).decode()
     d, _ = _system(Q, (8, 8, 8, 8), 0.1357, 766, 2, sap_bs=(4, 4, 4, 4), precond=Q.PRECOND_NONE)
     _, _, st = Q.solve_group([a, d], [ea, ea])
     assert st == Q.QDD_EINVAL and "preconditioner" in Q.lib().qdd_last_error(a.h).decode()
