@@ -123,6 +123,10 @@ typedef struct {
                        restarts; kernels run asynchronously, so a stage's GPU time is
                        counted where the host next waits (the Gram-Schmidt reductions);
                        only index 0 is a GPU-inclusive wall time */
+  double gpu_ms[4]; /* GPU time of the stages, from HIP events on the solver's stream:
+                       0 preconditioner, 1 operator (with the FP32 -> FP64 conversion),
+                       2 Gram-Schmidt and residual update, 3 the restarts (solution
+                       update and true residual); shared by the rhs of a batch */
 } qdd_solve_info;
 
 typedef struct {

@@ -99,6 +99,8 @@ extern "C" qdd_status qdd_solve_group(qdd_ctx* const* ctxs, int nsys, const int*
   for (int s = 1; s < nsys; ++s) HCK(ctxs[s], hipStreamSynchronize(ctxs[s]->st));
   const auto t0 = std::chrono::steady_clock::now();
   double tstage[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  StageEvents ev;
+  HCK(x0, ev.init());
   auto tic = []() { return std::chrono::steady_clock::now(); };
   auto since = [](std::chrono::steady_clock::time_point a) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
@@ -230,6 +232,7 @@ extern "C" qdd_status qdd_solve_group(qdd_ctx* const* ctxs, int nsys, const int*
     for (int k = 0; !run.empty(); ++k) {
       // phi_k = M(r)
       auto ta = tic();
+      HCK(x0, ev.mark(0, st));
       if (ctxs[0]->cfg.precond == QDD_PRECOND_SAP) {
         std::vector<qdd_ctx*> xs;
         std::vector<int> nr;
@@ -249,6 +252,7 @@ extern "C" qdd_status qdd_solve_group(qdd_ctx* const* ctxs, int nsys, const int*
                                  hipMemcpyDeviceToDevice, st));
       }
       tstage[1] += since(ta);
+      HCK(x0, ev.mark(1, st));
       ta = tic();
       // chi_k = D phi_k (FP64; an FP32 phi converted first)
       {
@@ -274,6 +278,7 @@ extern "C" qdd_status qdd_solve_group(qdd_ctx* const* ctxs, int nsys, const int*
         HCK(x0, launch_dw_grp<double>(a.data(), (int)a.size(), dcfg, st));
       }
       tstage[2] += since(ta);
+      HCK(x0, ev.mark(2, st));
       ta = tic();
       // Gram-Schmidt against chi_0 .. chi_{k-1}, two passes, then normalise
       {
@@ -330,8 +335,10 @@ extern "C" qdd_status qdd_solve_group(qdd_ctx* const* ctxs, int nsys, const int*
         HCK(x0, launch_axpy_multi_grp<double2>(ax.data(), (int)ax.size(), st));
         q = r_sqnorm(run);
         if (q != QDD_OK) return q;
+        HCK(x0, ev.mark(3, st));
         q = fetch_rn2(run);
         if (q != QDD_OK) return q;
+        HCK(x0, ev.add(0, 3));
       }
       tstage[3] += since(ta);
       // per-rhs convergence of the recursive residual; systems leave the cycle
@@ -383,6 +390,7 @@ extern "C" qdd_status qdd_solve_group(qdd_ctx* const* ctxs, int nsys, const int*
       // the staged copy must not be overwritten before it has been taken
       HCK(x0, hipStreamSynchronize(st));
     }
+    HCK(x0, ev.mark(3, st));
     if (S[live[0]].phi32) {
       std::vector<AxpyArgs<float2>> ax;
       for (int s : live) {
@@ -412,8 +420,10 @@ extern "C" qdd_status qdd_solve_group(qdd_ctx* const* ctxs, int nsys, const int*
     }
     q = r_sqnorm(live);
     if (q != QDD_OK) return q;
+    HCK(x0, ev.mark(4, st));
     q = fetch_rn2(live);
     if (q != QDD_OK) return q;
+    HCK(x0, ev.add(3, 4));
     tstage[7] += since(ta);
     for (int s : live) {
       Sys& y = S[s];
@@ -454,6 +464,7 @@ extern "C" qdd_status qdd_solve_group(qdd_ctx* const* ctxs, int nsys, const int*
         f.true_res = y.etan[i] > 0 ? y.rn[i] / y.etan[i] : 0.0;
         for (int j = 1; j < 8; ++j) f.t_ms[j] = tstage[j];
         f.t_ms[0] = tot;
+        for (int j = 0; j < 4; ++j) f.gpu_ms[j] = ev.gpu_ms[j];
       }
     }
     if (!ok) {

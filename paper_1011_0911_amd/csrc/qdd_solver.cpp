@@ -54,6 +54,8 @@ qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qd
   auto t0 = std::chrono::steady_clock::now();
   x->net_calls_done = 0;  // a new solve: the network stage counts its applications afresh
   std::vector<double> tstage(8, 0.0);
+  StageEvents ev;
+  HCK(x, ev.init());
   auto tic = [&]() { return std::chrono::steady_clock::now(); };
   auto since = [&](std::chrono::steady_clock::time_point a) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
@@ -104,11 +106,13 @@ qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qd
     int k = 0;
     for (; k < nkv && total_it < nmx; ++k) {
       auto ta = tic();
+      HCK(x, ev.mark(0, st));
       // phi_k = M(r)
       qdd_status s = F.prec(r, phi_k(k));
       if (s != QDD_OK) return s;
       if (F.sync_stages) HCK(x, hipStreamSynchronize(st));
       tstage[1] += since(ta);
+      HCK(x, ev.mark(1, st));
       ta = tic();
       // chi_k = D phi_k
       if (F.phi32) {
@@ -124,6 +128,7 @@ qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qd
       if (s != QDD_OK) return s;
       if (F.sync_stages) HCK(x, hipStreamSynchronize(st));
       tstage[2] += since(ta);
+      HCK(x, ev.mark(2, st));
       ta = tic();
       // Gram-Schmidt against chi_0 .. chi_{k-1}, two passes
       double2* ak = ahist + (size_t)k * nr * kMaxKv;
@@ -142,8 +147,10 @@ qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qd
       HCK(x, launch_axpy_multi<double2>(r, n, chi_k(k), 0, n, 1, chist + (size_t)k * nr, 1, -1.0, n, nr, active,
                                         st));
       HCK(x, launch_dots<double2>(r, 0, n, 1, r, n, n, nr, part, rn2, st));
+      HCK(x, ev.mark(3, st));
       HCK(x, hipMemcpyAsync(h2.data(), rn2, nr * sizeof(double2), hipMemcpyDeviceToHost, st));
       HCK(x, hipStreamSynchronize(st));
+      HCK(x, ev.add(0, 3));
       tstage[3] += since(ta);
       // (the iteration that converges is not captured: its iterate is the solution, e = 0)
       // capture (r_k, psi_k) of every right-hand side still iterating, with
@@ -208,6 +215,7 @@ qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qd
     std::fill(al.begin(), al.end(), double2{0.0, 0.0});
     for (int i = 0; i < nr; ++i) fgcr_backsub(ah.data(), bh.data(), chh.data(), nr, i, ks[i], al.data() + (size_t)i * kMaxKv);
     HCK(x, hipMemcpyAsync(alpha, al.data(), (size_t)nr * kMaxKv * sizeof(double2), hipMemcpyHostToDevice, st));
+    HCK(x, ev.mark(3, st));
     if (F.phi32)
       HCK(x, launch_axpy_multi<float2>(psi, n, (const float2*)phi, lstride, n, kk, alpha, kMaxKv, 1.0, n, nr, nullptr,
                                        st));
@@ -219,8 +227,10 @@ qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qd
     if (s != QDD_OK) return s;
     HCK(x, launch_sub(r, eta, t, n, n, nr, st));
     HCK(x, launch_dots<double2>(r, 0, n, 1, r, n, n, nr, part, rn2, st));
+    HCK(x, ev.mark(4, st));
     HCK(x, hipMemcpyAsync(h2.data(), rn2, nr * sizeof(double2), hipMemcpyDeviceToHost, st));
     HCK(x, hipStreamSynchronize(st));
+    HCK(x, ev.add(3, 4));
     tstage[7] += since(ta);
     for (int i = 0; i < nr; ++i) {
       if (conv[i]) continue;
@@ -258,6 +268,7 @@ qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qd
       for (int s2 = 0; s2 < 8; ++s2) info[i].t_ms[s2] = tstage[s2];
       info[i].t_ms[0] = tot;
       for (int s2 = 4; s2 < 7; ++s2) info[i].t_ms[s2] = F.tstage ? F.tstage[s2] : 0.0;
+      for (int s2 = 0; s2 < 4; ++s2) info[i].gpu_ms[s2] = ev.gpu_ms[s2];
     }
   }
   if (status != QDD_OK) x->fail(nonfinite ? "non-finite residual" : "no convergence within nmx iterations");

@@ -28,6 +28,35 @@ struct FgcrOps {
 };
 
 qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qdd_solve_info* info);
+// HIP events at stage boundaries on one stream; gpu_ms[k] accumulates the time
+// between marks k and k + 1 once the stream has been waited for
+struct StageEvents {
+  hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double gpu_ms[4] = {0, 0, 0, 0};
+  hipError_t init() {
+    for (auto& v : e) {
+      hipError_t r = hipEventCreate(&v);
+      if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+  }
+  hipError_t mark(int k, hipStream_t st) { return hipEventRecord(e[k], st); }
+  // after a wait on the stream: stage k = [mark k, mark k + 1) for k in [k0, k1)
+  hipError_t add(int k0, int k1) {
+    for (int k = k0; k < k1; ++k) {
+      float ms = 0;
+      hipError_t r = hipEventElapsedTime(&ms, e[k], e[k + 1]);
+      if (r != hipSuccess) return r;
+      gpu_ms[k] += ms;
+    }
+    return hipSuccess;
+  }
+  ~StageEvents() {
+    for (auto v : e)
+      if (v) (void)hipEventDestroy(v);
+  }
+};
+
 // alpha (al[0 .. m)) of right-hand side i from the host copies of the Gram-Schmidt
 // coefficients (ah), the norms (bh) and the projections (chh) of m steps
 void fgcr_backsub(const double2* ah, const double* bh, const double2* chh, int nr, int i, int m, double2* al);

@@ -60,11 +60,13 @@ class BlockInfo(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
-                ("fallbacks", ctypes.c_int), ("true_res", ctypes.c_double), ("t_ms", ctypes.c_double * 8)]
+                ("fallbacks", ctypes.c_int), ("true_res", ctypes.c_double), ("t_ms", ctypes.c_double * 8),
+                ("gpu_ms", ctypes.c_double * 4)]
 
     def as_dict(self):
         return {"iters": self.iters, "restarts": self.restarts, "converged": bool(self.converged),
-                "fallbacks": self.fallbacks, "true_res": self.true_res, "t_ms": list(self.t_ms)}
+                "fallbacks": self.fallbacks, "true_res": self.true_res, "t_ms": list(self.t_ms),
+                "gpu_ms": list(self.gpu_ms)}
 
 
 _lib = None

@@ -102,7 +102,8 @@ def run_solve_workload(wid: int, plain_rhs: int = 1, log=print, U=None):
     psi, info, st, dt = timed_solve(ctx, eta)
     out["mixed"] = {"solve_s": dt, "iters": [i["iters"] for i in info],
                     "true_res_max": max(i["true_res"] for i in info), "converged": all(i["converged"] for i in info),
-                    "sap_prec": {0: "f64", 1: "f32", 2: "f16"}[ctx.cfg.sap_prec]}
+                    "sap_prec": {0: "f64", 1: "f32", 2: "f16"}[ctx.cfg.sap_prec],
+                    "gpu_ms": info[0]["gpu_ms"]}
     log(f"[w{wid}] mixed: {out['mixed']}")
     # Q_S^{-1} (Eq. 5) on fresh even sources through the same solver and subspace
     phi = S.gaussian_field_device(V // 2, 6000, nrhs)
@@ -214,7 +215,7 @@ def run_learned(wid: int = 5, train_pairs: int | None = None, chunk_pairs: int =
     psi, info, st, dt = timed_solve(ctx, eta)
     out["learned"] = {"solve_s": dt, "iters": [i["iters"] for i in info], "fallbacks": [i["fallbacks"] for i in info],
                       "true_res_max": max(i["true_res"] for i in info), "converged": all(i["converged"] for i in info),
-                      "t_ms": info[0]["t_ms"]}
+                      "t_ms": info[0]["t_ms"], "gpu_ms": info[0]["gpu_ms"]}
     # the same network applied with activations rounded to one BF16 term (8
     # significant bits) in its products: a cheaper, inexact preconditioner stage
     ctx.net_set_terms(1)
@@ -245,7 +246,8 @@ def run_learned(wid: int = 5, train_pairs: int | None = None, chunk_pairs: int =
     pctx.dfl_build(init)
     psi1, info1, st1, dt1 = timed_solve(pctx, eta)
     out["plain"] = {"solve_s": dt1, "iters": [i["iters"] for i in info1],
-                    "true_res_max": max(i["true_res"] for i in info1), "t_ms": info1[0]["t_ms"]}
+                    "true_res_max": max(i["true_res"] for i in info1), "t_ms": info1[0]["t_ms"],
+                    "gpu_ms": info1[0]["gpu_ms"]}
     out["learned_vs_plain_time"] = dt1 / out["learned"]["solve_s"]
     log(f"[w{wid}] learned {out['learned']} plain {out['plain']}")
     return out

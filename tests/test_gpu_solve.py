@@ -57,6 +57,9 @@ def test_plain_fgcr_full_D_batched(Q, orc):
     for r in range(3):
         res = np.linalg.norm(eta[r] - orc.apply_D(L, U, A, psi[r])) / np.linalg.norm(eta[r])
         assert info[r]["converged"] and res <= 1e-10 and abs(info[r]["true_res"] - res) < 1e-11
+    # GPU stage times (HIP events): every stage ran, and together they fit in the wall time
+    g = info[0]["gpu_ms"]
+    assert all(v >= 0 for v in g) and g[1] > 0 and g[2] > 0 and g[3] > 0 and sum(g) <= info[0]["t_ms"][0]
 
 
 def test_nonconvergence_reported(Q):
