@@ -259,6 +259,12 @@ def solve_section(learned_pairs, U=None):
                                         for k in ("solve_s", "iters", "true_res_max", "converged")}
                 for c in (1, 2) for t in (3, 1)},
             "learned_calls2_terms1_over_plain_time": r5["learned_calls2_terms1"]["solve_s"] / r5["plain"]["solve_s"],
+            "learned_best": {
+                "policy": "network stage in the first 2 outer iterations of each solve (qdd_net_set_calls), one "
+                          "BF16 term per activation",
+                "solve_s": r5["learned_calls2_terms1"]["solve_s"], "iters": r5["learned_calls2_terms1"]["iters"],
+                "true_res_max": r5["learned_calls2_terms1"]["true_res_max"],
+                "over_plain_time": r5["learned_calls2_terms1"]["solve_s"] / r5["plain"]["solve_s"]},
             "loss_first": r5["loss_first"], "loss_last": r5["loss_last"],
             "harvest_s": r5["harvest_s"], "train_s": r5["train_s"]}
     return sec
