@@ -101,18 +101,23 @@ def block_sites(Lat, bs, blocks):
     return np.nonzero(np.isin(bid, blocks))[0], bid
 
 
-def test_sap_f16_8rhs_full_size(Q, orc, full):
-    # one Schwarz cycle (both colours, nmr 4) in FP16 storage on 8 right-hand sides
-    # in one call; tolerance 3e-3 as for the small lattices: six FP16-stored
-    # quantities (source, links, both clover blocks, rho, V), unit 2^-11 each
+@pytest.mark.parametrize("prec,variant,tol", [(2, 0, 3e-3), (1, 3, 1e-5)])
+def test_sap_8rhs_full_size(Q, orc, full, prec, variant, tol):
+    # one Schwarz cycle (both colours, nmr 4) on 8 right-hand sides in one call,
+    # FP16 storage with the default (LDS-staged) kernel and FP32 storage with the
+    # LDS-staged variant 3; FP16 tolerance 3e-3 as for the small lattices: six
+    # FP16-stored quantities (source, links, both clover blocks, rho, V), unit
+    # 2^-11 each
     import torch
 
     ctx0, U, A, Ai, _ = full
     bs = (4, 4, 4, 4)
     V = int(np.prod(L))
-    c = ctx_on(Q, U, L, max_nrhs=8, sap_bs=bs, ncy=1, nmr=4, sap_prec=2, precond=Q.PRECOND_SAP, nkv=1)
+    c = ctx_on(Q, U, L, max_nrhs=8, sap_bs=bs, ncy=1, nmr=4, sap_prec=prec, precond=Q.PRECOND_SAP, nkv=1)
+    if variant:
+        c.set_launch(Q.KERNEL_SAP, prec, 0, variant, 0, 0)
     eta = S.gaussian_field(V, 2350, nrhs=8)
-    print("[full-size SAP] FP16, 8 rhs, 32^3x64, one cycle", flush=True)
+    print(f"[full-size SAP] prec {prec} variant {variant}, 8 rhs, 32^3x64, one cycle", flush=True)
     out = c.sap(eta)
     white = sample_blocks(L, bs, 1)
     sites, bid = block_sites(L, bs, white)
@@ -133,7 +138,7 @@ def test_sap_f16_8rhs_full_size(Q, orc, full):
         ref = orc.sap_one_cycle_on_blocks(L, U, A, Ai, eta[r], bs, 4, white)[allsites]
         e = relerr(got[r], ref)
         print(f"  rhs {r}: err {e:.2e} over {allsites.size} sites", flush=True)
-        assert e < 3e-3, (r, e)
+        assert e < tol, (r, e)
 
 
 def test_deflation_ns24_full_size(Q, orc, full):
