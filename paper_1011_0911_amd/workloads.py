@@ -64,9 +64,20 @@ def solver_config(w: dict, nrhs: int, plain: bool = False, use_net: bool = False
     return cfg
 
 
+def on_device(a, device="cuda:0"):
+    """complex128 device tensor of a host array (the transfer happens here, outside
+    every timed region: the timings start with their inputs resident in HBM)."""
+    import torch
+
+    t = torch.as_tensor(a).to(device=device, dtype=torch.complex128).contiguous()
+    torch.cuda.synchronize()
+    return t
+
+
 def timed_solve(ctx, eta):
     import torch
 
+    eta = on_device(eta, ctx.device)
     torch.cuda.synchronize()
     t0 = time.time()
     psi, info, st = ctx.solve(eta, check=False)
@@ -90,7 +101,7 @@ def run_solve_workload(wid: int, plain_rhs: int = 1, log=print, U=None):
         U = S.random_su3_links(L, w["eps"], S.gauge_seed(wid))
     log(f"[w{wid}] links {time.time() - t0:.1f} s")
     eta = np.stack([S.gaussian_field(V, S.source_seed(wid, r)) for r in range(nrhs)])
-    init = S.gaussian_field(V, S.dfl_seed(wid), nrhs=w.get("dfl_Ns", 1))
+    init = on_device(S.gaussian_field(V, S.dfl_seed(wid), nrhs=w.get("dfl_Ns", 1)))
     # mixed precision, batched
     ctx, _ = make_context(L, w["eps"], w["kappa"], w["csw"], 0, U=U, tune_nrhs=nrhs, **solver_config(w, nrhs))
     if w.get("dfl_Ns"):
@@ -170,9 +181,10 @@ def run_learned(wid: int = 5, train_pairs: int | None = None, chunk_pairs: int =
     npairs = train_pairs or w["train_pairs"]
     out = {"workload": wid, "lattice": "x".join(map(str, L)), "train_pairs_target": npairs}
     U = S.random_su3_links(L, w["eps"], S.gauge_seed(wid))
-    init = S.gaussian_field(V, S.dfl_seed(wid), nrhs=w["dfl_Ns"])
+    init = on_device(S.gaussian_field(V, S.dfl_seed(wid), nrhs=w["dfl_Ns"]))
     ctx, _ = make_context(L, w["eps"], w["kappa"], w["csw"], 0, U=U, tune_nrhs=ntest,
                           **solver_config(w, ntest, use_net=True))
+    torch.cuda.synchronize()
     t0 = time.time()
     ctx.dfl_build(init)
     torch.cuda.synchronize()
@@ -211,7 +223,7 @@ def run_learned(wid: int = 5, train_pairs: int | None = None, chunk_pairs: int =
     out.update(train_pairs=got, train_solves=src, train_steps=steps, harvest_s=t_h, train_s=t_t,
                loss_first=losses[0] if losses else None, loss_last=losses[-1] if losses else None)
     # evaluate on fresh sources: learned vs plain (same deflation subspace, network off)
-    eta = np.stack([S.gaussian_field(V, 4000 + r) for r in range(ntest)])
+    eta = on_device(np.stack([S.gaussian_field(V, 4000 + r) for r in range(ntest)]))
     psi, info, st, dt = timed_solve(ctx, eta)
     out["learned"] = {"solve_s": dt, "iters": [i["iters"] for i in info], "fallbacks": [i["fallbacks"] for i in info],
                       "true_res_max": max(i["true_res"] for i in info), "converged": all(i["converged"] for i in info),
@@ -281,10 +293,11 @@ def run_multi(wid: int = 4, nkv: int = 8, precond: str = "sap", modes=None, log=
             c, _ = make_context(L, w["eps"], kappa, w["csw"], 0, U=U, tune_nrhs=nrhs, stream=torch.cuda.Stream(),
                                 **solver_config(w, nrhs, **extra))
             group.append(c)
-            etas.append(np.stack([S.gaussian_field(V, S.source_seed(wid, 10 * li + r) + ki) for r in range(nrhs)]))
+            etas.append(on_device(np.stack([S.gaussian_field(V, S.source_seed(wid, 10 * li + r) + ki)
+                                            for r in range(nrhs)])))
             names.append(f"{'x'.join(map(str, L))}/k{kappa}")
         if dfl:
-            init = S.gaussian_field(V, S.dfl_seed(wid) + 10 * li, nrhs=w["dfl_Ns"])
+            init = on_device(S.gaussian_field(V, S.dfl_seed(wid) + 10 * li, nrhs=w["dfl_Ns"]))
             mid = len(group) // 2
             torch.cuda.synchronize()
             t0 = time.time()
