@@ -158,9 +158,9 @@ qdd_status qdd_create(const qdd_geom* geom, const qdd_config* cfg, void* dev_ws,
 void qdd_destroy(qdd_ctx* ctx);
 const char* qdd_last_error(const qdd_ctx* ctx);
 
-/* Gauge ingest (canonical complex128 links, device pointer): builds the
- * parity-split hopping copies in FP64, FP32 and FP16 with the boundary sign
- * folded in.  Invalidates clover and deflation data. */
+/* Gauge ingest (canonical complex128 links, device pointer; the gauge field
+ * U_mu(x) of Eq. 1): builds the parity-split hopping copies in FP64, FP32 and
+ * FP16 with the boundary sign folded in.  Invalidates clover and deflation data. */
 qdd_status qdd_set_gauge(qdd_ctx* ctx, const double* dev_links);
 
 /* Clover setup (Eq. 1): F_{mu nu} from the clover leaves, A = (4+m) + c_sw
@@ -202,25 +202,26 @@ qdd_status qdd_sap(qdd_ctx* ctx, int nrhs, const double* eta, double* psi);
  * operator (self + 8 face couplings per block, FP64). */
 qdd_status qdd_dfl_build(qdd_ctx* ctx, const double* init);
 
-/* Inspection of the deflation data (device pointers, either may be NULL): the
+/* Inspection of the deflation data of Sect. 3 (device pointers, either may be NULL): the
  * block-orthonormal basis as dfl_Ns canonical full fields, and the little Dirac
  * operator A[b][f][k][l] = <w_bk, D w_b'l> (complex128, nblk x 9 x Ns x Ns;
  * f = 0 the block with itself, f = 1 + 2 mu + dir the coupling through the
  * block's upper (dir 0) or lower (dir 1) face in direction mu; blocks numbered
  * lexicographically like sites).  Synchronises. */
 qdd_status qdd_dfl_export(qdd_ctx* ctx, double* basis, double* little);
-/* Solves the little system A c = f (device [rhs][nblk][Ns] complex128) with the
- * FP64 GCR of the preconditioner to relative residual tol; *iters (host) gets
- * the iteration count. */
+/* Solves the little system A c = f of the deflation (Sect. 3; device
+ * [rhs][nblk][Ns] complex128) with the FP64 GCR of the preconditioner to
+ * relative residual tol; *iters (host) gets the iteration count. */
 qdd_status qdd_dfl_coarse_solve(qdd_ctx* ctx, int nrhs, const double* f, double* c, double tol, int* iters);
 /* Reuses the deflation subspace of `src` (same gauge field, lattice, blocks, Ns)
- * at the mass of `dst`: the basis is copied and the little operator shifted,
+ * at the mass of `dst` (several masses share one subspace, Sect. 4 and the
+ * mass-preconditioned solves of Sect. 2): the basis is copied and the little operator shifted,
  * A_dst = A_src + (1/(2 kappa_dst) - 1/(2 kappa_src)) 1 on every block's self
  * coupling (exact for a block-orthonormal basis).  Synchronises. */
 qdd_status qdd_dfl_share(qdd_ctx* dst, const qdd_ctx* src);
 
-/* One application of the two-level preconditioner, out = C r + M_sap(r - D C r)
- * with C = W A^{-1} W^dag (canonical full fields). */
+/* One application of the two-level preconditioner of the deflated solver (Sect. 3),
+ * out = C r + M_sap(r - D C r) with C = W A^{-1} W^dag (canonical full fields). */
 qdd_status qdd_dfl_precond(qdd_ctx* ctx, int nrhs, const double* r, double* out);
 
 /* Solves D psi = eta (canonical full fields, nrhs right-hand sides, psi
@@ -231,11 +232,11 @@ qdd_status qdd_dfl_precond(qdd_ctx* ctx, int nrhs, const double* r, double* out)
  * iterations refreshes the subspace afterwards.  info: nrhs entries (host
  * memory) or NULL.  QDD_ENOCONV if any rhs fails. */
 qdd_status qdd_solve(qdd_ctx* ctx, int nrhs, const double* eta, double* psi, qdd_solve_info* info);
-/* As qdd_solve, but psi holds an initial guess on entry (warm start: the first
- * residual is eta - D psi; a guess that already meets tol returns at once with
- * 0 iterations). */
+/* As qdd_solve, but psi holds an initial guess on entry (warm start, as the
+ * chronological inversion of Sect. 3 uses: the first residual is eta - D psi; a
+ * guess that already meets tol returns at once with 0 iterations). */
 qdd_status qdd_solve_guess(qdd_ctx* ctx, int nrhs, const double* eta, double* psi, qdd_solve_info* info);
-/* The chronological guess for eta from the stored solutions (what qdd_solve
+/* The chronological guess (Sect. 3) for eta from the stored solutions (what qdd_solve
  * would start from), written to psi without solving; QDD_EINVAL with
  * chrono_nv = 0.  psi = 0 for a rhs slot with no stored solution. */
 qdd_status qdd_chrono_guess(qdd_ctx* ctx, int nrhs, const double* eta, double* psi);
@@ -276,7 +277,8 @@ qdd_status qdd_solve_multi(qdd_ctx* const* ctxs, int nsys, const int* nrhs, cons
  * qdd_solve_multi; QDD_ENOCONV if any rhs fails (its context holds the text). */
 qdd_status qdd_solve_group(qdd_ctx* const* ctxs, int nsys, const int* nrhs, const double* const* eta,
                            double* const* psi, qdd_solve_info* const* info);
-/* Solves Dhat psi_e = eta_e (canonical even fields) with unpreconditioned FP64 FGCR. */
+/* Solves Dhat psi_e = eta_e (Eq. 2; canonical even fields) with unpreconditioned
+ * FP64 FGCR (the plain method). */
 qdd_status qdd_solve_dhat(qdd_ctx* ctx, int nrhs, const double* eta_e, double* psi_e, qdd_solve_info* info);
 
 /* ---- mass preconditioning (Sect. 2, Eqs. 2-5) ----
@@ -361,7 +363,8 @@ qdd_status qdd_force(qdd_ctx* ctx, double dm, const double* phi1, const double* 
 qdd_status qdd_block_solve(qdd_ctx* ctx, int nrhs, const double* eta, double* psi, double tol, int maxit,
                            int* blk_iters, double* blk_res, qdd_block_info* info);
 
-/* ---- learned preconditioner stage (configuration use_net = 1) ----
+/* ---- learned preconditioner stage (configuration use_net = 1; an extension
+ * the paper does not have, placed inside its deflated solver of Sect. 3) ----
  * A gauge-covariant parallel-transport convolution network N with net_nl
  * layers and channels net_ch[0..nl]; layer: out_c(x) = sum_{c',d} W[d][c][c']
  * (T_d in_{c'})(x), d = 0 identity, d = 1+2mu forward transport U_mu(x)
@@ -406,7 +409,9 @@ qdd_status qdd_net_train_step(qdd_ctx* ctx, int nb, const void* r, const void* e
 qdd_status qdd_solve_harvest(qdd_ctx* ctx, int nrhs, const double* eta, double* psi, qdd_solve_info* info,
                              void* r_pairs, void* e_pairs, int max_pairs, int* npairs, int* pair_rhs);
 
-/* Launch shape of a kernel family (kernel: 0 = Dhat, 1 = D, 2 = the Schwarz
+/* ---- launch tuning and measurement (extensions: the autotuner and the roofline
+ * measurement of the GPU kernels; no passage of the paper) ----
+ * Launch shape of a kernel family (kernel: 0 = Dhat, 1 = D, 2 = the Schwarz
  * half-sweep; prec: qdd_prec).  For kernel 2 only nr is used, the kernel variant
  * of FP32 / FP16 storage (block, xcd and sb must be 0): 1 one lane per site with
  * its links and clover block in registers, the right-hand sides one after
