@@ -28,23 +28,11 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// partial sums: part[(r*m + l) * nb + b] = sum over block b of conj(x_l[r]) y[r]
-template <class E, int MM>
-__device__ __forceinline__ void dots_body(const E* x, int64_t lstride, int64_t xrs, int m, const double2* y,
-                                          int64_t yrs, int64_t n, double2* part, int r, int bid, int nb) {
-  __shared__ double sh[MM][4][2];
-  const E* xr = x + r * xrs;
-  const double2* yr = y + r * yrs;
-  cx<double> acc[MM];
-#pragma unroll
-  for (int l = 0; l < MM; ++l) acc[l] = {0.0, 0.0};
-  for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < n; i += (int64_t)nb * blockDim.x) {
-    double2 yv = yr[i];
-    cx<double> yy{yv.x, yv.y};
-#pragma unroll
-    for (int l = 0; l < MM; ++l)
-      if (l < m) acc[l] = fmac_c(ldz(xr + l * lstride + i), yy, acc[l]);
-  }
+// the workgroup's sums of the per-lane values acc[l] (l < m): wavefront sums,
+// then the wavefronts in order, into part[(r*m + l) * nb + bid]
+template <int MM>
+__device__ __forceinline__ void block_partials(const cx<double> acc[MM], int m, double (*sh)[4][2], double2* part,
+                                               int r, int bid, int nb) {
   int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int l = 0; l < MM; ++l) {
@@ -66,6 +54,26 @@ __device__ __forceinline__ void dots_body(const E* x, int64_t lstride, int64_t x
     }
     part[((int64_t)r * m + l) * nb + bid] = make_double2(re, im);
   }
+}
+
+// partial sums: part[(r*m + l) * nb + b] = sum over block b of conj(x_l[r]) y[r]
+template <class E, int MM>
+__device__ __forceinline__ void dots_body(const E* x, int64_t lstride, int64_t xrs, int m, const double2* y,
+                                          int64_t yrs, int64_t n, double2* part, int r, int bid, int nb) {
+  __shared__ double sh[MM][4][2];
+  const E* xr = x + r * xrs;
+  const double2* yr = y + r * yrs;
+  cx<double> acc[MM];
+#pragma unroll
+  for (int l = 0; l < MM; ++l) acc[l] = {0.0, 0.0};
+  for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < n; i += (int64_t)nb * blockDim.x) {
+    double2 yv = yr[i];
+    cx<double> yy{yv.x, yv.y};
+#pragma unroll
+    for (int l = 0; l < MM; ++l)
+      if (l < m) acc[l] = fmac_c(ldz(xr + l * lstride + i), yy, acc[l]);
+  }
+  block_partials<MM>(acc, m, sh, part, r, bid, nb);
 }
 template <class E, int MM>
 __global__ void __launch_bounds__(256) k_dots(const E* x, int64_t lstride, int64_t xrs, int m, const double2* y,
@@ -108,6 +116,155 @@ __global__ void __launch_bounds__(256) k_dots_final_grp(Grp<DotsArgs<E>> G) {
 }
 
 static int dots_blocks(int64_t n) { return (int)std::min<int64_t>(kDotBlocks, (n + 255) / 256); }
+
+// One sweep that updates y[r] and reduces over the updated values, in the
+// element order and partial-sum blocking of k_dots (so that the sums equal those
+// of the separate update and reduction bit for bit, and y is read once):
+//   UPD 0: y <- y - sum_{l<m} c_l x_l   (as k_axpy_multi with sgn -1; not where
+//          active[r] == 0), then MODE 0: part of conj(x_l) y for l < m (the next
+//          Gram-Schmidt pass), MODE 1: part of conj(y) y (a norm);
+//   UPD 1: y <- a[r] y (as k_axpby with b = 0), then part of conj(y) w[r].
+template <int MM, int UPD, int MODE>
+__device__ __forceinline__ void upd_dots_body(double2* y, int64_t yrs, const double2* x, int64_t lstride,
+                                              int64_t xrs, int m, const double2* coef, int ldc, const int* active,
+                                              const double* a, const double2* w, int64_t wrs, int64_t n,
+                                              double2* part, int r, int bid, int nb) {
+  __shared__ double sh[MM][4][2];
+  __shared__ cx<double> c[MM];
+  const bool upd = !(active && !active[r]);
+  if constexpr (UPD == 0) {
+    if ((int)threadIdx.x < m) {
+      double2 v = coef[r * ldc + threadIdx.x];
+      c[threadIdx.x] = {-1.0 * v.x, -1.0 * v.y};
+    }
+    __syncthreads();
+  }
+  double2* yr = y + r * yrs;
+  const double2* xr = x + r * xrs;
+  const double2* wr = w ? w + r * wrs : nullptr;
+  const double av = (UPD == 1 && a) ? a[r] : 1.0;
+  constexpr int NS = MODE == 0 ? MM : 1;
+  const int ns = MODE == 0 ? m : 1;
+  cx<double> acc[NS];
+#pragma unroll
+  for (int l = 0; l < NS; ++l) acc[l] = {0.0, 0.0};
+  for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < n; i += (int64_t)nb * blockDim.x) {
+    const double2 yv = yr[i];
+    cx<double> yy{yv.x, yv.y};
+    if constexpr (UPD == 0) {
+      cx<double> xv[MM];
+#pragma unroll
+      for (int l = 0; l < MM; ++l)
+        if (l < m) xv[l] = ldz(xr + l * lstride + i);
+      if (upd) {
+#pragma unroll
+        for (int l = 0; l < MM; ++l)
+          if (l < m) yy = fma_c(c[l], xv[l], yy);
+        yr[i] = make_double2(yy.re, yy.im);
+      }
+      if constexpr (MODE == 0) {
+#pragma unroll
+        for (int l = 0; l < MM; ++l)
+          if (l < m) acc[l] = fmac_c(xv[l], yy, acc[l]);
+      } else {
+        acc[0] = fmac_c(yy, yy, acc[0]);
+      }
+    } else {
+      yy = {av * yv.x + 0.0 * yv.x, av * yv.y + 0.0 * yv.y};
+      yr[i] = make_double2(yy.re, yy.im);
+      const double2 wv = wr[i];
+      acc[0] = fmac_c(yy, cx<double>{wv.x, wv.y}, acc[0]);
+    }
+  }
+  block_partials<NS>(acc, ns, sh, part, r, bid, nb);
+}
+template <int MM, int UPD, int MODE>
+__global__ void __launch_bounds__(256) k_upd_dots(double2* y, int64_t yrs, const double2* x, int64_t lstride,
+                                                  int64_t xrs, int m, const double2* coef, int ldc,
+                                                  const int* active, const double* a, const double2* w, int64_t wrs,
+                                                  int64_t n, double2* part) {
+  upd_dots_body<MM, UPD, MODE>(y, yrs, x, lstride, xrs, m, coef, ldc, active, a, w, wrs, n, part, blockIdx.y,
+                               blockIdx.x, gridDim.x);
+}
+template <int MM, int UPD, int MODE>
+__global__ void __launch_bounds__(256) k_upd_dots_grp(Grp<UpdArgs> G) {
+  const int s = grp_sys(G.start, G.ns, blockIdx.x);
+  const UpdArgs& q = G.a[s];
+  if ((int)blockIdx.y >= q.nrhs) return;
+  upd_dots_body<MM, UPD, MODE>(q.y, q.yrs, q.x, q.lstride, q.xrs, q.m, q.coef, q.ldc, q.active, q.a, q.w, q.wrs, q.n,
+                               q.part, blockIdx.y, blockIdx.x - G.start[s], G.start[s + 1] - G.start[s]);
+}
+__global__ void __launch_bounds__(256) k_upd_final_grp(Grp<UpdArgs> G, int mode) {
+  const int s = grp_sys(G.start, G.ns, blockIdx.x);
+  const UpdArgs& q = G.a[s];
+  dots_final_body(q.part, q.nb, q.nrhs * (mode == 0 ? q.m : 1), q.out, blockIdx.x - G.start[s]);
+}
+
+// the same sweeps over several systems, one launch each (UpdArgs per system)
+template <int UPD, int MODE>
+static hipError_t launch_upd_dots_grp_m(const UpdArgs* a, int ns, hipStream_t st) {
+  if (ns < 1 || ns > kGrpMax) return hipErrorInvalidValue;
+  Grp<UpdArgs> G = grp_new<UpdArgs>(), F = grp_new<UpdArgs>();
+  int mm = 1;
+  for (int s = 0; s < ns; ++s) {
+    if (a[s].m < 1) return hipErrorInvalidValue;
+    UpdArgs b = a[s];
+    b.nb = dots_blocks(b.n);
+    grp_add(G, b, b.nb, b.nrhs);
+    grp_add(F, b, (b.nrhs * (MODE == 0 ? b.m : 1) + 3) / 4);
+    mm = std::max(mm, b.m);
+  }
+  const dim3 grid(G.start[ns], G.ny), blk(256);
+#define UG(MM) hipLaunchKernelGGL((k_upd_dots_grp<MM, UPD, MODE>), grid, blk, 0, st, G)
+  if (UPD == 1 || mm <= 1) UG(1);
+  else if (mm <= 4) UG(4);
+  else if (mm <= 8) UG(8);
+  else if (mm <= 16) UG(16);
+  else if (mm <= 32) UG(32);
+  else return hipErrorInvalidValue;
+#undef UG
+  hipLaunchKernelGGL(k_upd_final_grp, dim3(F.start[ns]), blk, 0, st, F, MODE);
+  return hipGetLastError();
+}
+hipError_t launch_sub_dots_grp(const UpdArgs* a, int ns, int mode, hipStream_t st) {
+  return mode == 0 ? launch_upd_dots_grp_m<0, 0>(a, ns, st) : launch_upd_dots_grp_m<0, 1>(a, ns, st);
+}
+hipError_t launch_scale_dot_grp(const UpdArgs* a, int ns, hipStream_t st) { return launch_upd_dots_grp_m<1, 1>(a, ns, st); }
+
+template <int UPD, int MODE>
+static hipError_t launch_upd_dots_m(double2* y, int64_t yrs, const double2* x, int64_t lstride, int64_t xrs, int m,
+                                    const double2* coef, int ldc, const int* active, const double* a,
+                                    const double2* w, int64_t wrs, int64_t n, int nrhs, double2* part, double2* out,
+                                    hipStream_t st) {
+  const int nb = dots_blocks(n);
+  const dim3 grid(nb, nrhs), blk(256);
+#define UD(MM) hipLaunchKernelGGL((k_upd_dots<MM, UPD, MODE>), grid, blk, 0, st, y, yrs, x, lstride, xrs, m, coef, ldc, \
+                                  active, a, w, wrs, n, part)
+  if (UPD == 1 || m <= 1) UD(1);
+  else if (m <= 4) UD(4);
+  else if (m <= 8) UD(8);
+  else if (m <= 16) UD(16);
+  else if (m <= 32) UD(32);
+  else return hipErrorInvalidValue;
+#undef UD
+  const int total = nrhs * (MODE == 0 ? m : 1);
+  hipLaunchKernelGGL(k_dots_final, dim3((total + 3) / 4), blk, 0, st, part, nb, total, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_dots(double2* y, int64_t yrs, const double2* x, int64_t lstride, int64_t xrs, int m,
+                           const double2* coef, int ldc, const int* active, int mode, int64_t n, int nrhs,
+                           double2* part, double2* out, hipStream_t st) {
+  if (m < 1) return hipErrorInvalidValue;
+  return mode == 0 ? launch_upd_dots_m<0, 0>(y, yrs, x, lstride, xrs, m, coef, ldc, active, nullptr, nullptr, 0, n,
+                                             nrhs, part, out, st)
+                   : launch_upd_dots_m<0, 1>(y, yrs, x, lstride, xrs, m, coef, ldc, active, nullptr, nullptr, 0, n,
+                                             nrhs, part, out, st);
+}
+hipError_t launch_scale_dot(double2* y, int64_t yrs, const double* a, const double2* w, int64_t wrs, int64_t n,
+                            int nrhs, double2* part, double2* out, hipStream_t st) {
+  return launch_upd_dots_m<1, 1>(y, yrs, nullptr, 0, 0, 1, nullptr, 1, nullptr, a, w, wrs, n, nrhs, part, out, st);
+}
 
 template <class E>
 hipError_t launch_dots(const E* x, int64_t lstride, int64_t xrs, int m, const double2* y, int64_t yrs, int64_t n,
@@ -241,25 +398,11 @@ __global__ void k_axpby(double2* y, int64_t yrs, const double2* x, int64_t xrs, 
                         int64_t n, const int* active) {
   axpby_body(y, yrs, x, xrs, a, b, n, active, blockIdx.y, blockIdx.x, gridDim.x);
 }
-__global__ void k_axpby_grp(Grp<AxpbyArgs> G) {
-  const int s = grp_sys(G.start, G.ns, blockIdx.x);
-  const AxpbyArgs& a = G.a[s];
-  if ((int)blockIdx.y >= a.nrhs) return;
-  axpby_body(a.y, a.yrs, a.x, a.xrs, a.a, a.b, a.n, a.active, blockIdx.y, blockIdx.x - G.start[s],
-             G.start[s + 1] - G.start[s]);
-}
 
 hipError_t launch_axpby(double2* y, int64_t yrs, const double2* x, int64_t xrs, const double* a, const double* b,
                         int64_t n, int nrhs, const int* active, hipStream_t st) {
   int nb = vec_blocks(n);
   hipLaunchKernelGGL(k_axpby, dim3(nb, nrhs), dim3(256), 0, st, y, yrs, x, xrs, a, b, n, active);
-  return hipGetLastError();
-}
-hipError_t launch_axpby_grp(const AxpbyArgs* a, int ns, hipStream_t st) {
-  if (ns < 1 || ns > kGrpMax) return hipErrorInvalidValue;
-  Grp<AxpbyArgs> G = grp_new<AxpbyArgs>();
-  for (int s = 0; s < ns; ++s) grp_add(G, a[s], vec_blocks(a[s].n), a[s].nrhs);
-  hipLaunchKernelGGL(k_axpby_grp, dim3(G.start[ns], G.ny), dim3(256), 0, st, G);
   return hipGetLastError();
 }
 

@@ -289,52 +289,57 @@ extern "C" qdd_status qdd_solve_group(qdd_ctx* const* ctxs, int nsys, const int*
                                y.nr});
         }
         HCK(x0, launch_coef_grp(c.data(), (int)c.size(), 0, st));
-        if (k > 0)
-          for (int pass = 0; pass < 2; ++pass) {
-            qdd_status q = dots(
-                run, [](const Sys& y) { return std::make_pair((const double2*)y.chi, y.lstride); }, k,
-                [k](const Sys& y) { return (const double2*)y.chi_k(k); }, [](const Sys& y) { return y.coef; });
-            if (q != QDD_OK) return q;
-            std::vector<AxpyArgs<double2>> ax;
-            for (size_t j = 0; j < run.size(); ++j) {
-              const Sys& y = S[run[j]];
-              ax.push_back(AxpyArgs<double2>{y.chi_k(k), y.n, y.chi, y.lstride, y.n, k, y.coef, k, -1.0, y.n, nullptr,
-                                             y.nr});
-              c[j] = CoefArgs{y.ahist + (size_t)k * y.nr * kMaxKv, kMaxKv, y.coef, k, nullptr, nullptr, nullptr, y.nr};
-            }
-            HCK(x0, launch_axpy_multi_grp<double2>(ax.data(), (int)ax.size(), st));
-            HCK(x0, launch_coef_grp(c.data(), (int)c.size(), 2, st));
+        // the update sweeps also form the next inner products (as in the
+        // single-system solver, the same sums as separate launches)
+        auto upd = [&](auto fill) {
+          std::vector<UpdArgs> u;
+          for (int s : run) u.push_back(fill(S[s]));
+          return u;
+        };
+        qdd_status q = QDD_OK;
+        if (k > 0) {
+          q = dots(
+              run, [](const Sys& y) { return std::make_pair((const double2*)y.chi, y.lstride); }, k,
+              [k](const Sys& y) { return (const double2*)y.chi_k(k); }, [](const Sys& y) { return y.coef; });
+          if (q != QDD_OK) return q;
+          for (size_t j = 0; j < run.size(); ++j) {
+            const Sys& y = S[run[j]];
+            c[j] = CoefArgs{y.ahist + (size_t)k * y.nr * kMaxKv, kMaxKv, y.coef, k, nullptr, nullptr, nullptr, y.nr};
           }
-        qdd_status q = dots(
-            run, [k](const Sys& y) { return std::make_pair((const double2*)y.chi_k(k), (int64_t)0); }, 1,
-            [k](const Sys& y) { return (const double2*)y.chi_k(k); }, [](const Sys& y) { return y.rn2; });
-        if (q != QDD_OK) return q;
+          HCK(x0, launch_coef_grp(c.data(), (int)c.size(), 2, st));
+          auto u0 = upd([k](const Sys& y) {
+            return UpdArgs{y.chi_k(k), y.n, y.chi, y.lstride, y.n, k, y.coef, k, nullptr, nullptr, nullptr, 0,
+                           y.n, y.nr, 0, y.part, y.coef};
+          });
+          HCK(x0, launch_sub_dots_grp(u0.data(), (int)u0.size(), 0, st));
+          HCK(x0, launch_coef_grp(c.data(), (int)c.size(), 2, st));
+          auto u1 = upd([k](const Sys& y) {
+            return UpdArgs{y.chi_k(k), y.n, y.chi, y.lstride, y.n, k, y.coef, k, nullptr, nullptr, nullptr, 0,
+                           y.n, y.nr, 0, y.part, y.rn2};
+          });
+          HCK(x0, launch_sub_dots_grp(u1.data(), (int)u1.size(), 1, st));
+        } else {
+          q = dots(
+              run, [k](const Sys& y) { return std::make_pair((const double2*)y.chi_k(k), (int64_t)0); }, 1,
+              [k](const Sys& y) { return (const double2*)y.chi_k(k); }, [](const Sys& y) { return y.rn2; });
+          if (q != QDD_OK) return q;
+        }
         for (size_t j = 0; j < run.size(); ++j) {
           const Sys& y = S[run[j]];
           c[j] = CoefArgs{nullptr, 0, nullptr, 0, y.rn2, y.bhist + (size_t)k * y.nr, y.binv, y.nr};
         }
         HCK(x0, launch_coef_grp(c.data(), (int)c.size(), 1, st));
-        std::vector<AxpbyArgs> sc;
-        for (int s : run) {
-          const Sys& y = S[s];
-          sc.push_back(AxpbyArgs{y.chi_k(k), y.n, y.chi_k(k), y.n, y.binv, nullptr, y.n, nullptr, y.nr});
-        }
-        HCK(x0, launch_axpby_grp(sc.data(), (int)sc.size(), st));
-        // c_k = <chi_k, r>, r -= c_k chi_k (masked per rhs)
-        q = dots(
-            run, [k](const Sys& y) { return std::make_pair((const double2*)y.chi_k(k), (int64_t)0); }, 1,
-            [](const Sys& y) { return (const double2*)y.r; },
-            [k](const Sys& y) { return y.chist + (size_t)k * y.nr; });
-        if (q != QDD_OK) return q;
-        std::vector<AxpyArgs<double2>> ax;
-        for (int s : run) {
-          const Sys& y = S[s];
-          ax.push_back(AxpyArgs<double2>{y.r, y.n, y.chi_k(k), 0, y.n, 1, y.chist + (size_t)k * y.nr, 1, -1.0, y.n,
-                                         y.active, y.nr});
-        }
-        HCK(x0, launch_axpy_multi_grp<double2>(ax.data(), (int)ax.size(), st));
-        q = r_sqnorm(run);
-        if (q != QDD_OK) return q;
+        // chi_k /= |chi_k| + c_k = <chi_k, r>; r -= c_k chi_k (masked per rhs) + |r|^2
+        auto u2 = upd([k](const Sys& y) {
+          return UpdArgs{y.chi_k(k), y.n, nullptr, 0, 0, 1, nullptr, 1, nullptr, y.binv, y.r, y.n, y.n, y.nr, 0,
+                         y.part, y.chist + (size_t)k * y.nr};
+        });
+        HCK(x0, launch_scale_dot_grp(u2.data(), (int)u2.size(), st));
+        auto u3 = upd([k](const Sys& y) {
+          return UpdArgs{y.r, y.n, y.chi_k(k), 0, y.n, 1, y.chist + (size_t)k * y.nr, 1, y.active, nullptr, nullptr,
+                         0, y.n, y.nr, 0, y.part, y.rn2};
+        });
+        HCK(x0, launch_sub_dots_grp(u3.data(), (int)u3.size(), 1, st));
         HCK(x0, ev.mark(3, st));
         q = fetch_rn2(run);
         if (q != QDD_OK) return q;

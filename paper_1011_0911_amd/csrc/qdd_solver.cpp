@@ -130,23 +130,25 @@ qdd_status run_fgcr(qdd_ctx* x, FgcrOps& F, const double2* eta, double2* psi, qd
       tstage[2] += since(ta);
       HCK(x, ev.mark(2, st));
       ta = tic();
-      // Gram-Schmidt against chi_0 .. chi_{k-1}, two passes
+      // Gram-Schmidt against chi_0 .. chi_{k-1}, two passes; every update sweep
+      // also forms the next inner products (the same sums as separate launches)
       double2* ak = ahist + (size_t)k * nr * kMaxKv;
       HCK(x, hipMemsetAsync(ak, 0, (size_t)nr * kMaxKv * sizeof(double2), st));
-      if (k > 0)
-        for (int pass = 0; pass < 2; ++pass) {
-          HCK(x, launch_dots<double2>(chi, lstride, n, k, chi_k(k), n, n, nr, part, coef, st));
-          HCK(x, launch_axpy_multi<double2>(chi_k(k), n, chi, lstride, n, k, coef, k, -1.0, n, nr, nullptr, st));
-          HCK(x, launch_acc_coef(ak, kMaxKv, coef, k, nr, st));
-        }
-      HCK(x, launch_dots<double2>(chi_k(k), 0, n, 1, chi_k(k), n, n, nr, part, rn2, st));
+      if (k > 0) {
+        HCK(x, launch_dots<double2>(chi, lstride, n, k, chi_k(k), n, n, nr, part, coef, st));
+        HCK(x, launch_acc_coef(ak, kMaxKv, coef, k, nr, st));
+        // pass 1 update + pass 2 products
+        HCK(x, launch_sub_dots(chi_k(k), n, chi, lstride, n, k, coef, k, nullptr, 0, n, nr, part, coef, st));
+        HCK(x, launch_acc_coef(ak, kMaxKv, coef, k, nr, st));
+        // pass 2 update + |chi_k|^2
+        HCK(x, launch_sub_dots(chi_k(k), n, chi, lstride, n, k, coef, k, nullptr, 1, n, nr, part, rn2, st));
+      } else {
+        HCK(x, launch_dots<double2>(chi_k(k), 0, n, 1, chi_k(k), n, n, nr, part, rn2, st));
+      }
       HCK(x, launch_norm_finish(rn2, bhist + (size_t)k * nr, binv, nr, st));
-      HCK(x, launch_axpby(chi_k(k), n, chi_k(k), n, binv, nullptr, n, nr, nullptr, st));
-      // c_k = <chi_k, r>, r -= c_k chi_k
-      HCK(x, launch_dots<double2>(chi_k(k), 0, n, 1, r, n, n, nr, part, chist + (size_t)k * nr, st));
-      HCK(x, launch_axpy_multi<double2>(r, n, chi_k(k), 0, n, 1, chist + (size_t)k * nr, 1, -1.0, n, nr, active,
-                                        st));
-      HCK(x, launch_dots<double2>(r, 0, n, 1, r, n, n, nr, part, rn2, st));
+      // chi_k /= |chi_k| + c_k = <chi_k, r>; r -= c_k chi_k + |r|^2
+      HCK(x, launch_scale_dot(chi_k(k), n, binv, r, n, n, nr, part, chist + (size_t)k * nr, st));
+      HCK(x, launch_sub_dots(r, n, chi_k(k), 0, n, 1, chist + (size_t)k * nr, 1, active, 1, n, nr, part, rn2, st));
       HCK(x, ev.mark(3, st));
       HCK(x, hipMemcpyAsync(h2.data(), rn2, nr * sizeof(double2), hipMemcpyDeviceToHost, st));
       HCK(x, hipStreamSynchronize(st));
