@@ -16,6 +16,10 @@
       known number of bytes; merged into the JSON file J under the key
       prec{P}_nrhs{N} together with the kernel source hash and launch shape, so
       that the benchmark reports the figure only while both still match.
+
+  python -m paper_1011_0911_amd.profsum counters DIR --cmd "..." [--match k_block_mm]
+      per (kernel, grid size) of a `rocprofv3 --pmc` run: dispatches and the
+      average of every collected counter per dispatch (markdown table on stdout)
 """
 from __future__ import annotations
 
@@ -69,6 +73,27 @@ def _counter(d: str, counter: str):
             continue
         res.setdefault((_short(r["Kernel_Name"]), int(r["Grid_Size"])), []).append(float(r["Counter_Value"]))
     return res
+
+
+def counters(d: str, cmd: str, match: str | None = None) -> str:
+    """Average of every counter per dispatch, per (kernel, grid size)."""
+    vals, disp, names = {}, {}, []
+    for r in csv.DictReader(open(_one(d, "*counter_collection.csv"))):
+        k = (_short(r["Kernel_Name"]), int(r["Grid_Size"]))
+        if match and match not in k[0]:
+            continue
+        c = r["Counter_Name"]
+        if c not in names:
+            names.append(c)
+        vals.setdefault(k, {}).setdefault(c, 0.0)
+        vals[k][c] += float(r["Counter_Value"])
+        disp.setdefault(k, set()).add(r["Dispatch_Id"])
+    out = [f"Command: `{cmd}`", "", "| kernel | grid | dispatches | " + " | ".join(names) + " |",
+           "|---|---|---|" + "---|" * len(names)]
+    for k in sorted(vals):
+        n = len(disp[k])
+        out.append(f"| `{k[0]}` | {k[1]} | {n} | " + " | ".join(f"{vals[k].get(c, 0.0) / n:.4g}" for c in names) + " |")
+    return "\n".join(out)
 
 
 def kname_of(tab, prefix):
@@ -170,6 +195,10 @@ def main(argv=None):
     h.add_argument("--gap-ms", type=float, default=50.0)
     h.add_argument("--top", type=int, default=5)
     h.add_argument("--names", default=None)
+    c = sp.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("--cmd", required=True)
+    c.add_argument("--match", default=None)
     t = sp.add_parser("traffic")
     t.add_argument("--bench-json", required=True)
     t.add_argument("--fetch", required=True)
@@ -179,6 +208,8 @@ def main(argv=None):
     o = ap.parse_args(argv)
     if o.what == "stats":
         print(stats(o.dir, o.cmd))
+    elif o.what == "counters":
+        print(counters(o.dir, o.cmd, o.match))
     elif o.what == "phases":
         print(phases(o.dir, o.gap_ms, o.top, o.names.split(",") if o.names else None))
     else:
