@@ -23,6 +23,8 @@ element read or written once per pass, Hermitian 6x6 clover blocks as 36 reals):
 of each link, the third rebuilt)
 times the bytes per real (8 FP64, 4 FP32, 2 FP16) plus, for FP16, one FP32
 scale per site and spinor access (8 per rhs in pass A, 12 in pass B).
+config.ideal_fused states the whole apply's rate on the bytes of an ideal
+single pass instead (psi_e 24n + links + both clover blocks 144 + out 24n).
 """
 from __future__ import annotations
 
@@ -53,6 +55,18 @@ def bytes_per_site(prec: int, nrhs: int, compressed_links: bool = False):
         a += 8 * nrhs
         bb += 12 * nrhs
     return a, bb
+
+
+def fused_bytes_per_site(prec: int, nrhs: int, compressed_links: bool = False) -> int:
+    """Bytes per even site of an ideal single-pass Dhat (each datum touched once:
+    psi_e read and the output written once per rhs, the links once, both clover
+    blocks once); the lower bound the two-pass figures are compared with."""
+    b = {0: 8, 1: 4, 2: 2}[prec]
+    lk = 96 if compressed_links else 144
+    f = (48 * nrhs + lk + 144) * b
+    if prec == 2:
+        f += 8 * nrhs
+    return f
 
 
 def compressed(launch) -> bool:
@@ -335,6 +349,7 @@ def main():
     wall = time.time() - w0
     ms_step = e0.elapsed_time(e1) / args.steps
     a_b, b_b = bytes_per_site(prec, nrhs, compressed(launch))
+    fused = fused_bytes_per_site(prec, nrhs, compressed(launch))
     value = (a_b + b_b) * Vh / (ms_step * 1e-3) / 1e12
     # dominant kernel (pass B): per-launch durations from HIP events on the library stream
     ms_a, ms_b = ctx.dw_hat_timed(prec, nrhs, fin, fout, args.steps)
@@ -377,6 +392,8 @@ def main():
                                                 "sb": launch[3]},
                    "frac_of_peak_whole_apply": round(value / PEAK_HBM_TBS, 4),
                    "pass_a": {"ms": round(ms_a, 5), "TBs": round(ach_a, 4)},
+                   "ideal_fused": {"bytes_per_site": fused, "TBs": round(fused * Vh / (ms_step * 1e-3) / 1e12, 4),
+                                   "frac": round(fused * Vh / (ms_step * 1e-3) / 1e12 / PEAK_HBM_TBS, 4)},
                    "copy_reference_TBs": round(copy_tbs, 4), "copy_bytes": nb, "wall_s_timed": round(wall, 3),
                    "one_rhs": one_rhs, "mass_preconditioning": action},
         "roofline": {"bound": "hbm", "kernel": ("k_dhat_vb" if launch[1] > 1 and launch[2] & 32 else
