@@ -165,21 +165,25 @@ def run_solve_workload(wid: int, plain_rhs: int = 1, log=print, U=None):
 
 def run_learned(wid: int = 5, train_pairs: int | None = None, chunk_pairs: int = 64, batch: int = 4,
                 lr: float = 1e-3, epochs: int = 1, test_rhs: int | None = None, harvest_rhs: int | None = None,
-                log=print):
+                kappa: float | None = None, log=print):
     """Learned preconditioner workload: harvest (r_k, e_k) pairs from plain
     deflated SAP-GCR solves on training sources (harvest_rhs sources per batched
     solve, default the test batch size), train the network on them in streamed
     chunks, then solve fresh test sources with and without the network stage
-    (same deflation subspace).  Returns a dict."""
+    (same deflation subspace).  kappa: another hopping parameter on the same
+    gauge field (an extra workload closer to the critical one, where the plain
+    solver needs more iterations).  Returns a dict."""
     import torch
 
-    w = WORKLOADS[wid]
+    w = dict(WORKLOADS[wid])
+    if kappa is not None:
+        w["kappa"] = kappa
     L = w["L"]
     V = int(np.prod(L))
     ntest = test_rhs or w["nrhs"]
     harvest_rhs = min(harvest_rhs or ntest, ntest)
     npairs = train_pairs or w["train_pairs"]
-    out = {"workload": wid, "lattice": "x".join(map(str, L)), "train_pairs_target": npairs}
+    out = {"workload": wid, "lattice": "x".join(map(str, L)), "kappa": w["kappa"], "train_pairs_target": npairs}
     U = S.random_su3_links(L, w["eps"], S.gauge_seed(wid))
     init = on_device(S.gaussian_field(V, S.dfl_seed(wid), nrhs=w["dfl_Ns"]))
     ctx, _ = make_context(L, w["eps"], w["kappa"], w["csw"], 0, U=U, tune_nrhs=ntest,
@@ -486,6 +490,7 @@ def main(argv=None):
     ap.add_argument("--pairs", type=int, default=None, help="training pairs (workload 5)")
     ap.add_argument("--chunk", type=int, default=64, help="pairs per streamed training chunk (workload 5)")
     ap.add_argument("--epochs", type=int, default=1)
+    ap.add_argument("--kappa", type=float, default=None, help="workload 5: hopping parameter instead of 0.1357")
     ap.add_argument("--precond", choices=["sap", "dfl"], default="sap", help="workload 4: preconditioner")
     ap.add_argument("--modes", default=None, help="workload 4: comma-separated subset of group,threads,sequential")
     ap.add_argument("--sap-prec", type=int, default=qdd.F16, help="sap: storage precision (1 FP32, 2 FP16)")
@@ -499,7 +504,7 @@ def main(argv=None):
     elif a.wid == "sap":
         r = time_sap(prec=a.sap_prec, nrhs=a.nrhs, log=log)
     elif a.wid == "5":
-        r = run_learned(5, train_pairs=a.pairs, chunk_pairs=a.chunk, epochs=a.epochs, log=log)
+        r = run_learned(5, train_pairs=a.pairs, chunk_pairs=a.chunk, epochs=a.epochs, kappa=a.kappa, log=log)
     elif a.wid == "4":
         r = run_multi(4, precond=a.precond, modes=a.modes.split(",") if a.modes else None, log=log)
     else:
