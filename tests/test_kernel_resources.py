@@ -1,7 +1,8 @@
 """Register budget of the hot kernels (CPU: compiles the device code for gfx950
 and reads the compiler's resource report).  A kernel that spills to scratch
 memory runs several times slower; this guards the stencil, network and
-deflation kernels against changes that push them over the register file."""
+deflation kernels and the Schwarz half-sweeps and face corrections of the
+mixed-precision solver against changes that push them over the register file."""
 import os
 import re
 import shutil
@@ -23,6 +24,10 @@ HOT = [
     ("qdd_dirac.hip", r"k_dw<[^,]+, 1, true,"),
     ("qdd_net.hip", r"k_net_layer_mx<"),
     ("qdd_net.hip", r"k_net_wgrad_mx<"),
+    ("qdd_sap.hip", r"k_sap_lds<"),
+    ("qdd_sap.hip", r"k_sap_half<"),
+    ("qdd_sap.hip", r"k_sap_rhs<[^,]+, [^,]+, true>"),
+    ("qdd_sap.hip", r"k_sap_face<"),
     ("qdd_dfl.hip", r"k_block_orth"),
     ("qdd_dfl.hip", r"k_block_dots<"),
 ]
@@ -47,10 +52,22 @@ def resources(src):
     return rows
 
 
+SOURCES = sorted({s for s, _ in HOT})
+
+
+@pytest.fixture(scope="module")
+def reports():
+    """The resource reports of every source, compiled side by side."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(len(SOURCES)) as ex:
+        return dict(zip(SOURCES, ex.map(resources, SOURCES)))
+
+
 @pytest.mark.skipif(not os.path.exists(HIPCC) or shutil.which("c++filt") is None, reason="needs hipcc and c++filt")
-@pytest.mark.parametrize("src", sorted({s for s, _ in HOT}))
-def test_hot_kernels_do_not_spill(src):
-    rows = resources(src)
+@pytest.mark.parametrize("src", SOURCES)
+def test_hot_kernels_do_not_spill(reports, src):
+    rows = reports[src]
     pats = [p for s, p in HOT if s == src]
     checked = 0
     for r in rows:
