@@ -297,6 +297,98 @@ __device__ inline void hop_all_v(const Geo& g, const LinkV<S>& U, const FieldV<S
   __builtin_amdgcn_sched_barrier(0);
 }
 
+// The raw operands of one neighbour (link rows and the V spinors with their
+// scales), loaded one neighbour ahead of their use: the loads of the next
+// neighbour are in flight while the current one is computed.  Same arithmetic
+// as hop_one_v.
+template <class S, int V>
+struct HopRaw {
+  typename St<S>::E u[9];
+  VecE<S, V> s[12];
+  VecF<V> sc;
+};
+
+template <class S, int V, int MU, int SG, bool NTL, bool COMP>
+__device__ inline void hop_load_v(const Geo& g, const LinkV<S>& U, const FieldV<S>& in, int r0, int p, int i,
+                                  const int x[4], HopRaw<S, V>& h) {
+  typedef typename St<S>::E E;
+  typedef VecE<S, V> W;
+  const int j = nbr_idx(g, x, MU, SG);
+  const int par = SG > 0 ? p : 1 - p, li = SG > 0 ? i : j;
+  const E* b = U.p + ((int64_t)(par * 4 + MU) * 9) * U.n;
+  const uint32_t lo = (uint32_t)li * (uint32_t)sizeof(E);
+#pragma unroll
+  for (int k = 0; k < (COMP ? 6 : 9); ++k) h.u[k] = ld_off<E, NTL>(b + (int64_t)k * U.n, lo);
+  const uint32_t eo = (uint32_t)((int64_t)j * in.ss + r0), so = (uint32_t)((int64_t)j * in.sss + r0);
+  const uint32_t vo = eo * (uint32_t)sizeof(E);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) h.s[k] = ld_off<W, false>(reinterpret_cast<const W*>(in.p + (int64_t)k * in.n), vo);
+  if constexpr (sizeof(S) == 2) h.sc = ld_off<VecF<V>, false>(reinterpret_cast<const VecF<V>*>(in.scale), so * 4u);
+}
+
+template <class S, int V, int MU, int SG, bool COMP>
+__device__ inline void hop_use_v(const Geo& g, const HopRaw<S, V>& h, const int x[4], typename St<S>::T c0,
+                                 cx<typename St<S>::T> (&acc)[V][12]) {
+  typedef typename St<S>::T T;
+  cx<T> u[9];
+#pragma unroll
+  for (int k = 0; k < (COMP ? 6 : 9); ++k) u[k] = St<S>::from(h.u[k]);
+  if constexpr (COMP) {
+    const bool edge = MU == 0 && x[0] == (SG > 0 ? g.L[0] - 1 : 0);
+    link_row3<T>(T(edge ? g.bc : 1), u);
+  }
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    cx<T> s[12], hh[6], gg[6];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) s[k] = St<S>::from_reg(h.s[k].e[q]);
+    T sc;
+    if constexpr (sizeof(S) == 2) sc = h.sc.e[q];
+    else sc = T(1);
+    project<T, MU, SG>(s, hh);
+    su3_mul_half<T, (SG < 0)>(u, hh, gg);
+    reconstruct_add<T, MU, SG>(gg, acc[q], c0 * sc);
+  }
+}
+
+template <class S, int V, bool NTL, bool COMP>
+__device__ inline void hop_all_vp(const Geo& g, const LinkV<S>& U, const FieldV<S>& in, int r0, int p, int i,
+                                  const int x[4], typename St<S>::T c0, cx<typename St<S>::T> (&acc)[V][12]) {
+  HopRaw<S, V> a, b;
+  hop_load_v<S, V, 0, +1, NTL, COMP>(g, U, in, r0, p, i, x, a);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_load_v<S, V, 0, -1, NTL, COMP>(g, U, in, r0, p, i, x, b);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_use_v<S, V, 0, +1, COMP>(g, a, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_load_v<S, V, 1, +1, NTL, COMP>(g, U, in, r0, p, i, x, a);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_use_v<S, V, 0, -1, COMP>(g, b, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_load_v<S, V, 1, -1, NTL, COMP>(g, U, in, r0, p, i, x, b);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_use_v<S, V, 1, +1, COMP>(g, a, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_load_v<S, V, 2, +1, NTL, COMP>(g, U, in, r0, p, i, x, a);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_use_v<S, V, 1, -1, COMP>(g, b, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_load_v<S, V, 2, -1, NTL, COMP>(g, U, in, r0, p, i, x, b);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_use_v<S, V, 2, +1, COMP>(g, a, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_load_v<S, V, 3, +1, NTL, COMP>(g, U, in, r0, p, i, x, a);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_use_v<S, V, 2, -1, COMP>(g, b, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_load_v<S, V, 3, -1, NTL, COMP>(g, U, in, r0, p, i, x, b);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_use_v<S, V, 3, +1, COMP>(g, a, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_use_v<S, V, 3, -1, COMP>(g, b, x, c0, acc);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 // waves per SIMD the register budget is sized for
 template <int V>
 constexpr int vec_waves() { return V >= 4 ? 2 : 3; }
@@ -317,7 +409,10 @@ __global__ void __launch_bounds__(256, vec_waves<V>()) k_dhat_va(Geo g, LinkV<S>
   for (int q = 0; q < V; ++q)
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[q][k] = {T(0), T(0)};
-  hop_all_v<S, V, (NTM & 1) != 0, (NTM & 4) != 0>(g, U, in_e, r0, 1, i, x, T(1), acc);
+  if constexpr (sizeof(S) == 2)
+    hop_all_vp<S, V, (NTM & 1) != 0, (NTM & 4) != 0>(g, U, in_e, r0, 1, i, x, T(1), acc);
+  else
+    hop_all_v<S, V, (NTM & 1) != 0, (NTM & 4) != 0>(g, U, in_e, r0, 1, i, x, T(1), acc);
   // acc <- A_o^{-1} acc, one 6x6 block at a time for all V
   const E* b = Ai.p + (int64_t)36 * Ai.n;
   const uint32_t vo = (uint32_t)i * (uint32_t)sizeof(E);
@@ -355,7 +450,10 @@ __global__ void __launch_bounds__(256, vec_waves<V>()) k_dhat_vb(Geo g, LinkV<S>
   for (int q = 0; q < V; ++q)
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[q][k] = {T(0), T(0)};
-  hop_all_v<S, V, (NTM & 1) != 0, (NTM & 4) != 0>(g, U, t_o, r0, 0, i, x, T(-0.25), acc);
+  if constexpr (sizeof(S) == 2)
+    hop_all_vp<S, V, (NTM & 1) != 0, (NTM & 4) != 0>(g, U, t_o, r0, 0, i, x, T(-0.25), acc);
+  else
+    hop_all_v<S, V, (NTM & 1) != 0, (NTM & 4) != 0>(g, U, t_o, r0, 0, i, x, T(-0.25), acc);
   VecE<S, V> raw[12];
   T sc[V];
   ld_spinor_v<S, V, (NTM & 2) != 0>(in_e, (uint32_t)((int64_t)i * in_e.ss + r0),

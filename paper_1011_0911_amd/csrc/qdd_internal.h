@@ -309,15 +309,8 @@ __device__ inline void ld_link_u(const LinkV<S>& u, int par, int mu, int i, cx<t
 // for U in SU(3) it is the complex conjugate of the cross product of the first
 // two; sgn is the fermion boundary sign folded into this stored link (the
 // product of two signed rows loses it)
-template <class S, bool NT = false>
-__device__ inline void ld_link_u12(const LinkV<S>& u, int par, int mu, int i, typename St<S>::T sgn,
-                                   cx<typename St<S>::T> m[9]) {
-  typedef typename St<S>::E E;
-  typedef typename St<S>::T T;
-  const E* b = u.p + ((int64_t)(par * 4 + mu) * 9) * u.n;
-  const uint32_t vo = (uint32_t)i * (uint32_t)sizeof(E);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) m[k] = St<S>::from(ld_off<E, NT>(b + (int64_t)k * u.n, vo));
+template <class T>
+__device__ inline void link_row3(T sgn, cx<T> m[9]) {
   auto cross = [&](int a0, int a1, int b0, int b1) {
     // conj(m[a0] m[b1] - m[a1] m[b0]) * sgn
     const T re = m[a0].re * m[b1].re - m[a0].im * m[b1].im - (m[a1].re * m[b0].re - m[a1].im * m[b0].im);
@@ -327,6 +320,18 @@ __device__ inline void ld_link_u12(const LinkV<S>& u, int par, int mu, int i, ty
   m[6] = cross(1, 2, 4, 5);  // conj(m1 m5 - m2 m4)
   m[7] = cross(2, 0, 5, 3);  // conj(m2 m3 - m0 m5)
   m[8] = cross(0, 1, 3, 4);  // conj(m0 m4 - m1 m3)
+}
+
+template <class S, bool NT = false>
+__device__ inline void ld_link_u12(const LinkV<S>& u, int par, int mu, int i, typename St<S>::T sgn,
+                                   cx<typename St<S>::T> m[9]) {
+  typedef typename St<S>::E E;
+  typedef typename St<S>::T T;
+  const E* b = u.p + ((int64_t)(par * 4 + mu) * 9) * u.n;
+  const uint32_t vo = (uint32_t)i * (uint32_t)sizeof(E);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) m[k] = St<S>::from(ld_off<E, NT>(b + (int64_t)k * u.n, vo));
+  link_row3<T>(sgn, m);
 }
 
 // clover: A[p][slot][i], 36 slots (2 blocks x 18)
