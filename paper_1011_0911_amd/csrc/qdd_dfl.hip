@@ -588,44 +588,51 @@ __global__ void __launch_bounds__(256) k_block_rmul(Geo g, DflGeo d, double2* W,
   }
 }
 
-// out_r(x) = sum_k W_k(x) c[r][b(x)][k] (+ optional add of out), for nrhs rhs;
-// c: [rhs][nblk][Ns] FP64; W fields at stride wvs; out fields at stride ovs
-template <class EW, class EO>
+// out_r(x) = sum_k W_k(x) c[r][b(x)][k], for nrhs rhs;
+// c: [rhs][nblk][Ns] FP64; W fields at stride wvs; out fields at stride ovs.
+// A lane takes one site, NC of its 12 components and NQ right-hand sides at a
+// time; the 12 / NC component slices of a site go to different lanes (slice
+// slowest, so a wavefront reads 64 consecutive sites of one component array).
+// With NC = 6 and NQ = 8 an 8-rhs batch reads each basis element once instead
+// of once per 4 rhs; the sum over k runs in the same order either way.
+template <class EW, class EO, int NQ, int NC>
 __global__ void __launch_bounds__(256) k_prolong(Geo g, DflGeo d, const EW* W, int64_t wvs, int Ns,
                                                  const double2* c, int64_t nc, EO* out, int64_t ovs, int nrhs) {
+  constexpr int NS = 12 / NC;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.V) return;
-  int s = (int)t;
+  if (t >= (int64_t)g.V * NS) return;
+  const int sl = (int)(t / g.V);
+  int s = (int)(t - (int64_t)sl * g.V);
   int p = s >= g.Vh, i = s - p * g.Vh;
   int x[4];
   site_coords(g, p, i, x);
   int b = block_of(d, x);
-  int64_t o = (int64_t)p * 12 * g.Vh + i;
-  for (int r0 = 0; r0 < nrhs; r0 += 4) {
-    cx<double> acc[4][12];
+  int64_t o = (int64_t)p * 12 * g.Vh + i + (int64_t)sl * NC * g.Vh;
+  for (int r0 = 0; r0 < nrhs; r0 += NQ) {
+    cx<double> acc[NQ][NC];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < NQ; ++q)
 #pragma unroll
-      for (int k = 0; k < 12; ++k) acc[q][k] = {0.0, 0.0};
+      for (int k = 0; k < NC; ++k) acc[q][k] = {0.0, 0.0};
     for (int k = 0; k < Ns; ++k) {
-      cx<double> w[12];
+      cx<double> w[NC];
 #pragma unroll
-      for (int cc = 0; cc < 12; ++cc) w[cc] = cvt_any(W[k * wvs + o + (int64_t)cc * g.Vh]);
+      for (int cc = 0; cc < NC; ++cc) w[cc] = cvt_any(W[k * wvs + o + (int64_t)cc * g.Vh]);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         if (r0 + q < nrhs) {
           double2 cv = c[(r0 + q) * nc + (int64_t)b * Ns + k];
           cx<double> z{cv.x, cv.y};
 #pragma unroll
-          for (int cc = 0; cc < 12; ++cc) acc[q][cc] = fma_c(z, w[cc], acc[q][cc]);
+          for (int cc = 0; cc < NC; ++cc) acc[q][cc] = fma_c(z, w[cc], acc[q][cc]);
         }
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < NQ; ++q)
       if (r0 + q < nrhs)
 #pragma unroll
-        for (int cc = 0; cc < 12; ++cc) out[(r0 + q) * ovs + o + (int64_t)cc * g.Vh] = to_elem<EO>(acc[q][cc]);
+        for (int cc = 0; cc < NC; ++cc) out[(r0 + q) * ovs + o + (int64_t)cc * g.Vh] = to_elem<EO>(acc[q][cc]);
   }
 }
 
@@ -873,8 +880,12 @@ hipError_t launch_to_blocks(const Geo& g, const DflGeo& d, const double2* W, int
 template <class EW, class EO>
 hipError_t launch_prolong(const Geo& g, const DflGeo& d, const EW* W, int64_t wvs, int Ns, const double2* c,
                           int64_t nc, EO* out, int64_t ovs, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL((k_prolong<EW, EO>), dim3((g.V + 255) / 256), dim3(256), 0, st, g, d, W, wvs, Ns, c, nc, out,
-                     ovs, nrhs);
+  if (nrhs > 4)
+    hipLaunchKernelGGL((k_prolong<EW, EO, 8, 6>), dim3((unsigned)((2 * (int64_t)g.V + 255) / 256)), dim3(256), 0, st,
+                       g, d, W, wvs, Ns, c, nc, out, ovs, nrhs);
+  else
+    hipLaunchKernelGGL((k_prolong<EW, EO, 4, 12>), dim3((g.V + 255) / 256), dim3(256), 0, st, g, d, W, wvs, Ns, c,
+                       nc, out, ovs, nrhs);
   return hipGetLastError();
 }
 
